@@ -1,0 +1,589 @@
+"""CPU oracle for the BGV less-than hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the device library and never
+imports it; the two meet only through the seeded inputs of ``synth``.
+
+Layers:
+  * ``bgv_oracle.c`` (built into ``liboracle.so``): plain residue arithmetic,
+    textbook NTT products, key switching, modulus switching, automorphisms.
+  * this module: parameters, Python big-integer CRT decryption, the slot
+    encoding, and the comparison circuits written on top of the C ops.
+
+Paper passages followed: BGV ciphertexts, RNS residue matrices and the NTT
+(Background, "Word-wise Universal FHE Scheme" and "Efficient Polynomial and
+NTT"); digit-wise LT/EQ combined in lexicographic order (same section, the
+comparison paragraph); the univariate circuit and its sqrt(p-3)+O(log p)
+non-scalar multiplication count (Introduction).  The paper prints no LT
+polynomial, prime choice or representative convention; the reading used is
+restated at each function.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+from functools import lru_cache
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+u64p = ctypes.POINTER(ctypes.c_uint64)
+i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc (plain C, OpenMP over limbs)."""
+    if force or not os.path.exists(_LIB_PATH):
+        src = os.path.join(_HERE, "bgv_oracle.c")
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-o", tmp, src])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        V, P, I, L, U = ctypes.c_void_p, u64p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+        sig = {
+            "or_mulmod": (U, [U, U, U]),
+            "or_powmod": (U, [U, U, U]),
+            "or_invmod": (U, [U, U]),
+            "or_is_prime": (I, [U]),
+            "or_gen_primes": (I, [U, I, I, P, I, P]),
+            "or_find_psi": (U, [U, I]),
+            "or_ctx_new": (V, [I, U, I, I, I, I, I]),
+            "or_ctx_free": (None, [V]),
+            "or_ctx_nmod": (I, [V]),
+            "or_ctx_moduli": (None, [V, P]),
+            "or_ctx_psi": (U, [V, I]),
+            "or_ntt_forward": (None, [V, I, P]),
+            "or_ntt_inverse": (None, [V, I, P]),
+            "or_negacyclic_mul": (None, [V, I, P, P, P]),
+            "or_schoolbook_negacyclic": (None, [P, P, P, I, U]),
+            "or_keygen": (None, [V, V, P, V, i64p, I, P, P, P, P]),
+            "or_encrypt": (None, [V, P, V, V, V, V, P]),
+            "or_decrypt_residues": (None, [V, P, P, I, I, P]),
+            "or_add": (None, [V, P, P, I, I, P]),
+            "or_sub": (None, [V, P, P, I, I, P]),
+            "or_mul_scalar": (None, [V, P, I, I, L, P]),
+            "or_add_const": (None, [V, P, I, I, L, P]),
+            "or_tensor": (None, [V, P, P, I, P]),
+            "or_mod_switch": (None, [V, P, I, I, P]),
+            "or_modup": (None, [V, P, I, I, P]),
+            "or_moddown": (None, [V, P, I, P]),
+            "or_key_switch": (None, [V, P, P, I, P]),
+            "or_relin": (None, [V, P, P, I, P]),
+            "or_automorphism": (None, [V, P, I, I, L, P]),
+            "or_rotate": (None, [V, P, P, I, L, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def lib():
+    return _load()
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.uint64 and a.flags["C_CONTIGUOUS"], (a.dtype, a.flags)
+    return a.ctypes.data_as(u64p)
+
+
+def _v(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# number theory helpers (plain Python, used by tests and the encoding)
+# ---------------------------------------------------------------------------
+
+def primitive_root(p: int) -> int:
+    """Least primitive root of the prime p (trial over the factors of p-1)."""
+    phi = p - 1
+    fac, n, f = [], phi, 2
+    while f * f <= n:
+        if n % f == 0:
+            fac.append(f)
+            while n % f == 0:
+                n //= f
+        f += 1
+    if n > 1:
+        fac.append(n)
+    for g in range(2, p):
+        if all(pow(g, phi // f, p) != 1 for f in fac):
+            return g
+    raise ValueError(p)
+
+
+def slot_count(p: int) -> int:
+    """M = 2^(s-1) where 2^s exactly divides p-1: x^N+1 splits over F_p into M
+    factors x^d - zeta (zeta^M = -1), giving M slots when M <= N."""
+    s = ((p - 1) & -(p - 1)).bit_length() - 1
+    return 1 << (s - 1)
+
+
+def slot_roots(p: int, M: int) -> list[int]:
+    """zeta_j: slot j < M/2 <-> zeta^(5^j), slot M/2 + j <-> zeta^(-5^j), with
+    zeta = g^((p-1)/2M) for g the least primitive root mod p."""
+    g = primitive_root(p)
+    zeta = pow(g, (p - 1) // (2 * M), p)
+    roots = []
+    for j in range(M):
+        if j < M // 2:
+            e = pow(5, j, 2 * M)
+        else:
+            e = (-pow(5, j - M // 2, 2 * M)) % (2 * M)
+        roots.append(pow(zeta, e, p))
+    return roots
+
+
+def decode_poly(m: np.ndarray, p: int, N: int) -> np.ndarray:
+    """Slots of the plaintext m(x) = mu(x^d): v_j = mu(zeta_j) mod p."""
+    M = slot_count(p)
+    d = N // M
+    mu = [int(m[k * d]) % p for k in range(M)]
+    out = np.zeros(M, dtype=np.uint32)
+    for j, z in enumerate(slot_roots(p, M)):
+        acc, zk = 0, 1
+        for k in range(M):
+            acc = (acc + mu[k] * zk) % p
+            zk = zk * z % p
+        out[j] = acc
+    return out
+
+
+def encode_poly(v, p: int, N: int) -> np.ndarray:
+    """Inverse of ``decode_poly``: mu_k = M^-1 sum_j v_j zeta_j^-k (the zeta_j are
+    the M distinct roots of t^M + 1, so the evaluation matrix is orthogonal up to
+    the factor M); m has coefficient mu_k at x^(k d) and zero elsewhere."""
+    M = slot_count(p)
+    d = N // M
+    roots = slot_roots(p, M)
+    minv = pow(M, p - 2, p)
+    out = np.zeros(N, dtype=np.uint32)
+    for k in range(M):
+        acc = 0
+        for j, z in enumerate(roots):
+            acc = (acc + int(v[j]) * pow(z, (p - 1 - k) % (p - 1), p)) % p
+        out[k * d] = acc * minv % p
+    return out
+
+
+def galois_element(step: int, N: int) -> int:
+    """Rotation by ``step`` slots: g = 5^step mod 2N; step -1 means the row swap g = 2N-1."""
+    if step == -1:
+        return 2 * N - 1
+    return pow(5, step, 2 * N)
+
+
+# ---------------------------------------------------------------------------
+# parameters and context
+# ---------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Params:
+    logN: int
+    p: int
+    nQ: int
+    bitsQ: int
+    nP: int
+    bitsP: int
+    dnum: int
+
+    @property
+    def N(self) -> int:
+        return 1 << self.logN
+
+
+# Parameter sets of the workloads.  Readings: four 36-bit primes for the N=2^12
+# case because a depth-four circuit does not fit in three; three and four
+# special 60-bit primes for the two p=257 chains, because one special prime
+# leaves key-switching noise far above the modulus.
+PARAMS = {
+    "n12_p17": Params(12, 17, 4, 36, 1, 60, 4),
+    "n13_p257": Params(13, 257, 8, 50, 3, 60, 2),
+    "n14_p257": Params(14, 257, 8, 50, 3, 60, 2),
+    "n15_p257": Params(15, 257, 14, 50, 4, 60, 3),
+}
+
+
+@dataclass
+class Ct:
+    data: np.ndarray  # uint64 [ncomp][level+1][N], coefficient domain
+    level: int
+
+    @property
+    def ncomp(self) -> int:
+        return self.data.shape[0]
+
+
+class Oracle:
+    def __init__(self, prm: Params):
+        self.prm = prm
+        self.lib = _load()
+        self.ctx = self.lib.or_ctx_new(prm.logN, prm.p, prm.nQ, prm.bitsQ, prm.nP, prm.bitsP, prm.dnum)
+        if not self.ctx:
+            raise ValueError(f"oracle: cannot build parameters {prm}")
+        n = self.lib.or_ctx_nmod(self.ctx)
+        mods = np.zeros(n, dtype=np.uint64)
+        self.lib.or_ctx_moduli(self.ctx, _p(mods))
+        self.moduli = [int(x) for x in mods]
+        self.q = self.moduli[: prm.nQ]
+        self.special = self.moduli[prm.nQ:]
+        self.N = prm.N
+        self.p = prm.p
+        self.M = slot_count(prm.p)
+        self.alpha = -(-prm.nQ // prm.dnum)
+        self.keys = None
+
+    def __del__(self):
+        if getattr(self, "ctx", None) and self.lib is not None:
+            self.lib.or_ctx_free(self.ctx)
+            self.ctx = None
+
+    # ---------------- keys ----------------
+    def keygen(self, rnd: dict, rot_steps=()):
+        """Keys from the synth randomness (secret, pk, relin key, rotation keys)."""
+        prm, N = self.prm, self.N
+        nm = len(self.moduli)
+        gal = np.array([galois_element(r, N) for r in rot_steps], dtype=np.int64)
+        s = np.ascontiguousarray(rnd["s"], dtype=np.int8)
+        a = np.ascontiguousarray(rnd["a"], dtype=np.uint64)
+        e = np.ascontiguousarray(rnd["e"], dtype=np.int32)
+        need_a = prm.nQ * N + (1 + len(gal)) * prm.dnum * nm * N
+        need_e = N + (1 + len(gal)) * prm.dnum * N
+        assert a.size == need_a and e.size == need_e, (a.size, need_a, e.size, need_e)
+        sk = np.zeros((nm, N), np.uint64)
+        pk = np.zeros((2, prm.nQ, N), np.uint64)
+        rlk = np.zeros((prm.dnum, 2, nm, N), np.uint64)
+        gk = np.zeros((max(len(gal), 1), prm.dnum, 2, nm, N), np.uint64)
+        self.lib.or_keygen(self.ctx, _v(s), _p(a), _v(e), gal.ctypes.data_as(i64p), len(gal),
+                           _p(sk), _p(pk), _p(rlk), _p(gk))
+        self.keys = {"sk": sk, "s": s, "pk": pk, "rlk": rlk,
+                     "gk": {int(r): gk[i] for i, r in enumerate(rot_steps)}}
+        return self.keys
+
+    # ---------------- encryption ----------------
+    def encrypt_poly(self, m: np.ndarray, u: np.ndarray, e: np.ndarray) -> Ct:
+        N, nQ = self.N, self.prm.nQ
+        out = np.zeros((2, nQ, N), np.uint64)
+        m = np.ascontiguousarray(m, dtype=np.uint32)
+        u = np.ascontiguousarray(u, dtype=np.int8)
+        e0 = np.ascontiguousarray(e[0], dtype=np.int32)
+        e1 = np.ascontiguousarray(e[1], dtype=np.int32)
+        self.lib.or_encrypt(self.ctx, _p(self.keys["pk"]), _v(m), _v(u), _v(e0), _v(e1), _p(out))
+        return Ct(out, nQ - 1)
+
+    def encrypt(self, slots, u, e) -> Ct:
+        return self.encrypt_poly(encode_poly(slots, self.p, self.N), u, e)
+
+    def decrypt_residues(self, ct: Ct) -> np.ndarray:
+        out = np.zeros((ct.level + 1, self.N), np.uint64)
+        self.lib.or_decrypt_residues(self.ctx, _p(self.keys["sk"]), _p(np.ascontiguousarray(ct.data)),
+                                     ct.level, ct.ncomp, _p(out))
+        return out
+
+    def crt_centred(self, res: np.ndarray, level: int) -> list[int]:
+        """Integer in (-Q/2, Q/2] with the given residues: sum_i r_i Qhat_i [Qhat_i^-1]_{q_i} mod Q."""
+        qs = self.q[: level + 1]
+        Q = math.prod(qs)
+        terms = []
+        for i, q in enumerate(qs):
+            qh = Q // q
+            terms.append((qh * pow(qh % q, q - 2, q), q))
+        out = []
+        for n in range(self.N):
+            x = sum(int(res[i, n]) * t for i, (t, _) in enumerate(terms)) % Q
+            if x > Q // 2:
+                x -= Q
+            out.append(x)
+        return out
+
+    def decrypt_poly(self, ct: Ct) -> np.ndarray:
+        vals = self.crt_centred(self.decrypt_residues(ct), ct.level)
+        return np.array([v % self.p for v in vals], dtype=np.uint32)
+
+    def decrypt(self, ct: Ct) -> np.ndarray:
+        return decode_poly(self.decrypt_poly(ct), self.p, self.N)
+
+    def noise_bits(self, ct: Ct) -> float:
+        """log2 of the largest |[c0 + c1 s]_Q| coefficient (noise plus message)."""
+        vals = self.crt_centred(self.decrypt_residues(ct), ct.level)
+        return math.log2(max(1, max(abs(v) for v in vals)))
+
+    def budget_bits(self, ct: Ct) -> float:
+        Q = math.prod(self.q[: ct.level + 1])
+        return math.log2(Q / 2) - self.noise_bits(ct)
+
+    # ---------------- elementary ops ----------------
+    def _new(self, ncomp, level):
+        return np.zeros((ncomp, level + 1, self.N), np.uint64)
+
+    def mod_switch(self, ct: Ct) -> Ct:
+        assert ct.level > 0
+        out = self._new(ct.ncomp, ct.level - 1)
+        self.lib.or_mod_switch(self.ctx, _p(ct.data), ct.level, ct.ncomp, _p(out))
+        return Ct(out, ct.level - 1)
+
+    def to_level(self, ct: Ct, level: int) -> Ct:
+        while ct.level > level:
+            ct = self.mod_switch(ct)
+        return ct
+
+    def align(self, a: Ct, b: Ct):
+        lv = min(a.level, b.level)
+        return self.to_level(a, lv), self.to_level(b, lv)
+
+    def add(self, a: Ct, b: Ct) -> Ct:
+        a, b = self.align(a, b)
+        out = self._new(a.ncomp, a.level)
+        self.lib.or_add(self.ctx, _p(a.data), _p(b.data), a.level, a.ncomp, _p(out))
+        return Ct(out, a.level)
+
+    def sub(self, a: Ct, b: Ct) -> Ct:
+        a, b = self.align(a, b)
+        out = self._new(a.ncomp, a.level)
+        self.lib.or_sub(self.ctx, _p(a.data), _p(b.data), a.level, a.ncomp, _p(out))
+        return Ct(out, a.level)
+
+    def centred(self, c: int) -> int:
+        c %= self.p
+        return c - self.p if c > (self.p - 1) // 2 else c
+
+    def mul_scalar(self, a: Ct, c: int) -> Ct:
+        """Multiply by the centred representative of c in Z_p."""
+        out = self._new(a.ncomp, a.level)
+        self.lib.or_mul_scalar(self.ctx, _p(a.data), a.level, a.ncomp, self.centred(c), _p(out))
+        return Ct(out, a.level)
+
+    def add_const(self, a: Ct, c: int) -> Ct:
+        """Add the constant c (all slots) as its centred representative on x^0 of c0."""
+        out = self._new(a.ncomp, a.level)
+        self.lib.or_add_const(self.ctx, _p(a.data), a.level, a.ncomp, self.centred(c), _p(out))
+        return Ct(out, a.level)
+
+    def tensor(self, a: Ct, b: Ct) -> Ct:
+        a, b = self.align(a, b)
+        out = self._new(3, a.level)
+        self.lib.or_tensor(self.ctx, _p(a.data), _p(b.data), a.level, _p(out))
+        return Ct(out, a.level)
+
+    def relin(self, ct3: Ct) -> Ct:
+        out = self._new(2, ct3.level)
+        self.lib.or_relin(self.ctx, _p(self.keys["rlk"]), _p(ct3.data), ct3.level, _p(out))
+        return Ct(out, ct3.level)
+
+    def mul(self, a: Ct, b: Ct) -> Ct:
+        """Align, tensor, relinearise, then drop one prime unless at level 0."""
+        r = self.relin(self.tensor(a, b))
+        return self.mod_switch(r) if r.level > 0 else r
+
+    def modup(self, x: np.ndarray, level: int, digit: int) -> np.ndarray:
+        out = np.zeros((level + 1 + self.prm.nP, self.N), np.uint64)
+        self.lib.or_modup(self.ctx, _p(np.ascontiguousarray(x)), level, digit, _p(out))
+        return out
+
+    def moddown(self, acc: np.ndarray, level: int) -> np.ndarray:
+        out = np.zeros((level + 1, self.N), np.uint64)
+        self.lib.or_moddown(self.ctx, _p(np.ascontiguousarray(acc)), level, _p(out))
+        return out
+
+    def key_switch(self, ksk: np.ndarray, d: np.ndarray, level: int) -> np.ndarray:
+        out = np.zeros((2, level + 1, self.N), np.uint64)
+        self.lib.or_key_switch(self.ctx, _p(ksk), _p(np.ascontiguousarray(d)), level, _p(out))
+        return out
+
+    def automorphism(self, ct: Ct, g: int) -> Ct:
+        out = self._new(ct.ncomp, ct.level)
+        self.lib.or_automorphism(self.ctx, _p(ct.data), ct.level, ct.ncomp, g, _p(out))
+        return Ct(out, ct.level)
+
+    def rotate(self, ct: Ct, step: int) -> Ct:
+        g = galois_element(step, self.N)
+        out = self._new(2, ct.level)
+        self.lib.or_rotate(self.ctx, _p(self.keys["gk"][step]), _p(ct.data), ct.level, g, _p(out))
+        return Ct(out, ct.level)
+
+    def negacyclic_mul(self, prime: int, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+        out = np.zeros(self.N, np.uint64)
+        self.lib.or_negacyclic_mul(self.ctx, prime, _p(np.ascontiguousarray(a, np.uint64)),
+                                   _p(np.ascontiguousarray(b, np.uint64)), _p(out))
+        return out
+
+
+# ---------------------------------------------------------------------------
+# the comparison circuit (Introduction: univariate circuit; Background:
+# digit-wise LT/EQ combined lexicographically)
+# ---------------------------------------------------------------------------
+
+@lru_cache(maxsize=None)
+def _lt_coefficients(p: int) -> tuple:
+    """Coefficients c_0..c_{p-1} of the degree p-1 polynomial f over F_p with
+    f(z) = 1 for z in [(p+1)/2, p-1] and 0 elsewhere (so f(x - y) = [x < y] for
+    x, y in [0, (p-1)/2]).  Interpolating the indicator with (z-a)^(p-1) gives
+    c_k = sum_{b=1}^{(p-1)/2} b^(p-1-k) for odd k, c_{p-1} = (p+1)/2, and zero for
+    the even k (the half power sums vanish)."""
+    c = [0] * p
+    h = (p - 1) // 2
+    for k in range(1, p - 1, 2):
+        c[k] = sum(pow(b, p - 1 - k, p) for b in range(1, h + 1)) % p
+    c[p - 1] = (p + 1) // 2
+    return tuple(c)
+
+
+def lt_coefficients(p: int) -> list[int]:
+    return list(_lt_coefficients(p))
+
+
+class IntEvaluator:
+    """Plain Z_p arithmetic with the evaluator interface (for checking schedules)."""
+
+    def __init__(self, p):
+        self.p = p
+        self.mults = 0
+
+    def mul(self, a, b):
+        self.mults += 1
+        return a * b % self.p
+
+    def add(self, a, b):
+        return (a + b) % self.p
+
+    def sub(self, a, b):
+        return (a - b) % self.p
+
+    def mul_scalar(self, a, c):
+        return a * c % self.p
+
+    def add_const(self, a, c):
+        return (a + c) % self.p
+
+    def level(self, a):
+        return 0
+
+    def to_level(self, a, lv):
+        return a
+
+
+class CtEvaluator:
+    """Evaluator over oracle ciphertexts."""
+
+    def __init__(self, orc: Oracle):
+        self.o = orc
+        self.mults = 0
+
+    def mul(self, a, b):
+        self.mults += 1
+        return self.o.mul(a, b)
+
+    def add(self, a, b):
+        return self.o.add(a, b)
+
+    def sub(self, a, b):
+        return self.o.sub(a, b)
+
+    def mul_scalar(self, a, c):
+        return self.o.mul_scalar(a, c)
+
+    def add_const(self, a, c):
+        return self.o.add_const(a, c)
+
+    def level(self, a):
+        return a.level
+
+    def to_level(self, a, lv):
+        return self.o.to_level(a, lv)
+
+
+def lt_univariate(ev, Z, p: int):
+    """Paterson-Stockmeyer evaluation of f(Z) for p - 1 = 2^e (p = 17, 257).
+
+    Baby steps Z^k for odd k < b (b = 2^ceil(e/2)) from the squares
+    Z^2, ..., Z^(b/2) and products Z^(2^a + r) = Z^(2^a) Z^r; giant steps
+    Z^b, Z^2b, ..., Z^(p-1) by squaring; blocks B_t = sum_{k odd < b} c_{tb+k} Z^k
+    (scalar multiplications only, all babies first brought to the lowest baby
+    level); the blocks are joined by a binary tree
+    H[t0, t0 + 2^r) = H[t0, t0 + 2^(r-1)) + H[t0 + 2^(r-1), t0 + 2^r) Z^(2^(r-1) b);
+    finally f = H + c_{p-1} Z^(p-1).
+
+    Returns (f(Z), Z^(p-1)); Z^(p-1) gives EQ = 1 - Z^(p-1)."""
+    e = (p - 1).bit_length() - 1
+    assert 1 << e == p - 1, "schedule written for p - 1 a power of two"
+    b = 1 << ((e + 1) // 2)
+    c = lt_coefficients(p)
+    pw = {1: Z}
+    a = 1
+    while 2 * a <= b // 2:
+        pw[2 * a] = ev.mul(pw[a], pw[a])
+        a *= 2
+    for k in range(3, b, 2):
+        hi = 1 << (k.bit_length() - 1)
+        pw[k] = ev.mul(pw[hi], pw[k - hi])
+    giants = [ev.mul(pw[b // 2], pw[b // 2])] if b > 1 else [Z]
+    while b << len(giants) <= p - 1:
+        giants.append(ev.mul(giants[-1], giants[-1]))
+    odd = list(range(1, b, 2))
+    lv = min(ev.level(pw[k]) for k in odd)
+    baby = {k: ev.to_level(pw[k], lv) for k in odd}
+    nblk = (p - 1) // b
+    H = []
+    for t in range(nblk):
+        acc = ev.mul_scalar(baby[1], c[t * b + 1])
+        for k in odd[1:]:
+            acc = ev.add(acc, ev.mul_scalar(baby[k], c[t * b + k]))
+        H.append(acc)
+    r = 0
+    while len(H) > 1:
+        G = giants[r]
+        H = [ev.add(H[2 * i], ev.mul(H[2 * i + 1], G)) for i in range(len(H) // 2)]
+        r += 1
+    top = giants[-1]
+    f = ev.add(H[0], ev.mul_scalar(top, c[p - 1]))
+    return f, top
+
+
+def eq_from_top(ev, top):
+    """EQ = 1 - Z^(p-1)."""
+    return ev.add_const(ev.mul_scalar(top, -1), 1)
+
+
+def compare_lt(ev, a_digits, b_digits, p: int):
+    """Lexicographic LT over digit planes, most significant first:
+    LT = LT_0 + EQ_0 (LT_1 + EQ_1 (... LT_{n-1}))."""
+    lts, eqs = [], []
+    for a, b in zip(a_digits, b_digits):
+        f, top = lt_univariate(ev, ev.sub(a, b), p)
+        lts.append(f)
+        eqs.append(eq_from_top(ev, top))
+    acc = lts[-1]
+    for i in range(len(lts) - 2, -1, -1):
+        acc = ev.add(lts[i], ev.mul(eqs[i], acc))
+    return acc
+
+
+def max_min(ev, a_digits, b_digits, lt):
+    """max_d = a_d + LT (b_d - a_d), min_d = b_d + LT (a_d - b_d), per plane."""
+    mx = [ev.add(a, ev.mul(lt, ev.sub(b, a))) for a, b in zip(a_digits, b_digits)]
+    mn = [ev.add(b, ev.mul(lt, ev.sub(a, b))) for a, b in zip(a_digits, b_digits)]
+    return mx, mn
+
+
+def to_digits(values, base: int, ndigits: int):
+    """Integer -> digit planes, most significant first."""
+    v = np.asarray(values, dtype=np.int64)
+    return [((v // base ** (ndigits - 1 - i)) % base).astype(np.uint32) for i in range(ndigits)]
