@@ -1,0 +1,194 @@
+/*
+ * boostcom.h -- C ABI of the MI355X (gfx950) BGV less-than library.
+ *
+ * The library evaluates BoostCom's hot path -- the word-wise BGV comparison
+ * (paper, Background, "Word-wise Universal FHE Scheme": integers split into
+ * F_p digits, per-digit LT and EQ, lexicographic combination) -- on BGV
+ * ciphertexts in RNS form ("Efficient Polynomial and NTT": the (L+1) x N residue
+ * matrix, NTT-based multiplication).  Ring: Z_Q[x]/(x^N + 1), N a power of two,
+ * every prime q = 1 mod 2Np.  Plaintext slots: M = 2^(s-1) where 2^s exactly
+ * divides p - 1 (8 for p = 17, 128 for p = 257), one F_p value per slot.
+ *
+ * Conventions shared by every call:
+ *  - Return value: 0 on success, a negative BC_ERR_* code otherwise; no call
+ *    throws.  bc_last_error() returns a message for the calling thread.
+ *  - Ciphertext batches (bc_ctb) live in caller-owned DEVICE memory:
+ *    data[count][ncomp][level+1][N] uint64 residues in [0, q_i), limb i
+ *    reduced mod q_i, every limb in the NTT (evaluation) domain.  The caller
+ *    sizes buffers with bc_ct_words().  Outputs must not alias inputs unless a
+ *    call says otherwise.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *    enqueued asynchronously on it; calls returning host data synchronise it.
+ *  - Host pointers are read (or written) before the call returns.
+ *  - A context is immutable after creation; calls on one context may run
+ *    concurrently from several threads when they use different streams and
+ *    different output buffers.  Workspace comes from a per-context pool.
+ */
+#ifndef BOOSTCOM_H
+#define BOOSTCOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BC_OK = 0,
+    BC_ERR_ARG = -1,    /* null or malformed argument, size mismatch        */
+    BC_ERR_PARAM = -2,  /* parameters impossible (no such primes, N, p ...)  */
+    BC_ERR_LEVEL = -3,  /* operation needs a level below 0                   */
+    BC_ERR_OOM = -4,    /* device or host allocation failed                  */
+    BC_ERR_HIP = -5,    /* a HIP runtime call failed                         */
+    BC_ERR_KEY = -6     /* a required switching key was not generated        */
+};
+
+/* BGV parameter set.  Primes: the nQ largest primes below 2^bitsQ that are
+ * 1 mod 2Np, in decreasing order (q_0 > ... > q_{nQ-1}); then the nP largest
+ * primes below 2^bitsP with the same congruence, excluding those (special
+ * primes p_0 > ... ).  Modulus switching drops the smallest remaining q.  Key
+ * switching uses dnum digits of alpha = ceil(nQ/dnum) consecutive primes.
+ * Limits: 10 <= logN <= 16, bits <= 61, nQ + nP <= 40, 1 <= dnum <= nQ. */
+typedef struct {
+    int32_t logN;
+    int32_t p;
+    int32_t nQ, bitsQ;
+    int32_t nP, bitsP;
+    int32_t dnum;
+} bc_params;
+
+typedef struct bc_ctx bc_ctx;
+typedef struct bc_keys bc_keys;
+
+/* A batch of `count` ciphertexts at one level; see the layout above. */
+typedef struct {
+    uint64_t *data;
+    int32_t count;
+    int32_t level;
+    int32_t ncomp;
+} bc_ctb;
+
+/* Rotation step meaning the swap of the two slot rows (x -> x^(2N-1)). */
+#define BC_ROW_SWAP (-1)
+
+/* ---------------------------------------------------------------- context */
+
+/* Builds primes, NTT twiddles and every base-conversion constant on the
+ * device (computed once; paper, "GPU-related Optimizations": plan reuse). */
+int bc_ctx_create(const bc_params *prm, bc_ctx **out);
+int bc_ctx_destroy(bc_ctx *ctx);
+/* moduli[nQ + nP] in the order described at bc_params */
+int bc_ctx_moduli(const bc_ctx *ctx, uint64_t *moduli, int32_t cap);
+/* number of slots M */
+int bc_ctx_slots(const bc_ctx *ctx);
+/* uint64 words of one ciphertext with ncomp components at `level` */
+size_t bc_ct_words(const bc_ctx *ctx, int32_t level, int32_t ncomp);
+/* device bytes currently held by the context's workspace pool */
+size_t bc_ctx_pool_bytes(const bc_ctx *ctx);
+/* release every cached workspace block (no call may be in flight) */
+int bc_ctx_trim(bc_ctx *ctx);
+
+/* ------------------------------------------------------------------- keys */
+
+/* Sizes of the randomness consumed by bc_keygen for `nrot` rotation keys. */
+int bc_keygen_rand_sizes(const bc_ctx *ctx, int32_t nrot, size_t *n_words, size_t *n_errors);
+
+/* Key generation from caller-supplied randomness (host arrays):
+ *   s[N]        ternary secret in {-1, 0, 1};
+ *   a_words     uniform 64-bit words, each reduced mod its limb's prime:
+ *               public key [nQ][N], then for the relinearisation key and each
+ *               rotation key (in rot_steps order) and each digit j < dnum:
+ *               [nQ + nP][N];
+ *   errors      small signed errors: public key [N], then per key and digit [N].
+ * Produces pk = (-a s + p e, a), and switching keys
+ * ksk_j = (-a_j s + p e_j + P g_j s', a_j) over Q_L * P with g_j = 1 mod the
+ * primes of digit j and 0 mod all others; s' = s^2 (relinearisation) or
+ * s(x^g) with g = 5^r mod 2N for each rotation step r (g = 2N - 1 for
+ * BC_ROW_SWAP).  The secret stays inside the key object (decryption needs
+ * it).  Synchronous. */
+int bc_keygen(bc_ctx *ctx, const int8_t *s, const uint64_t *a_words, const int32_t *errors,
+              const int32_t *rot_steps, int32_t nrot, bc_keys **out);
+int bc_keys_destroy(bc_keys *keys);
+
+/* ------------------------------------------------------ client-side calls */
+
+/* Encrypts out->count slot vectors slots[count][M] (values taken mod p) at the
+ * top level with public-key randomness u[count][N] (ternary) and
+ * errors[count][2][N]: ct = (pk0 u + p e0 + m, pk1 u + p e1), m the slot
+ * encoding (coefficient mu_k at x^(k N/M)).  out->level is set to nQ - 1 and
+ * out->ncomp to 2; out->data must hold bc_ct_words(nQ-1, 2) * count words. */
+int bc_encrypt(bc_ctx *ctx, const bc_keys *keys, const uint32_t *slots, const int8_t *u,
+               const int32_t *errors, bc_ctb *out, void *stream);
+
+/* Decrypts [c0 + c1 s (+ c2 s^2)]_Q mod p and decodes the slots:
+ * slots[count][M].  Synchronises the stream. */
+int bc_decrypt(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t *slots, void *stream);
+/* Same, returning all N plaintext coefficients in [0, p): coeffs[count][N]. */
+int bc_decrypt_poly(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t *coeffs, void *stream);
+
+/* Host <-> device in the COEFFICIENT domain: host[count][ncomp][level+1][N]. */
+int bc_export(bc_ctx *ctx, const bc_ctb *in, uint64_t *host, void *stream);
+int bc_import(bc_ctx *ctx, const uint64_t *host, bc_ctb *out, void *stream);
+
+/* ------------------------------------------------------ server-side calls */
+/* Binary calls accept b->count == a->count, or b->count dividing a->count
+ * (ciphertext i of a pairs with i mod b->count of b).  Operands at different
+ * levels are first brought to the lower one by modulus switching. */
+
+/* Tensor (a0 b0, a0 b1 + a1 b0, a1 b1): out has 3 components. */
+int bc_tensor(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream);
+/* Relinearisation of a 3-component batch with the relinearisation key, same level. */
+int bc_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, bc_ctb *out, void *stream);
+/* Drops q_level: t = [c_l p^-1]_{q_l} in (-q_l/2, q_l/2], c_i' = (c_i - p t) q_l^-1. */
+int bc_mod_switch(bc_ctx *ctx, const bc_ctb *in, bc_ctb *out, void *stream);
+/* Multiplication: align levels, tensor, relinearise, then modulus-switch one
+ * prime down unless the level is 0 (paper: the non-scalar multiplication the
+ * comparison circuits count). */
+int bc_mul_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *a, const bc_ctb *b, bc_ctb *out,
+                 void *stream);
+/* Rotation of each slot row left by `steps` (or BC_ROW_SWAP): automorphism
+ * then key switch with the matching rotation key; level unchanged. */
+int bc_rotate(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, int32_t steps, bc_ctb *out, void *stream);
+int bc_add(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream);
+int bc_sub(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream);
+/* Multiply by c in Z_p (its representative in (-p/2, p/2]). */
+int bc_mul_scalar(bc_ctx *ctx, const bc_ctb *a, int32_t c, bc_ctb *out, void *stream);
+/* Add c in Z_p to every slot (representative in (-p/2, p/2] on x^0 of c0). */
+int bc_add_const(bc_ctx *ctx, const bc_ctb *a, int32_t c, bc_ctb *out, void *stream);
+
+/* ---------------------------------------------------------- comparisons */
+/* Digit planes: a_digits[d] (d < ndigits, most significant first) is a batch
+ * of `count` ciphertexts, all with the same count, level and ncomp == 2; slot
+ * k of plane d holds digit d of integer k.  The univariate circuit
+ * LT(x, y) = f(x - y), f the degree p-1 interpolant of [z in [(p+1)/2, p-1]],
+ * is exact for digits in [0, (p-1)/2] (base (p+1)/2); it is evaluated with a
+ * Paterson-Stockmeyer schedule (p - 1 a power of two: 8 multiplications for
+ * p = 17, 30 for p = 257).  EQ = 1 - (x - y)^(p-1).  Digits are combined as
+ * LT = LT_0 + EQ_0 (LT_1 + EQ_1 (...)).  Output buffers must be allocated at
+ * the level the call reports through bc_compare_levels. */
+int bc_compare_levels(const bc_ctx *ctx, int32_t in_level, int32_t ndigits, int32_t *lt_level,
+                      int32_t *maxmin_level);
+/* out: encryption of [a < b] in every slot. */
+int bc_compare_lt(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits,
+                  const bc_ctb *b_digits, bc_ctb *out, void *stream);
+/* max_d = a_d + LT (b_d - a_d) and/or min_d = b_d + LT (a_d - b_d) per plane;
+ * lt_out, max_out and min_out may each be NULL (at least one non-NULL). */
+int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits,
+                       const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out,
+                       void *stream);
+
+/* Execution mode of the comparison calls: BC_EXEC_BATCHED launches every step
+ * of the circuit once for the whole batch; BC_EXEC_GRAPH additionally records
+ * the launch sequence of a (shape, buffers) combination into a hipGraph on its
+ * first call and replays it afterwards. */
+enum { BC_EXEC_BATCHED = 0, BC_EXEC_GRAPH = 1 };
+int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
+
+const char *bc_strerror(int code);
+const char *bc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,338 @@
+"""Python binding of the gfx950 BGV less-than library (``libboostcom.so``).
+
+Argument marshalling only: every computation happens in the library's HIP
+kernels.  PyTorch provides device memory (ciphertext batches are int64 CUDA
+tensors reinterpreted as uint64 residues) and the current HIP stream.  The C
+functions keep their names (``bc_ctx_create`` ...); ``Context`` bundles them
+for convenience.  Importing never compiles anything; if the shared library is
+missing the first call raises ``BoostcomUnavailable``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libboostcom.so")
+
+BC_OK, BC_ERR_ARG, BC_ERR_PARAM, BC_ERR_LEVEL, BC_ERR_OOM, BC_ERR_HIP, BC_ERR_KEY = 0, -1, -2, -3, -4, -5, -6
+BC_ROW_SWAP = -1
+BC_EXEC_BATCHED, BC_EXEC_GRAPH = 0, 1
+
+
+class BoostcomUnavailable(RuntimeError):
+    pass
+
+
+class BoostcomError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(msg)
+        self.code = code
+
+
+class bc_params(ctypes.Structure):
+    _fields_ = [("logN", ctypes.c_int32), ("p", ctypes.c_int32), ("nQ", ctypes.c_int32), ("bitsQ", ctypes.c_int32),
+                ("nP", ctypes.c_int32), ("bitsP", ctypes.c_int32), ("dnum", ctypes.c_int32)]
+
+
+class bc_ctb(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("count", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("ncomp", ctypes.c_int32)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_V, _P, _I, _S = ctypes.c_void_p, ctypes.POINTER, ctypes.c_int32, ctypes.c_size_t
+_SIGS = {
+    "bc_ctx_create": (_I, [_P(bc_params), _P(_V)]),
+    "bc_ctx_destroy": (_I, [_V]),
+    "bc_ctx_moduli": (_I, [_V, _P(ctypes.c_uint64), _I]),
+    "bc_ctx_slots": (_I, [_V]),
+    "bc_ct_words": (_S, [_V, _I, _I]),
+    "bc_ctx_pool_bytes": (_S, [_V]),
+    "bc_ctx_trim": (_I, [_V]),
+    "bc_keygen_rand_sizes": (_I, [_V, _I, _P(_S), _P(_S)]),
+    "bc_keygen": (_I, [_V, _V, _V, _V, _V, _I, _P(_V)]),
+    "bc_keys_destroy": (_I, [_V]),
+    "bc_encrypt": (_I, [_V, _V, _V, _V, _V, _P(bc_ctb), _V]),
+    "bc_decrypt": (_I, [_V, _V, _P(bc_ctb), _V, _V]),
+    "bc_decrypt_poly": (_I, [_V, _V, _P(bc_ctb), _V, _V]),
+    "bc_export": (_I, [_V, _P(bc_ctb), _V, _V]),
+    "bc_import": (_I, [_V, _V, _P(bc_ctb), _V]),
+    "bc_tensor": (_I, [_V, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_relin": (_I, [_V, _V, _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_mod_switch": (_I, [_V, _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_mul_relin": (_I, [_V, _V, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_rotate": (_I, [_V, _V, _P(bc_ctb), _I, _P(bc_ctb), _V]),
+    "bc_add": (_I, [_V, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_sub": (_I, [_V, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_mul_scalar": (_I, [_V, _P(bc_ctb), _I, _P(bc_ctb), _V]),
+    "bc_add_const": (_I, [_V, _P(bc_ctb), _I, _P(bc_ctb), _V]),
+    "bc_compare_levels": (_I, [_V, _I, _I, _P(_I), _P(_I)]),
+    "bc_compare_lt": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_compare_max_min": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_set_exec_mode": (_I, [_V, _I]),
+    "bc_strerror": (ctypes.c_char_p, [_I]),
+    "bc_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Loads the in-tree shared library (never builds it)."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime with the same SONAME as the system
+        # one; loading torch first makes the library bind to that single
+        # runtime, so torch's device memory and streams are valid here.
+        import torch  # noqa: F401
+
+        if not os.path.exists(LIB_PATH):
+            raise BoostcomUnavailable(f"{LIB_PATH} is missing: build it with `python -m paper_2407_07308_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return sorted(_SIGS)
+
+
+def _check(rc: int):
+    if rc != BC_OK:
+        L = lib()
+        raise BoostcomError(rc, f"{L.bc_strerror(rc).decode()}: {L.bc_last_error().decode()}")
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _np_ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Batch:
+    """``count`` ciphertexts [count][ncomp][level+1][N] uint64 in a CUDA tensor."""
+    tensor: object  # torch.Tensor (int64, cuda)
+    count: int
+    level: int
+    ncomp: int
+
+    def ctb(self) -> bc_ctb:
+        return bc_ctb(self.tensor.data_ptr(), self.count, self.level, self.ncomp)
+
+
+def _ctb_array(batches):
+    arr = (bc_ctb * len(batches))()
+    for i, b in enumerate(batches):
+        arr[i] = b.ctb()
+    return arr
+
+
+class Keys:
+    def __init__(self, ctx: "Context", handle: ctypes.c_void_p, rot_steps):
+        self.ctx = ctx
+        self.handle = handle
+        self.rot_steps = tuple(rot_steps)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.bc_keys_destroy(self.handle)
+            self.handle = None
+
+
+class Context:
+    def __init__(self, logN: int, p: int, nQ: int, bitsQ: int, nP: int, bitsP: int, dnum: int):
+        self.prm = bc_params(logN, p, nQ, bitsQ, nP, bitsP, dnum)
+        self.L = lib()
+        h = ctypes.c_void_p()
+        _check(self.L.bc_ctx_create(ctypes.byref(self.prm), ctypes.byref(h)))
+        self.handle = h
+        self.N = 1 << logN
+        self.p = p
+        self.nQ, self.nP, self.dnum = nQ, nP, dnum
+        self.M = self.L.bc_ctx_slots(h)
+        mods = (ctypes.c_uint64 * (nQ + nP))()
+        _check(self.L.bc_ctx_moduli(h, mods, nQ + nP))
+        self.moduli = [int(x) for x in mods]
+
+    @classmethod
+    def from_params(cls, prm) -> "Context":
+        return cls(prm.logN, prm.p, prm.nQ, prm.bitsQ, prm.nP, prm.bitsP, prm.dnum)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.bc_ctx_destroy(self.handle)
+            self.handle = None
+
+    # ------------------------------------------------------------ memory
+    def ct_words(self, level: int, ncomp: int = 2) -> int:
+        return int(self.L.bc_ct_words(self.handle, level, ncomp))
+
+    def new_batch(self, count: int, level: int, ncomp: int = 2) -> Batch:
+        import torch
+
+        words = self.ct_words(level, ncomp) * count
+        return Batch(torch.empty(words, dtype=torch.int64, device="cuda"), count, level, ncomp)
+
+    def pool_bytes(self) -> int:
+        return int(self.L.bc_ctx_pool_bytes(self.handle))
+
+    def trim(self):
+        _check(self.L.bc_ctx_trim(self.handle))
+
+    # -------------------------------------------------------------- keys
+    def keygen_sizes(self, nrot: int):
+        w, e = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(self.L.bc_keygen_rand_sizes(self.handle, nrot, ctypes.byref(w), ctypes.byref(e)))
+        return w.value, e.value
+
+    def keygen(self, s, a_words, errors, rot_steps=()) -> Keys:
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        a = np.ascontiguousarray(a_words, dtype=np.uint64)
+        e = np.ascontiguousarray(errors, dtype=np.int32)
+        nw, ne = self.keygen_sizes(len(rot_steps))
+        if s.size != self.N or a.size != nw or e.size != ne:
+            raise BoostcomError(BC_ERR_ARG, f"keygen randomness sizes {s.size},{a.size},{e.size} != {self.N},{nw},{ne}")
+        steps = (ctypes.c_int32 * max(1, len(rot_steps)))(*rot_steps)
+        h = ctypes.c_void_p()
+        _check(self.L.bc_keygen(self.handle, _np_ptr(s), _np_ptr(a), _np_ptr(e), steps, len(rot_steps),
+                                ctypes.byref(h)))
+        return Keys(self, h, rot_steps)
+
+    # ------------------------------------------------------- client side
+    def encrypt(self, keys: Keys, slots, u, errors, out: Batch | None = None) -> Batch:
+        slots = np.ascontiguousarray(slots, dtype=np.uint32).reshape(-1, self.M)
+        count = slots.shape[0]
+        u = np.ascontiguousarray(u, dtype=np.int8).reshape(count, self.N)
+        e = np.ascontiguousarray(errors, dtype=np.int32).reshape(count, 2, self.N)
+        out = out or self.new_batch(count, self.nQ - 1, 2)
+        c = out.ctb()
+        _check(self.L.bc_encrypt(self.handle, keys.handle, _np_ptr(slots), _np_ptr(u), _np_ptr(e), ctypes.byref(c),
+                                 _stream()))
+        out.level, out.ncomp = c.level, c.ncomp
+        return out
+
+    def decrypt(self, keys: Keys, b: Batch) -> np.ndarray:
+        out = np.zeros((b.count, self.M), dtype=np.uint32)
+        c = b.ctb()
+        _check(self.L.bc_decrypt(self.handle, keys.handle, ctypes.byref(c), _np_ptr(out), _stream()))
+        return out
+
+    def decrypt_poly(self, keys: Keys, b: Batch) -> np.ndarray:
+        out = np.zeros((b.count, self.N), dtype=np.uint32)
+        c = b.ctb()
+        _check(self.L.bc_decrypt_poly(self.handle, keys.handle, ctypes.byref(c), _np_ptr(out), _stream()))
+        return out
+
+    def export(self, b: Batch) -> np.ndarray:
+        out = np.zeros((b.count, b.ncomp, b.level + 1, self.N), dtype=np.uint64)
+        c = b.ctb()
+        _check(self.L.bc_export(self.handle, ctypes.byref(c), _np_ptr(out), _stream()))
+        return out
+
+    def import_(self, host: np.ndarray, level: int, ncomp: int = 2) -> Batch:
+        host = np.ascontiguousarray(host, dtype=np.uint64).reshape(-1, ncomp, level + 1, self.N)
+        out = self.new_batch(host.shape[0], level, ncomp)
+        c = out.ctb()
+        _check(self.L.bc_import(self.handle, _np_ptr(host), ctypes.byref(c), _stream()))
+        return out
+
+    # ------------------------------------------------------- server side
+    def _binary(self, fn, a: Batch, b: Batch, level: int, ncomp: int, *extra) -> Batch:
+        out = self.new_batch(a.count, level, ncomp)
+        ca, cb, co = a.ctb(), b.ctb(), out.ctb()
+        _check(fn(self.handle, *extra, ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(co), _stream()))
+        return out
+
+    def tensor(self, a: Batch, b: Batch) -> Batch:
+        return self._binary(self.L.bc_tensor, a, b, min(a.level, b.level), 3)
+
+    def add(self, a: Batch, b: Batch) -> Batch:
+        return self._binary(self.L.bc_add, a, b, min(a.level, b.level), a.ncomp)
+
+    def sub(self, a: Batch, b: Batch) -> Batch:
+        return self._binary(self.L.bc_sub, a, b, min(a.level, b.level), a.ncomp)
+
+    def mul_relin(self, keys: Keys, a: Batch, b: Batch) -> Batch:
+        lv = min(a.level, b.level)
+        out = self.new_batch(a.count, lv - 1 if lv > 0 else 0, 2)
+        ca, cb, co = a.ctb(), b.ctb(), out.ctb()
+        _check(self.L.bc_mul_relin(self.handle, keys.handle, ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(co),
+                                   _stream()))
+        return out
+
+    def relin(self, keys: Keys, a: Batch) -> Batch:
+        out = self.new_batch(a.count, a.level, 2)
+        ca, co = a.ctb(), out.ctb()
+        _check(self.L.bc_relin(self.handle, keys.handle, ctypes.byref(ca), ctypes.byref(co), _stream()))
+        return out
+
+    def mod_switch(self, a: Batch) -> Batch:
+        out = self.new_batch(a.count, a.level - 1, 2)
+        ca, co = a.ctb(), out.ctb()
+        _check(self.L.bc_mod_switch(self.handle, ctypes.byref(ca), ctypes.byref(co), _stream()))
+        return out
+
+    def rotate(self, keys: Keys, a: Batch, steps: int) -> Batch:
+        out = self.new_batch(a.count, a.level, 2)
+        ca, co = a.ctb(), out.ctb()
+        _check(self.L.bc_rotate(self.handle, keys.handle, ctypes.byref(ca), steps, ctypes.byref(co), _stream()))
+        return out
+
+    def mul_scalar(self, a: Batch, c: int) -> Batch:
+        out = self.new_batch(a.count, a.level, a.ncomp)
+        ca, co = a.ctb(), out.ctb()
+        _check(self.L.bc_mul_scalar(self.handle, ctypes.byref(ca), int(c), ctypes.byref(co), _stream()))
+        return out
+
+    def add_const(self, a: Batch, c: int) -> Batch:
+        out = self.new_batch(a.count, a.level, a.ncomp)
+        ca, co = a.ctb(), out.ctb()
+        _check(self.L.bc_add_const(self.handle, ctypes.byref(ca), int(c), ctypes.byref(co), _stream()))
+        return out
+
+    # ------------------------------------------------------ comparisons
+    def compare_levels(self, in_level: int, ndigits: int):
+        lt, mm = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.L.bc_compare_levels(self.handle, in_level, ndigits, ctypes.byref(lt), ctypes.byref(mm)))
+        return lt.value, mm.value
+
+    def set_exec_mode(self, mode: int):
+        _check(self.L.bc_set_exec_mode(self.handle, mode))
+
+    def compare_max_min(self, keys: Keys, a_digits, b_digits, want_lt=True, want_max=True, want_min=True, outs=None):
+        """Returns (lt, [max planes], [min planes]); ``outs`` reuses earlier output batches."""
+        nd = len(a_digits)
+        G = a_digits[0].count
+        ltl, mml = self.compare_levels(a_digits[0].level, nd)
+        if outs is None:
+            lt = self.new_batch(G, ltl) if want_lt else None
+            mx = [self.new_batch(G, mml) for _ in range(nd)] if want_max else None
+            mn = [self.new_batch(G, mml) for _ in range(nd)] if want_min else None
+        else:
+            lt, mx, mn = outs
+        A, B = _ctb_array(a_digits), _ctb_array(b_digits)
+        clt = lt.ctb() if lt is not None else None
+        cmx = _ctb_array(mx) if mx is not None else None
+        cmn = _ctb_array(mn) if mn is not None else None
+        _check(self.L.bc_compare_max_min(self.handle, keys.handle, nd, A, B,
+                                         ctypes.byref(clt) if clt is not None else None, cmx, cmn, _stream()))
+        return lt, mx, mn
+
+    def compare_lt(self, keys: Keys, a_digits, b_digits) -> Batch:
+        return self.compare_max_min(keys, a_digits, b_digits, True, False, False)[0]

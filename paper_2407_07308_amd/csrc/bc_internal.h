@@ -1,0 +1,230 @@
+// bc_internal.h -- shared declarations of the gfx950 BGV library (device
+// arithmetic, context layout, launch descriptors).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/boostcom.h"
+
+namespace bc {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+typedef unsigned __int128 u128;
+
+constexpr int kMaxMod = 40;    // nQ + nP
+constexpr int kMaxJobs = 160;  // limbs listed in one transform launch
+
+// ------------------------------------------------------------------ errors
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define BC_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            throw ::bc::Error(BC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+#define BC_REQUIRE(cond, code, msg)                                                               \
+    do {                                                                                          \
+        if (!(cond)) throw ::bc::Error((code), (msg));                                            \
+    } while (0)
+
+// ------------------------------------------------------- device arithmetic
+// Residues are below q < 2^61.  Lazy values stay below 4q < 2^63.
+
+__device__ __forceinline__ u64 mulhi(u64 a, u64 b) { return __umul64hi(a, b); }
+
+// Shoup multiplication by a constant w < q with wp = floor(w 2^64 / q):
+// a w - floor(a wp / 2^64) q lies in [0, 2q) for every a < 2^64.
+__device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 wp, u64 q) { return a * w - mulhi(a, wp) * q; }
+
+__device__ __forceinline__ u64 shoup(u64 a, u64 w, u64 wp, u64 q) {
+    u64 r = shoup_lazy(a, w, wp, q);
+    return r >= q ? r - q : r;
+}
+
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+
+// Per-prime Barrett data for products of two variables a, b < q:
+// x = a b < q^2 < 2^(2s) (q < 2^s);  t = x >> (s-2);  qh = mulhi(t, mu),
+// mu = floor(2^(62+s) / q);  then qh is floor(x/q) minus at most 2 and
+// x - qh q < 3q.
+struct Barrett {
+    u64 q, mu;
+    int sh;  // s - 2
+    int pad;
+};
+
+__device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const Barrett &m) {
+    u64 lo = a * b, hi = mulhi(a, b);
+    u64 t = (hi << (64 - m.sh)) | (lo >> m.sh);
+    u64 r = lo - mulhi(t, m.mu) * m.q;
+    r = r >= 2 * m.q ? r - 2 * m.q : r;
+    return r >= m.q ? r - m.q : r;
+}
+
+// ------------------------------------------------------ launch descriptors
+
+// A list of residue polynomials (limbs) inside a batch: limb k of poly b sits
+// at base + b * poly_stride + off[k] * N and is reduced mod prime[k].
+struct LimbSet {
+    u64 *base;
+    u64 poly_stride;
+    int npoly;
+    int nlimb;
+    int16_t off[kMaxJobs];
+    int16_t prime[kMaxJobs];
+};
+
+// Constants of one prime (device copy).
+struct PrimeInfo {
+    u64 q;
+    Barrett br;
+    u64 ninv, ninvp;      // N^-1 (Shoup)
+    u64 ninvw1, ninvw1p;  // N^-1 * Winv[1] (Shoup): last inverse stage
+    u64 p_mod, p_modp;    // p mod q (Shoup)
+};
+
+// Fast base conversion from one digit at one level (modulus raising).
+struct ModUpPlan {
+    int src_lo, nsrc;    // source primes [src_lo, src_lo + nsrc)
+    int ntgt;            // target limbs (extended index e, prime index)
+    int tgt_e[kMaxMod];
+    int tgt_prime[kMaxMod];
+    u64 qhinv[kMaxMod][2];          // [Qhat_i^-1]_{q_i}, Shoup
+    u64 qhat[kMaxMod][kMaxMod][2];  // [t][i]: Qhat_i mod q_t, Shoup
+};
+
+// Exact division by P (modulus lowering); independent of the level.
+struct ModDownPlan {
+    u64 vfac[kMaxMod][2];           // [p^-1 Phat_j^-1]_{p_j}
+    u64 phat[kMaxMod][kMaxMod][2];  // [i][j]: Phat_j mod q_i
+    u64 pinv[kMaxMod][2];           // P^-1 mod q_i
+    u64 ppinv[kMaxMod][2];          // p P^-1 mod q_i
+};
+
+// Dropping q_l (modulus switching at level l).
+struct ModSwitchPlan {
+    u64 pinv_l[2];         // p^-1 mod q_l
+    u64 ql;                // q_l
+    u64 qlinv[kMaxMod][2]; // q_l^-1 mod q_i
+};
+
+// Mixed-radix (Garner) reconstruction tables for decryption.
+struct GarnerTable {
+    u64 inv[kMaxMod][kMaxMod][2];  // [i][j], j < i: q_j^-1 mod q_i (Shoup)
+    u64 one_p[kMaxMod];            // floor(2^64 / q_i): Shoup reduction by 1
+    u64 mprod_p[kMaxMod];          // prod_{j < i} q_j mod p
+    u64 qprod_p[kMaxMod];          // prod_{j <= i} q_j mod p
+};
+
+// ------------------------------------------------------------ workspace pool
+
+// Caching device allocator.  A released block is handed out again only for
+// work on the same stream (stream order makes the reuse safe); the stream is
+// the calling thread's current one, set at each C-ABI entry.
+extern thread_local hipStream_t tl_stream;
+
+struct Pool {
+    std::mutex mu;
+    std::multimap<std::pair<hipStream_t, size_t>, void *> free_;
+    std::map<void *, std::pair<size_t, hipStream_t>> live_;
+    size_t held = 0;
+    bool recording = false;          // collect every block handed out (graph capture)
+    std::vector<void *> recorded;
+    void *alloc(size_t bytes);
+    // Removes the recorded blocks (all released by now) from the pool and
+    // returns them: a recorded graph keeps using them.
+    std::vector<void *> detach_recorded();
+    void release(void *p);
+    void trim();
+    ~Pool();
+};
+
+// ----------------------------------------------------------------- context
+
+// Recorded comparison circuits: one hipGraph per (call, shape, buffers) key,
+// with the workspace blocks it was recorded on (owned until destruction).
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void *> blocks;
+};
+struct GraphCache {
+    std::map<std::string, GraphEntry> entries;
+    ~GraphCache();
+};
+
+}  // namespace bc
+
+struct bc_ctx {
+    bc_params prm;
+    int N, logN, nQ, nP, nmod, dnum, alpha, M;
+    bc::u64 p;
+    std::vector<bc::u64> mod;  // host copy of the moduli
+    // device tables
+    bc::u64 *tw = nullptr;            // [nmod][4][N]: W, W', Winv, Winv'
+    bc::PrimeInfo *pinfo = nullptr;   // [nmod]
+    bc::ModUpPlan *modup = nullptr;   // [nQ][dnum]  (level, digit)
+    bc::ModDownPlan *moddown = nullptr;
+    bc::ModSwitchPlan *modsw = nullptr;  // [nQ]
+    bc::GarnerTable *garner = nullptr;
+    std::vector<bc::PrimeInfo> h_pinfo;
+    std::vector<bc::ModUpPlan> h_modup;  // host copies (launch sizing)
+    bc::Pool pool;
+    int exec_mode = BC_EXEC_BATCHED;
+    std::unique_ptr<bc::GraphCache> graphs;
+    std::mutex graph_mu;
+    hipStream_t capture_stream = nullptr;      // graph recording (created on first use)
+    std::mutex table_mu;                       // guards lt_c and ps_coef
+    std::vector<int64_t> lt_c;                 // LT polynomial coefficients
+    std::map<int, bc::u64 *> ps_coef;          // per level: block coefficients (Shoup)
+    ~bc_ctx();
+};
+
+struct bc_keys {
+    bc_ctx *ctx;
+    int ngal;
+    std::vector<int> steps;      // rotation step of each Galois key
+    std::vector<bc::u64> gal;    // Galois element
+    bc::u64 *s_ntt = nullptr;    // [nmod][N]
+    bc::u64 *pk = nullptr;       // [2][nQ][N]
+    bc::u64 *rlk = nullptr;      // [dnum][2][nmod][N]
+    std::vector<bc::u64 *> gk;   // each [dnum][2][nmod][N]
+    std::vector<bc::u32 *> perm; // NTT-domain index map of each Galois key
+    ~bc_keys();
+};
+
+namespace bc {
+
+// ----------------------------------------------------------- host helpers
+u64 h_mulmod(u64 a, u64 b, u64 q);
+u64 h_powmod(u64 b, u64 e, u64 q);
+u64 h_invmod(u64 a, u64 q);
+inline u64 h_shoup(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+int bit_reverse(int x, int bits);
+
+// ----------------------------------------------------------------- kernels
+void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
+void ntt_inverse(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
+
+}  // namespace bc

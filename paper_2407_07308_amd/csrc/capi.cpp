@@ -1,0 +1,391 @@
+// capi.cpp -- the extern "C" boundary: argument checks, error codes, the
+// per-thread error message, and hipGraph recording of comparison calls.
+
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+
+#include "ops.h"
+
+namespace bc {
+GraphCache::~GraphCache() {
+    for (auto &kv : entries) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+        for (void *p : kv.second.blocks) (void)hipFree(p);
+    }
+}
+}  // namespace bc
+
+using namespace bc;
+
+namespace {
+
+thread_local std::string tl_err;
+
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(void *s) : prev(tl_stream) { tl_stream = (hipStream_t)s; }
+    ~StreamScope() { tl_stream = prev; }
+};
+
+template <class F>
+int guard(F &&f) {
+    try {
+        f();
+        return BC_OK;
+    } catch (const Error &e) {
+        tl_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        tl_err = "host allocation failed";
+        return BC_ERR_OOM;
+    } catch (const std::exception &e) {
+        tl_err = e.what();
+        return BC_ERR_ARG;
+    }
+}
+
+void check_ctx(const bc_ctx *c) { BC_REQUIRE(c, BC_ERR_ARG, "null context"); }
+void check_keys(const bc_ctx *c, const bc_keys *k) {
+    BC_REQUIRE(k, BC_ERR_ARG, "null keys");
+    BC_REQUIRE(k->ctx == c, BC_ERR_PARAM, "keys belong to another context");
+}
+
+// Runs the comparison and copies results into the caller's buffers.
+void run_compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, const bc_ctb *lt_out,
+                 const bc_ctb *max_out, const bc_ctb *min_out, hipStream_t st) {
+    bool mm = max_out || min_out;
+    CompareResult r = compare(c, k, ndig, A, B, mm, st);
+    const int G = A[0].count;
+    if (lt_out) copy_ct(c, r.lt, from_abi(c, lt_out), st);
+    for (int d = 0; d < ndig; d++) {
+        if (max_out) copy_ct(c, r.mx.slice(d * G, G, c->N), from_abi(c, &max_out[d]), st);
+        if (min_out) copy_ct(c, r.mn.slice(d * G, G, c->N), from_abi(c, &min_out[d]), st);
+    }
+}
+
+std::string graph_key(int ndig, const bc_ctb *a, const bc_ctb *b, const bc_ctb *lt, const bc_ctb *mx,
+                      const bc_ctb *mn, void *st, const bc_keys *k) {
+    std::ostringstream os;
+    os << ndig << '|' << st << '|' << k;
+    auto put = [&](const bc_ctb *x) { os << '|' << (x ? (void *)x->data : nullptr) << ',' << (x ? x->count : 0) << ','
+                                        << (x ? x->level : 0); };
+    for (int d = 0; d < ndig; d++) {
+        put(&a[d]);
+        put(&b[d]);
+        put(mx ? &mx[d] : nullptr);
+        put(mn ? &mn[d] : nullptr);
+    }
+    put(lt);
+    return os.str();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bc_strerror(int code) {
+    switch (code) {
+        case BC_OK: return "ok";
+        case BC_ERR_ARG: return "invalid argument";
+        case BC_ERR_PARAM: return "invalid or mismatched parameters";
+        case BC_ERR_LEVEL: return "out of levels";
+        case BC_ERR_OOM: return "out of memory";
+        case BC_ERR_HIP: return "HIP runtime error";
+        case BC_ERR_KEY: return "missing switching key";
+        default: return "unknown error";
+    }
+}
+
+const char *bc_last_error(void) { return tl_err.c_str(); }
+
+int bc_ctx_create(const bc_params *prm, bc_ctx **out) {
+    return guard([&] {
+        BC_REQUIRE(prm && out, BC_ERR_ARG, "null argument");
+        std::unique_ptr<bc_ctx> c(new bc_ctx());
+        build_context(c.get(), *prm);
+        c->graphs.reset(new GraphCache());
+        *out = c.release();
+    });
+}
+
+int bc_ctx_destroy(bc_ctx *ctx) {
+    return guard([&] {
+        if (ctx) (void)hipDeviceSynchronize();
+        delete ctx;
+    });
+}
+
+int bc_ctx_moduli(const bc_ctx *ctx, uint64_t *moduli, int32_t cap) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(moduli && cap >= ctx->nmod, BC_ERR_ARG, "moduli buffer too small");
+        std::memcpy(moduli, ctx->mod.data(), sizeof(uint64_t) * ctx->nmod);
+    });
+}
+
+int bc_ctx_slots(const bc_ctx *ctx) { return ctx ? ctx->M : BC_ERR_ARG; }
+
+size_t bc_ct_words(const bc_ctx *ctx, int32_t level, int32_t ncomp) {
+    if (!ctx || level < 0 || level >= ctx->nQ || ncomp < 1 || ncomp > 3) return 0;
+    return (size_t)ncomp * (level + 1) * ctx->N;
+}
+
+size_t bc_ctx_pool_bytes(const bc_ctx *ctx) { return ctx ? ctx->pool.held : 0; }
+
+int bc_ctx_trim(bc_ctx *ctx) {
+    return guard([&] {
+        check_ctx(ctx);
+        ctx->pool.trim();
+    });
+}
+
+int bc_keygen_rand_sizes(const bc_ctx *ctx, int32_t nrot, size_t *n_words, size_t *n_errors) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(nrot >= 0 && n_words && n_errors, BC_ERR_ARG, "bad arguments");
+        *n_words = (size_t)ctx->nQ * ctx->N + (size_t)(1 + nrot) * ctx->dnum * ctx->nmod * ctx->N;
+        *n_errors = (size_t)ctx->N + (size_t)(1 + nrot) * ctx->dnum * ctx->N;
+    });
+}
+
+int bc_keygen(bc_ctx *ctx, const int8_t *s, const uint64_t *a_words, const int32_t *errors, const int32_t *rot_steps,
+              int32_t nrot, bc_keys **out) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(out, BC_ERR_ARG, "null output");
+        StreamScope sc(nullptr);
+        *out = keygen(ctx, s, a_words, errors, rot_steps, nrot);
+    });
+}
+
+int bc_keys_destroy(bc_keys *keys) {
+    return guard([&] {
+        if (keys) (void)hipDeviceSynchronize();
+        delete keys;
+    });
+}
+
+int bc_encrypt(bc_ctx *ctx, const bc_keys *keys, const uint32_t *slots, const int8_t *u, const int32_t *errors,
+               bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(out && out->data && out->count >= 1, BC_ERR_ARG, "bad output batch");
+        out->level = ctx->nQ - 1;
+        out->ncomp = 2;
+        StreamScope sc(stream);
+        encrypt(ctx, keys, slots, u, errors, from_abi(ctx, out), (hipStream_t)stream);
+    });
+}
+
+int bc_decrypt_poly(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t *coeffs, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(coeffs, BC_ERR_ARG, "null output");
+        StreamScope sc(stream);
+        decrypt_poly(ctx, keys, from_abi(ctx, in), coeffs, (hipStream_t)stream);
+    });
+}
+
+int bc_decrypt(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t *slots, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(slots, BC_ERR_ARG, "null output");
+        StreamScope sc(stream);
+        CtB x = from_abi(ctx, in);
+        std::vector<uint32_t> coeffs((size_t)x.count * ctx->N);
+        decrypt_poly(ctx, keys, x, coeffs.data(), (hipStream_t)stream);
+        decode_slots(ctx, coeffs.data(), slots, x.count);
+    });
+}
+
+int bc_export(bc_ctx *ctx, const bc_ctb *in, uint64_t *host, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        StreamScope sc(stream);
+        export_ct(ctx, from_abi(ctx, in), host, (hipStream_t)stream);
+    });
+}
+
+int bc_import(bc_ctx *ctx, const uint64_t *host, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        StreamScope sc(stream);
+        import_ct(ctx, host, from_abi(ctx, out), (hipStream_t)stream);
+    });
+}
+
+int bc_tensor(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        StreamScope sc(stream);
+        tensor(ctx, from_abi(ctx, a), from_abi(ctx, b), from_abi(ctx, out), (hipStream_t)stream);
+    });
+}
+
+int bc_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        StreamScope sc(stream);
+        relin(ctx, keys, from_abi(ctx, in), from_abi(ctx, out), (hipStream_t)stream);
+    });
+}
+
+int bc_mod_switch(bc_ctx *ctx, const bc_ctb *in, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        StreamScope sc(stream);
+        mod_switch(ctx, from_abi(ctx, in), from_abi(ctx, out), (hipStream_t)stream);
+    });
+}
+
+int bc_mul_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        StreamScope sc(stream);
+        mul_relin(ctx, keys, from_abi(ctx, a), from_abi(ctx, b), from_abi(ctx, out), (hipStream_t)stream);
+    });
+}
+
+int bc_rotate(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, int32_t steps, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        StreamScope sc(stream);
+        rotate(ctx, keys, from_abi(ctx, in), steps, from_abi(ctx, out), (hipStream_t)stream);
+    });
+}
+
+int bc_add(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        StreamScope sc(stream);
+        add_sub(ctx, from_abi(ctx, a), from_abi(ctx, b), from_abi(ctx, out), false, (hipStream_t)stream);
+    });
+}
+
+int bc_sub(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        StreamScope sc(stream);
+        add_sub(ctx, from_abi(ctx, a), from_abi(ctx, b), from_abi(ctx, out), true, (hipStream_t)stream);
+    });
+}
+
+int bc_mul_scalar(bc_ctx *ctx, const bc_ctb *a, int32_t c, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        StreamScope sc(stream);
+        mul_scalar(ctx, from_abi(ctx, a), c, from_abi(ctx, out), (hipStream_t)stream);
+    });
+}
+
+int bc_add_const(bc_ctx *ctx, const bc_ctb *a, int32_t c, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        StreamScope sc(stream);
+        add_const(ctx, from_abi(ctx, a), c, from_abi(ctx, out), (hipStream_t)stream);
+    });
+}
+
+int bc_compare_levels(const bc_ctx *ctx, int32_t in_level, int32_t ndigits, int32_t *lt_level, int32_t *maxmin_level) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(in_level >= 0 && in_level < ctx->nQ && ndigits >= 1, BC_ERR_ARG, "bad level or digit count");
+        int lt = 0, mm = 0;
+        compare_levels(ctx, in_level, ndigits, &lt, &mm);
+        if (lt_level) *lt_level = lt;
+        if (maxmin_level) *maxmin_level = mm;
+    });
+}
+
+int bc_set_exec_mode(bc_ctx *ctx, int32_t mode) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(mode == BC_EXEC_BATCHED || mode == BC_EXEC_GRAPH, BC_ERR_ARG, "unknown execution mode");
+        ctx->exec_mode = mode;
+    });
+}
+
+int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits,
+                       const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(a_digits && b_digits && ndigits >= 1 && ndigits <= 16, BC_ERR_ARG, "bad digit planes");
+        BC_REQUIRE(lt_out || max_out || min_out, BC_ERR_ARG, "no output requested");
+        std::vector<CtB> A, B;
+        for (int d = 0; d < ndigits; d++) {
+            A.push_back(from_abi(ctx, &a_digits[d]));
+            B.push_back(from_abi(ctx, &b_digits[d]));
+        }
+        int ltl = 0, mml = 0;
+        compare_levels(ctx, A[0].level, ndigits, &ltl, &mml);
+        auto want = [&](const bc_ctb *x, int lv) {
+            CtB o = from_abi(ctx, x);
+            BC_REQUIRE(o.count == A[0].count && o.level == lv && o.ncomp == 2, BC_ERR_ARG,
+                       "output batch: wrong count, level or components");
+        };
+        if (lt_out) want(lt_out, ltl);
+        for (int d = 0; d < ndigits; d++) {
+            if (max_out) want(&max_out[d], mml);
+            if (min_out) want(&min_out[d], mml);
+        }
+        hipStream_t st = (hipStream_t)stream;
+        StreamScope sc(stream);
+        if (ctx->exec_mode != BC_EXEC_GRAPH) {
+            run_compare(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, st);
+            return;
+        }
+        std::string key = graph_key(ndigits, a_digits, b_digits, lt_out, max_out, min_out, stream, keys);
+        std::lock_guard<std::mutex> g(ctx->graph_mu);
+        auto it = ctx->graphs->entries.find(key);
+        if (it != ctx->graphs->entries.end()) {
+            BC_HIP(hipGraphLaunch(it->second.exec, st));
+            return;
+        }
+        // First call of this shape: run eagerly (warms the pool and the
+        // coefficient tables), then record the same launch sequence.
+        run_compare(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, st);
+        BC_HIP(hipStreamSynchronize(st));
+        GraphEntry e;
+        {
+            std::lock_guard<std::mutex> pg(ctx->pool.mu);
+            ctx->pool.recording = true;
+            ctx->pool.recorded.clear();
+        }
+        // Record on a private stream (the legacy default stream cannot be
+        // captured); the workspace lookups still use the caller's stream tag,
+        // so the recording reuses the blocks of the eager run above.
+        if (!ctx->capture_stream) BC_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        hipStream_t cap = ctx->capture_stream;
+        BC_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+        try {
+            run_compare(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, cap);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(cap, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            std::lock_guard<std::mutex> pg(ctx->pool.mu);
+            ctx->pool.recording = false;
+            throw;
+        }
+        BC_HIP(hipStreamEndCapture(cap, &e.graph));
+        BC_HIP(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+        e.blocks = ctx->pool.detach_recorded();
+        ctx->graphs->entries.emplace(key, std::move(e));
+    });
+}
+
+int bc_compare_lt(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits, const bc_ctb *b_digits,
+                  bc_ctb *out, void *stream) {
+    return bc_compare_max_min(ctx, keys, ndigits, a_digits, b_digits, out, nullptr, nullptr, stream);
+}
+
+}  // extern "C"

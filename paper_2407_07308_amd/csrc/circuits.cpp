@@ -1,0 +1,229 @@
+// circuits.cpp -- the univariate less-than circuit, lexicographic combination,
+// max / min, on batches of digit planes.
+//
+// Paper, Introduction: the univariate circuit computes LT(X, Y) = f(X - Y)
+// with about sqrt(p-3) + O(log p) non-scalar multiplications.  Paper,
+// Background, "Word-wise Universal FHE Scheme": integers are split into F_p
+// digits, LT and EQ are evaluated per digit and combined in lexicographic
+// order.  f is the degree p-1 interpolant of the indicator of
+// [(p+1)/2, p-1] (x - y "negative"); it is exact as [x < y] for digits in
+// [0, (p-1)/2].
+//
+// Batching: every plane of every group is one ciphertext of a single batch,
+// so each step of the schedule is one launch sequence for the whole batch;
+// the Paterson-Stockmeyer blocks are laid out in bit-reversed block order so
+// that every round of the block tree is one batched multiplication.
+
+#include <algorithm>
+
+#include "ops.h"
+
+namespace bc {
+
+namespace {
+
+// c_k = -sum_{z in [(p+1)/2, p-1]} z^(-k) mod p (k = 1 .. p-1), c_0 = 0: the
+// inverse transform over F_p^* of the indicator (sum_z z^(j-k) = -[j = k mod p-1]).
+std::vector<int64_t> lt_coefficients(u64 p) {
+    std::vector<int64_t> c(p, 0);
+    for (u64 k = 1; k <= p - 1; k++) {
+        u64 s = 0;
+        for (u64 z = (p + 1) / 2; z <= p - 1; z++) s = (s + h_powmod(h_invmod(z, p), k, p)) % p;
+        c[k] = (int64_t)((p - s) % p);
+    }
+    return c;
+}
+
+struct Shape {
+    int e, b, nblk;
+    std::vector<int> odd;
+};
+
+Shape ps_shape(u64 p) {
+    u64 pm1 = p - 1;
+    BC_REQUIRE((pm1 & (pm1 - 1)) == 0, BC_ERR_PARAM, "the comparison schedule needs p - 1 a power of two");
+    Shape s;
+    s.e = __builtin_ctzll(pm1);
+    s.b = 1 << ((s.e + 1) / 2);
+    s.nblk = (int)(pm1 / s.b);
+    for (int k = 1; k < s.b; k += 2) s.odd.push_back(k);
+    return s;
+}
+
+// ---------------------------------------------------------------- evaluators
+
+struct LevelEval {
+    typedef int V;
+    int count = 1;
+    V mul(V a, V b) { return out_level_mul(a, b); }
+    V add(V a, V b) { return std::min(a, b); }
+    V sub(V a, V b) { return std::min(a, b); }
+    V mul_scalar(V a, int64_t) { return a; }
+    V add_const(V a, int64_t) { return a; }
+    int level(V a) { return a; }
+    V to_level(V a, int lv) { return std::min(a, lv); }
+    V blocks(const std::vector<V> &babies, int, int) { return babies[0]; }
+    V slice(V a, int, int) { return a; }
+};
+
+struct DevEval {
+    typedef CtB V;
+    bc_ctx *c;
+    const bc_keys *k;
+    hipStream_t st;
+    V mul(const V &a, const V &b) { return bc::mul(c, k, a, b, st); }
+    V add(const V &a, const V &b) { return bc::add(c, a, b, st); }
+    V sub(const V &a, const V &b) { return bc::sub(c, a, b, st); }
+    V mul_scalar(const V &a, int64_t v) {
+        V o = alloc_ct(c, a.count, a.level, a.ncomp);
+        bc::mul_scalar(c, a, v, o, st);
+        return o;
+    }
+    V add_const(const V &a, int64_t v) {
+        V o = alloc_ct(c, a.count, a.level, a.ncomp);
+        bc::add_const(c, a, v, o, st);
+        return o;
+    }
+    int level(const V &a) { return a.level; }
+    V to_level(const V &a, int lv) { return bc::to_level(c, a, lv, st); }
+    V slice(const V &a, int first, int n) { return a.slice(first, n, c->N); }
+    // blocks B_t = sum_{k odd < b} c_{tb+k} Z^k for every t, stored at bit-reversed t
+    V blocks(const std::vector<V> &babies, int b, int nblk);
+};
+
+const u64 *ps_coef_table(bc_ctx *c, int level, int b, int nblk) {
+    std::lock_guard<std::mutex> g(c->table_mu);
+    auto it = c->ps_coef.find(level);
+    if (it != c->ps_coef.end()) return it->second;
+    if (c->lt_c.empty()) c->lt_c = lt_coefficients(c->p);
+    const int nbaby = b / 2, nl = level + 1;
+    std::vector<u64> tab((size_t)nblk * nbaby * nl * 2);
+    for (int t = 0; t < nblk; t++)
+        for (int kk = 0; kk < nbaby; kk++) {
+            int64_t cv = centred(c, c->lt_c[(size_t)t * b + 2 * kk + 1]);
+            for (int i = 0; i < nl; i++) {
+                u64 q = c->mod[i];
+                u64 r = cv >= 0 ? (u64)cv % q : q - (u64)(-cv) % q;
+                u64 *w = &tab[(((size_t)t * nbaby + kk) * nl + i) * 2];
+                w[0] = r % q;
+                w[1] = h_shoup(w[0], q);
+            }
+        }
+    u64 *d = nullptr;
+    BC_HIP(hipMalloc(&d, sizeof(u64) * tab.size()));
+    BC_HIP(hipMemcpy(d, tab.data(), sizeof(u64) * tab.size(), hipMemcpyHostToDevice));
+    c->ps_coef[level] = d;
+    return d;
+}
+
+DevEval::V DevEval::blocks(const std::vector<V> &babies, int b, int nblk) {
+    const int count = babies[0].count, lv = babies[0].level, nbaby = (int)babies.size();
+    const u64 *coef = ps_coef_table(c, lv, b, nblk);
+    V out = alloc_ct(c, nblk * count, lv, 2);
+    std::vector<const u64 *> bp;
+    for (auto &x : babies) bp.push_back(x.data);
+    int bits = __builtin_ctz(nblk);
+    std::vector<int> pos(nblk);
+    for (int t = 0; t < nblk; t++) pos[t] = bit_reverse(t, bits);
+    launch_lincomb(c, bp.data(), pos.data(), coef, out.data, nbaby, nblk, count, lv + 1, st);
+    BC_HIP(hipGetLastError());
+    return out;
+}
+
+// f(Z) and Z^(p-1) by the Paterson-Stockmeyer schedule described above.
+template <class Ev>
+std::pair<typename Ev::V, typename Ev::V> lt_poly(Ev &ev, const typename Ev::V &Z, const Shape &sh, int count,
+                                                  int64_t ctop) {
+    typedef typename Ev::V V;
+    const int b = sh.b;
+    std::vector<V> pw(b + 1);
+    std::vector<bool> have(b + 1, false);
+    pw[1] = Z;
+    have[1] = true;
+    for (int a = 1; 2 * a <= b / 2; a *= 2) {
+        pw[2 * a] = ev.mul(pw[a], pw[a]);
+        have[2 * a] = true;
+    }
+    for (int k = 3; k < b; k += 2) {
+        int hi = 1 << (31 - __builtin_clz(k));
+        pw[k] = ev.mul(pw[hi], pw[k - hi]);
+        have[k] = true;
+    }
+    std::vector<V> giants;
+    giants.push_back(b >= 2 ? ev.mul(pw[b / 2], pw[b / 2]) : Z);
+    while (((int64_t)b << giants.size()) <= (int64_t)(sh.nblk * b)) giants.push_back(ev.mul(giants.back(), giants.back()));
+    int lv = ev.level(pw[1]);
+    for (int k : sh.odd) lv = std::min(lv, ev.level(pw[k]));
+    std::vector<V> babies;
+    for (int k : sh.odd) babies.push_back(ev.to_level(pw[k], lv));
+    V H = ev.blocks(babies, b, sh.nblk);
+    int len = sh.nblk, r = 0;
+    while (len > 1) {
+        int half = len / 2;
+        V lo = ev.slice(H, 0, half * count), hi = ev.slice(H, half * count, half * count);
+        V prod = ev.mul(hi, giants[r]);
+        H = ev.add(lo, prod);
+        len = half;
+        r++;
+    }
+    V f = ev.add(H, ev.mul_scalar(giants.back(), ctop));
+    return {f, giants.back()};
+}
+
+// LT over planes (plane-major batches of `count` groups), EQ_d = 1 - Z_d^(p-1),
+// LT = LT_0 + EQ_0 (LT_1 + EQ_1 (... LT_{n-1})).
+template <class Ev>
+typename Ev::V lexicographic(Ev &ev, const typename Ev::V &f, const typename Ev::V &top, int ndig, int count) {
+    typedef typename Ev::V V;
+    V eq = ev.add_const(ev.mul_scalar(top, -1), 1);
+    V acc = ev.slice(f, (ndig - 1) * count, count);
+    for (int d = ndig - 2; d >= 0; d--)
+        acc = ev.add(ev.slice(f, d * count, count), ev.mul(ev.slice(eq, d * count, count), acc));
+    return acc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- entry points
+
+CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, bool want_mm, hipStream_t st) {
+    BC_REQUIRE(ndig >= 1 && ndig <= 16, BC_ERR_ARG, "ndigits must be in [1, 16]");
+    const int G = A[0].count, L0 = A[0].level;
+    for (int d = 0; d < ndig; d++) {
+        BC_REQUIRE(A[d].count == G && B[d].count == G, BC_ERR_ARG, "every plane needs the same count");
+        BC_REQUIRE(A[d].level == L0 && B[d].level == L0, BC_ERR_ARG, "every plane needs the same level");
+        BC_REQUIRE(A[d].ncomp == 2 && B[d].ncomp == 2, BC_ERR_ARG, "planes must have 2 components");
+    }
+    Shape sh = ps_shape(c->p);
+    if (c->lt_c.empty()) {
+        std::lock_guard<std::mutex> g(c->table_mu);
+        if (c->lt_c.empty()) c->lt_c = lt_coefficients(c->p);
+    }
+    DevEval ev{c, k, st};
+    CtB Aall = alloc_ct(c, ndig * G, L0, 2), Ball = alloc_ct(c, ndig * G, L0, 2);
+    for (int d = 0; d < ndig; d++) {
+        copy_ct(c, A[d], Aall.slice(d * G, G, c->N), st);
+        copy_ct(c, B[d], Ball.slice(d * G, G, c->N), st);
+    }
+    CtB Z = bc::sub(c, Aall, Ball, st);
+    auto fz = lt_poly(ev, Z, sh, ndig * G, c->lt_c[c->p - 1]);
+    Z = CtB();
+    CompareResult r;
+    r.lt = lexicographic(ev, fz.first, fz.second, ndig, G);
+    if (want_mm) {
+        r.mx = ev.add(Aall, ev.mul(ev.sub(Ball, Aall), r.lt));
+        r.mn = ev.add(Ball, ev.mul(ev.sub(Aall, Ball), r.lt));
+    }
+    return r;
+}
+
+void compare_levels(const bc_ctx *c, int in_level, int ndig, int *lt_level, int *mm_level) {
+    Shape sh = ps_shape(c->p);
+    LevelEval ev;
+    auto fz = lt_poly(ev, in_level, sh, 1, 0);
+    int lt = lexicographic(ev, fz.first, fz.second, ndig, 1);
+    if (lt_level) *lt_level = lt;
+    if (mm_level) *mm_level = ev.add(in_level, ev.mul(ev.sub(in_level, in_level), lt));
+}
+
+}  // namespace bc

@@ -1,0 +1,370 @@
+// context.cpp -- parameter set, prime chain and every precomputed table.
+//
+// All tables are built once per context and kept in HBM (the device-side
+// analogue of the paper's plan reuse, "GPU-related Optimizations": work that
+// does not depend on the data leaves the critical path).
+
+#include <algorithm>
+#include <cstring>
+
+#include "bc_internal.h"
+
+namespace bc {
+
+u64 h_mulmod(u64 a, u64 b, u64 q) { return (u64)(((u128)a * b) % q); }
+
+u64 h_powmod(u64 b, u64 e, u64 q) {
+    u64 r = 1 % q;
+    b %= q;
+    for (; e; e >>= 1) {
+        if (e & 1) r = h_mulmod(r, b, q);
+        b = h_mulmod(b, b, q);
+    }
+    return r;
+}
+
+u64 h_invmod(u64 a, u64 q) {
+    // extended Euclid on signed 128-bit values
+    __int128 t = 0, nt = 1, r = q, nr = a % q;
+    while (nr != 0) {
+        __int128 k = r / nr, tmp = t - k * nt;
+        t = nt;
+        nt = tmp;
+        tmp = r - k * nr;
+        r = nr;
+        nr = tmp;
+    }
+    if (t < 0) t += q;
+    return (u64)t;
+}
+
+int bit_reverse(int x, int bits) {
+    int r = 0;
+    for (int i = 0; i < bits; i++) r |= ((x >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+
+namespace {
+
+// Miller-Rabin with the seven bases of J. Sinclair, deterministic for n < 2^64.
+bool is_prime64(u64 n) {
+    if (n < 4) return n >= 2;
+    if (n % 2 == 0) return false;
+    u64 d = n - 1;
+    int s = __builtin_ctzll(d);
+    d >>= s;
+    static const u64 bases[] = {2, 325, 9375, 28178, 450775, 9780504, 1795265022};
+    for (u64 a : bases) {
+        a %= n;
+        if (a == 0) continue;
+        u64 x = h_powmod(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool witness = true;
+        for (int r = 1; r < s && witness; r++) {
+            x = h_mulmod(x, x, n);
+            if (x == n - 1) witness = false;
+        }
+        if (witness) return false;
+    }
+    return true;
+}
+
+// Largest `count` primes p < 2^bits with p = 1 mod step, skipping `taken`.
+std::vector<u64> prime_chain(u64 step, int bits, int count, const std::vector<u64> &taken) {
+    std::vector<u64> out;
+    u64 limit = (bits >= 64) ? ~(u64)0 : ((u64)1 << bits);
+    u64 k = (limit - 2) / step;
+    for (; k > 0 && (int)out.size() < count; k--) {
+        u64 c = k * step + 1;
+        if (std::find(taken.begin(), taken.end(), c) != taken.end()) continue;
+        if (is_prime64(c)) out.push_back(c);
+    }
+    if ((int)out.size() != count) throw Error(BC_ERR_PARAM, "not enough primes of the requested size");
+    return out;
+}
+
+// Primitive 2N-th root of unity: g^((q-1)/2N) for a generator g of Z_q^*.
+u64 root_2n(u64 q, int N) {
+    u64 phi = q - 1, n = phi;
+    std::vector<u64> fac;
+    for (u64 f = 2; f * f <= n; f += (f == 2 ? 1 : 2))
+        if (n % f == 0) {
+            fac.push_back(f);
+            while (n % f == 0) n /= f;
+        }
+    if (n > 1) fac.push_back(n);
+    for (u64 g = 2;; g++) {
+        bool gen = true;
+        for (u64 f : fac)
+            if (h_powmod(g, phi / f, q) == 1) { gen = false; break; }
+        if (gen) return h_powmod(g, phi / (2 * (u64)N), q);
+    }
+}
+
+template <class T>
+T *upload(const T *h, size_t n) {
+    T *d = nullptr;
+    BC_HIP(hipMalloc(&d, sizeof(T) * n));
+    BC_HIP(hipMemcpy(d, h, sizeof(T) * n, hipMemcpyHostToDevice));
+    return d;
+}
+
+void set_shoup(u64 dst[2], u64 w, u64 q) {
+    dst[0] = w % q;
+    dst[1] = h_shoup(dst[0], q);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ pool
+
+thread_local hipStream_t tl_stream = nullptr;
+
+void *Pool::alloc(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    std::lock_guard<std::mutex> g(mu);
+    const hipStream_t st = tl_stream;
+    auto it = free_.lower_bound({st, bytes});
+    if (it != free_.end() && it->first.first == st && it->first.second <= bytes + bytes / 8) {
+        void *p = it->second;
+        live_[p] = {it->first.second, st};
+        free_.erase(it);
+        if (recording) recorded.push_back(p);
+        return p;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        // give back cached blocks of this stream and retry once
+        for (auto i = free_.begin(); i != free_.end();) {
+            if (i->first.first == st) {
+                (void)hipFree(i->second);
+                held -= i->first.second;
+                i = free_.erase(i);
+            } else {
+                ++i;
+            }
+        }
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(BC_ERR_OOM, "device workspace allocation failed");
+        }
+    }
+    held += bytes;
+    live_[p] = {bytes, st};
+    if (recording) recorded.push_back(p);
+    return p;
+}
+
+std::vector<void *> Pool::detach_recorded() {
+    std::lock_guard<std::mutex> g(mu);
+    recording = false;
+    std::vector<void *> out;
+    for (void *p : recorded) {
+        if (std::find(out.begin(), out.end(), p) != out.end()) continue;
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second == p) {
+                held -= it->first.second;
+                free_.erase(it);
+                out.push_back(p);
+                break;
+            }
+    }
+    recorded.clear();
+    return out;
+}
+
+void Pool::release(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    free_.emplace(std::make_pair(it->second.second, it->second.first), p);
+    live_.erase(it);
+}
+
+void Pool::trim() {
+    std::lock_guard<std::mutex> g(mu);
+    for (auto &kv : free_) {
+        (void)hipFree(kv.second);
+        held -= kv.first.second;
+    }
+    free_.clear();
+}
+
+Pool::~Pool() {
+    for (auto &kv : free_) (void)hipFree(kv.second);
+    for (auto &kv : live_) (void)hipFree(kv.first);
+}
+
+// ----------------------------------------------------------------- context
+
+void build_context(bc_ctx *c, const bc_params &prm) {
+    BC_REQUIRE(prm.logN >= 10 && prm.logN <= 16, BC_ERR_PARAM, "logN must be in [10, 16]");
+    BC_REQUIRE(prm.p >= 3 && prm.p < (1 << 20), BC_ERR_PARAM, "p must be a small odd prime");
+    BC_REQUIRE(is_prime64((u64)prm.p), BC_ERR_PARAM, "p must be prime");
+    BC_REQUIRE(prm.nQ >= 1 && prm.nP >= 1 && prm.nQ + prm.nP <= kMaxMod, BC_ERR_PARAM, "bad prime counts");
+    BC_REQUIRE(prm.bitsQ >= 20 && prm.bitsQ <= 61 && prm.bitsP >= 20 && prm.bitsP <= 61, BC_ERR_PARAM,
+               "prime sizes must be in [20, 61] bits");
+    BC_REQUIRE(prm.dnum >= 1 && prm.dnum <= prm.nQ, BC_ERR_PARAM, "dnum must be in [1, nQ]");
+    c->prm = prm;
+    c->logN = prm.logN;
+    c->N = 1 << prm.logN;
+    c->nQ = prm.nQ;
+    c->nP = prm.nP;
+    c->nmod = prm.nQ + prm.nP;
+    c->dnum = prm.dnum;
+    c->alpha = (prm.nQ + prm.dnum - 1) / prm.dnum;
+    c->p = (u64)prm.p;
+    u64 pm1 = c->p - 1;
+    int s2 = __builtin_ctzll(pm1);
+    c->M = 1 << (s2 - 1);
+    BC_REQUIRE(c->M <= c->N, BC_ERR_PARAM, "more slots than coefficients");
+
+    const int N = c->N, nQ = c->nQ, nP = c->nP, nm = c->nmod;
+    const u64 step = 2 * (u64)N * c->p;
+    c->mod = prime_chain(step, prm.bitsQ, nQ, {});
+    auto sp = prime_chain(step, prm.bitsP, nP, c->mod);
+    c->mod.insert(c->mod.end(), sp.begin(), sp.end());
+
+    // twiddles and per-prime constants
+    std::vector<u64> tw((size_t)nm * 4 * N);
+    c->h_pinfo.resize(nm);
+    for (int m = 0; m < nm; m++) {
+        u64 q = c->mod[m];
+        u64 psi = root_2n(q, N), ipsi = h_invmod(psi, q);
+        u64 *W = &tw[(size_t)m * 4 * N], *Wp = W + N, *Wi = W + 2 * N, *Wip = W + 3 * N;
+        std::vector<u64> pw(N), ipw(N);
+        pw[0] = ipw[0] = 1;
+        for (int k = 1; k < N; k++) {
+            pw[k] = h_mulmod(pw[k - 1], psi, q);
+            ipw[k] = h_mulmod(ipw[k - 1], ipsi, q);
+        }
+        for (int k = 0; k < N; k++) {
+            int r = bit_reverse(k, c->logN);
+            W[k] = pw[r];
+            Wi[k] = ipw[r];
+            Wp[k] = h_shoup(W[k], q);
+            Wip[k] = h_shoup(Wi[k], q);
+        }
+        PrimeInfo &pi = c->h_pinfo[m];
+        pi.q = q;
+        int s = 64 - __builtin_clzll(q);
+        pi.br.q = q;
+        pi.br.sh = s - 2;
+        pi.br.mu = (u64)(((u128)1 << (62 + s)) / q);
+        pi.ninv = h_invmod((u64)N, q);
+        pi.ninvp = h_shoup(pi.ninv, q);
+        pi.ninvw1 = h_mulmod(pi.ninv, Wi[1], q);
+        pi.ninvw1p = h_shoup(pi.ninvw1, q);
+        pi.p_mod = c->p % q;
+        pi.p_modp = h_shoup(pi.p_mod, q);
+    }
+    c->tw = upload(tw.data(), tw.size());
+    c->pinfo = upload(c->h_pinfo.data(), nm);
+
+    // modulus raising plans, one per (level, digit)
+    c->h_modup.assign((size_t)nQ * c->dnum, ModUpPlan{});
+    for (int lv = 0; lv < nQ; lv++)
+        for (int j = 0; j < c->dnum; j++) {
+            ModUpPlan &pl = c->h_modup[(size_t)lv * c->dnum + j];
+            int lo = j * c->alpha, hi = std::min(std::min((j + 1) * c->alpha, nQ), lv + 1);
+            pl.src_lo = lo;
+            pl.nsrc = std::max(0, hi - lo);
+            pl.ntgt = 0;
+            if (pl.nsrc == 0) continue;
+            for (int i = lo; i < hi; i++) {
+                u64 q = c->mod[i], prod = 1;
+                for (int t = lo; t < hi; t++)
+                    if (t != i) prod = h_mulmod(prod, c->mod[t] % q, q);
+                set_shoup(pl.qhinv[i - lo], h_invmod(prod, q), q);
+            }
+            int next = lv + 1 + nP;
+            for (int e = 0; e < next; e++) {
+                if (e >= lo && e < hi) continue;
+                int prime = e <= lv ? e : nQ + (e - lv - 1);
+                u64 q = c->mod[prime];
+                int t = pl.ntgt++;
+                pl.tgt_e[t] = e;
+                pl.tgt_prime[t] = prime;
+                for (int i = lo; i < hi; i++) {
+                    u64 prod = 1;
+                    for (int k = lo; k < hi; k++)
+                        if (k != i) prod = h_mulmod(prod, c->mod[k] % q, q);
+                    set_shoup(pl.qhat[t][i - lo], prod, q);
+                }
+            }
+        }
+    c->modup = upload(c->h_modup.data(), c->h_modup.size());
+
+    // modulus lowering (exact division by P)
+    auto md = std::make_unique<ModDownPlan>();
+    std::memset(md.get(), 0, sizeof(ModDownPlan));
+    for (int j = 0; j < nP; j++) {
+        u64 pj = c->mod[nQ + j], prod = 1;
+        for (int t = 0; t < nP; t++)
+            if (t != j) prod = h_mulmod(prod, c->mod[nQ + t] % pj, pj);
+        set_shoup(md->vfac[j], h_mulmod(h_invmod(c->p % pj, pj), h_invmod(prod, pj), pj), pj);
+    }
+    for (int i = 0; i < nQ; i++) {
+        u64 q = c->mod[i], P = 1;
+        for (int j = 0; j < nP; j++) {
+            u64 prod = 1;
+            for (int t = 0; t < nP; t++)
+                if (t != j) prod = h_mulmod(prod, c->mod[nQ + t] % q, q);
+            set_shoup(md->phat[i][j], prod, q);
+            P = h_mulmod(P, c->mod[nQ + j] % q, q);
+        }
+        u64 Pinv = h_invmod(P, q);
+        set_shoup(md->pinv[i], Pinv, q);
+        set_shoup(md->ppinv[i], h_mulmod(Pinv, c->p % q, q), q);
+    }
+    c->moddown = upload(md.get(), 1);
+
+    // modulus switching plans
+    std::vector<ModSwitchPlan> ms(nQ);
+    std::memset(ms.data(), 0, sizeof(ModSwitchPlan) * nQ);
+    for (int lv = 1; lv < nQ; lv++) {
+        u64 ql = c->mod[lv];
+        ms[lv].ql = ql;
+        set_shoup(ms[lv].pinv_l, h_invmod(c->p % ql, ql), ql);
+        for (int i = 0; i < lv; i++) set_shoup(ms[lv].qlinv[i], h_invmod(ql % c->mod[i], c->mod[i]), c->mod[i]);
+    }
+    c->modsw = upload(ms.data(), nQ);
+
+    // decryption: Garner tables
+    auto g = std::make_unique<GarnerTable>();
+    std::memset(g.get(), 0, sizeof(GarnerTable));
+    u64 run = 1 % c->p;
+    for (int i = 0; i < nQ; i++) {
+        u64 q = c->mod[i];
+        for (int j = 0; j < i; j++) set_shoup(g->inv[i][j], h_invmod(c->mod[j] % q, q), q);
+        g->one_p[i] = (u64)(((u128)1 << 64) / q);
+        g->mprod_p[i] = run;
+        run = h_mulmod(run, q % c->p, c->p);
+        g->qprod_p[i] = run;
+    }
+    c->garner = upload(g.get(), 1);
+}
+
+}  // namespace bc
+
+bc_ctx::~bc_ctx() {
+    graphs.reset();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    (void)hipFree(tw);
+    (void)hipFree(pinfo);
+    (void)hipFree(modup);
+    (void)hipFree(moddown);
+    (void)hipFree(modsw);
+    (void)hipFree(garner);
+    for (auto &kv : ps_coef) (void)hipFree(kv.second);
+}
+
+bc_keys::~bc_keys() {
+    (void)hipFree(s_ntt);
+    (void)hipFree(pk);
+    (void)hipFree(rlk);
+    for (auto p : gk) (void)hipFree(p);
+    for (auto p : perm) (void)hipFree(p);
+}

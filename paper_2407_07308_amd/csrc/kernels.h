@@ -1,0 +1,42 @@
+// kernels.h -- host launchers of the element-wise and conversion kernels.
+#pragma once
+
+#include "bc_internal.h"
+
+namespace bc {
+
+void build_context(bc_ctx *c, const bc_params &prm);
+
+void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, hipStream_t st);
+void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, int ncomp,
+                   bool sub, hipStream_t st);
+void launch_mul_scalar(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st);
+void launch_add_const(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st);
+void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, int count, int nl, int ncomp,
+                    hipStream_t st);
+void launch_ks_prepare(const bc_ctx *c, const u64 *x, size_t x_ct_stride, u64 *mu, u64 *xc, int count, int nl,
+                       int next, hipStream_t st);
+void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, hipStream_t st);
+void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *key, u64 *acc, int count, int level, int next,
+                     int nact, hipStream_t st);
+void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, hipStream_t st);
+void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size_t base_ct_stride, const u64 *acc,
+                       const u64 *th, u64 *out, size_t out_ct_stride, int count, int level, int next, hipStream_t st);
+void launch_ms_top(const bc_ctx *c, const u64 *in, u64 *top, int count, int nl, hipStream_t st);
+void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st);
+void launch_ms_combine(const bc_ctx *c, const u64 *in, const u64 *R, u64 *out, int count, int level, hipStream_t st);
+void launch_words_mod(const bc_ctx *c, const u64 *w, u64 *out, const int16_t *primes, int npoly, int nlimb,
+                      hipStream_t st);
+void launch_lift_small(const bc_ctx *c, const int32_t *v32, const int8_t *v8, size_t vstride, const uint32_t *add,
+                       u64 *out, const int16_t *primes, int npoly, int nlimb, bool use_p, hipStream_t st);
+void launch_keypair(const bc_ctx *c, const u64 *A, const u64 *E, const u64 *S, const u64 *S2, const u64 *f, u64 *k0,
+                    u64 *k1, int nlimb, hipStream_t st);
+void launch_pmul(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int nlimb, hipStream_t st);
+void launch_enc_combine(const bc_ctx *c, const u64 *pk, const u64 *U, const u64 *E0, const u64 *E1, u64 *out, int count,
+                        hipStream_t st);
+void launch_dec_inner(const bc_ctx *c, const u64 *ct, const u64 *s, u64 *d, int count, int nl, int ncomp, hipStream_t st);
+void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *pos, const u64 *coef, u64 *out, int nbaby,
+                    int nblk, int count, int nl, hipStream_t st);
+void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st);
+
+}  // namespace bc

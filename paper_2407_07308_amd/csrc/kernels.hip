@@ -1,0 +1,449 @@
+// kernels.hip -- element-wise, base-conversion and key-switching kernels.
+//
+// Every ciphertext limb is a contiguous run of N uint64 residues; a batch is
+// [count][ncomp][nlimb][N].  Kernels use a 3-D grid: x covers the N
+// coefficients of a limb (256 per workgroup, fully coalesced), y the limb, z
+// the ciphertext of the batch, so no kernel divides by a runtime size.  These
+// are the element-wise operations the paper offloads as whole residue
+// matrices (paper, "GPU-related Optimizations": one launch over the
+// (L+1) x N matrix instead of one per row), plus the base conversions of
+// hybrid key switching and modulus switching.
+
+#include "kernels.h"
+
+namespace bc {
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ __forceinline__ int ext_prime(int e, int level, int nQ) { return e <= level ? e : nQ + (e - level - 1); }
+
+// ------------------------------------------------------------ ring ops
+
+__global__ void k_tensor(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 *__restrict__ out, int bcount,
+                         int nl, const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const size_t L = (size_t)nl * N;
+    const u64 *A = a + (size_t)ct * 2 * L + (size_t)i * N + n;
+    const u64 *B = b + (size_t)(ct % bcount) * 2 * L + (size_t)i * N + n;
+    u64 *O = out + (size_t)ct * 3 * L + (size_t)i * N + n;
+    const Barrett br = pinfo[i].br;
+    u64 a0 = A[0], a1 = A[L], b0 = B[0], b1 = B[L];
+    O[0] = mul_mod(a0, b0, br);
+    O[L] = add_mod(mul_mod(a0, b1, br), mul_mod(a1, b0, br), br.q);
+    O[2 * L] = mul_mod(a1, b1, br);
+}
+
+// out = a + sgn * b on ncomp components (sgn = +1 / -1)
+__global__ void k_addsub(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 *__restrict__ out, int bcount,
+                         int nl, int ncomp, int sub, const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const size_t L = (size_t)nl * N;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < ncomp; c++) {
+        size_t off = (size_t)c * L + (size_t)i * N + n;
+        u64 x = a[(size_t)ct * ncomp * L + off], y = b[(size_t)(ct % bcount) * ncomp * L + off];
+        out[(size_t)ct * ncomp * L + off] = sub ? sub_mod(x, y, q) : add_mod(x, y, q);
+    }
+}
+
+struct ScalarArg {
+    u64 w[kMaxMod][2];
+};
+
+__global__ void k_mul_scalar(const u64 *__restrict__ a, u64 *__restrict__ out, int nl, int ncomp, ScalarArg s,
+                             const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const size_t L = (size_t)nl * N;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < ncomp; c++) {
+        size_t off = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N + n;
+        out[off] = shoup(a[off], s.w[i][0], s.w[i][1], q);
+    }
+}
+
+// constant polynomial c: every evaluation of component 0 gains c mod q_i
+__global__ void k_add_const(const u64 *__restrict__ a, u64 *__restrict__ out, int nl, int ncomp, ScalarArg s,
+                            const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const size_t L = (size_t)nl * N;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < ncomp; c++) {
+        size_t off = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N + n;
+        u64 x = a[off];
+        out[off] = c == 0 ? add_mod(x, s.w[i][0], q) : x;
+    }
+}
+
+// out[ct][c][i][r] = in[ct][c][i][perm[r]]
+__global__ void k_permute(const u64 *__restrict__ in, u64 *__restrict__ out, const u32 *__restrict__ perm, int nl,
+                          int ncomp, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const size_t L = (size_t)nl * N;
+    const u32 src = perm[n];
+    for (int c = 0; c < ncomp; c++) {
+        size_t base = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N;
+        out[base + n] = in[base + src];
+    }
+}
+
+// ------------------------------------------------------- key switching
+
+// X[ct] (component `comp` of a batch, NTT domain) -> the digit-own limbs of
+// MU[ct][j][e] and a coefficient-domain staging copy XC[ct][i].
+__global__ void k_ks_prepare(const u64 *__restrict__ x, size_t x_ct_stride, u64 *__restrict__ mu, u64 *__restrict__ xc,
+                             int nl, int next, int dnum, int alpha, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    u64 v = x[(size_t)ct * x_ct_stride + (size_t)i * N + n];
+    int j = i / alpha;
+    mu[(((size_t)ct * dnum + j) * next + i) * N + n] = v;
+    xc[((size_t)ct * nl + i) * N + n] = v;
+}
+
+// Fast base conversion of digit j (z-grid = ct * dnum + j):
+// y_i = [x_i Qhat_i^-1]_{q_i}, u_t = sum_i y_i Qhat_i mod q_t.
+__global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const ModUpPlan *__restrict__ plans,
+                        const PrimeInfo *__restrict__ pinfo, int nl, int next, int dnum, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x;
+    const int ct = blockIdx.z / dnum, j = blockIdx.z - ct * dnum;
+    const ModUpPlan &pl = plans[j];
+    if (pl.nsrc == 0) return;
+    u64 y[kMaxMod];
+    for (int s = 0; s < pl.nsrc; s++) {
+        int i = pl.src_lo + s;
+        u64 x = xc[((size_t)ct * nl + i) * N + n];
+        y[s] = shoup(x, pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
+    }
+    u64 *out = mu + ((size_t)ct * dnum + j) * next * N + n;
+    for (int t = 0; t < pl.ntgt; t++) {
+        const u64 q = pinfo[pl.tgt_prime[t]].q;
+        u64 acc = 0;
+        for (int s = 0; s < pl.nsrc; s++) acc = add_mod(acc, shoup(y[s], pl.qhat[t][s][0], pl.qhat[t][s][1], q), q);
+        out[(size_t)pl.tgt_e[t] * N] = acc;
+    }
+}
+
+// ACC[ct][c][e] = sum_j MU[ct][j][e] * K_j,c[prime(e)]   (NTT domain)
+__global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ key, u64 *__restrict__ acc, int level,
+                           int nQ, int nmod, int next, int nact, int dnum, const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, e = blockIdx.y, ct = blockIdx.z;
+    const int prime = ext_prime(e, level, nQ);
+    const Barrett br = pinfo[prime].br;
+    u64 s0 = 0, s1 = 0;
+    for (int j = 0; j < nact; j++) {
+        u64 u = mu[(((size_t)ct * dnum + j) * next + e) * N + n];
+        const u64 *K = key + ((size_t)j * 2 * nmod + prime) * N + n;
+        s0 = add_mod(s0, mul_mod(u, K[0], br), br.q);
+        s1 = add_mod(s1, mul_mod(u, K[(size_t)nmod * N], br), br.q);
+    }
+    acc[(((size_t)ct * 2 + 0) * next + e) * N + n] = s0;
+    acc[(((size_t)ct * 2 + 1) * next + e) * N + n] = s1;
+}
+
+// Exact division by P, conversion part (z-grid = ct * 2 + c):
+// v_j = [acc_{p_j} p^-1 Phat_j^-1]_{p_j};  TH_i = sum_j v_j Phat_j mod q_i.
+__global__ void k_moddown(const u64 *__restrict__ acc, u64 *__restrict__ th, const ModDownPlan *__restrict__ pl,
+                          const PrimeInfo *__restrict__ pinfo, int level, int nQ, int nP, int next, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
+    const int nl = level + 1;
+    u64 v[kMaxMod];
+    for (int j = 0; j < nP; j++) {
+        u64 x = acc[((size_t)cc * next + nl + j) * N + n];
+        v[j] = shoup(x, pl->vfac[j][0], pl->vfac[j][1], pinfo[nQ + j].q);
+    }
+    for (int i = 0; i < nl; i++) {
+        const u64 q = pinfo[i].q;
+        u64 t = 0;
+        for (int j = 0; j < nP; j++) t = add_mod(t, shoup(v[j], pl->phat[i][j][0], pl->phat[i][j][1], q), q);
+        th[((size_t)cc * nl + i) * N + n] = t;
+    }
+}
+
+// out_c = base_c + ACC_c P^-1 - TH_c (p P^-1)   (NTT domain, limbs i <= level)
+__global__ void k_ks_combine(const u64 *__restrict__ base0, const u64 *__restrict__ base1, size_t base_ct_stride,
+                             const u64 *__restrict__ acc, const u64 *__restrict__ th, u64 *__restrict__ out,
+                             size_t out_ct_stride, const ModDownPlan *__restrict__ pl,
+                             const PrimeInfo *__restrict__ pinfo, int nl, int next, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < 2; c++) {
+        u64 a = acc[(((size_t)ct * 2 + c) * next + i) * N + n];
+        u64 t = th[(((size_t)ct * 2 + c) * nl + i) * N + n];
+        u64 r = sub_mod(shoup(a, pl->pinv[i][0], pl->pinv[i][1], q), shoup(t, pl->ppinv[i][0], pl->ppinv[i][1], q), q);
+        const u64 *bp = c == 0 ? base0 : base1;
+        if (bp) r = add_mod(r, bp[(size_t)ct * base_ct_stride + (size_t)i * N + n], q);
+        out[(size_t)ct * out_ct_stride + ((size_t)c * nl + i) * N + n] = r;
+    }
+}
+
+// ----------------------------------------------------- modulus switching
+
+// top limb of both components -> TOP[ct][c][n]
+__global__ void k_ms_top(const u64 *__restrict__ in, u64 *__restrict__ top, int nl, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, c = blockIdx.y, ct = blockIdx.z;
+    top[((size_t)ct * 2 + c) * N + n] = in[(((size_t)ct * 2 + c) * nl + (nl - 1)) * N + n];
+}
+
+// R[ct][c][i] = p t mod q_i, t = [top p^-1]_{q_l} lifted to (-q_l/2, q_l/2]
+__global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const ModSwitchPlan *__restrict__ pl,
+                         const PrimeInfo *__restrict__ pinfo, int level, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
+    const u64 ql = pl->ql;
+    u64 t = shoup(top[(size_t)cc * N + n], pl->pinv_l[0], pl->pinv_l[1], ql);
+    const bool neg = t > (ql - 1) / 2;
+    const u64 mag = neg ? ql - t : t;  // |t| < q_l < q_i
+    for (int i = 0; i < level; i++) {
+        const PrimeInfo &pi = pinfo[i];
+        u64 r = shoup(mag, pi.p_mod, pi.p_modp, pi.q);
+        R[((size_t)cc * level + i) * N + n] = (neg && r) ? pi.q - r : r;
+    }
+}
+
+// out[ct][c][i] = (in - R) q_l^-1, i < level
+__global__ void k_ms_combine(const u64 *__restrict__ in, const u64 *__restrict__ R, u64 *__restrict__ out,
+                             const ModSwitchPlan *__restrict__ pl, const PrimeInfo *__restrict__ pinfo, int level,
+                             int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < 2; c++) {
+        u64 x = in[(((size_t)ct * 2 + c) * (level + 1) + i) * N + n];
+        u64 r = R[(((size_t)ct * 2 + c) * level + i) * N + n];
+        out[(((size_t)ct * 2 + c) * level + i) * N + n] = shoup(sub_mod(x, r, q), pl->qlinv[i][0], pl->qlinv[i][1], q);
+    }
+}
+
+// -------------------------------------------------------- client side
+
+// words mod q_prime(limb) for a [npoly][nlimb][N] block of raw words
+// (Shoup reduction by 1 with floor(2^64 / q), valid for any 64-bit word)
+__global__ void k_words_mod(const u64 *__restrict__ w, u64 *__restrict__ out, const int16_t *__restrict__ primes,
+                            const PrimeInfo *__restrict__ pinfo, int nlimb, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, k = blockIdx.y, poly = blockIdx.z;
+    const u64 q = pinfo[primes[k]].q;
+    const u64 wp = (~(u64)0) / q;  // = floor(2^64 / q) for odd q
+    size_t off = ((size_t)poly * nlimb + k) * N + n;
+    out[off] = shoup(w[off], 1, wp, q);
+}
+
+// factor * v (signed small integers, poly `poly` at v + poly * vstride) mod
+// q_prime(limb), plus an optional uint32 addend (message coefficients)
+__global__ void k_lift_small(const int32_t *__restrict__ v32, const int8_t *__restrict__ v8, size_t vstride,
+                             const uint32_t *__restrict__ add, u64 *__restrict__ out, const int16_t *__restrict__ primes,
+                             const PrimeInfo *__restrict__ pinfo, int nlimb, int use_p, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, k = blockIdx.y, poly = blockIdx.z;
+    const PrimeInfo &pi = pinfo[primes[k]];
+    const u64 q = pi.q;
+    int64_t x = v32 ? (int64_t)v32[(size_t)poly * vstride + n] : (int64_t)v8[(size_t)poly * vstride + n];
+    u64 r = x >= 0 ? (u64)x : q - (u64)(-x);
+    if (use_p) r = shoup(r, pi.p_mod, pi.p_modp, q);
+    if (add) r = add_mod(r, (u64)add[(size_t)poly * N + n] % q, q);
+    out[((size_t)poly * nlimb + k) * N + n] = r;
+}
+
+// switching-key pair for one digit: k0 = -A S + E + f S', k1 = A  (NTT domain)
+struct FArg {
+    u64 f[kMaxMod];  // P mod q_i for the digit's primes, 0 elsewhere
+};
+__global__ void k_keypair(const u64 *__restrict__ A, const u64 *__restrict__ E, const u64 *__restrict__ S,
+                          const u64 *__restrict__ S2, FArg f, u64 *__restrict__ k0, u64 *__restrict__ k1,
+                          const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
+    const Barrett br = pinfo[i].br;
+    size_t off = (size_t)i * N + n;
+    u64 a = A[off];
+    u64 r = sub_mod(E[off], mul_mod(a, S[off], br), br.q);
+    if (S2 && f.f[i]) r = add_mod(r, mul_mod(f.f[i], S2[off], br), br.q);
+    k0[off] = r;
+    k1[off] = a;
+}
+
+// pointwise product of two [nlimb][N] blocks
+__global__ void k_pmul(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 *__restrict__ out,
+                       const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
+    size_t off = (size_t)i * N + n;
+    out[off] = mul_mod(a[off], b[off], pinfo[i].br);
+}
+
+// c0 = pk0 U + E0, c1 = pk1 U + E1 with U, E0, E1 each [count][nQ][N]
+__global__ void k_enc_combine(const u64 *__restrict__ pk, const u64 *__restrict__ U, const u64 *__restrict__ E0,
+                              const u64 *__restrict__ E1, u64 *__restrict__ out, int nQ,
+                              const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const Barrett br = pinfo[i].br;
+    const size_t L = (size_t)nQ * N, off = (size_t)i * N + n, x = (size_t)ct * L + off;
+    u64 u = U[x];
+    out[(size_t)ct * 2 * L + off] = add_mod(mul_mod(pk[off], u, br), E0[x], br.q);
+    out[(size_t)ct * 2 * L + L + off] = add_mod(mul_mod(pk[L + off], u, br), E1[x], br.q);
+}
+
+// D[ct][i] = c0 + c1 s (+ c2 s^2)   (NTT domain)
+__global__ void k_dec_inner(const u64 *__restrict__ ct_in, const u64 *__restrict__ s, u64 *__restrict__ d, int nl,
+                            int ncomp, const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const Barrett br = pinfo[i].br;
+    const size_t L = (size_t)nl * N, off = (size_t)i * N + n;
+    const u64 *C = ct_in + (size_t)ct * ncomp * L;
+    u64 sv = s[off], r = C[off], sp = sv;
+    for (int k = 1; k < ncomp; k++) {
+        r = add_mod(r, mul_mod(C[k * L + off], sp, br), br.q);
+        sp = mul_mod(sp, sv, br);
+    }
+    d[(size_t)ct * L + off] = r;
+}
+
+// Garner mixed radix x = v_0 + v_1 q_0 + ...; centred against (Q-1)/2 (whose
+// digits are (q_i - 1)/2); result x mod p or (x - Q) mod p.
+__global__ void k_crt_decode(const u64 *__restrict__ d, uint32_t *__restrict__ out, const GarnerTable *__restrict__ g,
+                             const PrimeInfo *__restrict__ pinfo, int nl, u64 p, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, ct = blockIdx.z;
+    u64 v[kMaxMod];
+    for (int i = 0; i < nl; i++) {
+        const u64 q = pinfo[i].q;
+        u64 t = d[((size_t)ct * nl + i) * N + n];
+        for (int j = 0; j < i; j++) {
+            u64 vj = shoup(v[j], 1, g->one_p[i], q);  // v_j mod q_i
+            t = shoup(sub_mod(t, vj, q), g->inv[i][j][0], g->inv[i][j][1], q);
+        }
+        v[i] = t;
+    }
+    int cmp = 0;  // sign of x - (Q-1)/2
+    for (int i = nl - 1; i >= 0 && cmp == 0; i--) {
+        u64 h = (pinfo[i].q - 1) / 2;
+        cmp = v[i] > h ? 1 : (v[i] < h ? -1 : 0);
+    }
+    u64 r = 0;
+    for (int i = 0; i < nl; i++) r = (r + (v[i] % p) * g->mprod_p[i]) % p;
+    if (cmp > 0) r = (r + p - g->qprod_p[nl - 1]) % p;
+    out[(size_t)ct * N + n] = (uint32_t)r;
+}
+
+// Paterson-Stockmeyer blocks: H[pos(t)][ct] = sum_k coef[t][k] * baby_k[ct]
+// (NTT domain, every baby at the same level).  coef holds Shoup pairs
+// [nblk][nbaby][nl][2] of the centred coefficients reduced mod q_i.
+struct BabyArg {
+    const u64 *baby[16];
+    int pos[64];  // storage position of block t
+};
+__global__ void k_lincomb(BabyArg ba, const u64 *__restrict__ coef, u64 *__restrict__ out, int nbaby, int nblk,
+                          int count, int nl, const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const u64 q = pinfo[i].q;
+    const size_t L = (size_t)nl * N;
+    for (int c = 0; c < 2; c++) {
+        u64 v[16];
+        for (int k = 0; k < nbaby; k++) v[k] = ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n];
+        for (int t = 0; t < nblk; t++) {
+            u64 acc = 0;
+            for (int k = 0; k < nbaby; k++) {
+                const u64 *w = coef + (((size_t)t * nbaby + k) * nl + i) * 2;
+                acc = add_mod(acc, shoup(v[k], w[0], w[1], q), q);
+            }
+            out[((size_t)ba.pos[t] * count + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] = acc;
+        }
+    }
+}
+
+inline dim3 grid3(int N, int y, int z) { return dim3((unsigned)(N / kT), (unsigned)y, (unsigned)z); }
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+
+void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, hipStream_t st) {
+    k_tensor<<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, out, bcount, nl, c->pinfo, c->N);
+}
+void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, int ncomp,
+                   bool sub, hipStream_t st) {
+    k_addsub<<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, out, bcount, nl, ncomp, sub ? 1 : 0, c->pinfo, c->N);
+}
+static ScalarArg scalar_arg(const bc_ctx *c, int64_t v, int nl) {
+    ScalarArg s{};
+    for (int i = 0; i < nl; i++) {
+        u64 q = c->mod[i];
+        u64 r = v >= 0 ? (u64)v % q : (q - ((u64)(-v) % q)) % q;
+        s.w[i][0] = r;
+        s.w[i][1] = h_shoup(r, q);
+    }
+    return s;
+}
+void launch_mul_scalar(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st) {
+    k_mul_scalar<<<grid3(c->N, nl, count), kT, 0, st>>>(a, out, nl, ncomp, scalar_arg(c, v, nl), c->pinfo, c->N);
+}
+void launch_add_const(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st) {
+    k_add_const<<<grid3(c->N, nl, count), kT, 0, st>>>(a, out, nl, ncomp, scalar_arg(c, v, nl), c->pinfo, c->N);
+}
+void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, int count, int nl, int ncomp,
+                    hipStream_t st) {
+    k_permute<<<grid3(c->N, nl, count), kT, 0, st>>>(in, out, perm, nl, ncomp, c->N);
+}
+void launch_ks_prepare(const bc_ctx *c, const u64 *x, size_t x_ct_stride, u64 *mu, u64 *xc, int count, int nl,
+                       int next, hipStream_t st) {
+    k_ks_prepare<<<grid3(c->N, nl, count), kT, 0, st>>>(x, x_ct_stride, mu, xc, nl, next, c->dnum, c->alpha, c->N);
+}
+void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, hipStream_t st) {
+    k_modup<<<grid3(c->N, 1, count * c->dnum), kT, 0, st>>>(xc, mu, c->modup + (size_t)level * c->dnum, c->pinfo,
+                                                           level + 1, next, c->dnum, c->N);
+}
+void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *key, u64 *acc, int count, int level, int next,
+                     int nact, hipStream_t st) {
+    k_ks_inner<<<grid3(c->N, next, count), kT, 0, st>>>(mu, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum,
+                                                        c->pinfo, c->N);
+}
+void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, hipStream_t st) {
+    k_moddown<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(acc, th, c->moddown, c->pinfo, level, c->nQ, c->nP, next, c->N);
+}
+void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size_t base_ct_stride, const u64 *acc,
+                       const u64 *th, u64 *out, size_t out_ct_stride, int count, int level, int next, hipStream_t st) {
+    k_ks_combine<<<grid3(c->N, level + 1, count), kT, 0, st>>>(base0, base1, base_ct_stride, acc, th, out,
+                                                               out_ct_stride, c->moddown, c->pinfo, level + 1, next,
+                                                               c->N);
+}
+void launch_ms_top(const bc_ctx *c, const u64 *in, u64 *top, int count, int nl, hipStream_t st) {
+    k_ms_top<<<grid3(c->N, 2, count), kT, 0, st>>>(in, top, nl, c->N);
+}
+void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st) {
+    k_ms_fbc<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(top, R, c->modsw + level, c->pinfo, level, c->N);
+}
+void launch_ms_combine(const bc_ctx *c, const u64 *in, const u64 *R, u64 *out, int count, int level, hipStream_t st) {
+    k_ms_combine<<<grid3(c->N, level, count), kT, 0, st>>>(in, R, out, c->modsw + level, c->pinfo, level, c->N);
+}
+void launch_words_mod(const bc_ctx *c, const u64 *w, u64 *out, const int16_t *primes, int npoly, int nlimb,
+                      hipStream_t st) {
+    k_words_mod<<<grid3(c->N, nlimb, npoly), kT, 0, st>>>(w, out, primes, c->pinfo, nlimb, c->N);
+}
+void launch_lift_small(const bc_ctx *c, const int32_t *v32, const int8_t *v8, size_t vstride, const uint32_t *add,
+                       u64 *out, const int16_t *primes, int npoly, int nlimb, bool use_p, hipStream_t st) {
+    k_lift_small<<<grid3(c->N, nlimb, npoly), kT, 0, st>>>(v32, v8, vstride, add, out, primes, c->pinfo, nlimb,
+                                                          use_p ? 1 : 0, c->N);
+}
+void launch_keypair(const bc_ctx *c, const u64 *A, const u64 *E, const u64 *S, const u64 *S2, const u64 *f, u64 *k0,
+                    u64 *k1, int nlimb, hipStream_t st) {
+    FArg fa{};
+    for (int i = 0; i < nlimb; i++) fa.f[i] = f ? f[i] : 0;
+    k_keypair<<<grid3(c->N, nlimb, 1), kT, 0, st>>>(A, E, S, S2, fa, k0, k1, c->pinfo, c->N);
+}
+void launch_pmul(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int nlimb, hipStream_t st) {
+    k_pmul<<<grid3(c->N, nlimb, 1), kT, 0, st>>>(a, b, out, c->pinfo, c->N);
+}
+void launch_enc_combine(const bc_ctx *c, const u64 *pk, const u64 *U, const u64 *E0, const u64 *E1, u64 *out, int count,
+                        hipStream_t st) {
+    k_enc_combine<<<grid3(c->N, c->nQ, count), kT, 0, st>>>(pk, U, E0, E1, out, c->nQ, c->pinfo, c->N);
+}
+void launch_dec_inner(const bc_ctx *c, const u64 *ct, const u64 *s, u64 *d, int count, int nl, int ncomp, hipStream_t st) {
+    k_dec_inner<<<grid3(c->N, nl, count), kT, 0, st>>>(ct, s, d, nl, ncomp, c->pinfo, c->N);
+}
+void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *pos, const u64 *coef, u64 *out, int nbaby,
+                    int nblk, int count, int nl, hipStream_t st) {
+    BC_REQUIRE(nbaby <= 16 && nblk <= 64, BC_ERR_PARAM, "schedule too large");
+    BabyArg ba{};
+    for (int k = 0; k < nbaby; k++) ba.baby[k] = babies[k];
+    for (int t = 0; t < nblk; t++) ba.pos[t] = pos[t];
+    k_lincomb<<<grid3(c->N, nl, count), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, nl, c->pinfo, c->N);
+}
+void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st) {
+    k_crt_decode<<<grid3(c->N, 1, count), kT, 0, st>>>(d, out, c->garner, c->pinfo, nl, c->p, c->N);
+}
+
+}  // namespace bc

@@ -1,0 +1,522 @@
+// ops.cpp -- BGV operations on batches of device ciphertexts.
+//
+// Ciphertexts stay in HBM in the NTT domain between operations; every
+// operation is a short fixed sequence of batched kernel launches on one
+// stream, each launch covering all ciphertexts, components and limbs of the
+// batch (the whole residue matrix, as in the paper's "GPU-related
+// Optimizations", instead of one launch per row or per ciphertext).
+//
+// Multiplication (tensor, then relinearisation by hybrid key switching, then
+// one modulus switch) and rotation (automorphism, then key switching) are the
+// operations the comparison circuit is made of (paper, Background, "Word-wise
+// Universal FHE Scheme").
+
+#include "ops.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace bc {
+
+CtB alloc_ct(bc_ctx *c, int count, int level, int ncomp) {
+    CtB x;
+    x.count = count;
+    x.level = level;
+    x.ncomp = ncomp;
+    x.own = make_buf(c, sizeof(u64) * (size_t)count * x.ct_words(c->N));
+    x.data = (u64 *)x.own->p;
+    return x;
+}
+
+CtB from_abi(const bc_ctx *c, const bc_ctb *x) {
+    BC_REQUIRE(x && x->data, BC_ERR_ARG, "null ciphertext batch");
+    BC_REQUIRE(x->count >= 1, BC_ERR_ARG, "empty ciphertext batch");
+    BC_REQUIRE(x->level >= 0 && x->level < c->nQ, BC_ERR_LEVEL, "ciphertext level out of range");
+    BC_REQUIRE(x->ncomp == 2 || x->ncomp == 3, BC_ERR_ARG, "ciphertexts have 2 or 3 components");
+    CtB b;
+    b.data = x->data;
+    b.count = x->count;
+    b.level = x->level;
+    b.ncomp = x->ncomp;
+    return b;
+}
+
+int64_t centred(const bc_ctx *c, int64_t v) {
+    int64_t p = (int64_t)c->p;
+    v %= p;
+    if (v < 0) v += p;
+    return v > (p - 1) / 2 ? v - p : v;
+}
+
+namespace {
+
+// Transform jobs over a batch; split across launches when too many limbs.
+struct Jobs {
+    std::vector<std::pair<int, int>> l;  // (limb slot, prime)
+    void add(int off, int prime) { l.emplace_back(off, prime); }
+};
+
+void run_ntt(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j, bool inverse, hipStream_t st) {
+    for (size_t s = 0; s < j.l.size(); s += kMaxJobs) {
+        LimbSet ls{};
+        ls.base = base;
+        ls.poly_stride = stride;
+        ls.npoly = npoly;
+        ls.nlimb = (int)std::min<size_t>(kMaxJobs, j.l.size() - s);
+        for (int k = 0; k < ls.nlimb; k++) {
+            ls.off[k] = (int16_t)j.l[s + k].first;
+            ls.prime[k] = (int16_t)j.l[s + k].second;
+        }
+        if (inverse) ntt_inverse(c, ls, st);
+        else ntt_forward(c, ls, st);
+    }
+}
+
+// all limbs of a [count][ncomp][nl][N] batch
+Jobs all_limbs(int ncomp, int nl) {
+    Jobs j;
+    for (int k = 0; k < ncomp; k++)
+        for (int i = 0; i < nl; i++) j.add(k * nl + i, i);
+    return j;
+}
+
+void check_hip() { BC_HIP(hipGetLastError()); }
+
+// Key switch of the NTT-domain polynomials X (stride x_stride per ciphertext,
+// level `level`) with key [dnum][2][nmod][N]:
+// out_c = base_c + ModDown(sum_j ModUp_j(X) * key_j,c), c = 0, 1.
+void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int count, int level, const u64 *base0,
+                const u64 *base1, size_t base_stride, u64 *out, size_t out_stride, hipStream_t st) {
+    const int N = c->N, nl = level + 1, next = nl + c->nP, dnum = c->dnum;
+    const int nact = level / c->alpha + 1;
+    BufP MU = make_buf(c, sizeof(u64) * (size_t)count * dnum * next * N);
+    BufP XC = make_buf(c, sizeof(u64) * (size_t)count * nl * N);
+    u64 *mu = (u64 *)MU->p, *xc = (u64 *)XC->p;
+    launch_ks_prepare(c, X, x_stride, mu, xc, count, nl, next, st);
+    Jobs jx;
+    for (int i = 0; i < nl; i++) jx.add(i, i);
+    run_ntt(c, xc, (size_t)nl * N, count, jx, true, st);
+    launch_modup(c, xc, mu, count, level, next, st);
+    Jobs jm;
+    for (int j = 0; j < nact; j++) {
+        const ModUpPlan &pl = c->h_modup[(size_t)level * dnum + j];
+        for (int t = 0; t < pl.ntgt; t++) jm.add(j * next + pl.tgt_e[t], pl.tgt_prime[t]);
+    }
+    run_ntt(c, mu, (size_t)dnum * next * N, count, jm, false, st);
+    XC.reset();
+    BufP ACC = make_buf(c, sizeof(u64) * (size_t)count * 2 * next * N);
+    u64 *acc = (u64 *)ACC->p;
+    launch_ks_inner(c, mu, key, acc, count, level, next, nact, st);
+    MU.reset();
+    Jobs js;
+    for (int k = 0; k < 2; k++)
+        for (int t = 0; t < c->nP; t++) js.add(k * next + nl + t, c->nQ + t);
+    run_ntt(c, acc, (size_t)2 * next * N, count, js, true, st);
+    BufP TH = make_buf(c, sizeof(u64) * (size_t)count * 2 * nl * N);
+    u64 *th = (u64 *)TH->p;
+    launch_moddown(c, acc, th, count, level, next, st);
+    run_ntt(c, th, (size_t)2 * nl * N, count, all_limbs(2, nl), false, st);
+    launch_ks_combine(c, base0, base1, base_stride, acc, th, out, out_stride, count, level, next, st);
+    check_hip();
+}
+
+}  // namespace
+
+void copy_ct(const bc_ctx *c, const CtB &src, const CtB &dst, hipStream_t st) {
+    BC_REQUIRE(src.count == dst.count && src.level == dst.level && src.ncomp == dst.ncomp, BC_ERR_ARG,
+               "copy: shape mismatch");
+    BC_HIP(hipMemcpyAsync(dst.data, src.data, sizeof(u64) * (size_t)src.count * src.ct_words(c->N),
+                          hipMemcpyDeviceToDevice, st));
+}
+
+void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st) {
+    BC_REQUIRE(in.ncomp == 2, BC_ERR_ARG, "modulus switching takes 2-component ciphertexts");
+    BC_REQUIRE(in.level >= 1, BC_ERR_LEVEL, "no prime left to drop");
+    BC_REQUIRE(out.level == in.level - 1 && out.ncomp == 2 && out.count == in.count, BC_ERR_ARG,
+               "modulus switch: output shape");
+    const int N = c->N, lv = in.level, count = in.count;
+    BufP TOP = make_buf(c, sizeof(u64) * (size_t)count * 2 * N);
+    u64 *top = (u64 *)TOP->p;
+    launch_ms_top(c, in.data, top, count, lv + 1, st);
+    Jobs jt;
+    jt.add(0, lv);
+    jt.add(1, lv);
+    run_ntt(c, top, (size_t)2 * N, count, jt, true, st);
+    BufP R = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
+    u64 *r = (u64 *)R->p;
+    launch_ms_fbc(c, top, r, count, lv, st);
+    run_ntt(c, r, (size_t)2 * lv * N, count, all_limbs(2, lv), false, st);
+    launch_ms_combine(c, in.data, r, out.data, count, lv, st);
+    check_hip();
+}
+
+CtB to_level(bc_ctx *c, const CtB &x, int level, hipStream_t st) {
+    BC_REQUIRE(level >= 0 && level <= x.level, BC_ERR_LEVEL, "cannot raise a level");
+    CtB cur = x;
+    while (cur.level > level) {
+        CtB nx = alloc_ct(c, cur.count, cur.level - 1, 2);
+        mod_switch(c, cur, nx, st);
+        cur = nx;
+    }
+    return cur;
+}
+
+static void check_pair(const CtB &a, const CtB &b) {
+    BC_REQUIRE(b.count >= 1 && a.count % b.count == 0, BC_ERR_ARG, "second operand count must divide the first");
+}
+
+void tensor(bc_ctx *c, const CtB &a0, const CtB &b0, const CtB &out, hipStream_t st) {
+    check_pair(a0, b0);
+    BC_REQUIRE(a0.ncomp == 2 && b0.ncomp == 2, BC_ERR_ARG, "tensor takes 2-component ciphertexts");
+    int lv = std::min(a0.level, b0.level);
+    CtB a = to_level(c, a0, lv, st), b = to_level(c, b0, lv, st);
+    BC_REQUIRE(out.ncomp == 3 && out.level == lv && out.count == a.count, BC_ERR_ARG, "tensor: output shape");
+    launch_tensor(c, a.data, b.data, out.data, a.count, b.count, lv + 1, st);
+    check_hip();
+}
+
+void relin(bc_ctx *c, const bc_keys *k, const CtB &in3, const CtB &out, hipStream_t st) {
+    BC_REQUIRE(in3.ncomp == 3, BC_ERR_ARG, "relinearisation takes 3-component ciphertexts");
+    BC_REQUIRE(out.ncomp == 2 && out.level == in3.level && out.count == in3.count, BC_ERR_ARG,
+               "relinearisation: output shape");
+    const size_t L = (size_t)(in3.level + 1) * c->N;
+    key_switch(c, k->rlk, in3.data + 2 * L, 3 * L, in3.count, in3.level, in3.data, in3.data + L, 3 * L, out.data,
+               2 * L, st);
+}
+
+int out_level_mul(int la, int lb) {
+    int lv = std::min(la, lb);
+    return lv > 0 ? lv - 1 : 0;
+}
+
+void mul_relin(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const CtB &out, hipStream_t st) {
+    check_pair(a, b);
+    int lv = std::min(a.level, b.level);
+    BC_REQUIRE(out.level == out_level_mul(a.level, b.level) && out.ncomp == 2 && out.count == a.count, BC_ERR_ARG,
+               "multiplication: output shape");
+    CtB t3 = alloc_ct(c, a.count, lv, 3);
+    tensor(c, a, b, t3, st);
+    if (lv == 0) {
+        relin(c, k, t3, out, st);
+        return;
+    }
+    CtB r2 = alloc_ct(c, a.count, lv, 2);
+    relin(c, k, t3, r2, st);
+    t3 = CtB();
+    mod_switch(c, r2, out, st);
+}
+
+CtB mul(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, hipStream_t st) {
+    CtB out = alloc_ct(c, a.count, out_level_mul(a.level, b.level), 2);
+    mul_relin(c, k, a, b, out, st);
+    return out;
+}
+
+u64 galois_for_step(const bc_ctx *c, int step) {
+    u64 twoN = 2 * (u64)c->N;
+    if (step == BC_ROW_SWAP) return twoN - 1;
+    return h_powmod(5, (u64)step, twoN);
+}
+
+void rotate(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB &out, hipStream_t st) {
+    BC_REQUIRE(in.ncomp == 2, BC_ERR_ARG, "rotation takes 2-component ciphertexts");
+    BC_REQUIRE(out.ncomp == 2 && out.level == in.level && out.count == in.count, BC_ERR_ARG, "rotation: output shape");
+    int idx = -1;
+    for (int i = 0; i < k->ngal; i++)
+        if (k->steps[i] == steps) idx = i;
+    BC_REQUIRE(idx >= 0, BC_ERR_KEY, "no rotation key for this step");
+    const size_t L = (size_t)(in.level + 1) * c->N;
+    CtB sig = alloc_ct(c, in.count, in.level, 2);
+    launch_permute(c, in.data, sig.data, k->perm[idx], in.count, in.level + 1, 2, st);
+    key_switch(c, k->gk[idx], sig.data + L, 2 * L, in.count, in.level, sig.data, nullptr, 2 * L, out.data, 2 * L, st);
+}
+
+void add_sub(bc_ctx *c, const CtB &a0, const CtB &b0, const CtB &out, bool sub, hipStream_t st) {
+    check_pair(a0, b0);
+    BC_REQUIRE(a0.ncomp == b0.ncomp, BC_ERR_ARG, "component counts differ");
+    int lv = std::min(a0.level, b0.level);
+    CtB a = to_level(c, a0, lv, st), b = to_level(c, b0, lv, st);
+    BC_REQUIRE(out.level == lv && out.ncomp == a.ncomp && out.count == a.count, BC_ERR_ARG, "add/sub: output shape");
+    launch_addsub(c, a.data, b.data, out.data, a.count, b.count, lv + 1, a.ncomp, sub, st);
+    check_hip();
+}
+
+CtB add(bc_ctx *c, const CtB &a, const CtB &b, hipStream_t st) {
+    CtB out = alloc_ct(c, a.count, std::min(a.level, b.level), a.ncomp);
+    add_sub(c, a, b, out, false, st);
+    return out;
+}
+
+CtB sub(bc_ctx *c, const CtB &a, const CtB &b, hipStream_t st) {
+    CtB out = alloc_ct(c, a.count, std::min(a.level, b.level), a.ncomp);
+    add_sub(c, a, b, out, true, st);
+    return out;
+}
+
+void mul_scalar(bc_ctx *c, const CtB &a, int64_t v, const CtB &out, hipStream_t st) {
+    BC_REQUIRE(out.level == a.level && out.ncomp == a.ncomp && out.count == a.count, BC_ERR_ARG, "scalar: output shape");
+    launch_mul_scalar(c, a.data, out.data, a.count, a.level + 1, a.ncomp, centred(c, v), st);
+    check_hip();
+}
+
+void add_const(bc_ctx *c, const CtB &a, int64_t v, const CtB &out, hipStream_t st) {
+    BC_REQUIRE(out.level == a.level && out.ncomp == a.ncomp && out.count == a.count, BC_ERR_ARG, "const: output shape");
+    launch_add_const(c, a.data, out.data, a.count, a.level + 1, a.ncomp, centred(c, v), st);
+    check_hip();
+}
+
+// ----------------------------------------------------------- slot encoding
+
+namespace {
+
+u64 least_primitive_root(u64 p) {
+    std::vector<u64> fac;
+    u64 n = p - 1;
+    for (u64 f = 2; f * f <= n; f++)
+        if (n % f == 0) {
+            fac.push_back(f);
+            while (n % f == 0) n /= f;
+        }
+    if (n > 1) fac.push_back(n);
+    for (u64 g = 2; g < p; g++) {
+        bool ok = true;
+        for (u64 f : fac) ok = ok && h_powmod(g, (p - 1) / f, p) != 1;
+        if (ok) return g;
+    }
+    throw Error(BC_ERR_PARAM, "no primitive root");
+}
+
+// Slot j < M/2 is the evaluation at zeta^(5^j), slot M/2 + j at zeta^(-5^j),
+// zeta = g^((p-1)/2M), g the least primitive root mod p.
+std::vector<u64> slot_points(const bc_ctx *c) {
+    const u64 p = c->p, M = (u64)c->M, twoM = 2 * M;
+    u64 zeta = h_powmod(least_primitive_root(p), (p - 1) / twoM, p);
+    std::vector<u64> pts(M);
+    u64 e = 1;
+    for (u64 j = 0; j < M / 2; j++) {
+        pts[j] = h_powmod(zeta, e, p);
+        pts[M / 2 + j] = h_powmod(zeta, (twoM - e) % twoM, p);
+        e = e * 5 % twoM;
+    }
+    return pts;
+}
+
+}  // namespace
+
+// coefficient mu_k at x^(k N / M), mu(zeta_j) = v_j
+static void encode(const bc_ctx *c, const u32 *slots, int count, u32 *m) {
+    const u64 p = c->p;
+    const int M = c->M, N = c->N, d = N / M;
+    auto pts = slot_points(c);
+    std::vector<u64> inv_pts(M);
+    for (int j = 0; j < M; j++) inv_pts[j] = h_invmod(pts[j], p);
+    const u64 minv = h_invmod((u64)M, p);
+    std::memset(m, 0, sizeof(u32) * (size_t)count * N);
+    std::vector<u64> pw(M);
+    for (int ct = 0; ct < count; ct++) {
+        const u32 *v = slots + (size_t)ct * M;
+        for (int j = 0; j < M; j++) pw[j] = 1;
+        for (int k = 0; k < M; k++) {
+            u64 acc = 0;
+            for (int j = 0; j < M; j++) {
+                acc = (acc + (v[j] % p) * pw[j]) % p;
+                pw[j] = pw[j] * inv_pts[j] % p;
+            }
+            m[(size_t)ct * N + (size_t)k * d] = (u32)(acc * minv % p);
+        }
+    }
+}
+
+void decode_slots(const bc_ctx *c, const u32 *coeffs, u32 *slots, int count) {
+    const u64 p = c->p;
+    const int M = c->M, N = c->N, d = N / M;
+    auto pts = slot_points(c);
+    for (int ct = 0; ct < count; ct++)
+        for (int j = 0; j < M; j++) {
+            u64 acc = 0, zk = 1;
+            for (int k = 0; k < M; k++) {
+                acc = (acc + (u64)coeffs[(size_t)ct * N + (size_t)k * d] * zk) % p;
+                zk = zk * pts[j] % p;
+            }
+            slots[(size_t)ct * M + j] = (u32)acc;
+        }
+}
+
+// ---------------------------------------------------------- client side
+
+namespace {
+
+template <class T>
+BufP upload_tmp(bc_ctx *c, const T *h, size_t n, hipStream_t st) {
+    BufP b = make_buf(c, sizeof(T) * n);
+    BC_HIP(hipMemcpyAsync(b->p, h, sizeof(T) * n, hipMemcpyHostToDevice, st));
+    return b;
+}
+
+std::vector<u32> galois_perm(const bc_ctx *c, u64 g) {
+    const int N = c->N, logN = c->logN;
+    const u64 twoN = 2 * (u64)N;
+    std::vector<u32> perm(N);
+    for (int r = 0; r < N; r++) {
+        u64 e = 2 * (u64)bit_reverse(r, logN) + 1;  // position r evaluates at psi^e
+        u64 eg = e * g % twoN;
+        perm[r] = (u32)bit_reverse((int)((eg - 1) / 2), logN);
+    }
+    return perm;
+}
+
+}  // namespace
+
+bc_keys *keygen(bc_ctx *c, const int8_t *s, const u64 *words, const int32_t *err, const int32_t *steps, int nrot) {
+    BC_REQUIRE(s && words && err, BC_ERR_ARG, "keygen: null randomness");
+    BC_REQUIRE(nrot >= 0 && (nrot == 0 || steps), BC_ERR_ARG, "keygen: rotation steps");
+    const int N = c->N, nQ = c->nQ, nm = c->nmod, dnum = c->dnum;
+    for (int r = 0; r < nrot; r++)
+        BC_REQUIRE(steps[r] == BC_ROW_SWAP || (steps[r] >= 1 && steps[r] < c->M / 2), BC_ERR_ARG,
+                   "rotation step out of range");
+    hipStream_t st = nullptr;
+    std::unique_ptr<bc_keys> k(new bc_keys());
+    k->ctx = c;
+    k->ngal = nrot;
+    const size_t nwords = (size_t)nQ * N + (size_t)(1 + nrot) * dnum * nm * N;
+    const size_t nerr = (size_t)N + (size_t)(1 + nrot) * dnum * N;
+    BufP dw = upload_tmp(c, words, nwords, st);
+    BufP de = upload_tmp(c, err, nerr, st);
+    BufP ds = upload_tmp(c, s, (size_t)N, st);
+    std::vector<int16_t> primes(nm);
+    for (int i = 0; i < nm; i++) primes[i] = (int16_t)i;
+    BufP dprimes = upload_tmp(c, primes.data(), primes.size(), st);
+    const int16_t *dpr = (const int16_t *)dprimes->p;
+    Jobs jall;
+    for (int i = 0; i < nm; i++) jall.add(i, i);
+
+    BC_HIP(hipMalloc(&k->s_ntt, sizeof(u64) * nm * N));
+    launch_lift_small(c, nullptr, (const int8_t *)ds->p, N, nullptr, k->s_ntt, dpr, 1, nm, false, st);
+    run_ntt(c, k->s_ntt, 0, 1, jall, false, st);
+
+    BufP A = make_buf(c, sizeof(u64) * nm * N), E = make_buf(c, sizeof(u64) * nm * N);
+    u64 *a = (u64 *)A->p, *e = (u64 *)E->p;
+    // public key over Q
+    BC_HIP(hipMalloc(&k->pk, sizeof(u64) * 2 * nQ * N));
+    launch_words_mod(c, (const u64 *)dw->p, a, dpr, 1, nQ, st);
+    launch_lift_small(c, (const int32_t *)de->p, nullptr, N, nullptr, e, dpr, 1, nQ, true, st);
+    Jobs jq;
+    for (int i = 0; i < nQ; i++) jq.add(i, i);
+    run_ntt(c, a, 0, 1, jq, false, st);
+    run_ntt(c, e, 0, 1, jq, false, st);
+    launch_keypair(c, a, e, k->s_ntt, nullptr, nullptr, k->pk, k->pk + (size_t)nQ * N, nQ, st);
+
+    // P mod q_i for the primes of each digit
+    std::vector<u64> Pmod(nQ);
+    for (int i = 0; i < nQ; i++) {
+        u64 q = c->mod[i], P = 1;
+        for (int t = 0; t < c->nP; t++) P = h_mulmod(P, c->mod[nQ + t] % q, q);
+        Pmod[i] = P;
+    }
+    auto make_ksk = [&](const u64 *sprime, u64 *dst, size_t key_index) {
+        for (int j = 0; j < dnum; j++) {
+            const u64 *w = (const u64 *)dw->p + (size_t)nQ * N + ((key_index * dnum + j) * nm) * N;
+            const int32_t *ee = (const int32_t *)de->p + N + (key_index * dnum + j) * N;
+            launch_words_mod(c, w, a, dpr, 1, nm, st);
+            launch_lift_small(c, ee, nullptr, N, nullptr, e, dpr, 1, nm, true, st);
+            run_ntt(c, a, 0, 1, jall, false, st);
+            run_ntt(c, e, 0, 1, jall, false, st);
+            std::vector<u64> f(nm, 0);
+            int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, nQ);
+            for (int i = lo; i < hi; i++) f[i] = Pmod[i];
+            u64 *k0 = dst + (size_t)j * 2 * nm * N, *k1 = k0 + (size_t)nm * N;
+            launch_keypair(c, a, e, k->s_ntt, sprime, f.data(), k0, k1, nm, st);
+        }
+    };
+    BufP S2 = make_buf(c, sizeof(u64) * nm * N);
+    u64 *s2 = (u64 *)S2->p;
+    launch_pmul(c, k->s_ntt, k->s_ntt, s2, nm, st);
+    BC_HIP(hipMalloc(&k->rlk, sizeof(u64) * (size_t)dnum * 2 * nm * N));
+    make_ksk(s2, k->rlk, 0);
+    for (int r = 0; r < nrot; r++) {
+        u64 g = galois_for_step(c, steps[r]);
+        auto perm = galois_perm(c, g);
+        u32 *dperm = nullptr;
+        BC_HIP(hipMalloc(&dperm, sizeof(u32) * N));
+        BC_HIP(hipMemcpy(dperm, perm.data(), sizeof(u32) * N, hipMemcpyHostToDevice));
+        k->perm.push_back(dperm);
+        k->steps.push_back(steps[r]);
+        k->gal.push_back(g);
+        launch_permute(c, k->s_ntt, s2, dperm, 1, nm, 1, st);
+        u64 *gk = nullptr;
+        BC_HIP(hipMalloc(&gk, sizeof(u64) * (size_t)dnum * 2 * nm * N));
+        k->gk.push_back(gk);
+        make_ksk(s2, gk, (size_t)(1 + r));
+    }
+    BC_HIP(hipStreamSynchronize(st));
+    check_hip();
+    return k.release();
+}
+
+void encrypt(bc_ctx *c, const bc_keys *k, const u32 *slots, const int8_t *u, const int32_t *err, const CtB &out,
+             hipStream_t st) {
+    BC_REQUIRE(slots && u && err, BC_ERR_ARG, "encrypt: null input");
+    const int N = c->N, nQ = c->nQ, count = out.count;
+    BC_REQUIRE(out.level == nQ - 1 && out.ncomp == 2, BC_ERR_ARG, "encrypt: output must be at the top level");
+    std::vector<u32> m((size_t)count * N);
+    encode(c, slots, count, m.data());
+    BufP dm = upload_tmp(c, m.data(), m.size(), st);
+    BufP du = upload_tmp(c, u, (size_t)count * N, st);
+    BufP de = upload_tmp(c, err, (size_t)count * 2 * N, st);
+    std::vector<int16_t> primes(nQ);
+    for (int i = 0; i < nQ; i++) primes[i] = (int16_t)i;
+    BufP dprimes = upload_tmp(c, primes.data(), primes.size(), st);
+    const int16_t *dpr = (const int16_t *)dprimes->p;
+    const size_t L = (size_t)nQ * N;
+    BufP U = make_buf(c, sizeof(u64) * count * L), E0 = make_buf(c, sizeof(u64) * count * L),
+         E1 = make_buf(c, sizeof(u64) * count * L);
+    launch_lift_small(c, nullptr, (const int8_t *)du->p, N, nullptr, (u64 *)U->p, dpr, count, nQ, false, st);
+    launch_lift_small(c, (const int32_t *)de->p, nullptr, 2 * N, (const u32 *)dm->p, (u64 *)E0->p, dpr, count, nQ,
+                      true, st);
+    launch_lift_small(c, (const int32_t *)de->p + N, nullptr, 2 * N, nullptr, (u64 *)E1->p, dpr, count, nQ, true, st);
+    Jobs jq;
+    for (int i = 0; i < nQ; i++) jq.add(i, i);
+    run_ntt(c, (u64 *)U->p, L, count, jq, false, st);
+    run_ntt(c, (u64 *)E0->p, L, count, jq, false, st);
+    run_ntt(c, (u64 *)E1->p, L, count, jq, false, st);
+    launch_enc_combine(c, k->pk, (u64 *)U->p, (u64 *)E0->p, (u64 *)E1->p, out.data, count, st);
+    check_hip();
+    // the staging buffers are released to the pool only after the stream has consumed them
+    BC_HIP(hipStreamSynchronize(st));
+}
+
+void decrypt_poly(bc_ctx *c, const bc_keys *k, const CtB &in, u32 *coeffs, hipStream_t st) {
+    const int N = c->N, nl = in.level + 1;
+    BufP D = make_buf(c, sizeof(u64) * (size_t)in.count * nl * N);
+    launch_dec_inner(c, in.data, k->s_ntt, (u64 *)D->p, in.count, nl, in.ncomp, st);
+    Jobs j;
+    for (int i = 0; i < nl; i++) j.add(i, i);
+    run_ntt(c, (u64 *)D->p, (size_t)nl * N, in.count, j, true, st);
+    BufP O = make_buf(c, sizeof(u32) * (size_t)in.count * N);
+    launch_crt_decode(c, (u64 *)D->p, (u32 *)O->p, in.count, nl, st);
+    check_hip();
+    BC_HIP(hipMemcpyAsync(coeffs, O->p, sizeof(u32) * (size_t)in.count * N, hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+}
+
+void import_ct(bc_ctx *c, const u64 *host, const CtB &out, hipStream_t st) {
+    BC_REQUIRE(host, BC_ERR_ARG, "import: null host buffer");
+    const size_t words = (size_t)out.count * out.ct_words(c->N);
+    BC_HIP(hipMemcpyAsync(out.data, host, sizeof(u64) * words, hipMemcpyHostToDevice, st));
+    run_ntt(c, out.data, out.ct_words(c->N), out.count, all_limbs(out.ncomp, out.level + 1), false, st);
+    check_hip();
+    BC_HIP(hipStreamSynchronize(st));
+}
+
+void export_ct(bc_ctx *c, const CtB &in, u64 *host, hipStream_t st) {
+    BC_REQUIRE(host, BC_ERR_ARG, "export: null host buffer");
+    const size_t words = (size_t)in.count * in.ct_words(c->N);
+    BufP T = make_buf(c, sizeof(u64) * words);
+    BC_HIP(hipMemcpyAsync(T->p, in.data, sizeof(u64) * words, hipMemcpyDeviceToDevice, st));
+    run_ntt(c, (u64 *)T->p, in.ct_words(c->N), in.count, all_limbs(in.ncomp, in.level + 1), true, st);
+    check_hip();
+    BC_HIP(hipMemcpyAsync(host, T->p, sizeof(u64) * words, hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace bc

@@ -1,0 +1,71 @@
+// ops.h -- BGV operations on device batches (host orchestration).
+#pragma once
+
+#include "kernels.h"
+
+namespace bc {
+
+// Pooled device buffer, returned to the context pool when the last owner drops it.
+struct Buf {
+    bc_ctx *c;
+    void *p;
+    Buf(bc_ctx *ctx, size_t bytes) : c(ctx), p(ctx->pool.alloc(bytes)) {}
+    ~Buf() { c->pool.release(p); }
+    Buf(const Buf &) = delete;
+    Buf &operator=(const Buf &) = delete;
+};
+using BufP = std::shared_ptr<Buf>;
+
+inline BufP make_buf(bc_ctx *c, size_t bytes) { return std::make_shared<Buf>(c, bytes); }
+
+// A batch of ciphertexts [count][ncomp][level+1][N] in device memory.
+struct CtB {
+    u64 *data = nullptr;
+    int count = 0, level = 0, ncomp = 2;
+    BufP own;  // null for caller-owned memory
+    size_t ct_words(int N) const { return (size_t)ncomp * (level + 1) * N; }
+    CtB slice(int first, int n, int N) const {
+        CtB s = *this;
+        s.data = data + (size_t)first * ct_words(N);
+        s.count = n;
+        return s;
+    }
+};
+
+CtB alloc_ct(bc_ctx *c, int count, int level, int ncomp);
+CtB from_abi(const bc_ctx *c, const bc_ctb *x);
+
+void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st);
+CtB to_level(bc_ctx *c, const CtB &x, int level, hipStream_t st);
+void tensor(bc_ctx *c, const CtB &a, const CtB &b, const CtB &out, hipStream_t st);
+void relin(bc_ctx *c, const bc_keys *k, const CtB &in3, const CtB &out, hipStream_t st);
+void mul_relin(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const CtB &out, hipStream_t st);
+CtB mul(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, hipStream_t st);
+void rotate(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB &out, hipStream_t st);
+void add_sub(bc_ctx *c, const CtB &a, const CtB &b, const CtB &out, bool sub, hipStream_t st);
+CtB add(bc_ctx *c, const CtB &a, const CtB &b, hipStream_t st);
+CtB sub(bc_ctx *c, const CtB &a, const CtB &b, hipStream_t st);
+void mul_scalar(bc_ctx *c, const CtB &a, int64_t v, const CtB &out, hipStream_t st);
+void add_const(bc_ctx *c, const CtB &a, int64_t v, const CtB &out, hipStream_t st);
+void copy_ct(const bc_ctx *c, const CtB &src, const CtB &dst, hipStream_t st);
+int64_t centred(const bc_ctx *c, int64_t v);
+int out_level_mul(int la, int lb);
+
+// keys and client side
+bc_keys *keygen(bc_ctx *c, const int8_t *s, const u64 *words, const int32_t *err, const int32_t *steps, int nrot);
+void encrypt(bc_ctx *c, const bc_keys *k, const u32 *slots, const int8_t *u, const int32_t *err, const CtB &out,
+             hipStream_t st);
+void decrypt_poly(bc_ctx *c, const bc_keys *k, const CtB &in, u32 *coeffs, hipStream_t st);
+void decode_slots(const bc_ctx *c, const u32 *coeffs, u32 *slots, int count);
+void import_ct(bc_ctx *c, const u64 *host, const CtB &out, hipStream_t st);
+void export_ct(bc_ctx *c, const CtB &in, u64 *host, hipStream_t st);
+u64 galois_for_step(const bc_ctx *c, int step);
+
+// comparison circuits (digit planes, most significant first)
+struct CompareResult {
+    CtB lt, mx, mn;  // mx, mn: plane-major [ndig * count]
+};
+CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, bool want_mm, hipStream_t st);
+void compare_levels(const bc_ctx *c, int in_level, int ndig, int *lt_level, int *mm_level);
+
+}  // namespace bc
