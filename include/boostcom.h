@@ -185,6 +185,17 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
 enum { BC_EXEC_BATCHED = 0, BC_EXEC_GRAPH = 1 };
 int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
 
+/* ------------------------------------------------------------ profiling */
+/* When enabled (outside graph mode), every transform launch pair is bracketed
+ * with HIP events recorded on the stream it runs on.  bc_profile_read sums,
+ * for one kind, the event-measured time (ms), the number of bracketed launch
+ * pairs and their algorithmic HBM bytes (every limb read and written once:
+ * 16 N bytes per limb).  Reading synchronises on the recorded events;
+ * enabling (or disabling) clears earlier records. */
+enum { BC_PROF_NTT_FWD = 0, BC_PROF_NTT_INV = 1 };
+int bc_profile_enable(bc_ctx *ctx, int32_t on);
+int bc_profile_read(bc_ctx *ctx, int32_t kind, double *ms, int64_t *launches, double *bytes);
+
 const char *bc_strerror(int code);
 const char *bc_last_error(void);
 

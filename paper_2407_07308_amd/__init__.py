@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libboostcom.so")
 BC_OK, BC_ERR_ARG, BC_ERR_PARAM, BC_ERR_LEVEL, BC_ERR_OOM, BC_ERR_HIP, BC_ERR_KEY = 0, -1, -2, -3, -4, -5, -6
 BC_ROW_SWAP = -1
 BC_EXEC_BATCHED, BC_EXEC_GRAPH = 0, 1
+BC_PROF_NTT_FWD, BC_PROF_NTT_INV = 0, 1
 
 
 class BoostcomUnavailable(RuntimeError):
@@ -76,6 +77,8 @@ _SIGS = {
     "bc_compare_lt": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_compare_max_min": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_set_exec_mode": (_I, [_V, _I]),
+    "bc_profile_enable": (_I, [_V, _I]),
+    "bc_profile_read": (_I, [_V, _I, _P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_double)]),
     "bc_strerror": (ctypes.c_char_p, [_I]),
     "bc_last_error": (ctypes.c_char_p, []),
 }
@@ -314,6 +317,15 @@ class Context:
 
     def set_exec_mode(self, mode: int):
         _check(self.L.bc_set_exec_mode(self.handle, mode))
+
+    def profile_enable(self, on: bool):
+        _check(self.L.bc_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self, kind: int):
+        """(milliseconds, launch pairs, algorithmic bytes) for BC_PROF_* `kind`."""
+        ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(self.L.bc_profile_read(self.handle, kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+        return ms.value, n.value, by.value
 
     def compare_max_min(self, keys: Keys, a_digits, b_digits, want_lt=True, want_max=True, want_min=True, outs=None):
         """Returns (lt, [max planes], [min planes]); ``outs`` reuses earlier output batches."""

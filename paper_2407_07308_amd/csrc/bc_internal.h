@@ -160,6 +160,26 @@ struct Pool {
     ~Pool();
 };
 
+// --------------------------------------------------------------- profiling
+// Optional HIP-event bracketing of kernel launches on their own stream.
+enum ProfKind { kProfNttFwd = 0, kProfNttInv = 1, kProfKinds = 2 };
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;  // algorithmic HBM bytes of the bracketed launches
+};
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> spare;
+    hipEvent_t take();
+    void begin(int kind, double bytes, hipStream_t st, ProfRec &r);
+    void end(ProfRec &r, hipStream_t st);
+    void clear();
+    ~Profiler();
+};
+
 // ----------------------------------------------------------------- context
 
 // Recorded comparison circuits: one hipGraph per (call, shape, buffers) key,
@@ -195,6 +215,7 @@ struct bc_ctx {
     std::unique_ptr<bc::GraphCache> graphs;
     std::mutex graph_mu;
     hipStream_t capture_stream = nullptr;      // graph recording (created on first use)
+    std::unique_ptr<bc::Profiler> prof{new bc::Profiler()};
     std::mutex table_mu;                       // guards lt_c and ps_coef
     std::vector<int64_t> lt_c;                 // LT polynomial coefficients
     std::map<int, bc::u64 *> ps_coef;          // per level: block coefficients (Shoup)

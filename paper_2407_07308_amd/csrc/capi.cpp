@@ -383,6 +383,37 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
     });
 }
 
+int bc_profile_enable(bc_ctx *ctx, int32_t on) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(ctx->exec_mode != BC_EXEC_GRAPH || !on, BC_ERR_ARG, "profiling is not available in graph mode");
+        ctx->prof->clear();
+        ctx->prof->on = on != 0;
+    });
+}
+
+int bc_profile_read(bc_ctx *ctx, int32_t kind, double *ms, int64_t *launches, double *bytes) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(kind >= 0 && kind < kProfKinds && ms && launches && bytes, BC_ERR_ARG, "bad profile query");
+        std::lock_guard<std::mutex> g(ctx->prof->mu);
+        double t = 0, by = 0;
+        int64_t n = 0;
+        for (auto &r : ctx->prof->recs) {
+            if (r.kind != kind) continue;
+            BC_HIP(hipEventSynchronize(r.b));
+            float e = 0;
+            BC_HIP(hipEventElapsedTime(&e, r.a, r.b));
+            t += e;
+            by += r.bytes;
+            n++;
+        }
+        *ms = t;
+        *launches = n;
+        *bytes = by;
+    });
+}
+
 int bc_compare_lt(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits, const bc_ctb *b_digits,
                   bc_ctb *out, void *stream) {
     return bc_compare_max_min(ctx, keys, ndigits, a_digits, b_digits, out, nullptr, nullptr, stream);

@@ -197,6 +197,51 @@ Pool::~Pool() {
     for (auto &kv : live_) (void)hipFree(kv.first);
 }
 
+// --------------------------------------------------------------- profiler
+
+hipEvent_t Profiler::take() {
+    if (!spare.empty()) {
+        hipEvent_t e = spare.back();
+        spare.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    BC_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void Profiler::begin(int kind, double bytes, hipStream_t st, ProfRec &r) {
+    std::lock_guard<std::mutex> g(mu);
+    r.kind = kind;
+    r.bytes = bytes;
+    r.a = take();
+    r.b = take();
+    BC_HIP(hipEventRecord(r.a, st));
+}
+
+void Profiler::end(ProfRec &r, hipStream_t st) {
+    BC_HIP(hipEventRecord(r.b, st));
+    std::lock_guard<std::mutex> g(mu);
+    recs.push_back(r);
+}
+
+void Profiler::clear() {
+    std::lock_guard<std::mutex> g(mu);
+    for (auto &r : recs) {
+        spare.push_back(r.a);
+        spare.push_back(r.b);
+    }
+    recs.clear();
+}
+
+Profiler::~Profiler() {
+    for (auto &r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : spare) (void)hipEventDestroy(e);
+}
+
 // ----------------------------------------------------------------- context
 
 void build_context(bc_ctx *c, const bc_params &prm) {

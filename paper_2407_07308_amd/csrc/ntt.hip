@@ -210,19 +210,30 @@ void launch_rows(int logN2, int logN, const LimbSet &ls, const bc_ctx *c, hipStr
 }  // namespace
 
 // N1 = 2^floor(logN/2) rows, N2 = 2^ceil(logN/2) columns.
+// Algorithmic bytes of a transform: every limb read once and written once.
+static double ntt_bytes(const bc_ctx *c, const LimbSet &ls) { return 16.0 * c->N * ls.npoly * ls.nlimb; }
+
 void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (ls.npoly == 0 || ls.nlimb == 0) return;
     int logN1 = c->logN / 2, logN2 = c->logN - logN1;
+    ProfRec r{};
+    const bool prof = c->prof->on;
+    if (prof) c->prof->begin(kProfNttFwd, ntt_bytes(c, ls), st, r);
     launch_cols<false>(logN1, c->logN, ls, c, st);
     launch_rows<false>(logN2, c->logN, ls, c, st);
+    if (prof) c->prof->end(r, st);
     BC_HIP(hipGetLastError());
 }
 
 void ntt_inverse(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (ls.npoly == 0 || ls.nlimb == 0) return;
     int logN1 = c->logN / 2, logN2 = c->logN - logN1;
+    ProfRec r{};
+    const bool prof = c->prof->on;
+    if (prof) c->prof->begin(kProfNttInv, ntt_bytes(c, ls), st, r);
     launch_rows<true>(logN2, c->logN, ls, c, st);
     launch_cols<true>(logN1, c->logN, ls, c, st);
+    if (prof) c->prof->end(r, st);
     BC_HIP(hipGetLastError());
 }
 
