@@ -112,19 +112,34 @@ def main():
     achieved = fwd_bytes / (fwd_ms / 1e3) / 1e9 if fwd_ms > 0 else 0.0
 
     # ------------------------------------------------- per-op launch path
+    # same circuit, same kernels, one ciphertext per launch
     per_op = None
     if not a.no_per_op:
-        def one_group(g):
-            w = lambda b: bc.Batch(b.tensor[g * dev.ct_words(b.level): (g + 1) * dev.ct_words(b.level)], 1, b.level, 2)
-            return [w(x) for x in A], [w(x) for x in B]
-        subs = [one_group(g) for g in range(G)]
-        dev.compare_max_min(keys, *subs[0])
+        dev.set_exec_mode(bc.BC_EXEC_PER_OP)
+        po = dev.compare_max_min(keys, A, B)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for g in range(G):
-            dev.compare_max_min(keys, *subs[g])
+        dev.compare_max_min(keys, A, B, outs=po)
         torch.cuda.synchronize()
         per_op = (time.perf_counter() - t0) * 1e3
+        same = all(np.array_equal(dev.export(x), dev.export(y)) for x, y in [(po[0], lt)] + list(zip(po[1], mx)))
+        dev.set_exec_mode(bc.BC_EXEC_BATCHED)
+        if not same:
+            print("bench: per-operation path differs from the batched path", file=sys.stderr)
+            sys.exit(3)
+
+    # recorded-graph replay of the batched launch sequence
+    dev.set_exec_mode(bc.BC_EXEC_GRAPH)
+    dev.compare_max_min(keys, A, B, outs=outs)  # records
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record()
+    for _ in range(a.steps):
+        dev.compare_max_min(keys, A, B, outs=outs)
+    g1.record()
+    torch.cuda.synchronize()
+    graph_ms = g0.elapsed_time(g1) / a.steps
+    dev.set_exec_mode(bc.BC_EXEC_BATCHED)
 
     # ------------------------------------------------------ CPU oracle
     cpu = None
@@ -174,6 +189,7 @@ def main():
                      "launches": fwd_n, "avg_launch_us": 1e3 * fwd_ms / max(1, fwd_n),
                      "avg_launch_MB": fwd_bytes / max(1, fwd_n) / 1e6,
                      "inverse_ntt_GBs": inv_bytes / (inv_ms / 1e3) / 1e9 if inv_ms > 0 else None},
+        "graph_replay_ms_per_step": graph_ms,
         "per_op_launch": None if per_op is None else {"ms_per_step": per_op, "batched_speedup": per_op / ms_step},
         "cpu_baseline": cpu,
     }

@@ -181,8 +181,10 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
 /* Execution mode of the comparison calls: BC_EXEC_BATCHED launches every step
  * of the circuit once for the whole batch; BC_EXEC_GRAPH additionally records
  * the launch sequence of a (shape, buffers) combination into a hipGraph on its
- * first call and replays it afterwards. */
-enum { BC_EXEC_BATCHED = 0, BC_EXEC_GRAPH = 1 };
+ * first call and replays it afterwards; BC_EXEC_PER_OP runs the same kernels
+ * with one ciphertext per launch (the unbatched reference path).  All modes
+ * produce identical ciphertexts. */
+enum { BC_EXEC_BATCHED = 0, BC_EXEC_GRAPH = 1, BC_EXEC_PER_OP = 2 };
 int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
 
 /* ------------------------------------------------------------ profiling */

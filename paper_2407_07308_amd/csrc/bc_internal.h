@@ -23,6 +23,7 @@ typedef unsigned __int128 u128;
 
 constexpr int kMaxMod = 40;    // nQ + nP
 constexpr int kMaxJobs = 160;  // limbs listed in one transform launch
+constexpr int kMaxDigit = 16;  // primes per key-switching digit, and special primes
 
 // ------------------------------------------------------------------ errors
 

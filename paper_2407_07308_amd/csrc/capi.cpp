@@ -308,7 +308,8 @@ int bc_compare_levels(const bc_ctx *ctx, int32_t in_level, int32_t ndigits, int3
 int bc_set_exec_mode(bc_ctx *ctx, int32_t mode) {
     return guard([&] {
         check_ctx(ctx);
-        BC_REQUIRE(mode == BC_EXEC_BATCHED || mode == BC_EXEC_GRAPH, BC_ERR_ARG, "unknown execution mode");
+        BC_REQUIRE(mode == BC_EXEC_BATCHED || mode == BC_EXEC_GRAPH || mode == BC_EXEC_PER_OP, BC_ERR_ARG,
+                   "unknown execution mode");
         ctx->exec_mode = mode;
     });
 }

@@ -71,21 +71,51 @@ struct DevEval {
     bc_ctx *c;
     const bc_keys *k;
     hipStream_t st;
-    V mul(const V &a, const V &b) { return bc::mul(c, k, a, b, st); }
-    V add(const V &a, const V &b) { return bc::add(c, a, b, st); }
-    V sub(const V &a, const V &b) { return bc::sub(c, a, b, st); }
+    bool per_op = false;  // one ciphertext per launch (the unbatched reference path)
+
+    // Applies f(out_slice, a_slice, b_slice) per ciphertext when per_op is set.
+    template <class F>
+    void each(const V &out, const V &a, const V *b, F &&f) {
+        if (!per_op) {
+            f(out, a, b ? *b : a);
+            return;
+        }
+        const int N = c->N;
+        for (int i = 0; i < a.count; i++)
+            f(out.slice(i, 1, N), a.slice(i, 1, N), b ? b->slice(i % b->count, 1, N) : a.slice(i, 1, N));
+    }
+    V mul(const V &a, const V &b) {
+        V o = alloc_ct(c, a.count, out_level_mul(a.level, b.level), 2);
+        each(o, a, &b, [&](const V &oo, const V &x, const V &y) { bc::mul_relin(c, k, x, y, oo, st); });
+        return o;
+    }
+    V add(const V &a, const V &b) {
+        V o = alloc_ct(c, a.count, std::min(a.level, b.level), a.ncomp);
+        each(o, a, &b, [&](const V &oo, const V &x, const V &y) { bc::add_sub(c, x, y, oo, false, st); });
+        return o;
+    }
+    V sub(const V &a, const V &b) {
+        V o = alloc_ct(c, a.count, std::min(a.level, b.level), a.ncomp);
+        each(o, a, &b, [&](const V &oo, const V &x, const V &y) { bc::add_sub(c, x, y, oo, true, st); });
+        return o;
+    }
     V mul_scalar(const V &a, int64_t v) {
         V o = alloc_ct(c, a.count, a.level, a.ncomp);
-        bc::mul_scalar(c, a, v, o, st);
+        each(o, a, nullptr, [&](const V &oo, const V &x, const V &) { bc::mul_scalar(c, x, v, oo, st); });
         return o;
     }
     V add_const(const V &a, int64_t v) {
         V o = alloc_ct(c, a.count, a.level, a.ncomp);
-        bc::add_const(c, a, v, o, st);
+        each(o, a, nullptr, [&](const V &oo, const V &x, const V &) { bc::add_const(c, x, v, oo, st); });
         return o;
     }
     int level(const V &a) { return a.level; }
-    V to_level(const V &a, int lv) { return bc::to_level(c, a, lv, st); }
+    V to_level(const V &a, int lv) {
+        if (!per_op || a.level == lv) return bc::to_level(c, a, lv, st);
+        V o = alloc_ct(c, a.count, lv, 2);
+        for (int i = 0; i < a.count; i++) copy_ct(c, bc::to_level(c, a.slice(i, 1, c->N), lv, st), o.slice(i, 1, c->N), st);
+        return o;
+    }
     V slice(const V &a, int first, int n) { return a.slice(first, n, c->N); }
     // blocks B_t = sum_{k odd < b} c_{tb+k} Z^k for every t, stored at bit-reversed t
     V blocks(const std::vector<V> &babies, int b, int nblk);
@@ -125,7 +155,16 @@ DevEval::V DevEval::blocks(const std::vector<V> &babies, int b, int nblk) {
     int bits = __builtin_ctz(nblk);
     std::vector<int> pos(nblk);
     for (int t = 0; t < nblk; t++) pos[t] = bit_reverse(t, bits);
-    launch_lincomb(c, bp.data(), pos.data(), coef, out.data, nbaby, nblk, count, lv + 1, st);
+    if (!per_op) {
+        launch_lincomb(c, bp.data(), pos.data(), coef, out.data, nbaby, nblk, count, 0, count, lv + 1, st);
+    } else {
+        const size_t w = babies[0].ct_words(c->N);
+        for (int i = 0; i < count; i++) {
+            std::vector<const u64 *> bi;
+            for (auto *p : bp) bi.push_back(p + (size_t)i * w);
+            launch_lincomb(c, bi.data(), pos.data(), coef, out.data, nbaby, nblk, count, i, 1, lv + 1, st);
+        }
+    }
     BC_HIP(hipGetLastError());
     return out;
 }
@@ -199,7 +238,7 @@ CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const
         std::lock_guard<std::mutex> g(c->table_mu);
         if (c->lt_c.empty()) c->lt_c = lt_coefficients(c->p);
     }
-    DevEval ev{c, k, st};
+    DevEval ev{c, k, st, c->exec_mode == BC_EXEC_PER_OP};
     CtB Aall = alloc_ct(c, ndig * G, L0, 2), Ball = alloc_ct(c, ndig * G, L0, 2);
     for (int d = 0; d < ndig; d++) {
         copy_ct(c, A[d], Aall.slice(d * G, G, c->N), st);

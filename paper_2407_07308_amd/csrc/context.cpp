@@ -252,6 +252,8 @@ void build_context(bc_ctx *c, const bc_params &prm) {
     BC_REQUIRE(prm.bitsQ >= 20 && prm.bitsQ <= 61 && prm.bitsP >= 20 && prm.bitsP <= 61, BC_ERR_PARAM,
                "prime sizes must be in [20, 61] bits");
     BC_REQUIRE(prm.dnum >= 1 && prm.dnum <= prm.nQ, BC_ERR_PARAM, "dnum must be in [1, nQ]");
+    BC_REQUIRE((prm.nQ + prm.dnum - 1) / prm.dnum <= kMaxDigit && prm.nP <= kMaxDigit, BC_ERR_PARAM,
+               "at most 16 primes per digit and 16 special primes");
     c->prm = prm;
     c->logN = prm.logN;
     c->N = 1 << prm.logN;

@@ -24,6 +24,7 @@ void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size
                        const u64 *th, u64 *out, size_t out_ct_stride, int count, int level, int next, hipStream_t st);
 void launch_ms_top(const bc_ctx *c, const u64 *in, u64 *top, int count, int nl, hipStream_t st);
 void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st);
+void launch_ms_multi(const bc_ctx *c, const u64 *in, u64 *out, int count, int from, int to, hipStream_t st);
 void launch_ms_combine(const bc_ctx *c, const u64 *in, const u64 *R, u64 *out, int count, int level, hipStream_t st);
 void launch_words_mod(const bc_ctx *c, const u64 *w, u64 *out, const int16_t *primes, int npoly, int nlimb,
                       hipStream_t st);
@@ -36,7 +37,7 @@ void launch_enc_combine(const bc_ctx *c, const u64 *pk, const u64 *U, const u64 
                         hipStream_t st);
 void launch_dec_inner(const bc_ctx *c, const u64 *ct, const u64 *s, u64 *d, int count, int nl, int ncomp, hipStream_t st);
 void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *pos, const u64 *coef, u64 *out, int nbaby,
-                    int nblk, int count, int nl, hipStream_t st);
+                    int nblk, int count, int ct0, int nlaunch, int nl, hipStream_t st);
 void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st);
 
 }  // namespace bc

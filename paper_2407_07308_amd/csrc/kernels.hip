@@ -109,8 +109,11 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
     const int ct = blockIdx.z / dnum, j = blockIdx.z - ct * dnum;
     const ModUpPlan &pl = plans[j];
     if (pl.nsrc == 0) return;
-    u64 y[kMaxMod];
-    for (int s = 0; s < pl.nsrc; s++) {
+    // fully unrolled over the compile-time bound so y[] stays in registers
+    u64 y[kMaxDigit];
+#pragma unroll
+    for (int s = 0; s < kMaxDigit; s++) {
+        if (s >= pl.nsrc) break;
         int i = pl.src_lo + s;
         u64 x = xc[((size_t)ct * nl + i) * N + n];
         y[s] = shoup(x, pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
@@ -119,7 +122,11 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
     for (int t = 0; t < pl.ntgt; t++) {
         const u64 q = pinfo[pl.tgt_prime[t]].q;
         u64 acc = 0;
-        for (int s = 0; s < pl.nsrc; s++) acc = add_mod(acc, shoup(y[s], pl.qhat[t][s][0], pl.qhat[t][s][1], q), q);
+#pragma unroll
+        for (int s = 0; s < kMaxDigit; s++) {
+            if (s >= pl.nsrc) break;
+            acc = add_mod(acc, shoup(y[s], pl.qhat[t][s][0], pl.qhat[t][s][1], q), q);
+        }
         out[(size_t)pl.tgt_e[t] * N] = acc;
     }
 }
@@ -147,15 +154,21 @@ __global__ void k_moddown(const u64 *__restrict__ acc, u64 *__restrict__ th, con
                           const PrimeInfo *__restrict__ pinfo, int level, int nQ, int nP, int next, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
     const int nl = level + 1;
-    u64 v[kMaxMod];
-    for (int j = 0; j < nP; j++) {
+    u64 v[kMaxDigit];
+#pragma unroll
+    for (int j = 0; j < kMaxDigit; j++) {
+        if (j >= nP) break;
         u64 x = acc[((size_t)cc * next + nl + j) * N + n];
         v[j] = shoup(x, pl->vfac[j][0], pl->vfac[j][1], pinfo[nQ + j].q);
     }
     for (int i = 0; i < nl; i++) {
         const u64 q = pinfo[i].q;
         u64 t = 0;
-        for (int j = 0; j < nP; j++) t = add_mod(t, shoup(v[j], pl->phat[i][j][0], pl->phat[i][j][1], q), q);
+#pragma unroll
+        for (int j = 0; j < kMaxDigit; j++) {
+            if (j >= nP) break;
+            t = add_mod(t, shoup(v[j], pl->phat[i][j][0], pl->phat[i][j][1], q), q);
+        }
         th[((size_t)cc * nl + i) * N + n] = t;
     }
 }
@@ -197,6 +210,53 @@ __global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const
         const PrimeInfo &pi = pinfo[i];
         u64 r = shoup(mag, pi.p_mod, pi.p_modp, pi.q);
         R[((size_t)cc * level + i) * N + n] = (neg && r) ? pi.q - r : r;
+    }
+}
+
+// Several primes at once, coefficient domain: drops q_from, q_from-1, ...,
+// q_to+1 in that order, each exactly as a single modulus switch (the NTT is
+// linear, so switching in either domain gives the same residues).  in/out are
+// [ct][2][from+1] and [ct][2][to+1] coefficient-domain limbs.
+constexpr int kMaxDrop = 16;
+__global__ void k_ms_multi(const u64 *__restrict__ in, u64 *__restrict__ out, const ModSwitchPlan *__restrict__ pl,
+                           const PrimeInfo *__restrict__ pinfo, int from, int to, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
+    const int nd = from - to;
+    const u64 *C = in + (size_t)cc * (from + 1) * N + n;
+    u64 tmag[kMaxDrop];
+    bool tneg[kMaxDrop];
+    // t_s for s = from, from-1, ..., to+1 (index d = from - s)
+#pragma unroll
+    for (int d = 0; d < kMaxDrop; d++) {
+        if (d >= nd) break;
+        const int s = from - d;
+        const u64 q = pinfo[s].q;
+        u64 c = C[(size_t)s * N];
+#pragma unroll
+        for (int e = 0; e < kMaxDrop; e++) {
+            if (e >= d) break;
+            const int se = from - e;
+            u64 r = shoup(tmag[e], pinfo[s].p_mod, pinfo[s].p_modp, q);
+            r = (tneg[e] && r) ? q - r : r;
+            c = shoup(sub_mod(c, r, q), pl[se].qlinv[s][0], pl[se].qlinv[s][1], q);
+        }
+        u64 t = shoup(c, pl[s].pinv_l[0], pl[s].pinv_l[1], q);
+        tneg[d] = t > (q - 1) / 2;
+        tmag[d] = tneg[d] ? q - t : t;
+    }
+    u64 *O = out + (size_t)cc * (to + 1) * N + n;
+    for (int i = 0; i <= to; i++) {
+        const u64 q = pinfo[i].q;
+        u64 c = C[(size_t)i * N];
+#pragma unroll
+        for (int e = 0; e < kMaxDrop; e++) {
+            if (e >= nd) break;
+            const int se = from - e;
+            u64 r = shoup(tmag[e], pinfo[i].p_mod, pinfo[i].p_modp, q);
+            r = (tneg[e] && r) ? q - r : r;
+            c = shoup(sub_mod(c, r, q), pl[se].qlinv[i][0], pl[se].qlinv[i][1], q);
+        }
+        O[(size_t)i * N] = c;
     }
 }
 
@@ -326,21 +386,29 @@ struct BabyArg {
     const u64 *baby[16];
     int pos[64];  // storage position of block t
 };
+// Babies are read at ciphertext blockIdx.z; outputs go to ciphertext
+// ct0 + blockIdx.z of a batch of `count` per block.
 __global__ void k_lincomb(BabyArg ba, const u64 *__restrict__ coef, u64 *__restrict__ out, int nbaby, int nblk,
-                          int count, int nl, const PrimeInfo *__restrict__ pinfo, int N) {
+                          int count, int ct0, int nl, const PrimeInfo *__restrict__ pinfo, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
     const u64 q = pinfo[i].q;
     const size_t L = (size_t)nl * N;
     for (int c = 0; c < 2; c++) {
         u64 v[16];
-        for (int k = 0; k < nbaby; k++) v[k] = ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n];
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (k >= nbaby) break;
+            v[k] = ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n];
+        }
         for (int t = 0; t < nblk; t++) {
             u64 acc = 0;
-            for (int k = 0; k < nbaby; k++) {
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                if (k >= nbaby) break;
                 const u64 *w = coef + (((size_t)t * nbaby + k) * nl + i) * 2;
                 acc = add_mod(acc, shoup(v[k], w[0], w[1], q), q);
             }
-            out[((size_t)ba.pos[t] * count + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] = acc;
+            out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] = acc;
         }
     }
 }
@@ -406,6 +474,10 @@ void launch_ms_top(const bc_ctx *c, const u64 *in, u64 *top, int count, int nl, 
 void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st) {
     k_ms_fbc<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(top, R, c->modsw + level, c->pinfo, level, c->N);
 }
+void launch_ms_multi(const bc_ctx *c, const u64 *in, u64 *out, int count, int from, int to, hipStream_t st) {
+    BC_REQUIRE(from - to <= kMaxDrop, BC_ERR_PARAM, "too many primes dropped at once");
+    k_ms_multi<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(in, out, c->modsw, c->pinfo, from, to, c->N);
+}
 void launch_ms_combine(const bc_ctx *c, const u64 *in, const u64 *R, u64 *out, int count, int level, hipStream_t st) {
     k_ms_combine<<<grid3(c->N, level, count), kT, 0, st>>>(in, R, out, c->modsw + level, c->pinfo, level, c->N);
 }
@@ -435,12 +507,12 @@ void launch_dec_inner(const bc_ctx *c, const u64 *ct, const u64 *s, u64 *d, int 
     k_dec_inner<<<grid3(c->N, nl, count), kT, 0, st>>>(ct, s, d, nl, ncomp, c->pinfo, c->N);
 }
 void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *pos, const u64 *coef, u64 *out, int nbaby,
-                    int nblk, int count, int nl, hipStream_t st) {
+                    int nblk, int count, int ct0, int nlaunch, int nl, hipStream_t st) {
     BC_REQUIRE(nbaby <= 16 && nblk <= 64, BC_ERR_PARAM, "schedule too large");
     BabyArg ba{};
     for (int k = 0; k < nbaby; k++) ba.baby[k] = babies[k];
     for (int t = 0; t < nblk; t++) ba.pos[t] = pos[t];
-    k_lincomb<<<grid3(c->N, nl, count), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, nl, c->pinfo, c->N);
+    k_lincomb<<<grid3(c->N, nl, nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo, c->N);
 }
 void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st) {
     k_crt_decode<<<grid3(c->N, 1, count), kT, 0, st>>>(d, out, c->garner, c->pinfo, nl, c->p, c->N);

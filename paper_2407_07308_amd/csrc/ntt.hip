@@ -4,17 +4,20 @@
 // domain (paper, Background, "Efficient Polynomial and NTT": radix-2
 // Cooley-Tukey forward and Gentleman-Sande inverse transforms for power-of-two
 // N).  Forward: natural-order coefficients in, bit-reversed evaluations out,
-// position r holding a(psi^(2 brv(r) + 1)); stage m (m = 1, 2, ..., N/2)
-// multiplies by W[m + i] = psi^brv(m + i) for butterfly group i.  Inverse:
-// Gentleman-Sande with Winv[k] = W[k]^-1, stages m = N/2 .. 1, scaled by N^-1.
+// position r holding a(psi^(2 brv(r) + 1)); the stage with butterfly span h
+// (m = N / 2h) multiplies group i by W[m + i] = psi^brv(m + i).  Inverse:
+// Gentleman-Sande with Winv[k] = W[k]^-1 in the reverse stage order, scaled
+// by N^-1.
 //
-// A limb of N = N1 * N2 words is treated as an N1 x N2 row-major matrix.  The
-// first log2 N1 forward stages only mix words of one column (butterfly span
-// >= N2); the remaining log2 N2 stages only mix words of one row.  Pass A
-// stages 16 columns of one limb in LDS, pass B stages whole rows; the inverse
-// runs B then A.  Each pass reads and writes every word once.  Butterflies are
-// Harvey's lazy ones: values live in [0, 4q) (forward) or [0, 2q) (inverse)
-// until the last stage, with Shoup multiplications by precomputed twiddles.
+// A limb of N = N1 * N2 words is an N1 x N2 row-major matrix.  The forward
+// stages with span >= N2 only mix words of one column (pass A), the others
+// only words of one row (pass B); the inverse runs B then A.  Each pass reads
+// and writes every word of the limb once.  Inside a pass the line (column or
+// row) is transformed in two register chunks of up to four stages: a thread
+// holds up to 16 words, applies its chunk's butterflies in registers, and the
+// two chunks exchange words through LDS once.  Butterflies are Harvey's lazy
+// ones (values in [0, 4q) forward, [0, 2q) inverse) with Shoup products by
+// precomputed twiddles.
 
 #include <algorithm>
 
@@ -25,7 +28,12 @@ namespace bc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLdsWords = 2048;  // 16 KiB of LDS per workgroup
+constexpr int kLineWords = kThreads * 16;  // words of one workgroup (32 KiB): 16 per thread
+
+// Columns per workgroup of pass A (N2 >= N1 always, so this never exceeds N2).
+constexpr int cols_per_block(int L1) {
+    return (kLineWords >> L1) < (1 << L1) ? (kLineWords >> L1) : (1 << L1);
+}
 
 struct Tw {
     const u64 *W, *Wp, *Wi, *Wip;
@@ -42,147 +50,229 @@ __device__ __forceinline__ u64 *limb_ptr(const LimbSet &ls, int job, int N, int 
     return ls.base + (size_t)poly * ls.poly_stride + (size_t)ls.off[k] * N;
 }
 
-// ---------------------------------------------------------------- pass A
-// One workgroup: C consecutive columns of one limb (N1 words each).
-template <int LOGN1, bool INVERSE>
-__global__ void __launch_bounds__(kThreads) ntt_pass_cols(LimbSet ls, const u64 *__restrict__ tw,
-                                                          const PrimeInfo *__restrict__ pinfo, int logN) {
-    constexpr int N1 = 1 << LOGN1;
-    constexpr int C = (N1 * 16 <= kLdsWords) ? 16 : kLdsWords / N1;
-    __shared__ u64 s[N1 * C];
-    const int N = 1 << logN, N2 = N >> LOGN1;
-    const int colblocks = N2 / C;
-    const int job = blockIdx.x / colblocks, c0 = (blockIdx.x - job * colblocks) * C;
-    int prime;
-    u64 *a = limb_ptr(ls, job, N, prime);
-    const u64 q = pinfo[prime].q, q2 = 2 * q;
-    const Tw t = tables(tw, prime, N);
-    const int tid = threadIdx.x;
+__device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2) {
+    u64 x = X >= q2 ? X - q2 : X;
+    u64 t = shoup_lazy(Y, w, wp, q);
+    X = x + t;
+    Y = x - t + q2;
+}
 
-    for (int idx = tid; idx < N1 * C; idx += kThreads) {
-        int r = idx / C, c = idx - r * C;
-        s[idx] = a[(size_t)r * N2 + c0 + c];
+__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2) {
+    u64 u = X + Y;
+    u64 d = X - Y + q2;
+    X = u >= q2 ? u - q2 : u;
+    Y = shoup_lazy(d, w, wp, q);
+}
+
+// Forward chunk: stages on line bits [blo, blo + C) (high to low) of the
+// 2^C words v[k] at line positions X0 + (k << blo).  For the stage on bit b
+// the twiddle index is tbase(b) + (k >> (C - s)), s = (blo + C - 1) - b, with
+// tbase(b) = mb(b) + G * 2^(L-1-b) + (X0 >> (b + 1)).
+template <int C>
+__device__ __forceinline__ void fwd_chunk(u64 *v, const Tw &t, int L, int blo, int X0, int G, int logM, u64 q) {
+    const u64 q2 = 2 * q;
+#pragma unroll
+    for (int s = 0; s < C; s++) {
+        const int b = blo + C - 1 - s;
+        const int half = 1 << (C - 1 - s);
+        const int tb = (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
+#pragma unroll
+        for (int blk = 0; blk < (1 << s); blk++) {
+            const u64 w = t.W[tb + blk], wp = t.Wp[tb + blk];
+#pragma unroll
+            for (int j = 0; j < half; j++) ct_bfly(v[blk * 2 * half + j], v[blk * 2 * half + j + half], w, wp, q, q2);
+        }
     }
-    __syncthreads();
+}
 
-    if (!INVERSE) {
-        for (int m = 1, tc = N1 / 2; m < N1; m <<= 1, tc >>= 1) {
-            for (int bf = tid; bf < (N1 / 2) * C; bf += kThreads) {
-                int c = bf % C, k = bf / C;
-                int i = k / tc, j = k - i * tc;
-                int r0 = 2 * i * tc + j, r1 = r0 + tc;
-                u64 w = t.W[m + i], wp = t.Wp[m + i];
-                u64 X = s[r0 * C + c], Y = s[r1 * C + c];
-                X = X >= q2 ? X - q2 : X;
-                u64 T = shoup_lazy(Y, w, wp, q);
-                s[r0 * C + c] = X + T;
-                s[r1 * C + c] = X - T + q2;
-            }
-            __syncthreads();
-        }
-        for (int idx = tid; idx < N1 * C; idx += kThreads) {
-            int r = idx / C, c = idx - r * C;
-            a[(size_t)r * N2 + c0 + c] = s[idx];
-        }
-    } else {
-        const PrimeInfo &pi = pinfo[prime];
-        for (int m = N1 / 2, tc = 1; m >= 1; m >>= 1, tc <<= 1) {
-            for (int bf = tid; bf < (N1 / 2) * C; bf += kThreads) {
-                int c = bf % C, k = bf / C;
-                int i = k / tc, j = k - i * tc;
-                int r0 = 2 * i * tc + j, r1 = r0 + tc;
-                u64 X = s[r0 * C + c], Y = s[r1 * C + c];
-                u64 U = X + Y;
-                U = U >= q2 ? U - q2 : U;
-                u64 D = X - Y + q2;
-                if (m > 1) {
-                    s[r0 * C + c] = U;
-                    s[r1 * C + c] = shoup_lazy(D, t.Wi[m + i], t.Wip[m + i], q);
-                } else {  // last stage: fold in N^-1 and reduce to [0, q)
-                    u64 u = shoup_lazy(U, pi.ninv, pi.ninvp, q);
-                    u64 v = shoup_lazy(D, pi.ninvw1, pi.ninvw1p, q);
-                    s[r0 * C + c] = u >= q ? u - q : u;
-                    s[r1 * C + c] = v >= q ? v - q : v;
+// Inverse chunk: stages on bits blo .. blo + C - 1 (low to high).  With
+// `scale`, the last stage (the transform's final one, m = 1) folds in N^-1.
+template <int C>
+__device__ __forceinline__ void inv_chunk(u64 *v, const Tw &t, int L, int blo, int X0, int G, int logM, u64 q,
+                                          bool scale, const PrimeInfo &pi) {
+    const u64 q2 = 2 * q;
+#pragma unroll
+    for (int s = 0; s < C; s++) {
+        const int b = blo + s;
+        const int half = 1 << s;
+        const int tb = (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
+#pragma unroll
+        for (int blk = 0; blk < (1 << (C - 1 - s)); blk++) {
+            const u64 w = t.Wi[tb + blk], wp = t.Wip[tb + blk];
+#pragma unroll
+            for (int j = 0; j < half; j++) {
+                u64 &X = v[blk * 2 * half + j], &Y = v[blk * 2 * half + j + half];
+                if (scale && s == C - 1) {
+                    u64 u = X + Y, d = X - Y + q2;
+                    u64 a = shoup_lazy(u, pi.ninv, pi.ninvp, q), r = shoup_lazy(d, pi.ninvw1, pi.ninvw1p, q);
+                    X = a >= q ? a - q : a;
+                    Y = r >= q ? r - q : r;
+                } else {
+                    gs_bfly(X, Y, w, wp, q, q2);
                 }
             }
-            __syncthreads();
         }
-        for (int idx = tid; idx < N1 * C; idx += kThreads) {
-            int r = idx / C, c = idx - r * C;
-            a[(size_t)r * N2 + c0 + c] = s[idx];
+    }
+}
+
+// ---------------------------------------------------------------- pass A
+// Columns: line = one column of N1 = 2^L1 words (stride N2 in memory), CW
+// columns per workgroup.  Twiddle index of the stage on bit b:
+// m = 2^(L1-1-b), group = row >> (b+1)  (so logM = L1, G = 0).
+template <int L1, bool INV>
+__global__ void __launch_bounds__(kThreads) ntt_cols(LimbSet ls, const u64 *__restrict__ tw,
+                                                     const PrimeInfo *__restrict__ pinfo, int logN) {
+    constexpr int N1 = 1 << L1;
+    constexpr int CW = cols_per_block(L1);
+    constexpr int CHI = (L1 + 1) / 2, CLO = L1 - CHI;  // chunk on the high / low row bits
+    __shared__ u64 s[N1 * CW];
+    const int N = 1 << logN, N2 = N >> L1;
+    const int colblocks = N2 / CW;
+    const int job = blockIdx.x / colblocks, c0 = (blockIdx.x - job * colblocks) * CW;
+    int prime;
+    u64 *a = limb_ptr(ls, job, N, prime) + c0;
+    const PrimeInfo &pi = pinfo[prime];
+    const u64 q = pi.q;
+    const Tw t = tables(tw, prime, N);
+    const int tid = threadIdx.x;
+    u64 v[16];
+
+    // Both chunks touch HBM directly: for a fixed k, consecutive threads take
+    // consecutive columns of one row, so every access is coalesced; LDS only
+    // carries the exchange between the chunks.
+    if (!INV) {
+        // high row bits first: words at rows X0 + (k << CLO)
+        for (int g = tid; g < (1 << CLO) * CW; g += kThreads) {
+            const int col = g % CW, X0 = g / CW;
+#pragma unroll
+            for (int k = 0; k < (1 << CHI); k++) v[k] = a[(size_t)(X0 + (k << CLO)) * N2 + col];
+            fwd_chunk<CHI>(v, t, L1, CLO, X0, 0, L1, q);
+#pragma unroll
+            for (int k = 0; k < (1 << CHI); k++) s[(X0 + (k << CLO)) * CW + col] = v[k];
+        }
+        __syncthreads();
+        for (int g = tid; g < (1 << CHI) * CW; g += kThreads) {
+            const int col = g % CW, X0 = (g / CW) << CLO;
+#pragma unroll
+            for (int k = 0; k < (1 << CLO); k++) v[k] = s[(X0 + k) * CW + col];
+            fwd_chunk<CLO>(v, t, L1, 0, X0, 0, L1, q);
+#pragma unroll
+            for (int k = 0; k < (1 << CLO); k++) a[(size_t)(X0 + k) * N2 + col] = v[k];
+        }
+    } else {
+        // low row bits first: words at rows X0 + k
+        for (int g = tid; g < (1 << CHI) * CW; g += kThreads) {
+            const int col = g % CW, X0 = (g / CW) << CLO;
+#pragma unroll
+            for (int k = 0; k < (1 << CLO); k++) v[k] = a[(size_t)(X0 + k) * N2 + col];
+            inv_chunk<CLO>(v, t, L1, 0, X0, 0, L1, q, false, pi);
+#pragma unroll
+            for (int k = 0; k < (1 << CLO); k++) s[(X0 + k) * CW + col] = v[k];
+        }
+        __syncthreads();
+        for (int g = tid; g < (1 << CLO) * CW; g += kThreads) {
+            const int col = g % CW, X0 = g / CW;
+#pragma unroll
+            for (int k = 0; k < (1 << CHI); k++) v[k] = s[(X0 + (k << CLO)) * CW + col];
+            inv_chunk<CHI>(v, t, L1, CLO, X0, 0, L1, q, true, pi);
+#pragma unroll
+            for (int k = 0; k < (1 << CHI); k++) a[(size_t)(X0 + (k << CLO)) * N2 + col] = v[k];
         }
     }
 }
 
 // ---------------------------------------------------------------- pass B
-// One workgroup: R consecutive rows (N2 contiguous words each) of one limb.
-template <int LOGN2, bool INVERSE>
-__global__ void __launch_bounds__(kThreads) ntt_pass_rows(LimbSet ls, const u64 *__restrict__ tw,
-                                                          const PrimeInfo *__restrict__ pinfo, int logN) {
-    constexpr int N2 = 1 << LOGN2;
-    __shared__ u64 s[kLdsWords];
-    const int N = 1 << logN, N1 = N >> LOGN2;
-    const int R = min(kLdsWords / N2, N1);
+// Rows: line = one row of N2 = 2^L2 contiguous words, R rows per workgroup.
+// Twiddle index of the stage on bit b in row u: m = N / 2^(b+1),
+// group = u * 2^(L2-1-b) + (x >> (b+1))  (logM = logN, G = u).
+// LDS rows are padded by one word per 16 so both chunks' accesses avoid
+// bank conflicts.
+__device__ __forceinline__ int padx(int x) { return x + (x >> 4); }
+
+template <int L2, bool INV>
+__global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const u64 *__restrict__ tw,
+                                                     const PrimeInfo *__restrict__ pinfo, int logN) {
+    constexpr int N2 = 1 << L2;
+    constexpr int RS = N2 + N2 / 16;  // padded row stride in LDS
+    constexpr int CHI = (L2 + 1) / 2, CLO = L2 - CHI;
+    constexpr int RMAX = kLineWords / N2;
+    __shared__ u64 s[RMAX * RS];
+    const int N = 1 << logN, N1 = N >> L2;
+    const int R = min(RMAX, N1);
     const int rowblocks = N1 / R;
     const int job = blockIdx.x / rowblocks, u0 = (blockIdx.x - job * rowblocks) * R;
     int prime;
     u64 *a = limb_ptr(ls, job, N, prime) + (size_t)u0 * N2;
-    const u64 q = pinfo[prime].q, q2 = 2 * q;
+    const PrimeInfo &pi = pinfo[prime];
+    const u64 q = pi.q;
     const Tw t = tables(tw, prime, N);
     const int tid = threadIdx.x;
+    u64 v[16];
 
-    for (int idx = tid; idx < R * N2; idx += kThreads) s[idx] = a[idx];
-    __syncthreads();
-
-    if (!INVERSE) {
-        for (int ml = 1, h = N2 / 2; ml < N2; ml <<= 1, h >>= 1) {
-            const int mg = ml * N1;
-            for (int bf = tid; bf < R * N2 / 2; bf += kThreads) {
-                int rr = bf / (N2 / 2), k = bf - rr * (N2 / 2);
-                int i = k / h, j = k - i * h;
-                int x0 = rr * N2 + 2 * i * h + j, x1 = x0 + h;
-                int wi = mg + (u0 + rr) * ml + i;
-                u64 X = s[x0], Y = s[x1];
-                X = X >= q2 ? X - q2 : X;
-                u64 T = shoup_lazy(Y, t.W[wi], t.Wp[wi], q);
-                s[x0] = X + T;
-                s[x1] = X - T + q2;
-            }
-            __syncthreads();
+    if (!INV) {
+        for (int g = tid; g < R << CLO; g += kThreads) {
+            const int rr = g >> CLO, X0 = g & ((1 << CLO) - 1);
+            const u64 *row = a + (size_t)rr * N2;
+#pragma unroll
+            for (int k = 0; k < (1 << CHI); k++) v[k] = row[X0 + (k << CLO)];
+            fwd_chunk<CHI>(v, t, L2, CLO, X0, u0 + rr, logN, q);
+#pragma unroll
+            for (int k = 0; k < (1 << CHI); k++) s[rr * RS + padx(X0 + (k << CLO))] = v[k];
         }
+        __syncthreads();
+        const u64 q2 = 2 * q;
+        for (int g = tid; g < R << CHI; g += kThreads) {
+            const int rr = g >> CHI, X0 = (g & ((1 << CHI) - 1)) << CLO;
+#pragma unroll
+            for (int k = 0; k < (1 << CLO); k++) v[k] = s[rr * RS + padx(X0 + k)];
+            fwd_chunk<CLO>(v, t, L2, 0, X0, u0 + rr, logN, q);
+#pragma unroll
+            for (int k = 0; k < (1 << CLO); k++) {
+                u64 x = v[k];
+                x = x >= q2 ? x - q2 : x;
+                s[rr * RS + padx(X0 + k)] = x >= q ? x - q : x;
+            }
+        }
+        __syncthreads();
         for (int idx = tid; idx < R * N2; idx += kThreads) {
-            u64 x = s[idx];
-            x = x >= q2 ? x - q2 : x;
-            a[idx] = x >= q ? x - q : x;
+            int rr = idx >> L2, x = idx & (N2 - 1);
+            a[idx] = s[rr * RS + padx(x)];
         }
     } else {
-        for (int ml = N2 / 2, h = 1; ml >= 1; ml >>= 1, h <<= 1) {
-            const int mg = ml * N1;
-            for (int bf = tid; bf < R * N2 / 2; bf += kThreads) {
-                int rr = bf / (N2 / 2), k = bf - rr * (N2 / 2);
-                int i = k / h, j = k - i * h;
-                int x0 = rr * N2 + 2 * i * h + j, x1 = x0 + h;
-                int wi = mg + (u0 + rr) * ml + i;
-                u64 X = s[x0], Y = s[x1];
-                u64 U = X + Y;
-                U = U >= q2 ? U - q2 : U;
-                s[x0] = U;
-                s[x1] = shoup_lazy(X - Y + q2, t.Wi[wi], t.Wip[wi], q);
-            }
-            __syncthreads();
+        for (int idx = tid; idx < R * N2; idx += kThreads) {
+            int rr = idx >> L2, x = idx & (N2 - 1);
+            s[rr * RS + padx(x)] = a[idx];
         }
-        for (int idx = tid; idx < R * N2; idx += kThreads) a[idx] = s[idx];
+        __syncthreads();
+        for (int g = tid; g < R << CHI; g += kThreads) {
+            const int rr = g >> CHI, X0 = (g & ((1 << CHI) - 1)) << CLO;
+#pragma unroll
+            for (int k = 0; k < (1 << CLO); k++) v[k] = s[rr * RS + padx(X0 + k)];
+            inv_chunk<CLO>(v, t, L2, 0, X0, u0 + rr, logN, q, false, pi);
+#pragma unroll
+            for (int k = 0; k < (1 << CLO); k++) s[rr * RS + padx(X0 + k)] = v[k];
+        }
+        __syncthreads();
+        for (int g = tid; g < R << CLO; g += kThreads) {
+            const int rr = g >> CLO, X0 = g & ((1 << CLO) - 1);
+#pragma unroll
+            for (int k = 0; k < (1 << CHI); k++) v[k] = s[rr * RS + padx(X0 + (k << CLO))];
+            inv_chunk<CHI>(v, t, L2, CLO, X0, u0 + rr, logN, q, false, pi);
+            u64 *row = a + (size_t)rr * N2;
+#pragma unroll
+            for (int k = 0; k < (1 << CHI); k++) row[X0 + (k << CLO)] = v[k];
+        }
     }
 }
 
-template <bool INVERSE>
+template <bool INV>
 void launch_cols(int logN1, int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
-    int N2 = 1 << (logN - logN1), C = ((16 << logN1) <= kLdsWords) ? 16 : (kLdsWords >> logN1);
+    int N2 = 1 << (logN - logN1), C = cols_per_block(logN1);
     int njobs = ls.npoly * ls.nlimb;
     dim3 grid((unsigned)(njobs * (N2 / C)));
 #define BC_COLS(L)                                                                                \
     case L:                                                                                       \
-        ntt_pass_cols<L, INVERSE><<<grid, kThreads, 0, st>>>(ls, c->tw, c->pinfo, logN);          \
+        ntt_cols<L, INV><<<grid, kThreads, 0, st>>>(ls, c->tw, c->pinfo, logN);                   \
         break;
     switch (logN1) {
         BC_COLS(5) BC_COLS(6) BC_COLS(7) BC_COLS(8)
@@ -191,14 +281,14 @@ void launch_cols(int logN1, int logN, const LimbSet &ls, const bc_ctx *c, hipStr
 #undef BC_COLS
 }
 
-template <bool INVERSE>
+template <bool INV>
 void launch_rows(int logN2, int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
-    int N1 = 1 << (logN - logN2), R = std::min(kLdsWords >> logN2, N1);
+    int N1 = 1 << (logN - logN2), R = std::min(kLineWords >> logN2, N1);
     int njobs = ls.npoly * ls.nlimb;
     dim3 grid((unsigned)(njobs * (N1 / R)));
 #define BC_ROWS(L)                                                                                \
     case L:                                                                                       \
-        ntt_pass_rows<L, INVERSE><<<grid, kThreads, 0, st>>>(ls, c->tw, c->pinfo, logN);          \
+        ntt_rows<L, INV><<<grid, kThreads, 0, st>>>(ls, c->tw, c->pinfo, logN);                   \
         break;
     switch (logN2) {
         BC_ROWS(5) BC_ROWS(6) BC_ROWS(7) BC_ROWS(8)
@@ -209,10 +299,10 @@ void launch_rows(int logN2, int logN, const LimbSet &ls, const bc_ctx *c, hipStr
 
 }  // namespace
 
-// N1 = 2^floor(logN/2) rows, N2 = 2^ceil(logN/2) columns.
 // Algorithmic bytes of a transform: every limb read once and written once.
 static double ntt_bytes(const bc_ctx *c, const LimbSet &ls) { return 16.0 * c->N * ls.npoly * ls.nlimb; }
 
+// N1 = 2^floor(logN/2) rows, N2 = 2^ceil(logN/2) columns.
 void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (ls.npoly == 0 || ls.nlimb == 0) return;
     int logN1 = c->logN / 2, logN2 = c->logN - logN1;

@@ -95,6 +95,25 @@ def dev_slice(dev, b, i):
     return bc.Batch(b.tensor[i * w:(i + 1) * w], 1, b.level, b.ncomp)
 
 
+def test_per_op_path_equals_batched():
+    """One ciphertext per launch gives the same bytes as the batched launches."""
+    import paper_2407_07308_amd as bc
+
+    prm = Params(10, 17, 6, 36, 1, 60, 3)
+    dev, dk, orc = make(prm)
+    G, base, nd = 3, 9, 2
+    xs = synth.integers(95, (G, orc.M), 0, base ** nd)
+    ys = synth.integers(95, (G, orc.M), 0, base ** nd, index=1)
+    DA, _ = enc_planes(dev, dk, orc, oracle.to_digits(xs, base, nd), 96)
+    DB, _ = enc_planes(dev, dk, orc, oracle.to_digits(ys, base, nd), 97)
+    lt, mx, mn = dev.compare_max_min(dk, DA, DB)
+    dev.set_exec_mode(bc.BC_EXEC_PER_OP)
+    lt2, mx2, mn2 = dev.compare_max_min(dk, DA, DB)
+    dev.set_exec_mode(bc.BC_EXEC_BATCHED)
+    for x, y in [(lt, lt2)] + list(zip(mx, mx2)) + list(zip(mn, mn2)):
+        assert np.array_equal(dev.export(x), dev.export(y))
+
+
 def test_lt_p257_matches_oracle_and_graph_replay():
     import paper_2407_07308_amd as bc
 
