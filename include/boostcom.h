@@ -187,6 +187,22 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
 enum { BC_EXEC_BATCHED = 0, BC_EXEC_GRAPH = 1, BC_EXEC_PER_OP = 2 };
 int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
 
+/* Tuning knobs (results never change, only speed):
+ *   BC_TUNE_NTT_CHUNK_BYTES: split every batched transform into launch pairs
+ *   over at most this many bytes of limbs (0 = no split), so the first pass's
+ *   output is still cached when the second pass reads it.
+ *   BC_TUNE_NTT_SINGLE_PASS: 1 (default) transforms a whole limb in one
+ *   workgroup for N = 2^12 .. 2^15 (each word read and written once); 0 uses
+ *   the two-pass column/row transform for every N. */
+enum { BC_TUNE_NTT_CHUNK_BYTES = 0, BC_TUNE_NTT_SINGLE_PASS = 1 };
+int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
+int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);
+/* Times each transform schedule (two-pass, two-pass in cache-sized chunks,
+ * single-pass where N allows) on a synthetic batch of this context's shape
+ * (about 384 MB of limbs) and keeps the fastest.  Synchronises the stream;
+ * takes a few tens of milliseconds. */
+int bc_autotune(bc_ctx *ctx, void *stream);
+
 /* ------------------------------------------------------------ profiling */
 /* When enabled (outside graph mode), every transform launch pair is bracketed
  * with HIP events recorded on the stream it runs on.  bc_profile_read sums,

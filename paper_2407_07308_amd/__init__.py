@@ -22,6 +22,7 @@ BC_OK, BC_ERR_ARG, BC_ERR_PARAM, BC_ERR_LEVEL, BC_ERR_OOM, BC_ERR_HIP, BC_ERR_KE
 BC_ROW_SWAP = -1
 BC_EXEC_BATCHED, BC_EXEC_GRAPH, BC_EXEC_PER_OP = 0, 1, 2
 BC_PROF_NTT_FWD, BC_PROF_NTT_INV = 0, 1
+BC_TUNE_NTT_CHUNK_BYTES, BC_TUNE_NTT_SINGLE_PASS = 0, 1
 
 
 class BoostcomUnavailable(RuntimeError):
@@ -77,6 +78,9 @@ _SIGS = {
     "bc_compare_lt": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_compare_max_min": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_set_exec_mode": (_I, [_V, _I]),
+    "bc_set_tuning": (_I, [_V, _I, ctypes.c_int64]),
+    "bc_autotune": (_I, [_V, _V]),
+    "bc_get_tuning": (_I, [_V, _I, _P(ctypes.c_int64)]),
     "bc_profile_enable": (_I, [_V, _I]),
     "bc_profile_read": (_I, [_V, _I, _P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_double)]),
     "bc_strerror": (ctypes.c_char_p, [_I]),
@@ -317,6 +321,20 @@ class Context:
 
     def set_exec_mode(self, mode: int):
         _check(self.L.bc_set_exec_mode(self.handle, mode))
+
+    def set_tuning(self, key: int, value: int):
+        _check(self.L.bc_set_tuning(self.handle, key, int(value)))
+
+    def autotune(self) -> dict:
+        """Picks the fastest transform schedule for this context; returns it."""
+        _check(self.L.bc_autotune(self.handle, _stream()))
+        return {"single_pass": self.get_tuning(BC_TUNE_NTT_SINGLE_PASS),
+                "chunk_bytes": self.get_tuning(BC_TUNE_NTT_CHUNK_BYTES)}
+
+    def get_tuning(self, key: int) -> int:
+        v = ctypes.c_int64()
+        _check(self.L.bc_get_tuning(self.handle, key, ctypes.byref(v)))
+        return v.value
 
     def profile_enable(self, on: bool):
         _check(self.L.bc_profile_enable(self.handle, 1 if on else 0))

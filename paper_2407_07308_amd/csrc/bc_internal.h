@@ -213,6 +213,8 @@ struct bc_ctx {
     std::vector<bc::ModUpPlan> h_modup;  // host copies (launch sizing)
     bc::Pool pool;
     int exec_mode = BC_EXEC_BATCHED;
+    size_t ntt_chunk_bytes = 0;  // 0: one launch pair per transform call
+    int ntt_single_pass = 1;     // one-launch transform for N = 2^12 .. 2^15
     std::unique_ptr<bc::GraphCache> graphs;
     std::mutex graph_mu;
     hipStream_t capture_stream = nullptr;      // graph recording (created on first use)

@@ -384,6 +384,85 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
     });
 }
 
+int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(value >= 0, BC_ERR_ARG, "tuning value must be non-negative");
+        if (key == BC_TUNE_NTT_CHUNK_BYTES) ctx->ntt_chunk_bytes = (size_t)value;
+        else if (key == BC_TUNE_NTT_SINGLE_PASS) ctx->ntt_single_pass = value != 0;
+        else throw Error(BC_ERR_ARG, "unknown tuning key");
+    });
+}
+
+int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(value, BC_ERR_ARG, "null output");
+        if (key == BC_TUNE_NTT_CHUNK_BYTES) *value = (int64_t)ctx->ntt_chunk_bytes;
+        else if (key == BC_TUNE_NTT_SINGLE_PASS) *value = ctx->ntt_single_pass;
+        else throw Error(BC_ERR_ARG, "unknown tuning key");
+    });
+}
+
+int bc_autotune(bc_ctx *ctx, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        StreamScope sc(stream);
+        hipStream_t st = (hipStream_t)stream;
+        const int N = ctx->N, nl = ctx->nQ;
+        const size_t per_poly = (size_t)nl * N * sizeof(u64);
+        const int count = (int)std::max<size_t>(4, ((size_t)384 << 20) / per_poly);
+        BufP buf = make_buf(ctx, per_poly * count);
+        BC_HIP(hipMemsetAsync(buf->p, 0, per_poly * count, st));
+        LimbSet ls{};
+        ls.base = (u64 *)buf->p;
+        ls.poly_stride = (u64)nl * N;
+        ls.npoly = count;
+        ls.nlimb = nl;
+        for (int i = 0; i < nl; i++) {
+            ls.off[i] = (int16_t)i;
+            ls.prime[i] = (int16_t)i;
+        }
+        struct Cand {
+            int single;
+            size_t chunk;
+        };
+        std::vector<Cand> cands = {{0, 0}, {0, (size_t)128 << 20}};
+        if (ctx->logN >= 12 && ctx->logN <= 15) cands.push_back({1, 0});
+        const bool prof = ctx->prof->on;
+        ctx->prof->on = false;
+        hipEvent_t e0, e1;
+        BC_HIP(hipEventCreate(&e0));
+        BC_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        Cand pick = cands[0];
+        for (const Cand &cd : cands) {
+            ctx->ntt_single_pass = cd.single;
+            ctx->ntt_chunk_bytes = cd.chunk;
+            ntt_forward(ctx, ls, st);
+            ntt_inverse(ctx, ls, st);
+            BC_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 3; r++) {
+                ntt_forward(ctx, ls, st);
+                ntt_inverse(ctx, ls, st);
+            }
+            BC_HIP(hipEventRecord(e1, st));
+            BC_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            BC_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                pick = cd;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->ntt_single_pass = pick.single;
+        ctx->ntt_chunk_bytes = pick.chunk;
+        ctx->prof->on = prof;
+    });
+}
+
 int bc_profile_enable(bc_ctx *ctx, int32_t on) {
     return guard([&] {
         check_ctx(ctx);

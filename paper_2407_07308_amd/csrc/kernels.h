@@ -24,6 +24,10 @@ void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size
                        const u64 *th, u64 *out, size_t out_ct_stride, int count, int level, int next, hipStream_t st);
 void launch_ms_top(const bc_ctx *c, const u64 *in, u64 *top, int count, int nl, hipStream_t st);
 void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st);
+void launch_relin_ms_fbc(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
+                         int level, int next, hipStream_t st);
+void launch_relin_ms_combine(const bc_ctx *c, const u64 *d, size_t d_ct_stride, const u64 *acc, const u64 *E, u64 *out,
+                             int count, int level, int next, hipStream_t st);
 void launch_ms_multi(const bc_ctx *c, const u64 *in, u64 *out, int count, int from, int to, hipStream_t st);
 void launch_ms_combine(const bc_ctx *c, const u64 *in, const u64 *R, u64 *out, int count, int level, hipStream_t st);
 void launch_words_mod(const bc_ctx *c, const u64 *w, u64 *out, const int16_t *primes, int npoly, int nlimb,

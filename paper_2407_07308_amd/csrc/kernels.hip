@@ -190,6 +190,77 @@ __global__ void k_ks_combine(const u64 *__restrict__ base0, const u64 *__restric
     }
 }
 
+// ---------------------- relinearisation fused with one modulus switch
+// Coefficient domain, per coefficient and component c (z-grid = ct * 2 + c):
+//   th_i  = sum_j v_j Phat_j mod q_i, v_j = [acc_{p_j} p^-1 Phat_j^-1]_{p_j}
+//   r_l   = d_l + (acc_l - p th_l) P^-1            (relinearised top limb)
+//   t     = [r_l p^-1]_{q_l} in (-q_l/2, q_l/2]
+//   E_i   = (th_i p P^-1 + p t) q_l^-1,  i < l
+// so that, after E is transformed, out_i = (d_i + acc_i P^-1) q_l^-1 - E_i
+// equals the modulus switch of the relinearised ciphertext exactly (every
+// step is linear over Z_{q_i}).  d and acc limbs l are coefficient domain here.
+__global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restrict__ d, size_t d_ct_stride,
+                               u64 *__restrict__ E, const ModDownPlan *__restrict__ md,
+                               const ModSwitchPlan *__restrict__ ms, const PrimeInfo *__restrict__ pinfo, int level,
+                               int nQ, int nP, int next, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
+    const int ct = cc >> 1, c = cc & 1, nl = level + 1;
+    u64 v[kMaxDigit];
+#pragma unroll
+    for (int j = 0; j < kMaxDigit; j++) {
+        if (j >= nP) break;
+        u64 x = acc[((size_t)cc * next + nl + j) * N + n];
+        v[j] = shoup(x, md->vfac[j][0], md->vfac[j][1], pinfo[nQ + j].q);
+    }
+    // top limb of the relinearised component
+    const u64 ql = pinfo[level].q;
+    u64 th = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxDigit; j++) {
+        if (j >= nP) break;
+        th = add_mod(th, shoup(v[j], md->phat[level][j][0], md->phat[level][j][1], ql), ql);
+    }
+    u64 a = acc[((size_t)cc * next + level) * N + n];
+    u64 r = sub_mod(shoup(a, md->pinv[level][0], md->pinv[level][1], ql),
+                    shoup(th, md->ppinv[level][0], md->ppinv[level][1], ql), ql);
+    r = add_mod(r, d[(size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n], ql);
+    const u64 t = shoup(r, ms->pinv_l[0], ms->pinv_l[1], ql);
+    const bool neg = t > (ql - 1) / 2;
+    const u64 mag = neg ? ql - t : t;
+    for (int i = 0; i < level; i++) {
+        const PrimeInfo &pi = pinfo[i];
+        const u64 q = pi.q;
+        u64 h = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxDigit; j++) {
+            if (j >= nP) break;
+            h = add_mod(h, shoup(v[j], md->phat[i][j][0], md->phat[i][j][1], q), q);
+        }
+        u64 pt = shoup(mag, pi.p_mod, pi.p_modp, q);
+        pt = (neg && pt) ? q - pt : pt;
+        u64 e = add_mod(shoup(h, md->ppinv[i][0], md->ppinv[i][1], q), pt, q);
+        E[((size_t)cc * level + i) * N + n] = shoup(e, ms->qlinv[i][0], ms->qlinv[i][1], q);
+    }
+}
+
+// out[ct][c][i] = (d_i + acc_i P^-1) q_l^-1 - E_i, i < level (NTT domain)
+struct PairArg {
+    u64 w[kMaxMod][4];  // q_l^-1 and P^-1 q_l^-1 mod q_i (Shoup pairs)
+};
+__global__ void k_relin_ms_combine(const u64 *__restrict__ d, size_t d_ct_stride, const u64 *__restrict__ acc,
+                                   const u64 *__restrict__ E, u64 *__restrict__ out, PairArg pa,
+                                   const PrimeInfo *__restrict__ pinfo, int level, int next, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const u64 q = pinfo[i].q;
+    const int nl = level + 1;
+    for (int c = 0; c < 2; c++) {
+        u64 x = shoup(d[(size_t)ct * d_ct_stride + ((size_t)c * nl + i) * N + n], pa.w[i][0], pa.w[i][1], q);
+        u64 y = shoup(acc[(((size_t)ct * 2 + c) * next + i) * N + n], pa.w[i][2], pa.w[i][3], q);
+        u64 e = E[(((size_t)ct * 2 + c) * level + i) * N + n];
+        out[(((size_t)ct * 2 + c) * level + i) * N + n] = sub_mod(add_mod(x, y, q), e, q);
+    }
+}
+
 // ----------------------------------------------------- modulus switching
 
 // top limb of both components -> TOP[ct][c][n]
@@ -473,6 +544,28 @@ void launch_ms_top(const bc_ctx *c, const u64 *in, u64 *top, int count, int nl, 
 }
 void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st) {
     k_ms_fbc<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(top, R, c->modsw + level, c->pinfo, level, c->N);
+}
+void launch_relin_ms_fbc(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
+                         int level, int next, hipStream_t st) {
+    k_relin_ms_fbc<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(acc, d, d_ct_stride, E, c->moddown, c->modsw + level,
+                                                            c->pinfo, level, c->nQ, c->nP, next, c->N);
+}
+void launch_relin_ms_combine(const bc_ctx *c, const u64 *d, size_t d_ct_stride, const u64 *acc, const u64 *E, u64 *out,
+                             int count, int level, int next, hipStream_t st) {
+    PairArg pa{};
+    const u64 ql = c->mod[level];
+    for (int i = 0; i < level; i++) {
+        const u64 q = c->mod[i];
+        u64 P = 1;
+        for (int t = 0; t < c->nP; t++) P = h_mulmod(P, c->mod[c->nQ + t] % q, q);
+        const u64 qlinv = h_invmod(ql % q, q), pq = h_mulmod(h_invmod(P, q), qlinv, q);
+        pa.w[i][0] = qlinv;
+        pa.w[i][1] = h_shoup(qlinv, q);
+        pa.w[i][2] = pq;
+        pa.w[i][3] = h_shoup(pq, q);
+    }
+    k_relin_ms_combine<<<grid3(c->N, level, count), kT, 0, st>>>(d, d_ct_stride, acc, E, out, pa, c->pinfo, level,
+                                                                 next, c->N);
 }
 void launch_ms_multi(const bc_ctx *c, const u64 *in, u64 *out, int count, int from, int to, hipStream_t st) {
     BC_REQUIRE(from - to <= kMaxDrop, BC_ERR_PARAM, "too many primes dropped at once");

@@ -44,8 +44,11 @@ __device__ __forceinline__ Tw tables(const u64 *tw, int prime, int N) {
     return {b, b + N, b + 2 * N, b + 3 * N};
 }
 
+// Jobs are ordered limb-major: consecutive workgroups transform the same limb
+// of consecutive ciphertexts, so they share one prime's twiddle table and the
+// set of tables live in each XCD's L2 at any time stays small.
 __device__ __forceinline__ u64 *limb_ptr(const LimbSet &ls, int job, int N, int &prime) {
-    int poly = job / ls.nlimb, k = job - poly * ls.nlimb;
+    int k = job / ls.npoly, poly = job - k * ls.npoly;
     prime = ls.prime[k];
     return ls.base + (size_t)poly * ls.poly_stride + (size_t)ls.off[k] * N;
 }
@@ -265,6 +268,156 @@ __global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const u64 *__re
     }
 }
 
+// ------------------------------------------------------------ single pass
+// One workgroup of N/32 threads transforms a whole limb (N = 2^12 .. 2^15):
+// 32 words per thread in registers, three register chunks on the bit ranges
+// [LOGN-5, LOGN), [C3, C3+5) and [0, C3) (C3 = LOGN - 10), two LDS exchanges
+// between them.  Every word crosses HBM once in and once out.  At N = 2^15
+// the 256 KiB limb does not fit in LDS, so each exchange runs in two rounds
+// split on bit 14 of the word index (128 KiB each).
+struct alignas(16) U64x2 {
+    u64 a, b;
+};
+
+constexpr int kSplitWords = 16384;
+
+// LDS slot of word x.  With SPLIT the exchange runs in two rounds on bit BIT
+// of x (removed from the slot index); BIT is chosen so that in both layouts it
+// is a bit of the thread id, i.e. every thread writes and reads in one round.
+// One pad word per 32 keeps the strided accesses conflict-free.
+template <bool SPLIT, int BIT>
+__device__ __forceinline__ int lds_pos(int x) {
+    int y = SPLIT ? (((x >> (BIT + 1)) << BIT) | (x & ((1 << BIT) - 1))) : x;
+    return y + (y >> 5);
+}
+template <bool SPLIT, int BIT>
+__device__ __forceinline__ int lds_round(int x) {
+    return SPLIT ? (x >> BIT) & 1 : 0;
+}
+
+template <int LOGN, bool INV>
+__global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const u64 *__restrict__ tw,
+                                                            const PrimeInfo *__restrict__ pinfo) {
+    constexpr int N = 1 << LOGN, C3 = LOGN - 10, NSPLIT = N > kSplitWords ? 2 : 1;
+    constexpr int G3 = 1 << (5 - C3);  // chunk-3 groups per thread
+    constexpr int LW = N > kSplitWords ? kSplitWords : N;
+    __shared__ u64 s[LW + LW / 32];
+    const int t = threadIdx.x;
+    int prime;
+    u64 *a = limb_ptr(ls, blockIdx.x, N, prime);
+    const PrimeInfo &pi = pinfo[prime];
+    const u64 q = pi.q;
+    const Tw tb = tables(tw, prime, N);
+    // word index of register k in each layout
+    const int x1 = t;                                                     // + (k << (LOGN - 5))
+    const int x2 = ((t >> C3) << (C3 + 5)) | (t & ((1 << C3) - 1));       // + (k << C3)
+    const int x3 = t << 5;                                                // + k
+    u64 v[32];
+
+    // exchange 1-2 splits on bit 4 (from t in both layouts), exchange 2-3 on
+    // bit 14 (t's bits 5..9 in both layouts)
+    constexpr bool SP = NSPLIT == 2;
+    const int ra = lds_round<SP, 4>(x1), rb = lds_round<SP, 14>(x3);
+    if (!INV) {
+#pragma unroll
+        for (int k = 0; k < 32; k++) v[k] = a[x1 + (k << (LOGN - 5))];
+        fwd_chunk<5>(v, tb, LOGN, LOGN - 5, x1, 0, LOGN, q);
+#pragma unroll
+        for (int r = 0; r < NSPLIT; r++) {
+            if (ra == r) {
+#pragma unroll
+                for (int k = 0; k < 32; k++) s[lds_pos<SP, 4>(x1 + (k << (LOGN - 5)))] = v[k];
+            }
+            __syncthreads();
+            if (ra == r) {
+#pragma unroll
+                for (int k = 0; k < 32; k++) v[k] = s[lds_pos<SP, 4>(x2 + (k << C3))];
+            }
+            __syncthreads();
+        }
+        fwd_chunk<5>(v, tb, LOGN, C3, x2, 0, LOGN, q);
+#pragma unroll
+        for (int r = 0; r < NSPLIT; r++) {
+            if (rb == r) {
+#pragma unroll
+                for (int k = 0; k < 32; k++) s[lds_pos<SP, 14>(x2 + (k << C3))] = v[k];
+            }
+            __syncthreads();
+            if (rb == r) {
+#pragma unroll
+                for (int k = 0; k < 32; k++) v[k] = s[lds_pos<SP, 14>(x3 + k)];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), tb, LOGN, 0, x3 + (j << C3), 0, LOGN, q);
+        const u64 q2 = 2 * q;
+        U64x2 *out = reinterpret_cast<U64x2 *>(a + x3);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            u64 e = v[2 * k], o = v[2 * k + 1];
+            e = e >= q2 ? e - q2 : e;
+            o = o >= q2 ? o - q2 : o;
+            out[k] = U64x2{e >= q ? e - q : e, o >= q ? o - q : o};
+        }
+    } else {
+        const U64x2 *in = reinterpret_cast<const U64x2 *>(a + x3);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            U64x2 p = in[k];
+            v[2 * k] = p.a;
+            v[2 * k + 1] = p.b;
+        }
+#pragma unroll
+        for (int j = 0; j < G3; j++)
+            inv_chunk<C3>(v + (j << C3), tb, LOGN, 0, x3 + (j << C3), 0, LOGN, q, false, pi);
+#pragma unroll
+        for (int r = 0; r < NSPLIT; r++) {
+            if (rb == r) {
+#pragma unroll
+                for (int k = 0; k < 32; k++) s[lds_pos<SP, 14>(x3 + k)] = v[k];
+            }
+            __syncthreads();
+            if (rb == r) {
+#pragma unroll
+                for (int k = 0; k < 32; k++) v[k] = s[lds_pos<SP, 14>(x2 + (k << C3))];
+            }
+            __syncthreads();
+        }
+        inv_chunk<5>(v, tb, LOGN, C3, x2, 0, LOGN, q, false, pi);
+#pragma unroll
+        for (int r = 0; r < NSPLIT; r++) {
+            if (ra == r) {
+#pragma unroll
+                for (int k = 0; k < 32; k++) s[lds_pos<SP, 4>(x2 + (k << C3))] = v[k];
+            }
+            __syncthreads();
+            if (ra == r) {
+#pragma unroll
+                for (int k = 0; k < 32; k++) v[k] = s[lds_pos<SP, 4>(x1 + (k << (LOGN - 5)))];
+            }
+            __syncthreads();
+        }
+        inv_chunk<5>(v, tb, LOGN, LOGN - 5, x1, 0, LOGN, q, true, pi);
+#pragma unroll
+        for (int k = 0; k < 32; k++) a[x1 + (k << (LOGN - 5))] = v[k];
+    }
+}
+
+template <bool INV>
+bool launch_full(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+    const unsigned njobs = (unsigned)(ls.npoly * ls.nlimb);
+#define BC_FULL(L)                                                                                \
+    case L:                                                                                       \
+        ntt_full<L, INV><<<njobs, 1 << (L - 5), 0, st>>>(ls, c->tw, c->pinfo);                    \
+        return true;
+    switch (logN) {
+        BC_FULL(12) BC_FULL(13) BC_FULL(14) BC_FULL(15)
+        default: return false;
+    }
+#undef BC_FULL
+}
+
 template <bool INV>
 void launch_cols(int logN1, int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
     int N2 = 1 << (logN - logN1), C = cols_per_block(logN1);
@@ -302,6 +455,15 @@ void launch_rows(int logN2, int logN, const LimbSet &ls, const bc_ctx *c, hipStr
 // Algorithmic bytes of a transform: every limb read once and written once.
 static double ntt_bytes(const bc_ctx *c, const LimbSet &ls) { return 16.0 * c->N * ls.npoly * ls.nlimb; }
 
+// Polynomials per launch pair: with a chunk size set, the two passes run on
+// slices of at most that many bytes, so the intermediate written by the first
+// pass can still sit in the 256 MB last-level cache when the second reads it.
+static int polys_per_chunk(const bc_ctx *c, const LimbSet &ls) {
+    const size_t per_poly = (size_t)ls.nlimb * 8 * c->N;
+    if (c->ntt_chunk_bytes == 0 || ls.poly_stride == 0) return ls.npoly;
+    return (int)std::max<size_t>(1, c->ntt_chunk_bytes / per_poly);
+}
+
 // N1 = 2^floor(logN/2) rows, N2 = 2^ceil(logN/2) columns.
 void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (ls.npoly == 0 || ls.nlimb == 0) return;
@@ -309,8 +471,19 @@ void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     ProfRec r{};
     const bool prof = c->prof->on;
     if (prof) c->prof->begin(kProfNttFwd, ntt_bytes(c, ls), st, r);
-    launch_cols<false>(logN1, c->logN, ls, c, st);
-    launch_rows<false>(logN2, c->logN, ls, c, st);
+    if (c->ntt_single_pass && launch_full<false>(c->logN, ls, c, st)) {
+        if (prof) c->prof->end(r, st);
+        BC_HIP(hipGetLastError());
+        return;
+    }
+    const int step = polys_per_chunk(c, ls);
+    for (int p0 = 0; p0 < ls.npoly; p0 += step) {
+        LimbSet sub = ls;
+        sub.base = ls.base + (size_t)p0 * ls.poly_stride;
+        sub.npoly = std::min(step, ls.npoly - p0);
+        launch_cols<false>(logN1, c->logN, sub, c, st);
+        launch_rows<false>(logN2, c->logN, sub, c, st);
+    }
     if (prof) c->prof->end(r, st);
     BC_HIP(hipGetLastError());
 }
@@ -321,8 +494,19 @@ void ntt_inverse(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     ProfRec r{};
     const bool prof = c->prof->on;
     if (prof) c->prof->begin(kProfNttInv, ntt_bytes(c, ls), st, r);
-    launch_rows<true>(logN2, c->logN, ls, c, st);
-    launch_cols<true>(logN1, c->logN, ls, c, st);
+    if (c->ntt_single_pass && launch_full<true>(c->logN, ls, c, st)) {
+        if (prof) c->prof->end(r, st);
+        BC_HIP(hipGetLastError());
+        return;
+    }
+    const int step = polys_per_chunk(c, ls);
+    for (int p0 = 0; p0 < ls.npoly; p0 += step) {
+        LimbSet sub = ls;
+        sub.base = ls.base + (size_t)p0 * ls.poly_stride;
+        sub.npoly = std::min(step, ls.npoly - p0);
+        launch_rows<true>(logN2, c->logN, sub, c, st);
+        launch_cols<true>(logN1, c->logN, sub, c, st);
+    }
     if (prof) c->prof->end(r, st);
     BC_HIP(hipGetLastError());
 }

@@ -85,8 +85,9 @@ void check_hip() { BC_HIP(hipGetLastError()); }
 // Key switch of the NTT-domain polynomials X (stride x_stride per ciphertext,
 // level `level`) with key [dnum][2][nmod][N]:
 // out_c = base_c + ModDown(sum_j ModUp_j(X) * key_j,c), c = 0, 1.
-void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int count, int level, const u64 *base0,
-                const u64 *base1, size_t base_stride, u64 *out, size_t out_stride, hipStream_t st) {
+// Digit decomposition, basis extension and inner product with the key:
+// returns ACC[count][2][l+1+nP][N] = sum_j ModUp_j(X) * key_j,c (NTT domain).
+BufP ks_accumulate(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int count, int level, hipStream_t st) {
     const int N = c->N, nl = level + 1, next = nl + c->nP, dnum = c->dnum;
     const int nact = level / c->alpha + 1;
     BufP MU = make_buf(c, sizeof(u64) * (size_t)count * dnum * next * N);
@@ -105,9 +106,40 @@ void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int co
     run_ntt(c, mu, (size_t)dnum * next * N, count, jm, false, st);
     XC.reset();
     BufP ACC = make_buf(c, sizeof(u64) * (size_t)count * 2 * next * N);
+    launch_ks_inner(c, mu, key, (u64 *)ACC->p, count, level, next, nact, st);
+    return ACC;
+}
+
+// Relinearisation of T3 (level l > 0) followed by one modulus switch, written
+// to out (level l-1): the ModDown correction and the modulus-switch correction
+// are formed together in the coefficient domain and transformed once.
+void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out, hipStream_t st) {
+    const int N = c->N, lv = t3.level, nl = lv + 1, next = nl + c->nP, count = t3.count;
+    const size_t L = (size_t)nl * N;
+    BufP ACC = ks_accumulate(c, k->rlk, t3.data + 2 * L, 3 * L, count, lv, st);
     u64 *acc = (u64 *)ACC->p;
-    launch_ks_inner(c, mu, key, acc, count, level, next, nact, st);
-    MU.reset();
+    Jobs ja;  // special limbs and the top limb of both accumulators
+    for (int cc = 0; cc < 2; cc++) {
+        for (int t = 0; t < c->nP; t++) ja.add(cc * next + nl + t, c->nQ + t);
+        ja.add(cc * next + lv, lv);
+    }
+    run_ntt(c, acc, (size_t)2 * next * N, count, ja, true, st);
+    Jobs jd;  // top limb of d0 and d1 (T3 is workspace: transformed in place)
+    jd.add(lv, lv);
+    jd.add(nl + lv, lv);
+    run_ntt(c, t3.data, 3 * L, count, jd, true, st);
+    BufP E = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
+    launch_relin_ms_fbc(c, acc, t3.data, 3 * L, (u64 *)E->p, count, lv, next, st);
+    run_ntt(c, (u64 *)E->p, (size_t)2 * lv * N, count, all_limbs(2, lv), false, st);
+    launch_relin_ms_combine(c, t3.data, 3 * L, acc, (u64 *)E->p, out.data, count, lv, next, st);
+    check_hip();
+}
+
+void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int count, int level, const u64 *base0,
+                const u64 *base1, size_t base_stride, u64 *out, size_t out_stride, hipStream_t st) {
+    const int N = c->N, nl = level + 1, next = nl + c->nP;
+    BufP ACC = ks_accumulate(c, key, X, x_stride, count, level, st);
+    u64 *acc = (u64 *)ACC->p;
     Jobs js;
     for (int k = 0; k < 2; k++)
         for (int t = 0; t < c->nP; t++) js.add(k * next + nl + t, c->nQ + t);
@@ -213,10 +245,7 @@ void mul_relin(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const Ct
         relin(c, k, t3, out, st);
         return;
     }
-    CtB r2 = alloc_ct(c, a.count, lv, 2);
-    relin(c, k, t3, r2, st);
-    t3 = CtB();
-    mod_switch(c, r2, out, st);
+    relin_mod_switch(c, k, t3, out, st);
 }
 
 CtB mul(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, hipStream_t st) {
