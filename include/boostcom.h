@@ -178,6 +178,23 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
                        const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out,
                        void *stream);
 
+/* Mixed ring sizes.  A group holds several contexts (e.g. N = 2^13, 2^14,
+ * 2^15).  bc_group_compare evaluates every member's comparison batch; members
+ * run on their own streams, forked from and joined back into `stream`.  The
+ * first call for a given set of buffers runs eagerly and records the whole
+ * fork/join launch sequence into one hipGraph; later calls replay it with one
+ * graph launch, so kernels of different ring sizes overlap on the device.
+ * Per member i: keys[i], ndigits[i], planes a_digits[i][0..ndigits[i]) and
+ * b_digits[i][..] as for bc_compare_max_min, outputs lt_out[i] (or NULL),
+ * max_out[i] / min_out[i] (arrays of ndigits[i] batches, or NULL).  Results
+ * are identical to separate bc_compare_max_min calls. */
+typedef struct bc_group bc_group;
+int bc_group_create(int32_t n, bc_ctx *const *ctxs, bc_group **out);
+int bc_group_destroy(bc_group *g);
+int bc_group_compare(bc_group *g, const bc_keys *const *keys, const int32_t *ndigits, const bc_ctb *const *a_digits,
+                     const bc_ctb *const *b_digits, bc_ctb *const *lt_out, bc_ctb *const *max_out,
+                     bc_ctb *const *min_out, void *stream);
+
 /* Execution mode of the comparison calls: BC_EXEC_BATCHED launches every step
  * of the circuit once for the whole batch; BC_EXEC_GRAPH additionally records
  * the launch sequence of a (shape, buffers) combination into a hipGraph on its

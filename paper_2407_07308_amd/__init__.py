@@ -78,6 +78,10 @@ _SIGS = {
     "bc_compare_lt": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_compare_max_min": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_set_exec_mode": (_I, [_V, _I]),
+    "bc_group_create": (_I, [_I, _P(_V), _P(_V)]),
+    "bc_group_destroy": (_I, [_V]),
+    "bc_group_compare": (_I, [_V, _P(_V), _P(_I), _P(_P(bc_ctb)), _P(_P(bc_ctb)), _P(_P(bc_ctb)),
+                              _P(_P(bc_ctb)), _P(_P(bc_ctb)), _V]),
     "bc_set_tuning": (_I, [_V, _I, ctypes.c_int64]),
     "bc_autotune": (_I, [_V, _V]),
     "bc_get_tuning": (_I, [_V, _I, _P(ctypes.c_int64)]),
@@ -366,3 +370,52 @@ class Context:
 
     def compare_lt(self, keys: Keys, a_digits, b_digits) -> Batch:
         return self.compare_max_min(keys, a_digits, b_digits, True, False, False)[0]
+
+
+class Group:
+    """Several contexts (ring sizes) whose comparison batches run as one
+    recorded fork/join graph (``bc_group_*``)."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        self.L = lib()
+        arr = (ctypes.c_void_p * len(self.contexts))(*[c.handle.value for c in self.contexts])
+        h = ctypes.c_void_p()
+        _check(self.L.bc_group_create(len(self.contexts), arr, ctypes.byref(h)))
+        self.handle = h
+        self._keep = []
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.bc_group_destroy(self.handle)
+            self.handle = None
+
+    def compare_max_min(self, requests, outs=None, want_lt=True, want_max=True, want_min=True):
+        """requests: list over members of (keys, a_digits, b_digits).  Returns
+        per member (lt, [max planes], [min planes]); ``outs`` reuses earlier outputs."""
+        n = len(self.contexts)
+        assert len(requests) == n
+        if outs is None:
+            outs = []
+            for c, (k, a, b) in zip(self.contexts, requests):
+                ltl, mml = c.compare_levels(a[0].level, len(a))
+                G = a[0].count
+                outs.append((c.new_batch(G, ltl) if want_lt else None,
+                             [c.new_batch(G, mml) for _ in a] if want_max else None,
+                             [c.new_batch(G, mml) for _ in a] if want_min else None))
+        keys = (ctypes.c_void_p * n)(*[k.handle.value for (k, _, _) in requests])
+        nd = (ctypes.c_int32 * n)(*[len(a) for (_, a, _) in requests])
+        PA = ctypes.POINTER(bc_ctb)
+        A = [_ctb_array(a) for (_, a, _) in requests]
+        B = [_ctb_array(b) for (_, _, b) in requests]
+        LT = [ctypes.pointer(o[0].ctb()) if o[0] is not None else None for o in outs]
+        MX = [_ctb_array(o[1]) if o[1] is not None else None for o in outs]
+        MN = [_ctb_array(o[2]) if o[2] is not None else None for o in outs]
+        self._keep = [A, B, LT, MX, MN]
+        pa = (PA * n)(*[ctypes.cast(x, PA) for x in A])
+        pb = (PA * n)(*[ctypes.cast(x, PA) for x in B])
+        plt = (PA * n)(*[ctypes.cast(x, PA) if x is not None else PA() for x in LT]) if want_lt else None
+        pmx = (PA * n)(*[ctypes.cast(x, PA) if x is not None else PA() for x in MX]) if want_max else None
+        pmn = (PA * n)(*[ctypes.cast(x, PA) if x is not None else PA() for x in MN]) if want_min else None
+        _check(self.L.bc_group_compare(self.handle, keys, nd, pa, pb, plt, pmx, pmn, _stream()))
+        return outs

@@ -81,9 +81,147 @@ std::string graph_key(int ndig, const bc_ctb *a, const bc_ctb *b, const bc_ctb *
     return os.str();
 }
 
+// Checks one comparison request and returns its planes.
+void check_compare(bc_ctx *ctx, const bc_keys *keys, int ndigits, const bc_ctb *a_digits, const bc_ctb *b_digits,
+                   const bc_ctb *lt_out, const bc_ctb *max_out, const bc_ctb *min_out, std::vector<CtB> &A,
+                   std::vector<CtB> &B) {
+    check_ctx(ctx);
+    check_keys(ctx, keys);
+    BC_REQUIRE(a_digits && b_digits && ndigits >= 1 && ndigits <= 16, BC_ERR_ARG, "bad digit planes");
+    BC_REQUIRE(lt_out || max_out || min_out, BC_ERR_ARG, "no output requested");
+    A.clear();
+    B.clear();
+    for (int d = 0; d < ndigits; d++) {
+        A.push_back(from_abi(ctx, &a_digits[d]));
+        B.push_back(from_abi(ctx, &b_digits[d]));
+    }
+    int ltl = 0, mml = 0;
+    compare_levels(ctx, A[0].level, ndigits, &ltl, &mml);
+    auto want = [&](const bc_ctb *x, int lv) {
+        CtB o = from_abi(ctx, x);
+        BC_REQUIRE(o.count == A[0].count && o.level == lv && o.ncomp == 2, BC_ERR_ARG,
+                   "output batch: wrong count, level or components");
+    };
+    if (lt_out) want(lt_out, ltl);
+    for (int d = 0; d < ndigits; d++) {
+        if (max_out) want(&max_out[d], mml);
+        if (min_out) want(&min_out[d], mml);
+    }
+}
+
 }  // namespace
 
+struct bc_group {
+    std::vector<bc_ctx *> ctxs;
+    std::vector<hipStream_t> streams;  // one per member (default priority)
+    std::vector<hipEvent_t> done;      // one per member
+    hipEvent_t fork = nullptr;
+    hipStream_t cap = nullptr;          // recording stream
+    bc::GraphCache graphs;
+    std::mutex mu;
+    ~bc_group() {
+        for (auto s : streams) (void)hipStreamDestroy(s);
+        for (auto e : done) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
 extern "C" {
+
+int bc_group_create(int32_t n, bc_ctx *const *ctxs, bc_group **out) {
+    return guard([&] {
+        BC_REQUIRE(n >= 1 && n <= 16 && ctxs && out, BC_ERR_ARG, "bad group");
+        std::unique_ptr<bc_group> g(new bc_group());
+        for (int i = 0; i < n; i++) {
+            check_ctx(ctxs[i]);
+            for (int j = 0; j < i; j++) BC_REQUIRE(ctxs[j] != ctxs[i], BC_ERR_ARG, "a context appears twice");
+            g->ctxs.push_back(ctxs[i]);
+            hipStream_t s;
+            BC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            g->streams.push_back(s);
+            hipEvent_t e;
+            BC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            g->done.push_back(e);
+        }
+        BC_HIP(hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
+        BC_HIP(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+        *out = g.release();
+    });
+}
+
+int bc_group_destroy(bc_group *g) {
+    return guard([&] {
+        if (g) (void)hipDeviceSynchronize();
+        delete g;
+    });
+}
+
+int bc_group_compare(bc_group *g, const bc_keys *const *keys, const int32_t *ndigits, const bc_ctb *const *a_digits,
+                     const bc_ctb *const *b_digits, bc_ctb *const *lt_out, bc_ctb *const *max_out,
+                     bc_ctb *const *min_out, void *stream) {
+    return guard([&] {
+        BC_REQUIRE(g && keys && ndigits && a_digits && b_digits, BC_ERR_ARG, "null argument");
+        const int n = (int)g->ctxs.size();
+        std::vector<std::vector<CtB>> A(n), B(n);
+        std::ostringstream key;
+        for (int i = 0; i < n; i++) {
+            const bc_ctb *lt = lt_out ? lt_out[i] : nullptr, *mx = max_out ? max_out[i] : nullptr,
+                         *mn = min_out ? min_out[i] : nullptr;
+            check_compare(g->ctxs[i], keys[i], ndigits[i], a_digits[i], b_digits[i], lt, mx, mn, A[i], B[i]);
+            key << graph_key(ndigits[i], a_digits[i], b_digits[i], lt, mx, mn, stream, keys[i]) << '#';
+        }
+        hipStream_t st = (hipStream_t)stream;
+        std::lock_guard<std::mutex> lk(g->mu);
+        auto it = g->graphs.entries.find(key.str());
+        if (it != g->graphs.entries.end()) {
+            BC_HIP(hipGraphLaunch(it->second.exec, st));
+            return;
+        }
+        // fork/join over the member streams; `origin` is the stream the
+        // branches fork from and join back into
+        auto run_all = [&](hipStream_t origin) {
+            BC_HIP(hipEventRecord(g->fork, origin));
+            for (int i = 0; i < n; i++) {
+                BC_HIP(hipStreamWaitEvent(g->streams[i], g->fork, 0));
+                StreamScope sc(g->streams[i]);
+                run_compare(g->ctxs[i], keys[i], ndigits[i], A[i].data(), B[i].data(), lt_out ? lt_out[i] : nullptr,
+                            max_out ? max_out[i] : nullptr, min_out ? min_out[i] : nullptr, g->streams[i]);
+                BC_HIP(hipEventRecord(g->done[i], g->streams[i]));
+                BC_HIP(hipStreamWaitEvent(origin, g->done[i], 0));
+            }
+        };
+        run_all(st);  // eager: results of this call; warms every pool
+        BC_HIP(hipStreamSynchronize(st));
+        for (auto *c : g->ctxs) {
+            std::lock_guard<std::mutex> pg(c->pool.mu);
+            c->pool.recording = true;
+            c->pool.recorded.clear();
+        }
+        GraphEntry e;
+        BC_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeRelaxed));
+        try {
+            run_all(g->cap);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(g->cap, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            for (auto *c : g->ctxs) {
+                std::lock_guard<std::mutex> pg(c->pool.mu);
+                c->pool.recording = false;
+                c->pool.recorded.clear();
+            }
+            throw;
+        }
+        BC_HIP(hipStreamEndCapture(g->cap, &e.graph));
+        BC_HIP(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+        for (auto *c : g->ctxs) {
+            auto b = c->pool.detach_recorded();
+            e.blocks.insert(e.blocks.end(), b.begin(), b.end());
+        }
+        g->graphs.entries.emplace(key.str(), std::move(e));
+    });
+}
 
 const char *bc_strerror(int code) {
     switch (code) {
@@ -317,27 +455,8 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode) {
 int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits,
                        const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out, void *stream) {
     return guard([&] {
-        check_ctx(ctx);
-        check_keys(ctx, keys);
-        BC_REQUIRE(a_digits && b_digits && ndigits >= 1 && ndigits <= 16, BC_ERR_ARG, "bad digit planes");
-        BC_REQUIRE(lt_out || max_out || min_out, BC_ERR_ARG, "no output requested");
         std::vector<CtB> A, B;
-        for (int d = 0; d < ndigits; d++) {
-            A.push_back(from_abi(ctx, &a_digits[d]));
-            B.push_back(from_abi(ctx, &b_digits[d]));
-        }
-        int ltl = 0, mml = 0;
-        compare_levels(ctx, A[0].level, ndigits, &ltl, &mml);
-        auto want = [&](const bc_ctb *x, int lv) {
-            CtB o = from_abi(ctx, x);
-            BC_REQUIRE(o.count == A[0].count && o.level == lv && o.ncomp == 2, BC_ERR_ARG,
-                       "output batch: wrong count, level or components");
-        };
-        if (lt_out) want(lt_out, ltl);
-        for (int d = 0; d < ndigits; d++) {
-            if (max_out) want(&max_out[d], mml);
-            if (min_out) want(&min_out[d], mml);
-        }
+        check_compare(ctx, keys, ndigits, a_digits, b_digits, lt_out, max_out, min_out, A, B);
         hipStream_t st = (hipStream_t)stream;
         StreamScope sc(stream);
         if (ctx->exec_mode != BC_EXEC_GRAPH) {

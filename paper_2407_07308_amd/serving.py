@@ -1,0 +1,161 @@
+"""Continuous-batching server for encrypted comparison requests.
+
+A request carries two encrypted operands as digit planes (one batch of
+`groups` ciphertexts per plane, 128 integers per ciphertext group) and asks
+for LT, MAX or ARGMAX (the LT bit: 1 where the second operand is larger).  The
+server keeps keys resident per ring size, admits arrived requests while the
+device-memory estimate of the work in flight stays under a budget, coalesces
+admitted requests of one ring size into a single batch (their planes are
+concatenated on the device), launches the batched comparison on one of
+several streams so consecutive batches overlap on the GPU, and completes
+requests by polling the batch's event.  Latency = completion time - arrival
+time.  Everything the batch computes runs in the library's kernels; this loop
+only schedules.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Batch, Context, Keys
+
+
+@dataclass
+class Request:
+    rid: int
+    kind: str  # "lt", "max" or "argmax"
+    N: int
+    groups: int
+    arrival: float  # seconds from the start of the run
+    a: list = field(default_factory=list)  # digit planes (Batch, count = groups), most significant first
+    b: list = field(default_factory=list)
+    result: object = None  # (lt Batch slice, max planes or None)
+    done_at: float = None
+
+
+class _InFlight:
+    def __init__(self, reqs, event, outs, offsets, bytes_):
+        self.reqs, self.event, self.outs, self.offsets, self.bytes = reqs, event, outs, offsets, bytes_
+
+
+def _concat(planes_per_req, ctx: Context):
+    """Concatenate the requests' plane d into one batch per plane."""
+    import torch
+
+    nd = len(planes_per_req[0])
+    out = []
+    for d in range(nd):
+        ts = [pl[d].tensor for pl in planes_per_req]
+        lv = planes_per_req[0][d].level
+        cnt = sum(pl[d].count for pl in planes_per_req)
+        out.append(Batch(torch.cat(ts), cnt, lv, 2))
+    return out
+
+
+def _slice(b: Batch, ctx: Context, first: int, n: int) -> Batch:
+    w = ctx.ct_words(b.level, b.ncomp)
+    return Batch(b.tensor[first * w:(first + n) * w], n, b.level, b.ncomp)
+
+
+class Server:
+    def __init__(self, members: dict, max_batch_groups: int = 64, mem_budget_bytes: int = 64 << 30,
+                 streams: int = 2, bytes_per_group: dict | None = None):
+        """members: {N: (Context, Keys)}.  bytes_per_group: device-memory
+        estimate of one group's circuit (default: 40 top-level ciphertexts
+        per plane-pair)."""
+        import torch
+
+        self.members = members
+        self.max_batch_groups = max_batch_groups
+        self.budget = mem_budget_bytes
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.bpg = bytes_per_group or {N: 8 * 40 * 3 * ctx.ct_words(ctx.nQ - 1) for N, (ctx, _) in members.items()}
+        self.stats = {"batches": 0, "max_inflight_bytes": 0, "groups": 0}
+
+    def _launch(self, reqs, stream_idx):
+        import torch
+
+        N = reqs[0].N
+        ctx, keys = self.members[N]
+        s = self.streams[stream_idx]
+        with torch.cuda.stream(s):
+            A = _concat([r.a for r in reqs], ctx)
+            B = _concat([r.b for r in reqs], ctx)
+            want_max = any(r.kind == "max" for r in reqs)
+            outs = ctx.compare_max_min(keys, A, B, True, want_max, False)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        offsets, o = [], 0
+        for r in reqs:
+            offsets.append(o)
+            o += r.groups
+        self.stats["batches"] += 1
+        self.stats["groups"] += o
+        # keep the concatenated inputs alive until the batch completes
+        return _InFlight(reqs, ev, (outs, A, B), offsets, sum(self.bpg[N] * r.groups for r in reqs))
+
+    def run(self, requests: list, clock=time.perf_counter):
+        """Serves `requests` (sorted by arrival) against their arrival times;
+        returns them completed, with latencies filled in."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        ready = collections.deque()
+        inflight: list[_InFlight] = []
+        busy = [False] * len(self.streams)
+        t0 = clock()
+        used = 0
+        while pending or ready or inflight:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                ready.append(pending.popleft())
+            for f in list(inflight):
+                if f.event.query():
+                    t = clock() - t0
+                    (lt, mx, _), _, _ = f.outs
+                    for r, off in zip(f.reqs, f.offsets):
+                        ctx = self.members[r.N][0]
+                        r.result = (_slice(lt, ctx, off, r.groups),
+                                    [_slice(m, ctx, off, r.groups) for m in mx] if (mx and r.kind == "max") else None)
+                        r.done_at = t
+                    used -= f.bytes
+                    busy[f.stream] = False
+                    inflight.remove(f)
+            launched = False
+            if ready and not all(busy):
+                N = ready[0].N  # ring size of the oldest waiting request
+                batch, nbytes, g = [], 0, 0
+                for r in list(ready):
+                    if r.N != N:
+                        continue
+                    need = self.bpg[N] * r.groups
+                    if batch and (g + r.groups > self.max_batch_groups or used + nbytes + need > self.budget):
+                        break
+                    if not batch and used + need > self.budget and inflight:
+                        break  # wait for memory to free up
+                    batch.append(r)
+                    nbytes += need
+                    g += r.groups
+                if batch:
+                    for r in batch:
+                        ready.remove(r)
+                    si = busy.index(False)
+                    f = self._launch(batch, si)
+                    f.stream = si
+                    busy[si] = True
+                    used += nbytes
+                    self.stats["max_inflight_bytes"] = max(self.stats["max_inflight_bytes"], used)
+                    inflight.append(f)
+                    launched = True
+            if not launched:
+                time.sleep(0.0002)
+        return requests
+
+
+def latency_summary(reqs):
+    lat = np.array([r.done_at - r.arrival for r in reqs])
+    span = max(r.done_at for r in reqs) - min(r.arrival for r in reqs)
+    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "throughput_req_s": len(reqs) / span if span > 0 else None}

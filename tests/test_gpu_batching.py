@@ -1,0 +1,106 @@
+"""Mixed ring sizes in one recorded graph, and the continuous-batching server.
+
+Both are scheduling layers: their results must be byte-identical to the plain
+per-context comparison of the same inputs, which is itself pinned to the
+oracle by the circuit parity tests; decryptions are checked against the
+plaintext semantics.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import Params
+
+pytestmark = pytest.mark.gpu
+
+BASE, ND = 129, 3
+
+
+def member(prm, seed):
+    import paper_2407_07308_amd as bc
+
+    dev = bc.Context.from_params(prm)
+    rnd = synth.keygen_randomness(seed, prm.N, prm.nQ, prm.nP, prm.dnum, 0)
+    return dev, dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
+
+
+def planes(dev, dk, vals, seed):
+    out = []
+    for d, pl in enumerate(oracle.to_digits(vals, BASE, ND)):
+        r = synth.encrypt_randomness(seed + d, pl.shape[0], dev.N)
+        out.append(dev.encrypt(dk, pl, r["u"], r["e"]))
+    return out
+
+
+def same(dev, x, y):
+    return np.array_equal(dev.export(x), dev.export(y))
+
+
+def test_group_equals_separate_calls_and_replays():
+    import paper_2407_07308_amd as bc
+
+    members = [member(Params(10, 257, 12, 50, 3, 60, 3), 1), member(Params(11, 257, 12, 50, 3, 60, 3), 2)]
+    reqs, refs, vals = [], [], []
+    for i, (dev, dk) in enumerate(members):
+        G = 2 + i
+        xs = synth.integers(10 + i, (G, dev.M), 0, 65536)
+        ys = synth.integers(10 + i, (G, dev.M), 0, 65536, index=1)
+        a, b = planes(dev, dk, xs, 20 + 10 * i), planes(dev, dk, ys, 40 + 10 * i)
+        reqs.append((dk, a, b))
+        refs.append(dev.compare_max_min(dk, a, b))
+        vals.append((xs, ys))
+    grp = bc.Group([m[0] for m in members])
+    outs = grp.compare_max_min(reqs)  # eager + record
+    for rep in range(3):
+        for (dev, dk), o, ref, (xs, ys) in zip(members, outs, refs, vals):
+            assert same(dev, o[0], ref[0])
+            for x, y in zip(o[1] + o[2], ref[1] + ref[2]):
+                assert same(dev, x, y)
+            assert np.array_equal(dev.decrypt(dk, o[0]), (xs < ys).astype(np.uint32))
+        for o in outs:
+            for x in [o[0]] + o[1] + o[2]:
+                x.tensor.zero_()
+        grp.compare_max_min(reqs, outs=outs)  # replay
+
+
+def test_server_results_equal_alone_and_in_the_mix():
+    from paper_2407_07308_amd import serving
+
+    members = {1 << 10: member(Params(10, 257, 12, 50, 3, 60, 3), 3),
+               1 << 11: member(Params(11, 257, 12, 50, 3, 60, 3), 4)}
+    g = synth.generator(77, "schedule")
+    reqs = []
+    t = 0.0
+    for rid in range(10):
+        N = [1 << 10, 1 << 11][int(g.integers(0, 2))]
+        dev, dk = members[N]
+        groups = int(g.integers(1, 4))
+        kind = ["lt", "max", "argmax"][int(g.integers(0, 3))]
+        xs = synth.integers(100 + rid, (groups, dev.M), 0, 65536)
+        ys = synth.integers(100 + rid, (groups, dev.M), 0, 65536, index=1)
+        xs[0, :3] = ys[0, :3]
+        r = serving.Request(rid, kind, N, groups, t, planes(dev, dk, xs, 300 + 10 * rid),
+                            planes(dev, dk, ys, 600 + 10 * rid))
+        r.xs, r.ys = xs, ys
+        reqs.append(r)
+        t += float(g.exponential(0.004))
+    # a budget of about two groups forces requests to wait for memory
+    bpg = {N: 2 * 40 * 3 * 8 * m[0].ct_words(m[0].nQ - 1) for N, m in members.items()}
+    srv = serving.Server(members, max_batch_groups=4, mem_budget_bytes=2 * max(bpg.values()), streams=2,
+                         bytes_per_group=bpg)
+    srv.run(reqs)
+    assert all(r.done_at is not None for r in reqs)
+    assert srv.stats["batches"] < len(reqs)  # some requests shared a batch
+    for r in reqs:
+        dev, dk = members[r.N]
+        lt, mx, _ = dev.compare_max_min(dk, r.a, r.b, True, r.kind == "max", False)
+        assert same(dev, r.result[0], lt)
+        assert np.array_equal(dev.decrypt(dk, r.result[0]), (r.xs < r.ys).astype(np.uint32))
+        if r.kind == "max":
+            for x, y in zip(r.result[1], mx):
+                assert same(dev, x, y)
+            val = sum(dev.decrypt(dk, p).astype(np.int64) * BASE ** (ND - 1 - i) for i, p in enumerate(r.result[1]))
+            assert np.array_equal(val, np.maximum(r.xs, r.ys))
+    summ = serving.latency_summary(reqs)
+    assert summ["p99_ms"] >= summ["p50_ms"] > 0
