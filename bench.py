@@ -39,6 +39,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-op", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--workload", choices=["uint16", "mixed", "serving"], default="uint16",
+                    help="uint16: LT+max+min at N=2^15 (default); mixed: 256 single-digit pairs over "
+                         "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream")
+    ap.add_argument("--window", type=float, default=0.5, help="serving: seconds of arrivals")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: mean requests per second")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="write the forward-NTT traffic summary from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--ntt-chunk-mb", type=float, default=None,
                     help="split batched transforms into launch pairs over at most this many MB")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -60,6 +67,12 @@ def main():
               f"independent, so a multi-GPU run would give each GPU its own share of groups and keys; "
               f"that is not built here. Nothing was run.", file=sys.stderr)
         sys.exit(2)
+    if a.pmc_summary:
+        return pmc_summary(*a.pmc_summary)
+    if a.workload == "mixed":
+        return mixed(a)
+    if a.workload == "serving":
+        return serve(a)
     import numpy as np
     import torch
 
@@ -126,6 +139,7 @@ def main():
     comparisons = G * M
     value = comparisons / (ms_step / 1e3)
     achieved = fwd_bytes / (fwd_ms / 1e3) / 1e9 if fwd_ms > 0 else 0.0
+    traffic = measured_traffic()
 
     # ------------------------------------------------- per-op launch path
     # same circuit, same kernels, one ciphertext per launch
@@ -202,7 +216,8 @@ def main():
         "slot_comparisons_per_s": value * NDIG,
         "wall_ms_per_step": t_wall * 1e3 / a.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, copy-calibrated",
                      "kernel": ("forward NTT, " + ("single pass" if tuned["single_pass"] else "column pass + row pass")
                                 + ", 16 N bytes per limb"),
                      "ntt_schedule": tuned,
@@ -214,6 +229,188 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ntt_forward_traffic_n15.txt")
+NTT_SOURCES = [os.path.join(ROOT, "paper_2407_07308_amd", "csrc", f) for f in ("ntt.hip", "bc_internal.h")]
+
+
+def ntt_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in NTT_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def is_forward_ntt(name: str) -> str | None:
+    """'a' for the first pass (or the single pass) of a forward transform, 'b' for the second."""
+    import re
+
+    m = re.search(r"ntt_(cols|rows|full)<\d+, false>", name)
+    if not m:
+        return None
+    return "b" if m.group(1) == "rows" else "a"
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, command: str):
+    """Per-launch HBM bytes of the forward NTT from two rocprofv3 --pmc runs.
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they read
+    for the 1 GiB device copy the profiled run performs first."""
+    import csv
+
+    out = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        rows = [r for r in csv.DictReader(open(path)) if r.get("Counter_Name", counter) == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        # the calibration copy is the first copy dispatched after the 1 GiB fill
+        fill = max((i for i, r in enumerate(rows) if "Fill" in r["Kernel_Name"]),
+                   key=lambda i: int(rows[i]["Grid_Size"]))
+        ref = next(float(r["Counter_Value"]) for r in rows[fill + 1:] if "copyBuffer" in r["Kernel_Name"])
+        scale = (1 << 20) / ref  # KiB the copy should have counted / KiB counted
+        # only the comparison steps (they start with the plane subtraction),
+        # as in the timed region; set-up transforms (tuning, encryption) excluded
+        first = next(i for i, r in enumerate(rows) if "k_addsub" in r["Kernel_Name"])
+        tot, launches = 0.0, 0
+        for r in rows[first:]:
+            kind = is_forward_ntt(r["Kernel_Name"])
+            if kind:
+                tot += float(r["Counter_Value"]) * 1024 * scale
+                launches += kind == "a"
+        out[counter] = {"scale": scale, "bytes": tot, "launches": launches}
+    per_launch = (out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"]) / max(1, out["FETCH_SIZE"]["launches"])
+    rec = {"kernel": "forward NTT", "source_hash": ntt_source_hash(), "traffic_bytes_per_launch": per_launch,
+           "fetch_scale": out["FETCH_SIZE"]["scale"], "write_scale": out["WRITE_SIZE"]["scale"],
+           "launches": out["FETCH_SIZE"]["launches"], "command": command}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def measured_traffic():
+    """Forward-NTT bytes per launch from the committed counter summary, if the
+    transform source is unchanged since the counters were taken."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("source_hash") == ntt_source_hash() else None
+
+
+CHAINS = {13: dict(logN=13, p=257, nQ=8, bitsQ=50, nP=3, bitsP=60, dnum=2),
+          14: dict(logN=14, p=257, nQ=8, bitsQ=50, nP=3, bitsP=60, dnum=2),
+          15: dict(logN=15, p=257, nQ=14, bitsQ=50, nP=4, bitsP=60, dnum=3)}
+
+
+def mixed(a):
+    """256 single-digit LT pairs, N i.i.d. uniform on {2^13, 2^14, 2^15}, uniform
+    slot values in [0, 257): one recorded fork/join graph per step."""
+    import numpy as np
+    import torch
+
+    import paper_2407_07308_amd as bc
+    import synth
+
+    torch.cuda.set_device(0)
+    seed = 104
+    pick = synth.generator(seed, "schedule").integers(13, 16, size=256)
+    members, reqs, truth = [], [], []
+    for j, L in enumerate((13, 14, 15)):
+        G = int((pick == L).sum())
+        dev = bc.Context(**CHAINS[L])
+        rnd = synth.keygen_randomness(seed + L, dev.N, dev.nQ, dev.nP, dev.dnum, 0)
+        dk = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
+        dev.autotune()
+        x = synth.slot_values(seed, G, dev.M, 0, 257, index=L)
+        y = synth.slot_values(seed, G, dev.M, 0, 257, index=100 + L)
+        rx, ry = synth.encrypt_randomness(seed + 10 * L, G, dev.N), synth.encrypt_randomness(seed + 10 * L + 1, G, dev.N)
+        A, B = [dev.encrypt(dk, x, rx["u"], rx["e"])], [dev.encrypt(dk, y, ry["u"], ry["e"])]
+        members.append(dev)
+        reqs.append((dk, A, B))
+        truth.append(((x.astype(np.int64) - y) % 257 >= 129).astype(np.uint32))
+    grp = bc.Group(members)
+    outs = grp.compare_max_min(reqs, want_max=False, want_min=False)
+    for _ in range(max(0, a.warmup - 1)):
+        grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    for dev, (dk, _, _), o, t in zip(members, reqs, outs, truth):
+        if not np.array_equal(dev.decrypt(dk, o[0]), t):
+            print("bench: mixed decryptions are wrong", file=sys.stderr)
+            sys.exit(3)
+    comps = 256 * members[0].M
+    print(json.dumps({"metric": "encrypted LT slot comparisons/s, mixed N in one graph", "value": comps / (ms / 1e3),
+                      "unit": "comparisons/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                      "data": "synthetic",
+                      "config": {"workload": "256 single-digit LT pairs, N uniform on {2^13,2^14,2^15}, p=257",
+                                 "pairs_per_N": {str(1 << L): int((pick == L).sum()) for L in (13, 14, 15)}}}))
+
+
+def serve(a):
+    """Poisson arrivals of LT / max / argmax requests over uint16 vectors of
+    length n (log-uniform on 64..4096), N uniform on {2^14, 2^15}."""
+    import numpy as np
+    import torch
+
+    import paper_2407_07308_amd as bc
+    import synth
+    from paper_2407_07308_amd import serving
+
+    torch.cuda.set_device(0)
+    seed = 105
+    members = {}
+    for L in (14, 15):
+        prm = dict(CHAINS[15])
+        prm["logN"] = L
+        dev = bc.Context(**prm)
+        rnd = synth.keygen_randomness(seed + L, dev.N, dev.nQ, dev.nP, dev.dnum, 0)
+        members[dev.N] = (dev, dev.keygen(rnd["s"], rnd["a"], rnd["e"], ()))
+        dev.autotune()
+    g = synth.generator(seed, "schedule")
+    reqs, t = [], 0.0
+    while True:
+        t += float(g.exponential(1.0 / a.rate))
+        if t > a.window:
+            break
+        N = 1 << int(g.integers(14, 16))
+        n = 1 << int(g.integers(6, 13))
+        kind = ["lt", "max", "argmax"][int(g.integers(0, 3))]
+        dev, dk = members[N]
+        groups = -(-n // dev.M)
+        rid = len(reqs)
+        xs = synth.integers(seed + rid, (groups, dev.M), 0, 65536)
+        ys = synth.integers(seed + rid, (groups, dev.M), 0, 65536, index=1)
+        enc = lambda vals, s: [dev.encrypt(dk, pl, *synth.encrypt_randomness(s + d, groups, dev.N).values())
+                               for d, pl in enumerate(digits(vals, BASE, NDIG))]
+        r = serving.Request(rid, kind, N, groups, t, enc(xs, 1000 + 7 * rid), enc(ys, 5000 + 7 * rid))
+        r.xs, r.ys = xs, ys
+        reqs.append(r)
+    torch.cuda.synchronize()
+    srv = serving.Server(members, max_batch_groups=32, mem_budget_bytes=64 << 30, streams=2)
+    srv.run(reqs)
+    for r in reqs[:: max(1, len(reqs) // 8)]:
+        dev, dk = members[r.N]
+        if not np.array_equal(dev.decrypt(dk, r.result[0]), (r.xs < r.ys).astype(np.uint32)):
+            print("bench: served decryptions are wrong", file=sys.stderr)
+            sys.exit(3)
+    s = serving.latency_summary(reqs)
+    groups = sum(r.groups for r in reqs)
+    span = max(r.done_at for r in reqs)
+    print(json.dumps({"metric": "serving latency p50/p99 and throughput", "value": s["throughput_req_s"],
+                      "unit": "requests/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64",
+                      "data": "synthetic", "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "mean_ms": s["mean_ms"],
+                      "uint16_comparisons_per_s": groups * 128 / span, "batches": srv.stats["batches"],
+                      "config": {"workload": f"Poisson {a.rate:.0f} req/s for {a.window} s, LT/max/argmax, "
+                                             f"n log-uniform 64..4096, N in {{2^14,2^15}}, p=257",
+                                 "requests": len(reqs), "groups": groups}}))
 
 
 if __name__ == "__main__":

@@ -135,16 +135,13 @@ void *Pool::alloc(size_t bytes) {
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        // give back cached blocks of this stream and retry once
-        for (auto i = free_.begin(); i != free_.end();) {
-            if (i->first.first == st) {
-                (void)hipFree(i->second);
-                held -= i->first.second;
-                i = free_.erase(i);
-            } else {
-                ++i;
-            }
+        // give back every cached block and retry once (hipFree waits for the
+        // device, so blocks whose last users are still queued are safe to free)
+        for (auto &kv : free_) {
+            (void)hipFree(kv.second);
+            held -= kv.first.second;
         }
+        free_.clear();
         if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             throw Error(BC_ERR_OOM, "device workspace allocation failed");
