@@ -3,7 +3,7 @@
 
 Workload (one step): 64 groups of 128 uint16 pairs, each integer split into
 three base-129 digit planes (one BGV ciphertext per plane and group, p = 257,
-N = 2^15, 14 x 50-bit primes, 4 x 60-bit special primes, dnum = 3); the step
+N = 2^15, 14 x 50-bit primes, 5 x 50-bit special primes, dnum = 3); the step
 evaluates the lexicographic less-than over the planes and the max and min
 planes -- 98 ciphertext multiplications per group, all groups batched.
 Inputs are encrypted and resident in HBM before the timed region.
@@ -80,7 +80,7 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
-    prm = dict(logN=15, p=257, nQ=14, bitsQ=50, nP=4, bitsP=60, dnum=3)
+    prm = dict(logN=15, p=257, nQ=14, bitsQ=50, nP=5, bitsP=50, dnum=3)
     G = a.groups
     dev = bc.Context(**prm)
     N, M = dev.N, dev.M
@@ -211,7 +211,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": f"uint16 lexicographic LT+max+min, {G} groups x {M} slots x {NDIG} base-129 planes, "
-                               f"BGV N=2^15 p=257 Q=14x50b P=4x60b dnum=3, batched",
+                               f"BGV N=2^{prm['logN']} p={prm['p']} Q={prm['nQ']}x{prm['bitsQ']}b "
+                               f"P={prm['nP']}x{prm['bitsP']}b dnum={prm['dnum']}, batched",
                    "groups": G, "slots": M, "planes": NDIG, "N": N},
         "slot_comparisons_per_s": value * NDIG,
         "wall_ms_per_step": t_wall * 1e3 / a.steps,
@@ -298,9 +299,9 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"] if rec.get("source_hash") == ntt_source_hash() else None
 
 
-CHAINS = {13: dict(logN=13, p=257, nQ=8, bitsQ=50, nP=3, bitsP=60, dnum=2),
-          14: dict(logN=14, p=257, nQ=8, bitsQ=50, nP=3, bitsP=60, dnum=2),
-          15: dict(logN=15, p=257, nQ=14, bitsQ=50, nP=4, bitsP=60, dnum=3)}
+CHAINS = {13: dict(logN=13, p=257, nQ=8, bitsQ=50, nP=4, bitsP=50, dnum=2),
+          14: dict(logN=14, p=257, nQ=8, bitsQ=50, nP=4, bitsP=50, dnum=2),
+          15: dict(logN=15, p=257, nQ=14, bitsQ=50, nP=5, bitsP=50, dnum=3)}
 
 
 def mixed(a):

@@ -210,12 +210,20 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   output is still cached when the second pass reads it.
  *   BC_TUNE_NTT_SINGLE_PASS: 1 (default) transforms a whole limb in one
  *   workgroup for N = 2^12 .. 2^15 (each word read and written once); 0 uses
- *   the two-pass column/row transform for every N. */
-enum { BC_TUNE_NTT_CHUNK_BYTES = 0, BC_TUNE_NTT_SINGLE_PASS = 1 };
+ *   the two-pass column/row transform for every N.
+ *   BC_TUNE_FP64: 1 (default) runs the modular arithmetic of the transforms
+ *   and of the base conversions (modulus raising, the fused relinearisation
+ *   and modulus switch, multi-prime switching, the polynomial's linear
+ *   combinations) in exact fp64 (integers below 2^53 held in doubles) when
+ *   every prime of the context is below 2^50; 0 uses 64-bit integer
+ *   arithmetic.  Reading it returns 0 for a context with a prime of 2^50 or
+ *   more. */
+enum { BC_TUNE_NTT_CHUNK_BYTES = 0, BC_TUNE_NTT_SINGLE_PASS = 1, BC_TUNE_FP64 = 2 };
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);
 /* Times each transform schedule (two-pass, two-pass in cache-sized chunks,
- * single-pass where N allows) on a synthetic batch of this context's shape
+ * single-pass where N allows; each with fp64 and integer arithmetic where the
+ * primes allow fp64) on a synthetic batch of this context's shape
  * (about 384 MB of limbs) and keeps the fastest.  Synchronises the stream;
  * takes a few tens of milliseconds. */
 int bc_autotune(bc_ctx *ctx, void *stream);

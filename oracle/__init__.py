@@ -211,14 +211,15 @@ class Params:
 
 
 # Parameter sets of the workloads.  Readings: four 36-bit primes for the N=2^12
-# case because a depth-four circuit does not fit in three; three and four
-# special 60-bit primes for the two p=257 chains, because one special prime
-# leaves key-switching noise far above the modulus.
+# case because a depth-four circuit does not fit in three; for the p=257
+# chains as many 50-bit special primes as one digit has primes (P no smaller
+# than a digit's modulus), because fewer leave key-switching noise far above
+# the modulus.  Every prime stays below 2^50.
 PARAMS = {
-    "n12_p17": Params(12, 17, 4, 36, 1, 60, 4),
-    "n13_p257": Params(13, 257, 8, 50, 3, 60, 2),
-    "n14_p257": Params(14, 257, 8, 50, 3, 60, 2),
-    "n15_p257": Params(15, 257, 14, 50, 4, 60, 3),
+    "n12_p17": Params(12, 17, 4, 36, 1, 50, 4),
+    "n13_p257": Params(13, 257, 8, 50, 4, 50, 2),
+    "n14_p257": Params(14, 257, 8, 50, 4, 50, 2),
+    "n15_p257": Params(15, 257, 14, 50, 5, 50, 3),
 }
 
 

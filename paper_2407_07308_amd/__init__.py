@@ -22,7 +22,7 @@ BC_OK, BC_ERR_ARG, BC_ERR_PARAM, BC_ERR_LEVEL, BC_ERR_OOM, BC_ERR_HIP, BC_ERR_KE
 BC_ROW_SWAP = -1
 BC_EXEC_BATCHED, BC_EXEC_GRAPH, BC_EXEC_PER_OP = 0, 1, 2
 BC_PROF_NTT_FWD, BC_PROF_NTT_INV = 0, 1
-BC_TUNE_NTT_CHUNK_BYTES, BC_TUNE_NTT_SINGLE_PASS = 0, 1
+BC_TUNE_NTT_CHUNK_BYTES, BC_TUNE_NTT_SINGLE_PASS, BC_TUNE_FP64 = 0, 1, 2
 
 
 class BoostcomUnavailable(RuntimeError):
@@ -333,7 +333,8 @@ class Context:
         """Picks the fastest transform schedule for this context; returns it."""
         _check(self.L.bc_autotune(self.handle, _stream()))
         return {"single_pass": self.get_tuning(BC_TUNE_NTT_SINGLE_PASS),
-                "chunk_bytes": self.get_tuning(BC_TUNE_NTT_CHUNK_BYTES)}
+                "chunk_bytes": self.get_tuning(BC_TUNE_NTT_CHUNK_BYTES),
+                "fp64": self.get_tuning(BC_TUNE_FP64)}
 
     def get_tuning(self, key: int) -> int:
         v = ctypes.c_int64()

@@ -21,8 +21,9 @@ ARCH = "gfx950"
 
 SOURCES = ["ntt.hip", "kernels.hip", "context.cpp", "ops.cpp", "circuits.cpp", "capi.cpp"]
 
-# Packed FP32 instructions are disabled for all device code (the library has
-# no floating point, the flag keeps the compiler from emitting them anyway).
+# Packed FP32 instructions are disabled for all device code (the only floating
+# point is the fp64 transform arithmetic; the flag keeps the compiler from
+# emitting packed fp32 forms anyway).
 FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

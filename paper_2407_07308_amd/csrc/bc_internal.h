@@ -65,6 +65,56 @@ __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
 
 __device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
 
+// ------------------------------------------- exact fp64 residue arithmetic
+// For primes below 2^50 a residue can be held as an integer-valued double and
+// multiplied at the full fp64 rate.  A constant w (0 <= w < q) travels as the
+// pair (w, w/q) of doubles (FPair; stored in the two words of a Shoup pair).
+// f_mulmod(y, c) for |y| < 2^52: quotient estimate k = rint(y * (w/q)), off
+// from y w / q by at most 1/2 + |y| 2^-52; the exact split y w = ph + pl
+// (ph = fl(y w), pl = fma(y, w, -ph)); result (ph - k q) + pl, where fma
+// forms ph - k q exactly because it is an integer below 2^53 and the final
+// sum is exact for the same reason.  The result is congruent to y w and
+// |result| <= q (1/2 + |y| 2^-52).  f_reduce(x) = x - rint(x/q) q is exact and
+// lies in [-q/2, q/2] up to one unit for |x| < 2^53.
+struct FPair {
+    double w, wq;
+};
+__device__ __forceinline__ FPair fpair(const u64 *p) {
+    return {__longlong_as_double((long long)p[0]), __longlong_as_double((long long)p[1])};
+}
+__device__ __forceinline__ double f_mulmod(double y, FPair c, double q) {
+#pragma clang fp contract(off)
+    double k = __builtin_rint(y * c.wq), ph = y * c.w, pl = __builtin_fma(y, c.w, -ph);
+    return __builtin_fma(-k, q, ph) + pl;
+}
+__device__ __forceinline__ double f_reduce(double x, double q, double qinv) {
+#pragma clang fp contract(off)
+    return __builtin_fma(-__builtin_rint(x * qinv), q, x);
+}
+// canonical representative in [0, q)
+__device__ __forceinline__ double f_canon(double x, double q, double qinv) {
+#pragma clang fp contract(off)
+    double r = f_reduce(x, q, qinv);
+    return r < 0.0 ? r + q : r;
+}
+// centred representative in [-(q-1)/2, (q-1)/2] (q odd)
+__device__ __forceinline__ double f_centre(double x, double q, double qinv) {
+#pragma clang fp contract(off)
+    double r = f_reduce(x, q, qinv), h = 0.5 * (q - 1.0);
+    r = r > h ? r - q : r;
+    return r < -h ? r + q : r;
+}
+// 0 <= x < 2^52 as a double: OR-ing 2^52's exponent into the pattern gives 2^52 + x
+__device__ __forceinline__ double f_load(u64 x) {
+#pragma clang fp contract(off)
+    return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 0x1p52;
+}
+// integer-valued double in [0, 2^52) -> u64
+__device__ __forceinline__ u64 f_bits(double x) {
+#pragma clang fp contract(off)
+    return (u64)__double_as_longlong(x + 0x1p52) & 0x000FFFFFFFFFFFFFull;
+}
+
 // Per-prime Barrett data for products of two variables a, b < q:
 // x = a b < q^2 < 2^(2s) (q < 2^s);  t = x >> (s-2);  qh = mulhi(t, mu),
 // mu = floor(2^(62+s) / q);  then qh is floor(x/q) minus at most 2 and
@@ -103,6 +153,10 @@ struct PrimeInfo {
     u64 ninv, ninvp;      // N^-1 (Shoup)
     u64 ninvw1, ninvw1p;  // N^-1 * Winv[1] (Shoup): last inverse stage
     u64 p_mod, p_modp;    // p mod q (Shoup)
+    // fp64 transform arithmetic (q < 2^50): q, 1/q, and N^-1, N^-1 * Winv[1]
+    // each with its ratio to q
+    double qd, qinv, ninv_d, ninv_q, ninvw1_d, ninvw1_q;
+    u64 p_f[2];  // p mod q as an FPair (fp64 base conversions)
 };
 
 // Fast base conversion from one digit at one level (modulus raising).
@@ -152,6 +206,7 @@ struct Pool {
     size_t held = 0;
     bool recording = false;          // collect every block handed out (graph capture)
     std::vector<void *> recorded;
+    static size_t size_class(size_t bytes);
     void *alloc(size_t bytes);
     // Removes the recorded blocks (all released by now) from the pool and
     // returns them: a recorded graph keeps using them.
@@ -204,10 +259,15 @@ struct bc_ctx {
     std::vector<bc::u64> mod;  // host copy of the moduli
     // device tables
     bc::u64 *tw = nullptr;            // [nmod][4][N]: W, W', Winv, Winv'
+    double *twf = nullptr;            // [nmod][4][N]: W, W/q, Winv, Winv/q (all primes < 2^50)
     bc::PrimeInfo *pinfo = nullptr;   // [nmod]
     bc::ModUpPlan *modup = nullptr;   // [nQ][dnum]  (level, digit)
     bc::ModDownPlan *moddown = nullptr;
     bc::ModSwitchPlan *modsw = nullptr;  // [nQ]
+    // the same plans with FPair constants (only when every prime < 2^50)
+    bc::ModUpPlan *modup_f = nullptr;
+    bc::ModDownPlan *moddown_f = nullptr;
+    bc::ModSwitchPlan *modsw_f = nullptr;
     bc::GarnerTable *garner = nullptr;
     std::vector<bc::PrimeInfo> h_pinfo;
     std::vector<bc::ModUpPlan> h_modup;  // host copies (launch sizing)
@@ -215,15 +275,22 @@ struct bc_ctx {
     int exec_mode = BC_EXEC_BATCHED;
     size_t ntt_chunk_bytes = 0;  // 0: one launch pair per transform call
     int ntt_single_pass = 1;     // one-launch transform for N = 2^12 .. 2^15
+    int fp64 = 1;                // fp64 transforms and base conversions where twf exists
     std::unique_ptr<bc::GraphCache> graphs;
     std::mutex graph_mu;
     hipStream_t capture_stream = nullptr;      // graph recording (created on first use)
     std::unique_ptr<bc::Profiler> prof{new bc::Profiler()};
     std::mutex table_mu;                       // guards lt_c and ps_coef
     std::vector<int64_t> lt_c;                 // LT polynomial coefficients
-    std::map<int, bc::u64 *> ps_coef;          // per level: block coefficients (Shoup)
+    std::map<int, bc::u64 *> ps_coef;          // key 2 level + fp64: block coefficient pairs
     ~bc_ctx();
 };
+
+namespace bc {
+// fp64 arithmetic for the transforms and the base conversions: every prime
+// below 2^50 (the fp64 tables exist) and not switched off
+inline bool use_fp64(const bc_ctx *c) { return c->fp64 && c->twf != nullptr; }
+}  // namespace bc
 
 struct bc_keys {
     bc_ctx *ctx;

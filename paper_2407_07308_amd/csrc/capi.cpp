@@ -509,6 +509,7 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
         BC_REQUIRE(value >= 0, BC_ERR_ARG, "tuning value must be non-negative");
         if (key == BC_TUNE_NTT_CHUNK_BYTES) ctx->ntt_chunk_bytes = (size_t)value;
         else if (key == BC_TUNE_NTT_SINGLE_PASS) ctx->ntt_single_pass = value != 0;
+        else if (key == BC_TUNE_FP64) ctx->fp64 = value != 0;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }
@@ -519,6 +520,7 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
         BC_REQUIRE(value, BC_ERR_ARG, "null output");
         if (key == BC_TUNE_NTT_CHUNK_BYTES) *value = (int64_t)ctx->ntt_chunk_bytes;
         else if (key == BC_TUNE_NTT_SINGLE_PASS) *value = ctx->ntt_single_pass;
+        else if (key == BC_TUNE_FP64) *value = ctx->fp64 && ctx->twf != nullptr;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }
@@ -545,9 +547,15 @@ int bc_autotune(bc_ctx *ctx, void *stream) {
         struct Cand {
             int single;
             size_t chunk;
+            int fp;
         };
-        std::vector<Cand> cands = {{0, 0}, {0, (size_t)128 << 20}};
-        if (ctx->logN >= 12 && ctx->logN <= 15) cands.push_back({1, 0});
+        std::vector<Cand> cands;
+        for (int fp : {1, 0}) {
+            if (fp && !ctx->twf) continue;
+            cands.push_back({0, 0, fp});
+            cands.push_back({0, (size_t)128 << 20, fp});
+            if (ctx->logN >= 12 && ctx->logN <= 15) cands.push_back({1, 0, fp});
+        }
         const bool prof = ctx->prof->on;
         ctx->prof->on = false;
         hipEvent_t e0, e1;
@@ -558,6 +566,7 @@ int bc_autotune(bc_ctx *ctx, void *stream) {
         for (const Cand &cd : cands) {
             ctx->ntt_single_pass = cd.single;
             ctx->ntt_chunk_bytes = cd.chunk;
+            ctx->fp64 = cd.fp;
             ntt_forward(ctx, ls, st);
             ntt_inverse(ctx, ls, st);
             BC_HIP(hipEventRecord(e0, st));
@@ -578,6 +587,7 @@ int bc_autotune(bc_ctx *ctx, void *stream) {
         (void)hipEventDestroy(e1);
         ctx->ntt_single_pass = pick.single;
         ctx->ntt_chunk_bytes = pick.chunk;
+        ctx->fp64 = pick.fp;
         ctx->prof->on = prof;
     });
 }

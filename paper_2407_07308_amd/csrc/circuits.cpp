@@ -15,6 +15,7 @@
 // that every round of the block tree is one batched multiplication.
 
 #include <algorithm>
+#include <cstring>
 
 #include "ops.h"
 
@@ -123,7 +124,9 @@ struct DevEval {
 
 const u64 *ps_coef_table(bc_ctx *c, int level, int b, int nblk) {
     std::lock_guard<std::mutex> g(c->table_mu);
-    auto it = c->ps_coef.find(level);
+    const bool fp = use_fp64(c);
+    const int key = 2 * level + (fp ? 1 : 0);
+    auto it = c->ps_coef.find(key);
     if (it != c->ps_coef.end()) return it->second;
     if (c->lt_c.empty()) c->lt_c = lt_coefficients(c->p);
     const int nbaby = b / 2, nl = level + 1;
@@ -135,14 +138,20 @@ const u64 *ps_coef_table(bc_ctx *c, int level, int b, int nblk) {
                 u64 q = c->mod[i];
                 u64 r = cv >= 0 ? (u64)cv % q : q - (u64)(-cv) % q;
                 u64 *w = &tab[(((size_t)t * nbaby + kk) * nl + i) * 2];
-                w[0] = r % q;
-                w[1] = h_shoup(w[0], q);
+                if (fp) {
+                    const double wd = (double)(r % q), wq = wd / (double)q;
+                    std::memcpy(&w[0], &wd, sizeof(double));
+                    std::memcpy(&w[1], &wq, sizeof(double));
+                } else {
+                    w[0] = r % q;
+                    w[1] = h_shoup(w[0], q);
+                }
             }
         }
     u64 *d = nullptr;
     BC_HIP(hipMalloc(&d, sizeof(u64) * tab.size()));
     BC_HIP(hipMemcpy(d, tab.data(), sizeof(u64) * tab.size(), hipMemcpyHostToDevice));
-    c->ps_coef[level] = d;
+    c->ps_coef[key] = d;
     return d;
 }
 

@@ -114,18 +114,109 @@ void set_shoup(u64 dst[2], u64 w, u64 q) {
     dst[1] = h_shoup(dst[0], q);
 }
 
+// (w, w/q) as doubles in the two words of a pair (fp64 arithmetic, q < 2^50;
+// the quotient is correctly rounded)
+void set_fpair(u64 dst[2], u64 w, u64 q) {
+    const double wd = (double)(w % q), r = wd / (double)q;
+    std::memcpy(&dst[0], &wd, sizeof(double));
+    std::memcpy(&dst[1], &r, sizeof(double));
+}
+
+typedef void (*PairSet)(u64 dst[2], u64 w, u64 q);
+
+// Base-conversion and modulus-switching constants, each stored as a pair by
+// `setp` (Shoup pairs for the integer kernels, FPairs for the fp64 ones).
+void build_plans(const bc_ctx *c, PairSet setp, std::vector<ModUpPlan> &mu, ModDownPlan &md,
+                 std::vector<ModSwitchPlan> &ms) {
+    const int nQ = c->nQ, nP = c->nP;
+    // modulus raising, one plan per (level, digit)
+    mu.assign((size_t)nQ * c->dnum, ModUpPlan{});
+    for (int lv = 0; lv < nQ; lv++)
+        for (int j = 0; j < c->dnum; j++) {
+            ModUpPlan &pl = mu[(size_t)lv * c->dnum + j];
+            int lo = j * c->alpha, hi = std::min(std::min((j + 1) * c->alpha, nQ), lv + 1);
+            pl.src_lo = lo;
+            pl.nsrc = std::max(0, hi - lo);
+            pl.ntgt = 0;
+            if (pl.nsrc == 0) continue;
+            for (int i = lo; i < hi; i++) {
+                u64 q = c->mod[i], prod = 1;
+                for (int t = lo; t < hi; t++)
+                    if (t != i) prod = h_mulmod(prod, c->mod[t] % q, q);
+                setp(pl.qhinv[i - lo], h_invmod(prod, q), q);
+            }
+            int next = lv + 1 + nP;
+            for (int e = 0; e < next; e++) {
+                if (e >= lo && e < hi) continue;
+                int prime = e <= lv ? e : nQ + (e - lv - 1);
+                u64 q = c->mod[prime];
+                int t = pl.ntgt++;
+                pl.tgt_e[t] = e;
+                pl.tgt_prime[t] = prime;
+                for (int i = lo; i < hi; i++) {
+                    u64 prod = 1;
+                    for (int k = lo; k < hi; k++)
+                        if (k != i) prod = h_mulmod(prod, c->mod[k] % q, q);
+                    setp(pl.qhat[t][i - lo], prod, q);
+                }
+            }
+        }
+    // modulus lowering (exact division by P)
+    std::memset(&md, 0, sizeof(ModDownPlan));
+    for (int j = 0; j < nP; j++) {
+        u64 pj = c->mod[nQ + j], prod = 1;
+        for (int t = 0; t < nP; t++)
+            if (t != j) prod = h_mulmod(prod, c->mod[nQ + t] % pj, pj);
+        setp(md.vfac[j], h_mulmod(h_invmod(c->p % pj, pj), h_invmod(prod, pj), pj), pj);
+    }
+    for (int i = 0; i < nQ; i++) {
+        u64 q = c->mod[i], P = 1;
+        for (int j = 0; j < nP; j++) {
+            u64 prod = 1;
+            for (int t = 0; t < nP; t++)
+                if (t != j) prod = h_mulmod(prod, c->mod[nQ + t] % q, q);
+            setp(md.phat[i][j], prod, q);
+            P = h_mulmod(P, c->mod[nQ + j] % q, q);
+        }
+        u64 Pinv = h_invmod(P, q);
+        setp(md.pinv[i], Pinv, q);
+        setp(md.ppinv[i], h_mulmod(Pinv, c->p % q, q), q);
+    }
+    // modulus switching, one plan per level
+    ms.assign(nQ, ModSwitchPlan{});
+    std::memset(ms.data(), 0, sizeof(ModSwitchPlan) * nQ);
+    for (int lv = 1; lv < nQ; lv++) {
+        u64 ql = c->mod[lv];
+        ms[lv].ql = ql;
+        setp(ms[lv].pinv_l, h_invmod(c->p % ql, ql), ql);
+        for (int i = 0; i < lv; i++) setp(ms[lv].qlinv[i], h_invmod(ql % c->mod[i], c->mod[i]), c->mod[i]);
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ pool
 
 thread_local hipStream_t tl_stream = nullptr;
 
+// Block sizes are rounded up to a size class (four per power of two, at
+// least 256 bytes), and a request takes any cached block of its stream up to
+// twice its class: batches of varying shape then reuse each other's blocks
+// instead of allocating (and eventually freeing, which waits for the device).
+size_t Pool::size_class(size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    int e = 63 - __builtin_clzll(bytes);
+    if (e < 2) return 256;
+    const size_t step = (size_t)1 << (e - 2);
+    return (bytes + step - 1) / step * step;
+}
+
 void *Pool::alloc(size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
+    bytes = size_class(bytes);
     std::lock_guard<std::mutex> g(mu);
     const hipStream_t st = tl_stream;
     auto it = free_.lower_bound({st, bytes});
-    if (it != free_.end() && it->first.first == st && it->first.second <= bytes + bytes / 8) {
+    if (it != free_.end() && it->first.first == st && it->first.second <= 2 * bytes) {
         void *p = it->second;
         live_[p] = {it->first.second, st};
         free_.erase(it);
@@ -303,78 +394,50 @@ void build_context(bc_ctx *c, const bc_params &prm) {
         pi.ninvw1p = h_shoup(pi.ninvw1, q);
         pi.p_mod = c->p % q;
         pi.p_modp = h_shoup(pi.p_mod, q);
+        // fp64 constants: integers below 2^50 are exact doubles and the
+        // quotients are correctly rounded
+        pi.qd = (double)q;
+        pi.qinv = 1.0 / pi.qd;
+        pi.ninv_d = (double)pi.ninv;
+        pi.ninv_q = pi.ninv_d / pi.qd;
+        pi.ninvw1_d = (double)pi.ninvw1;
+        pi.ninvw1_q = pi.ninvw1_d / pi.qd;
+        set_fpair(pi.p_f, c->p, q);
     }
     c->tw = upload(tw.data(), tw.size());
+    if (*std::max_element(c->mod.begin(), c->mod.end()) < ((u64)1 << 50)) {
+        std::vector<double> twf(tw.size());
+        for (int m = 0; m < nm; m++) {
+            const u64 *W = &tw[(size_t)m * 4 * N], *Wi = W + 2 * N;
+            double *F = &twf[(size_t)m * 4 * N], qd = (double)c->mod[m];
+            for (int k = 0; k < N; k++) {
+                F[k] = (double)W[k];
+                F[N + k] = F[k] / qd;
+                F[2 * N + k] = (double)Wi[k];
+                F[3 * N + k] = F[2 * N + k] / qd;
+            }
+        }
+        c->twf = upload(twf.data(), twf.size());
+    }
     c->pinfo = upload(c->h_pinfo.data(), nm);
 
-    // modulus raising plans, one per (level, digit)
-    c->h_modup.assign((size_t)nQ * c->dnum, ModUpPlan{});
-    for (int lv = 0; lv < nQ; lv++)
-        for (int j = 0; j < c->dnum; j++) {
-            ModUpPlan &pl = c->h_modup[(size_t)lv * c->dnum + j];
-            int lo = j * c->alpha, hi = std::min(std::min((j + 1) * c->alpha, nQ), lv + 1);
-            pl.src_lo = lo;
-            pl.nsrc = std::max(0, hi - lo);
-            pl.ntgt = 0;
-            if (pl.nsrc == 0) continue;
-            for (int i = lo; i < hi; i++) {
-                u64 q = c->mod[i], prod = 1;
-                for (int t = lo; t < hi; t++)
-                    if (t != i) prod = h_mulmod(prod, c->mod[t] % q, q);
-                set_shoup(pl.qhinv[i - lo], h_invmod(prod, q), q);
-            }
-            int next = lv + 1 + nP;
-            for (int e = 0; e < next; e++) {
-                if (e >= lo && e < hi) continue;
-                int prime = e <= lv ? e : nQ + (e - lv - 1);
-                u64 q = c->mod[prime];
-                int t = pl.ntgt++;
-                pl.tgt_e[t] = e;
-                pl.tgt_prime[t] = prime;
-                for (int i = lo; i < hi; i++) {
-                    u64 prod = 1;
-                    for (int k = lo; k < hi; k++)
-                        if (k != i) prod = h_mulmod(prod, c->mod[k] % q, q);
-                    set_shoup(pl.qhat[t][i - lo], prod, q);
-                }
-            }
+    // base-conversion and modulus-switching plans (fp64 twins when every
+    // prime is below 2^50)
+    {
+        auto md = std::make_unique<ModDownPlan>();
+        std::vector<ModSwitchPlan> ms;
+        build_plans(c, set_shoup, c->h_modup, *md, ms);
+        c->modup = upload(c->h_modup.data(), c->h_modup.size());
+        c->moddown = upload(md.get(), 1);
+        c->modsw = upload(ms.data(), nQ);
+        if (c->twf) {
+            std::vector<ModUpPlan> mu;
+            build_plans(c, set_fpair, mu, *md, ms);
+            c->modup_f = upload(mu.data(), mu.size());
+            c->moddown_f = upload(md.get(), 1);
+            c->modsw_f = upload(ms.data(), nQ);
         }
-    c->modup = upload(c->h_modup.data(), c->h_modup.size());
-
-    // modulus lowering (exact division by P)
-    auto md = std::make_unique<ModDownPlan>();
-    std::memset(md.get(), 0, sizeof(ModDownPlan));
-    for (int j = 0; j < nP; j++) {
-        u64 pj = c->mod[nQ + j], prod = 1;
-        for (int t = 0; t < nP; t++)
-            if (t != j) prod = h_mulmod(prod, c->mod[nQ + t] % pj, pj);
-        set_shoup(md->vfac[j], h_mulmod(h_invmod(c->p % pj, pj), h_invmod(prod, pj), pj), pj);
     }
-    for (int i = 0; i < nQ; i++) {
-        u64 q = c->mod[i], P = 1;
-        for (int j = 0; j < nP; j++) {
-            u64 prod = 1;
-            for (int t = 0; t < nP; t++)
-                if (t != j) prod = h_mulmod(prod, c->mod[nQ + t] % q, q);
-            set_shoup(md->phat[i][j], prod, q);
-            P = h_mulmod(P, c->mod[nQ + j] % q, q);
-        }
-        u64 Pinv = h_invmod(P, q);
-        set_shoup(md->pinv[i], Pinv, q);
-        set_shoup(md->ppinv[i], h_mulmod(Pinv, c->p % q, q), q);
-    }
-    c->moddown = upload(md.get(), 1);
-
-    // modulus switching plans
-    std::vector<ModSwitchPlan> ms(nQ);
-    std::memset(ms.data(), 0, sizeof(ModSwitchPlan) * nQ);
-    for (int lv = 1; lv < nQ; lv++) {
-        u64 ql = c->mod[lv];
-        ms[lv].ql = ql;
-        set_shoup(ms[lv].pinv_l, h_invmod(c->p % ql, ql), ql);
-        for (int i = 0; i < lv; i++) set_shoup(ms[lv].qlinv[i], h_invmod(ql % c->mod[i], c->mod[i]), c->mod[i]);
-    }
-    c->modsw = upload(ms.data(), nQ);
 
     // decryption: Garner tables
     auto g = std::make_unique<GarnerTable>();
@@ -397,10 +460,14 @@ bc_ctx::~bc_ctx() {
     graphs.reset();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     (void)hipFree(tw);
+    (void)hipFree(twf);
     (void)hipFree(pinfo);
     (void)hipFree(modup);
     (void)hipFree(moddown);
     (void)hipFree(modsw);
+    (void)hipFree(modup_f);
+    (void)hipFree(moddown_f);
+    (void)hipFree(modsw_f);
     (void)hipFree(garner);
     for (auto &kv : ps_coef) (void)hipFree(kv.second);
 }

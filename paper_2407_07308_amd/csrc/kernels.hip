@@ -103,31 +103,57 @@ __global__ void k_ks_prepare(const u64 *__restrict__ x, size_t x_ct_stride, u64 
 
 // Fast base conversion of digit j (z-grid = ct * dnum + j):
 // y_i = [x_i Qhat_i^-1]_{q_i}, u_t = sum_i y_i Qhat_i mod q_t.
+template <bool FP>
 __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const ModUpPlan *__restrict__ plans,
                         const PrimeInfo *__restrict__ pinfo, int nl, int next, int dnum, int N) {
     const int n = blockIdx.x * kT + threadIdx.x;
     const int ct = blockIdx.z / dnum, j = blockIdx.z - ct * dnum;
     const ModUpPlan &pl = plans[j];
     if (pl.nsrc == 0) return;
-    // fully unrolled over the compile-time bound so y[] stays in registers
-    u64 y[kMaxDigit];
-#pragma unroll
-    for (int s = 0; s < kMaxDigit; s++) {
-        if (s >= pl.nsrc) break;
-        int i = pl.src_lo + s;
-        u64 x = xc[((size_t)ct * nl + i) * N + n];
-        y[s] = shoup(x, pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
-    }
     u64 *out = mu + ((size_t)ct * dnum + j) * next * N + n;
-    for (int t = 0; t < pl.ntgt; t++) {
-        const u64 q = pinfo[pl.tgt_prime[t]].q;
-        u64 acc = 0;
+    if constexpr (!FP) {
+        // fully unrolled over the compile-time bound so y[] stays in registers
+        u64 y[kMaxDigit];
 #pragma unroll
         for (int s = 0; s < kMaxDigit; s++) {
             if (s >= pl.nsrc) break;
-            acc = add_mod(acc, shoup(y[s], pl.qhat[t][s][0], pl.qhat[t][s][1], q), q);
+            int i = pl.src_lo + s;
+            u64 x = xc[((size_t)ct * nl + i) * N + n];
+            y[s] = shoup(x, pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
         }
-        out[(size_t)pl.tgt_e[t] * N] = acc;
+        for (int t = 0; t < pl.ntgt; t++) {
+            const u64 q = pinfo[pl.tgt_prime[t]].q;
+            u64 acc = 0;
+#pragma unroll
+            for (int s = 0; s < kMaxDigit; s++) {
+                if (s >= pl.nsrc) break;
+                acc = add_mod(acc, shoup(y[s], pl.qhat[t][s][0], pl.qhat[t][s][1], q), q);
+            }
+            out[(size_t)pl.tgt_e[t] * N] = acc;
+        }
+    } else {
+#pragma clang fp contract(off)
+        // y_s canonical in [0, q_s); each product below 0.75 q_t in magnitude,
+        // so eight of them sum exactly before a reduction
+        double y[kMaxDigit];
+#pragma unroll
+        for (int s = 0; s < kMaxDigit; s++) {
+            if (s >= pl.nsrc) break;
+            const PrimeInfo &pi = pinfo[pl.src_lo + s];
+            double x = f_load(xc[((size_t)ct * nl + pl.src_lo + s) * N + n]);
+            y[s] = f_canon(f_mulmod(x, fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
+        }
+        for (int t = 0; t < pl.ntgt; t++) {
+            const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < kMaxDigit; s++) {
+                if (s >= pl.nsrc) break;
+                acc += f_mulmod(y[s], fpair(pl.qhat[t][s]), pt.qd);
+                if ((s & 7) == 7) acc = f_reduce(acc, pt.qd, pt.qinv);
+            }
+            out[(size_t)pl.tgt_e[t] * N] = f_bits(f_canon(acc, pt.qd, pt.qinv));
+        }
     }
 }
 
@@ -199,47 +225,88 @@ __global__ void k_ks_combine(const u64 *__restrict__ base0, const u64 *__restric
 // so that, after E is transformed, out_i = (d_i + acc_i P^-1) q_l^-1 - E_i
 // equals the modulus switch of the relinearised ciphertext exactly (every
 // step is linear over Z_{q_i}).  d and acc limbs l are coefficient domain here.
+template <bool FP>
 __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restrict__ d, size_t d_ct_stride,
                                u64 *__restrict__ E, const ModDownPlan *__restrict__ md,
                                const ModSwitchPlan *__restrict__ ms, const PrimeInfo *__restrict__ pinfo, int level,
                                int nQ, int nP, int next, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
     const int ct = cc >> 1, c = cc & 1, nl = level + 1;
-    u64 v[kMaxDigit];
-#pragma unroll
-    for (int j = 0; j < kMaxDigit; j++) {
-        if (j >= nP) break;
-        u64 x = acc[((size_t)cc * next + nl + j) * N + n];
-        v[j] = shoup(x, md->vfac[j][0], md->vfac[j][1], pinfo[nQ + j].q);
-    }
-    // top limb of the relinearised component
-    const u64 ql = pinfo[level].q;
-    u64 th = 0;
-#pragma unroll
-    for (int j = 0; j < kMaxDigit; j++) {
-        if (j >= nP) break;
-        th = add_mod(th, shoup(v[j], md->phat[level][j][0], md->phat[level][j][1], ql), ql);
-    }
-    u64 a = acc[((size_t)cc * next + level) * N + n];
-    u64 r = sub_mod(shoup(a, md->pinv[level][0], md->pinv[level][1], ql),
-                    shoup(th, md->ppinv[level][0], md->ppinv[level][1], ql), ql);
-    r = add_mod(r, d[(size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n], ql);
-    const u64 t = shoup(r, ms->pinv_l[0], ms->pinv_l[1], ql);
-    const bool neg = t > (ql - 1) / 2;
-    const u64 mag = neg ? ql - t : t;
-    for (int i = 0; i < level; i++) {
-        const PrimeInfo &pi = pinfo[i];
-        const u64 q = pi.q;
-        u64 h = 0;
+    if constexpr (!FP) {
+        u64 v[kMaxDigit];
 #pragma unroll
         for (int j = 0; j < kMaxDigit; j++) {
             if (j >= nP) break;
-            h = add_mod(h, shoup(v[j], md->phat[i][j][0], md->phat[i][j][1], q), q);
+            u64 x = acc[((size_t)cc * next + nl + j) * N + n];
+            v[j] = shoup(x, md->vfac[j][0], md->vfac[j][1], pinfo[nQ + j].q);
         }
-        u64 pt = shoup(mag, pi.p_mod, pi.p_modp, q);
-        pt = (neg && pt) ? q - pt : pt;
-        u64 e = add_mod(shoup(h, md->ppinv[i][0], md->ppinv[i][1], q), pt, q);
-        E[((size_t)cc * level + i) * N + n] = shoup(e, ms->qlinv[i][0], ms->qlinv[i][1], q);
+        // top limb of the relinearised component
+        const u64 ql = pinfo[level].q;
+        u64 th = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxDigit; j++) {
+            if (j >= nP) break;
+            th = add_mod(th, shoup(v[j], md->phat[level][j][0], md->phat[level][j][1], ql), ql);
+        }
+        u64 a = acc[((size_t)cc * next + level) * N + n];
+        u64 r = sub_mod(shoup(a, md->pinv[level][0], md->pinv[level][1], ql),
+                        shoup(th, md->ppinv[level][0], md->ppinv[level][1], ql), ql);
+        r = add_mod(r, d[(size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n], ql);
+        const u64 t = shoup(r, ms->pinv_l[0], ms->pinv_l[1], ql);
+        const bool neg = t > (ql - 1) / 2;
+        const u64 mag = neg ? ql - t : t;
+        for (int i = 0; i < level; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            const u64 q = pi.q;
+            u64 h = 0;
+#pragma unroll
+            for (int j = 0; j < kMaxDigit; j++) {
+                if (j >= nP) break;
+                h = add_mod(h, shoup(v[j], md->phat[i][j][0], md->phat[i][j][1], q), q);
+            }
+            u64 pt = shoup(mag, pi.p_mod, pi.p_modp, q);
+            pt = (neg && pt) ? q - pt : pt;
+            u64 e = add_mod(shoup(h, md->ppinv[i][0], md->ppinv[i][1], q), pt, q);
+            E[((size_t)cc * level + i) * N + n] = shoup(e, ms->qlinv[i][0], ms->qlinv[i][1], q);
+        }
+    } else {
+#pragma clang fp contract(off)
+        double v[kMaxDigit];  // canonical in [0, p_j)
+#pragma unroll
+        for (int j = 0; j < kMaxDigit; j++) {
+            if (j >= nP) break;
+            const PrimeInfo &pj = pinfo[nQ + j];
+            double x = f_load(acc[((size_t)cc * next + nl + j) * N + n]);
+            v[j] = f_canon(f_mulmod(x, fpair(md->vfac[j]), pj.qd), pj.qd, pj.qinv);
+        }
+        const PrimeInfo &pl = pinfo[level];
+        const double ql = pl.qd;
+        double th = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxDigit; j++) {
+            if (j >= nP) break;
+            th += f_mulmod(v[j], fpair(md->phat[level][j]), ql);
+            if ((j & 7) == 7) th = f_reduce(th, ql, pl.qinv);
+        }
+        th = f_reduce(th, ql, pl.qinv);
+        double a = f_load(acc[((size_t)cc * next + level) * N + n]);
+        double r = f_mulmod(a, fpair(md->pinv[level]), ql) - f_mulmod(th, fpair(md->ppinv[level]), ql) +
+                   f_load(d[(size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n]);
+        // the exact centred lift: it enters every other modulus as an integer
+        const double t = f_centre(f_mulmod(r, fpair(ms->pinv_l), ql), ql, pl.qinv);
+        for (int i = 0; i < level; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            const double q = pi.qd;
+            double h = 0.0;
+#pragma unroll
+            for (int j = 0; j < kMaxDigit; j++) {
+                if (j >= nP) break;
+                h += f_mulmod(v[j], fpair(md->phat[i][j]), q);
+                if ((j & 7) == 7) h = f_reduce(h, q, pi.qinv);
+            }
+            double e = f_mulmod(h, fpair(md->ppinv[i]), q) + f_mulmod(t, fpair(pi.p_f), q);
+            E[((size_t)cc * level + i) * N + n] = f_bits(f_canon(f_mulmod(e, fpair(ms->qlinv[i]), q), q, pi.qinv));
+        }
     }
 }
 
@@ -270,17 +337,27 @@ __global__ void k_ms_top(const u64 *__restrict__ in, u64 *__restrict__ top, int 
 }
 
 // R[ct][c][i] = p t mod q_i, t = [top p^-1]_{q_l} lifted to (-q_l/2, q_l/2]
+template <bool FP>
 __global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const ModSwitchPlan *__restrict__ pl,
                          const PrimeInfo *__restrict__ pinfo, int level, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
-    const u64 ql = pl->ql;
-    u64 t = shoup(top[(size_t)cc * N + n], pl->pinv_l[0], pl->pinv_l[1], ql);
-    const bool neg = t > (ql - 1) / 2;
-    const u64 mag = neg ? ql - t : t;  // |t| < q_l < q_i
-    for (int i = 0; i < level; i++) {
-        const PrimeInfo &pi = pinfo[i];
-        u64 r = shoup(mag, pi.p_mod, pi.p_modp, pi.q);
-        R[((size_t)cc * level + i) * N + n] = (neg && r) ? pi.q - r : r;
+    if constexpr (!FP) {
+        const u64 ql = pl->ql;
+        u64 t = shoup(top[(size_t)cc * N + n], pl->pinv_l[0], pl->pinv_l[1], ql);
+        const bool neg = t > (ql - 1) / 2;
+        const u64 mag = neg ? ql - t : t;  // |t| < q_l < q_i
+        for (int i = 0; i < level; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            u64 r = shoup(mag, pi.p_mod, pi.p_modp, pi.q);
+            R[((size_t)cc * level + i) * N + n] = (neg && r) ? pi.q - r : r;
+        }
+    } else {
+        const PrimeInfo &pq = pinfo[level];
+        const double t = f_centre(f_mulmod(f_load(top[(size_t)cc * N + n]), fpair(pl->pinv_l), pq.qd), pq.qd, pq.qinv);
+        for (int i = 0; i < level; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            R[((size_t)cc * level + i) * N + n] = f_bits(f_canon(f_mulmod(t, fpair(pi.p_f), pi.qd), pi.qd, pi.qinv));
+        }
     }
 }
 
@@ -289,45 +366,74 @@ __global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const
 // linear, so switching in either domain gives the same residues).  in/out are
 // [ct][2][from+1] and [ct][2][to+1] coefficient-domain limbs.
 constexpr int kMaxDrop = 16;
+template <bool FP>
 __global__ void k_ms_multi(const u64 *__restrict__ in, u64 *__restrict__ out, const ModSwitchPlan *__restrict__ pl,
                            const PrimeInfo *__restrict__ pinfo, int from, int to, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
     const int nd = from - to;
     const u64 *C = in + (size_t)cc * (from + 1) * N + n;
-    u64 tmag[kMaxDrop];
-    bool tneg[kMaxDrop];
-    // t_s for s = from, from-1, ..., to+1 (index d = from - s)
-#pragma unroll
-    for (int d = 0; d < kMaxDrop; d++) {
-        if (d >= nd) break;
-        const int s = from - d;
-        const u64 q = pinfo[s].q;
-        u64 c = C[(size_t)s * N];
-#pragma unroll
-        for (int e = 0; e < kMaxDrop; e++) {
-            if (e >= d) break;
-            const int se = from - e;
-            u64 r = shoup(tmag[e], pinfo[s].p_mod, pinfo[s].p_modp, q);
-            r = (tneg[e] && r) ? q - r : r;
-            c = shoup(sub_mod(c, r, q), pl[se].qlinv[s][0], pl[se].qlinv[s][1], q);
-        }
-        u64 t = shoup(c, pl[s].pinv_l[0], pl[s].pinv_l[1], q);
-        tneg[d] = t > (q - 1) / 2;
-        tmag[d] = tneg[d] ? q - t : t;
-    }
     u64 *O = out + (size_t)cc * (to + 1) * N + n;
-    for (int i = 0; i <= to; i++) {
-        const u64 q = pinfo[i].q;
-        u64 c = C[(size_t)i * N];
+    if constexpr (!FP) {
+        u64 tmag[kMaxDrop];
+        bool tneg[kMaxDrop];
+        // t_s for s = from, from-1, ..., to+1 (index d = from - s)
 #pragma unroll
-        for (int e = 0; e < kMaxDrop; e++) {
-            if (e >= nd) break;
-            const int se = from - e;
-            u64 r = shoup(tmag[e], pinfo[i].p_mod, pinfo[i].p_modp, q);
-            r = (tneg[e] && r) ? q - r : r;
-            c = shoup(sub_mod(c, r, q), pl[se].qlinv[i][0], pl[se].qlinv[i][1], q);
+        for (int d = 0; d < kMaxDrop; d++) {
+            if (d >= nd) break;
+            const int s = from - d;
+            const u64 q = pinfo[s].q;
+            u64 c = C[(size_t)s * N];
+#pragma unroll
+            for (int e = 0; e < kMaxDrop; e++) {
+                if (e >= d) break;
+                const int se = from - e;
+                u64 r = shoup(tmag[e], pinfo[s].p_mod, pinfo[s].p_modp, q);
+                r = (tneg[e] && r) ? q - r : r;
+                c = shoup(sub_mod(c, r, q), pl[se].qlinv[s][0], pl[se].qlinv[s][1], q);
+            }
+            u64 t = shoup(c, pl[s].pinv_l[0], pl[s].pinv_l[1], q);
+            tneg[d] = t > (q - 1) / 2;
+            tmag[d] = tneg[d] ? q - t : t;
         }
-        O[(size_t)i * N] = c;
+        for (int i = 0; i <= to; i++) {
+            const u64 q = pinfo[i].q;
+            u64 c = C[(size_t)i * N];
+#pragma unroll
+            for (int e = 0; e < kMaxDrop; e++) {
+                if (e >= nd) break;
+                const int se = from - e;
+                u64 r = shoup(tmag[e], pinfo[i].p_mod, pinfo[i].p_modp, q);
+                r = (tneg[e] && r) ? q - r : r;
+                c = shoup(sub_mod(c, r, q), pl[se].qlinv[i][0], pl[se].qlinv[i][1], q);
+            }
+            O[(size_t)i * N] = c;
+        }
+    } else {
+#pragma clang fp contract(off)
+        double t[kMaxDrop];  // exact centred lifts
+#pragma unroll
+        for (int d = 0; d < kMaxDrop; d++) {
+            if (d >= nd) break;
+            const int s = from - d;
+            const PrimeInfo &ps = pinfo[s];
+            double c = f_load(C[(size_t)s * N]);
+#pragma unroll
+            for (int e = 0; e < kMaxDrop; e++) {
+                if (e >= d) break;
+                c = f_mulmod(c - f_mulmod(t[e], fpair(ps.p_f), ps.qd), fpair(pl[from - e].qlinv[s]), ps.qd);
+            }
+            t[d] = f_centre(f_mulmod(c, fpair(pl[s].pinv_l), ps.qd), ps.qd, ps.qinv);
+        }
+        for (int i = 0; i <= to; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            double c = f_load(C[(size_t)i * N]);
+#pragma unroll
+            for (int e = 0; e < kMaxDrop; e++) {
+                if (e >= nd) break;
+                c = f_mulmod(c - f_mulmod(t[e], fpair(pi.p_f), pi.qd), fpair(pl[from - e].qlinv[i]), pi.qd);
+            }
+            O[(size_t)i * N] = f_bits(f_canon(c, pi.qd, pi.qinv));
+        }
     }
 }
 
@@ -451,35 +557,59 @@ __global__ void k_crt_decode(const u64 *__restrict__ d, uint32_t *__restrict__ o
 }
 
 // Paterson-Stockmeyer blocks: H[pos(t)][ct] = sum_k coef[t][k] * baby_k[ct]
-// (NTT domain, every baby at the same level).  coef holds Shoup pairs
-// [nblk][nbaby][nl][2] of the centred coefficients reduced mod q_i.
+// (NTT domain, every baby at the same level).  coef holds pairs
+// [nblk][nbaby][nl][2] of the centred coefficients reduced mod q_i: Shoup
+// pairs for the integer kernel, FPairs for the fp64 one.
 struct BabyArg {
     const u64 *baby[16];
     int pos[64];  // storage position of block t
 };
 // Babies are read at ciphertext blockIdx.z; outputs go to ciphertext
 // ct0 + blockIdx.z of a batch of `count` per block.
+template <bool FP>
 __global__ void k_lincomb(BabyArg ba, const u64 *__restrict__ coef, u64 *__restrict__ out, int nbaby, int nblk,
                           int count, int ct0, int nl, const PrimeInfo *__restrict__ pinfo, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    const u64 q = pinfo[i].q;
+    const PrimeInfo &pi = pinfo[i];
+    const u64 q = pi.q;
     const size_t L = (size_t)nl * N;
     for (int c = 0; c < 2; c++) {
-        u64 v[16];
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-            if (k >= nbaby) break;
-            v[k] = ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n];
-        }
-        for (int t = 0; t < nblk; t++) {
-            u64 acc = 0;
+        if constexpr (!FP) {
+            u64 v[16];
 #pragma unroll
             for (int k = 0; k < 16; k++) {
                 if (k >= nbaby) break;
-                const u64 *w = coef + (((size_t)t * nbaby + k) * nl + i) * 2;
-                acc = add_mod(acc, shoup(v[k], w[0], w[1], q), q);
+                v[k] = ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n];
             }
-            out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] = acc;
+            for (int t = 0; t < nblk; t++) {
+                u64 acc = 0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    if (k >= nbaby) break;
+                    const u64 *w = coef + (((size_t)t * nbaby + k) * nl + i) * 2;
+                    acc = add_mod(acc, shoup(v[k], w[0], w[1], q), q);
+                }
+                out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] = acc;
+            }
+        } else {
+#pragma clang fp contract(off)
+            double v[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                if (k >= nbaby) break;
+                v[k] = f_load(ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n]);
+            }
+            for (int t = 0; t < nblk; t++) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    if (k >= nbaby) break;
+                    acc += f_mulmod(v[k], fpair(coef + (((size_t)t * nbaby + k) * nl + i) * 2), pi.qd);
+                    if ((k & 7) == 7) acc = f_reduce(acc, pi.qd, pi.qinv);
+                }
+                out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] =
+                    f_bits(f_canon(acc, pi.qd, pi.qinv));
+            }
         }
     }
 }
@@ -522,8 +652,12 @@ void launch_ks_prepare(const bc_ctx *c, const u64 *x, size_t x_ct_stride, u64 *m
     k_ks_prepare<<<grid3(c->N, nl, count), kT, 0, st>>>(x, x_ct_stride, mu, xc, nl, next, c->dnum, c->alpha, c->N);
 }
 void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, hipStream_t st) {
-    k_modup<<<grid3(c->N, 1, count * c->dnum), kT, 0, st>>>(xc, mu, c->modup + (size_t)level * c->dnum, c->pinfo,
-                                                           level + 1, next, c->dnum, c->N);
+    if (use_fp64(c))
+        k_modup<true><<<grid3(c->N, 1, count * c->dnum), kT, 0, st>>>(xc, mu, c->modup_f + (size_t)level * c->dnum,
+                                                                     c->pinfo, level + 1, next, c->dnum, c->N);
+    else
+        k_modup<false><<<grid3(c->N, 1, count * c->dnum), kT, 0, st>>>(xc, mu, c->modup + (size_t)level * c->dnum,
+                                                                      c->pinfo, level + 1, next, c->dnum, c->N);
 }
 void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *key, u64 *acc, int count, int level, int next,
                      int nact, hipStream_t st) {
@@ -543,12 +677,19 @@ void launch_ms_top(const bc_ctx *c, const u64 *in, u64 *top, int count, int nl, 
     k_ms_top<<<grid3(c->N, 2, count), kT, 0, st>>>(in, top, nl, c->N);
 }
 void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st) {
-    k_ms_fbc<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(top, R, c->modsw + level, c->pinfo, level, c->N);
+    if (use_fp64(c))
+        k_ms_fbc<true><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(top, R, c->modsw_f + level, c->pinfo, level, c->N);
+    else
+        k_ms_fbc<false><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(top, R, c->modsw + level, c->pinfo, level, c->N);
 }
 void launch_relin_ms_fbc(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
                          int level, int next, hipStream_t st) {
-    k_relin_ms_fbc<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(acc, d, d_ct_stride, E, c->moddown, c->modsw + level,
-                                                            c->pinfo, level, c->nQ, c->nP, next, c->N);
+    if (use_fp64(c))
+        k_relin_ms_fbc<true><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(
+            acc, d, d_ct_stride, E, c->moddown_f, c->modsw_f + level, c->pinfo, level, c->nQ, c->nP, next, c->N);
+    else
+        k_relin_ms_fbc<false><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(
+            acc, d, d_ct_stride, E, c->moddown, c->modsw + level, c->pinfo, level, c->nQ, c->nP, next, c->N);
 }
 void launch_relin_ms_combine(const bc_ctx *c, const u64 *d, size_t d_ct_stride, const u64 *acc, const u64 *E, u64 *out,
                              int count, int level, int next, hipStream_t st) {
@@ -569,7 +710,10 @@ void launch_relin_ms_combine(const bc_ctx *c, const u64 *d, size_t d_ct_stride, 
 }
 void launch_ms_multi(const bc_ctx *c, const u64 *in, u64 *out, int count, int from, int to, hipStream_t st) {
     BC_REQUIRE(from - to <= kMaxDrop, BC_ERR_PARAM, "too many primes dropped at once");
-    k_ms_multi<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(in, out, c->modsw, c->pinfo, from, to, c->N);
+    if (use_fp64(c))
+        k_ms_multi<true><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(in, out, c->modsw_f, c->pinfo, from, to, c->N);
+    else
+        k_ms_multi<false><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(in, out, c->modsw, c->pinfo, from, to, c->N);
 }
 void launch_ms_combine(const bc_ctx *c, const u64 *in, const u64 *R, u64 *out, int count, int level, hipStream_t st) {
     k_ms_combine<<<grid3(c->N, level, count), kT, 0, st>>>(in, R, out, c->modsw + level, c->pinfo, level, c->N);
@@ -605,7 +749,12 @@ void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *pos, c
     BabyArg ba{};
     for (int k = 0; k < nbaby; k++) ba.baby[k] = babies[k];
     for (int t = 0; t < nblk; t++) ba.pos[t] = pos[t];
-    k_lincomb<<<grid3(c->N, nl, nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo, c->N);
+    if (use_fp64(c))
+        k_lincomb<true><<<grid3(c->N, nl, nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo,
+                                                                c->N);
+    else
+        k_lincomb<false><<<grid3(c->N, nl, nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo,
+                                                                 c->N);
 }
 void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st) {
     k_crt_decode<<<grid3(c->N, 1, count), kT, 0, st>>>(d, out, c->garner, c->pinfo, nl, c->p, c->N);

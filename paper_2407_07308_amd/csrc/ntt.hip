@@ -15,9 +15,9 @@
 // and writes every word of the limb once.  Inside a pass the line (column or
 // row) is transformed in two register chunks of up to four stages: a thread
 // holds up to 16 words, applies its chunk's butterflies in registers, and the
-// two chunks exchange words through LDS once.  Butterflies are Harvey's lazy
-// ones (values in [0, 4q) forward, [0, 2q) inverse) with Shoup products by
-// precomputed twiddles.
+// two chunks exchange words through LDS once.  The butterflies' arithmetic
+// is a policy: integer (Harvey's lazy butterflies with Shoup products) for
+// any prime, or fp64 for primes below 2^50 (see FpA).
 
 #include <algorithm>
 
@@ -35,14 +35,123 @@ constexpr int cols_per_block(int L1) {
     return (kLineWords >> L1) < (1 << L1) ? (kLineWords >> L1) : (1 << L1);
 }
 
-struct Tw {
+// ------------------------------------------------------------ arithmetic
+// The transforms are written once over an arithmetic policy A:
+//   A::V                the register type of a word inside a transform
+//   load(u64) / store() canonical word in [0, q) <-> register value
+//   raw(V) / unraw(u64) register value <-> its 64-bit pattern, for LDS and
+//                       for the intermediate between two passes
+//   fw(k) / iw(k)       forward / inverse twiddle of table index k
+//   ct, gs              one butterfly; gs_last folds N^-1 into the final one
+//
+// IntA: Harvey's lazy butterflies on u64 with Shoup products (any q < 2^62):
+// values in [0, 4q) forward, [0, 2q) inverse.
+//
+// FpA (every prime below 2^50): words are integers held in doubles, where
+// the products run at the full fp64 rate (f_mulmod and f_reduce, exact).
+// Values are reduced (prep) at the start of every register chunk (at most
+// five stages) except one loaded from canonical words.  Forward butterflies
+// are lazy, X +- y w mod q: a stage adds at most q (1/2 + B 2^-52) to the bound
+// B, so five stages from B = q stay below 7.2 q.  Inverse butterflies reduce
+// the sum on the chunk's odd stages, keeping values below 4 q and sums and
+// differences below 6 q.  Everything stays below 2^53 (= 8 q for q < 2^50):
+// no step rounds.
+struct IntA {
+    using V = u64;
+    struct T {
+        u64 w, wp;
+    };
     const u64 *W, *Wp, *Wi, *Wip;
+    u64 q, q2, ninv, ninvp, ninvw1, ninvw1p;
+    __device__ IntA(const void *tw, const PrimeInfo &pi, int prime, int N) {
+        const u64 *b = static_cast<const u64 *>(tw) + (size_t)prime * 4 * N;
+        W = b;
+        Wp = b + N;
+        Wi = b + 2 * N;
+        Wip = b + 3 * N;
+        q = pi.q;
+        q2 = 2 * q;
+        ninv = pi.ninv;
+        ninvp = pi.ninvp;
+        ninvw1 = pi.ninvw1;
+        ninvw1p = pi.ninvw1p;
+    }
+    __device__ T fw(int k) const { return {W[k], Wp[k]}; }
+    __device__ T iw(int k) const { return {Wi[k], Wip[k]}; }
+    __device__ V load(u64 x) const { return x; }
+    __device__ u64 store(V x) const {
+        x = x >= q2 ? x - q2 : x;
+        return x >= q ? x - q : x;
+    }
+    __device__ static u64 raw(V x) { return x; }
+    __device__ static V unraw(u64 x) { return x; }
+    __device__ V prep(V x) const { return x; }
+    __device__ void ct(V &X, V &Y, T t) const {
+        u64 x = X >= q2 ? X - q2 : X;
+        u64 p = shoup_lazy(Y, t.w, t.wp, q);
+        X = x + p;
+        Y = x - p + q2;
+    }
+    __device__ void gs(V &X, V &Y, T t, bool) const {
+        u64 u = X + Y, d = X - Y + q2;
+        X = u >= q2 ? u - q2 : u;
+        Y = shoup_lazy(d, t.w, t.wp, q);
+    }
+    __device__ void gs_last(V &X, V &Y) const {
+        u64 u = X + Y, d = X - Y + q2;
+        X = shoup_lazy(u, ninv, ninvp, q);
+        Y = shoup_lazy(d, ninvw1, ninvw1p, q);
+    }
 };
 
-__device__ __forceinline__ Tw tables(const u64 *tw, int prime, int N) {
-    const u64 *b = tw + (size_t)prime * 4 * N;
-    return {b, b + N, b + 2 * N, b + 3 * N};
-}
+struct FpA {
+    using V = double;
+    struct T {
+        double w, wq;
+    };
+    const double *W, *Wq, *Wi, *Wiq;
+    double q, u, ninv, ninvq, ninvw1, ninvw1q;
+    __device__ FpA(const void *tw, const PrimeInfo &pi, int prime, int N) {
+        const double *b = static_cast<const double *>(tw) + (size_t)prime * 4 * N;
+        W = b;
+        Wq = b + N;
+        Wi = b + 2 * N;
+        Wiq = b + 3 * N;
+        q = pi.qd;
+        u = pi.qinv;
+        ninv = pi.ninv_d;
+        ninvq = pi.ninv_q;
+        ninvw1 = pi.ninvw1_d;
+        ninvw1q = pi.ninvw1_q;
+    }
+    __device__ T fw(int k) const { return {W[k], Wq[k]}; }
+    __device__ T iw(int k) const { return {Wi[k], Wiq[k]}; }
+    __device__ double mulmod(double y, double w, double wq) const { return f_mulmod(y, FPair{w, wq}, q); }
+    __device__ double reduce(double x) const { return f_reduce(x, q, u); }
+    __device__ V load(u64 x) const { return f_load(x); }
+    __device__ u64 store(V x) const { return f_bits(f_canon(x, q, u)); }
+    __device__ static u64 raw(V x) { return (u64)__double_as_longlong(x); }
+    __device__ static V unraw(u64 x) { return __longlong_as_double((long long)x); }
+    __device__ V prep(V x) const { return reduce(x); }
+    __device__ void ct(V &X, V &Y, T t) const {
+#pragma clang fp contract(off)
+        double x = X, p = mulmod(Y, t.w, t.wq);
+        X = x + p;
+        Y = x - p;
+    }
+    __device__ void gs(V &X, V &Y, T t, bool red) const {
+#pragma clang fp contract(off)
+        double s = X + Y, d = X - Y;
+        X = red ? reduce(s) : s;
+        Y = mulmod(d, t.w, t.wq);
+    }
+    __device__ void gs_last(V &X, V &Y) const {
+#pragma clang fp contract(off)
+        double s = X + Y, d = X - Y;
+        X = mulmod(s, ninv, ninvq);
+        Y = mulmod(d, ninvw1, ninvw1q);
+    }
+};
 
 // Jobs are ordered limb-major: consecutive workgroups transform the same limb
 // of consecutive ciphertexts, so they share one prime's twiddle table and the
@@ -53,27 +162,18 @@ __device__ __forceinline__ u64 *limb_ptr(const LimbSet &ls, int job, int N, int 
     return ls.base + (size_t)poly * ls.poly_stride + (size_t)ls.off[k] * N;
 }
 
-__device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2) {
-    u64 x = X >= q2 ? X - q2 : X;
-    u64 t = shoup_lazy(Y, w, wp, q);
-    X = x + t;
-    Y = x - t + q2;
-}
-
-__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2) {
-    u64 u = X + Y;
-    u64 d = X - Y + q2;
-    X = u >= q2 ? u - q2 : u;
-    Y = shoup_lazy(d, w, wp, q);
-}
-
 // Forward chunk: stages on line bits [blo, blo + C) (high to low) of the
-// 2^C words v[k] at line positions X0 + (k << blo).  For the stage on bit b
+// 2^C words v[k] at line positions X0 + (k << blo); `fresh`: the words are
+// canonical (just loaded), else they are first brought back into range.  For the stage on bit b
 // the twiddle index is tbase(b) + (k >> (C - s)), s = (blo + C - 1) - b, with
 // tbase(b) = mb(b) + G * 2^(L-1-b) + (X0 >> (b + 1)).
-template <int C>
-__device__ __forceinline__ void fwd_chunk(u64 *v, const Tw &t, int L, int blo, int X0, int G, int logM, u64 q) {
-    const u64 q2 = 2 * q;
+template <int C, class A>
+__device__ __forceinline__ void fwd_chunk(typename A::V *v, const A &ar, int L, int blo, int X0, int G, int logM,
+                                          bool fresh) {
+    if (!fresh) {
+#pragma unroll
+        for (int k = 0; k < (1 << C); k++) v[k] = ar.prep(v[k]);
+    }
 #pragma unroll
     for (int s = 0; s < C; s++) {
         const int b = blo + C - 1 - s;
@@ -81,19 +181,22 @@ __device__ __forceinline__ void fwd_chunk(u64 *v, const Tw &t, int L, int blo, i
         const int tb = (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
 #pragma unroll
         for (int blk = 0; blk < (1 << s); blk++) {
-            const u64 w = t.W[tb + blk], wp = t.Wp[tb + blk];
+            const typename A::T w = ar.fw(tb + blk);
 #pragma unroll
-            for (int j = 0; j < half; j++) ct_bfly(v[blk * 2 * half + j], v[blk * 2 * half + j + half], w, wp, q, q2);
+            for (int j = 0; j < half; j++) ar.ct(v[blk * 2 * half + j], v[blk * 2 * half + j + half], w);
         }
     }
 }
 
 // Inverse chunk: stages on bits blo .. blo + C - 1 (low to high).  With
 // `scale`, the last stage (the transform's final one, m = 1) folds in N^-1.
-template <int C>
-__device__ __forceinline__ void inv_chunk(u64 *v, const Tw &t, int L, int blo, int X0, int G, int logM, u64 q,
-                                          bool scale, const PrimeInfo &pi) {
-    const u64 q2 = 2 * q;
+template <int C, class A>
+__device__ __forceinline__ void inv_chunk(typename A::V *v, const A &ar, int L, int blo, int X0, int G, int logM,
+                                          bool scale, bool fresh) {
+    if (!fresh) {
+#pragma unroll
+        for (int k = 0; k < (1 << C); k++) v[k] = ar.prep(v[k]);
+    }
 #pragma unroll
     for (int s = 0; s < C; s++) {
         const int b = blo + s;
@@ -101,18 +204,13 @@ __device__ __forceinline__ void inv_chunk(u64 *v, const Tw &t, int L, int blo, i
         const int tb = (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
 #pragma unroll
         for (int blk = 0; blk < (1 << (C - 1 - s)); blk++) {
-            const u64 w = t.Wi[tb + blk], wp = t.Wip[tb + blk];
+            if (scale && s == C - 1) {
 #pragma unroll
-            for (int j = 0; j < half; j++) {
-                u64 &X = v[blk * 2 * half + j], &Y = v[blk * 2 * half + j + half];
-                if (scale && s == C - 1) {
-                    u64 u = X + Y, d = X - Y + q2;
-                    u64 a = shoup_lazy(u, pi.ninv, pi.ninvp, q), r = shoup_lazy(d, pi.ninvw1, pi.ninvw1p, q);
-                    X = a >= q ? a - q : a;
-                    Y = r >= q ? r - q : r;
-                } else {
-                    gs_bfly(X, Y, w, wp, q, q2);
-                }
+                for (int j = 0; j < half; j++) ar.gs_last(v[blk * 2 * half + j], v[blk * 2 * half + j + half]);
+            } else {
+                const typename A::T w = ar.iw(tb + blk);
+#pragma unroll
+                for (int j = 0; j < half; j++) ar.gs(v[blk * 2 * half + j], v[blk * 2 * half + j + half], w, s & 1);
             }
         }
     }
@@ -121,10 +219,13 @@ __device__ __forceinline__ void inv_chunk(u64 *v, const Tw &t, int L, int blo, i
 // ---------------------------------------------------------------- pass A
 // Columns: line = one column of N1 = 2^L1 words (stride N2 in memory), CW
 // columns per workgroup.  Twiddle index of the stage on bit b:
-// m = 2^(L1-1-b), group = row >> (b+1)  (so logM = L1, G = 0).
-template <int L1, bool INV>
-__global__ void __launch_bounds__(kThreads) ntt_cols(LimbSet ls, const u64 *__restrict__ tw,
+// m = 2^(L1-1-b), group = row >> (b+1)  (so logM = L1, G = 0).  Forward:
+// canonical words in, raw register values out (read by pass B); inverse: raw
+// in, canonical out.
+template <int L1, bool INV, class A>
+__global__ void __launch_bounds__(kThreads) ntt_cols(LimbSet ls, const void *__restrict__ tw,
                                                      const PrimeInfo *__restrict__ pinfo, int logN) {
+    using V = typename A::V;
     constexpr int N1 = 1 << L1;
     constexpr int CW = cols_per_block(L1);
     constexpr int CHI = (L1 + 1) / 2, CLO = L1 - CHI;  // chunk on the high / low row bits
@@ -134,11 +235,9 @@ __global__ void __launch_bounds__(kThreads) ntt_cols(LimbSet ls, const u64 *__re
     const int job = blockIdx.x / colblocks, c0 = (blockIdx.x - job * colblocks) * CW;
     int prime;
     u64 *a = limb_ptr(ls, job, N, prime) + c0;
-    const PrimeInfo &pi = pinfo[prime];
-    const u64 q = pi.q;
-    const Tw t = tables(tw, prime, N);
+    const A ar(tw, pinfo[prime], prime, N);
     const int tid = threadIdx.x;
-    u64 v[16];
+    V v[16];
 
     // Both chunks touch HBM directly: for a fixed k, consecutive threads take
     // consecutive columns of one row, so every access is coalesced; LDS only
@@ -148,38 +247,38 @@ __global__ void __launch_bounds__(kThreads) ntt_cols(LimbSet ls, const u64 *__re
         for (int g = tid; g < (1 << CLO) * CW; g += kThreads) {
             const int col = g % CW, X0 = g / CW;
 #pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) v[k] = a[(size_t)(X0 + (k << CLO)) * N2 + col];
-            fwd_chunk<CHI>(v, t, L1, CLO, X0, 0, L1, q);
+            for (int k = 0; k < (1 << CHI); k++) v[k] = ar.load(a[(size_t)(X0 + (k << CLO)) * N2 + col]);
+            fwd_chunk<CHI>(v, ar, L1, CLO, X0, 0, L1, true);
 #pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) s[(X0 + (k << CLO)) * CW + col] = v[k];
+            for (int k = 0; k < (1 << CHI); k++) s[(X0 + (k << CLO)) * CW + col] = A::raw(v[k]);
         }
         __syncthreads();
         for (int g = tid; g < (1 << CHI) * CW; g += kThreads) {
             const int col = g % CW, X0 = (g / CW) << CLO;
 #pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) v[k] = s[(X0 + k) * CW + col];
-            fwd_chunk<CLO>(v, t, L1, 0, X0, 0, L1, q);
+            for (int k = 0; k < (1 << CLO); k++) v[k] = A::unraw(s[(X0 + k) * CW + col]);
+            fwd_chunk<CLO>(v, ar, L1, 0, X0, 0, L1, false);
 #pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) a[(size_t)(X0 + k) * N2 + col] = v[k];
+            for (int k = 0; k < (1 << CLO); k++) a[(size_t)(X0 + k) * N2 + col] = A::raw(v[k]);
         }
     } else {
         // low row bits first: words at rows X0 + k
         for (int g = tid; g < (1 << CHI) * CW; g += kThreads) {
             const int col = g % CW, X0 = (g / CW) << CLO;
 #pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) v[k] = a[(size_t)(X0 + k) * N2 + col];
-            inv_chunk<CLO>(v, t, L1, 0, X0, 0, L1, q, false, pi);
+            for (int k = 0; k < (1 << CLO); k++) v[k] = A::unraw(a[(size_t)(X0 + k) * N2 + col]);
+            inv_chunk<CLO>(v, ar, L1, 0, X0, 0, L1, false, false);
 #pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) s[(X0 + k) * CW + col] = v[k];
+            for (int k = 0; k < (1 << CLO); k++) s[(X0 + k) * CW + col] = A::raw(v[k]);
         }
         __syncthreads();
         for (int g = tid; g < (1 << CLO) * CW; g += kThreads) {
             const int col = g % CW, X0 = g / CW;
 #pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) v[k] = s[(X0 + (k << CLO)) * CW + col];
-            inv_chunk<CHI>(v, t, L1, CLO, X0, 0, L1, q, true, pi);
+            for (int k = 0; k < (1 << CHI); k++) v[k] = A::unraw(s[(X0 + (k << CLO)) * CW + col]);
+            inv_chunk<CHI>(v, ar, L1, CLO, X0, 0, L1, true, false);
 #pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) a[(size_t)(X0 + (k << CLO)) * N2 + col] = v[k];
+            for (int k = 0; k < (1 << CHI); k++) a[(size_t)(X0 + (k << CLO)) * N2 + col] = ar.store(v[k]);
         }
     }
 }
@@ -189,12 +288,14 @@ __global__ void __launch_bounds__(kThreads) ntt_cols(LimbSet ls, const u64 *__re
 // Twiddle index of the stage on bit b in row u: m = N / 2^(b+1),
 // group = u * 2^(L2-1-b) + (x >> (b+1))  (logM = logN, G = u).
 // LDS rows are padded by one word per 16 so both chunks' accesses avoid
-// bank conflicts.
+// bank conflicts.  Forward: raw in, canonical out; inverse: canonical in, raw
+// out.
 __device__ __forceinline__ int padx(int x) { return x + (x >> 4); }
 
-template <int L2, bool INV>
-__global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const u64 *__restrict__ tw,
+template <int L2, bool INV, class A>
+__global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const void *__restrict__ tw,
                                                      const PrimeInfo *__restrict__ pinfo, int logN) {
+    using V = typename A::V;
     constexpr int N2 = 1 << L2;
     constexpr int RS = N2 + N2 / 16;  // padded row stride in LDS
     constexpr int CHI = (L2 + 1) / 2, CLO = L2 - CHI;
@@ -206,35 +307,28 @@ __global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const u64 *__re
     const int job = blockIdx.x / rowblocks, u0 = (blockIdx.x - job * rowblocks) * R;
     int prime;
     u64 *a = limb_ptr(ls, job, N, prime) + (size_t)u0 * N2;
-    const PrimeInfo &pi = pinfo[prime];
-    const u64 q = pi.q;
-    const Tw t = tables(tw, prime, N);
+    const A ar(tw, pinfo[prime], prime, N);
     const int tid = threadIdx.x;
-    u64 v[16];
+    V v[16];
 
     if (!INV) {
         for (int g = tid; g < R << CLO; g += kThreads) {
             const int rr = g >> CLO, X0 = g & ((1 << CLO) - 1);
             const u64 *row = a + (size_t)rr * N2;
 #pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) v[k] = row[X0 + (k << CLO)];
-            fwd_chunk<CHI>(v, t, L2, CLO, X0, u0 + rr, logN, q);
+            for (int k = 0; k < (1 << CHI); k++) v[k] = A::unraw(row[X0 + (k << CLO)]);
+            fwd_chunk<CHI>(v, ar, L2, CLO, X0, u0 + rr, logN, false);
 #pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) s[rr * RS + padx(X0 + (k << CLO))] = v[k];
+            for (int k = 0; k < (1 << CHI); k++) s[rr * RS + padx(X0 + (k << CLO))] = A::raw(v[k]);
         }
         __syncthreads();
-        const u64 q2 = 2 * q;
         for (int g = tid; g < R << CHI; g += kThreads) {
             const int rr = g >> CHI, X0 = (g & ((1 << CHI) - 1)) << CLO;
 #pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) v[k] = s[rr * RS + padx(X0 + k)];
-            fwd_chunk<CLO>(v, t, L2, 0, X0, u0 + rr, logN, q);
+            for (int k = 0; k < (1 << CLO); k++) v[k] = A::unraw(s[rr * RS + padx(X0 + k)]);
+            fwd_chunk<CLO>(v, ar, L2, 0, X0, u0 + rr, logN, false);
 #pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) {
-                u64 x = v[k];
-                x = x >= q2 ? x - q2 : x;
-                s[rr * RS + padx(X0 + k)] = x >= q ? x - q : x;
-            }
+            for (int k = 0; k < (1 << CLO); k++) s[rr * RS + padx(X0 + k)] = ar.store(v[k]);
         }
         __syncthreads();
         for (int idx = tid; idx < R * N2; idx += kThreads) {
@@ -250,20 +344,20 @@ __global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const u64 *__re
         for (int g = tid; g < R << CHI; g += kThreads) {
             const int rr = g >> CHI, X0 = (g & ((1 << CHI) - 1)) << CLO;
 #pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) v[k] = s[rr * RS + padx(X0 + k)];
-            inv_chunk<CLO>(v, t, L2, 0, X0, u0 + rr, logN, q, false, pi);
+            for (int k = 0; k < (1 << CLO); k++) v[k] = ar.load(s[rr * RS + padx(X0 + k)]);
+            inv_chunk<CLO>(v, ar, L2, 0, X0, u0 + rr, logN, false, true);
 #pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) s[rr * RS + padx(X0 + k)] = v[k];
+            for (int k = 0; k < (1 << CLO); k++) s[rr * RS + padx(X0 + k)] = A::raw(v[k]);
         }
         __syncthreads();
         for (int g = tid; g < R << CLO; g += kThreads) {
             const int rr = g >> CLO, X0 = g & ((1 << CLO) - 1);
 #pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) v[k] = s[rr * RS + padx(X0 + (k << CLO))];
-            inv_chunk<CHI>(v, t, L2, CLO, X0, u0 + rr, logN, q, false, pi);
+            for (int k = 0; k < (1 << CHI); k++) v[k] = A::unraw(s[rr * RS + padx(X0 + (k << CLO))]);
+            inv_chunk<CHI>(v, ar, L2, CLO, X0, u0 + rr, logN, false, false);
             u64 *row = a + (size_t)rr * N2;
 #pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) row[X0 + (k << CLO)] = v[k];
+            for (int k = 0; k < (1 << CHI); k++) row[X0 + (k << CLO)] = A::raw(v[k]);
         }
     }
 }
@@ -284,20 +378,25 @@ constexpr int kSplitWords = 16384;
 // LDS slot of word x.  With SPLIT the exchange runs in two rounds on bit BIT
 // of x (removed from the slot index); BIT is chosen so that in both layouts it
 // is a bit of the thread id, i.e. every thread writes and reads in one round.
-// One pad word per 32 keeps the strided accesses conflict-free.
+// One pad word per 32 keeps the strided accesses conflict-free.  For every
+// access below, x = base(thread) + (k << S) with the bits of k << S disjoint
+// from the base's and aligned so that lds_pos(base + (k << S)) =
+// lds_pos(base) + lds_pos(k << S): the slot is a per-thread base plus a
+// compile-time offset (an immediate of the LDS instruction).
 template <bool SPLIT, int BIT>
-__device__ __forceinline__ int lds_pos(int x) {
+__host__ __device__ constexpr int lds_pos(int x) {
     int y = SPLIT ? (((x >> (BIT + 1)) << BIT) | (x & ((1 << BIT) - 1))) : x;
     return y + (y >> 5);
 }
 template <bool SPLIT, int BIT>
-__device__ __forceinline__ int lds_round(int x) {
+__host__ __device__ constexpr int lds_round(int x) {
     return SPLIT ? (x >> BIT) & 1 : 0;
 }
 
-template <int LOGN, bool INV>
-__global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const u64 *__restrict__ tw,
+template <int LOGN, bool INV, class A>
+__global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const void *__restrict__ tw,
                                                             const PrimeInfo *__restrict__ pinfo) {
+    using V = typename A::V;
     constexpr int N = 1 << LOGN, C3 = LOGN - 10, NSPLIT = N > kSplitWords ? 2 : 1;
     constexpr int G3 = 1 << (5 - C3);  // chunk-3 groups per thread
     constexpr int LW = N > kSplitWords ? kSplitWords : N;
@@ -305,111 +404,109 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const u6
     const int t = threadIdx.x;
     int prime;
     u64 *a = limb_ptr(ls, blockIdx.x, N, prime);
-    const PrimeInfo &pi = pinfo[prime];
-    const u64 q = pi.q;
-    const Tw tb = tables(tw, prime, N);
+    const A ar(tw, pinfo[prime], prime, N);
     // word index of register k in each layout
     const int x1 = t;                                                     // + (k << (LOGN - 5))
     const int x2 = ((t >> C3) << (C3 + 5)) | (t & ((1 << C3) - 1));       // + (k << C3)
     const int x3 = t << 5;                                                // + k
-    u64 v[32];
+    V v[32];
 
     // exchange 1-2 splits on bit 4 (from t in both layouts), exchange 2-3 on
     // bit 14 (t's bits 5..9 in both layouts)
     constexpr bool SP = NSPLIT == 2;
     const int ra = lds_round<SP, 4>(x1), rb = lds_round<SP, 14>(x3);
+    const int pa1 = lds_pos<SP, 4>(x1), pa2 = lds_pos<SP, 4>(x2);    // exchange 1-2 bases
+    const int pb2 = lds_pos<SP, 14>(x2), pb3 = lds_pos<SP, 14>(x3);  // exchange 2-3 bases
     if (!INV) {
 #pragma unroll
-        for (int k = 0; k < 32; k++) v[k] = a[x1 + (k << (LOGN - 5))];
-        fwd_chunk<5>(v, tb, LOGN, LOGN - 5, x1, 0, LOGN, q);
+        for (int k = 0; k < 32; k++) v[k] = ar.load(a[x1 + (k << (LOGN - 5))]);
+        fwd_chunk<5>(v, ar, LOGN, LOGN - 5, x1, 0, LOGN, true);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (ra == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) s[lds_pos<SP, 4>(x1 + (k << (LOGN - 5)))] = v[k];
+                for (int k = 0; k < 32; k++) s[pa1 + lds_pos<SP, 4>(k << (LOGN - 5))] = A::raw(v[k]);
             }
             __syncthreads();
             if (ra == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = s[lds_pos<SP, 4>(x2 + (k << C3))];
+                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa2 + lds_pos<SP, 4>(k << C3)]);
             }
             __syncthreads();
         }
-        fwd_chunk<5>(v, tb, LOGN, C3, x2, 0, LOGN, q);
+        fwd_chunk<5>(v, ar, LOGN, C3, x2, 0, LOGN, false);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (rb == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) s[lds_pos<SP, 14>(x2 + (k << C3))] = v[k];
+                for (int k = 0; k < 32; k++) s[pb2 + lds_pos<SP, 14>(k << C3)] = A::raw(v[k]);
             }
             __syncthreads();
             if (rb == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = s[lds_pos<SP, 14>(x3 + k)];
+                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb3 + lds_pos<SP, 14>(k)]);
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), tb, LOGN, 0, x3 + (j << C3), 0, LOGN, q);
-        const u64 q2 = 2 * q;
+        for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), 0, LOGN, false);
         U64x2 *out = reinterpret_cast<U64x2 *>(a + x3);
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
-            u64 e = v[2 * k], o = v[2 * k + 1];
-            e = e >= q2 ? e - q2 : e;
-            o = o >= q2 ? o - q2 : o;
-            out[k] = U64x2{e >= q ? e - q : e, o >= q ? o - q : o};
-        }
+        for (int k = 0; k < 16; k++) out[k] = U64x2{ar.store(v[2 * k]), ar.store(v[2 * k + 1])};
     } else {
         const U64x2 *in = reinterpret_cast<const U64x2 *>(a + x3);
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             U64x2 p = in[k];
-            v[2 * k] = p.a;
-            v[2 * k + 1] = p.b;
+            v[2 * k] = ar.load(p.a);
+            v[2 * k + 1] = ar.load(p.b);
         }
 #pragma unroll
-        for (int j = 0; j < G3; j++)
-            inv_chunk<C3>(v + (j << C3), tb, LOGN, 0, x3 + (j << C3), 0, LOGN, q, false, pi);
+        for (int j = 0; j < G3; j++) inv_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), 0, LOGN, false, true);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (rb == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) s[lds_pos<SP, 14>(x3 + k)] = v[k];
+                for (int k = 0; k < 32; k++) s[pb3 + lds_pos<SP, 14>(k)] = A::raw(v[k]);
             }
             __syncthreads();
             if (rb == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = s[lds_pos<SP, 14>(x2 + (k << C3))];
+                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb2 + lds_pos<SP, 14>(k << C3)]);
             }
             __syncthreads();
         }
-        inv_chunk<5>(v, tb, LOGN, C3, x2, 0, LOGN, q, false, pi);
+        inv_chunk<5>(v, ar, LOGN, C3, x2, 0, LOGN, false, false);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (ra == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) s[lds_pos<SP, 4>(x2 + (k << C3))] = v[k];
+                for (int k = 0; k < 32; k++) s[pa2 + lds_pos<SP, 4>(k << C3)] = A::raw(v[k]);
             }
             __syncthreads();
             if (ra == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = s[lds_pos<SP, 4>(x1 + (k << (LOGN - 5)))];
+                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa1 + lds_pos<SP, 4>(k << (LOGN - 5))]);
             }
             __syncthreads();
         }
-        inv_chunk<5>(v, tb, LOGN, LOGN - 5, x1, 0, LOGN, q, true, pi);
+        inv_chunk<5>(v, ar, LOGN, LOGN - 5, x1, 0, LOGN, true, false);
 #pragma unroll
-        for (int k = 0; k < 32; k++) a[x1 + (k << (LOGN - 5))] = v[k];
+        for (int k = 0; k < 32; k++) a[x1 + (k << (LOGN - 5))] = ar.store(v[k]);
     }
 }
 
-template <bool INV>
-bool launch_full(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+// Arithmetic of a context's transforms: fp64 when every prime allows it and
+// it is enabled, else the integer butterflies.
+inline bool use_fp(const bc_ctx *c) { return use_fp64(c); }
+inline const void *tw_of(const bc_ctx *c) { return use_fp(c) ? (const void *)c->twf : (const void *)c->tw; }
+
+template <bool INV, class A>
+bool launch_full_a(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
     const unsigned njobs = (unsigned)(ls.npoly * ls.nlimb);
 #define BC_FULL(L)                                                                                \
     case L:                                                                                       \
-        ntt_full<L, INV><<<njobs, 1 << (L - 5), 0, st>>>(ls, c->tw, c->pinfo);                    \
+        ntt_full<L, INV, A><<<njobs, 1 << (L - 5), 0, st>>>(ls, tw_of(c), c->pinfo);              \
         return true;
     switch (logN) {
         BC_FULL(12) BC_FULL(13) BC_FULL(14) BC_FULL(15)
@@ -419,13 +516,18 @@ bool launch_full(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
 }
 
 template <bool INV>
-void launch_cols(int logN1, int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+bool launch_full(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+    return use_fp(c) ? launch_full_a<INV, FpA>(logN, ls, c, st) : launch_full_a<INV, IntA>(logN, ls, c, st);
+}
+
+template <bool INV, class A>
+void launch_cols_a(int logN1, int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
     int N2 = 1 << (logN - logN1), C = cols_per_block(logN1);
     int njobs = ls.npoly * ls.nlimb;
     dim3 grid((unsigned)(njobs * (N2 / C)));
 #define BC_COLS(L)                                                                                \
     case L:                                                                                       \
-        ntt_cols<L, INV><<<grid, kThreads, 0, st>>>(ls, c->tw, c->pinfo, logN);                   \
+        ntt_cols<L, INV, A><<<grid, kThreads, 0, st>>>(ls, tw_of(c), c->pinfo, logN);             \
         break;
     switch (logN1) {
         BC_COLS(5) BC_COLS(6) BC_COLS(7) BC_COLS(8)
@@ -435,19 +537,31 @@ void launch_cols(int logN1, int logN, const LimbSet &ls, const bc_ctx *c, hipStr
 }
 
 template <bool INV>
-void launch_rows(int logN2, int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+void launch_cols(int logN1, int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+    if (use_fp(c)) launch_cols_a<INV, FpA>(logN1, logN, ls, c, st);
+    else launch_cols_a<INV, IntA>(logN1, logN, ls, c, st);
+}
+
+template <bool INV, class A>
+void launch_rows_a(int logN2, int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
     int N1 = 1 << (logN - logN2), R = std::min(kLineWords >> logN2, N1);
     int njobs = ls.npoly * ls.nlimb;
     dim3 grid((unsigned)(njobs * (N1 / R)));
 #define BC_ROWS(L)                                                                                \
     case L:                                                                                       \
-        ntt_rows<L, INV><<<grid, kThreads, 0, st>>>(ls, c->tw, c->pinfo, logN);                   \
+        ntt_rows<L, INV, A><<<grid, kThreads, 0, st>>>(ls, tw_of(c), c->pinfo, logN);             \
         break;
     switch (logN2) {
         BC_ROWS(5) BC_ROWS(6) BC_ROWS(7) BC_ROWS(8)
         default: throw Error(BC_ERR_PARAM, "ntt: unsupported row length");
     }
 #undef BC_ROWS
+}
+
+template <bool INV>
+void launch_rows(int logN2, int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+    if (use_fp(c)) launch_rows_a<INV, FpA>(logN2, logN, ls, c, st);
+    else launch_rows_a<INV, IntA>(logN2, logN, ls, c, st);
 }
 
 }  // namespace

@@ -40,7 +40,7 @@ def same(dev, x, y):
 def test_group_equals_separate_calls_and_replays():
     import paper_2407_07308_amd as bc
 
-    members = [member(Params(10, 257, 12, 50, 3, 60, 3), 1), member(Params(11, 257, 12, 50, 3, 60, 3), 2)]
+    members = [member(Params(10, 257, 12, 50, 4, 50, 3), 1), member(Params(11, 257, 12, 50, 4, 50, 3), 2)]
     reqs, refs, vals = [], [], []
     for i, (dev, dk) in enumerate(members):
         G = 2 + i
@@ -67,8 +67,8 @@ def test_group_equals_separate_calls_and_replays():
 def test_server_results_equal_alone_and_in_the_mix():
     from paper_2407_07308_amd import serving
 
-    members = {1 << 10: member(Params(10, 257, 12, 50, 3, 60, 3), 3),
-               1 << 11: member(Params(11, 257, 12, 50, 3, 60, 3), 4)}
+    members = {1 << 10: member(Params(10, 257, 12, 50, 4, 50, 3), 3),
+               1 << 11: member(Params(11, 257, 12, 50, 4, 50, 3), 4)}
     g = synth.generator(77, "schedule")
     reqs = []
     t = 0.0

@@ -117,7 +117,7 @@ def test_per_op_path_equals_batched():
 def test_lt_p257_matches_oracle_and_graph_replay():
     import paper_2407_07308_amd as bc
 
-    prm = Params(10, 257, 8, 50, 3, 60, 2)
+    prm = Params(10, 257, 8, 50, 4, 50, 2)  # all primes < 2^50: fp64 transforms
     dev, dk, orc = make(prm)
     G = 2
     x = synth.slot_values(90, G, orc.M, 0, 129)

@@ -1,0 +1,68 @@
+"""Transform arithmetic and schedules at the workload ring sizes.
+
+With every prime below 2^50 the transforms run in fp64 arithmetic; the
+integer butterflies remain selectable.  Both must give the same bytes under
+every schedule (single-pass and two-pass, whole or chunked), and the
+ciphertexts must equal the oracle's.  Sizes: N = 2^12 .. 2^15, the range of
+the single-pass kernel, with two-digit key switching so special-prime limbs
+are transformed too.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import Oracle, Params
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [  # (fp64, single pass, chunk bytes)
+    (1, 1, 0), (1, 0, 0), (1, 0, 1 << 20), (0, 1, 0), (0, 0, 0), (0, 0, 1 << 20)]
+
+
+def run_all(dev, dk, slots, r):
+    import paper_2407_07308_amd as bc
+
+    outs = []
+    for fp, single, chunk in SCHEDULES:
+        dev.set_tuning(bc.BC_TUNE_FP64, fp)
+        dev.set_tuning(bc.BC_TUNE_NTT_SINGLE_PASS, single)
+        dev.set_tuning(bc.BC_TUNE_NTT_CHUNK_BYTES, chunk)
+        ct = dev.encrypt(dk, slots, r["u"], r["e"])
+        prod = dev.mul_relin(dk, ct, ct)
+        outs.append((dev.export(ct), dev.export(prod), dev.decrypt(dk, prod)))
+    return outs
+
+
+@pytest.mark.parametrize("logN", [12, 13, 14, 15])
+def test_fp64_and_integer_transforms_agree(logN):
+    import paper_2407_07308_amd as bc
+
+    prm = Params(logN, 257, 4, 50, 2, 50, 2)
+    print(f"\n[ntt arith] logN {logN}", flush=True)
+    dev = bc.Context.from_params(prm)
+    assert dev.get_tuning(bc.BC_TUNE_FP64) == 1
+    rnd = synth.keygen_randomness(31, prm.N, prm.nQ, prm.nP, prm.dnum, 0)
+    dk = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
+    count = 3
+    slots = synth.slot_values(32, count, dev.M, 0, prm.p)
+    r = synth.encrypt_randomness(33, count, prm.N)
+    outs = run_all(dev, dk, slots, r)
+    want = (slots.astype(np.int64) ** 2 % prm.p).astype(np.uint32)
+    for i, (ct, prod, dec) in enumerate(outs):
+        assert np.array_equal(ct, outs[0][0]), SCHEDULES[i]
+        assert np.array_equal(prod, outs[0][1]), SCHEDULES[i]
+        assert np.array_equal(dec, want), SCHEDULES[i]
+    if logN <= 13:  # the oracle's ciphertexts (seconds at these sizes)
+        orc = Oracle(prm)
+        orc.keygen(rnd)
+        o = [orc.encrypt(slots[i], r["u"][i], r["e"][i]) for i in range(count)]
+        assert np.array_equal(outs[0][0], np.stack([c.data for c in o]))
+        op = [orc.mul(c, c) for c in o]
+        assert np.array_equal(outs[0][1], np.stack([c.data for c in op]))
+
+
+def test_integer_only_context_reports_no_fp64():
+    import paper_2407_07308_amd as bc
+
+    dev = bc.Context.from_params(Params(12, 257, 4, 50, 1, 60, 4))
+    assert dev.get_tuning(bc.BC_TUNE_FP64) == 0

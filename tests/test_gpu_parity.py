@@ -20,6 +20,8 @@ SETS = {
     "p17": Params(10, 17, 6, 36, 1, 60, 3),
     "p257": Params(10, 257, 8, 50, 3, 60, 2),
     "p257_uneven": Params(11, 257, 7, 50, 4, 60, 3),  # digits of 3, 3 and 1 primes
+    # every prime below 2^50: the transforms run in fp64 arithmetic
+    "p257_fp64": Params(11, 257, 7, 50, 3, 50, 3),
 }
 ROT = (1, 2, -1)
 
