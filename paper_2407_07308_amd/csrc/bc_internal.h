@@ -144,6 +144,11 @@ struct LimbSet {
     int nlimb;
     int16_t off[kMaxJobs];
     int16_t prime[kMaxJobs];
+    // out-of-place input (null: in place): limb k of poly j is read from
+    // ibase + j * ipoly_stride + ioff[k] * N and written to base + ...
+    const u64 *ibase;
+    u64 ipoly_stride;
+    int16_t ioff[kMaxJobs];
 };
 
 // Constants of one prime (device copy).

@@ -90,17 +90,6 @@ __global__ void k_permute(const u64 *__restrict__ in, u64 *__restrict__ out, con
 
 // ------------------------------------------------------- key switching
 
-// X[ct] (component `comp` of a batch, NTT domain) -> the digit-own limbs of
-// MU[ct][j][e] and a coefficient-domain staging copy XC[ct][i].
-__global__ void k_ks_prepare(const u64 *__restrict__ x, size_t x_ct_stride, u64 *__restrict__ mu, u64 *__restrict__ xc,
-                             int nl, int next, int dnum, int alpha, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    u64 v = x[(size_t)ct * x_ct_stride + (size_t)i * N + n];
-    int j = i / alpha;
-    mu[(((size_t)ct * dnum + j) * next + i) * N + n] = v;
-    xc[((size_t)ct * nl + i) * N + n] = v;
-}
-
 // Fast base conversion of digit j (z-grid = ct * dnum + j):
 // y_i = [x_i Qhat_i^-1]_{q_i}, u_t = sum_i y_i Qhat_i mod q_t.
 template <bool FP>
@@ -157,15 +146,19 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
     }
 }
 
-// ACC[ct][c][e] = sum_j MU[ct][j][e] * K_j,c[prime(e)]   (NTT domain)
-__global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ key, u64 *__restrict__ acc, int level,
-                           int nQ, int nmod, int next, int nact, int dnum, const PrimeInfo *__restrict__ pinfo, int N) {
+// ACC[ct][c][e] = sum_j MU[ct][j][e] * K_j,c[prime(e)]   (NTT domain), where
+// digit j's own limbs (e in [j alpha, (j+1) alpha)) are X's limbs themselves
+__global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ x, size_t x_ct_stride,
+                           const u64 *__restrict__ key, u64 *__restrict__ acc, int level, int nQ, int nmod, int next,
+                           int nact, int dnum, int alpha, const PrimeInfo *__restrict__ pinfo, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, e = blockIdx.y, ct = blockIdx.z;
     const int prime = ext_prime(e, level, nQ);
     const Barrett br = pinfo[prime].br;
+    const int own = e <= level ? e / alpha : -1;
     u64 s0 = 0, s1 = 0;
     for (int j = 0; j < nact; j++) {
-        u64 u = mu[(((size_t)ct * dnum + j) * next + e) * N + n];
+        u64 u = j == own ? x[(size_t)ct * x_ct_stride + (size_t)e * N + n]
+                         : mu[(((size_t)ct * dnum + j) * next + e) * N + n];
         const u64 *K = key + ((size_t)j * 2 * nmod + prime) * N + n;
         s0 = add_mod(s0, mul_mod(u, K[0], br), br.q);
         s1 = add_mod(s1, mul_mod(u, K[(size_t)nmod * N], br), br.q);
@@ -329,12 +322,6 @@ __global__ void k_relin_ms_combine(const u64 *__restrict__ d, size_t d_ct_stride
 }
 
 // ----------------------------------------------------- modulus switching
-
-// top limb of both components -> TOP[ct][c][n]
-__global__ void k_ms_top(const u64 *__restrict__ in, u64 *__restrict__ top, int nl, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, c = blockIdx.y, ct = blockIdx.z;
-    top[((size_t)ct * 2 + c) * N + n] = in[(((size_t)ct * 2 + c) * nl + (nl - 1)) * N + n];
-}
 
 // R[ct][c][i] = p t mod q_i, t = [top p^-1]_{q_l} lifted to (-q_l/2, q_l/2]
 template <bool FP>
@@ -647,10 +634,6 @@ void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, i
                     hipStream_t st) {
     k_permute<<<grid3(c->N, nl, count), kT, 0, st>>>(in, out, perm, nl, ncomp, c->N);
 }
-void launch_ks_prepare(const bc_ctx *c, const u64 *x, size_t x_ct_stride, u64 *mu, u64 *xc, int count, int nl,
-                       int next, hipStream_t st) {
-    k_ks_prepare<<<grid3(c->N, nl, count), kT, 0, st>>>(x, x_ct_stride, mu, xc, nl, next, c->dnum, c->alpha, c->N);
-}
 void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, hipStream_t st) {
     if (use_fp64(c))
         k_modup<true><<<grid3(c->N, 1, count * c->dnum), kT, 0, st>>>(xc, mu, c->modup_f + (size_t)level * c->dnum,
@@ -659,10 +642,10 @@ void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level,
         k_modup<false><<<grid3(c->N, 1, count * c->dnum), kT, 0, st>>>(xc, mu, c->modup + (size_t)level * c->dnum,
                                                                       c->pinfo, level + 1, next, c->dnum, c->N);
 }
-void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *key, u64 *acc, int count, int level, int next,
-                     int nact, hipStream_t st) {
-    k_ks_inner<<<grid3(c->N, next, count), kT, 0, st>>>(mu, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum,
-                                                        c->pinfo, c->N);
+void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_stride, const u64 *key, u64 *acc,
+                     int count, int level, int next, int nact, hipStream_t st) {
+    k_ks_inner<<<grid3(c->N, next, count), kT, 0, st>>>(mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact,
+                                                        c->dnum, c->alpha, c->pinfo, c->N);
 }
 void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, hipStream_t st) {
     k_moddown<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(acc, th, c->moddown, c->pinfo, level, c->nQ, c->nP, next, c->N);
@@ -672,9 +655,6 @@ void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size
     k_ks_combine<<<grid3(c->N, level + 1, count), kT, 0, st>>>(base0, base1, base_ct_stride, acc, th, out,
                                                                out_ct_stride, c->moddown, c->pinfo, level + 1, next,
                                                                c->N);
-}
-void launch_ms_top(const bc_ctx *c, const u64 *in, u64 *top, int count, int nl, hipStream_t st) {
-    k_ms_top<<<grid3(c->N, 2, count), kT, 0, st>>>(in, top, nl, c->N);
 }
 void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st) {
     if (use_fp64(c))

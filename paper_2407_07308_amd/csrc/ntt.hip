@@ -161,6 +161,12 @@ __device__ __forceinline__ u64 *limb_ptr(const LimbSet &ls, int job, int N, int 
     prime = ls.prime[k];
     return ls.base + (size_t)poly * ls.poly_stride + (size_t)ls.off[k] * N;
 }
+// where the job's words are read (its output limb when in place)
+__device__ __forceinline__ const u64 *limb_src(const LimbSet &ls, int job, int N) {
+    int k = job / ls.npoly, poly = job - k * ls.npoly;
+    if (!ls.ibase) return ls.base + (size_t)poly * ls.poly_stride + (size_t)ls.off[k] * N;
+    return ls.ibase + (size_t)poly * ls.ipoly_stride + (size_t)ls.ioff[k] * N;
+}
 
 // Forward chunk: stages on line bits [blo, blo + C) (high to low) of the
 // 2^C words v[k] at line positions X0 + (k << blo); `fresh`: the words are
@@ -235,6 +241,7 @@ __global__ void __launch_bounds__(kThreads) ntt_cols(LimbSet ls, const void *__r
     const int job = blockIdx.x / colblocks, c0 = (blockIdx.x - job * colblocks) * CW;
     int prime;
     u64 *a = limb_ptr(ls, job, N, prime) + c0;
+    const u64 *ain = limb_src(ls, job, N) + c0;  // forward: the transform's input
     const A ar(tw, pinfo[prime], prime, N);
     const int tid = threadIdx.x;
     V v[16];
@@ -247,7 +254,7 @@ __global__ void __launch_bounds__(kThreads) ntt_cols(LimbSet ls, const void *__r
         for (int g = tid; g < (1 << CLO) * CW; g += kThreads) {
             const int col = g % CW, X0 = g / CW;
 #pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) v[k] = ar.load(a[(size_t)(X0 + (k << CLO)) * N2 + col]);
+            for (int k = 0; k < (1 << CHI); k++) v[k] = ar.load(ain[(size_t)(X0 + (k << CLO)) * N2 + col]);
             fwd_chunk<CHI>(v, ar, L1, CLO, X0, 0, L1, true);
 #pragma unroll
             for (int k = 0; k < (1 << CHI); k++) s[(X0 + (k << CLO)) * CW + col] = A::raw(v[k]);
@@ -307,6 +314,7 @@ __global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const void *__r
     const int job = blockIdx.x / rowblocks, u0 = (blockIdx.x - job * rowblocks) * R;
     int prime;
     u64 *a = limb_ptr(ls, job, N, prime) + (size_t)u0 * N2;
+    const u64 *ain = limb_src(ls, job, N) + (size_t)u0 * N2;  // inverse: the transform's input
     const A ar(tw, pinfo[prime], prime, N);
     const int tid = threadIdx.x;
     V v[16];
@@ -338,7 +346,7 @@ __global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const void *__r
     } else {
         for (int idx = tid; idx < R * N2; idx += kThreads) {
             int rr = idx >> L2, x = idx & (N2 - 1);
-            s[rr * RS + padx(x)] = a[idx];
+            s[rr * RS + padx(x)] = ain[idx];
         }
         __syncthreads();
         for (int g = tid; g < R << CHI; g += kThreads) {
@@ -393,6 +401,53 @@ __host__ __device__ constexpr int lds_round(int x) {
     return SPLIT ? (x >> BIT) & 1 : 0;
 }
 
+// In the last layout lane l of a wave holds words l*32 .. l*32+31 of the
+// wave's 2048-word block, so direct 16-byte accesses would touch 64 cache
+// lines per instruction.  These move a wave's block between registers and HBM
+// through a wave-private LDS tile (16 x 64 words, rows padded to 65) in two
+// halves of 16 registers, every instruction then covering eight whole
+// 128-byte lines: in half r, instruction j, lane m handles words 2p, 2p+1
+// (p = m % 8) of lane s = 8j + m / 8's sixteen.  Needs 1040 LDS words per
+// wave and no workgroup barrier: only the wave touches its tile.
+constexpr int kTileRow = 65;
+
+template <class A>
+__device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, const A &ar, u64 *tile, int lane) {
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+#pragma unroll
+        for (int i = 0; i < 16; i++) tile[i * kTileRow + lane] = ar.store(v[16 * r + i]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int p = lane & 7;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int sl = 8 * j + (lane >> 3);
+            U64x2 w{tile[(2 * p) * kTileRow + sl], tile[(2 * p + 1) * kTileRow + sl]};
+            *reinterpret_cast<U64x2 *>(blk + sl * 32 + 16 * r + 2 * p) = w;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
+template <class A>
+__device__ __forceinline__ void load_block(const u64 *blk, typename A::V *v, const A &ar, u64 *tile, int lane) {
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        const int p = lane & 7;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int sl = 8 * j + (lane >> 3);
+            U64x2 w = *reinterpret_cast<const U64x2 *>(blk + sl * 32 + 16 * r + 2 * p);
+            tile[(2 * p) * kTileRow + sl] = w.a;
+            tile[(2 * p + 1) * kTileRow + sl] = w.b;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int i = 0; i < 16; i++) v[16 * r + i] = ar.load(tile[i * kTileRow + lane]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
 template <int LOGN, bool INV, class A>
 __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const void *__restrict__ tw,
                                                             const PrimeInfo *__restrict__ pinfo) {
@@ -404,6 +459,7 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const vo
     const int t = threadIdx.x;
     int prime;
     u64 *a = limb_ptr(ls, blockIdx.x, N, prime);
+    const u64 *ain = limb_src(ls, blockIdx.x, N);
     const A ar(tw, pinfo[prime], prime, N);
     // word index of register k in each layout
     const int x1 = t;                                                     // + (k << (LOGN - 5))
@@ -419,7 +475,7 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const vo
     const int pb2 = lds_pos<SP, 14>(x2), pb3 = lds_pos<SP, 14>(x3);  // exchange 2-3 bases
     if (!INV) {
 #pragma unroll
-        for (int k = 0; k < 32; k++) v[k] = ar.load(a[x1 + (k << (LOGN - 5))]);
+        for (int k = 0; k < 32; k++) v[k] = ar.load(ain[x1 + (k << (LOGN - 5))]);
         fwd_chunk<5>(v, ar, LOGN, LOGN - 5, x1, 0, LOGN, true);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
@@ -450,17 +506,13 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const vo
         }
 #pragma unroll
         for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), 0, LOGN, false);
-        U64x2 *out = reinterpret_cast<U64x2 *>(a + x3);
-#pragma unroll
-        for (int k = 0; k < 16; k++) out[k] = U64x2{ar.store(v[2 * k]), ar.store(v[2 * k + 1])};
+        // the exchange above ended with a barrier: LDS is free for the wave tiles
+        const int wave = t >> 6, lane = t & 63;
+        store_block(a + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
     } else {
-        const U64x2 *in = reinterpret_cast<const U64x2 *>(a + x3);
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-            U64x2 p = in[k];
-            v[2 * k] = ar.load(p.a);
-            v[2 * k + 1] = ar.load(p.b);
-        }
+        const int wave = t >> 6, lane = t & 63;
+        load_block(ain + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
+        __syncthreads();  // every wave is done with its tile before the exchanges reuse LDS
 #pragma unroll
         for (int j = 0; j < G3; j++) inv_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), 0, LOGN, false, true);
 #pragma unroll
@@ -496,6 +548,84 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const vo
     }
 }
 
+// ------------------------------------------------- forward, two per limb
+// The forward transform's first stage (span N/2, twiddle W[1]) is the only
+// one that mixes the two halves of a limb; after it each half is an
+// independent transform.  Workgroup h of a limb computes the first stage's
+// outputs for half h (reading both halves: the second read is usually served
+// by the cache, its partner reading the same lines at the same time) and
+// then transforms its half of H = N/2 words exactly like ntt_full, with the
+// half's twiddle group offset h.  H/32 threads, LDS exchanges in rounds of at
+// most 8192 words (66 KiB) and at most 128 registers per lane (four waves per
+// SIMD), so two workgroups fit on a CU and one can stream its limb from HBM
+// while the other computes.
+constexpr int kHalfLdsWords = 8192;
+
+template <int LOGN, class A>
+__global__ void __launch_bounds__(1 << (LOGN - 6), 4) ntt_half_fwd(LimbSet ls, const void *__restrict__ tw,
+                                                                const PrimeInfo *__restrict__ pinfo) {
+    using V = typename A::V;
+    constexpr int N = 1 << LOGN, LOGH = LOGN - 1, H = 1 << LOGH, C3 = LOGH - 10;
+    constexpr int G3 = 1 << (5 - C3);
+    constexpr int LW = H > kHalfLdsWords ? kHalfLdsWords : H, NSPLIT = H / LW;
+    constexpr bool SP = NSPLIT == 2;
+    constexpr int BA = C3 - 1, BB = LOGH - 1;  // split bits: thread-id bits in both layouts
+    __shared__ u64 s[LW + LW / 32];
+    const int t = threadIdx.x, h = blockIdx.x & 1, job = blockIdx.x >> 1;
+    int prime;
+    u64 *a = limb_ptr(ls, job, N, prime) + h * H;
+    const u64 *ain = limb_src(ls, job, N);
+    const A ar(tw, pinfo[prime], prime, N);
+    const int x1 = t;                                                // + (k << (LOGH - 5))
+    const int x2 = ((t >> C3) << (C3 + 5)) | (t & ((1 << C3) - 1));  // + (k << C3)
+    const int x3 = t << 5;                                           // + k
+    const int ra = lds_round<SP, BA>(x1), rb = lds_round<SP, BB>(x3);
+    const int pa1 = lds_pos<SP, BA>(x1), pa2 = lds_pos<SP, BA>(x2);
+    const int pb2 = lds_pos<SP, BB>(x2), pb3 = lds_pos<SP, BB>(x3);
+    V v[32];
+
+    // first stage: X +- W[1] Y for this half; then the half's stages
+    const typename A::T w1 = ar.fw(1);
+#pragma unroll
+    for (int k = 0; k < 32; k++) {
+        V X = ar.load(ain[x1 + (k << (LOGH - 5))]), Y = ar.load(ain[H + x1 + (k << (LOGH - 5))]);
+        ar.ct(X, Y, w1);
+        v[k] = h ? Y : X;
+    }
+    fwd_chunk<5>(v, ar, LOGH, LOGH - 5, x1, h, LOGN, false);
+#pragma unroll
+    for (int r = 0; r < NSPLIT; r++) {
+        if (ra == r) {
+#pragma unroll
+            for (int k = 0; k < 32; k++) s[pa1 + lds_pos<SP, BA>(k << (LOGH - 5))] = A::raw(v[k]);
+        }
+        __syncthreads();
+        if (ra == r) {
+#pragma unroll
+            for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa2 + lds_pos<SP, BA>(k << C3)]);
+        }
+        __syncthreads();
+    }
+    fwd_chunk<5>(v, ar, LOGH, C3, x2, h, LOGN, false);
+#pragma unroll
+    for (int r = 0; r < NSPLIT; r++) {
+        if (rb == r) {
+#pragma unroll
+            for (int k = 0; k < 32; k++) s[pb2 + lds_pos<SP, BB>(k << C3)] = A::raw(v[k]);
+        }
+        __syncthreads();
+        if (rb == r) {
+#pragma unroll
+            for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb3 + lds_pos<SP, BB>(k)]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGH, 0, x3 + (j << C3), h, LOGN, false);
+    const int wave = t >> 6, lane = t & 63;
+    store_block(a + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
+}
+
 // Arithmetic of a context's transforms: fp64 when every prime allows it and
 // it is enabled, else the integer butterflies.
 inline bool use_fp(const bc_ctx *c) { return use_fp64(c); }
@@ -518,6 +648,24 @@ bool launch_full_a(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st)
 template <bool INV>
 bool launch_full(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
     return use_fp(c) ? launch_full_a<INV, FpA>(logN, ls, c, st) : launch_full_a<INV, IntA>(logN, ls, c, st);
+}
+
+template <class A>
+bool launch_half_a(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+    const unsigned nblk = (unsigned)(2 * ls.npoly * ls.nlimb);
+#define BC_HALF(L)                                                                                \
+    case L:                                                                                       \
+        ntt_half_fwd<L, A><<<nblk, 1 << (L - 6), 0, st>>>(ls, tw_of(c), c->pinfo);                \
+        return true;
+    switch (logN) {
+        BC_HALF(13) BC_HALF(14) BC_HALF(15)
+        default: return false;
+    }
+#undef BC_HALF
+}
+
+bool launch_half(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+    return use_fp(c) ? launch_half_a<FpA>(logN, ls, c, st) : launch_half_a<IntA>(logN, ls, c, st);
 }
 
 template <bool INV, class A>
@@ -578,6 +726,15 @@ static int polys_per_chunk(const bc_ctx *c, const LimbSet &ls) {
     return (int)std::max<size_t>(1, c->ntt_chunk_bytes / per_poly);
 }
 
+// Polys [p0, p0 + step) of a limb set.
+static LimbSet chunk_of(const LimbSet &ls, int p0, int step) {
+    LimbSet sub = ls;
+    sub.base = ls.base + (size_t)p0 * ls.poly_stride;
+    if (ls.ibase) sub.ibase = ls.ibase + (size_t)p0 * ls.ipoly_stride;
+    sub.npoly = std::min(step, ls.npoly - p0);
+    return sub;
+}
+
 // N1 = 2^floor(logN/2) rows, N2 = 2^ceil(logN/2) columns.
 void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (ls.npoly == 0 || ls.nlimb == 0) return;
@@ -585,6 +742,11 @@ void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     ProfRec r{};
     const bool prof = c->prof->on;
     if (prof) c->prof->begin(kProfNttFwd, ntt_bytes(c, ls), st, r);
+    if (c->ntt_single_pass == 2 && launch_half(c->logN, ls, c, st)) {
+        if (prof) c->prof->end(r, st);
+        BC_HIP(hipGetLastError());
+        return;
+    }
     if (c->ntt_single_pass && launch_full<false>(c->logN, ls, c, st)) {
         if (prof) c->prof->end(r, st);
         BC_HIP(hipGetLastError());
@@ -592,10 +754,9 @@ void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     }
     const int step = polys_per_chunk(c, ls);
     for (int p0 = 0; p0 < ls.npoly; p0 += step) {
-        LimbSet sub = ls;
-        sub.base = ls.base + (size_t)p0 * ls.poly_stride;
-        sub.npoly = std::min(step, ls.npoly - p0);
+        LimbSet sub = chunk_of(ls, p0, step);
         launch_cols<false>(logN1, c->logN, sub, c, st);
+        sub.ibase = nullptr;  // the second pass works in place on the output
         launch_rows<false>(logN2, c->logN, sub, c, st);
     }
     if (prof) c->prof->end(r, st);
@@ -615,10 +776,9 @@ void ntt_inverse(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     }
     const int step = polys_per_chunk(c, ls);
     for (int p0 = 0; p0 < ls.npoly; p0 += step) {
-        LimbSet sub = ls;
-        sub.base = ls.base + (size_t)p0 * ls.poly_stride;
-        sub.npoly = std::min(step, ls.npoly - p0);
+        LimbSet sub = chunk_of(ls, p0, step);
         launch_rows<true>(logN2, c->logN, sub, c, st);
+        sub.ibase = nullptr;  // the second pass works in place on the output
         launch_cols<true>(logN1, c->logN, sub, c, st);
     }
     if (prof) c->prof->end(r, st);

@@ -52,20 +52,30 @@ namespace {
 
 // Transform jobs over a batch; split across launches when too many limbs.
 struct Jobs {
-    std::vector<std::pair<int, int>> l;  // (limb slot, prime)
-    void add(int off, int prime) { l.emplace_back(off, prime); }
+    struct J {
+        int off, prime, ioff;  // output limb slot, prime, input limb slot (out of place)
+    };
+    std::vector<J> l;
+    void add(int off, int prime, int ioff = -1) { l.push_back({off, prime, ioff < 0 ? off : ioff}); }
 };
 
-void run_ntt(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j, bool inverse, hipStream_t st) {
+// Transforms the jobs' limbs of `npoly` polys (stride `stride` words) in
+// place, or, with `in`, reads limb ioff of poly j at in + j * in_stride and
+// writes the result to the output slot.
+void run_ntt(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j, bool inverse, hipStream_t st,
+             const u64 *in = nullptr, size_t in_stride = 0) {
     for (size_t s = 0; s < j.l.size(); s += kMaxJobs) {
         LimbSet ls{};
         ls.base = base;
         ls.poly_stride = stride;
         ls.npoly = npoly;
         ls.nlimb = (int)std::min<size_t>(kMaxJobs, j.l.size() - s);
+        ls.ibase = in;
+        ls.ipoly_stride = in_stride;
         for (int k = 0; k < ls.nlimb; k++) {
-            ls.off[k] = (int16_t)j.l[s + k].first;
-            ls.prime[k] = (int16_t)j.l[s + k].second;
+            ls.off[k] = (int16_t)j.l[s + k].off;
+            ls.prime[k] = (int16_t)j.l[s + k].prime;
+            ls.ioff[k] = (int16_t)j.l[s + k].ioff;
         }
         if (inverse) ntt_inverse(c, ls, st);
         else ntt_forward(c, ls, st);
@@ -90,13 +100,13 @@ void check_hip() { BC_HIP(hipGetLastError()); }
 BufP ks_accumulate(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int count, int level, hipStream_t st) {
     const int N = c->N, nl = level + 1, next = nl + c->nP, dnum = c->dnum;
     const int nact = level / c->alpha + 1;
+    // MU[ct][j][e] holds digit j's new limbs; its own limbs are read from X
     BufP MU = make_buf(c, sizeof(u64) * (size_t)count * dnum * next * N);
     BufP XC = make_buf(c, sizeof(u64) * (size_t)count * nl * N);
     u64 *mu = (u64 *)MU->p, *xc = (u64 *)XC->p;
-    launch_ks_prepare(c, X, x_stride, mu, xc, count, nl, next, st);
-    Jobs jx;
+    Jobs jx;  // coefficient-domain copy of X
     for (int i = 0; i < nl; i++) jx.add(i, i);
-    run_ntt(c, xc, (size_t)nl * N, count, jx, true, st);
+    run_ntt(c, xc, (size_t)nl * N, count, jx, true, st, X, x_stride);
     launch_modup(c, xc, mu, count, level, next, st);
     Jobs jm;
     for (int j = 0; j < nact; j++) {
@@ -106,7 +116,7 @@ BufP ks_accumulate(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int
     run_ntt(c, mu, (size_t)dnum * next * N, count, jm, false, st);
     XC.reset();
     BufP ACC = make_buf(c, sizeof(u64) * (size_t)count * 2 * next * N);
-    launch_ks_inner(c, mu, key, (u64 *)ACC->p, count, level, next, nact, st);
+    launch_ks_inner(c, mu, X, x_stride, key, (u64 *)ACC->p, count, level, next, nact, st);
     return ACC;
 }
 
@@ -169,11 +179,10 @@ void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st) {
     const int N = c->N, lv = in.level, count = in.count;
     BufP TOP = make_buf(c, sizeof(u64) * (size_t)count * 2 * N);
     u64 *top = (u64 *)TOP->p;
-    launch_ms_top(c, in.data, top, count, lv + 1, st);
-    Jobs jt;
-    jt.add(0, lv);
-    jt.add(1, lv);
-    run_ntt(c, top, (size_t)2 * N, count, jt, true, st);
+    Jobs jt;  // the top limb of both components, coefficient domain, into TOP[ct][c]
+    jt.add(0, lv, lv);
+    jt.add(1, lv, (lv + 1) + lv);
+    run_ntt(c, top, (size_t)2 * N, count, jt, true, st, in.data, in.ct_words(N));
     BufP R = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
     u64 *r = (u64 *)R->p;
     launch_ms_fbc(c, top, r, count, lv, st);
@@ -197,8 +206,7 @@ CtB to_level(bc_ctx *c, const CtB &x, int level, hipStream_t st) {
     const int N = c->N, nl = x.level + 1;
     BufP T = make_buf(c, sizeof(u64) * (size_t)x.count * 2 * nl * N);
     u64 *t = (u64 *)T->p;
-    BC_HIP(hipMemcpyAsync(t, x.data, sizeof(u64) * (size_t)x.count * 2 * nl * N, hipMemcpyDeviceToDevice, st));
-    run_ntt(c, t, (size_t)2 * nl * N, x.count, all_limbs(2, nl), true, st);
+    run_ntt(c, t, (size_t)2 * nl * N, x.count, all_limbs(2, nl), true, st, x.data, x.ct_words(N));
     CtB out = alloc_ct(c, x.count, level, 2);
     launch_ms_multi(c, t, out.data, x.count, x.level, level, st);
     run_ntt(c, out.data, out.ct_words(N), out.count, all_limbs(2, level + 1), false, st);
@@ -554,8 +562,8 @@ void export_ct(bc_ctx *c, const CtB &in, u64 *host, hipStream_t st) {
     BC_REQUIRE(host, BC_ERR_ARG, "export: null host buffer");
     const size_t words = (size_t)in.count * in.ct_words(c->N);
     BufP T = make_buf(c, sizeof(u64) * words);
-    BC_HIP(hipMemcpyAsync(T->p, in.data, sizeof(u64) * words, hipMemcpyDeviceToDevice, st));
-    run_ntt(c, (u64 *)T->p, in.ct_words(c->N), in.count, all_limbs(in.ncomp, in.level + 1), true, st);
+    run_ntt(c, (u64 *)T->p, in.ct_words(c->N), in.count, all_limbs(in.ncomp, in.level + 1), true, st, in.data,
+            in.ct_words(c->N));
     check_hip();
     BC_HIP(hipMemcpyAsync(host, T->p, sizeof(u64) * words, hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));

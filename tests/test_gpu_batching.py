@@ -69,14 +69,14 @@ def test_server_results_equal_alone_and_in_the_mix():
 
     members = {1 << 10: member(Params(10, 257, 12, 50, 4, 50, 3), 3),
                1 << 11: member(Params(11, 257, 12, 50, 4, 50, 3), 4)}
-    g = synth.generator(77, "schedule")
+    # (N, groups, kind, arrival s): a burst at t = 0 whose three N = 2^10
+    # requests fit one batch (so coalescing must happen), then later arrivals
+    specs = [(1 << 10, 1, "lt", 0.0), (1 << 11, 2, "max", 0.0), (1 << 10, 1, "argmax", 0.0),
+             (1 << 10, 2, "max", 0.0), (1 << 11, 1, "lt", 0.002), (1 << 11, 3, "argmax", 0.004),
+             (1 << 10, 1, "max", 0.006), (1 << 11, 1, "lt", 0.006), (1 << 10, 3, "lt", 0.008)]
     reqs = []
-    t = 0.0
-    for rid in range(10):
-        N = [1 << 10, 1 << 11][int(g.integers(0, 2))]
+    for rid, (N, groups, kind, t) in enumerate(specs):
         dev, dk = members[N]
-        groups = int(g.integers(1, 4))
-        kind = ["lt", "max", "argmax"][int(g.integers(0, 3))]
         xs = synth.integers(100 + rid, (groups, dev.M), 0, 65536)
         ys = synth.integers(100 + rid, (groups, dev.M), 0, 65536, index=1)
         xs[0, :3] = ys[0, :3]
@@ -84,14 +84,15 @@ def test_server_results_equal_alone_and_in_the_mix():
                             planes(dev, dk, ys, 600 + 10 * rid))
         r.xs, r.ys = xs, ys
         reqs.append(r)
-        t += float(g.exponential(0.004))
-    # a budget of about two groups forces requests to wait for memory
+    # a budget of four of the larger groups: the 3-group N = 2^11 request has
+    # to wait for memory while the first batches are in flight
     bpg = {N: 2 * 40 * 3 * 8 * m[0].ct_words(m[0].nQ - 1) for N, m in members.items()}
-    srv = serving.Server(members, max_batch_groups=4, mem_budget_bytes=2 * max(bpg.values()), streams=2,
+    srv = serving.Server(members, max_batch_groups=4, mem_budget_bytes=4 * max(bpg.values()), streams=2,
                          bytes_per_group=bpg)
     srv.run(reqs)
     assert all(r.done_at is not None for r in reqs)
-    assert srv.stats["batches"] < len(reqs)  # some requests shared a batch
+    assert srv.stats["batches"] < len(reqs)  # the burst's N = 2^10 requests shared a batch
+    assert srv.stats["max_inflight_bytes"] <= 4 * max(bpg.values())
     for r in reqs:
         dev, dk = members[r.N]
         lt, mx, _ = dev.compare_max_min(dk, r.a, r.b, True, r.kind == "max", False)
