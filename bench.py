@@ -219,8 +219,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, copy-calibrated",
-                     "kernel": ("forward NTT, " + {0: "column pass + row pass", 1: "single pass",
-                                                  2: "two workgroups per limb (one per half)"}[tuned["single_pass"]]
+                     "kernel": ("forward NTT, " + ("single pass" if tuned["single_pass"] else "column pass + row pass")
                                 + (", fp64" if tuned.get("fp64") else ", integer") + " arithmetic, 16 N bytes per limb"),
                      "ntt_schedule": tuned,
                      "launches": fwd_n, "avg_launch_us": 1e3 * fwd_ms / max(1, fwd_n),
@@ -250,7 +249,7 @@ def is_forward_ntt(name: str) -> str | None:
     """'a' for the first pass (or the single pass) of a forward transform, 'b' for the second."""
     import re
 
-    m = re.search(r"ntt_(cols|rows|full)<\d+, false>", name)
+    m = re.search(r"ntt_(cols|rows|full)<\d+, false[,>]", name)
     if not m:
         return None
     return "b" if m.group(1) == "rows" else "a"

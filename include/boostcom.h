@@ -209,11 +209,8 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   over at most this many bytes of limbs (0 = no split), so the first pass's
  *   output is still cached when the second pass reads it.
  *   BC_TUNE_NTT_SINGLE_PASS: 1 (default) transforms a whole limb in one
- *   workgroup for N = 2^12 .. 2^15 (each word read and written once); 2 does
- *   the same for the inverse and, for N = 2^13 .. 2^15, runs each forward
- *   transform as two workgroups per limb (one per half after the first
- *   stage, so two fit on a compute unit); 0 uses the two-pass column/row
- *   transform for every N.
+ *   workgroup for N = 2^12 .. 2^15 (each word read and written once); 0 uses
+ *   the two-pass column/row transform for every N.
  *   BC_TUNE_FP64: 1 (default) runs the modular arithmetic of the transforms
  *   and of the base conversions (modulus raising, the fused relinearisation
  *   and modulus switch, multi-prime switching, the polynomial's linear
@@ -225,7 +222,7 @@ enum { BC_TUNE_NTT_CHUNK_BYTES = 0, BC_TUNE_NTT_SINGLE_PASS = 1, BC_TUNE_FP64 = 
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);
 /* Times each transform schedule (two-pass, two-pass in cache-sized chunks,
- * single-pass and half-limb forward where N allows; each with fp64 and integer arithmetic where the
+ * single-pass where N allows; each with fp64 and integer arithmetic where the
  * primes allow fp64) on a synthetic batch of this context's shape
  * (about 384 MB of limbs) and keeps the fastest.  Synchronises the stream;
  * takes a few tens of milliseconds. */

@@ -508,7 +508,7 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
         check_ctx(ctx);
         BC_REQUIRE(value >= 0, BC_ERR_ARG, "tuning value must be non-negative");
         if (key == BC_TUNE_NTT_CHUNK_BYTES) ctx->ntt_chunk_bytes = (size_t)value;
-        else if (key == BC_TUNE_NTT_SINGLE_PASS) ctx->ntt_single_pass = (int)std::min<int64_t>(value, 2);
+        else if (key == BC_TUNE_NTT_SINGLE_PASS) ctx->ntt_single_pass = value != 0;
         else if (key == BC_TUNE_FP64) ctx->fp64 = value != 0;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
@@ -555,7 +555,6 @@ int bc_autotune(bc_ctx *ctx, void *stream) {
             cands.push_back({0, 0, fp});
             cands.push_back({0, (size_t)128 << 20, fp});
             if (ctx->logN >= 12 && ctx->logN <= 15) cands.push_back({1, 0, fp});
-            if (ctx->logN >= 13 && ctx->logN <= 15) cands.push_back({2, 0, fp});
         }
         const bool prof = ctx->prof->on;
         ctx->prof->on = false;

@@ -548,84 +548,6 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const vo
     }
 }
 
-// ------------------------------------------------- forward, two per limb
-// The forward transform's first stage (span N/2, twiddle W[1]) is the only
-// one that mixes the two halves of a limb; after it each half is an
-// independent transform.  Workgroup h of a limb computes the first stage's
-// outputs for half h (reading both halves: the second read is usually served
-// by the cache, its partner reading the same lines at the same time) and
-// then transforms its half of H = N/2 words exactly like ntt_full, with the
-// half's twiddle group offset h.  H/32 threads, LDS exchanges in rounds of at
-// most 8192 words (66 KiB) and at most 128 registers per lane (four waves per
-// SIMD), so two workgroups fit on a CU and one can stream its limb from HBM
-// while the other computes.
-constexpr int kHalfLdsWords = 8192;
-
-template <int LOGN, class A>
-__global__ void __launch_bounds__(1 << (LOGN - 6), 4) ntt_half_fwd(LimbSet ls, const void *__restrict__ tw,
-                                                                const PrimeInfo *__restrict__ pinfo) {
-    using V = typename A::V;
-    constexpr int N = 1 << LOGN, LOGH = LOGN - 1, H = 1 << LOGH, C3 = LOGH - 10;
-    constexpr int G3 = 1 << (5 - C3);
-    constexpr int LW = H > kHalfLdsWords ? kHalfLdsWords : H, NSPLIT = H / LW;
-    constexpr bool SP = NSPLIT == 2;
-    constexpr int BA = C3 - 1, BB = LOGH - 1;  // split bits: thread-id bits in both layouts
-    __shared__ u64 s[LW + LW / 32];
-    const int t = threadIdx.x, h = blockIdx.x & 1, job = blockIdx.x >> 1;
-    int prime;
-    u64 *a = limb_ptr(ls, job, N, prime) + h * H;
-    const u64 *ain = limb_src(ls, job, N);
-    const A ar(tw, pinfo[prime], prime, N);
-    const int x1 = t;                                                // + (k << (LOGH - 5))
-    const int x2 = ((t >> C3) << (C3 + 5)) | (t & ((1 << C3) - 1));  // + (k << C3)
-    const int x3 = t << 5;                                           // + k
-    const int ra = lds_round<SP, BA>(x1), rb = lds_round<SP, BB>(x3);
-    const int pa1 = lds_pos<SP, BA>(x1), pa2 = lds_pos<SP, BA>(x2);
-    const int pb2 = lds_pos<SP, BB>(x2), pb3 = lds_pos<SP, BB>(x3);
-    V v[32];
-
-    // first stage: X +- W[1] Y for this half; then the half's stages
-    const typename A::T w1 = ar.fw(1);
-#pragma unroll
-    for (int k = 0; k < 32; k++) {
-        V X = ar.load(ain[x1 + (k << (LOGH - 5))]), Y = ar.load(ain[H + x1 + (k << (LOGH - 5))]);
-        ar.ct(X, Y, w1);
-        v[k] = h ? Y : X;
-    }
-    fwd_chunk<5>(v, ar, LOGH, LOGH - 5, x1, h, LOGN, false);
-#pragma unroll
-    for (int r = 0; r < NSPLIT; r++) {
-        if (ra == r) {
-#pragma unroll
-            for (int k = 0; k < 32; k++) s[pa1 + lds_pos<SP, BA>(k << (LOGH - 5))] = A::raw(v[k]);
-        }
-        __syncthreads();
-        if (ra == r) {
-#pragma unroll
-            for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa2 + lds_pos<SP, BA>(k << C3)]);
-        }
-        __syncthreads();
-    }
-    fwd_chunk<5>(v, ar, LOGH, C3, x2, h, LOGN, false);
-#pragma unroll
-    for (int r = 0; r < NSPLIT; r++) {
-        if (rb == r) {
-#pragma unroll
-            for (int k = 0; k < 32; k++) s[pb2 + lds_pos<SP, BB>(k << C3)] = A::raw(v[k]);
-        }
-        __syncthreads();
-        if (rb == r) {
-#pragma unroll
-            for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb3 + lds_pos<SP, BB>(k)]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGH, 0, x3 + (j << C3), h, LOGN, false);
-    const int wave = t >> 6, lane = t & 63;
-    store_block(a + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
-}
-
 // Arithmetic of a context's transforms: fp64 when every prime allows it and
 // it is enabled, else the integer butterflies.
 inline bool use_fp(const bc_ctx *c) { return use_fp64(c); }
@@ -648,24 +570,6 @@ bool launch_full_a(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st)
 template <bool INV>
 bool launch_full(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
     return use_fp(c) ? launch_full_a<INV, FpA>(logN, ls, c, st) : launch_full_a<INV, IntA>(logN, ls, c, st);
-}
-
-template <class A>
-bool launch_half_a(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
-    const unsigned nblk = (unsigned)(2 * ls.npoly * ls.nlimb);
-#define BC_HALF(L)                                                                                \
-    case L:                                                                                       \
-        ntt_half_fwd<L, A><<<nblk, 1 << (L - 6), 0, st>>>(ls, tw_of(c), c->pinfo);                \
-        return true;
-    switch (logN) {
-        BC_HALF(13) BC_HALF(14) BC_HALF(15)
-        default: return false;
-    }
-#undef BC_HALF
-}
-
-bool launch_half(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
-    return use_fp(c) ? launch_half_a<FpA>(logN, ls, c, st) : launch_half_a<IntA>(logN, ls, c, st);
 }
 
 template <bool INV, class A>
@@ -742,11 +646,6 @@ void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     ProfRec r{};
     const bool prof = c->prof->on;
     if (prof) c->prof->begin(kProfNttFwd, ntt_bytes(c, ls), st, r);
-    if (c->ntt_single_pass == 2 && launch_half(c->logN, ls, c, st)) {
-        if (prof) c->prof->end(r, st);
-        BC_HIP(hipGetLastError());
-        return;
-    }
     if (c->ntt_single_pass && launch_full<false>(c->logN, ls, c, st)) {
         if (prof) c->prof->end(r, st);
         BC_HIP(hipGetLastError());

@@ -105,3 +105,36 @@ def test_server_results_equal_alone_and_in_the_mix():
             assert np.array_equal(val, np.maximum(r.xs, r.ys))
     summ = serving.latency_summary(reqs)
     assert summ["p99_ms"] >= summ["p50_ms"] > 0
+
+
+def test_mixed_ring_sizes_at_workload_sizes_concurrently():
+    """The three workload chains (N = 2^13, 2^14, 2^15) in one fork/join graph,
+    batches large enough that many workgroups of different members run at
+    once: every member's LT equals its own single-context call, byte for
+    byte, after the eager call and after a replay."""
+    import paper_2407_07308_amd as bc
+
+    chains = {13: Params(13, 257, 8, 50, 4, 50, 2), 14: Params(14, 257, 8, 50, 4, 50, 2),
+              15: Params(15, 257, 14, 50, 5, 50, 3)}
+    members, reqs, truth = [], [], []
+    for L, prm in chains.items():
+        dev, dk = member(prm, 50 + L)
+        dev.autotune()
+        G = 24
+        x = synth.slot_values(60 + L, G, dev.M, 0, 257)
+        y = synth.slot_values(70 + L, G, dev.M, 0, 257)
+        rx, ry = synth.encrypt_randomness(80 + L, G, dev.N), synth.encrypt_randomness(90 + L, G, dev.N)
+        A, B = [dev.encrypt(dk, x, rx["u"], rx["e"])], [dev.encrypt(dk, y, ry["u"], ry["e"])]
+        members.append((dev, dk))
+        reqs.append((dk, A, B))
+        truth.append(((x.astype(np.int64) - y) % 257 >= 129).astype(np.uint32))
+    refs = [dev.compare_lt(dk, A, B) for (dev, dk), (_, A, B) in zip(members, reqs)]
+    grp = bc.Group([m[0] for m in members])
+    outs = grp.compare_max_min(reqs, want_max=False, want_min=False)
+    for rep in range(2):
+        for (dev, dk), o, ref, t in zip(members, outs, refs, truth):
+            assert same(dev, o[0], ref), f"N = {dev.N}, pass {rep}"
+            assert np.array_equal(dev.decrypt(dk, o[0]), t)
+        for o in outs:
+            o[0].tensor.zero_()
+        grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)  # replay
