@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -197,6 +198,22 @@ struct GarnerTable {
     u64 qprod_p[kMaxMod];          // prod_{j <= i} q_j mod p
 };
 
+// Final step of relinearisation fused with a modulus switch, applied by the
+// forward transform of E as it stores (NTT domain, limbs i < level):
+//   out_i = (d_i + acc_i P^-1) q_l^-1 - E_i
+// E is [count][2][level][N]; d and acc are the tensor product (stride
+// d_ct_stride, limbs [c][level+1]) and the key-switch accumulator
+// ([count][2][next]).  w[i] holds q_l^-1 and P^-1 q_l^-1 mod q_i as two pairs
+// of the transform's arithmetic (Shoup pairs, or (w, w/q) doubles).
+struct RelinMsCombine {
+    const u64 *d;
+    u64 d_ct_stride;
+    const u64 *acc;
+    u64 *out;
+    int level, next;
+    u64 w[kMaxMod][4];
+};
+
 // ------------------------------------------------------------ workspace pool
 
 // Caching device allocator.  A released block is handed out again only for
@@ -223,7 +240,7 @@ struct Pool {
 
 // --------------------------------------------------------------- profiling
 // Optional HIP-event bracketing of kernel launches on their own stream.
-enum ProfKind { kProfNttFwd = 0, kProfNttInv = 1, kProfKinds = 2 };
+enum ProfKind { kProfNttFwd = 0, kProfNttInv = 1, kProfNttFwdRelinMs = 2, kProfKinds = 3 };
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
@@ -317,10 +334,22 @@ u64 h_mulmod(u64 a, u64 b, u64 q);
 u64 h_powmod(u64 b, u64 e, u64 q);
 u64 h_invmod(u64 a, u64 q);
 inline u64 h_shoup(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+// (w, w/q) as doubles in the two words of a pair (fp64 arithmetic, q < 2^50;
+// the quotient is correctly rounded)
+inline void h_fpair(u64 dst[2], u64 w, u64 q) {
+    const double wd = (double)(w % q), r = wd / (double)q;
+    std::memcpy(&dst[0], &wd, sizeof(double));
+    std::memcpy(&dst[1], &r, sizeof(double));
+}
 int bit_reverse(int x, int bits);
 
 // ----------------------------------------------------------------- kernels
 void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
 void ntt_inverse(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
+// Forward transform of E with the relinearise + switch combination as its
+// epilogue (E itself is not written back).  Returns false, launching nothing,
+// when the context's transform schedule has no such kernel; the caller then
+// transforms E and combines separately (same result).
+bool ntt_forward_relin_ms(const bc_ctx *c, const LimbSet &ls, const RelinMsCombine &cb, hipStream_t st);
 
 }  // namespace bc

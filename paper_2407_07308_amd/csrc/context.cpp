@@ -114,13 +114,7 @@ void set_shoup(u64 dst[2], u64 w, u64 q) {
     dst[1] = h_shoup(dst[0], q);
 }
 
-// (w, w/q) as doubles in the two words of a pair (fp64 arithmetic, q < 2^50;
-// the quotient is correctly rounded)
-void set_fpair(u64 dst[2], u64 w, u64 q) {
-    const double wd = (double)(w % q), r = wd / (double)q;
-    std::memcpy(&dst[0], &wd, sizeof(double));
-    std::memcpy(&dst[1], &r, sizeof(double));
-}
+void set_fpair(u64 dst[2], u64 w, u64 q) { h_fpair(dst, w, q); }
 
 typedef void (*PairSet)(u64 dst[2], u64 w, u64 q);
 

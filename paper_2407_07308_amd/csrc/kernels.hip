@@ -147,24 +147,44 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
 }
 
 // ACC[ct][c][e] = sum_j MU[ct][j][e] * K_j,c[prime(e)]   (NTT domain), where
-// digit j's own limbs (e in [j alpha, (j+1) alpha)) are X's limbs themselves
+// digit j's own limbs (e in [j alpha, (j+1) alpha)) are X's limbs themselves.
+// A thread takes kKsCts consecutive ciphertexts: each key word is read once
+// for all of them, and every load is issued before the arithmetic.
+constexpr int kKsCts = 2;
 __global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ x, size_t x_ct_stride,
                            const u64 *__restrict__ key, u64 *__restrict__ acc, int level, int nQ, int nmod, int next,
-                           int nact, int dnum, int alpha, const PrimeInfo *__restrict__ pinfo, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, e = blockIdx.y, ct = blockIdx.z;
+                           int nact, int dnum, int alpha, int count, const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = blockIdx.x * kT + threadIdx.x, e = blockIdx.y, ct0 = blockIdx.z * kKsCts;
     const int prime = ext_prime(e, level, nQ);
     const Barrett br = pinfo[prime].br;
     const int own = e <= level ? e / alpha : -1;
-    u64 s0 = 0, s1 = 0;
+    u64 s0[kKsCts], s1[kKsCts];
+#pragma unroll
+    for (int c = 0; c < kKsCts; c++) s0[c] = s1[c] = 0;
     for (int j = 0; j < nact; j++) {
-        u64 u = j == own ? x[(size_t)ct * x_ct_stride + (size_t)e * N + n]
-                         : mu[(((size_t)ct * dnum + j) * next + e) * N + n];
         const u64 *K = key + ((size_t)j * 2 * nmod + prime) * N + n;
-        s0 = add_mod(s0, mul_mod(u, K[0], br), br.q);
-        s1 = add_mod(s1, mul_mod(u, K[(size_t)nmod * N], br), br.q);
+        const u64 k0 = K[0], k1 = K[(size_t)nmod * N];
+        u64 u[kKsCts];
+#pragma unroll
+        for (int c = 0; c < kKsCts; c++) {
+            const int ct = min(ct0 + c, count - 1);  // a tail thread repeats the last ciphertext
+            u[c] = j == own ? x[(size_t)ct * x_ct_stride + (size_t)e * N + n]
+                            : mu[(((size_t)ct * dnum + j) * next + e) * N + n];
+        }
+#pragma unroll
+        for (int c = 0; c < kKsCts; c++) {
+            s0[c] = add_mod(s0[c], mul_mod(u[c], k0, br), br.q);
+            s1[c] = add_mod(s1[c], mul_mod(u[c], k1, br), br.q);
+        }
     }
-    acc[(((size_t)ct * 2 + 0) * next + e) * N + n] = s0;
-    acc[(((size_t)ct * 2 + 1) * next + e) * N + n] = s1;
+#pragma unroll
+    for (int c = 0; c < kKsCts; c++) {
+        const int ct = ct0 + c;
+        if (ct < count) {
+            acc[(((size_t)ct * 2 + 0) * next + e) * N + n] = s0[c];
+            acc[(((size_t)ct * 2 + 1) * next + e) * N + n] = s1[c];
+        }
+    }
 }
 
 // Exact division by P, conversion part (z-grid = ct * 2 + c):
@@ -644,8 +664,8 @@ void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level,
 }
 void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_stride, const u64 *key, u64 *acc,
                      int count, int level, int next, int nact, hipStream_t st) {
-    k_ks_inner<<<grid3(c->N, next, count), kT, 0, st>>>(mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact,
-                                                        c->dnum, c->alpha, c->pinfo, c->N);
+    k_ks_inner<<<grid3(c->N, next, (count + kKsCts - 1) / kKsCts), kT, 0, st>>>(
+        mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum, c->alpha, count, c->pinfo, c->N);
 }
 void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, hipStream_t st) {
     k_moddown<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(acc, th, c->moddown, c->pinfo, level, c->nQ, c->nP, next, c->N);

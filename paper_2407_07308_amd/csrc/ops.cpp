@@ -140,8 +140,44 @@ void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out
     run_ntt(c, t3.data, 3 * L, count, jd, true, st);
     BufP E = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
     launch_relin_ms_fbc(c, acc, t3.data, 3 * L, (u64 *)E->p, count, lv, next, st);
-    run_ntt(c, (u64 *)E->p, (size_t)2 * lv * N, count, all_limbs(2, lv), false, st);
-    launch_relin_ms_combine(c, t3.data, 3 * L, acc, (u64 *)E->p, out.data, count, lv, next, st);
+    // out = (d + acc P^-1) q_l^-1 - NTT(E): fused into E's transform where the
+    // schedule has such a kernel, else transform and combine separately
+    RelinMsCombine cb{};
+    cb.d = t3.data;
+    cb.d_ct_stride = 3 * L;
+    cb.acc = acc;
+    cb.out = out.data;
+    cb.level = lv;
+    cb.next = next;
+    const u64 ql = c->mod[lv];
+    for (int i = 0; i < lv; i++) {
+        const u64 q = c->mod[i];
+        u64 P = 1;
+        for (int t = 0; t < c->nP; t++) P = h_mulmod(P, c->mod[c->nQ + t] % q, q);
+        const u64 qlinv = h_invmod(ql % q, q), pq = h_mulmod(h_invmod(P, q), qlinv, q);
+        if (use_fp64(c)) {
+            h_fpair(cb.w[i], qlinv, q);
+            h_fpair(cb.w[i] + 2, pq, q);
+        } else {
+            cb.w[i][0] = qlinv;
+            cb.w[i][1] = h_shoup(qlinv, q);
+            cb.w[i][2] = pq;
+            cb.w[i][3] = h_shoup(pq, q);
+        }
+    }
+    LimbSet ls{};
+    ls.base = (u64 *)E->p;
+    ls.poly_stride = (u64)2 * lv * N;
+    ls.npoly = count;
+    ls.nlimb = 2 * lv;
+    for (int k = 0; k < 2 * lv; k++) {
+        ls.off[k] = (int16_t)k;
+        ls.prime[k] = (int16_t)(k % lv);
+    }
+    if (!ntt_forward_relin_ms(c, ls, cb, st)) {
+        run_ntt(c, (u64 *)E->p, (size_t)2 * lv * N, count, all_limbs(2, lv), false, st);
+        launch_relin_ms_combine(c, t3.data, 3 * L, acc, (u64 *)E->p, out.data, count, lv, next, st);
+    }
     check_hip();
 }
 
