@@ -233,12 +233,13 @@ int bc_autotune(bc_ctx *ctx, void *stream);
  * with HIP events recorded on the stream it runs on.  bc_profile_read sums,
  * for one kind, the event-measured time (ms), the number of bracketed launch
  * pairs and their algorithmic HBM bytes (every limb read and written once:
- * 16 N bytes per limb).  BC_PROF_NTT_FWD_RELIN_MS counts the forward
- * transforms that also apply the last step of a multiplication's
- * relinearisation and modulus switch as they store (32 N bytes per limb:
- * the limb, two operand limbs and the output limb).  Reading synchronises on
- * the recorded events; enabling (or disabling) clears earlier records. */
-enum { BC_PROF_NTT_FWD = 0, BC_PROF_NTT_INV = 1, BC_PROF_NTT_FWD_RELIN_MS = 2 };
+ * 16 N bytes per limb).  BC_PROF_NTT_FWD_COMBINE counts the forward
+ * transforms that also apply the last step of a multiplication
+ * (relinearisation and modulus switch) or of a modulus switch as they store
+ * (32 N resp. 24 N bytes per limb: the limb, the operand limbs and the output
+ * limb).  Reading synchronises on the recorded events; enabling (or
+ * disabling) clears earlier records. */
+enum { BC_PROF_NTT_FWD = 0, BC_PROF_NTT_INV = 1, BC_PROF_NTT_FWD_COMBINE = 2 };
 int bc_profile_enable(bc_ctx *ctx, int32_t on);
 int bc_profile_read(bc_ctx *ctx, int32_t kind, double *ms, int64_t *launches, double *bytes);
 

@@ -162,7 +162,8 @@ struct PrimeInfo {
     // fp64 transform arithmetic (q < 2^50): q, 1/q, and N^-1, N^-1 * Winv[1]
     // each with its ratio to q
     double qd, qinv, ninv_d, ninv_q, ninvw1_d, ninvw1_q;
-    u64 p_f[2];  // p mod q as an FPair (fp64 base conversions)
+    u64 p_f[2];      // p mod q as an FPair (fp64 base conversions)
+    u64 two25_f[2];  // 2^25 mod q as an FPair (small-coefficient linear combinations)
 };
 
 // Fast base conversion from one digit at one level (modulus raising).
@@ -198,14 +199,18 @@ struct GarnerTable {
     u64 qprod_p[kMaxMod];          // prod_{j <= i} q_j mod p
 };
 
-// Final step of relinearisation fused with a modulus switch, applied by the
-// forward transform of E as it stores (NTT domain, limbs i < level):
-//   out_i = (d_i + acc_i P^-1) q_l^-1 - E_i
-// E is [count][2][level][N]; d and acc are the tensor product (stride
-// d_ct_stride, limbs [c][level+1]) and the key-switch accumulator
-// ([count][2][next]).  w[i] holds q_l^-1 and P^-1 q_l^-1 mod q_i as two pairs
-// of the transform's arithmetic (Shoup pairs, or (w, w/q) doubles).
-struct RelinMsCombine {
+// Final step of a multiplication or of a modulus switch, applied by the
+// forward transform of a correction E ([count][2][level][N], coefficient
+// domain in, transformed) as it stores, limbs i < level of both components:
+//   kNttRelinMs:  out_i = d_i w0_i + acc_i w1_i - E_i   (relinearise + switch:
+//                 w0 = q_l^-1, w1 = P^-1 q_l^-1, acc the key-switch accumulator)
+//   kNttSwitch:   out_i = (d_i - E_i) w0_i               (switch: w0 = q_l^-1)
+// d has level + 1 limbs per component (stride d_ct_stride per ciphertext);
+// acc is [count][2][next][N].  w[i] holds the constants mod q_i as pairs of
+// the transform's arithmetic (Shoup pairs, or (w, w/q) doubles).
+enum { kNttRelinMs = 1, kNttSwitch = 2 };
+struct NttCombine {
+    int mode;
     const u64 *d;
     u64 d_ct_stride;
     const u64 *acc;
@@ -240,7 +245,7 @@ struct Pool {
 
 // --------------------------------------------------------------- profiling
 // Optional HIP-event bracketing of kernel launches on their own stream.
-enum ProfKind { kProfNttFwd = 0, kProfNttInv = 1, kProfNttFwdRelinMs = 2, kProfKinds = 3 };
+enum ProfKind { kProfNttFwd = 0, kProfNttInv = 1, kProfNttFwdCombine = 2, kProfKinds = 3 };
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
@@ -304,7 +309,7 @@ struct bc_ctx {
     std::unique_ptr<bc::Profiler> prof{new bc::Profiler()};
     std::mutex table_mu;                       // guards lt_c and ps_coef
     std::vector<int64_t> lt_c;                 // LT polynomial coefficients
-    std::map<int, bc::u64 *> ps_coef;          // key 2 level + fp64: block coefficient pairs
+    std::map<int, bc::u64 *> ps_coef;          // block coefficients: per level (pairs), -1 (small ints)
     ~bc_ctx();
 };
 
@@ -312,6 +317,9 @@ namespace bc {
 // fp64 arithmetic for the transforms and the base conversions: every prime
 // below 2^50 (the fp64 tables exist) and not switched off
 inline bool use_fp64(const bc_ctx *c) { return c->fp64 && c->twf != nullptr; }
+// the polynomial's linear combinations with its small centred coefficients
+// as fp64 integers (|c| < p/2 < 2^19 keeps every partial sum exact)
+inline bool lincomb_small(const bc_ctx *c) { return use_fp64(c) && c->p < ((u64)1 << 20); }
 }  // namespace bc
 
 struct bc_keys {
@@ -346,10 +354,10 @@ int bit_reverse(int x, int bits);
 // ----------------------------------------------------------------- kernels
 void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
 void ntt_inverse(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
-// Forward transform of E with the relinearise + switch combination as its
-// epilogue (E itself is not written back).  Returns false, launching nothing,
-// when the context's transform schedule has no such kernel; the caller then
-// transforms E and combines separately (same result).
-bool ntt_forward_relin_ms(const bc_ctx *c, const LimbSet &ls, const RelinMsCombine &cb, hipStream_t st);
+// Forward transform of E with the NttCombine step as its epilogue (E itself
+// is not written back).  Returns false, launching nothing, when the context's
+// transform schedule has no such kernel; the caller then transforms E and
+// combines separately (same result).
+bool ntt_forward_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &cb, hipStream_t st);
 
 }  // namespace bc

@@ -122,32 +122,40 @@ struct DevEval {
     V blocks(const std::vector<V> &babies, int b, int nblk);
 };
 
+// Linear-combination coefficients of the Paterson-Stockmeyer blocks, centred
+// in (-p/2, p/2].  With fp64 arithmetic (and p small enough, see k_lincomb)
+// they are one table of doubles [nblk][nbaby], the same for every prime;
+// otherwise Shoup pairs [nblk][nbaby][nl][2] of their residues mod q_i.
 const u64 *ps_coef_table(bc_ctx *c, int level, int b, int nblk) {
     std::lock_guard<std::mutex> g(c->table_mu);
-    const bool fp = use_fp64(c);
-    const int key = 2 * level + (fp ? 1 : 0);
+    const bool small = lincomb_small(c);
+    const int key = small ? -1 : level;
     auto it = c->ps_coef.find(key);
     if (it != c->ps_coef.end()) return it->second;
     if (c->lt_c.empty()) c->lt_c = lt_coefficients(c->p);
     const int nbaby = b / 2, nl = level + 1;
-    std::vector<u64> tab((size_t)nblk * nbaby * nl * 2);
-    for (int t = 0; t < nblk; t++)
-        for (int kk = 0; kk < nbaby; kk++) {
-            int64_t cv = centred(c, c->lt_c[(size_t)t * b + 2 * kk + 1]);
-            for (int i = 0; i < nl; i++) {
-                u64 q = c->mod[i];
-                u64 r = cv >= 0 ? (u64)cv % q : q - (u64)(-cv) % q;
-                u64 *w = &tab[(((size_t)t * nbaby + kk) * nl + i) * 2];
-                if (fp) {
-                    const double wd = (double)(r % q), wq = wd / (double)q;
-                    std::memcpy(&w[0], &wd, sizeof(double));
-                    std::memcpy(&w[1], &wq, sizeof(double));
-                } else {
+    std::vector<u64> tab;
+    if (small) {
+        tab.resize((size_t)nblk * nbaby);
+        for (int t = 0; t < nblk; t++)
+            for (int kk = 0; kk < nbaby; kk++) {
+                const double cv = (double)centred(c, c->lt_c[(size_t)t * b + 2 * kk + 1]);
+                std::memcpy(&tab[(size_t)t * nbaby + kk], &cv, sizeof(double));
+            }
+    } else {
+        tab.resize((size_t)nblk * nbaby * nl * 2);
+        for (int t = 0; t < nblk; t++)
+            for (int kk = 0; kk < nbaby; kk++) {
+                int64_t cv = centred(c, c->lt_c[(size_t)t * b + 2 * kk + 1]);
+                for (int i = 0; i < nl; i++) {
+                    u64 q = c->mod[i];
+                    u64 r = cv >= 0 ? (u64)cv % q : q - (u64)(-cv) % q;
+                    u64 *w = &tab[(((size_t)t * nbaby + kk) * nl + i) * 2];
                     w[0] = r % q;
                     w[1] = h_shoup(w[0], q);
                 }
             }
-        }
+    }
     u64 *d = nullptr;
     BC_HIP(hipMalloc(&d, sizeof(u64) * tab.size()));
     BC_HIP(hipMemcpy(d, tab.data(), sizeof(u64) * tab.size(), hipMemcpyHostToDevice));

@@ -397,6 +397,7 @@ void build_context(bc_ctx *c, const bc_params &prm) {
         pi.ninvw1_d = (double)pi.ninvw1;
         pi.ninvw1_q = pi.ninvw1_d / pi.qd;
         set_fpair(pi.p_f, c->p, q);
+        set_fpair(pi.two25_f, (u64)1 << 25, q);
     }
     c->tw = upload(tw.data(), tw.size());
     if (*std::max_element(c->mod.begin(), c->mod.end()) < ((u64)1 << 50)) {

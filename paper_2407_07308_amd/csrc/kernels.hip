@@ -564,9 +564,13 @@ __global__ void k_crt_decode(const u64 *__restrict__ d, uint32_t *__restrict__ o
 }
 
 // Paterson-Stockmeyer blocks: H[pos(t)][ct] = sum_k coef[t][k] * baby_k[ct]
-// (NTT domain, every baby at the same level).  coef holds pairs
-// [nblk][nbaby][nl][2] of the centred coefficients reduced mod q_i: Shoup
-// pairs for the integer kernel, FPairs for the fp64 one.
+// (NTT domain, every baby at the same level).  Integer kernel: coef holds
+// Shoup pairs [nblk][nbaby][nl][2] of the centred coefficients mod q_i.
+// fp64 kernel: coef holds the centred coefficients themselves as doubles
+// [nblk][nbaby] (|c| < p/2 < 2^19): each baby word v < 2^50 is split as
+// v = h 2^25 + l, the sums of c h and of c l stay below 16 2^19 2^25 = 2^48
+// (exact in fp64 fused multiply-adds), and the result is
+// (sum c h) (2^25 mod q) + sum c l reduced once.
 struct BabyArg {
     const u64 *baby[16];
     int pos[64];  // storage position of block t
@@ -600,22 +604,27 @@ __global__ void k_lincomb(BabyArg ba, const u64 *__restrict__ coef, u64 *__restr
             }
         } else {
 #pragma clang fp contract(off)
-            double v[16];
+            const double *cf = reinterpret_cast<const double *>(coef);
+            double hi[16], lo[16];
 #pragma unroll
             for (int k = 0; k < 16; k++) {
                 if (k >= nbaby) break;
-                v[k] = f_load(ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n]);
+                const double v = f_load(ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n]);
+                hi[k] = __builtin_floor(v * 0x1p-25);
+                lo[k] = __builtin_fma(-hi[k], 0x1p25, v);
             }
+            const FPair p25 = fpair(pi.two25_f);
             for (int t = 0; t < nblk; t++) {
-                double acc = 0.0;
+                double sh = 0.0, sl = 0.0;
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
                     if (k >= nbaby) break;
-                    acc += f_mulmod(v[k], fpair(coef + (((size_t)t * nbaby + k) * nl + i) * 2), pi.qd);
-                    if ((k & 7) == 7) acc = f_reduce(acc, pi.qd, pi.qinv);
+                    const double w = cf[t * nbaby + k];
+                    sh = __builtin_fma(w, hi[k], sh);
+                    sl = __builtin_fma(w, lo[k], sl);
                 }
                 out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] =
-                    f_bits(f_canon(acc, pi.qd, pi.qinv));
+                    f_bits(f_canon(f_mulmod(sh, p25, pi.qd) + sl, pi.qd, pi.qinv));
             }
         }
     }
@@ -749,7 +758,7 @@ void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *pos, c
     BabyArg ba{};
     for (int k = 0; k < nbaby; k++) ba.baby[k] = babies[k];
     for (int t = 0; t < nblk; t++) ba.pos[t] = pos[t];
-    if (use_fp64(c))
+    if (lincomb_small(c))
         k_lincomb<true><<<grid3(c->N, nl, nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo,
                                                                 c->N);
     else

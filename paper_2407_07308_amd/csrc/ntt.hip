@@ -103,10 +103,11 @@ struct IntA {
         Y = shoup_lazy(d, ninvw1, ninvw1p, q);
     }
     __device__ static T pair(const u64 *p) { return {p[0], p[1]}; }
-    // d w0 + a w1 - e, canonical words in and out
+    // d w0 + a w1 - e and (d - e) w0, canonical words in and out
     __device__ u64 combine(u64 d, u64 a, u64 e, T w0, T w1) const {
         return sub_mod(add_mod(shoup(d, w0.w, w0.wp, q), shoup(a, w1.w, w1.wp, q), q), e, q);
     }
+    __device__ u64 switch_(u64 d, u64 e, T w0) const { return shoup(sub_mod(d, e, q), w0.w, w0.wp, q); }
 };
 
 struct FpA {
@@ -163,6 +164,10 @@ struct FpA {
 #pragma clang fp contract(off)
         double r = mulmod(f_load(d), w0.w, w0.wq) + mulmod(f_load(a), w1.w, w1.wq) - f_load(e);
         return store(r);
+    }
+    __device__ u64 switch_(u64 d, u64 e, T w0) const {
+#pragma clang fp contract(off)
+        return store(mulmod(f_load(d) - f_load(e), w0.w, w0.wq));
     }
 };
 
@@ -424,8 +429,8 @@ __host__ __device__ constexpr int lds_round(int x) {
 // wave and no workgroup barrier: only the wave touches its tile.
 constexpr int kTileRow = 65;
 
-// Epilogue of a forward transform of one E limb (RelinMsCombine): the limb's
-// d, acc and out words and its two constants.
+// Epilogue of a forward transform of one E limb (NttCombine): the limb's d,
+// acc and out words and its constants.
 template <class A>
 struct McLimb {
     const u64 *d, *acc;
@@ -433,7 +438,7 @@ struct McLimb {
     typename A::T w0, w1;
 };
 
-template <class A, bool EPI = false>
+template <class A, int EPI = 0>
 __device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, const A &ar, u64 *tile, int lane,
                                             const McLimb<A> *mc = nullptr, int boff = 0) {
 #pragma unroll
@@ -446,12 +451,16 @@ __device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, co
         for (int j = 0; j < 8; j++) {
             const int sl = 8 * j + (lane >> 3), wi = sl * 32 + 16 * r + 2 * p;
             U64x2 w{tile[(2 * p) * kTileRow + sl], tile[(2 * p + 1) * kTileRow + sl]};
-            if constexpr (EPI) {
+            if constexpr (EPI == kNttRelinMs) {
                 const int x = boff + wi;  // word of the limb
                 const U64x2 dv = *reinterpret_cast<const U64x2 *>(mc->d + x);
                 const U64x2 av = *reinterpret_cast<const U64x2 *>(mc->acc + x);
                 *reinterpret_cast<U64x2 *>(mc->out + x) =
                     U64x2{ar.combine(dv.a, av.a, w.a, mc->w0, mc->w1), ar.combine(dv.b, av.b, w.b, mc->w0, mc->w1)};
+            } else if constexpr (EPI == kNttSwitch) {
+                const int x = boff + wi;
+                const U64x2 dv = *reinterpret_cast<const U64x2 *>(mc->d + x);
+                *reinterpret_cast<U64x2 *>(mc->out + x) = U64x2{ar.switch_(dv.a, w.a, mc->w0), ar.switch_(dv.b, w.b, mc->w0)};
             } else {
                 *reinterpret_cast<U64x2 *>(blk + wi) = w;
             }
@@ -479,9 +488,9 @@ __device__ __forceinline__ void load_block(const u64 *blk, typename A::V *v, con
     }
 }
 
-template <int LOGN, bool INV, class A, bool EPI>
+template <int LOGN, bool INV, class A, int EPI>
 __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__restrict__ tw,
-                                              const PrimeInfo *__restrict__ pinfo, const RelinMsCombine *cb) {
+                                              const PrimeInfo *__restrict__ pinfo, const NttCombine *cb) {
     using V = typename A::V;
     constexpr int N = 1 << LOGN, C3 = LOGN - 10, NSPLIT = N > kSplitWords ? 2 : 1;
     constexpr int G3 = 1 << (5 - C3);  // chunk-3 groups per thread
@@ -539,16 +548,16 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
         for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), 0, LOGN, false);
         // the exchange above ended with a barrier: LDS is free for the wave tiles
         const int wave = t >> 6, lane = t & 63;
-        if constexpr (EPI) {
+        if constexpr (EPI != 0) {
             const int k = blockIdx.x / ls.npoly, ct = blockIdx.x - k * ls.npoly;
             const int cc = ls.off[k] / cb->level, i = ls.off[k] - cc * cb->level;
             McLimb<A> mc;
             mc.d = cb->d + (size_t)ct * cb->d_ct_stride + ((size_t)cc * (cb->level + 1) + i) * N;
-            mc.acc = cb->acc + (((size_t)ct * 2 + cc) * cb->next + i) * N;
+            mc.acc = EPI == kNttRelinMs ? cb->acc + (((size_t)ct * 2 + cc) * cb->next + i) * N : nullptr;
             mc.out = cb->out + (((size_t)ct * 2 + cc) * cb->level + i) * N;
             mc.w0 = A::pair(cb->w[i]);
             mc.w1 = A::pair(cb->w[i] + 2);
-            store_block<A, true>(nullptr, v, ar, s + wave * 16 * kTileRow, lane, &mc, wave << 11);
+            store_block<A, EPI>(nullptr, v, ar, s + wave * 16 * kTileRow, lane, &mc, wave << 11);
         } else {
             store_block(a + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
         }
@@ -594,16 +603,16 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
 template <int LOGN, bool INV, class A>
 __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const void *__restrict__ tw,
                                                             const PrimeInfo *__restrict__ pinfo) {
-    ntt_full_body<LOGN, INV, A, false>(ls, tw, pinfo, nullptr);
+    ntt_full_body<LOGN, INV, A, 0>(ls, tw, pinfo, nullptr);
 }
 
-// forward transform of E limbs with the relinearise + switch combination as
-// the store (out gets the combination; E is not written back)
-template <int LOGN, class A>
-__global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full_relin_ms(LimbSet ls, const void *__restrict__ tw,
-                                                                     const PrimeInfo *__restrict__ pinfo,
-                                                                     RelinMsCombine cb) {
-    ntt_full_body<LOGN, false, A, true>(ls, tw, pinfo, &cb);
+// forward transform of E limbs with an NttCombine step as the store (out
+// gets the combination; E is not written back)
+template <int LOGN, class A, int EPI>
+__global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full_combine(LimbSet ls, const void *__restrict__ tw,
+                                                                    const PrimeInfo *__restrict__ pinfo,
+                                                                    NttCombine cb) {
+    ntt_full_body<LOGN, false, A, EPI>(ls, tw, pinfo, &cb);
 }
 
 // Arithmetic of a context's transforms: fp64 when every prime allows it and
@@ -742,30 +751,38 @@ void ntt_inverse(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     BC_HIP(hipGetLastError());
 }
 
-template <class A>
-static bool launch_full_relin_ms(int logN, const LimbSet &ls, const RelinMsCombine &cb, const bc_ctx *c,
-                                 hipStream_t st) {
+template <class A, int EPI>
+static bool launch_full_combine(int logN, const LimbSet &ls, const NttCombine &cb, const bc_ctx *c, hipStream_t st) {
     const unsigned njobs = (unsigned)(ls.npoly * ls.nlimb);
-#define BC_FULL_MS(L)                                                                             \
+#define BC_FULL_CB(L)                                                                             \
     case L:                                                                                       \
-        ntt_full_relin_ms<L, A><<<njobs, 1 << (L - 5), 0, st>>>(ls, tw_of(c), c->pinfo, cb);      \
+        ntt_full_combine<L, A, EPI><<<njobs, 1 << (L - 5), 0, st>>>(ls, tw_of(c), c->pinfo, cb);  \
         return true;
     switch (logN) {
-        BC_FULL_MS(12) BC_FULL_MS(13) BC_FULL_MS(14) BC_FULL_MS(15)
+        BC_FULL_CB(12) BC_FULL_CB(13) BC_FULL_CB(14) BC_FULL_CB(15)
         default: return false;
     }
-#undef BC_FULL_MS
+#undef BC_FULL_CB
 }
 
-bool ntt_forward_relin_ms(const bc_ctx *c, const LimbSet &ls, const RelinMsCombine &cb, hipStream_t st) {
+template <class A>
+static bool launch_full_combine_a(int logN, const LimbSet &ls, const NttCombine &cb, const bc_ctx *c,
+                                  hipStream_t st) {
+    return cb.mode == kNttRelinMs ? launch_full_combine<A, kNttRelinMs>(logN, ls, cb, c, st)
+                                  : launch_full_combine<A, kNttSwitch>(logN, ls, cb, c, st);
+}
+
+bool ntt_forward_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &cb, hipStream_t st) {
     if (!c->ntt_single_pass || c->logN < 12 || c->logN > 15) return false;
+    if (cb.mode != kNttRelinMs && cb.mode != kNttSwitch) throw Error(BC_ERR_ARG, "ntt: unknown combine step");
     if (ls.npoly == 0 || ls.nlimb == 0) return true;
     ProfRec r{};
     const bool prof = c->prof->on;
-    // E read, d and acc read, out written
-    if (prof) c->prof->begin(kProfNttFwdRelinMs, 32.0 * c->N * ls.npoly * ls.nlimb, st, r);
-    const bool ok = use_fp(c) ? launch_full_relin_ms<FpA>(c->logN, ls, cb, c, st)
-                              : launch_full_relin_ms<IntA>(c->logN, ls, cb, c, st);
+    // E read and out written, d (and acc) read
+    const double per_limb = (cb.mode == kNttRelinMs ? 32.0 : 24.0) * c->N;
+    if (prof) c->prof->begin(kProfNttFwdCombine, per_limb * ls.npoly * ls.nlimb, st, r);
+    const bool ok = use_fp(c) ? launch_full_combine_a<FpA>(c->logN, ls, cb, c, st)
+                              : launch_full_combine_a<IntA>(c->logN, ls, cb, c, st);
     if (prof) c->prof->end(r, st);
     BC_HIP(hipGetLastError());
     return ok;

@@ -142,7 +142,8 @@ void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out
     launch_relin_ms_fbc(c, acc, t3.data, 3 * L, (u64 *)E->p, count, lv, next, st);
     // out = (d + acc P^-1) q_l^-1 - NTT(E): fused into E's transform where the
     // schedule has such a kernel, else transform and combine separately
-    RelinMsCombine cb{};
+    NttCombine cb{};
+    cb.mode = kNttRelinMs;
     cb.d = t3.data;
     cb.d_ct_stride = 3 * L;
     cb.acc = acc;
@@ -174,7 +175,7 @@ void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out
         ls.off[k] = (int16_t)k;
         ls.prime[k] = (int16_t)(k % lv);
     }
-    if (!ntt_forward_relin_ms(c, ls, cb, st)) {
+    if (!ntt_forward_combine(c, ls, cb, st)) {
         run_ntt(c, (u64 *)E->p, (size_t)2 * lv * N, count, all_limbs(2, lv), false, st);
         launch_relin_ms_combine(c, t3.data, 3 * L, acc, (u64 *)E->p, out.data, count, lv, next, st);
     }
@@ -222,8 +223,37 @@ void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st) {
     BufP R = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
     u64 *r = (u64 *)R->p;
     launch_ms_fbc(c, top, r, count, lv, st);
-    run_ntt(c, r, (size_t)2 * lv * N, count, all_limbs(2, lv), false, st);
-    launch_ms_combine(c, in.data, r, out.data, count, lv, st);
+    // out = (in - NTT(R)) q_l^-1: fused into R's transform where the schedule
+    // has such a kernel, else transform and combine separately
+    NttCombine cb{};
+    cb.mode = kNttSwitch;
+    cb.d = in.data;
+    cb.d_ct_stride = in.ct_words(N);
+    cb.out = out.data;
+    cb.level = lv;
+    const u64 ql = c->mod[lv];
+    for (int i = 0; i < lv; i++) {
+        const u64 q = c->mod[i], qlinv = h_invmod(ql % q, q);
+        if (use_fp64(c)) {
+            h_fpair(cb.w[i], qlinv, q);
+        } else {
+            cb.w[i][0] = qlinv;
+            cb.w[i][1] = h_shoup(qlinv, q);
+        }
+    }
+    LimbSet ls{};
+    ls.base = r;
+    ls.poly_stride = (u64)2 * lv * N;
+    ls.npoly = count;
+    ls.nlimb = 2 * lv;
+    for (int k = 0; k < 2 * lv; k++) {
+        ls.off[k] = (int16_t)k;
+        ls.prime[k] = (int16_t)(k % lv);
+    }
+    if (!ntt_forward_combine(c, ls, cb, st)) {
+        run_ntt(c, r, (size_t)2 * lv * N, count, all_limbs(2, lv), false, st);
+        launch_ms_combine(c, in.data, r, out.data, count, lv, st);
+    }
     check_hip();
 }
 

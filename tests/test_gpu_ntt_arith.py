@@ -3,9 +3,12 @@
 With every prime below 2^50 the transforms run in fp64 arithmetic; the
 integer butterflies remain selectable.  Both must give the same bytes under
 every schedule (single-pass, two-pass whole or chunked), and the
-ciphertexts must equal the oracle's.  Sizes: N = 2^12 .. 2^15, the range of
-the single-pass kernel, with two-digit key switching so special-prime limbs
-are transformed too.
+ciphertexts must equal the oracle's.  With the single-pass schedule the last
+steps of a multiplication and of a modulus switch run inside the forward
+transform's store; the other schedules run them as separate kernels, so the
+comparison covers both.  Sizes: N = 2^12 .. 2^15, the range of the
+single-pass kernel, with two-digit key switching so special-prime limbs are
+transformed too.
 """
 import numpy as np
 import pytest
@@ -29,7 +32,8 @@ def run_all(dev, dk, slots, r):
         dev.set_tuning(bc.BC_TUNE_NTT_CHUNK_BYTES, chunk)
         ct = dev.encrypt(dk, slots, r["u"], r["e"])
         prod = dev.mul_relin(dk, ct, ct)
-        outs.append((dev.export(ct), dev.export(prod), dev.decrypt(dk, prod)))
+        ms = dev.mod_switch(ct)
+        outs.append((dev.export(ct), dev.export(prod), dev.decrypt(dk, prod), dev.export(ms)))
     return outs
 
 
@@ -48,10 +52,11 @@ def test_fp64_and_integer_transforms_agree(logN):
     r = synth.encrypt_randomness(33, count, prm.N)
     outs = run_all(dev, dk, slots, r)
     want = (slots.astype(np.int64) ** 2 % prm.p).astype(np.uint32)
-    for i, (ct, prod, dec) in enumerate(outs):
+    for i, (ct, prod, dec, ms) in enumerate(outs):
         assert np.array_equal(ct, outs[0][0]), SCHEDULES[i]
         assert np.array_equal(prod, outs[0][1]), SCHEDULES[i]
         assert np.array_equal(dec, want), SCHEDULES[i]
+        assert np.array_equal(ms, outs[0][3]), SCHEDULES[i]
     if logN <= 13:  # the oracle's ciphertexts (seconds at these sizes)
         orc = Oracle(prm)
         orc.keygen(rnd)
@@ -59,6 +64,8 @@ def test_fp64_and_integer_transforms_agree(logN):
         assert np.array_equal(outs[0][0], np.stack([c.data for c in o]))
         op = [orc.mul(c, c) for c in o]
         assert np.array_equal(outs[0][1], np.stack([c.data for c in op]))
+        om = [orc.mod_switch(c) for c in o]
+        assert np.array_equal(outs[0][3], np.stack([c.data for c in om]))
 
 
 def test_integer_only_context_reports_no_fp64():
