@@ -189,6 +189,10 @@ struct ModSwitchPlan {
     u64 pinv_l[2];         // p^-1 mod q_l
     u64 ql;                // q_l
     u64 qlinv[kMaxMod][2]; // q_l^-1 mod q_i
+    // relinearisation fused with this switch, folded constants mod q_i:
+    // Phat_j p P^-1 q_l^-1 and p q_l^-1
+    u64 rk1[kMaxMod][kMaxDigit][2];
+    u64 rk2[kMaxMod][2];
 };
 
 // Mixed-radix (Garner) reconstruction tables for decryption.

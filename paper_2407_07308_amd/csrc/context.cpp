@@ -183,7 +183,20 @@ void build_plans(const bc_ctx *c, PairSet setp, std::vector<ModUpPlan> &mu, ModD
         u64 ql = c->mod[lv];
         ms[lv].ql = ql;
         setp(ms[lv].pinv_l, h_invmod(c->p % ql, ql), ql);
-        for (int i = 0; i < lv; i++) setp(ms[lv].qlinv[i], h_invmod(ql % c->mod[i], c->mod[i]), c->mod[i]);
+        for (int i = 0; i < lv; i++) {
+            const u64 q = c->mod[i], qlinv = h_invmod(ql % q, q);
+            setp(ms[lv].qlinv[i], qlinv, q);
+            u64 P = 1;
+            for (int t = 0; t < nP; t++) P = h_mulmod(P, c->mod[nQ + t] % q, q);
+            const u64 ppq = h_mulmod(h_mulmod(c->p % q, h_invmod(P, q), q), qlinv, q);  // p P^-1 q_l^-1
+            for (int j = 0; j < nP; j++) {
+                u64 phat = 1;
+                for (int t = 0; t < nP; t++)
+                    if (t != j) phat = h_mulmod(phat, c->mod[nQ + t] % q, q);
+                setp(ms[lv].rk1[i][j], h_mulmod(phat, ppq, q), q);
+            }
+            setp(ms[lv].rk2[i], h_mulmod(c->p % q, qlinv, q), q);
+        }
     }
 }
 

@@ -150,7 +150,7 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
 // digit j's own limbs (e in [j alpha, (j+1) alpha)) are X's limbs themselves.
 // A thread takes kKsCts consecutive ciphertexts: each key word is read once
 // for all of them, and every load is issued before the arithmetic.
-constexpr int kKsCts = 2;
+constexpr int kKsCts = 4;
 __global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ x, size_t x_ct_stride,
                            const u64 *__restrict__ key, u64 *__restrict__ acc, int level, int nQ, int nmod, int next,
                            int nact, int dnum, int alpha, int count, const PrimeInfo *__restrict__ pinfo, int N) {
@@ -307,18 +307,18 @@ __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restric
                    f_load(d[(size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n]);
         // the exact centred lift: it enters every other modulus as an integer
         const double t = f_centre(f_mulmod(r, fpair(ms->pinv_l), ql), ql, pl.qinv);
+        // E_i = (sum_j v_j Phat_j p P^-1 + p t) q_l^-1 with the constants folded
         for (int i = 0; i < level; i++) {
             const PrimeInfo &pi = pinfo[i];
             const double q = pi.qd;
-            double h = 0.0;
+            double e = f_mulmod(t, fpair(ms->rk2[i]), q);
 #pragma unroll
             for (int j = 0; j < kMaxDigit; j++) {
                 if (j >= nP) break;
-                h += f_mulmod(v[j], fpair(md->phat[i][j]), q);
-                if ((j & 7) == 7) h = f_reduce(h, q, pi.qinv);
+                e += f_mulmod(v[j], fpair(ms->rk1[i][j]), q);
+                if ((j & 7) == 6) e = f_reduce(e, q, pi.qinv);
             }
-            double e = f_mulmod(h, fpair(md->ppinv[i]), q) + f_mulmod(t, fpair(pi.p_f), q);
-            E[((size_t)cc * level + i) * N + n] = f_bits(f_canon(f_mulmod(e, fpair(ms->qlinv[i]), q), q, pi.qinv));
+            E[((size_t)cc * level + i) * N + n] = f_bits(f_canon(e, q, pi.qinv));
         }
     }
 }
