@@ -10,8 +10,10 @@ Inputs are encrypted and resident in HBM before the timed region.
 
 Reported: uint16 comparisons per second (each comparison also yields its max
 and min), the forward-NTT roofline measured with HIP events on the launch
-stream during the timed steps, the plain per-operation path (one group per
-call, same kernels), and the CPU oracle on a one-group sample.
+stream during the timed steps, the same step with 64-bit integer arithmetic
+in place of the exact fp64 residue products (checked byte-identical), the
+plain per-operation path (one group per call, same kernels), and the CPU
+oracle on a one-group sample.
 """
 from __future__ import annotations
 
@@ -39,6 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-op", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-int", action="store_true", help="skip the integer-arithmetic comparison run")
     ap.add_argument("--workload", choices=["uint16", "mixed", "serving"], default="uint16",
                     help="uint16: LT+max+min at N=2^15 (default); mixed: 256 single-digit pairs over "
                          "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream")
@@ -158,6 +161,28 @@ def main():
             print("bench: per-operation path differs from the batched path", file=sys.stderr)
             sys.exit(3)
 
+    # the same step with 64-bit integer arithmetic everywhere (Shoup / Barrett
+    # products): must give byte-identical ciphertexts; timed for comparison
+    int_path = None
+    if not a.no_int and tuned.get("fp64"):
+        dev.set_tuning(bc.BC_TUNE_FP64, 0)
+        io = dev.compare_max_min(keys, A, B)  # warm-up, integer tables
+        torch.cuda.synchronize()
+        i0, i1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        i0.record()
+        for _ in range(a.steps):
+            dev.compare_max_min(keys, A, B, outs=io)
+        i1.record()
+        torch.cuda.synchronize()
+        int_ms = i0.elapsed_time(i1) / a.steps
+        same = all(np.array_equal(dev.export(x), dev.export(y))
+                   for x, y in [(io[0], lt)] + list(zip(io[1], mx)) + list(zip(io[2], mn)))
+        dev.set_tuning(bc.BC_TUNE_FP64, 1)
+        if not same:
+            print("bench: integer arithmetic gives different ciphertexts", file=sys.stderr)
+            sys.exit(3)
+        int_path = {"ms_per_step": int_ms, "value": comparisons / (int_ms / 1e3), "identical_ciphertexts": True}
+
     # recorded-graph replay of the batched launch sequence
     graph_ms = None
     if not a.no_graph:
@@ -226,6 +251,7 @@ def main():
                      "avg_launch_MB": fwd_bytes / max(1, fwd_n) / 1e6,
                      "inverse_ntt_GBs": inv_bytes / (inv_ms / 1e3) / 1e9 if inv_ms > 0 else None},
         "graph_replay_ms_per_step": graph_ms,
+        "integer_arithmetic": int_path,
         "per_op_launch": None if per_op is None else {"ms_per_step": per_op, "batched_speedup": per_op / ms_step},
         "cpu_baseline": cpu,
     }
