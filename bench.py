@@ -402,6 +402,24 @@ def serve(a):
         members[dev.N] = (dev, dev.keygen(rnd["s"], rnd["a"], rnd["e"], ()))
         dev.autotune()
     g = synth.generator(seed, "schedule")
+    # Requests draw their encrypted operands from a pool of POOL distinct
+    # payloads per (N, groups), encrypted up front: the server's work does not
+    # depend on the values, and a long window would not fit in HBM otherwise.
+    POOL = 4
+    pool = {}
+
+    def payload(N, groups, k):
+        key = (N, groups, k)
+        if key not in pool:
+            dev, dk = members[N]
+            s0 = 1000 + 97 * len(pool)
+            xs = synth.integers(s0, (groups, dev.M), 0, 65536)
+            ys = synth.integers(s0, (groups, dev.M), 0, 65536, index=1)
+            enc = lambda vals, s: [dev.encrypt(dk, pl, *synth.encrypt_randomness(s + d, groups, dev.N).values())
+                                   for d, pl in enumerate(digits(vals, BASE, NDIG))]
+            pool[key] = (xs, ys, enc(xs, s0 + 11), enc(ys, s0 + 31))
+        return pool[key]
+
     reqs, t = [], 0.0
     while True:
         t += float(g.exponential(1.0 / a.rate))
@@ -410,14 +428,10 @@ def serve(a):
         N = 1 << int(g.integers(14, 16))
         n = 1 << int(g.integers(6, 13))
         kind = ["lt", "max", "argmax"][int(g.integers(0, 3))]
-        dev, dk = members[N]
-        groups = -(-n // dev.M)
+        groups = -(-n // members[N][0].M)
         rid = len(reqs)
-        xs = synth.integers(seed + rid, (groups, dev.M), 0, 65536)
-        ys = synth.integers(seed + rid, (groups, dev.M), 0, 65536, index=1)
-        enc = lambda vals, s: [dev.encrypt(dk, pl, *synth.encrypt_randomness(s + d, groups, dev.N).values())
-                               for d, pl in enumerate(digits(vals, BASE, NDIG))]
-        r = serving.Request(rid, kind, N, groups, t, enc(xs, 1000 + 7 * rid), enc(ys, 5000 + 7 * rid))
+        xs, ys, pa, pb = payload(N, groups, rid % POOL)
+        r = serving.Request(rid, kind, N, groups, t, pa, pb)
         r.xs, r.ys = xs, ys
         reqs.append(r)
     torch.cuda.synchronize()
@@ -437,7 +451,8 @@ def serve(a):
                       "uint16_comparisons_per_s": groups * 128 / span, "batches": srv.stats["batches"],
                       "config": {"workload": f"Poisson {a.rate:.0f} req/s for {a.window} s, LT/max/argmax, "
                                              f"n log-uniform 64..4096, N in {{2^14,2^15}}, p=257",
-                                 "requests": len(reqs), "groups": groups}}))
+                                 "requests": len(reqs), "groups": groups,
+                                 "distinct_payloads": len(pool)}}))
 
 
 if __name__ == "__main__":
