@@ -435,9 +435,19 @@ def serve(a):
         r.xs, r.ys = xs, ys
         reqs.append(r)
     torch.cuda.synchronize()
-    srv = serving.Server(members, max_batch_groups=32, mem_budget_bytes=64 << 30, streams=2)
-    srv.run(reqs)
-    for r in reqs[:: max(1, len(reqs) // 8)]:
+    srv = serving.Server(members, max_batch_groups=32, streams=2)
+    step = max(1, len(reqs) // 20)
+    checked = reqs[:: max(1, len(reqs) // 8)]
+    keep = {id(r) for r in checked}
+
+    def hand_on(r):
+        # results leave the server (as if sent to the client); the checked ones stay
+        if id(r) not in keep:
+            r.result = None
+
+    srv.run(reqs, progress=lambda d, n: print(f"served {d}/{n}", file=sys.stderr, flush=True)
+            if d // step != (d - 1) // step or d == n else None, on_complete=hand_on)
+    for r in checked:
         dev, dk = members[r.N]
         if not np.array_equal(dev.decrypt(dk, r.result[0]), (r.xs < r.ys).astype(np.uint32)):
             print("bench: served decryptions are wrong", file=sys.stderr)
@@ -449,6 +459,10 @@ def serve(a):
                       "unit": "requests/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64",
                       "data": "synthetic", "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "mean_ms": s["mean_ms"],
                       "uint16_comparisons_per_s": groups * 128 / span, "batches": srv.stats["batches"],
+                      "oom_retries": srv.stats.get("oom_retries", 0),
+                      "max_workspace_gb": srv.stats.get("max_pool_bytes", 0) / 1e9,
+                      "budget_gb": srv.budget / 1e9,
+                      "group_gb": {f"{N}x{nd}": b / 1e9 for (N, nd), b in srv.bpg.items()},
                       "config": {"workload": f"Poisson {a.rate:.0f} req/s for {a.window} s, LT/max/argmax, "
                                              f"n log-uniform 64..4096, N in {{2^14,2^15}}, p=257",
                                  "requests": len(reqs), "groups": groups,

@@ -217,8 +217,18 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   combinations) in exact fp64 (integers below 2^53 held in doubles) when
  *   every prime of the context is below 2^50; 0 uses 64-bit integer
  *   arithmetic.  Reading it returns 0 for a context with a prime of 2^50 or
- *   more. */
-enum { BC_TUNE_NTT_CHUNK_BYTES = 0, BC_TUNE_NTT_SINGLE_PASS = 1, BC_TUNE_FP64 = 2 };
+ *   more.
+ *   BC_TUNE_POOL_LIMIT_BYTES: a bound on the device memory the context's
+ *   workspace pool holds, blocks in use plus released blocks kept for reuse
+ *   (0, the default: no bound; released blocks are then only given back by
+ *   bc_ctx_trim or when an allocation fails).  When a new block would take
+ *   the pool past the bound, the released blocks that were released longest
+ *   ago are given back first until the new block fits under seven eighths of
+ *   it (one wait for the device).  Blocks in use are never given back: a
+ *   call whose own working set exceeds the bound still runs.  Set it above
+ *   the working set of the batches in flight, or calls re-allocate their
+ *   workspace. */
+enum { BC_TUNE_NTT_CHUNK_BYTES = 0, BC_TUNE_NTT_SINGLE_PASS = 1, BC_TUNE_FP64 = 2, BC_TUNE_POOL_LIMIT_BYTES = 3 };
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);
 /* Times each transform schedule (two-pass, two-pass in cache-sized chunks,

@@ -232,9 +232,16 @@ extern thread_local hipStream_t tl_stream;
 
 struct Pool {
     std::mutex mu;
-    std::multimap<std::pair<hipStream_t, size_t>, void *> free_;
+    struct Cached {
+        void *p;
+        uint64_t seq;  // release order, for least-recently-released eviction
+    };
+    std::multimap<std::pair<hipStream_t, size_t>, Cached> free_;
+    uint64_t seq = 0;
     std::map<void *, std::pair<size_t, hipStream_t>> live_;
     size_t held = 0;
+    size_t cached = 0;               // bytes of free_ blocks
+    size_t limit = 0;                // bytes held (live + cached) beyond which cached blocks are evicted (0: none)
     bool recording = false;          // collect every block handed out (graph capture)
     std::vector<void *> recorded;
     static size_t size_class(size_t bytes);
@@ -244,6 +251,8 @@ struct Pool {
     std::vector<void *> detach_recorded();
     void release(void *p);
     void trim();
+    void free_cached();          // caller holds mu
+    void evict_to(size_t bytes);  // caller holds mu: oldest releases first, until held <= bytes
     ~Pool();
 };
 

@@ -510,7 +510,10 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
         if (key == BC_TUNE_NTT_CHUNK_BYTES) ctx->ntt_chunk_bytes = (size_t)value;
         else if (key == BC_TUNE_NTT_SINGLE_PASS) ctx->ntt_single_pass = value != 0;
         else if (key == BC_TUNE_FP64) ctx->fp64 = value != 0;
-        else throw Error(BC_ERR_ARG, "unknown tuning key");
+        else if (key == BC_TUNE_POOL_LIMIT_BYTES) {
+            std::lock_guard<std::mutex> g(ctx->pool.mu);
+            ctx->pool.limit = (size_t)value;
+        } else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }
 
@@ -521,6 +524,7 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
         if (key == BC_TUNE_NTT_CHUNK_BYTES) *value = (int64_t)ctx->ntt_chunk_bytes;
         else if (key == BC_TUNE_NTT_SINGLE_PASS) *value = ctx->ntt_single_pass;
         else if (key == BC_TUNE_FP64) *value = ctx->fp64 && ctx->twf != nullptr;
+        else if (key == BC_TUNE_POOL_LIMIT_BYTES) *value = (int64_t)ctx->pool.limit;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }

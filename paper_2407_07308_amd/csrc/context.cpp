@@ -208,8 +208,9 @@ thread_local hipStream_t tl_stream = nullptr;
 
 // Block sizes are rounded up to a size class (four per power of two, at
 // least 256 bytes), and a request takes any cached block of its stream up to
-// twice its class: batches of varying shape then reuse each other's blocks
-// instead of allocating (and eventually freeing, which waits for the device).
+// twice its class (any larger one once the pool is at its limit): batches of
+// varying shape then reuse each other's blocks instead of allocating (and
+// eventually freeing, which waits for the device).
 size_t Pool::size_class(size_t bytes) {
     bytes = std::max<size_t>(bytes, 256);
     int e = 63 - __builtin_clzll(bytes);
@@ -223,23 +224,28 @@ void *Pool::alloc(size_t bytes) {
     std::lock_guard<std::mutex> g(mu);
     const hipStream_t st = tl_stream;
     auto it = free_.lower_bound({st, bytes});
-    if (it != free_.end() && it->first.first == st && it->first.second <= 2 * bytes) {
-        void *p = it->second;
+    // at the limit, any larger cached block of the stream serves rather than
+    // a new one (which would first evict the blocks of other shapes)
+    const bool full = limit && held + bytes > limit && !recording;
+    if (it != free_.end() && it->first.first == st && (full || it->first.second <= 2 * bytes)) {
+        void *p = it->second.p;
         live_[p] = {it->first.second, st};
+        cached -= it->first.second;
         free_.erase(it);
         if (recording) recorded.push_back(p);
         return p;
     }
     void *p = nullptr;
+    // growing past the limit: give back the cached blocks released longest
+    // ago until the new block fits under seven eighths of it (hipFree waits
+    // for the device, so blocks whose last users are still queued are safe
+    // to free); the blocks of the shapes in current use were released last
+    // and stay.  Never while a graph records: it owns the blocks it was handed.
+    if (full) evict_to(limit / 8 * 7 > bytes ? limit / 8 * 7 - bytes : 0);
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        // give back every cached block and retry once (hipFree waits for the
-        // device, so blocks whose last users are still queued are safe to free)
-        for (auto &kv : free_) {
-            (void)hipFree(kv.second);
-            held -= kv.first.second;
-        }
-        free_.clear();
+        // give back every cached block and retry once
+        free_cached();
         if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             throw Error(BC_ERR_OOM, "device workspace allocation failed");
@@ -258,8 +264,9 @@ std::vector<void *> Pool::detach_recorded() {
     for (void *p : recorded) {
         if (std::find(out.begin(), out.end(), p) != out.end()) continue;
         for (auto it = free_.begin(); it != free_.end(); ++it)
-            if (it->second == p) {
+            if (it->second.p == p) {
                 held -= it->first.second;
+                cached -= it->first.second;
                 free_.erase(it);
                 out.push_back(p);
                 break;
@@ -274,21 +281,43 @@ void Pool::release(void *p) {
     std::lock_guard<std::mutex> g(mu);
     auto it = live_.find(p);
     if (it == live_.end()) return;
-    free_.emplace(std::make_pair(it->second.second, it->second.first), p);
+    free_.emplace(std::make_pair(it->second.second, it->second.first), Cached{p, ++seq});
+    cached += it->second.first;
     live_.erase(it);
+}
+
+// caller holds mu
+void Pool::free_cached() {
+    for (auto &kv : free_) {
+        (void)hipFree(kv.second.p);
+        held -= kv.first.second;
+    }
+    free_.clear();
+    cached = 0;
+}
+
+// caller holds mu
+void Pool::evict_to(size_t bytes) {
+    std::vector<decltype(free_)::iterator> order;
+    order.reserve(free_.size());
+    for (auto it = free_.begin(); it != free_.end(); ++it) order.push_back(it);
+    std::sort(order.begin(), order.end(), [](auto a, auto b) { return a->second.seq < b->second.seq; });
+    for (auto it : order) {
+        if (held <= bytes) break;
+        (void)hipFree(it->second.p);
+        held -= it->first.second;
+        cached -= it->first.second;
+        free_.erase(it);
+    }
 }
 
 void Pool::trim() {
     std::lock_guard<std::mutex> g(mu);
-    for (auto &kv : free_) {
-        (void)hipFree(kv.second);
-        held -= kv.first.second;
-    }
-    free_.clear();
+    free_cached();
 }
 
 Pool::~Pool() {
-    for (auto &kv : free_) (void)hipFree(kv.second);
+    for (auto &kv : free_) (void)hipFree(kv.second.p);
     for (auto &kv : live_) (void)hipFree(kv.first);
 }
 

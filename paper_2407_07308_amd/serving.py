@@ -20,7 +20,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Batch, Context, Keys
+from . import BC_ERR_OOM, BC_TUNE_POOL_LIMIT_BYTES, Batch, BoostcomError, Context, Keys
 
 
 @dataclass
@@ -61,19 +61,60 @@ def _slice(b: Batch, ctx: Context, first: int, n: int) -> Batch:
 
 
 class Server:
-    def __init__(self, members: dict, max_batch_groups: int = 64, mem_budget_bytes: int = 64 << 30,
-                 streams: int = 2, bytes_per_group: dict | None = None):
-        """members: {N: (Context, Keys)}.  bytes_per_group: device-memory
-        estimate of one group's circuit (default: 40 top-level ciphertexts
-        per plane-pair)."""
+    def __init__(self, members: dict, max_batch_groups: int = 64, mem_budget_bytes: int | None = None,
+                 streams: int = 2, bytes_per_group: dict | None = None, headroom: float = 0.1):
+        """members: {N: (Context, Keys)}.  mem_budget_bytes: device memory the
+        batches in flight may use (default: the free device memory less
+        `headroom` of the total).  bytes_per_group: {(N, planes): bytes} of one
+        group's comparison at its peak; measured on first use of a shape
+        otherwise (see _group_bytes)."""
         import torch
 
         self.members = members
         self.max_batch_groups = max_batch_groups
-        self.budget = mem_budget_bytes
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
-        self.bpg = bytes_per_group or {N: 8 * 40 * 3 * ctx.ct_words(ctx.nQ - 1) for N, (ctx, _) in members.items()}
+        if mem_budget_bytes is None:
+            free, total = torch.cuda.mem_get_info()
+            mem_budget_bytes = int(free - headroom * total)
+        self.budget = mem_budget_bytes
+        self.bpg = dict(bytes_per_group or {})
+        # Each context's workspace pool may hold its share of the budget (by
+        # ciphertext size): blocks of finished batches stay cached for the
+        # next ones up to that bound, and the pools together never take the
+        # memory the operands and the runtime need.
+        words = {N: ctx.ct_words(ctx.nQ - 1) for N, (ctx, _) in members.items()}
+        for N, (ctx, _) in members.items():
+            ctx.set_tuning(BC_TUNE_POOL_LIMIT_BYTES, max(1, self.budget * words[N] // sum(words.values())))
         self.stats = {"batches": 0, "max_inflight_bytes": 0, "groups": 0}
+
+    def _group_bytes(self, N: int, planes: int) -> int:
+        """Peak workspace of one group of an LT + max batch with `planes`
+        digit planes: measured once per shape on a 4-group batch of zero
+        ciphertexts (the pool, emptied first, then holds exactly the blocks
+        the call needed)."""
+        import torch
+
+        key = (N, planes)
+        if key not in self.bpg:
+            ctx, keys = self.members[N]
+            G = 4
+            torch.cuda.synchronize()
+            ctx.trim()
+            zero = lambda: [Batch(torch.zeros(G * ctx.ct_words(ctx.nQ - 1), dtype=torch.int64, device="cuda"),
+                                  G, ctx.nQ - 1, 2) for _ in range(planes)]
+            ctx.compare_max_min(keys, zero(), zero(), True, True, False)
+            torch.cuda.synchronize()
+            self.bpg[key] = -(-ctx.pool_bytes() // G)
+            ctx.trim()
+        return self.bpg[key]
+
+    def _release_cached(self):
+        import torch
+
+        torch.cuda.synchronize()
+        for ctx, _ in self.members.values():
+            ctx.trim()
+        torch.cuda.empty_cache()
 
     def _launch(self, reqs, stream_idx):
         import torch
@@ -81,13 +122,24 @@ class Server:
         N = reqs[0].N
         ctx, keys = self.members[N]
         s = self.streams[stream_idx]
-        with torch.cuda.stream(s):
-            A = _concat([r.a for r in reqs], ctx)
-            B = _concat([r.b for r in reqs], ctx)
-            want_max = any(r.kind == "max" for r in reqs)
-            outs = ctx.compare_max_min(keys, A, B, True, want_max, False)
-            ev = torch.cuda.Event()
-            ev.record(s)
+        want_max = any(r.kind == "max" for r in reqs)
+        for attempt in range(2):
+            try:
+                with torch.cuda.stream(s):
+                    A = _concat([r.a for r in reqs], ctx)
+                    B = _concat([r.b for r in reqs], ctx)
+                    outs = ctx.compare_max_min(keys, A, B, True, want_max, False)
+                    ev = torch.cuda.Event()
+                    ev.record(s)
+                break
+            except (torch.OutOfMemoryError, BoostcomError) as err:
+                # device memory held in the caches (the library's workspace
+                # blocks of earlier batch shapes, or torch's): wait for the
+                # device, give it all back once and retry
+                if attempt or (isinstance(err, BoostcomError) and err.code != BC_ERR_OOM):
+                    raise
+                self.stats["oom_retries"] = self.stats.get("oom_retries", 0) + 1
+                self._release_cached()
         offsets, o = [], 0
         for r in reqs:
             offsets.append(o)
@@ -95,17 +147,21 @@ class Server:
         self.stats["batches"] += 1
         self.stats["groups"] += o
         # keep the concatenated inputs alive until the batch completes
-        return _InFlight(reqs, ev, (outs, A, B), offsets, sum(self.bpg[N] * r.groups for r in reqs))
+        return _InFlight(reqs, ev, (outs, A, B), offsets, sum(self._group_bytes(N, len(r.a)) * r.groups for r in reqs))
 
-    def run(self, requests: list, clock=time.perf_counter):
+    def run(self, requests: list, clock=time.perf_counter, progress=None, on_complete=None):
         """Serves `requests` (sorted by arrival) against their arrival times;
-        returns them completed, with latencies filled in."""
+        returns them completed, with latencies filled in.  `progress(done,
+        total)` is called as batches complete; `on_complete(request)` as each
+        request completes (its result set: a caller that hands results on can
+        drop them there, so that finished batches free their memory)."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         ready = collections.deque()
         inflight: list[_InFlight] = []
         busy = [False] * len(self.streams)
         t0 = clock()
         used = 0
+        done = 0
         while pending or ready or inflight:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
@@ -119,9 +175,16 @@ class Server:
                         r.result = (_slice(lt, ctx, off, r.groups),
                                     [_slice(m, ctx, off, r.groups) for m in mx] if (mx and r.kind == "max") else None)
                         r.done_at = t
+                        if on_complete:
+                            on_complete(r)
                     used -= f.bytes
                     busy[f.stream] = False
                     inflight.remove(f)
+                    done += len(f.reqs)
+                    held = sum(c.pool_bytes() for c, _ in self.members.values())
+                    self.stats["max_pool_bytes"] = max(self.stats.get("max_pool_bytes", 0), held)
+                    if progress:
+                        progress(done, len(requests))
             launched = False
             if ready and not all(busy):
                 N = ready[0].N  # ring size of the oldest waiting request
@@ -129,7 +192,7 @@ class Server:
                 for r in list(ready):
                     if r.N != N:
                         continue
-                    need = self.bpg[N] * r.groups
+                    need = self._group_bytes(N, len(r.a)) * r.groups
                     if batch and (g + r.groups > self.max_batch_groups or used + nbytes + need > self.budget):
                         break
                     if not batch and used + need > self.budget and inflight:

@@ -86,7 +86,7 @@ def test_server_results_equal_alone_and_in_the_mix():
         reqs.append(r)
     # a budget of four of the larger groups: the 3-group N = 2^11 request has
     # to wait for memory while the first batches are in flight
-    bpg = {N: 2 * 40 * 3 * 8 * m[0].ct_words(m[0].nQ - 1) for N, m in members.items()}
+    bpg = {(N, ND): 2 * 40 * 3 * 8 * m[0].ct_words(m[0].nQ - 1) for N, m in members.items()}
     srv = serving.Server(members, max_batch_groups=4, mem_budget_bytes=4 * max(bpg.values()), streams=2,
                          bytes_per_group=bpg)
     srv.run(reqs)
@@ -105,6 +105,24 @@ def test_server_results_equal_alone_and_in_the_mix():
             assert np.array_equal(val, np.maximum(r.xs, r.ys))
     summ = serving.latency_summary(reqs)
     assert summ["p99_ms"] >= summ["p50_ms"] > 0
+
+
+def test_server_measures_group_bytes_and_bounds_pools():
+    """Without given sizes the server measures a shape's workspace once (the
+    pool is empty again afterwards) and bounds each context's pool by its
+    share of the budget."""
+    import paper_2407_07308_amd as bc
+    from paper_2407_07308_amd import serving
+
+    members = {1 << 10: member(Params(10, 257, 12, 50, 4, 50, 3), 5),
+               1 << 11: member(Params(11, 257, 12, 50, 4, 50, 3), 6)}
+    srv = serving.Server(members, max_batch_groups=4, mem_budget_bytes=3 << 30, streams=1)
+    limits = {N: m[0].get_tuning(bc.BC_TUNE_POOL_LIMIT_BYTES) for N, m in members.items()}
+    assert sum(limits.values()) <= 3 << 30 and limits[1 << 11] > limits[1 << 10] > 0
+    one, three = srv._group_bytes(1 << 11, 1), srv._group_bytes(1 << 11, ND)
+    assert three > one > 0
+    assert srv._group_bytes(1 << 11, ND) == three  # measured once
+    assert members[1 << 11][0].pool_bytes() == 0
 
 
 def test_mixed_ring_sizes_at_workload_sizes_concurrently():
@@ -138,3 +156,23 @@ def test_mixed_ring_sizes_at_workload_sizes_concurrently():
         for o in outs:
             o[0].tensor.zero_()
         grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)  # replay
+
+
+def test_workspace_cache_limit_keeps_results():
+    """With a workspace cache limit the pool gives its cached blocks back
+    whenever it must grow past the limit; results are the same bytes."""
+    import paper_2407_07308_amd as bc
+
+    prm = Params(10, 257, 8, 50, 4, 50, 2)
+    dev, dk = member(prm, 9)
+    x = synth.slot_values(71, 2, dev.M, 0, 129)
+    y = synth.slot_values(72, 2, dev.M, 0, 129)
+    rx, ry = synth.encrypt_randomness(73, 2, dev.N), synth.encrypt_randomness(74, 2, dev.N)
+    A, B = [dev.encrypt(dk, x, rx["u"], rx["e"])], [dev.encrypt(dk, y, ry["u"], ry["e"])]
+    ref = dev.export(dev.compare_lt(dk, A, B))
+    dev.trim()
+    dev.set_tuning(bc.BC_TUNE_POOL_LIMIT_BYTES, 1 << 20)
+    assert dev.get_tuning(bc.BC_TUNE_POOL_LIMIT_BYTES) == 1 << 20
+    for _ in range(2):
+        assert np.array_equal(dev.export(dev.compare_lt(dk, A, B)), ref)
+    assert np.array_equal(dev.decrypt(dk, dev.compare_lt(dk, A, B)), (x < y).astype(np.uint32))
