@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--workload", choices=["uint16", "mixed", "serving"], default="uint16",
                     help="uint16: LT+max+min at N=2^15 (default); mixed: 256 single-digit pairs over "
                          "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream")
-    ap.add_argument("--window", type=float, default=0.5, help="serving: seconds of arrivals")
+    ap.add_argument("--window", type=float, default=10.0, help="serving: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: mean requests per second")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="write the forward-NTT traffic summary from two rocprofv3 --pmc runs and exit")
