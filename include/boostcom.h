@@ -218,6 +218,13 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   every prime of the context is below 2^50; 0 uses 64-bit integer
  *   arithmetic.  Reading it returns 0 for a context with a prime of 2^50 or
  *   more.
+ *   BC_TUNE_NTT_PARTS: nonzero (the default) lets the key-switching kernels
+ *   that produce words for a forward transform apply its first one (N =
+ *   2^14) or two (N = 2^15) butterfly stages themselves, so that the rest of
+ *   the transform runs as independent 2^13-word parts, several per CU (only
+ *   with the single-pass schedule and digits of at most 8 primes).  Results
+ *   are the same bytes either way.  Reading it returns the number of folded
+ *   stages in effect (0 when off or not applicable).
  *   BC_TUNE_POOL_LIMIT_BYTES: a bound on the device memory the context's
  *   workspace pool holds, blocks in use plus released blocks kept for reuse
  *   (0, the default: no bound; released blocks are then only given back by
@@ -228,7 +235,13 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   call whose own working set exceeds the bound still runs.  Set it above
  *   the working set of the batches in flight, or calls re-allocate their
  *   workspace. */
-enum { BC_TUNE_NTT_CHUNK_BYTES = 0, BC_TUNE_NTT_SINGLE_PASS = 1, BC_TUNE_FP64 = 2, BC_TUNE_POOL_LIMIT_BYTES = 3 };
+enum {
+    BC_TUNE_NTT_CHUNK_BYTES = 0,
+    BC_TUNE_NTT_SINGLE_PASS = 1,
+    BC_TUNE_FP64 = 2,
+    BC_TUNE_POOL_LIMIT_BYTES = 3,
+    BC_TUNE_NTT_PARTS = 4
+};
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);
 /* Times each transform schedule (two-pass, two-pass in cache-sized chunks,

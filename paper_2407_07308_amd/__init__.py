@@ -23,6 +23,7 @@ BC_ROW_SWAP = -1
 BC_EXEC_BATCHED, BC_EXEC_GRAPH, BC_EXEC_PER_OP = 0, 1, 2
 BC_PROF_NTT_FWD, BC_PROF_NTT_INV, BC_PROF_NTT_FWD_COMBINE = 0, 1, 2
 BC_TUNE_NTT_CHUNK_BYTES, BC_TUNE_NTT_SINGLE_PASS, BC_TUNE_FP64, BC_TUNE_POOL_LIMIT_BYTES = 0, 1, 2, 3
+BC_TUNE_NTT_PARTS = 4
 
 
 class BoostcomUnavailable(RuntimeError):
@@ -334,7 +335,8 @@ class Context:
         _check(self.L.bc_autotune(self.handle, _stream()))
         return {"single_pass": self.get_tuning(BC_TUNE_NTT_SINGLE_PASS),
                 "chunk_bytes": self.get_tuning(BC_TUNE_NTT_CHUNK_BYTES),
-                "fp64": self.get_tuning(BC_TUNE_FP64)}
+                "fp64": self.get_tuning(BC_TUNE_FP64),
+                "parts_log": self.get_tuning(BC_TUNE_NTT_PARTS)}
 
     def get_tuning(self, key: int) -> int:
         v = ctypes.c_int64()

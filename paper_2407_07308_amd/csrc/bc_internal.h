@@ -25,6 +25,7 @@ typedef unsigned __int128 u128;
 constexpr int kMaxMod = 40;    // nQ + nP
 constexpr int kMaxJobs = 160;  // limbs listed in one transform launch
 constexpr int kMaxDigit = 16;  // primes per key-switching digit, and special primes
+constexpr int kFoldDigit = 8;  // the same bound for the kernels that fold transform stages
 
 // ------------------------------------------------------------------ errors
 
@@ -164,7 +165,57 @@ struct PrimeInfo {
     double qd, qinv, ninv_d, ninv_q, ninvw1_d, ninvw1_q;
     u64 p_f[2];      // p mod q as an FPair (fp64 base conversions)
     u64 two25_f[2];  // 2^25 mod q as an FPair (small-coefficient linear combinations)
+    // forward twiddles W[1], W[2], W[3] of the first two stages, folded into
+    // the kernels that produce words for a part-limb transform: Shoup pairs
+    // and FPairs
+    u64 w123[3][2];
+    u64 w123_f[3][2];
 };
+
+// The first PL forward stages (PL = 1, 2) of a limb's transform applied to
+// the 2^PL words v[j] = a[x + j N / 2^PL] of one position x: the stage of
+// span N/2 pairs (v0, v1) (PL = 1) or (v0, v2), (v1, v3) with twiddle W[1],
+// the stage of span N/4 pairs (v0, v1) with W[2] and (v2, v3) with W[3].
+// Canonical words in and out.  What remains of the transform splits into
+// 2^PL independent parts.
+__device__ __forceinline__ void bfly_int(u64 &x, u64 &y, const u64 *w, u64 q) {
+    const u64 p = shoup(y, w[0], w[1], q);
+    y = sub_mod(x, p, q);
+    x = add_mod(x, p, q);
+}
+template <int PL>
+__device__ __forceinline__ void fold_int(u64 *v, const PrimeInfo &pi) {
+    static_assert(PL == 1 || PL == 2, "one or two stages");
+    if constexpr (PL == 1) {
+        bfly_int(v[0], v[1], pi.w123[0], pi.q);
+    } else {
+        bfly_int(v[0], v[2], pi.w123[0], pi.q);
+        bfly_int(v[1], v[3], pi.w123[0], pi.q);
+        bfly_int(v[0], v[1], pi.w123[1], pi.q);
+        bfly_int(v[2], v[3], pi.w123[2], pi.q);
+    }
+}
+// fp64: |x|, |y| < 1.6 q in, |x| < 2.1 q out (f_mulmod's bound), exact
+__device__ __forceinline__ void bfly_fp(double &x, double &y, const u64 *w, double q) {
+#pragma clang fp contract(off)
+    const double p = f_mulmod(y, fpair(w), q);
+    y = x - p;
+    x = x + p;
+}
+template <int PL>
+__device__ __forceinline__ void fold_fp(double *v, const PrimeInfo &pi) {
+    static_assert(PL == 1 || PL == 2, "one or two stages");
+    if constexpr (PL == 1) {
+        bfly_fp(v[0], v[1], pi.w123_f[0], pi.qd);
+    } else {
+        bfly_fp(v[0], v[2], pi.w123_f[0], pi.qd);
+        bfly_fp(v[1], v[3], pi.w123_f[0], pi.qd);
+        bfly_fp(v[0], v[1], pi.w123_f[1], pi.qd);
+        bfly_fp(v[2], v[3], pi.w123_f[2], pi.qd);
+    }
+#pragma unroll
+    for (int j = 0; j < (1 << PL); j++) v[j] = f_canon(v[j], pi.qd, pi.qinv);
+}
 
 // Fast base conversion from one digit at one level (modulus raising).
 struct ModUpPlan {
@@ -315,6 +366,7 @@ struct bc_ctx {
     int exec_mode = BC_EXEC_BATCHED;
     size_t ntt_chunk_bytes = 0;  // 0: one launch pair per transform call
     int ntt_single_pass = 1;     // one-launch transform for N = 2^12 .. 2^15
+    int ntt_parts = 1;           // N = 2^14, 2^15: producers fold the first stages, parts finish
     int fp64 = 1;                // fp64 transforms and base conversions where twf exists
     std::unique_ptr<bc::GraphCache> graphs;
     std::mutex graph_mu;
@@ -372,5 +424,14 @@ void ntt_inverse(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
 // transform schedule has no such kernel; the caller then transforms E and
 // combines separately (same result).
 bool ntt_forward_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &cb, hipStream_t st);
+// Part-limb forward transforms.  When PL = ntt_parts_log(c) > 0 (N = 2^14:
+// 1, N = 2^15: 2), the kernels that produce words for the key-switching
+// transforms (modulus raising, the relinearise+switch and switch corrections)
+// apply the transform's first PL butterfly stages themselves (fold_int /
+// fold_fp), and these finish it in 2^PL independent parts of 2^13 words: one
+// block of 256 threads each, four blocks per CU.
+int ntt_parts_log(const bc_ctx *c);
+void ntt_forward_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
+void ntt_forward_parts_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &cb, hipStream_t st);
 
 }  // namespace bc

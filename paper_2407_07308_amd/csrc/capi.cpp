@@ -510,6 +510,7 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
         if (key == BC_TUNE_NTT_CHUNK_BYTES) ctx->ntt_chunk_bytes = (size_t)value;
         else if (key == BC_TUNE_NTT_SINGLE_PASS) ctx->ntt_single_pass = value != 0;
         else if (key == BC_TUNE_FP64) ctx->fp64 = value != 0;
+        else if (key == BC_TUNE_NTT_PARTS) ctx->ntt_parts = value != 0;
         else if (key == BC_TUNE_POOL_LIMIT_BYTES) {
             std::lock_guard<std::mutex> g(ctx->pool.mu);
             ctx->pool.limit = (size_t)value;
@@ -524,6 +525,7 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
         if (key == BC_TUNE_NTT_CHUNK_BYTES) *value = (int64_t)ctx->ntt_chunk_bytes;
         else if (key == BC_TUNE_NTT_SINGLE_PASS) *value = ctx->ntt_single_pass;
         else if (key == BC_TUNE_FP64) *value = ctx->fp64 && ctx->twf != nullptr;
+        else if (key == BC_TUNE_NTT_PARTS) *value = ntt_parts_log(ctx);
         else if (key == BC_TUNE_POOL_LIMIT_BYTES) *value = (int64_t)ctx->pool.limit;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });

@@ -440,6 +440,11 @@ void build_context(bc_ctx *c, const bc_params &prm) {
         pi.ninvw1_q = pi.ninvw1_d / pi.qd;
         set_fpair(pi.p_f, c->p, q);
         set_fpair(pi.two25_f, (u64)1 << 25, q);
+        for (int k = 1; k <= 3; k++) {
+            pi.w123[k - 1][0] = W[k];
+            pi.w123[k - 1][1] = Wp[k];
+            set_fpair(pi.w123_f[k - 1], W[k], q);
+        }
     }
     c->tw = upload(tw.data(), tw.size());
     if (*std::max_element(c->mod.begin(), c->mod.end()) < ((u64)1 << 50)) {

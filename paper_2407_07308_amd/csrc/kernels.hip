@@ -92,56 +92,77 @@ __global__ void k_permute(const u64 *__restrict__ in, u64 *__restrict__ out, con
 
 // Fast base conversion of digit j (z-grid = ct * dnum + j):
 // y_i = [x_i Qhat_i^-1]_{q_i}, u_t = sum_i y_i Qhat_i mod q_t.
-template <bool FP>
+// With PL > 0 a thread takes the 2^PL words n + v N/2^PL of each limb and
+// applies the first PL forward stages of the new limbs' transforms to its
+// outputs (fold_int / fold_fp); MD bounds the digit size at compile time.
+template <bool FP, int PL = 0, int MD = kMaxDigit>
 __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const ModUpPlan *__restrict__ plans,
                         const PrimeInfo *__restrict__ pinfo, int nl, int next, int dnum, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x;
+    constexpr int NV = 1 << PL;
+    const int n = blockIdx.x * kT + threadIdx.x, Q = N >> PL;
     const int ct = blockIdx.z / dnum, j = blockIdx.z - ct * dnum;
     const ModUpPlan &pl = plans[j];
     if (pl.nsrc == 0) return;
     u64 *out = mu + ((size_t)ct * dnum + j) * next * N + n;
+    const u64 *in = xc + (size_t)ct * nl * N + n;
     if constexpr (!FP) {
         // fully unrolled over the compile-time bound so y[] stays in registers
-        u64 y[kMaxDigit];
+        u64 y[NV][MD];
 #pragma unroll
-        for (int s = 0; s < kMaxDigit; s++) {
+        for (int s = 0; s < MD; s++) {
             if (s >= pl.nsrc) break;
-            int i = pl.src_lo + s;
-            u64 x = xc[((size_t)ct * nl + i) * N + n];
-            y[s] = shoup(x, pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
+            const int i = pl.src_lo + s;
+#pragma unroll
+            for (int v = 0; v < NV; v++) y[v][s] = shoup(in[(size_t)i * N + v * Q], pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
         }
         for (int t = 0; t < pl.ntgt; t++) {
-            const u64 q = pinfo[pl.tgt_prime[t]].q;
-            u64 acc = 0;
+            const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
+            u64 acc[NV];
 #pragma unroll
-            for (int s = 0; s < kMaxDigit; s++) {
-                if (s >= pl.nsrc) break;
-                acc = add_mod(acc, shoup(y[s], pl.qhat[t][s][0], pl.qhat[t][s][1], q), q);
+            for (int v = 0; v < NV; v++) {
+                acc[v] = 0;
+#pragma unroll
+                for (int s = 0; s < MD; s++) {
+                    if (s >= pl.nsrc) break;
+                    acc[v] = add_mod(acc[v], shoup(y[v][s], pl.qhat[t][s][0], pl.qhat[t][s][1], pt.q), pt.q);
+                }
             }
-            out[(size_t)pl.tgt_e[t] * N] = acc;
+            if constexpr (PL > 0) fold_int<PL>(acc, pt);
+#pragma unroll
+            for (int v = 0; v < NV; v++) out[(size_t)pl.tgt_e[t] * N + v * Q] = acc[v];
         }
     } else {
 #pragma clang fp contract(off)
         // y_s canonical in [0, q_s); each product below 0.75 q_t in magnitude,
         // so eight of them sum exactly before a reduction
-        double y[kMaxDigit];
+        double y[NV][MD];
 #pragma unroll
-        for (int s = 0; s < kMaxDigit; s++) {
+        for (int s = 0; s < MD; s++) {
             if (s >= pl.nsrc) break;
             const PrimeInfo &pi = pinfo[pl.src_lo + s];
-            double x = f_load(xc[((size_t)ct * nl + pl.src_lo + s) * N + n]);
-            y[s] = f_canon(f_mulmod(x, fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const double x = f_load(in[(size_t)(pl.src_lo + s) * N + v * Q]);
+                y[v][s] = f_canon(f_mulmod(x, fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
+            }
         }
         for (int t = 0; t < pl.ntgt; t++) {
             const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
-            double acc = 0.0;
+            double acc[NV];
 #pragma unroll
-            for (int s = 0; s < kMaxDigit; s++) {
-                if (s >= pl.nsrc) break;
-                acc += f_mulmod(y[s], fpair(pl.qhat[t][s]), pt.qd);
-                if ((s & 7) == 7) acc = f_reduce(acc, pt.qd, pt.qinv);
+            for (int v = 0; v < NV; v++) {
+                acc[v] = 0.0;
+#pragma unroll
+                for (int s = 0; s < MD; s++) {
+                    if (s >= pl.nsrc) break;
+                    acc[v] += f_mulmod(y[v][s], fpair(pl.qhat[t][s]), pt.qd);
+                    if ((s & 7) == 7) acc[v] = f_reduce(acc[v], pt.qd, pt.qinv);
+                }
+                acc[v] = f_canon(acc[v], pt.qd, pt.qinv);
             }
-            out[(size_t)pl.tgt_e[t] * N] = f_bits(f_canon(acc, pt.qd, pt.qinv));
+            if constexpr (PL > 0) fold_fp<PL>(acc, pt);
+#pragma unroll
+            for (int v = 0; v < NV; v++) out[(size_t)pl.tgt_e[t] * N + v * Q] = f_bits(acc[v]);
         }
     }
 }
@@ -238,87 +259,113 @@ __global__ void k_ks_combine(const u64 *__restrict__ base0, const u64 *__restric
 // so that, after E is transformed, out_i = (d_i + acc_i P^-1) q_l^-1 - E_i
 // equals the modulus switch of the relinearised ciphertext exactly (every
 // step is linear over Z_{q_i}).  d and acc limbs l are coefficient domain here.
-template <bool FP>
+template <bool FP, int PL = 0, int MD = kMaxDigit>
 __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restrict__ d, size_t d_ct_stride,
                                u64 *__restrict__ E, const ModDownPlan *__restrict__ md,
                                const ModSwitchPlan *__restrict__ ms, const PrimeInfo *__restrict__ pinfo, int level,
                                int nQ, int nP, int next, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
+    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (first PL forward stages folded)
+    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z, Q = N >> PL;
     const int ct = cc >> 1, c = cc & 1, nl = level + 1;
+    const u64 *A = acc + (size_t)cc * next * N + n;
+    const u64 *D = d + (size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n;
+    u64 *Eo = E + (size_t)cc * level * N + n;
     if constexpr (!FP) {
-        u64 v[kMaxDigit];
-#pragma unroll
-        for (int j = 0; j < kMaxDigit; j++) {
-            if (j >= nP) break;
-            u64 x = acc[((size_t)cc * next + nl + j) * N + n];
-            v[j] = shoup(x, md->vfac[j][0], md->vfac[j][1], pinfo[nQ + j].q);
-        }
-        // top limb of the relinearised component
+        u64 v[NV][MD], mag[NV];
+        bool neg[NV];
         const u64 ql = pinfo[level].q;
-        u64 th = 0;
 #pragma unroll
-        for (int j = 0; j < kMaxDigit; j++) {
-            if (j >= nP) break;
-            th = add_mod(th, shoup(v[j], md->phat[level][j][0], md->phat[level][j][1], ql), ql);
+        for (int w = 0; w < NV; w++) {
+#pragma unroll
+            for (int j = 0; j < MD; j++) {
+                if (j >= nP) break;
+                u64 x = A[(size_t)(nl + j) * N + w * Q];
+                v[w][j] = shoup(x, md->vfac[j][0], md->vfac[j][1], pinfo[nQ + j].q);
+            }
+            // top limb of the relinearised component
+            u64 th = 0;
+#pragma unroll
+            for (int j = 0; j < MD; j++) {
+                if (j >= nP) break;
+                th = add_mod(th, shoup(v[w][j], md->phat[level][j][0], md->phat[level][j][1], ql), ql);
+            }
+            u64 a = A[(size_t)level * N + w * Q];
+            u64 r = sub_mod(shoup(a, md->pinv[level][0], md->pinv[level][1], ql),
+                            shoup(th, md->ppinv[level][0], md->ppinv[level][1], ql), ql);
+            r = add_mod(r, D[w * Q], ql);
+            const u64 t = shoup(r, ms->pinv_l[0], ms->pinv_l[1], ql);
+            neg[w] = t > (ql - 1) / 2;
+            mag[w] = neg[w] ? ql - t : t;
         }
-        u64 a = acc[((size_t)cc * next + level) * N + n];
-        u64 r = sub_mod(shoup(a, md->pinv[level][0], md->pinv[level][1], ql),
-                        shoup(th, md->ppinv[level][0], md->ppinv[level][1], ql), ql);
-        r = add_mod(r, d[(size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n], ql);
-        const u64 t = shoup(r, ms->pinv_l[0], ms->pinv_l[1], ql);
-        const bool neg = t > (ql - 1) / 2;
-        const u64 mag = neg ? ql - t : t;
         for (int i = 0; i < level; i++) {
             const PrimeInfo &pi = pinfo[i];
             const u64 q = pi.q;
-            u64 h = 0;
+            u64 e[NV];
 #pragma unroll
-            for (int j = 0; j < kMaxDigit; j++) {
-                if (j >= nP) break;
-                h = add_mod(h, shoup(v[j], md->phat[i][j][0], md->phat[i][j][1], q), q);
+            for (int w = 0; w < NV; w++) {
+                u64 h = 0;
+#pragma unroll
+                for (int j = 0; j < MD; j++) {
+                    if (j >= nP) break;
+                    h = add_mod(h, shoup(v[w][j], md->phat[i][j][0], md->phat[i][j][1], q), q);
+                }
+                u64 pt = shoup(mag[w], pi.p_mod, pi.p_modp, q);
+                pt = (neg[w] && pt) ? q - pt : pt;
+                const u64 x = add_mod(shoup(h, md->ppinv[i][0], md->ppinv[i][1], q), pt, q);
+                e[w] = shoup(x, ms->qlinv[i][0], ms->qlinv[i][1], q);
             }
-            u64 pt = shoup(mag, pi.p_mod, pi.p_modp, q);
-            pt = (neg && pt) ? q - pt : pt;
-            u64 e = add_mod(shoup(h, md->ppinv[i][0], md->ppinv[i][1], q), pt, q);
-            E[((size_t)cc * level + i) * N + n] = shoup(e, ms->qlinv[i][0], ms->qlinv[i][1], q);
+            if constexpr (PL > 0) fold_int<PL>(e, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) Eo[(size_t)i * N + w * Q] = e[w];
         }
     } else {
 #pragma clang fp contract(off)
-        double v[kMaxDigit];  // canonical in [0, p_j)
-#pragma unroll
-        for (int j = 0; j < kMaxDigit; j++) {
-            if (j >= nP) break;
-            const PrimeInfo &pj = pinfo[nQ + j];
-            double x = f_load(acc[((size_t)cc * next + nl + j) * N + n]);
-            v[j] = f_canon(f_mulmod(x, fpair(md->vfac[j]), pj.qd), pj.qd, pj.qinv);
-        }
+        double v[NV][MD];  // canonical in [0, p_j)
+        double t[NV];
         const PrimeInfo &pl = pinfo[level];
         const double ql = pl.qd;
-        double th = 0.0;
 #pragma unroll
-        for (int j = 0; j < kMaxDigit; j++) {
-            if (j >= nP) break;
-            th += f_mulmod(v[j], fpair(md->phat[level][j]), ql);
-            if ((j & 7) == 7) th = f_reduce(th, ql, pl.qinv);
+        for (int w = 0; w < NV; w++) {
+#pragma unroll
+            for (int j = 0; j < MD; j++) {
+                if (j >= nP) break;
+                const PrimeInfo &pj = pinfo[nQ + j];
+                double x = f_load(A[(size_t)(nl + j) * N + w * Q]);
+                v[w][j] = f_canon(f_mulmod(x, fpair(md->vfac[j]), pj.qd), pj.qd, pj.qinv);
+            }
+            double th = 0.0;
+#pragma unroll
+            for (int j = 0; j < MD; j++) {
+                if (j >= nP) break;
+                th += f_mulmod(v[w][j], fpair(md->phat[level][j]), ql);
+                if ((j & 7) == 7) th = f_reduce(th, ql, pl.qinv);
+            }
+            th = f_reduce(th, ql, pl.qinv);
+            double a = f_load(A[(size_t)level * N + w * Q]);
+            double r = f_mulmod(a, fpair(md->pinv[level]), ql) - f_mulmod(th, fpair(md->ppinv[level]), ql) +
+                       f_load(D[w * Q]);
+            // the exact centred lift: it enters every other modulus as an integer
+            t[w] = f_centre(f_mulmod(r, fpair(ms->pinv_l), ql), ql, pl.qinv);
         }
-        th = f_reduce(th, ql, pl.qinv);
-        double a = f_load(acc[((size_t)cc * next + level) * N + n]);
-        double r = f_mulmod(a, fpair(md->pinv[level]), ql) - f_mulmod(th, fpair(md->ppinv[level]), ql) +
-                   f_load(d[(size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n]);
-        // the exact centred lift: it enters every other modulus as an integer
-        const double t = f_centre(f_mulmod(r, fpair(ms->pinv_l), ql), ql, pl.qinv);
         // E_i = (sum_j v_j Phat_j p P^-1 + p t) q_l^-1 with the constants folded
         for (int i = 0; i < level; i++) {
             const PrimeInfo &pi = pinfo[i];
             const double q = pi.qd;
-            double e = f_mulmod(t, fpair(ms->rk2[i]), q);
+            double e[NV];
 #pragma unroll
-            for (int j = 0; j < kMaxDigit; j++) {
-                if (j >= nP) break;
-                e += f_mulmod(v[j], fpair(ms->rk1[i][j]), q);
-                if ((j & 7) == 6) e = f_reduce(e, q, pi.qinv);
+            for (int w = 0; w < NV; w++) {
+                e[w] = f_mulmod(t[w], fpair(ms->rk2[i]), q);
+#pragma unroll
+                for (int j = 0; j < MD; j++) {
+                    if (j >= nP) break;
+                    e[w] += f_mulmod(v[w][j], fpair(ms->rk1[i][j]), q);
+                    if ((j & 7) == 6) e[w] = f_reduce(e[w], q, pi.qinv);
+                }
+                e[w] = f_canon(e[w], q, pi.qinv);
             }
-            E[((size_t)cc * level + i) * N + n] = f_bits(f_canon(e, q, pi.qinv));
+            if constexpr (PL > 0) fold_fp<PL>(e, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) Eo[(size_t)i * N + w * Q] = f_bits(e[w]);
         }
     }
 }
@@ -344,26 +391,49 @@ __global__ void k_relin_ms_combine(const u64 *__restrict__ d, size_t d_ct_stride
 // ----------------------------------------------------- modulus switching
 
 // R[ct][c][i] = p t mod q_i, t = [top p^-1]_{q_l} lifted to (-q_l/2, q_l/2]
-template <bool FP>
+template <bool FP, int PL = 0>
 __global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const ModSwitchPlan *__restrict__ pl,
                          const PrimeInfo *__restrict__ pinfo, int level, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
+    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (first PL forward stages folded)
+    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z, Q = N >> PL;
+    const u64 *T = top + (size_t)cc * N + n;
+    u64 *Ro = R + (size_t)cc * level * N + n;
     if constexpr (!FP) {
         const u64 ql = pl->ql;
-        u64 t = shoup(top[(size_t)cc * N + n], pl->pinv_l[0], pl->pinv_l[1], ql);
-        const bool neg = t > (ql - 1) / 2;
-        const u64 mag = neg ? ql - t : t;  // |t| < q_l < q_i
+        u64 mag[NV];
+        bool neg[NV];
+#pragma unroll
+        for (int w = 0; w < NV; w++) {
+            const u64 t = shoup(T[w * Q], pl->pinv_l[0], pl->pinv_l[1], ql);
+            neg[w] = t > (ql - 1) / 2;
+            mag[w] = neg[w] ? ql - t : t;  // |t| < q_l < q_i
+        }
         for (int i = 0; i < level; i++) {
             const PrimeInfo &pi = pinfo[i];
-            u64 r = shoup(mag, pi.p_mod, pi.p_modp, pi.q);
-            R[((size_t)cc * level + i) * N + n] = (neg && r) ? pi.q - r : r;
+            u64 r[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) {
+                r[w] = shoup(mag[w], pi.p_mod, pi.p_modp, pi.q);
+                r[w] = (neg[w] && r[w]) ? pi.q - r[w] : r[w];
+            }
+            if constexpr (PL > 0) fold_int<PL>(r, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) Ro[(size_t)i * N + w * Q] = r[w];
         }
     } else {
         const PrimeInfo &pq = pinfo[level];
-        const double t = f_centre(f_mulmod(f_load(top[(size_t)cc * N + n]), fpair(pl->pinv_l), pq.qd), pq.qd, pq.qinv);
+        double t[NV];
+#pragma unroll
+        for (int w = 0; w < NV; w++)
+            t[w] = f_centre(f_mulmod(f_load(T[w * Q]), fpair(pl->pinv_l), pq.qd), pq.qd, pq.qinv);
         for (int i = 0; i < level; i++) {
             const PrimeInfo &pi = pinfo[i];
-            R[((size_t)cc * level + i) * N + n] = f_bits(f_canon(f_mulmod(t, fpair(pi.p_f), pi.qd), pi.qd, pi.qinv));
+            double r[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) r[w] = f_canon(f_mulmod(t[w], fpair(pi.p_f), pi.qd), pi.qd, pi.qinv);
+            if constexpr (PL > 0) fold_fp<PL>(r, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) Ro[(size_t)i * N + w * Q] = f_bits(r[w]);
         }
     }
 }
@@ -663,13 +733,20 @@ void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, i
                     hipStream_t st) {
     k_permute<<<grid3(c->N, nl, count), kT, 0, st>>>(in, out, perm, nl, ncomp, c->N);
 }
-void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, hipStream_t st) {
-    if (use_fp64(c))
-        k_modup<true><<<grid3(c->N, 1, count * c->dnum), kT, 0, st>>>(xc, mu, c->modup_f + (size_t)level * c->dnum,
-                                                                     c->pinfo, level + 1, next, c->dnum, c->N);
-    else
-        k_modup<false><<<grid3(c->N, 1, count * c->dnum), kT, 0, st>>>(xc, mu, c->modup + (size_t)level * c->dnum,
-                                                                      c->pinfo, level + 1, next, c->dnum, c->N);
+template <bool FP, int PL, int MD>
+static void modup_pl(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, hipStream_t st) {
+    k_modup<FP, PL, MD><<<grid3(c->N >> PL, 1, count * c->dnum), kT, 0, st>>>(
+        xc, mu, (FP ? c->modup_f : c->modup) + (size_t)level * c->dnum, c->pinfo, level + 1, next, c->dnum, c->N);
+}
+template <bool FP>
+static void modup_a(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, hipStream_t st) {
+    if (pl == 2) modup_pl<FP, 2, kFoldDigit>(c, xc, mu, count, level, next, st);
+    else if (pl == 1) modup_pl<FP, 1, kFoldDigit>(c, xc, mu, count, level, next, st);
+    else modup_pl<FP, 0, kMaxDigit>(c, xc, mu, count, level, next, st);
+}
+void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, hipStream_t st) {
+    if (use_fp64(c)) modup_a<true>(c, xc, mu, count, level, next, pl, st);
+    else modup_a<false>(c, xc, mu, count, level, next, pl, st);
 }
 void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_stride, const u64 *key, u64 *acc,
                      int count, int level, int next, int nact, hipStream_t st) {
@@ -685,20 +762,39 @@ void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size
                                                                out_ct_stride, c->moddown, c->pinfo, level + 1, next,
                                                                c->N);
 }
-void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st) {
-    if (use_fp64(c))
-        k_ms_fbc<true><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(top, R, c->modsw_f + level, c->pinfo, level, c->N);
-    else
-        k_ms_fbc<false><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(top, R, c->modsw + level, c->pinfo, level, c->N);
+template <bool FP, int PL>
+static void ms_fbc_pl(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, hipStream_t st) {
+    k_ms_fbc<FP, PL><<<grid3(c->N >> PL, 1, count * 2), kT, 0, st>>>(top, R, (FP ? c->modsw_f : c->modsw) + level,
+                                                                    c->pinfo, level, c->N);
+}
+template <bool FP>
+static void ms_fbc_a(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, int pl, hipStream_t st) {
+    if (pl == 2) ms_fbc_pl<FP, 2>(c, top, R, count, level, st);
+    else if (pl == 1) ms_fbc_pl<FP, 1>(c, top, R, count, level, st);
+    else ms_fbc_pl<FP, 0>(c, top, R, count, level, st);
+}
+void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, int pl, hipStream_t st) {
+    if (use_fp64(c)) ms_fbc_a<true>(c, top, R, count, level, pl, st);
+    else ms_fbc_a<false>(c, top, R, count, level, pl, st);
+}
+template <bool FP, int PL, int MD>
+static void relin_ms_fbc_pl(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
+                            int level, int next, hipStream_t st) {
+    k_relin_ms_fbc<FP, PL, MD><<<grid3(c->N >> PL, 1, count * 2), kT, 0, st>>>(
+        acc, d, d_ct_stride, E, FP ? c->moddown_f : c->moddown, (FP ? c->modsw_f : c->modsw) + level, c->pinfo, level,
+        c->nQ, c->nP, next, c->N);
+}
+template <bool FP>
+static void relin_ms_fbc_a(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
+                           int level, int next, int pl, hipStream_t st) {
+    if (pl == 2) relin_ms_fbc_pl<FP, 2, kFoldDigit>(c, acc, d, d_ct_stride, E, count, level, next, st);
+    else if (pl == 1) relin_ms_fbc_pl<FP, 1, kFoldDigit>(c, acc, d, d_ct_stride, E, count, level, next, st);
+    else relin_ms_fbc_pl<FP, 0, kMaxDigit>(c, acc, d, d_ct_stride, E, count, level, next, st);
 }
 void launch_relin_ms_fbc(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
-                         int level, int next, hipStream_t st) {
-    if (use_fp64(c))
-        k_relin_ms_fbc<true><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(
-            acc, d, d_ct_stride, E, c->moddown_f, c->modsw_f + level, c->pinfo, level, c->nQ, c->nP, next, c->N);
-    else
-        k_relin_ms_fbc<false><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(
-            acc, d, d_ct_stride, E, c->moddown, c->modsw + level, c->pinfo, level, c->nQ, c->nP, next, c->N);
+                         int level, int next, int pl, hipStream_t st) {
+    if (use_fp64(c)) relin_ms_fbc_a<true>(c, acc, d, d_ct_stride, E, count, level, next, pl, st);
+    else relin_ms_fbc_a<false>(c, acc, d, d_ct_stride, E, count, level, next, pl, st);
 }
 void launch_relin_ms_combine(const bc_ctx *c, const u64 *d, size_t d_ct_stride, const u64 *acc, const u64 *E, u64 *out,
                              int count, int level, int next, hipStream_t st) {

@@ -488,73 +488,84 @@ __device__ __forceinline__ void load_block(const u64 *blk, typename A::V *v, con
     }
 }
 
-template <int LOGN, bool INV, class A, int EPI>
+// PL > 0 (forward only): the block transforms one of 2^PL parts of a limb of
+// 2^PL N words whose first PL stages the producer of the words has already
+// applied: what remains are the stages on bits LOGN-1 .. 0, whose twiddles
+// are those of the full transform's group `hh` (G = hh, logM = LOGN + PL).
+// Parts always exchange in two rounds, so several blocks share a CU.
+template <int LOGN, bool INV, class A, int EPI, int PL = 0>
 __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__restrict__ tw,
                                               const PrimeInfo *__restrict__ pinfo, const NttCombine *cb) {
+    static_assert(!(PL && INV), "part-limb blocks are forward only");
     using V = typename A::V;
-    constexpr int N = 1 << LOGN, C3 = LOGN - 10, NSPLIT = N > kSplitWords ? 2 : 1;
+    constexpr int N = 1 << LOGN, C3 = LOGN - 10;
+    constexpr bool SP = PL > 0 || N > kSplitWords;
+    constexpr int NSPLIT = SP ? 2 : 1;
+    constexpr int NL = N << PL;        // words of the limb
     constexpr int G3 = 1 << (5 - C3);  // chunk-3 groups per thread
-    constexpr int LW = N > kSplitWords ? kSplitWords : N;
+    constexpr int LW = SP ? N / 2 : N;
     __shared__ u64 s[LW + LW / 32];
     const int t = threadIdx.x;
+    const int job = blockIdx.x >> PL, hh = blockIdx.x & ((1 << PL) - 1);
+    constexpr int LOGM = LOGN + PL;
     int prime;
-    u64 *a = limb_ptr(ls, blockIdx.x, N, prime);
-    const u64 *ain = limb_src(ls, blockIdx.x, N);
-    const A ar(tw, pinfo[prime], prime, N);
+    u64 *a = limb_ptr(ls, job, NL, prime) + hh * N;
+    const u64 *ain = limb_src(ls, job, NL) + hh * N;
+    const A ar(tw, pinfo[prime], prime, NL);
     // word index of register k in each layout
     const int x1 = t;                                                     // + (k << (LOGN - 5))
     const int x2 = ((t >> C3) << (C3 + 5)) | (t & ((1 << C3) - 1));       // + (k << C3)
     const int x3 = t << 5;                                                // + k
     V v[32];
 
-    // exchange 1-2 splits on bit 4 (from t in both layouts), exchange 2-3 on
-    // bit 14 (t's bits 5..9 in both layouts)
-    constexpr bool SP = NSPLIT == 2;
-    const int ra = lds_round<SP, 4>(x1), rb = lds_round<SP, 14>(x3);
-    const int pa1 = lds_pos<SP, 4>(x1), pa2 = lds_pos<SP, 4>(x2);    // exchange 1-2 bases
-    const int pb2 = lds_pos<SP, 14>(x2), pb3 = lds_pos<SP, 14>(x3);  // exchange 2-3 bases
+    // exchange 1-2 splits on bit C3-1 (a bit of t in both layouts), exchange
+    // 2-3 on bit LOGN-1 (t's bit LOGN-6 in both layouts)
+    constexpr int BA = C3 - 1, BB = LOGN - 1;
+    const int ra = lds_round<SP, BA>(x1), rb = lds_round<SP, BB>(x3);
+    const int pa1 = lds_pos<SP, BA>(x1), pa2 = lds_pos<SP, BA>(x2);  // exchange 1-2 bases
+    const int pb2 = lds_pos<SP, BB>(x2), pb3 = lds_pos<SP, BB>(x3);  // exchange 2-3 bases
     if (!INV) {
 #pragma unroll
         for (int k = 0; k < 32; k++) v[k] = ar.load(ain[x1 + (k << (LOGN - 5))]);
-        fwd_chunk<5>(v, ar, LOGN, LOGN - 5, x1, 0, LOGN, true);
+        fwd_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, true);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (ra == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) s[pa1 + lds_pos<SP, 4>(k << (LOGN - 5))] = A::raw(v[k]);
+                for (int k = 0; k < 32; k++) s[pa1 + lds_pos<SP, BA>(k << (LOGN - 5))] = A::raw(v[k]);
             }
             __syncthreads();
             if (ra == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa2 + lds_pos<SP, 4>(k << C3)]);
+                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa2 + lds_pos<SP, BA>(k << C3)]);
             }
             __syncthreads();
         }
-        fwd_chunk<5>(v, ar, LOGN, C3, x2, 0, LOGN, false);
+        fwd_chunk<5>(v, ar, LOGN, C3, x2, hh, LOGM, false);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (rb == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) s[pb2 + lds_pos<SP, 14>(k << C3)] = A::raw(v[k]);
+                for (int k = 0; k < 32; k++) s[pb2 + lds_pos<SP, BB>(k << C3)] = A::raw(v[k]);
             }
             __syncthreads();
             if (rb == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb3 + lds_pos<SP, 14>(k)]);
+                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb3 + lds_pos<SP, BB>(k)]);
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), 0, LOGN, false);
+        for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), hh, LOGM, false);
         // the exchange above ended with a barrier: LDS is free for the wave tiles
         const int wave = t >> 6, lane = t & 63;
         if constexpr (EPI != 0) {
-            const int k = blockIdx.x / ls.npoly, ct = blockIdx.x - k * ls.npoly;
+            const int k = job / ls.npoly, ct = job - k * ls.npoly;
             const int cc = ls.off[k] / cb->level, i = ls.off[k] - cc * cb->level;
             McLimb<A> mc;
-            mc.d = cb->d + (size_t)ct * cb->d_ct_stride + ((size_t)cc * (cb->level + 1) + i) * N;
-            mc.acc = EPI == kNttRelinMs ? cb->acc + (((size_t)ct * 2 + cc) * cb->next + i) * N : nullptr;
-            mc.out = cb->out + (((size_t)ct * 2 + cc) * cb->level + i) * N;
+            mc.d = cb->d + (size_t)ct * cb->d_ct_stride + ((size_t)cc * (cb->level + 1) + i) * NL + hh * N;
+            mc.acc = EPI == kNttRelinMs ? cb->acc + (((size_t)ct * 2 + cc) * cb->next + i) * NL + hh * N : nullptr;
+            mc.out = cb->out + (((size_t)ct * 2 + cc) * cb->level + i) * NL + hh * N;
             mc.w0 = A::pair(cb->w[i]);
             mc.w1 = A::pair(cb->w[i] + 2);
             store_block<A, EPI>(nullptr, v, ar, s + wave * 16 * kTileRow, lane, &mc, wave << 11);
@@ -571,12 +582,12 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
         for (int r = 0; r < NSPLIT; r++) {
             if (rb == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) s[pb3 + lds_pos<SP, 14>(k)] = A::raw(v[k]);
+                for (int k = 0; k < 32; k++) s[pb3 + lds_pos<SP, BB>(k)] = A::raw(v[k]);
             }
             __syncthreads();
             if (rb == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb2 + lds_pos<SP, 14>(k << C3)]);
+                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb2 + lds_pos<SP, BB>(k << C3)]);
             }
             __syncthreads();
         }
@@ -585,12 +596,12 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
         for (int r = 0; r < NSPLIT; r++) {
             if (ra == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) s[pa2 + lds_pos<SP, 4>(k << C3)] = A::raw(v[k]);
+                for (int k = 0; k < 32; k++) s[pa2 + lds_pos<SP, BA>(k << C3)] = A::raw(v[k]);
             }
             __syncthreads();
             if (ra == r) {
 #pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa1 + lds_pos<SP, 4>(k << (LOGN - 5))]);
+                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa1 + lds_pos<SP, BA>(k << (LOGN - 5))]);
             }
             __syncthreads();
         }
@@ -604,6 +615,19 @@ template <int LOGN, bool INV, class A>
 __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const void *__restrict__ tw,
                                                             const PrimeInfo *__restrict__ pinfo) {
     ntt_full_body<LOGN, INV, A, 0>(ls, tw, pinfo, nullptr);
+}
+
+// Parts of 2^(LOGN+PL)-word limbs (2^PL blocks per limb, block 2^PL job +
+// part); at most 128 registers a lane, so that several blocks share a CU.
+template <int LOGN, class A, int PL = 1>
+__global__ void __launch_bounds__(1 << (LOGN - 5), 4) ntt_part(LimbSet ls, const void *__restrict__ tw,
+                                                                         const PrimeInfo *__restrict__ pinfo) {
+    ntt_full_body<LOGN, false, A, 0, PL>(ls, tw, pinfo, nullptr);
+}
+template <int LOGN, class A, int EPI, int PL = 1>
+__global__ void __launch_bounds__(1 << (LOGN - 5), 4)
+    ntt_part_combine(LimbSet ls, const void *__restrict__ tw, const PrimeInfo *__restrict__ pinfo, NttCombine cb) {
+    ntt_full_body<LOGN, false, A, EPI, PL>(ls, tw, pinfo, &cb);
 }
 
 // forward transform of E limbs with an NttCombine step as the store (out
@@ -770,6 +794,63 @@ static bool launch_full_combine_a(int logN, const LimbSet &ls, const NttCombine 
                                   hipStream_t st) {
     return cb.mode == kNttRelinMs ? launch_full_combine<A, kNttRelinMs>(logN, ls, cb, c, st)
                                   : launch_full_combine<A, kNttSwitch>(logN, ls, cb, c, st);
+}
+
+// ----------------------------------------------------------- part limbs
+// Forward transforms whose first PL stages the producer of the words applied:
+// 2^PL blocks of 2^13 words per limb.
+int ntt_parts_log(const bc_ctx *c) {
+    if (!c->ntt_single_pass || !c->ntt_parts || c->alpha > kFoldDigit || c->nP > kFoldDigit) return 0;
+    return c->logN == 15 ? 2 : c->logN == 14 ? 1 : 0;
+}
+
+template <class A>
+static void launch_parts(int pl, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+    const unsigned nblk = (unsigned)(ls.npoly * ls.nlimb) << pl;
+    if (pl == 2) ntt_part<13, A, 2><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
+    else ntt_part<13, A, 1><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
+}
+
+void ntt_forward_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
+    const int pl = ntt_parts_log(c);
+    if (!pl) throw Error(BC_ERR_ARG, "ntt: part-limb transforms are off for this context");
+    if (ls.npoly == 0 || ls.nlimb == 0) return;
+    ProfRec r{};
+    const bool prof = c->prof->on;
+    if (prof) c->prof->begin(kProfNttFwd, ntt_bytes(c, ls), st, r);
+    if (use_fp(c)) launch_parts<FpA>(pl, ls, c, st);
+    else launch_parts<IntA>(pl, ls, c, st);
+    if (prof) c->prof->end(r, st);
+    BC_HIP(hipGetLastError());
+}
+
+template <class A, int EPI>
+static void launch_parts_combine(int pl, const LimbSet &ls, const NttCombine &cb, const bc_ctx *c, hipStream_t st) {
+    const unsigned nblk = (unsigned)(ls.npoly * ls.nlimb) << pl;
+    if (pl == 2) ntt_part_combine<13, A, EPI, 2><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo, cb);
+    else ntt_part_combine<13, A, EPI, 1><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo, cb);
+}
+
+template <class A>
+static void launch_parts_combine_a(int pl, const LimbSet &ls, const NttCombine &cb, const bc_ctx *c,
+                                   hipStream_t st) {
+    if (cb.mode == kNttRelinMs) launch_parts_combine<A, kNttRelinMs>(pl, ls, cb, c, st);
+    else launch_parts_combine<A, kNttSwitch>(pl, ls, cb, c, st);
+}
+
+void ntt_forward_parts_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &cb, hipStream_t st) {
+    const int pl = ntt_parts_log(c);
+    if (!pl) throw Error(BC_ERR_ARG, "ntt: part-limb transforms are off for this context");
+    if (cb.mode != kNttRelinMs && cb.mode != kNttSwitch) throw Error(BC_ERR_ARG, "ntt: unknown combine step");
+    if (ls.npoly == 0 || ls.nlimb == 0) return;
+    ProfRec r{};
+    const bool prof = c->prof->on;
+    const double per_limb = (cb.mode == kNttRelinMs ? 32.0 : 24.0) * c->N;
+    if (prof) c->prof->begin(kProfNttFwdCombine, per_limb * ls.npoly * ls.nlimb, st, r);
+    if (use_fp(c)) launch_parts_combine_a<FpA>(pl, ls, cb, c, st);
+    else launch_parts_combine_a<IntA>(pl, ls, cb, c, st);
+    if (prof) c->prof->end(r, st);
+    BC_HIP(hipGetLastError());
 }
 
 bool ntt_forward_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &cb, hipStream_t st) {

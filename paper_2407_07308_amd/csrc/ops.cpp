@@ -82,6 +82,24 @@ void run_ntt(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j
     }
 }
 
+// Forward transforms of limbs whose first stages their producer applied
+// (ntt_parts_log(c) > 0), in place.
+void run_ntt_parts(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j, hipStream_t st) {
+    for (size_t s = 0; s < j.l.size(); s += kMaxJobs) {
+        LimbSet ls{};
+        ls.base = base;
+        ls.poly_stride = stride;
+        ls.npoly = npoly;
+        ls.nlimb = (int)std::min<size_t>(kMaxJobs, j.l.size() - s);
+        for (int k = 0; k < ls.nlimb; k++) {
+            ls.off[k] = (int16_t)j.l[s + k].off;
+            ls.prime[k] = (int16_t)j.l[s + k].prime;
+            ls.ioff[k] = (int16_t)j.l[s + k].off;
+        }
+        ntt_forward_parts(c, ls, st);
+    }
+}
+
 // all limbs of a [count][ncomp][nl][N] batch
 Jobs all_limbs(int ncomp, int nl) {
     Jobs j;
@@ -107,13 +125,15 @@ BufP ks_accumulate(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int
     Jobs jx;  // coefficient-domain copy of X
     for (int i = 0; i < nl; i++) jx.add(i, i);
     run_ntt(c, xc, (size_t)nl * N, count, jx, true, st, X, x_stride);
-    launch_modup(c, xc, mu, count, level, next, st);
+    const int parts = ntt_parts_log(c);  // the first stages of the new limbs' transforms run in modup
+    launch_modup(c, xc, mu, count, level, next, parts, st);
     Jobs jm;
     for (int j = 0; j < nact; j++) {
         const ModUpPlan &pl = c->h_modup[(size_t)level * dnum + j];
         for (int t = 0; t < pl.ntgt; t++) jm.add(j * next + pl.tgt_e[t], pl.tgt_prime[t]);
     }
-    run_ntt(c, mu, (size_t)dnum * next * N, count, jm, false, st);
+    if (parts) run_ntt_parts(c, mu, (size_t)dnum * next * N, count, jm, st);
+    else run_ntt(c, mu, (size_t)dnum * next * N, count, jm, false, st);
     XC.reset();
     BufP ACC = make_buf(c, sizeof(u64) * (size_t)count * 2 * next * N);
     launch_ks_inner(c, mu, X, x_stride, key, (u64 *)ACC->p, count, level, next, nact, st);
@@ -139,7 +159,8 @@ void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out
     jd.add(nl + lv, lv);
     run_ntt(c, t3.data, 3 * L, count, jd, true, st);
     BufP E = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
-    launch_relin_ms_fbc(c, acc, t3.data, 3 * L, (u64 *)E->p, count, lv, next, st);
+    const int parts = ntt_parts_log(c);  // the first stages of E's transform run in the fbc kernel
+    launch_relin_ms_fbc(c, acc, t3.data, 3 * L, (u64 *)E->p, count, lv, next, parts, st);
     // out = (d + acc P^-1) q_l^-1 - NTT(E): fused into E's transform where the
     // schedule has such a kernel, else transform and combine separately
     NttCombine cb{};
@@ -175,7 +196,9 @@ void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out
         ls.off[k] = (int16_t)k;
         ls.prime[k] = (int16_t)(k % lv);
     }
-    if (!ntt_forward_combine(c, ls, cb, st)) {
+    if (parts) {
+        ntt_forward_parts_combine(c, ls, cb, st);
+    } else if (!ntt_forward_combine(c, ls, cb, st)) {
         run_ntt(c, (u64 *)E->p, (size_t)2 * lv * N, count, all_limbs(2, lv), false, st);
         launch_relin_ms_combine(c, t3.data, 3 * L, acc, (u64 *)E->p, out.data, count, lv, next, st);
     }
@@ -222,7 +245,8 @@ void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st) {
     run_ntt(c, top, (size_t)2 * N, count, jt, true, st, in.data, in.ct_words(N));
     BufP R = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
     u64 *r = (u64 *)R->p;
-    launch_ms_fbc(c, top, r, count, lv, st);
+    const int parts = ntt_parts_log(c);  // the first stages of R's transform run in the fbc kernel
+    launch_ms_fbc(c, top, r, count, lv, parts, st);
     // out = (in - NTT(R)) q_l^-1: fused into R's transform where the schedule
     // has such a kernel, else transform and combine separately
     NttCombine cb{};
@@ -250,7 +274,9 @@ void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st) {
         ls.off[k] = (int16_t)k;
         ls.prime[k] = (int16_t)(k % lv);
     }
-    if (!ntt_forward_combine(c, ls, cb, st)) {
+    if (parts) {
+        ntt_forward_parts_combine(c, ls, cb, st);
+    } else if (!ntt_forward_combine(c, ls, cb, st)) {
         run_ntt(c, r, (size_t)2 * lv * N, count, all_limbs(2, lv), false, st);
         launch_ms_combine(c, in.data, r, out.data, count, lv, st);
     }

@@ -2,8 +2,8 @@
 
 With every prime below 2^50 the transforms run in fp64 arithmetic; the
 integer butterflies remain selectable.  Both must give the same bytes under
-every schedule (single-pass, two-pass whole or chunked), and the
-ciphertexts must equal the oracle's.  With the single-pass schedule the last
+every schedule (single-pass with or without part-limb transforms, two-pass
+whole or chunked), and the ciphertexts must equal the oracle's.  With the single-pass schedule the last
 steps of a multiplication and of a modulus switch run inside the forward
 transform's store; the other schedules run them as separate kernels, so the
 comparison covers both.  Sizes: N = 2^12 .. 2^15, the range of the
@@ -18,18 +18,24 @@ from oracle import Oracle, Params
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [  # (fp64, single pass, chunk bytes)
-    (1, 1, 0), (1, 0, 0), (1, 0, 1 << 20), (0, 1, 0), (0, 0, 0), (0, 0, 1 << 20)]
+SCHEDULES = [  # (fp64, single pass, chunk bytes, part-limb transforms)
+    (1, 1, 0, 1), (1, 1, 0, 0), (1, 0, 0, 1), (1, 0, 1 << 20, 1),
+    (0, 1, 0, 1), (0, 1, 0, 0), (0, 0, 0, 1), (0, 0, 1 << 20, 1)]
 
 
 def run_all(dev, dk, slots, r):
     import paper_2407_07308_amd as bc
 
     outs = []
-    for fp, single, chunk in SCHEDULES:
+    for fp, single, chunk, parts in SCHEDULES:
         dev.set_tuning(bc.BC_TUNE_FP64, fp)
         dev.set_tuning(bc.BC_TUNE_NTT_SINGLE_PASS, single)
         dev.set_tuning(bc.BC_TUNE_NTT_CHUNK_BYTES, chunk)
+        dev.set_tuning(bc.BC_TUNE_NTT_PARTS, parts)
+        # the key-switching producers fold 1 (N = 2^14) or 2 (N = 2^15) stages
+        logN = dev.N.bit_length() - 1
+        folded = logN - 13 if (single and parts and logN >= 14) else 0
+        assert dev.get_tuning(bc.BC_TUNE_NTT_PARTS) == folded
         ct = dev.encrypt(dk, slots, r["u"], r["e"])
         prod = dev.mul_relin(dk, ct, ct)
         ms = dev.mod_switch(ct)
