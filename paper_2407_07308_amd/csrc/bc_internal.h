@@ -170,6 +170,11 @@ struct PrimeInfo {
     // and FPairs
     u64 w123[3][2];
     u64 w123_f[3][2];
+    // inverse twiddles Winv[2], Winv[3] of the second-to-last inverse stage
+    // (N = 2^15), unfolded by the kernels that consume a part-limb inverse
+    // transform: Shoup pairs and FPairs
+    u64 wi23[2][2];
+    u64 wi23_f[2][2];
 };
 
 // The first PL forward stages (PL = 1, 2) of a limb's transform applied to
@@ -215,6 +220,61 @@ __device__ __forceinline__ void fold_fp(double *v, const PrimeInfo &pi) {
     }
 #pragma unroll
     for (int j = 0; j < (1 << PL); j++) v[j] = f_canon(v[j], pi.qd, pi.qinv);
+}
+
+// The last PL inverse stages (PL = 1, 2), N^-1 included, on the 2^PL words
+// v[j] = a[x + j N / 2^PL] of one position after a part-limb inverse
+// transform: with PL = 2 the stage of span N/4 pairs (v0, v1) with Winv[2]
+// and (v2, v3) with Winv[3]; the final stage of span N/2 pairs (v0, v2),
+// (v1, v3) (PL = 2) or (v0, v1) (PL = 1), scaled by N^-1 and N^-1 Winv[1].
+// Canonical words in and out.
+template <int PL>
+__device__ __forceinline__ void unfold_int(u64 *v, const PrimeInfo &pi) {
+    static_assert(PL == 1 || PL == 2, "one or two stages");
+    const u64 q = pi.q;
+    auto gs = [q](u64 &x, u64 &y, u64 w, u64 wp) {
+        const u64 s = add_mod(x, y, q), d = sub_mod(x, y, q);
+        x = s;
+        y = shoup(d, w, wp, q);
+    };
+    auto last = [q, &pi](u64 &x, u64 &y) {
+        const u64 s = add_mod(x, y, q), d = sub_mod(x, y, q);
+        x = shoup(s, pi.ninv, pi.ninvp, q);
+        y = shoup(d, pi.ninvw1, pi.ninvw1p, q);
+    };
+    if constexpr (PL == 1) {
+        last(v[0], v[1]);
+    } else {
+        gs(v[0], v[1], pi.wi23[0][0], pi.wi23[0][1]);
+        gs(v[2], v[3], pi.wi23[1][0], pi.wi23[1][1]);
+        last(v[0], v[2]);
+        last(v[1], v[3]);
+    }
+}
+// fp64: sums below 4 q before the last products (f_mulmod's bound), exact
+template <int PL>
+__device__ __forceinline__ void unfold_fp(double *v, const PrimeInfo &pi) {
+#pragma clang fp contract(off)
+    static_assert(PL == 1 || PL == 2, "one or two stages");
+    const double q = pi.qd;
+    auto last = [q, &pi](double &x, double &y) {
+        const double s = x + y, d = x - y;
+        x = f_mulmod(s, FPair{pi.ninv_d, pi.ninv_q}, q);
+        y = f_mulmod(d, FPair{pi.ninvw1_d, pi.ninvw1_q}, q);
+    };
+    if constexpr (PL == 1) {
+        last(v[0], v[1]);
+    } else {
+        const double d0 = v[0] - v[1], d1 = v[2] - v[3];
+        v[0] = v[0] + v[1];
+        v[2] = v[2] + v[3];
+        v[1] = f_mulmod(d0, fpair(pi.wi23_f[0]), q);
+        v[3] = f_mulmod(d1, fpair(pi.wi23_f[1]), q);
+        last(v[0], v[2]);
+        last(v[1], v[3]);
+    }
+#pragma unroll
+    for (int j = 0; j < (1 << PL); j++) v[j] = f_canon(v[j], q, pi.qinv);
 }
 
 // Fast base conversion from one digit at one level (modulus raising).
@@ -433,5 +493,9 @@ bool ntt_forward_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &c
 int ntt_parts_log(const bc_ctx *c);
 void ntt_forward_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
 void ntt_forward_parts_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &cb, hipStream_t st);
+// Inverse transform of every part of each limb except its last PL stages,
+// which the kernel that consumes the words applies (unfold_int / unfold_fp):
+// modulus raising, and the relinearise+switch and switch corrections.
+void ntt_inverse_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st);
 
 }  // namespace bc

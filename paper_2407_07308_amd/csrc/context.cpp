@@ -445,6 +445,11 @@ void build_context(bc_ctx *c, const bc_params &prm) {
             pi.w123[k - 1][1] = Wp[k];
             set_fpair(pi.w123_f[k - 1], W[k], q);
         }
+        for (int k = 2; k <= 3; k++) {
+            pi.wi23[k - 2][0] = Wi[k];
+            pi.wi23[k - 2][1] = Wip[k];
+            set_fpair(pi.wi23_f[k - 2], Wi[k], q);
+        }
     }
     c->tw = upload(tw.data(), tw.size());
     if (*std::max_element(c->mod.begin(), c->mod.end()) < ((u64)1 << 50)) {

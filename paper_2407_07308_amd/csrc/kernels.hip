@@ -92,9 +92,11 @@ __global__ void k_permute(const u64 *__restrict__ in, u64 *__restrict__ out, con
 
 // Fast base conversion of digit j (z-grid = ct * dnum + j):
 // y_i = [x_i Qhat_i^-1]_{q_i}, u_t = sum_i y_i Qhat_i mod q_t.
-// With PL > 0 a thread takes the 2^PL words n + v N/2^PL of each limb and
-// applies the first PL forward stages of the new limbs' transforms to its
-// outputs (fold_int / fold_fp); MD bounds the digit size at compile time.
+// With PL > 0 a thread takes the 2^PL words n + v N/2^PL of each limb: it
+// applies the last PL stages of the part-limb inverse transform that made xc
+// to its inputs (unfold_int / unfold_fp) and the first PL forward stages of
+// the new limbs' transforms to its outputs (fold_int / fold_fp).  MD bounds
+// the digit size at compile time.
 template <bool FP, int PL = 0, int MD = kMaxDigit>
 __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const ModUpPlan *__restrict__ plans,
                         const PrimeInfo *__restrict__ pinfo, int nl, int next, int dnum, int N) {
@@ -112,8 +114,12 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
         for (int s = 0; s < MD; s++) {
             if (s >= pl.nsrc) break;
             const int i = pl.src_lo + s;
+            u64 x[NV];
 #pragma unroll
-            for (int v = 0; v < NV; v++) y[v][s] = shoup(in[(size_t)i * N + v * Q], pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
+            for (int v = 0; v < NV; v++) x[v] = in[(size_t)i * N + v * Q];
+            if constexpr (PL > 0) unfold_int<PL>(x, pinfo[i]);
+#pragma unroll
+            for (int v = 0; v < NV; v++) y[v][s] = shoup(x[v], pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
         }
         for (int t = 0; t < pl.ntgt; t++) {
             const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
@@ -140,11 +146,12 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
         for (int s = 0; s < MD; s++) {
             if (s >= pl.nsrc) break;
             const PrimeInfo &pi = pinfo[pl.src_lo + s];
+            double x[NV];
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                const double x = f_load(in[(size_t)(pl.src_lo + s) * N + v * Q]);
-                y[v][s] = f_canon(f_mulmod(x, fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
-            }
+            for (int v = 0; v < NV; v++) x[v] = f_load(in[(size_t)(pl.src_lo + s) * N + v * Q]);
+            if constexpr (PL > 0) unfold_fp<PL>(x, pi);
+#pragma unroll
+            for (int v = 0; v < NV; v++) y[v][s] = f_canon(f_mulmod(x[v], fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
         }
         for (int t = 0; t < pl.ntgt; t++) {
             const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
@@ -264,7 +271,7 @@ __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restric
                                u64 *__restrict__ E, const ModDownPlan *__restrict__ md,
                                const ModSwitchPlan *__restrict__ ms, const PrimeInfo *__restrict__ pinfo, int level,
                                int nQ, int nP, int next, int N) {
-    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (first PL forward stages folded)
+    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (PL inverse stages unfolded, PL forward folded)
     const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z, Q = N >> PL;
     const int ct = cc >> 1, c = cc & 1, nl = level + 1;
     const u64 *A = acc + (size_t)cc * next * N + n;
@@ -274,13 +281,34 @@ __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restric
         u64 v[NV][MD], mag[NV];
         bool neg[NV];
         const u64 ql = pinfo[level].q;
+        // inputs: the special limbs and the top limb of the accumulator, the
+        // top limb of d (the last PL inverse stages applied here when PL > 0)
+        u64 sp[NV][MD], top[NV], dt[NV];
+#pragma unroll
+        for (int j = 0; j < MD; j++) {
+            if (j >= nP) break;
+            u64 x[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) x[w] = A[(size_t)(nl + j) * N + w * Q];
+            if constexpr (PL > 0) unfold_int<PL>(x, pinfo[nQ + j]);
+#pragma unroll
+            for (int w = 0; w < NV; w++) sp[w][j] = x[w];
+        }
+#pragma unroll
+        for (int w = 0; w < NV; w++) {
+            top[w] = A[(size_t)level * N + w * Q];
+            dt[w] = D[w * Q];
+        }
+        if constexpr (PL > 0) {
+            unfold_int<PL>(top, pinfo[level]);
+            unfold_int<PL>(dt, pinfo[level]);
+        }
 #pragma unroll
         for (int w = 0; w < NV; w++) {
 #pragma unroll
             for (int j = 0; j < MD; j++) {
                 if (j >= nP) break;
-                u64 x = A[(size_t)(nl + j) * N + w * Q];
-                v[w][j] = shoup(x, md->vfac[j][0], md->vfac[j][1], pinfo[nQ + j].q);
+                v[w][j] = shoup(sp[w][j], md->vfac[j][0], md->vfac[j][1], pinfo[nQ + j].q);
             }
             // top limb of the relinearised component
             u64 th = 0;
@@ -289,10 +317,9 @@ __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restric
                 if (j >= nP) break;
                 th = add_mod(th, shoup(v[w][j], md->phat[level][j][0], md->phat[level][j][1], ql), ql);
             }
-            u64 a = A[(size_t)level * N + w * Q];
-            u64 r = sub_mod(shoup(a, md->pinv[level][0], md->pinv[level][1], ql),
+            u64 r = sub_mod(shoup(top[w], md->pinv[level][0], md->pinv[level][1], ql),
                             shoup(th, md->ppinv[level][0], md->ppinv[level][1], ql), ql);
-            r = add_mod(r, D[w * Q], ql);
+            r = add_mod(r, dt[w], ql);
             const u64 t = shoup(r, ms->pinv_l[0], ms->pinv_l[1], ql);
             neg[w] = t > (ql - 1) / 2;
             mag[w] = neg[w] ? ql - t : t;
@@ -324,15 +351,31 @@ __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restric
         double t[NV];
         const PrimeInfo &pl = pinfo[level];
         const double ql = pl.qd;
+        // inputs: the special limbs and the top limb of the accumulator, the
+        // top limb of d (the last PL inverse stages applied here when PL > 0)
+        double top[NV], dt[NV];
+#pragma unroll
+        for (int j = 0; j < MD; j++) {
+            if (j >= nP) break;
+            const PrimeInfo &pj = pinfo[nQ + j];
+            double x[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) x[w] = f_load(A[(size_t)(nl + j) * N + w * Q]);
+            if constexpr (PL > 0) unfold_fp<PL>(x, pj);
+#pragma unroll
+            for (int w = 0; w < NV; w++) v[w][j] = f_canon(f_mulmod(x[w], fpair(md->vfac[j]), pj.qd), pj.qd, pj.qinv);
+        }
 #pragma unroll
         for (int w = 0; w < NV; w++) {
+            top[w] = f_load(A[(size_t)level * N + w * Q]);
+            dt[w] = f_load(D[w * Q]);
+        }
+        if constexpr (PL > 0) {
+            unfold_fp<PL>(top, pl);
+            unfold_fp<PL>(dt, pl);
+        }
 #pragma unroll
-            for (int j = 0; j < MD; j++) {
-                if (j >= nP) break;
-                const PrimeInfo &pj = pinfo[nQ + j];
-                double x = f_load(A[(size_t)(nl + j) * N + w * Q]);
-                v[w][j] = f_canon(f_mulmod(x, fpair(md->vfac[j]), pj.qd), pj.qd, pj.qinv);
-            }
+        for (int w = 0; w < NV; w++) {
             double th = 0.0;
 #pragma unroll
             for (int j = 0; j < MD; j++) {
@@ -341,9 +384,8 @@ __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restric
                 if ((j & 7) == 7) th = f_reduce(th, ql, pl.qinv);
             }
             th = f_reduce(th, ql, pl.qinv);
-            double a = f_load(A[(size_t)level * N + w * Q]);
-            double r = f_mulmod(a, fpair(md->pinv[level]), ql) - f_mulmod(th, fpair(md->ppinv[level]), ql) +
-                       f_load(D[w * Q]);
+            double r = f_mulmod(top[w], fpair(md->pinv[level]), ql) - f_mulmod(th, fpair(md->ppinv[level]), ql) +
+                       dt[w];
             // the exact centred lift: it enters every other modulus as an integer
             t[w] = f_centre(f_mulmod(r, fpair(ms->pinv_l), ql), ql, pl.qinv);
         }
@@ -394,17 +436,20 @@ __global__ void k_relin_ms_combine(const u64 *__restrict__ d, size_t d_ct_stride
 template <bool FP, int PL = 0>
 __global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const ModSwitchPlan *__restrict__ pl,
                          const PrimeInfo *__restrict__ pinfo, int level, int N) {
-    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (first PL forward stages folded)
+    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (PL inverse stages unfolded, PL forward folded)
     const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z, Q = N >> PL;
     const u64 *T = top + (size_t)cc * N + n;
     u64 *Ro = R + (size_t)cc * level * N + n;
     if constexpr (!FP) {
         const u64 ql = pl->ql;
-        u64 mag[NV];
+        u64 mag[NV], x[NV];
         bool neg[NV];
 #pragma unroll
+        for (int w = 0; w < NV; w++) x[w] = T[w * Q];
+        if constexpr (PL > 0) unfold_int<PL>(x, pinfo[level]);
+#pragma unroll
         for (int w = 0; w < NV; w++) {
-            const u64 t = shoup(T[w * Q], pl->pinv_l[0], pl->pinv_l[1], ql);
+            const u64 t = shoup(x[w], pl->pinv_l[0], pl->pinv_l[1], ql);
             neg[w] = t > (ql - 1) / 2;
             mag[w] = neg[w] ? ql - t : t;  // |t| < q_l < q_i
         }
@@ -424,8 +469,10 @@ __global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const
         const PrimeInfo &pq = pinfo[level];
         double t[NV];
 #pragma unroll
-        for (int w = 0; w < NV; w++)
-            t[w] = f_centre(f_mulmod(f_load(T[w * Q]), fpair(pl->pinv_l), pq.qd), pq.qd, pq.qinv);
+        for (int w = 0; w < NV; w++) t[w] = f_load(T[w * Q]);
+        if constexpr (PL > 0) unfold_fp<PL>(t, pq);
+#pragma unroll
+        for (int w = 0; w < NV; w++) t[w] = f_centre(f_mulmod(t[w], fpair(pl->pinv_l), pq.qd), pq.qd, pq.qinv);
         for (int i = 0; i < level; i++) {
             const PrimeInfo &pi = pinfo[i];
             double r[NV];

@@ -488,15 +488,16 @@ __device__ __forceinline__ void load_block(const u64 *blk, typename A::V *v, con
     }
 }
 
-// PL > 0 (forward only): the block transforms one of 2^PL parts of a limb of
-// 2^PL N words whose first PL stages the producer of the words has already
-// applied: what remains are the stages on bits LOGN-1 .. 0, whose twiddles
-// are those of the full transform's group `hh` (G = hh, logM = LOGN + PL).
-// Parts always exchange in two rounds, so several blocks share a CU.
+// PL > 0: the block transforms one of 2^PL parts of a limb of 2^PL N words.
+// Forward: the producer of the words has already applied the first PL
+// stages, and what remains are the stages on bits LOGN-1 .. 0, whose
+// twiddles are those of the full transform's group `hh` (G = hh, logM =
+// LOGN + PL).  Inverse: the stages on bits 0 .. LOGN-1 of the part, without
+// N^-1; the consumer of the words applies the last PL stages.  Parts always
+// exchange in two rounds, so several blocks share a CU.
 template <int LOGN, bool INV, class A, int EPI, int PL = 0>
 __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__restrict__ tw,
                                               const PrimeInfo *__restrict__ pinfo, const NttCombine *cb) {
-    static_assert(!(PL && INV), "part-limb blocks are forward only");
     using V = typename A::V;
     constexpr int N = 1 << LOGN, C3 = LOGN - 10;
     constexpr bool SP = PL > 0 || N > kSplitWords;
@@ -577,7 +578,7 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
         load_block(ain + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
         __syncthreads();  // every wave is done with its tile before the exchanges reuse LDS
 #pragma unroll
-        for (int j = 0; j < G3; j++) inv_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), 0, LOGN, false, true);
+        for (int j = 0; j < G3; j++) inv_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), hh, LOGM, false, true);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (rb == r) {
@@ -591,7 +592,7 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             }
             __syncthreads();
         }
-        inv_chunk<5>(v, ar, LOGN, C3, x2, 0, LOGN, false, false);
+        inv_chunk<5>(v, ar, LOGN, C3, x2, hh, LOGM, false, false);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (ra == r) {
@@ -605,7 +606,7 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             }
             __syncthreads();
         }
-        inv_chunk<5>(v, ar, LOGN, LOGN - 5, x1, 0, LOGN, true, false);
+        inv_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, PL == 0, false);
 #pragma unroll
         for (int k = 0; k < 32; k++) a[x1 + (k << (LOGN - 5))] = ar.store(v[k]);
     }
@@ -619,10 +620,10 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const vo
 
 // Parts of 2^(LOGN+PL)-word limbs (2^PL blocks per limb, block 2^PL job +
 // part); at most 128 registers a lane, so that several blocks share a CU.
-template <int LOGN, class A, int PL = 1>
+template <int LOGN, class A, int PL = 1, bool INV = false>
 __global__ void __launch_bounds__(1 << (LOGN - 5), 4) ntt_part(LimbSet ls, const void *__restrict__ tw,
                                                                          const PrimeInfo *__restrict__ pinfo) {
-    ntt_full_body<LOGN, false, A, 0, PL>(ls, tw, pinfo, nullptr);
+    ntt_full_body<LOGN, INV, A, 0, PL>(ls, tw, pinfo, nullptr);
 }
 template <int LOGN, class A, int EPI, int PL = 1>
 __global__ void __launch_bounds__(1 << (LOGN - 5), 4)
@@ -820,6 +821,26 @@ void ntt_forward_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (prof) c->prof->begin(kProfNttFwd, ntt_bytes(c, ls), st, r);
     if (use_fp(c)) launch_parts<FpA>(pl, ls, c, st);
     else launch_parts<IntA>(pl, ls, c, st);
+    if (prof) c->prof->end(r, st);
+    BC_HIP(hipGetLastError());
+}
+
+template <class A>
+static void launch_parts_inv(int pl, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+    const unsigned nblk = (unsigned)(ls.npoly * ls.nlimb) << pl;
+    if (pl == 2) ntt_part<13, A, 2, true><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
+    else ntt_part<13, A, 1, true><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
+}
+
+void ntt_inverse_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
+    const int pl = ntt_parts_log(c);
+    if (!pl) throw Error(BC_ERR_ARG, "ntt: part-limb transforms are off for this context");
+    if (ls.npoly == 0 || ls.nlimb == 0) return;
+    ProfRec r{};
+    const bool prof = c->prof->on;
+    if (prof) c->prof->begin(kProfNttInv, ntt_bytes(c, ls), st, r);
+    if (use_fp(c)) launch_parts_inv<FpA>(pl, ls, c, st);
+    else launch_parts_inv<IntA>(pl, ls, c, st);
     if (prof) c->prof->end(r, st);
     BC_HIP(hipGetLastError());
 }

@@ -82,21 +82,26 @@ void run_ntt(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j
     }
 }
 
-// Forward transforms of limbs whose first stages their producer applied
-// (ntt_parts_log(c) > 0), in place.
-void run_ntt_parts(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j, hipStream_t st) {
+// Part-limb transforms (ntt_parts_log(c) > 0), as run_ntt: forward, of limbs
+// whose first stages their producer applied; inverse, leaving the last
+// stages to the kernel that consumes the limbs.
+void run_ntt_parts(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j, bool inverse, hipStream_t st,
+                   const u64 *in = nullptr, size_t in_stride = 0) {
     for (size_t s = 0; s < j.l.size(); s += kMaxJobs) {
         LimbSet ls{};
         ls.base = base;
         ls.poly_stride = stride;
         ls.npoly = npoly;
         ls.nlimb = (int)std::min<size_t>(kMaxJobs, j.l.size() - s);
+        ls.ibase = in;
+        ls.ipoly_stride = in_stride;
         for (int k = 0; k < ls.nlimb; k++) {
             ls.off[k] = (int16_t)j.l[s + k].off;
             ls.prime[k] = (int16_t)j.l[s + k].prime;
-            ls.ioff[k] = (int16_t)j.l[s + k].off;
+            ls.ioff[k] = (int16_t)j.l[s + k].ioff;
         }
-        ntt_forward_parts(c, ls, st);
+        if (inverse) ntt_inverse_parts(c, ls, st);
+        else ntt_forward_parts(c, ls, st);
     }
 }
 
@@ -124,15 +129,18 @@ BufP ks_accumulate(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int
     u64 *mu = (u64 *)MU->p, *xc = (u64 *)XC->p;
     Jobs jx;  // coefficient-domain copy of X
     for (int i = 0; i < nl; i++) jx.add(i, i);
-    run_ntt(c, xc, (size_t)nl * N, count, jx, true, st, X, x_stride);
-    const int parts = ntt_parts_log(c);  // the first stages of the new limbs' transforms run in modup
+    // with part-limb transforms, modup applies the last stages of X's inverse
+    // transform and the first stages of the new limbs' forward transforms
+    const int parts = ntt_parts_log(c);
+    if (parts) run_ntt_parts(c, xc, (size_t)nl * N, count, jx, true, st, X, x_stride);
+    else run_ntt(c, xc, (size_t)nl * N, count, jx, true, st, X, x_stride);
     launch_modup(c, xc, mu, count, level, next, parts, st);
     Jobs jm;
     for (int j = 0; j < nact; j++) {
         const ModUpPlan &pl = c->h_modup[(size_t)level * dnum + j];
         for (int t = 0; t < pl.ntgt; t++) jm.add(j * next + pl.tgt_e[t], pl.tgt_prime[t]);
     }
-    if (parts) run_ntt_parts(c, mu, (size_t)dnum * next * N, count, jm, st);
+    if (parts) run_ntt_parts(c, mu, (size_t)dnum * next * N, count, jm, false, st);
     else run_ntt(c, mu, (size_t)dnum * next * N, count, jm, false, st);
     XC.reset();
     BufP ACC = make_buf(c, sizeof(u64) * (size_t)count * 2 * next * N);
@@ -153,13 +161,20 @@ void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out
         for (int t = 0; t < c->nP; t++) ja.add(cc * next + nl + t, c->nQ + t);
         ja.add(cc * next + lv, lv);
     }
-    run_ntt(c, acc, (size_t)2 * next * N, count, ja, true, st);
     Jobs jd;  // top limb of d0 and d1 (T3 is workspace: transformed in place)
     jd.add(lv, lv);
     jd.add(nl + lv, lv);
-    run_ntt(c, t3.data, 3 * L, count, jd, true, st);
+    // with part-limb transforms the fbc kernel applies the last stages of
+    // these inverse transforms and the first stages of E's forward transform
+    const int parts = ntt_parts_log(c);
+    if (parts) {
+        run_ntt_parts(c, acc, (size_t)2 * next * N, count, ja, true, st);
+        run_ntt_parts(c, t3.data, 3 * L, count, jd, true, st);
+    } else {
+        run_ntt(c, acc, (size_t)2 * next * N, count, ja, true, st);
+        run_ntt(c, t3.data, 3 * L, count, jd, true, st);
+    }
     BufP E = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
-    const int parts = ntt_parts_log(c);  // the first stages of E's transform run in the fbc kernel
     launch_relin_ms_fbc(c, acc, t3.data, 3 * L, (u64 *)E->p, count, lv, next, parts, st);
     // out = (d + acc P^-1) q_l^-1 - NTT(E): fused into E's transform where the
     // schedule has such a kernel, else transform and combine separately
@@ -242,10 +257,13 @@ void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st) {
     Jobs jt;  // the top limb of both components, coefficient domain, into TOP[ct][c]
     jt.add(0, lv, lv);
     jt.add(1, lv, (lv + 1) + lv);
-    run_ntt(c, top, (size_t)2 * N, count, jt, true, st, in.data, in.ct_words(N));
+    // with part-limb transforms the fbc kernel applies the last stages of the
+    // top limbs' inverse transform and the first stages of R's forward one
+    const int parts = ntt_parts_log(c);
+    if (parts) run_ntt_parts(c, top, (size_t)2 * N, count, jt, true, st, in.data, in.ct_words(N));
+    else run_ntt(c, top, (size_t)2 * N, count, jt, true, st, in.data, in.ct_words(N));
     BufP R = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
     u64 *r = (u64 *)R->p;
-    const int parts = ntt_parts_log(c);  // the first stages of R's transform run in the fbc kernel
     launch_ms_fbc(c, top, r, count, lv, parts, st);
     // out = (in - NTT(R)) q_l^-1: fused into R's transform where the schedule
     // has such a kernel, else transform and combine separately
