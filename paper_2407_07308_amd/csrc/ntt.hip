@@ -619,9 +619,11 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const vo
 }
 
 // Parts of 2^(LOGN+PL)-word limbs (2^PL blocks per limb, block 2^PL job +
-// part); at most 128 registers a lane, so that several blocks share a CU.
+// part), several blocks per CU: four waves per SIMD (128 registers a lane)
+// forward; three inverse, whose chunks need more registers (timed faster
+// than four with spills).
 template <int LOGN, class A, int PL = 1, bool INV = false>
-__global__ void __launch_bounds__(1 << (LOGN - 5), 4) ntt_part(LimbSet ls, const void *__restrict__ tw,
+__global__ void __launch_bounds__(1 << (LOGN - 5), INV ? 3 : 4) ntt_part(LimbSet ls, const void *__restrict__ tw,
                                                                          const PrimeInfo *__restrict__ pinfo) {
     ntt_full_body<LOGN, INV, A, 0, PL>(ls, tw, pinfo, nullptr);
 }
