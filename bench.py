@@ -126,9 +126,15 @@ def main():
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     ms_step = e0.elapsed_time(e1) / a.steps
-    fwd_ms, fwd_n, fwd_bytes = dev.profile_read(bc.BC_PROF_NTT_FWD)
-    inv_ms, inv_n, inv_bytes = dev.profile_read(bc.BC_PROF_NTT_INV)
+    prof = {name: dev.profile_read(kind) for name, kind in (
+        ("forward", bc.BC_PROF_NTT_FWD), ("inverse", bc.BC_PROF_NTT_INV),
+        ("forward_part", bc.BC_PROF_NTT_FWD_PART), ("inverse_part", bc.BC_PROF_NTT_INV_PART),
+        ("forward_combine", bc.BC_PROF_NTT_FWD_COMBINE))}
     dev.profile_enable(False)
+    # the roofline kernel: the key-switching forward transform (part-limb
+    # blocks when the producers fold its first stages, else whole limbs)
+    rk = "forward_part" if prof["forward_part"][1] > 0 else "forward"
+    fwd_ms, fwd_n, fwd_bytes = prof[rk]
 
     # results of the last step must be the plaintext answers
     lt, mx, mn = outs
@@ -244,12 +250,16 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, copy-calibrated",
-                     "kernel": ("forward NTT, " + ("single pass" if tuned["single_pass"] else "column pass + row pass")
+                     "kernel": ("forward NTT of the key-switching limbs, "
+                                + ("2^13-word part-limb blocks (first stages folded into modulus raising)"
+                                   if rk == "forward_part" else
+                                   "single pass" if tuned["single_pass"] else "column pass + row pass")
                                 + (", fp64" if tuned.get("fp64") else ", integer") + " arithmetic, 16 N bytes per limb"),
                      "ntt_schedule": tuned,
                      "launches": fwd_n, "avg_launch_us": 1e3 * fwd_ms / max(1, fwd_n),
                      "avg_launch_MB": fwd_bytes / max(1, fwd_n) / 1e6,
-                     "inverse_ntt_GBs": inv_bytes / (inv_ms / 1e3) / 1e9 if inv_ms > 0 else None},
+                     "transforms": {k: {"GBs": b / (ms / 1e3) / 1e9, "launches": n, "avg_launch_us": 1e3 * ms / n}
+                                    for k, (ms, n, b) in prof.items() if n > 0 and ms > 0}},
         "graph_replay_ms_per_step": graph_ms,
         "integer_arithmetic": int_path,
         "per_op_launch": None if per_op is None else {"ms_per_step": per_op, "batched_speedup": per_op / ms_step},
@@ -271,10 +281,14 @@ def ntt_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def is_forward_ntt(name: str) -> str | None:
-    """'a' for the first pass (or the single pass) of a forward transform, 'b' for the second."""
+def is_forward_ntt(name: str, parts: bool) -> str | None:
+    """The roofline kernel's launches: with part-limb transforms, 'a' for each
+    forward part-limb launch; else 'a' for the first pass (or the single pass)
+    of a forward transform and 'b' for the second."""
     import re
 
+    if parts:
+        return "a" if re.search(r"ntt_part<\d+, [^,]+, \d+(, false)?>", name) else None
     m = re.search(r"ntt_(cols|rows|full)<\d+, false[,>]", name)
     if not m:
         return None
@@ -299,15 +313,17 @@ def pmc_summary(fetch_csv: str, write_csv: str, command: str):
         # only the comparison steps (they start with the plane subtraction),
         # as in the timed region; set-up transforms (tuning, encryption) excluded
         first = next(i for i, r in enumerate(rows) if "k_addsub" in r["Kernel_Name"])
+        parts = any("ntt_part<" in r["Kernel_Name"] for r in rows[first:])
         tot, launches = 0.0, 0
         for r in rows[first:]:
-            kind = is_forward_ntt(r["Kernel_Name"])
+            kind = is_forward_ntt(r["Kernel_Name"], parts)
             if kind:
                 tot += float(r["Counter_Value"]) * 1024 * scale
                 launches += kind == "a"
         out[counter] = {"scale": scale, "bytes": tot, "launches": launches}
     per_launch = (out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"]) / max(1, out["FETCH_SIZE"]["launches"])
-    rec = {"kernel": "forward NTT", "source_hash": ntt_source_hash(), "traffic_bytes_per_launch": per_launch,
+    rec = {"kernel": "forward NTT" + (", part-limb blocks" if parts else ""), "source_hash": ntt_source_hash(),
+           "traffic_bytes_per_launch": per_launch,
            "fetch_scale": out["FETCH_SIZE"]["scale"], "write_scale": out["WRITE_SIZE"]["scale"],
            "launches": out["FETCH_SIZE"]["launches"], "command": command}
     with open(TRAFFIC_FILE, "w") as f:

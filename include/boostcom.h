@@ -260,9 +260,19 @@ int bc_autotune(bc_ctx *ctx, void *stream);
  * transforms that also apply the last step of a multiplication
  * (relinearisation and modulus switch) or of a modulus switch as they store
  * (32 N resp. 24 N bytes per limb: the limb, the operand limbs and the output
- * limb).  Reading synchronises on the recorded events; enabling (or
- * disabling) clears earlier records. */
-enum { BC_PROF_NTT_FWD = 0, BC_PROF_NTT_INV = 1, BC_PROF_NTT_FWD_COMBINE = 2 };
+ * limb).  BC_PROF_NTT_FWD_PART and BC_PROF_NTT_INV_PART count the part-limb
+ * transforms of key switching (BC_TUNE_NTT_PARTS; 16 N bytes per limb: the
+ * stages folded into the neighbouring kernels move no extra bytes), and
+ * BC_PROF_NTT_FWD / BC_PROF_NTT_INV then the remaining whole-limb ones.
+ * Reading synchronises on the recorded events; enabling (or disabling) clears
+ * earlier records. */
+enum {
+    BC_PROF_NTT_FWD = 0,
+    BC_PROF_NTT_INV = 1,
+    BC_PROF_NTT_FWD_COMBINE = 2,
+    BC_PROF_NTT_FWD_PART = 3,
+    BC_PROF_NTT_INV_PART = 4
+};
 int bc_profile_enable(bc_ctx *ctx, int32_t on);
 int bc_profile_read(bc_ctx *ctx, int32_t kind, double *ms, int64_t *launches, double *bytes);
 

@@ -369,7 +369,14 @@ struct Pool {
 
 // --------------------------------------------------------------- profiling
 // Optional HIP-event bracketing of kernel launches on their own stream.
-enum ProfKind { kProfNttFwd = 0, kProfNttInv = 1, kProfNttFwdCombine = 2, kProfKinds = 3 };
+enum ProfKind {
+    kProfNttFwd = 0,
+    kProfNttInv = 1,
+    kProfNttFwdCombine = 2,
+    kProfNttFwdPart = 3,
+    kProfNttInvPart = 4,
+    kProfKinds = 5
+};
 struct ProfRec {
     int kind;
     hipEvent_t a, b;

@@ -9,6 +9,8 @@
 // (L+1) x N matrix instead of one per row), plus the base conversions of
 // hybrid key switching and modulus switching.
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace bc {
@@ -179,16 +181,23 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
 // A thread takes kKsCts consecutive ciphertexts: each key word is read once
 // for all of them, and every load is issued before the arithmetic.
 constexpr int kKsCts = 4;
+// FP: the products of two variable residues in fp64 (f_mulmod with the
+// quotient factor w/q formed as w * (1/q): two roundings instead of one, so
+// each product lies within 0.875 q of zero for q < 2^50, and eight of them
+// sum exactly before a reduction).  Otherwise Barrett products on u64.
+template <bool FP>
 __global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ x, size_t x_ct_stride,
                            const u64 *__restrict__ key, u64 *__restrict__ acc, int level, int nQ, int nmod, int next,
                            int nact, int dnum, int alpha, int count, const PrimeInfo *__restrict__ pinfo, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, e = blockIdx.y, ct0 = blockIdx.z * kKsCts;
     const int prime = ext_prime(e, level, nQ);
-    const Barrett br = pinfo[prime].br;
     const int own = e <= level ? e / alpha : -1;
-    u64 s0[kKsCts], s1[kKsCts];
+    using S = typename std::conditional<FP, double, u64>::type;
+    S s0[kKsCts], s1[kKsCts];
 #pragma unroll
     for (int c = 0; c < kKsCts; c++) s0[c] = s1[c] = 0;
+    const Barrett br = pinfo[prime].br;
+    const double q = pinfo[prime].qd, qinv = pinfo[prime].qinv;
     for (int j = 0; j < nact; j++) {
         const u64 *K = key + ((size_t)j * 2 * nmod + prime) * N + n;
         const u64 k0 = K[0], k1 = K[(size_t)nmod * N];
@@ -199,18 +208,42 @@ __global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ x
             u[c] = j == own ? x[(size_t)ct * x_ct_stride + (size_t)e * N + n]
                             : mu[(((size_t)ct * dnum + j) * next + e) * N + n];
         }
+        if constexpr (FP) {
+#pragma clang fp contract(off)
+            const double w0 = f_load(k0), w1 = f_load(k1);
+            const FPair c0{w0, w0 * qinv}, c1{w1, w1 * qinv};
 #pragma unroll
-        for (int c = 0; c < kKsCts; c++) {
-            s0[c] = add_mod(s0[c], mul_mod(u[c], k0, br), br.q);
-            s1[c] = add_mod(s1[c], mul_mod(u[c], k1, br), br.q);
+            for (int c = 0; c < kKsCts; c++) {
+                const double y = f_load(u[c]);
+                s0[c] += f_mulmod(y, c0, q);
+                s1[c] += f_mulmod(y, c1, q);
+                if ((j & 7) == 7) {
+                    s0[c] = f_reduce(s0[c], q, qinv);
+                    s1[c] = f_reduce(s1[c], q, qinv);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < kKsCts; c++) {
+                s0[c] = add_mod(s0[c], mul_mod(u[c], k0, br), br.q);
+                s1[c] = add_mod(s1[c], mul_mod(u[c], k1, br), br.q);
+            }
         }
     }
 #pragma unroll
     for (int c = 0; c < kKsCts; c++) {
         const int ct = ct0 + c;
         if (ct < count) {
-            acc[(((size_t)ct * 2 + 0) * next + e) * N + n] = s0[c];
-            acc[(((size_t)ct * 2 + 1) * next + e) * N + n] = s1[c];
+            u64 r0, r1;
+            if constexpr (FP) {
+                r0 = f_bits(f_canon(s0[c], q, qinv));
+                r1 = f_bits(f_canon(s1[c], q, qinv));
+            } else {
+                r0 = s0[c];
+                r1 = s1[c];
+            }
+            acc[(((size_t)ct * 2 + 0) * next + e) * N + n] = r0;
+            acc[(((size_t)ct * 2 + 1) * next + e) * N + n] = r1;
         }
     }
 }
@@ -797,8 +830,13 @@ void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level,
 }
 void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_stride, const u64 *key, u64 *acc,
                      int count, int level, int next, int nact, hipStream_t st) {
-    k_ks_inner<<<grid3(c->N, next, (count + kKsCts - 1) / kKsCts), kT, 0, st>>>(
-        mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum, c->alpha, count, c->pinfo, c->N);
+    const dim3 g = grid3(c->N, next, (count + kKsCts - 1) / kKsCts);
+    if (use_fp64(c))
+        k_ks_inner<true><<<g, kT, 0, st>>>(mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum,
+                                           c->alpha, count, c->pinfo, c->N);
+    else
+        k_ks_inner<false><<<g, kT, 0, st>>>(mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum,
+                                            c->alpha, count, c->pinfo, c->N);
 }
 void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, hipStream_t st) {
     k_moddown<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(acc, th, c->moddown, c->pinfo, level, c->nQ, c->nP, next, c->N);

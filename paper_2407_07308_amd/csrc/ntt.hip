@@ -820,7 +820,7 @@ void ntt_forward_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (ls.npoly == 0 || ls.nlimb == 0) return;
     ProfRec r{};
     const bool prof = c->prof->on;
-    if (prof) c->prof->begin(kProfNttFwd, ntt_bytes(c, ls), st, r);
+    if (prof) c->prof->begin(kProfNttFwdPart, ntt_bytes(c, ls), st, r);
     if (use_fp(c)) launch_parts<FpA>(pl, ls, c, st);
     else launch_parts<IntA>(pl, ls, c, st);
     if (prof) c->prof->end(r, st);
@@ -840,7 +840,7 @@ void ntt_inverse_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (ls.npoly == 0 || ls.nlimb == 0) return;
     ProfRec r{};
     const bool prof = c->prof->on;
-    if (prof) c->prof->begin(kProfNttInv, ntt_bytes(c, ls), st, r);
+    if (prof) c->prof->begin(kProfNttInvPart, ntt_bytes(c, ls), st, r);
     if (use_fp(c)) launch_parts_inv<FpA>(pl, ls, c, st);
     else launch_parts_inv<IntA>(pl, ls, c, st);
     if (prof) c->prof->end(r, st);
