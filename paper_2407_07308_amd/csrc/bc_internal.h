@@ -200,7 +200,7 @@ __device__ __forceinline__ void fold_int(u64 *v, const PrimeInfo &pi) {
         bfly_int(v[2], v[3], pi.w123[2], pi.q);
     }
 }
-// fp64: |x|, |y| < 1.6 q in, |x| < 2.1 q out (f_mulmod's bound), exact
+// fp64: |x|, |y| < 1.6 q in, |x| < 2.6 q out (f_mulmod's bound), exact
 __device__ __forceinline__ void bfly_fp(double &x, double &y, const u64 *w, double q) {
 #pragma clang fp contract(off)
     const double p = f_mulmod(y, fpair(w), q);
@@ -251,8 +251,10 @@ __device__ __forceinline__ void unfold_int(u64 *v, const PrimeInfo &pi) {
         last(v[1], v[3]);
     }
 }
-// fp64: sums below 4 q before the last products (f_mulmod's bound), exact
-template <int PL>
+// fp64: sums below 4 q before the last products (f_mulmod's bound), exact;
+// results below 1.5 q in magnitude, canonical only with CANON (a consumer
+// that only multiplies or adds them before reducing can skip that)
+template <int PL, bool CANON = true>
 __device__ __forceinline__ void unfold_fp(double *v, const PrimeInfo &pi) {
 #pragma clang fp contract(off)
     static_assert(PL == 1 || PL == 2, "one or two stages");
@@ -273,8 +275,10 @@ __device__ __forceinline__ void unfold_fp(double *v, const PrimeInfo &pi) {
         last(v[0], v[2]);
         last(v[1], v[3]);
     }
+    if constexpr (CANON) {
 #pragma unroll
-    for (int j = 0; j < (1 << PL); j++) v[j] = f_canon(v[j], q, pi.qinv);
+        for (int j = 0; j < (1 << PL); j++) v[j] = f_canon(v[j], q, pi.qinv);
+    }
 }
 
 // Fast base conversion from one digit at one level (modulus raising).

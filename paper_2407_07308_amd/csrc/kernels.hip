@@ -151,7 +151,7 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
             double x[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) x[v] = f_load(in[(size_t)(pl.src_lo + s) * N + v * Q]);
-            if constexpr (PL > 0) unfold_fp<PL>(x, pi);
+            if constexpr (PL > 0) unfold_fp<PL, false>(x, pi);  // |x| < 1.5 q: fine for the product
 #pragma unroll
             for (int v = 0; v < NV; v++) y[v][s] = f_canon(f_mulmod(x[v], fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
         }
@@ -167,7 +167,8 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
                     acc[v] += f_mulmod(y[v][s], fpair(pl.qhat[t][s]), pt.qd);
                     if ((s & 7) == 7) acc[v] = f_reduce(acc[v], pt.qd, pt.qinv);
                 }
-                acc[v] = f_canon(acc[v], pt.qd, pt.qinv);
+                // the fold takes |x| < 1.6 q and returns canonical words
+                acc[v] = PL > 0 ? f_reduce(acc[v], pt.qd, pt.qinv) : f_canon(acc[v], pt.qd, pt.qinv);
             }
             if constexpr (PL > 0) fold_fp<PL>(acc, pt);
 #pragma unroll
@@ -394,7 +395,7 @@ __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restric
             double x[NV];
 #pragma unroll
             for (int w = 0; w < NV; w++) x[w] = f_load(A[(size_t)(nl + j) * N + w * Q]);
-            if constexpr (PL > 0) unfold_fp<PL>(x, pj);
+            if constexpr (PL > 0) unfold_fp<PL, false>(x, pj);  // |x| < 1.5 q: fine for the product
 #pragma unroll
             for (int w = 0; w < NV; w++) v[w][j] = f_canon(f_mulmod(x[w], fpair(md->vfac[j]), pj.qd), pj.qd, pj.qinv);
         }
@@ -403,9 +404,9 @@ __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restric
             top[w] = f_load(A[(size_t)level * N + w * Q]);
             dt[w] = f_load(D[w * Q]);
         }
-        if constexpr (PL > 0) {
-            unfold_fp<PL>(top, pl);
-            unfold_fp<PL>(dt, pl);
+        if constexpr (PL > 0) {  // |.| < 1.5 q: they enter r below through a product and a sum
+            unfold_fp<PL, false>(top, pl);
+            unfold_fp<PL, false>(dt, pl);
         }
 #pragma unroll
         for (int w = 0; w < NV; w++) {
@@ -436,7 +437,8 @@ __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restric
                     e[w] += f_mulmod(v[w][j], fpair(ms->rk1[i][j]), q);
                     if ((j & 7) == 6) e[w] = f_reduce(e[w], q, pi.qinv);
                 }
-                e[w] = f_canon(e[w], q, pi.qinv);
+                // the fold takes |x| < 1.6 q and returns canonical words
+                e[w] = PL > 0 ? f_reduce(e[w], q, pi.qinv) : f_canon(e[w], q, pi.qinv);
             }
             if constexpr (PL > 0) fold_fp<PL>(e, pi);
 #pragma unroll
@@ -503,14 +505,17 @@ __global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const
         double t[NV];
 #pragma unroll
         for (int w = 0; w < NV; w++) t[w] = f_load(T[w * Q]);
-        if constexpr (PL > 0) unfold_fp<PL>(t, pq);
+        if constexpr (PL > 0) unfold_fp<PL, false>(t, pq);  // |t| < 1.5 q: fine for the product
 #pragma unroll
         for (int w = 0; w < NV; w++) t[w] = f_centre(f_mulmod(t[w], fpair(pl->pinv_l), pq.qd), pq.qd, pq.qinv);
         for (int i = 0; i < level; i++) {
             const PrimeInfo &pi = pinfo[i];
             double r[NV];
 #pragma unroll
-            for (int w = 0; w < NV; w++) r[w] = f_canon(f_mulmod(t[w], fpair(pi.p_f), pi.qd), pi.qd, pi.qinv);
+            for (int w = 0; w < NV; w++) {
+                r[w] = f_mulmod(t[w], fpair(pi.p_f), pi.qd);  // |r| < 0.65 q
+                if constexpr (PL == 0) r[w] = f_canon(r[w], pi.qd, pi.qinv);
+            }
             if constexpr (PL > 0) fold_fp<PL>(r, pi);
 #pragma unroll
             for (int w = 0; w < NV; w++) Ro[(size_t)i * N + w * Q] = f_bits(r[w]);
