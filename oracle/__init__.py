@@ -394,6 +394,22 @@ class Oracle:
         r = self.relin(self.tensor(a, b))
         return self.mod_switch(r) if r.level > 0 else r
 
+    def mul_add(self, a: Ct, b: Ct, c: Ct) -> Ct:
+        """a b + c with the addition before the product's relinearisation and
+        modulus switch: tensor a and b, bring the tensor and c to their lower
+        level, add c to the first two components, relinearise, then drop one
+        prime unless at level 0 (one switch for the sum instead of one for the
+        product and another for c)."""
+        t = self.tensor(a, b)
+        lv = min(t.level, c.level)
+        t, c = self.to_level(t, lv), self.to_level(c, lv)
+        d01 = np.ascontiguousarray(t.data[:2])
+        s = self._new(2, lv)
+        self.lib.or_add(self.ctx, _p(d01), _p(c.data), lv, 2, _p(s))
+        t3 = np.concatenate([s, t.data[2:]], axis=0)
+        r = self.relin(Ct(t3, lv))
+        return self.mod_switch(r) if r.level > 0 else r
+
     def modup(self, x: np.ndarray, level: int, digit: int) -> np.ndarray:
         out = np.zeros((level + 1 + self.prm.nP, self.N), np.uint64)
         self.lib.or_modup(self.ctx, _p(np.ascontiguousarray(x)), level, digit, _p(out))
@@ -462,6 +478,10 @@ class IntEvaluator:
         self.mults += 1
         return a * b % self.p
 
+    def mul_add(self, a, b, c):
+        self.mults += 1
+        return (a * b + c) % self.p
+
     def add(self, a, b):
         return (a + b) % self.p
 
@@ -492,6 +512,10 @@ class CtEvaluator:
         self.mults += 1
         return self.o.mul(a, b)
 
+    def mul_add(self, a, b, c):
+        self.mults += 1
+        return self.o.mul_add(a, b, c)
+
     def add(self, a, b):
         return self.o.add(a, b)
 
@@ -519,8 +543,10 @@ def lt_univariate(ev, Z, p: int):
     Z^b, Z^2b, ..., Z^(p-1) by squaring; blocks B_t = sum_{k odd < b} c_{tb+k} Z^k
     (scalar multiplications only, all babies first brought to the lowest baby
     level); the blocks are joined by a binary tree
-    H[t0, t0 + 2^r) = H[t0, t0 + 2^(r-1)) + H[t0 + 2^(r-1), t0 + 2^r) Z^(2^(r-1) b);
-    finally f = H + c_{p-1} Z^(p-1).
+    H[t0, t0 + 2^r) = H[t0, t0 + 2^(r-1)) + H[t0 + 2^(r-1), t0 + 2^r) Z^(2^(r-1) b),
+    each node one multiply-accumulate (the lower half added before the
+    product's modulus switch, see Oracle.mul_add); finally
+    f = H + c_{p-1} Z^(p-1).
 
     Returns (f(Z), Z^(p-1)); Z^(p-1) gives EQ = 1 - Z^(p-1)."""
     e = (p - 1).bit_length() - 1
@@ -551,7 +577,7 @@ def lt_univariate(ev, Z, p: int):
     r = 0
     while len(H) > 1:
         G = giants[r]
-        H = [ev.add(H[2 * i], ev.mul(H[2 * i + 1], G)) for i in range(len(H) // 2)]
+        H = [ev.mul_add(H[2 * i + 1], G, H[2 * i]) for i in range(len(H) // 2)]
         r += 1
     top = giants[-1]
     f = ev.add(H[0], ev.mul_scalar(top, c[p - 1]))
@@ -565,7 +591,8 @@ def eq_from_top(ev, top):
 
 def compare_lt(ev, a_digits, b_digits, p: int):
     """Lexicographic LT over digit planes, most significant first:
-    LT = LT_0 + EQ_0 (LT_1 + EQ_1 (... LT_{n-1}))."""
+    LT = LT_0 + EQ_0 (LT_1 + EQ_1 (... LT_{n-1})), each step one
+    multiply-accumulate."""
     lts, eqs = [], []
     for a, b in zip(a_digits, b_digits):
         f, top = lt_univariate(ev, ev.sub(a, b), p)
@@ -573,14 +600,15 @@ def compare_lt(ev, a_digits, b_digits, p: int):
         eqs.append(eq_from_top(ev, top))
     acc = lts[-1]
     for i in range(len(lts) - 2, -1, -1):
-        acc = ev.add(lts[i], ev.mul(eqs[i], acc))
+        acc = ev.mul_add(eqs[i], acc, lts[i])
     return acc
 
 
 def max_min(ev, a_digits, b_digits, lt):
-    """max_d = a_d + LT (b_d - a_d), min_d = b_d + LT (a_d - b_d), per plane."""
-    mx = [ev.add(a, ev.mul(lt, ev.sub(b, a))) for a, b in zip(a_digits, b_digits)]
-    mn = [ev.add(b, ev.mul(lt, ev.sub(a, b))) for a, b in zip(a_digits, b_digits)]
+    """max_d = a_d + LT (b_d - a_d), min_d = b_d + LT (a_d - b_d), per plane,
+    each one multiply-accumulate."""
+    mx = [ev.mul_add(lt, ev.sub(b, a), a) for a, b in zip(a_digits, b_digits)]
+    mn = [ev.mul_add(lt, ev.sub(a, b), b) for a, b in zip(a_digits, b_digits)]
     return mx, mn
 
 

@@ -13,6 +13,11 @@
 // so each step of the schedule is one launch sequence for the whole batch;
 // the Paterson-Stockmeyer blocks are laid out in bit-reversed block order so
 // that every round of the block tree is one batched multiplication.
+//
+// Every "x + y z" of the schedule (a node of the block tree, a lexicographic
+// step, max and min) is one multiply-accumulate: x is added to the tensor of
+// y and z before relinearisation and the modulus switch, so the sum is
+// switched once (x is never below the product's level here).
 
 #include <algorithm>
 #include <cstring>
@@ -57,6 +62,7 @@ struct LevelEval {
     typedef int V;
     int count = 1;
     V mul(V a, V b) { return out_level_mul(a, b); }
+    V mul_add(V a, V b, V) { return out_level_mul(a, b); }  // the addend is never below the product
     V add(V a, V b) { return std::min(a, b); }
     V sub(V a, V b) { return std::min(a, b); }
     V mul_scalar(V a, int64_t) { return a; }
@@ -88,6 +94,19 @@ struct DevEval {
     V mul(const V &a, const V &b) {
         V o = alloc_ct(c, a.count, out_level_mul(a.level, b.level), 2);
         each(o, a, &b, [&](const V &oo, const V &x, const V &y) { bc::mul_relin(c, k, x, y, oo, st); });
+        return o;
+    }
+    // a b + d: the sum is formed before the product's relinearisation and
+    // modulus switch (one switch instead of one for the product and one for d)
+    V mul_add(const V &a, const V &b, const V &d) {
+        V o = alloc_ct(c, a.count, out_level_mul(a.level, b.level), 2);
+        if (!per_op) {
+            bc::mul_relin_add(c, k, a, b, d, o, st);
+            return o;
+        }
+        const int N = c->N;
+        for (int i = 0; i < a.count; i++)
+            bc::mul_relin_add(c, k, a.slice(i, 1, N), b.slice(i % b.count, 1, N), d.slice(i, 1, N), o.slice(i, 1, N), st);
         return o;
     }
     V add(const V &a, const V &b) {
@@ -217,8 +236,7 @@ std::pair<typename Ev::V, typename Ev::V> lt_poly(Ev &ev, const typename Ev::V &
     while (len > 1) {
         int half = len / 2;
         V lo = ev.slice(H, 0, half * count), hi = ev.slice(H, half * count, half * count);
-        V prod = ev.mul(hi, giants[r]);
-        H = ev.add(lo, prod);
+        H = ev.mul_add(hi, giants[r], lo);
         len = half;
         r++;
     }
@@ -234,7 +252,7 @@ typename Ev::V lexicographic(Ev &ev, const typename Ev::V &f, const typename Ev:
     V eq = ev.add_const(ev.mul_scalar(top, -1), 1);
     V acc = ev.slice(f, (ndig - 1) * count, count);
     for (int d = ndig - 2; d >= 0; d--)
-        acc = ev.add(ev.slice(f, d * count, count), ev.mul(ev.slice(eq, d * count, count), acc));
+        acc = ev.mul_add(ev.slice(eq, d * count, count), acc, ev.slice(f, d * count, count));
     return acc;
 }
 
@@ -267,8 +285,8 @@ CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const
     CompareResult r;
     r.lt = lexicographic(ev, fz.first, fz.second, ndig, G);
     if (want_mm) {
-        r.mx = ev.add(Aall, ev.mul(ev.sub(Ball, Aall), r.lt));
-        r.mn = ev.add(Ball, ev.mul(ev.sub(Aall, Ball), r.lt));
+        r.mx = ev.mul_add(ev.sub(Ball, Aall), r.lt, Aall);
+        r.mn = ev.mul_add(ev.sub(Aall, Ball), r.lt, Ball);
     }
     return r;
 }
@@ -279,7 +297,7 @@ void compare_levels(const bc_ctx *c, int in_level, int ndig, int *lt_level, int 
     auto fz = lt_poly(ev, in_level, sh, 1, 0);
     int lt = lexicographic(ev, fz.first, fz.second, ndig, 1);
     if (lt_level) *lt_level = lt;
-    if (mm_level) *mm_level = ev.add(in_level, ev.mul(ev.sub(in_level, in_level), lt));
+    if (mm_level) *mm_level = ev.mul_add(ev.sub(in_level, in_level), lt, in_level);
 }
 
 }  // namespace bc

@@ -7,7 +7,9 @@ namespace bc {
 
 void build_context(bc_ctx *c, const bc_params &prm);
 
-void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, hipStream_t st);
+// addend: null, or [count][2][nl][N] added to the first two components
+void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, const u64 *addend, u64 *out, int count, int bcount,
+                   int nl, hipStream_t st);
 void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, int ncomp,
                    bool sub, hipStream_t st);
 void launch_mul_scalar(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st);

@@ -23,8 +23,11 @@ __device__ __forceinline__ int ext_prime(int e, int level, int nQ) { return e <=
 
 // ------------------------------------------------------------ ring ops
 
-__global__ void k_tensor(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 *__restrict__ out, int bcount,
-                         int nl, const PrimeInfo *__restrict__ pinfo, int N) {
+// (a0 b0, a0 b1 + a1 b0, a1 b1), plus (c0, c1) on the first two components
+// when an addend c is given (a multiply-accumulate's sum before relinearising)
+template <bool ADD>
+__global__ void k_tensor(const u64 *__restrict__ a, const u64 *__restrict__ b, const u64 *__restrict__ c,
+                         u64 *__restrict__ out, int bcount, int nl, const PrimeInfo *__restrict__ pinfo, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
     const size_t L = (size_t)nl * N;
     const u64 *A = a + (size_t)ct * 2 * L + (size_t)i * N + n;
@@ -32,8 +35,14 @@ __global__ void k_tensor(const u64 *__restrict__ a, const u64 *__restrict__ b, u
     u64 *O = out + (size_t)ct * 3 * L + (size_t)i * N + n;
     const Barrett br = pinfo[i].br;
     u64 a0 = A[0], a1 = A[L], b0 = B[0], b1 = B[L];
-    O[0] = mul_mod(a0, b0, br);
-    O[L] = add_mod(mul_mod(a0, b1, br), mul_mod(a1, b0, br), br.q);
+    u64 d0 = mul_mod(a0, b0, br), d1 = add_mod(mul_mod(a0, b1, br), mul_mod(a1, b0, br), br.q);
+    if constexpr (ADD) {
+        const u64 *C = c + (size_t)ct * 2 * L + (size_t)i * N + n;
+        d0 = add_mod(d0, C[0], br.q);
+        d1 = add_mod(d1, C[L], br.q);
+    }
+    O[0] = d0;
+    O[L] = d1;
     O[2 * L] = mul_mod(a1, b1, br);
 }
 
@@ -791,8 +800,10 @@ inline dim3 grid3(int N, int y, int z) { return dim3((unsigned)(N / kT), (unsign
 
 // ------------------------------------------------------------ launchers
 
-void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, hipStream_t st) {
-    k_tensor<<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, out, bcount, nl, c->pinfo, c->N);
+void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, const u64 *addend, u64 *out, int count, int bcount,
+                   int nl, hipStream_t st) {
+    if (addend) k_tensor<true><<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, addend, out, bcount, nl, c->pinfo, c->N);
+    else k_tensor<false><<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, nullptr, out, bcount, nl, c->pinfo, c->N);
 }
 void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, int ncomp,
                    bool sub, hipStream_t st) {

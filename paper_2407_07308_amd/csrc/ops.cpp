@@ -334,7 +334,7 @@ void tensor(bc_ctx *c, const CtB &a0, const CtB &b0, const CtB &out, hipStream_t
     int lv = std::min(a0.level, b0.level);
     CtB a = to_level(c, a0, lv, st), b = to_level(c, b0, lv, st);
     BC_REQUIRE(out.ncomp == 3 && out.level == lv && out.count == a.count, BC_ERR_ARG, "tensor: output shape");
-    launch_tensor(c, a.data, b.data, out.data, a.count, b.count, lv + 1, st);
+    launch_tensor(c, a.data, b.data, nullptr, out.data, a.count, b.count, lv + 1, st);
     check_hip();
 }
 
@@ -359,6 +359,29 @@ void mul_relin(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const Ct
                "multiplication: output shape");
     CtB t3 = alloc_ct(c, a.count, lv, 3);
     tensor(c, a, b, t3, st);
+    if (lv == 0) {
+        relin(c, k, t3, out, st);
+        return;
+    }
+    relin_mod_switch(c, k, t3, out, st);
+}
+
+// a b + add with the addition before relinearisation and the modulus switch.
+// The addend may sit above the tensor's level (it is switched down to it),
+// not below.
+void mul_relin_add(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const CtB &add, const CtB &out,
+                   hipStream_t st) {
+    check_pair(a, b);
+    const int lv = std::min(a.level, b.level);
+    BC_REQUIRE(add.ncomp == 2 && add.count == a.count, BC_ERR_ARG, "multiply-accumulate: addend shape");
+    BC_REQUIRE(add.level >= lv, BC_ERR_LEVEL, "multiply-accumulate: addend below the product's level");
+    BC_REQUIRE(out.level == out_level_mul(a.level, b.level) && out.ncomp == 2 && out.count == a.count, BC_ERR_ARG,
+               "multiply-accumulate: output shape");
+    BC_REQUIRE(a.ncomp == 2 && b.ncomp == 2, BC_ERR_ARG, "tensor takes 2-component ciphertexts");
+    CtB a2 = to_level(c, a, lv, st), b2 = to_level(c, b, lv, st), c2 = to_level(c, add, lv, st);
+    CtB t3 = alloc_ct(c, a.count, lv, 3);
+    launch_tensor(c, a2.data, b2.data, c2.data, t3.data, a2.count, b2.count, lv + 1, st);
+    check_hip();
     if (lv == 0) {
         relin(c, k, t3, out, st);
         return;

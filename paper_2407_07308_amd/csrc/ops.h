@@ -40,6 +40,8 @@ CtB to_level(bc_ctx *c, const CtB &x, int level, hipStream_t st);
 void tensor(bc_ctx *c, const CtB &a, const CtB &b, const CtB &out, hipStream_t st);
 void relin(bc_ctx *c, const bc_keys *k, const CtB &in3, const CtB &out, hipStream_t st);
 void mul_relin(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const CtB &out, hipStream_t st);
+void mul_relin_add(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const CtB &add, const CtB &out,
+                   hipStream_t st);
 CtB mul(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, hipStream_t st);
 void rotate(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB &out, hipStream_t st);
 void add_sub(bc_ctx *c, const CtB &a, const CtB &b, const CtB &out, bool sub, hipStream_t st);

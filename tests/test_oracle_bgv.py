@@ -121,6 +121,27 @@ def test_mul_relin_and_modswitch_levels(ctx):
     assert np.array_equal(o.decrypt(m2), (u * v * w) % o.p)
 
 
+def test_mul_add_levels_and_values(ctx):
+    """a b + c with the addition before the product's switch: one level
+    below the lower of the tensor and the addend, decrypting to the slotwise
+    a b + c, whichever operand sits higher."""
+    o = ctx
+    u, v, w = rand_slots(o, 18), rand_slots(o, 19), rand_slots(o, 20)
+    cu, cv, cw = enc(o, u, 21, 0), enc(o, v, 21, 1), enc(o, w, 21, 2)
+    top = o.prm.nQ - 1
+    m = o.mul_add(cu, cv, cw)
+    assert m.level == top - 1
+    assert np.array_equal(o.decrypt(m), (u * v + w) % o.p)
+    m1 = o.mul(cu, cv)
+    hi = o.mul_add(m1, cw, cu)  # addend above the tensor: switched down to it
+    assert hi.level == top - 2
+    assert np.array_equal(o.decrypt(hi), (u * v * w + u) % o.p)
+    lo = o.mul_add(cu, cv, m1)  # addend below the tensor: the tensor is switched down
+    assert lo.level == top - 2
+    assert np.array_equal(o.decrypt(lo), (2 * u * v) % o.p)
+    assert o.budget_bits(m) >= o.budget_bits(o.add(cw, o.mul(cu, cv))) - 1
+
+
 def test_mod_switch_exact_division(ctx):
     """c' q_l = c - p t exactly, with t = [c_l p^-1]_{q_l} in (-q_l/2, q_l/2]."""
     o = ctx

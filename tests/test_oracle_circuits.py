@@ -48,6 +48,10 @@ class LevelEvaluator(IntEvaluator):
         self.mults += 1
         return (a[0] * b[0] % self.p, min(a[1], b[1]) - 1)
 
+    def mul_add(self, a, b, c):
+        self.mults += 1
+        return ((a[0] * b[0] + c[0]) % self.p, min(a[1], b[1], c[1]) - 1)
+
     def add(self, a, b):
         return ((a[0] + b[0]) % self.p, min(a[1], b[1]))
 
