@@ -606,9 +606,13 @@ def compare_lt(ev, a_digits, b_digits, p: int):
 
 def max_min(ev, a_digits, b_digits, lt):
     """max_d = a_d + LT (b_d - a_d), min_d = b_d + LT (a_d - b_d), per plane,
-    each one multiply-accumulate."""
-    mx = [ev.mul_add(lt, ev.sub(b, a), a) for a, b in zip(a_digits, b_digits)]
-    mn = [ev.mul_add(lt, ev.sub(a, b), b) for a, b in zip(a_digits, b_digits)]
+    each one multiply-accumulate; a_d and b_d are first brought to LT's level
+    (the differences are formed there)."""
+    lv = ev.level(lt)
+    al = [ev.to_level(a, lv) for a in a_digits]
+    bl = [ev.to_level(b, lv) for b in b_digits]
+    mx = [ev.mul_add(lt, ev.sub(b, a), a) for a, b in zip(al, bl)]
+    mn = [ev.mul_add(lt, ev.sub(a, b), b) for a, b in zip(al, bl)]
     return mx, mn
 
 

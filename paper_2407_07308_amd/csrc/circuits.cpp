@@ -285,8 +285,12 @@ CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const
     CompareResult r;
     r.lt = lexicographic(ev, fz.first, fz.second, ndig, G);
     if (want_mm) {
-        r.mx = ev.mul_add(ev.sub(Ball, Aall), r.lt, Aall);
-        r.mn = ev.mul_add(ev.sub(Aall, Ball), r.lt, Ball);
+        // both operands at LT's level first: the differences are formed there
+        CtB Al = ev.to_level(Aall, r.lt.level), Bl = ev.to_level(Ball, r.lt.level);
+        Aall = CtB();
+        Ball = CtB();
+        r.mx = ev.mul_add(ev.sub(Bl, Al), r.lt, Al);
+        r.mn = ev.mul_add(ev.sub(Al, Bl), r.lt, Bl);
     }
     return r;
 }
@@ -297,7 +301,10 @@ void compare_levels(const bc_ctx *c, int in_level, int ndig, int *lt_level, int 
     auto fz = lt_poly(ev, in_level, sh, 1, 0);
     int lt = lexicographic(ev, fz.first, fz.second, ndig, 1);
     if (lt_level) *lt_level = lt;
-    if (mm_level) *mm_level = ev.mul_add(ev.sub(in_level, in_level), lt, in_level);
+    if (mm_level) {
+        const int al = ev.to_level(in_level, lt);
+        *mm_level = ev.mul_add(ev.sub(al, al), lt, al);
+    }
 }
 
 }  // namespace bc
