@@ -190,7 +190,7 @@ __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const 
 // digit j's own limbs (e in [j alpha, (j+1) alpha)) are X's limbs themselves.
 // A thread takes kKsCts consecutive ciphertexts: each key word is read once
 // for all of them, and every load is issued before the arithmetic.
-constexpr int kKsCts = 4;
+constexpr int kKsCts = 8;
 // FP: the products of two variable residues in fp64 (f_mulmod with the
 // quotient factor w/q formed as w * (1/q): two roundings instead of one, so
 // each product lies within 0.875 q of zero for q < 2^50, and eight of them
