@@ -274,21 +274,27 @@ CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const
         if (c->lt_c.empty()) c->lt_c = lt_coefficients(c->p);
     }
     DevEval ev{c, k, st, c->exec_mode == BC_EXEC_PER_OP};
-    CtB Aall = alloc_ct(c, ndig * G, L0, 2), Ball = alloc_ct(c, ndig * G, L0, 2);
-    for (int d = 0; d < ndig; d++) {
-        copy_ct(c, A[d], Aall.slice(d * G, G, c->N), st);
-        copy_ct(c, B[d], Ball.slice(d * G, G, c->N), st);
-    }
-    CtB Z = bc::sub(c, Aall, Ball, st);
+    const int N = c->N;
+    // the planes of every group as one batch, plane-major, read straight from
+    // the caller's planes: Z = A - B at the input level
+    CtB Z = alloc_ct(c, ndig * G, L0, 2);
+    for (int d = 0; d < ndig; d++)
+        ev.each(Z.slice(d * G, G, N), A[d], &B[d],
+                [&](const CtB &oo, const CtB &x, const CtB &y) { bc::add_sub(c, x, y, oo, true, st); });
     auto fz = lt_poly(ev, Z, sh, ndig * G, c->lt_c[c->p - 1]);
     Z = CtB();
     CompareResult r;
     r.lt = lexicographic(ev, fz.first, fz.second, ndig, G);
     if (want_mm) {
         // both operands at LT's level first: the differences are formed there
-        CtB Al = ev.to_level(Aall, r.lt.level), Bl = ev.to_level(Ball, r.lt.level);
-        Aall = CtB();
-        Ball = CtB();
+        auto at_lt = [&](const CtB *X) {
+            CtB o = alloc_ct(c, ndig * G, r.lt.level, 2);
+            for (int d = 0; d < ndig; d++)
+                ev.each(o.slice(d * G, G, N), X[d], nullptr,
+                        [&](const CtB &oo, const CtB &x, const CtB &) { bc::to_level_into(c, x, oo, st); });
+            return o;
+        };
+        CtB Al = at_lt(A), Bl = at_lt(B);
         r.mx = ev.mul_add(ev.sub(Bl, Al), r.lt, Al);
         r.mn = ev.mul_add(ev.sub(Al, Bl), r.lt, Bl);
     }

@@ -739,16 +739,18 @@ struct BabyArg {
     const u64 *baby[16];
     int pos[64];  // storage position of block t
 };
-// Babies are read at ciphertext blockIdx.z; outputs go to ciphertext
-// ct0 + blockIdx.z of a batch of `count` per block.
+// Component c of ciphertext ct (blockIdx.z = 2 ct + c): babies are read at
+// ciphertext ct; outputs go to ciphertext ct0 + ct of a batch of `count` per
+// block.
 template <bool FP>
 __global__ void k_lincomb(BabyArg ba, const u64 *__restrict__ coef, u64 *__restrict__ out, int nbaby, int nblk,
                           int count, int ct0, int nl, const PrimeInfo *__restrict__ pinfo, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z >> 1;
     const PrimeInfo &pi = pinfo[i];
     const u64 q = pi.q;
     const size_t L = (size_t)nl * N;
-    for (int c = 0; c < 2; c++) {
+    {
+        const int c = blockIdx.z & 1;
         if constexpr (!FP) {
             u64 v[16];
 #pragma unroll
@@ -956,10 +958,10 @@ void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *pos, c
     for (int k = 0; k < nbaby; k++) ba.baby[k] = babies[k];
     for (int t = 0; t < nblk; t++) ba.pos[t] = pos[t];
     if (lincomb_small(c))
-        k_lincomb<true><<<grid3(c->N, nl, nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo,
-                                                                c->N);
+        k_lincomb<true><<<grid3(c->N, nl, 2 * nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl,
+                                                                    c->pinfo, c->N);
     else
-        k_lincomb<false><<<grid3(c->N, nl, nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo,
+        k_lincomb<false><<<grid3(c->N, nl, 2 * nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo,
                                                                  c->N);
 }
 void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st) {

@@ -304,23 +304,33 @@ void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st) {
 // Dropping k >= 2 primes: one inverse transform of every limb, the k
 // single-prime switches fused per coefficient, one forward transform of the
 // remaining limbs (instead of k rounds of top-limb transforms and corrections).
-CtB to_level(bc_ctx *c, const CtB &x, int level, hipStream_t st) {
+void to_level_into(bc_ctx *c, const CtB &x, const CtB &out, hipStream_t st) {
+    const int level = out.level;
     BC_REQUIRE(level >= 0 && level <= x.level, BC_ERR_LEVEL, "cannot raise a level");
-    if (x.level == level) return x;
+    BC_REQUIRE(out.count == x.count && out.ncomp == x.ncomp, BC_ERR_ARG, "level change: output shape");
+    if (x.level == level) {
+        copy_ct(c, x, out, st);
+        return;
+    }
     if (x.level - level == 1) {
-        CtB nx = alloc_ct(c, x.count, level, 2);
-        mod_switch(c, x, nx, st);
-        return nx;
+        mod_switch(c, x, out, st);
+        return;
     }
     BC_REQUIRE(x.ncomp == 2, BC_ERR_ARG, "modulus switching takes 2-component ciphertexts");
     const int N = c->N, nl = x.level + 1;
     BufP T = make_buf(c, sizeof(u64) * (size_t)x.count * 2 * nl * N);
     u64 *t = (u64 *)T->p;
     run_ntt(c, t, (size_t)2 * nl * N, x.count, all_limbs(2, nl), true, st, x.data, x.ct_words(N));
-    CtB out = alloc_ct(c, x.count, level, 2);
     launch_ms_multi(c, t, out.data, x.count, x.level, level, st);
     run_ntt(c, out.data, out.ct_words(N), out.count, all_limbs(2, level + 1), false, st);
     check_hip();
+}
+
+CtB to_level(bc_ctx *c, const CtB &x, int level, hipStream_t st) {
+    BC_REQUIRE(level >= 0 && level <= x.level, BC_ERR_LEVEL, "cannot raise a level");
+    if (x.level == level) return x;
+    CtB out = alloc_ct(c, x.count, level, x.ncomp);
+    to_level_into(c, x, out, st);
     return out;
 }
 
