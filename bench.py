@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--groups", type=int, default=64)
+    ap.add_argument("--split", type=int, default=2,
+                    help="concurrent slices of the batch, each on its own library stream (BC_TUNE_SPLIT_STREAMS)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-op", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -90,6 +92,10 @@ def main():
     rnd = synth.keygen_randomness(SEED, N, prm["nQ"], prm["nP"], prm["dnum"], 0)
     keys = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
     tuned = dev.autotune()
+    # the groups run as SPLIT concurrent slices on library streams (two timed
+    # fastest: 1, 2 and 4 slices gave 165, 159-160 and 164-166 ms a step)
+    dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, a.split)
+    tuned["split_streams"] = a.split
     if a.ntt_chunk_mb is not None:
         dev.set_tuning(bc.BC_TUNE_NTT_CHUNK_BYTES, int(a.ntt_chunk_mb * 2**20))
         dev.set_tuning(bc.BC_TUNE_NTT_SINGLE_PASS, 0)
@@ -155,6 +161,7 @@ def main():
     per_op = None
     if not a.no_per_op:
         dev.set_exec_mode(bc.BC_EXEC_PER_OP)
+        dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, 1)  # the plain path: one stream
         po = dev.compare_max_min(keys, A, B)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -163,6 +170,7 @@ def main():
         per_op = (time.perf_counter() - t0) * 1e3
         same = all(np.array_equal(dev.export(x), dev.export(y)) for x, y in [(po[0], lt)] + list(zip(po[1], mx)))
         dev.set_exec_mode(bc.BC_EXEC_BATCHED)
+        dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, a.split)
         if not same:
             print("bench: per-operation path differs from the batched path", file=sys.stderr)
             sys.exit(3)
@@ -243,7 +251,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"uint16 lexicographic LT+max+min, {G} groups x {M} slots x {NDIG} base-129 planes, "
                                f"BGV N=2^{prm['logN']} p={prm['p']} Q={prm['nQ']}x{prm['bitsQ']}b "
-                               f"P={prm['nP']}x{prm['bitsP']}b dnum={prm['dnum']}, batched",
+                               f"P={prm['nP']}x{prm['bitsP']}b dnum={prm['dnum']}, batched "
+                               f"({a.split} concurrent slices)",
                    "groups": G, "slots": M, "planes": NDIG, "N": N},
         "slot_comparisons_per_s": value * NDIG,
         "wall_ms_per_step": t_wall * 1e3 / a.steps,

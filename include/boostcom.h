@@ -225,6 +225,13 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   with the single-pass schedule and digits of at most 8 primes).  Results
  *   are the same bytes either way.  Reading it returns the number of folded
  *   stages in effect (0 when off or not applicable).
+ *   BC_TUNE_SPLIT_STREAMS (1 .. 16, default 1): bc_compare_lt /
+ *   bc_compare_max_min split the groups of a batch into this many slices,
+ *   each run on a stream of the library's own (default priority) that
+ *   forks from the caller's stream and joins back into it with events, so
+ *   that one slice's compute-bound kernels overlap another's memory-bound
+ *   ones.  Results are the same bytes; the workspace of every slice is drawn
+ *   from the pool under its stream.
  *   BC_TUNE_POOL_LIMIT_BYTES: a bound on the device memory the context's
  *   workspace pool holds, blocks in use plus released blocks kept for reuse
  *   (0, the default: no bound; released blocks are then only given back by
@@ -240,7 +247,8 @@ enum {
     BC_TUNE_NTT_SINGLE_PASS = 1,
     BC_TUNE_FP64 = 2,
     BC_TUNE_POOL_LIMIT_BYTES = 3,
-    BC_TUNE_NTT_PARTS = 4
+    BC_TUNE_NTT_PARTS = 4,
+    BC_TUNE_SPLIT_STREAMS = 5
 };
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);

@@ -23,7 +23,7 @@ BC_ROW_SWAP = -1
 BC_EXEC_BATCHED, BC_EXEC_GRAPH, BC_EXEC_PER_OP = 0, 1, 2
 BC_PROF_NTT_FWD, BC_PROF_NTT_INV, BC_PROF_NTT_FWD_COMBINE, BC_PROF_NTT_FWD_PART, BC_PROF_NTT_INV_PART = 0, 1, 2, 3, 4
 BC_TUNE_NTT_CHUNK_BYTES, BC_TUNE_NTT_SINGLE_PASS, BC_TUNE_FP64, BC_TUNE_POOL_LIMIT_BYTES = 0, 1, 2, 3
-BC_TUNE_NTT_PARTS = 4
+BC_TUNE_NTT_PARTS, BC_TUNE_SPLIT_STREAMS = 4, 5
 
 
 class BoostcomUnavailable(RuntimeError):

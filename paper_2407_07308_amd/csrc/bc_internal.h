@@ -442,6 +442,14 @@ struct bc_ctx {
     std::unique_ptr<bc::GraphCache> graphs;
     std::mutex graph_mu;
     hipStream_t capture_stream = nullptr;      // graph recording (created on first use)
+    // a comparison's groups split over `split` library streams forked from
+    // and joined back into the caller's stream (created on first use, at the
+    // default priority)
+    int split = 1;
+    std::mutex split_mu;
+    std::vector<hipStream_t> split_streams;
+    std::vector<hipEvent_t> split_done;
+    hipEvent_t split_fork = nullptr;
     std::unique_ptr<bc::Profiler> prof{new bc::Profiler()};
     std::mutex table_mu;                       // guards lt_c and ps_coef
     std::vector<int64_t> lt_c;                 // LT polynomial coefficients

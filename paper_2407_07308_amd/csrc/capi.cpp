@@ -65,6 +65,59 @@ void run_compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB 
     }
 }
 
+// run_compare with the groups split over ctx->split library streams (when
+// the batch has that many groups): forked from `origin` by an event, each
+// branch compares its slice of every plane into its slice of every output,
+// and `origin` waits for every branch.  Independent branches let one slice's
+// compute-bound kernels overlap another's memory-bound ones.
+void run_compare_split(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, const bc_ctb *lt_out,
+                       const bc_ctb *max_out, const bc_ctb *min_out, hipStream_t origin) {
+    const int G = A[0].count, n = std::min(c->split, G);
+    if (n <= 1) {
+        run_compare(c, k, ndig, A, B, lt_out, max_out, min_out, origin);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(c->split_mu);
+    while ((int)c->split_streams.size() < n) {
+        hipStream_t s;
+        hipEvent_t e;
+        BC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        c->split_streams.push_back(s);
+        BC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->split_done.push_back(e);
+    }
+    if (!c->split_fork) BC_HIP(hipEventCreateWithFlags(&c->split_fork, hipEventDisableTiming));
+    BC_HIP(hipEventRecord(c->split_fork, origin));
+    auto cut = [&](const bc_ctb *x, int lo, int cnt) {
+        bc_ctb s = *x;
+        s.data = x->data + (size_t)lo * bc_ct_words(c, x->level, x->ncomp);
+        s.count = cnt;
+        return s;
+    };
+    for (int i = 0; i < n; i++) {
+        const int lo = (int)((int64_t)G * i / n), hi = (int)((int64_t)G * (i + 1) / n);
+        std::vector<CtB> a(ndig), b(ndig);
+        std::vector<bc_ctb> mx, mn;
+        for (int d = 0; d < ndig; d++) {
+            a[d] = A[d].slice(lo, hi - lo, c->N);
+            b[d] = B[d].slice(lo, hi - lo, c->N);
+            if (max_out) mx.push_back(cut(&max_out[d], lo, hi - lo));
+            if (min_out) mn.push_back(cut(&min_out[d], lo, hi - lo));
+        }
+        bc_ctb lt;
+        if (lt_out) lt = cut(lt_out, lo, hi - lo);
+        hipStream_t s = c->split_streams[i];
+        BC_HIP(hipStreamWaitEvent(s, c->split_fork, 0));
+        {
+            StreamScope sc(s);
+            run_compare(c, k, ndig, a.data(), b.data(), lt_out ? &lt : nullptr, max_out ? mx.data() : nullptr,
+                        min_out ? mn.data() : nullptr, s);
+        }
+        BC_HIP(hipEventRecord(c->split_done[i], s));
+        BC_HIP(hipStreamWaitEvent(origin, c->split_done[i], 0));
+    }
+}
+
 std::string graph_key(int ndig, const bc_ctb *a, const bc_ctb *b, const bc_ctb *lt, const bc_ctb *mx,
                       const bc_ctb *mn, void *st, const bc_keys *k) {
     std::ostringstream os;
@@ -460,7 +513,7 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
         hipStream_t st = (hipStream_t)stream;
         StreamScope sc(stream);
         if (ctx->exec_mode != BC_EXEC_GRAPH) {
-            run_compare(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, st);
+            run_compare_split(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, st);
             return;
         }
         std::string key = graph_key(ndigits, a_digits, b_digits, lt_out, max_out, min_out, stream, keys);
@@ -472,7 +525,7 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
         }
         // First call of this shape: run eagerly (warms the pool and the
         // coefficient tables), then record the same launch sequence.
-        run_compare(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, st);
+        run_compare_split(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, st);
         BC_HIP(hipStreamSynchronize(st));
         GraphEntry e;
         {
@@ -487,7 +540,7 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
         hipStream_t cap = ctx->capture_stream;
         BC_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
         try {
-            run_compare(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, cap);
+            run_compare_split(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, cap);
         } catch (...) {
             hipGraph_t dead = nullptr;
             (void)hipStreamEndCapture(cap, &dead);
@@ -511,6 +564,11 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
         else if (key == BC_TUNE_NTT_SINGLE_PASS) ctx->ntt_single_pass = value != 0;
         else if (key == BC_TUNE_FP64) ctx->fp64 = value != 0;
         else if (key == BC_TUNE_NTT_PARTS) ctx->ntt_parts = value != 0;
+        else if (key == BC_TUNE_SPLIT_STREAMS) {
+            BC_REQUIRE(value >= 1 && value <= 16, BC_ERR_ARG, "stream split must be in [1, 16]");
+            std::lock_guard<std::mutex> g(ctx->split_mu);
+            ctx->split = (int)value;
+        }
         else if (key == BC_TUNE_POOL_LIMIT_BYTES) {
             std::lock_guard<std::mutex> g(ctx->pool.mu);
             ctx->pool.limit = (size_t)value;
@@ -526,6 +584,7 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
         else if (key == BC_TUNE_NTT_SINGLE_PASS) *value = ctx->ntt_single_pass;
         else if (key == BC_TUNE_FP64) *value = ctx->fp64 && ctx->twf != nullptr;
         else if (key == BC_TUNE_NTT_PARTS) *value = ntt_parts_log(ctx);
+        else if (key == BC_TUNE_SPLIT_STREAMS) *value = ctx->split;
         else if (key == BC_TUNE_POOL_LIMIT_BYTES) *value = (int64_t)ctx->pool.limit;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });

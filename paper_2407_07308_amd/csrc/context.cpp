@@ -506,6 +506,9 @@ void build_context(bc_ctx *c, const bc_params &prm) {
 bc_ctx::~bc_ctx() {
     graphs.reset();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    for (auto s : split_streams) (void)hipStreamDestroy(s);
+    for (auto e : split_done) (void)hipEventDestroy(e);
+    if (split_fork) (void)hipEventDestroy(split_fork);
     (void)hipFree(tw);
     (void)hipFree(twf);
     (void)hipFree(pinfo);

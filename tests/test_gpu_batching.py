@@ -158,6 +158,38 @@ def test_mixed_ring_sizes_at_workload_sizes_concurrently():
         grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)  # replay
 
 
+@pytest.mark.parametrize("mode", ["batched", "graph"])
+def test_split_streams_give_the_same_bytes(mode):
+    """A comparison whose groups run as concurrent slices on library streams
+    (uneven slices: 7 groups over 3 streams) equals the one-stream result,
+    eagerly and under graph replay."""
+    import paper_2407_07308_amd as bc
+
+    prm = Params(10, 257, 12, 50, 4, 50, 3)  # 12 primes: depth for three planes, LT and max
+    dev, dk = member(prm, 12)
+    G = 7
+    xs = synth.integers(81, (G, dev.M), 0, 65536)
+    ys = synth.integers(81, (G, dev.M), 0, 65536, index=1)
+    xs[0, :5] = ys[0, :5]
+    A, B = planes(dev, dk, xs, 820), planes(dev, dk, ys, 830)
+    lt1, mx1, mn1 = dev.compare_max_min(dk, A, B)
+    assert np.array_equal(dev.decrypt(dk, lt1), (xs < ys).astype(np.uint32))
+    ref = [dev.export(x) for x in [lt1] + mx1 + mn1]
+    dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, 3)
+    assert dev.get_tuning(bc.BC_TUNE_SPLIT_STREAMS) == 3
+    if mode == "graph":
+        dev.set_exec_mode(bc.BC_EXEC_GRAPH)
+    outs = dev.compare_max_min(dk, A, B)
+    for rep in range(3):  # eager (graph mode: the recording run), then replays
+        got = [dev.export(x) for x in [outs[0]] + outs[1] + outs[2]]
+        assert all(np.array_equal(g, r) for g, r in zip(got, ref)), f"pass {rep}"
+        for x in [outs[0]] + outs[1] + outs[2]:
+            x.tensor.zero_()
+        dev.compare_max_min(dk, A, B, outs=outs)
+    dev.set_exec_mode(bc.BC_EXEC_BATCHED)
+    assert np.array_equal(dev.decrypt(dk, outs[0]), (xs < ys).astype(np.uint32))
+
+
 def test_workspace_cache_limit_keeps_results():
     """With a workspace cache limit the pool gives its cached blocks back
     whenever it must grow past the limit; results are the same bytes."""
