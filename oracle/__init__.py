@@ -342,9 +342,15 @@ class Oracle:
         return Ct(out, ct.level - 1)
 
     def to_level(self, ct: Ct, level: int) -> Ct:
-        while ct.level > level:
-            ct = self.mod_switch(ct)
-        return ct
+        """ct brought down to `level` for level alignment by dropping its top
+        primes: the residues modulo the smaller modulus, no rescaling.  It
+        decrypts to the same plaintext while its noise is below half the
+        smaller modulus; the operands aligned in the circuit carry noise near
+        the modulus-switching floor, where switching would not lower it."""
+        assert level <= ct.level
+        if ct.level == level:
+            return ct
+        return Ct(np.ascontiguousarray(ct.data[:, : level + 1]), level)
 
     def align(self, a: Ct, b: Ct):
         lv = min(a.level, b.level)

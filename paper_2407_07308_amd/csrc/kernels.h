@@ -29,7 +29,6 @@ void launch_relin_ms_fbc(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d
                          int level, int next, int pl, hipStream_t st);
 void launch_relin_ms_combine(const bc_ctx *c, const u64 *d, size_t d_ct_stride, const u64 *acc, const u64 *E, u64 *out,
                              int count, int level, int next, hipStream_t st);
-void launch_ms_multi(const bc_ctx *c, const u64 *in, u64 *out, int count, int from, int to, hipStream_t st);
 void launch_ms_combine(const bc_ctx *c, const u64 *in, const u64 *R, u64 *out, int count, int level, hipStream_t st);
 void launch_words_mod(const bc_ctx *c, const u64 *w, u64 *out, const int16_t *primes, int npoly, int nlimb,
                       hipStream_t st);

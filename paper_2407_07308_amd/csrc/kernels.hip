@@ -532,82 +532,6 @@ __global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const
     }
 }
 
-// Several primes at once, coefficient domain: drops q_from, q_from-1, ...,
-// q_to+1 in that order, each exactly as a single modulus switch (the NTT is
-// linear, so switching in either domain gives the same residues).  in/out are
-// [ct][2][from+1] and [ct][2][to+1] coefficient-domain limbs.
-constexpr int kMaxDrop = 16;
-template <bool FP>
-__global__ void k_ms_multi(const u64 *__restrict__ in, u64 *__restrict__ out, const ModSwitchPlan *__restrict__ pl,
-                           const PrimeInfo *__restrict__ pinfo, int from, int to, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
-    const int nd = from - to;
-    const u64 *C = in + (size_t)cc * (from + 1) * N + n;
-    u64 *O = out + (size_t)cc * (to + 1) * N + n;
-    if constexpr (!FP) {
-        u64 tmag[kMaxDrop];
-        bool tneg[kMaxDrop];
-        // t_s for s = from, from-1, ..., to+1 (index d = from - s)
-#pragma unroll
-        for (int d = 0; d < kMaxDrop; d++) {
-            if (d >= nd) break;
-            const int s = from - d;
-            const u64 q = pinfo[s].q;
-            u64 c = C[(size_t)s * N];
-#pragma unroll
-            for (int e = 0; e < kMaxDrop; e++) {
-                if (e >= d) break;
-                const int se = from - e;
-                u64 r = shoup(tmag[e], pinfo[s].p_mod, pinfo[s].p_modp, q);
-                r = (tneg[e] && r) ? q - r : r;
-                c = shoup(sub_mod(c, r, q), pl[se].qlinv[s][0], pl[se].qlinv[s][1], q);
-            }
-            u64 t = shoup(c, pl[s].pinv_l[0], pl[s].pinv_l[1], q);
-            tneg[d] = t > (q - 1) / 2;
-            tmag[d] = tneg[d] ? q - t : t;
-        }
-        for (int i = 0; i <= to; i++) {
-            const u64 q = pinfo[i].q;
-            u64 c = C[(size_t)i * N];
-#pragma unroll
-            for (int e = 0; e < kMaxDrop; e++) {
-                if (e >= nd) break;
-                const int se = from - e;
-                u64 r = shoup(tmag[e], pinfo[i].p_mod, pinfo[i].p_modp, q);
-                r = (tneg[e] && r) ? q - r : r;
-                c = shoup(sub_mod(c, r, q), pl[se].qlinv[i][0], pl[se].qlinv[i][1], q);
-            }
-            O[(size_t)i * N] = c;
-        }
-    } else {
-#pragma clang fp contract(off)
-        double t[kMaxDrop];  // exact centred lifts
-#pragma unroll
-        for (int d = 0; d < kMaxDrop; d++) {
-            if (d >= nd) break;
-            const int s = from - d;
-            const PrimeInfo &ps = pinfo[s];
-            double c = f_load(C[(size_t)s * N]);
-#pragma unroll
-            for (int e = 0; e < kMaxDrop; e++) {
-                if (e >= d) break;
-                c = f_mulmod(c - f_mulmod(t[e], fpair(ps.p_f), ps.qd), fpair(pl[from - e].qlinv[s]), ps.qd);
-            }
-            t[d] = f_centre(f_mulmod(c, fpair(pl[s].pinv_l), ps.qd), ps.qd, ps.qinv);
-        }
-        for (int i = 0; i <= to; i++) {
-            const PrimeInfo &pi = pinfo[i];
-            double c = f_load(C[(size_t)i * N]);
-#pragma unroll
-            for (int e = 0; e < kMaxDrop; e++) {
-                if (e >= nd) break;
-                c = f_mulmod(c - f_mulmod(t[e], fpair(pi.p_f), pi.qd), fpair(pl[from - e].qlinv[i]), pi.qd);
-            }
-            O[(size_t)i * N] = f_bits(f_canon(c, pi.qd, pi.qinv));
-        }
-    }
-}
-
 // out[ct][c][i] = (in - R) q_l^-1, i < level
 __global__ void k_ms_combine(const u64 *__restrict__ in, const u64 *__restrict__ R, u64 *__restrict__ out,
                              const ModSwitchPlan *__restrict__ pl, const PrimeInfo *__restrict__ pinfo, int level,
@@ -915,13 +839,6 @@ void launch_relin_ms_combine(const bc_ctx *c, const u64 *d, size_t d_ct_stride, 
     }
     k_relin_ms_combine<<<grid3(c->N, level, count), kT, 0, st>>>(d, d_ct_stride, acc, E, out, pa, c->pinfo, level,
                                                                  next, c->N);
-}
-void launch_ms_multi(const bc_ctx *c, const u64 *in, u64 *out, int count, int from, int to, hipStream_t st) {
-    BC_REQUIRE(from - to <= kMaxDrop, BC_ERR_PARAM, "too many primes dropped at once");
-    if (use_fp64(c))
-        k_ms_multi<true><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(in, out, c->modsw_f, c->pinfo, from, to, c->N);
-    else
-        k_ms_multi<false><<<grid3(c->N, 1, count * 2), kT, 0, st>>>(in, out, c->modsw, c->pinfo, from, to, c->N);
 }
 void launch_ms_combine(const bc_ctx *c, const u64 *in, const u64 *R, u64 *out, int count, int level, hipStream_t st) {
     k_ms_combine<<<grid3(c->N, level, count), kT, 0, st>>>(in, R, out, c->modsw + level, c->pinfo, level, c->N);

@@ -304,6 +304,10 @@ void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st) {
 // Dropping k >= 2 primes: one inverse transform of every limb, the k
 // single-prime switches fused per coefficient, one forward transform of the
 // remaining limbs (instead of k rounds of top-limb transforms and corrections).
+// Level alignment drops the top primes: every component keeps its residues
+// modulo the remaining primes (one strided copy; no rescaling).  The operands
+// aligned in the circuit carry noise near the modulus-switching floor, where
+// a switch would not lower it.
 void to_level_into(bc_ctx *c, const CtB &x, const CtB &out, hipStream_t st) {
     const int level = out.level;
     BC_REQUIRE(level >= 0 && level <= x.level, BC_ERR_LEVEL, "cannot raise a level");
@@ -312,18 +316,9 @@ void to_level_into(bc_ctx *c, const CtB &x, const CtB &out, hipStream_t st) {
         copy_ct(c, x, out, st);
         return;
     }
-    if (x.level - level == 1) {
-        mod_switch(c, x, out, st);
-        return;
-    }
-    BC_REQUIRE(x.ncomp == 2, BC_ERR_ARG, "modulus switching takes 2-component ciphertexts");
-    const int N = c->N, nl = x.level + 1;
-    BufP T = make_buf(c, sizeof(u64) * (size_t)x.count * 2 * nl * N);
-    u64 *t = (u64 *)T->p;
-    run_ntt(c, t, (size_t)2 * nl * N, x.count, all_limbs(2, nl), true, st, x.data, x.ct_words(N));
-    launch_ms_multi(c, t, out.data, x.count, x.level, level, st);
-    run_ntt(c, out.data, out.ct_words(N), out.count, all_limbs(2, level + 1), false, st);
-    check_hip();
+    const size_t limb = sizeof(u64) * c->N;
+    BC_HIP(hipMemcpy2DAsync(out.data, (level + 1) * limb, x.data, (x.level + 1) * limb, (level + 1) * limb,
+                            (size_t)x.count * x.ncomp, hipMemcpyDeviceToDevice, st));
 }
 
 CtB to_level(bc_ctx *c, const CtB &x, int level, hipStream_t st) {

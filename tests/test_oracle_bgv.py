@@ -142,6 +142,21 @@ def test_mul_add_levels_and_values(ctx):
     assert o.budget_bits(m) >= o.budget_bits(o.add(cw, o.mul(cu, cv))) - 1
 
 
+def test_to_level_drops_primes(ctx):
+    """Level alignment keeps the residues modulo the remaining primes: the
+    same plaintext at every lower level, with the noise budget of the smaller
+    modulus (a product's noise sits at the switching floor)."""
+    o = ctx
+    u, v = rand_slots(o, 22), rand_slots(o, 23)
+    m = o.mul(enc(o, u, 24, 0), enc(o, v, 24, 1))
+    for lv in range(m.level - 1, -1, -1):
+        d = o.to_level(m, lv)
+        assert d.level == lv and d.data.shape[1] == lv + 1
+        assert np.array_equal(o.decrypt(d), (u * v) % o.p)
+        if lv > 0:
+            assert o.budget_bits(d) > 10
+
+
 def test_mod_switch_exact_division(ctx):
     """c' q_l = c - p t exactly, with t = [c_l p^-1]_{q_l} in (-q_l/2, q_l/2]."""
     o = ctx
