@@ -121,22 +121,40 @@ def main():
     torch.cuda.synchronize()
 
     # ------------------------------------------------------------ timed
-    dev.profile_enable(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e0.record()
-    for _ in range(a.steps):
-        dev.compare_max_min(keys, A, B, outs=outs)
-    e1.record()
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    ms_step = e0.elapsed_time(e1) / a.steps
-    prof = {name: dev.profile_read(kind) for name, kind in (
-        ("forward", bc.BC_PROF_NTT_FWD), ("inverse", bc.BC_PROF_NTT_INV),
-        ("forward_part", bc.BC_PROF_NTT_FWD_PART), ("inverse_part", bc.BC_PROF_NTT_INV_PART),
-        ("forward_combine", bc.BC_PROF_NTT_FWD_COMBINE))}
-    dev.profile_enable(False)
+    def timed(profile: bool):
+        """ms per step over a.steps steps (and the transform records when profiling)."""
+        dev.profile_enable(profile)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(a.steps):
+            dev.compare_max_min(keys, A, B, outs=outs)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / a.steps
+        rec = None
+        if profile:
+            rec = {name: dev.profile_read(kind) for name, kind in (
+                ("forward", bc.BC_PROF_NTT_FWD), ("inverse", bc.BC_PROF_NTT_INV),
+                ("forward_part", bc.BC_PROF_NTT_FWD_PART), ("inverse_part", bc.BC_PROF_NTT_INV_PART),
+                ("forward_combine", bc.BC_PROF_NTT_FWD_COMBINE))}
+        dev.profile_enable(False)
+        return e0.elapsed_time(e1) / a.steps, wall, rec
+
+    if a.split > 1:
+        # throughput with the slices concurrent; the per-launch transform
+        # figures then come from a second pass with the slices one after
+        # another, where launches do not overlap (an overlapped launch's
+        # duration includes the other slice's kernels)
+        ms_step, wall_step, _ = timed(False)
+        dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, 1)
+        dev.compare_max_min(keys, A, B, outs=outs)  # warms the unsplit workspace
+        unsplit_ms, _, prof = timed(True)
+        dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, a.split)
+    else:
+        ms_step, wall_step, prof = timed(True)
+        unsplit_ms = ms_step
     # the roofline kernel: the key-switching forward transform (part-limb
     # blocks when the producers fold its first stages, else whole limbs)
     rk = "forward_part" if prof["forward_part"][1] > 0 else "forward"
@@ -255,8 +273,11 @@ def main():
                                f"({a.split} concurrent slices)",
                    "groups": G, "slots": M, "planes": NDIG, "N": N},
         "slot_comparisons_per_s": value * NDIG,
-        "wall_ms_per_step": t_wall * 1e3 / a.steps,
+        "wall_ms_per_step": wall_step,
+        "unsplit_ms_per_step": unsplit_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "measured_in": ("the same step with the slices one after another (launches do not overlap)"
+                                     if a.split > 1 else "the timed steps"),
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, copy-calibrated",
                      "kernel": ("forward NTT of the key-switching limbs, "

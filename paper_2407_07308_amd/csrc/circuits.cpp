@@ -69,7 +69,7 @@ struct LevelEval {
     V add_const(V a, int64_t) { return a; }
     int level(V a) { return a; }
     V to_level(V a, int lv) { return std::min(a, lv); }
-    V blocks(const std::vector<V> &babies, int, int) { return babies[0]; }
+    V blocks(const std::vector<V> &, int lv, int, int) { return lv; }
     V slice(V a, int, int) { return a; }
 };
 
@@ -130,15 +130,11 @@ struct DevEval {
         return o;
     }
     int level(const V &a) { return a.level; }
-    V to_level(const V &a, int lv) {
-        if (!per_op || a.level == lv) return bc::to_level(c, a, lv, st);
-        V o = alloc_ct(c, a.count, lv, 2);
-        for (int i = 0; i < a.count; i++) copy_ct(c, bc::to_level(c, a.slice(i, 1, c->N), lv, st), o.slice(i, 1, c->N), st);
-        return o;
-    }
     V slice(const V &a, int first, int n) { return a.slice(first, n, c->N); }
-    // blocks B_t = sum_{k odd < b} c_{tb+k} Z^k for every t, stored at bit-reversed t
-    V blocks(const std::vector<V> &babies, int b, int nblk);
+    // blocks B_t = sum_{k odd < b} c_{tb+k} Z^k for every t at level lv (each
+    // baby's lowest lv + 1 limbs: alignment by dropping primes), stored at
+    // bit-reversed t
+    V blocks(const std::vector<V> &babies, int lv, int b, int nblk);
 };
 
 // Linear-combination coefficients of the Paterson-Stockmeyer blocks, centred
@@ -182,23 +178,26 @@ const u64 *ps_coef_table(bc_ctx *c, int level, int b, int nblk) {
     return d;
 }
 
-DevEval::V DevEval::blocks(const std::vector<V> &babies, int b, int nblk) {
-    const int count = babies[0].count, lv = babies[0].level, nbaby = (int)babies.size();
+DevEval::V DevEval::blocks(const std::vector<V> &babies, int lv, int b, int nblk) {
+    const int count = babies[0].count, nbaby = (int)babies.size();
     const u64 *coef = ps_coef_table(c, lv, b, nblk);
     V out = alloc_ct(c, nblk * count, lv, 2);
     std::vector<const u64 *> bp;
-    for (auto &x : babies) bp.push_back(x.data);
+    std::vector<int> nlb;
+    for (auto &x : babies) {
+        bp.push_back(x.data);
+        nlb.push_back(x.level + 1);
+    }
     int bits = __builtin_ctz(nblk);
     std::vector<int> pos(nblk);
     for (int t = 0; t < nblk; t++) pos[t] = bit_reverse(t, bits);
     if (!per_op) {
-        launch_lincomb(c, bp.data(), pos.data(), coef, out.data, nbaby, nblk, count, 0, count, lv + 1, st);
+        launch_lincomb(c, bp.data(), nlb.data(), pos.data(), coef, out.data, nbaby, nblk, count, 0, count, lv + 1, st);
     } else {
-        const size_t w = babies[0].ct_words(c->N);
         for (int i = 0; i < count; i++) {
             std::vector<const u64 *> bi;
-            for (auto *p : bp) bi.push_back(p + (size_t)i * w);
-            launch_lincomb(c, bi.data(), pos.data(), coef, out.data, nbaby, nblk, count, i, 1, lv + 1, st);
+            for (auto &x : babies) bi.push_back(x.data + (size_t)i * x.ct_words(c->N));
+            launch_lincomb(c, bi.data(), nlb.data(), pos.data(), coef, out.data, nbaby, nblk, count, i, 1, lv + 1, st);
         }
     }
     BC_HIP(hipGetLastError());
@@ -229,9 +228,9 @@ std::pair<typename Ev::V, typename Ev::V> lt_poly(Ev &ev, const typename Ev::V &
     while (((int64_t)b << giants.size()) <= (int64_t)(sh.nblk * b)) giants.push_back(ev.mul(giants.back(), giants.back()));
     int lv = ev.level(pw[1]);
     for (int k : sh.odd) lv = std::min(lv, ev.level(pw[k]));
-    std::vector<V> babies;
-    for (int k : sh.odd) babies.push_back(ev.to_level(pw[k], lv));
-    V H = ev.blocks(babies, b, sh.nblk);
+    std::vector<V> babies;  // brought to lv by the blocks step (lowest lv + 1 limbs)
+    for (int k : sh.odd) babies.push_back(pw[k]);
+    V H = ev.blocks(babies, lv, b, sh.nblk);
     int len = sh.nblk, r = 0;
     while (len > 1) {
         int half = len / 2;

@@ -7,11 +7,13 @@ namespace bc {
 
 void build_context(bc_ctx *c, const bc_params &prm);
 
-// addend: null, or [count][2][nl][N] added to the first two components
+// The output has nl limbs per component; na, nb, nc (>= nl) are the limbs
+// per component the operands are stored with (their lowest nl are read).
+// addend: null, or [count][2][nc][N] added to the first two components.
 void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, const u64 *addend, u64 *out, int count, int bcount,
-                   int nl, hipStream_t st);
-void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, int ncomp,
-                   bool sub, hipStream_t st);
+                   int nl, int na, int nb, int nc, hipStream_t st);
+void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, int na,
+                   int nb, int ncomp, bool sub, hipStream_t st);
 void launch_mul_scalar(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st);
 void launch_add_const(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st);
 void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, int count, int nl, int ncomp,
@@ -40,8 +42,8 @@ void launch_pmul(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int nlim
 void launch_enc_combine(const bc_ctx *c, const u64 *pk, const u64 *U, const u64 *E0, const u64 *E1, u64 *out, int count,
                         hipStream_t st);
 void launch_dec_inner(const bc_ctx *c, const u64 *ct, const u64 *s, u64 *d, int count, int nl, int ncomp, hipStream_t st);
-void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *pos, const u64 *coef, u64 *out, int nbaby,
-                    int nblk, int count, int ct0, int nlaunch, int nl, hipStream_t st);
+void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *nlb, const int *pos, const u64 *coef,
+                    u64 *out, int nbaby, int nblk, int count, int ct0, int nlaunch, int nl, hipStream_t st);
 void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st);
 
 }  // namespace bc

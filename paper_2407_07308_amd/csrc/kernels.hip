@@ -24,38 +24,44 @@ __device__ __forceinline__ int ext_prime(int e, int level, int nQ) { return e <=
 // ------------------------------------------------------------ ring ops
 
 // (a0 b0, a0 b1 + a1 b0, a1 b1), plus (c0, c1) on the first two components
-// when an addend c is given (a multiply-accumulate's sum before relinearising)
+// when an addend c is given (a multiply-accumulate's sum before relinearising).
+// The output has nl limbs; each operand is read at its own limb count (na,
+// nb, nc >= nl): an operand above the output's level contributes its lowest
+// nl limbs (level alignment by dropping primes, without a copy).
 template <bool ADD>
 __global__ void k_tensor(const u64 *__restrict__ a, const u64 *__restrict__ b, const u64 *__restrict__ c,
-                         u64 *__restrict__ out, int bcount, int nl, const PrimeInfo *__restrict__ pinfo, int N) {
+                         u64 *__restrict__ out, int bcount, int nl, int na, int nb, int nc,
+                         const PrimeInfo *__restrict__ pinfo, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    const size_t L = (size_t)nl * N;
-    const u64 *A = a + (size_t)ct * 2 * L + (size_t)i * N + n;
-    const u64 *B = b + (size_t)(ct % bcount) * 2 * L + (size_t)i * N + n;
+    const size_t L = (size_t)nl * N, La = (size_t)na * N, Lb = (size_t)nb * N;
+    const u64 *A = a + (size_t)ct * 2 * La + (size_t)i * N + n;
+    const u64 *B = b + (size_t)(ct % bcount) * 2 * Lb + (size_t)i * N + n;
     u64 *O = out + (size_t)ct * 3 * L + (size_t)i * N + n;
     const Barrett br = pinfo[i].br;
-    u64 a0 = A[0], a1 = A[L], b0 = B[0], b1 = B[L];
+    u64 a0 = A[0], a1 = A[La], b0 = B[0], b1 = B[Lb];
     u64 d0 = mul_mod(a0, b0, br), d1 = add_mod(mul_mod(a0, b1, br), mul_mod(a1, b0, br), br.q);
     if constexpr (ADD) {
-        const u64 *C = c + (size_t)ct * 2 * L + (size_t)i * N + n;
+        const size_t Lc = (size_t)nc * N;
+        const u64 *C = c + (size_t)ct * 2 * Lc + (size_t)i * N + n;
         d0 = add_mod(d0, C[0], br.q);
-        d1 = add_mod(d1, C[L], br.q);
+        d1 = add_mod(d1, C[Lc], br.q);
     }
     O[0] = d0;
     O[L] = d1;
     O[2 * L] = mul_mod(a1, b1, br);
 }
 
-// out = a + sgn * b on ncomp components (sgn = +1 / -1)
+// out = a + sgn * b on ncomp components (sgn = +1 / -1); out has nl limbs,
+// a and b are read at their own limb counts (na, nb >= nl)
 __global__ void k_addsub(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 *__restrict__ out, int bcount,
-                         int nl, int ncomp, int sub, const PrimeInfo *__restrict__ pinfo, int N) {
+                         int nl, int na, int nb, int ncomp, int sub, const PrimeInfo *__restrict__ pinfo, int N) {
     const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    const size_t L = (size_t)nl * N;
+    const size_t L = (size_t)nl * N, La = (size_t)na * N, Lb = (size_t)nb * N;
     const u64 q = pinfo[i].q;
     for (int c = 0; c < ncomp; c++) {
-        size_t off = (size_t)c * L + (size_t)i * N + n;
-        u64 x = a[(size_t)ct * ncomp * L + off], y = b[(size_t)(ct % bcount) * ncomp * L + off];
-        out[(size_t)ct * ncomp * L + off] = sub ? sub_mod(x, y, q) : add_mod(x, y, q);
+        const size_t off = (size_t)i * N + n;
+        u64 x = a[(size_t)ct * ncomp * La + c * La + off], y = b[(size_t)(ct % bcount) * ncomp * Lb + c * Lb + off];
+        out[(size_t)ct * ncomp * L + c * L + off] = sub ? sub_mod(x, y, q) : add_mod(x, y, q);
     }
 }
 
@@ -661,6 +667,7 @@ __global__ void k_crt_decode(const u64 *__restrict__ d, uint32_t *__restrict__ o
 // (sum c h) (2^25 mod q) + sum c l reduced once.
 struct BabyArg {
     const u64 *baby[16];
+    int nlb[16];  // limbs per component each baby is stored with (>= nl: its lowest nl are read)
     int pos[64];  // storage position of block t
 };
 // Component c of ciphertext ct (blockIdx.z = 2 ct + c): babies are read at
@@ -680,7 +687,8 @@ __global__ void k_lincomb(BabyArg ba, const u64 *__restrict__ coef, u64 *__restr
 #pragma unroll
             for (int k = 0; k < 16; k++) {
                 if (k >= nbaby) break;
-                v[k] = ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n];
+                const size_t Lk = (size_t)ba.nlb[k] * N;
+                v[k] = ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n];
             }
             for (int t = 0; t < nblk; t++) {
                 u64 acc = 0;
@@ -699,7 +707,8 @@ __global__ void k_lincomb(BabyArg ba, const u64 *__restrict__ coef, u64 *__restr
 #pragma unroll
             for (int k = 0; k < 16; k++) {
                 if (k >= nbaby) break;
-                const double v = f_load(ba.baby[k][(size_t)ct * 2 * L + (size_t)c * L + (size_t)i * N + n]);
+                const size_t Lk = (size_t)ba.nlb[k] * N;
+                const double v = f_load(ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n]);
                 hi[k] = __builtin_floor(v * 0x1p-25);
                 lo[k] = __builtin_fma(-hi[k], 0x1p25, v);
             }
@@ -727,13 +736,18 @@ inline dim3 grid3(int N, int y, int z) { return dim3((unsigned)(N / kT), (unsign
 // ------------------------------------------------------------ launchers
 
 void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, const u64 *addend, u64 *out, int count, int bcount,
-                   int nl, hipStream_t st) {
-    if (addend) k_tensor<true><<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, addend, out, bcount, nl, c->pinfo, c->N);
-    else k_tensor<false><<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, nullptr, out, bcount, nl, c->pinfo, c->N);
+                   int nl, int na, int nb, int nc, hipStream_t st) {
+    if (addend)
+        k_tensor<true><<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, addend, out, bcount, nl, na, nb, nc, c->pinfo,
+                                                             c->N);
+    else
+        k_tensor<false><<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, nullptr, out, bcount, nl, na, nb, nl, c->pinfo,
+                                                              c->N);
 }
-void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, int ncomp,
-                   bool sub, hipStream_t st) {
-    k_addsub<<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, out, bcount, nl, ncomp, sub ? 1 : 0, c->pinfo, c->N);
+void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, int na,
+                   int nb, int ncomp, bool sub, hipStream_t st) {
+    k_addsub<<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, out, bcount, nl, na, nb, ncomp, sub ? 1 : 0, c->pinfo,
+                                                    c->N);
 }
 static ScalarArg scalar_arg(const bc_ctx *c, int64_t v, int nl) {
     ScalarArg s{};
@@ -868,11 +882,15 @@ void launch_enc_combine(const bc_ctx *c, const u64 *pk, const u64 *U, const u64 
 void launch_dec_inner(const bc_ctx *c, const u64 *ct, const u64 *s, u64 *d, int count, int nl, int ncomp, hipStream_t st) {
     k_dec_inner<<<grid3(c->N, nl, count), kT, 0, st>>>(ct, s, d, nl, ncomp, c->pinfo, c->N);
 }
-void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *pos, const u64 *coef, u64 *out, int nbaby,
-                    int nblk, int count, int ct0, int nlaunch, int nl, hipStream_t st) {
+void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *nlb, const int *pos, const u64 *coef,
+                    u64 *out, int nbaby, int nblk, int count, int ct0, int nlaunch, int nl, hipStream_t st) {
     BC_REQUIRE(nbaby <= 16 && nblk <= 64, BC_ERR_PARAM, "schedule too large");
     BabyArg ba{};
-    for (int k = 0; k < nbaby; k++) ba.baby[k] = babies[k];
+    for (int k = 0; k < nbaby; k++) {
+        BC_REQUIRE(nlb[k] >= nl, BC_ERR_LEVEL, "a baby step below the blocks' level");
+        ba.baby[k] = babies[k];
+        ba.nlb[k] = nlb[k];
+    }
     for (int t = 0; t < nblk; t++) ba.pos[t] = pos[t];
     if (lincomb_small(c))
         k_lincomb<true><<<grid3(c->N, nl, 2 * nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl,

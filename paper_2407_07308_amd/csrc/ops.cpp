@@ -321,13 +321,6 @@ void to_level_into(bc_ctx *c, const CtB &x, const CtB &out, hipStream_t st) {
                             (size_t)x.count * x.ncomp, hipMemcpyDeviceToDevice, st));
 }
 
-CtB to_level(bc_ctx *c, const CtB &x, int level, hipStream_t st) {
-    BC_REQUIRE(level >= 0 && level <= x.level, BC_ERR_LEVEL, "cannot raise a level");
-    if (x.level == level) return x;
-    CtB out = alloc_ct(c, x.count, level, x.ncomp);
-    to_level_into(c, x, out, st);
-    return out;
-}
 
 static void check_pair(const CtB &a, const CtB &b) {
     BC_REQUIRE(b.count >= 1 && a.count % b.count == 0, BC_ERR_ARG, "second operand count must divide the first");
@@ -336,10 +329,9 @@ static void check_pair(const CtB &a, const CtB &b) {
 void tensor(bc_ctx *c, const CtB &a0, const CtB &b0, const CtB &out, hipStream_t st) {
     check_pair(a0, b0);
     BC_REQUIRE(a0.ncomp == 2 && b0.ncomp == 2, BC_ERR_ARG, "tensor takes 2-component ciphertexts");
-    int lv = std::min(a0.level, b0.level);
-    CtB a = to_level(c, a0, lv, st), b = to_level(c, b0, lv, st);
-    BC_REQUIRE(out.ncomp == 3 && out.level == lv && out.count == a.count, BC_ERR_ARG, "tensor: output shape");
-    launch_tensor(c, a.data, b.data, nullptr, out.data, a.count, b.count, lv + 1, st);
+    int lv = std::min(a0.level, b0.level);  // the higher operand is read at its lowest lv + 1 limbs
+    BC_REQUIRE(out.ncomp == 3 && out.level == lv && out.count == a0.count, BC_ERR_ARG, "tensor: output shape");
+    launch_tensor(c, a0.data, b0.data, nullptr, out.data, a0.count, b0.count, lv + 1, a0.level + 1, b0.level + 1, 0, st);
     check_hip();
 }
 
@@ -383,9 +375,10 @@ void mul_relin_add(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, cons
     BC_REQUIRE(out.level == out_level_mul(a.level, b.level) && out.ncomp == 2 && out.count == a.count, BC_ERR_ARG,
                "multiply-accumulate: output shape");
     BC_REQUIRE(a.ncomp == 2 && b.ncomp == 2, BC_ERR_ARG, "tensor takes 2-component ciphertexts");
-    CtB a2 = to_level(c, a, lv, st), b2 = to_level(c, b, lv, st), c2 = to_level(c, add, lv, st);
+    // operands above lv are read at their lowest lv + 1 limbs (alignment by dropping primes)
     CtB t3 = alloc_ct(c, a.count, lv, 3);
-    launch_tensor(c, a2.data, b2.data, c2.data, t3.data, a2.count, b2.count, lv + 1, st);
+    launch_tensor(c, a.data, b.data, add.data, t3.data, a.count, b.count, lv + 1, a.level + 1, b.level + 1,
+                  add.level + 1, st);
     check_hip();
     if (lv == 0) {
         relin(c, k, t3, out, st);
@@ -422,10 +415,10 @@ void rotate(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB &ou
 void add_sub(bc_ctx *c, const CtB &a0, const CtB &b0, const CtB &out, bool sub, hipStream_t st) {
     check_pair(a0, b0);
     BC_REQUIRE(a0.ncomp == b0.ncomp, BC_ERR_ARG, "component counts differ");
-    int lv = std::min(a0.level, b0.level);
-    CtB a = to_level(c, a0, lv, st), b = to_level(c, b0, lv, st);
-    BC_REQUIRE(out.level == lv && out.ncomp == a.ncomp && out.count == a.count, BC_ERR_ARG, "add/sub: output shape");
-    launch_addsub(c, a.data, b.data, out.data, a.count, b.count, lv + 1, a.ncomp, sub, st);
+    int lv = std::min(a0.level, b0.level);  // the higher operand is read at its lowest lv + 1 limbs
+    BC_REQUIRE(out.level == lv && out.ncomp == a0.ncomp && out.count == a0.count, BC_ERR_ARG, "add/sub: output shape");
+    launch_addsub(c, a0.data, b0.data, out.data, a0.count, b0.count, lv + 1, a0.level + 1, b0.level + 1, a0.ncomp, sub,
+                  st);
     check_hip();
 }
 

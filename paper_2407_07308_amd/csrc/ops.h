@@ -36,7 +36,6 @@ CtB alloc_ct(bc_ctx *c, int count, int level, int ncomp);
 CtB from_abi(const bc_ctx *c, const bc_ctb *x);
 
 void mod_switch(bc_ctx *c, const CtB &in, const CtB &out, hipStream_t st);
-CtB to_level(bc_ctx *c, const CtB &x, int level, hipStream_t st);
 // x brought down to out.level, written to out (a copy when the levels agree)
 void to_level_into(bc_ctx *c, const CtB &x, const CtB &out, hipStream_t st);
 void tensor(bc_ctx *c, const CtB &a, const CtB &b, const CtB &out, hipStream_t st);
