@@ -44,9 +44,10 @@ def parse():
     ap.add_argument("--no-per-op", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-int", action="store_true", help="skip the integer-arithmetic comparison run")
-    ap.add_argument("--workload", choices=["uint16", "mixed", "serving"], default="uint16",
+    ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate"], default="uint16",
                     help="uint16: LT+max+min at N=2^15 (default); mixed: 256 single-digit pairs over "
-                         "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream")
+                         "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream; "
+                         "rotate: slot rotations of 192 ciphertexts at N=2^15")
     ap.add_argument("--window", type=float, default=10.0, help="serving: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: mean requests per second")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -78,6 +79,8 @@ def main():
         return mixed(a)
     if a.workload == "serving":
         return serve(a)
+    if a.workload == "rotate":
+        return rotate(a)
     import numpy as np
     import torch
 
@@ -374,6 +377,48 @@ def measured_traffic():
 CHAINS = {13: dict(logN=13, p=257, nQ=8, bitsQ=50, nP=4, bitsP=50, dnum=2),
           14: dict(logN=14, p=257, nQ=8, bitsQ=50, nP=4, bitsP=50, dnum=2),
           15: dict(logN=15, p=257, nQ=14, bitsQ=50, nP=5, bitsP=50, dnum=3)}
+
+
+def rotate(a):
+    """Slot rotations (automorphism + key switch) of a batch of top-level
+    ciphertexts at N=2^15: rotations/s."""
+    import numpy as np
+    import torch
+
+    import paper_2407_07308_amd as bc
+    import synth
+
+    torch.cuda.set_device(0)
+    prm = CHAINS[15]
+    dev = bc.Context(**prm)
+    steps_rot = (1, bc.BC_ROW_SWAP)
+    rnd = synth.keygen_randomness(SEED + 7, dev.N, prm["nQ"], prm["nP"], prm["dnum"], len(steps_rot))
+    keys = dev.keygen(rnd["s"], rnd["a"], rnd["e"], steps_rot)
+    dev.autotune()
+    G = 3 * a.groups  # the comparison batch's ciphertext count
+    vals = synth.slot_values(SEED + 8, G, dev.M, 0, prm["p"])
+    r = synth.encrypt_randomness(SEED + 9, G, dev.N)
+    x = dev.encrypt(keys, vals, r["u"], r["e"])
+    y = dev.rotate(keys, x, 1)  # warm-up
+    half = dev.M // 2
+    want = np.concatenate([np.roll(vals[:, :half], -1, axis=1), np.roll(vals[:, half:], -1, axis=1)], axis=1)
+    if not np.array_equal(dev.decrypt(keys, y), want):
+        print("bench: rotated slots are wrong", file=sys.stderr)
+        sys.exit(3)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        dev.rotate(keys, x, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    print(json.dumps({"metric": "ciphertext rotations/s at N=2^15", "value": G / (ms / 1e3), "unit": "rotations/s",
+                      "n_gpus": 1, "steps": a.steps, "warmup": 1, "ms_per_step": ms, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+                      "slot_rotations_per_s": G * dev.M / (ms / 1e3),
+                      "config": {"workload": f"rotation by one slot of {G} top-level ciphertexts, BGV N=2^15 "
+                                             f"p=257 Q=14x50b P=5x50b dnum=3, batched", "ciphertexts": G}}))
 
 
 def mixed(a):
