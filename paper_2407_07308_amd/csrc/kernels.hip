@@ -27,12 +27,17 @@ __device__ __forceinline__ int ext_prime(int e, int level, int nQ) { return e <=
 // when an addend c is given (a multiply-accumulate's sum before relinearising).
 // The output has nl limbs; each operand is read at its own limb count (na,
 // nb, nc >= nl): an operand above the output's level contributes its lowest
-// nl limbs (level alignment by dropping primes, without a copy).
+// nl limbs (level alignment by dropping primes, without a copy).  When b is
+// broadcast (bcount < count, ciphertext ct uses b[ct % bcount]) the grid runs
+// the count / bcount products that share a b ciphertext back to back, so
+// its limbs come from the cache after the first.
 template <bool ADD>
 __global__ void k_tensor(const u64 *__restrict__ a, const u64 *__restrict__ b, const u64 *__restrict__ c,
                          u64 *__restrict__ out, int bcount, int nl, int na, int nb, int nc,
                          const PrimeInfo *__restrict__ pinfo, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
+    const int rep = gridDim.z / bcount;  // products per b ciphertext
+    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
+    const int ct = (int)(blockIdx.z % rep) * bcount + (int)(blockIdx.z / rep);
     const size_t L = (size_t)nl * N, La = (size_t)na * N, Lb = (size_t)nb * N;
     const u64 *A = a + (size_t)ct * 2 * La + (size_t)i * N + n;
     const u64 *B = b + (size_t)(ct % bcount) * 2 * Lb + (size_t)i * N + n;
