@@ -206,11 +206,15 @@ constexpr int kKsCts = 8;
 // quotient factor w/q formed as w * (1/q): two roundings instead of one, so
 // each product lies within 0.875 q of zero for q < 2^50, and eight of them
 // sum exactly before a reduction).  Otherwise Barrett products on u64.
+// Blocks are numbered so that the ciphertext groups vary fastest: the groups
+// that read the same key words run back to back and find them in the cache.
 template <bool FP>
 __global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ x, size_t x_ct_stride,
                            const u64 *__restrict__ key, u64 *__restrict__ acc, int level, int nQ, int nmod, int next,
                            int nact, int dnum, int alpha, int count, const PrimeInfo *__restrict__ pinfo, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, e = blockIdx.y, ct0 = blockIdx.z * kKsCts;
+    const unsigned lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned zg = lin % gridDim.z, rest = lin / gridDim.z;
+    const int n = (int)(rest % gridDim.x) * kT + threadIdx.x, e = (int)(rest / gridDim.x), ct0 = (int)zg * kKsCts;
     const int prime = ext_prime(e, level, nQ);
     const int own = e <= level ? e / alpha : -1;
     using S = typename std::conditional<FP, double, u64>::type;
