@@ -191,9 +191,11 @@ __device__ __forceinline__ const u64 *limb_src(const LimbSet &ls, int job, int N
 // canonical (just loaded), else they are first brought back into range.  For the stage on bit b
 // the twiddle index is tbase(b) + (k >> (C - s)), s = (blo + C - 1) - b, with
 // tbase(b) = mb(b) + G * 2^(L-1-b) + (X0 >> (b + 1)).
-template <int C, class A>
+// With NPRE > 0 the twiddles of the first NPRE stages come from pre (stage s,
+// group blk at pre[2^s - 1 + blk]), loaded earlier by fwd_twiddles.
+template <int C, class A, int NPRE = 0>
 __device__ __forceinline__ void fwd_chunk(typename A::V *v, const A &ar, int L, int blo, int X0, int G, int logM,
-                                          bool fresh) {
+                                          bool fresh, const typename A::T *pre = nullptr) {
     if (!fresh) {
 #pragma unroll
         for (int k = 0; k < (1 << C); k++) v[k] = ar.prep(v[k]);
@@ -205,10 +207,25 @@ __device__ __forceinline__ void fwd_chunk(typename A::V *v, const A &ar, int L, 
         const int tb = (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
 #pragma unroll
         for (int blk = 0; blk < (1 << s); blk++) {
-            const typename A::T w = ar.fw(tb + blk);
+            const typename A::T w = s < NPRE ? pre[(1 << s) - 1 + blk] : ar.fw(tb + blk);
 #pragma unroll
             for (int j = 0; j < half; j++) ar.ct(v[blk * 2 * half + j], v[blk * 2 * half + j + half], w);
         }
+    }
+}
+
+// Loads the twiddles of the first NPRE stages of fwd_chunk<C> (same indices)
+// into pre, so that a caller can issue them before an LDS exchange, whose
+// barriers wait only for LDS traffic, and find them arrived afterwards.
+template <int C, int NPRE, class A>
+__device__ __forceinline__ void fwd_twiddles(typename A::T *pre, const A &ar, int L, int blo, int X0, int G,
+                                             int logM) {
+#pragma unroll
+    for (int s = 0; s < NPRE; s++) {
+        const int b = blo + C - 1 - s;
+        const int tb = (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
+#pragma unroll
+        for (int blk = 0; blk < (1 << s); blk++) pre[(1 << s) - 1 + blk] = ar.fw(tb + blk);
     }
 }
 
@@ -529,6 +546,12 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
 #pragma unroll
         for (int k = 0; k < 32; k++) v[k] = ar.load(ain[x1 + (k << (LOGN - 5))]);
         fwd_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, true);
+        // with an epilogue, the next chunk's first two stages' twiddles travel
+        // during the exchange (timed faster there; the plain transform, with
+        // fewer registers to spare, was timed slower with it)
+        constexpr int NPRE = EPI != 0 ? 2 : 0;
+        typename A::T pre[3];
+        if constexpr (NPRE > 0) fwd_twiddles<5, NPRE>(pre, ar, LOGN, C3, x2, hh, LOGM);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (ra == r) {
@@ -542,7 +565,7 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             }
             __syncthreads();
         }
-        fwd_chunk<5>(v, ar, LOGN, C3, x2, hh, LOGM, false);
+        fwd_chunk<5, A, NPRE>(v, ar, LOGN, C3, x2, hh, LOGM, false, pre);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (rb == r) {
