@@ -138,10 +138,7 @@ def main():
         wall = (time.perf_counter() - t0) * 1e3 / a.steps
         rec = None
         if profile:
-            rec = {name: dev.profile_read(kind) for name, kind in (
-                ("forward", bc.BC_PROF_NTT_FWD), ("inverse", bc.BC_PROF_NTT_INV),
-                ("forward_part", bc.BC_PROF_NTT_FWD_PART), ("inverse_part", bc.BC_PROF_NTT_INV_PART),
-                ("forward_combine", bc.BC_PROF_NTT_FWD_COMBINE))}
+            rec = {name: dev.profile_read(getattr(bc, k["prof"])) for name, k in KINDS.items()}
         dev.profile_enable(False)
         return e0.elapsed_time(e1) / a.steps, wall, rec
 
@@ -158,10 +155,14 @@ def main():
     else:
         ms_step, wall_step, prof = timed(True)
         unsplit_ms = ms_step
-    # the roofline kernel: the key-switching forward transform (part-limb
-    # blocks when the producers fold its first stages, else whole limbs)
-    rk = "forward_part" if prof["forward_part"][1] > 0 else "forward"
-    fwd_ms, fwd_n, fwd_bytes = prof[rk]
+    # the roofline kernel: the kernel kind of the key-switching path with the
+    # most time in the step; every kind is listed with its achieved GB/s
+    rk = max((k for k in KINDS if k != "mul" and prof[k][1] > 0), key=lambda k: prof[k][0])
+    rk_ms, rk_n, rk_bytes = prof[rk]
+    # the comparisons roofline: fused-minimum bytes of every multiplication
+    # of the step at its level, at 8 TB/s, against the measured step
+    mul_ms, mul_n, mul_bytes = prof["mul"]
+    step_min_bytes = mul_bytes / a.steps
 
     # results of the last step must be the plaintext answers
     lt, mx, mn = outs
@@ -174,8 +175,9 @@ def main():
 
     comparisons = G * M
     value = comparisons / (ms_step / 1e3)
-    achieved = fwd_bytes / (fwd_ms / 1e3) / 1e9 if fwd_ms > 0 else 0.0
-    traffic = measured_traffic()
+    achieved = rk_bytes / (rk_ms / 1e3) / 1e9 if rk_ms > 0 else 0.0
+    traffic = measured_traffic(rk)
+    step_bytes = [dev.export(x) for x in [lt] + mx + mn]  # the step's results, coefficient domain
 
     # ------------------------------------------------- per-op launch path
     # same circuit, same kernels, one ciphertext per launch
@@ -232,9 +234,13 @@ def main():
         torch.cuda.synchronize()
         graph_ms = g0.elapsed_time(g1) / a.steps
         dev.set_exec_mode(bc.BC_EXEC_BATCHED)
+        if not all(np.array_equal(dev.export(x), y) for x, y in zip([lt] + mx + mn, step_bytes)):
+            print("bench: graph replay differs from the eager step", file=sys.stderr)
+            sys.exit(3)
 
     # ------------------------------------------------------ CPU oracle
     cpu = None
+    oracle_parity = None
     if not a.no_cpu_baseline:
         import oracle
 
@@ -249,8 +255,14 @@ def main():
         ev = oracle.CtEvaluator(orc)
         t0 = time.perf_counter()
         o_lt = oracle.compare_lt(ev, oa, ob, prm["p"])
-        oracle.max_min(ev, oa, ob, o_lt)
+        o_mx, o_mn = oracle.max_min(ev, oa, ob, o_lt)
         t_cpu = time.perf_counter() - t0
+        # group 0 of the timed step, residue for residue
+        oracle_parity = all(np.array_equal(got[0], want.data)
+                            for got, want in zip(step_bytes, [o_lt] + o_mx + o_mn))
+        if not oracle_parity:
+            print("bench: group 0 differs from the oracle", file=sys.stderr)
+            sys.exit(3)
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         cores = min(cores, os.cpu_count() or cores)
         cpu = {"value": M / t_cpu, "unit": "comparisons/s", "cores": cores, "kind": "oracle",
@@ -279,62 +291,87 @@ def main():
         "wall_ms_per_step": wall_step,
         "unsplit_ms_per_step": unsplit_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "measured_in": ("the same step with the slices one after another (launches do not overlap)"
-                                     if a.split > 1 else "the timed steps"),
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, copy-calibrated",
-                     "kernel": ("forward NTT of the key-switching limbs, "
-                                + ("2^13-word part-limb blocks (first stages folded into modulus raising)"
-                                   if rk == "forward_part" else
-                                   "single pass" if tuned["single_pass"] else "column pass + row pass")
-                                + (", fp64" if tuned.get("fp64") else ", integer") + " arithmetic, 16 N bytes per limb"),
+                     "kernel": KINDS[rk]["desc"], "kind": rk,
+                     "measured_in": ("the same step with the slices one after another (launches do not overlap)"
+                                     if a.split > 1 else "the timed steps"),
+                     "launches": rk_n, "avg_launch_us": 1e3 * rk_ms / max(1, rk_n),
+                     "avg_launch_MB": rk_bytes / max(1, rk_n) / 1e6,
                      "ntt_schedule": tuned,
-                     "launches": fwd_n, "avg_launch_us": 1e3 * fwd_ms / max(1, fwd_n),
-                     "avg_launch_MB": fwd_bytes / max(1, fwd_n) / 1e6,
-                     "transforms": {k: {"GBs": b / (ms / 1e3) / 1e9, "launches": n, "avg_launch_us": 1e3 * ms / n}
-                                    for k, (ms, n, b) in prof.items() if n > 0 and ms > 0}},
+                     "kernels": {k: {"GBs": b / (ms / 1e3) / 1e9, "frac": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                     "launches": n, "avg_launch_us": 1e3 * ms / n, "ms_per_step": ms / a.steps}
+                                 for k, (ms, n, b) in prof.items() if n > 0 and ms > 0 and k != "mul"}},
+        "comparisons_roofline": {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "min_bytes_per_step": step_min_bytes, "multiplications_per_step": mul_n / a.steps,
+            "min_ms_per_step": step_min_bytes / (HBM_PEAK_GBS * 1e9) * 1e3,
+            "achieved": step_min_bytes / (ms_step / 1e3) / 1e9,
+            "frac": step_min_bytes / (HBM_PEAK_GBS * 1e9) / (ms_step / 1e3),
+            "note": "fused-minimum bytes of every multiplication at its level (two operands, the key once per "
+                    "ciphertext, the result; an addend where there is one) against ms_per_step"},
         "graph_replay_ms_per_step": graph_ms,
         "integer_arithmetic": int_path,
         "per_op_launch": None if per_op is None else {"ms_per_step": per_op, "batched_speedup": per_op / ms_step},
         "cpu_baseline": cpu,
+        "oracle_parity": oracle_parity,
+        "oracle_parity_sample": "group 0 of the timed step: LT, 3 max and 3 min planes, every residue" if cpu else None,
     }
     print(json.dumps(out))
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ntt_forward_traffic_n15.txt")
-NTT_SOURCES = [os.path.join(ROOT, "paper_2407_07308_amd", "csrc", f) for f in ("ntt.hip", "bc_internal.h")]
+# Kernel kinds of the comparison step: profiler kind, the kernels' names in a
+# rocprofv3 trace, the sources their code comes from, and what a launch moves.
+KINDS = {
+    "forward_combine": {"prof": "BC_PROF_NTT_FWD_COMBINE", "re": r"ntt_(part|full)_combine<",
+                        "src": ["ntt.hip", "bc_internal.h"],
+                        "desc": "forward NTT of the relinearise+switch correction with the multiplication's last step "
+                                "as its store (32 N bytes per limb: the limb, d and the accumulator read, the result "
+                                "written)"},
+    "forward_part": {"prof": "BC_PROF_NTT_FWD_PART", "re": r"ntt_part<\d+, [^,]+, \d+(, false)?>",
+                     "src": ["ntt.hip", "bc_internal.h"],
+                     "desc": "forward NTT of the raised limbs, 2^13-word part-limb blocks (16 N bytes per limb)"},
+    "inverse_part": {"prof": "BC_PROF_NTT_INV_PART", "re": r"ntt_part<\d+, [^,]+, \d+, true>",
+                     "src": ["ntt.hip", "bc_internal.h"],
+                     "desc": "inverse NTT of the key-switched limbs, 2^13-word part-limb blocks (16 N bytes per limb)"},
+    "forward": {"prof": "BC_PROF_NTT_FWD", "re": r"ntt_(full|cols|rows)<\d+, false",
+                "src": ["ntt.hip", "bc_internal.h"], "desc": "whole-limb forward NTT (16 N bytes per limb)"},
+    "inverse": {"prof": "BC_PROF_NTT_INV", "re": r"ntt_(full|cols|rows)<\d+, true",
+                "src": ["ntt.hip", "bc_internal.h"], "desc": "whole-limb inverse NTT (16 N bytes per limb)"},
+    "tensor": {"prof": "BC_PROF_TENSOR", "re": r"k_tensor<", "src": ["kernels.hip", "bc_internal.h"],
+               "desc": "tensor product / multiply-accumulate (operands read once, 3 components written)"},
+    "modup": {"prof": "BC_PROF_MODUP", "re": r"k_modup<", "src": ["kernels.hip", "bc_internal.h"],
+              "desc": "digit decomposition + basis extension (each digit's limbs read, new limbs written)"},
+    "ks_inner": {"prof": "BC_PROF_KS_INNER", "re": r"k_ks_inner<", "src": ["kernels.hip", "bc_internal.h"],
+                 "desc": "key-switch inner product (raised limbs and key read, two accumulators written)"},
+    "relin_ms": {"prof": "BC_PROF_RELIN_MS", "re": r"k_relin_ms_fbc<", "src": ["kernels.hip", "bc_internal.h"],
+                 "desc": "ModDown + modulus-switch correction (special and top limbs read, correction written)"},
+    "lincomb": {"prof": "BC_PROF_LINCOMB", "re": r"k_lincomb<", "src": ["kernels.hip", "bc_internal.h"],
+                "desc": "Paterson-Stockmeyer block combinations (babies read, blocks written)"},
+    "mul": {"prof": "BC_PROF_MUL", "re": None, "src": [], "desc": "whole multiplications"},
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernel_traffic_n15.json")
 
 
-def ntt_source_hash() -> str:
+def source_hash(kind: str) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in NTT_SOURCES:
-        h.update(open(f, "rb").read())
+    for f in KINDS[kind]["src"]:
+        h.update(open(os.path.join(ROOT, "paper_2407_07308_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def is_forward_ntt(name: str, parts: bool) -> str | None:
-    """The roofline kernel's launches: with part-limb transforms, 'a' for each
-    forward part-limb launch; else 'a' for the first pass (or the single pass)
-    of a forward transform and 'b' for the second."""
+def pmc_summary(fetch_csv: str, write_csv: str, command: str):
+    """Per-launch HBM bytes of every kernel kind from two rocprofv3 --pmc runs.
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they read
+    for the 1 GiB device copy the profiled run performs first; only the
+    comparison's dispatches count (from the first plane subtraction on)."""
+    import csv
     import re
 
-    if parts:
-        return "a" if re.search(r"ntt_part<\d+, [^,]+, \d+(, false)?>", name) else None
-    m = re.search(r"ntt_(cols|rows|full)<\d+, false[,>]", name)
-    if not m:
-        return None
-    return "b" if m.group(1) == "rows" else "a"
-
-
-def pmc_summary(fetch_csv: str, write_csv: str, command: str):
-    """Per-launch HBM bytes of the forward NTT from two rocprofv3 --pmc runs.
-    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they read
-    for the 1 GiB device copy the profiled run performs first."""
-    import csv
-
-    out = {}
+    per = {k: {} for k in KINDS if KINDS[k]["re"]}
+    scales = {}
     for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
         rows = [r for r in csv.DictReader(open(path)) if r.get("Counter_Name", counter) == counter]
         rows.sort(key=lambda r: int(r["Dispatch_Id"]))
@@ -342,36 +379,31 @@ def pmc_summary(fetch_csv: str, write_csv: str, command: str):
         fill = max((i for i, r in enumerate(rows) if "Fill" in r["Kernel_Name"]),
                    key=lambda i: int(rows[i]["Grid_Size"]))
         ref = next(float(r["Counter_Value"]) for r in rows[fill + 1:] if "copyBuffer" in r["Kernel_Name"])
-        scale = (1 << 20) / ref  # KiB the copy should have counted / KiB counted
-        # only the comparison steps (they start with the plane subtraction),
-        # as in the timed region; set-up transforms (tuning, encryption) excluded
+        scales[counter] = (1 << 20) / ref  # KiB the copy should have counted / KiB counted
         first = next(i for i, r in enumerate(rows) if "k_addsub" in r["Kernel_Name"])
-        parts = any("ntt_part<" in r["Kernel_Name"] for r in rows[first:])
-        tot, launches = 0.0, 0
-        for r in rows[first:]:
-            kind = is_forward_ntt(r["Kernel_Name"], parts)
-            if kind:
-                tot += float(r["Counter_Value"]) * 1024 * scale
-                launches += kind == "a"
-        out[counter] = {"scale": scale, "bytes": tot, "launches": launches}
-    per_launch = (out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"]) / max(1, out["FETCH_SIZE"]["launches"])
-    rec = {"kernel": "forward NTT" + (", part-limb blocks" if parts else ""), "source_hash": ntt_source_hash(),
-           "traffic_bytes_per_launch": per_launch,
-           "fetch_scale": out["FETCH_SIZE"]["scale"], "write_scale": out["WRITE_SIZE"]["scale"],
-           "launches": out["FETCH_SIZE"]["launches"], "command": command}
+        for k in per:
+            sel = [r for r in rows[first:] if re.search(KINDS[k]["re"], r["Kernel_Name"])]
+            per[k][counter] = (sum(float(r["Counter_Value"]) for r in sel) * 1024 * scales[counter], len(sel))
+    rec = {"command": command, "fetch_scale": scales["FETCH_SIZE"], "write_scale": scales["WRITE_SIZE"],
+           "kinds": {}}
+    for k, v in per.items():
+        n = v["FETCH_SIZE"][1]
+        if n:
+            rec["kinds"][k] = {"source_hash": source_hash(k), "launches": n,
+                               "traffic_bytes_per_launch": (v["FETCH_SIZE"][0] + v["WRITE_SIZE"][0]) / n}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
 
 
-def measured_traffic():
-    """Forward-NTT bytes per launch from the committed counter summary, if the
-    transform source is unchanged since the counters were taken."""
+def measured_traffic(kind: str):
+    """HBM bytes per launch of `kind` from the committed counter summary, if
+    its sources are unchanged since the counters were taken."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
-    except (OSError, ValueError):
+        rec = json.load(open(TRAFFIC_FILE))["kinds"][kind]
+    except (OSError, ValueError, KeyError):
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("source_hash") == ntt_source_hash() else None
+    return rec["traffic_bytes_per_launch"] if rec.get("source_hash") == source_hash(kind) else None
 
 
 CHAINS = {13: dict(logN=13, p=257, nQ=8, bitsQ=50, nP=4, bitsP=50, dnum=2),

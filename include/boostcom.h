@@ -4,22 +4,27 @@
  * The library evaluates BoostCom's hot path -- the word-wise BGV comparison
  * (paper, Background, "Word-wise Universal FHE Scheme": integers split into
  * F_p digits, per-digit LT and EQ, lexicographic combination) -- on BGV
- * ciphertexts in RNS form ("Efficient Polynomial and NTT": the (L+1) x N residue
- * matrix, NTT-based multiplication).  Ring: Z_Q[x]/(x^N + 1), N a power of two,
- * every prime q = 1 mod 2Np.  Plaintext slots: M = 2^(s-1) where 2^s exactly
- * divides p - 1 (8 for p = 17, 128 for p = 257), one F_p value per slot.
+ * ciphertexts in RNS form (Background, "Efficient Polynomial and NTT": the
+ * (L+1) x N residue matrix, NTT-based multiplication).  Ring:
+ * Z_Q[x]/(x^N + 1), N a power of two, every prime q = 1 mod 2Np.  Plaintext
+ * slots: M = 2^(s-1) where 2^s exactly divides p - 1 (8 for p = 17, 128 for
+ * p = 257), one F_p value per slot.  Notation follows the paper's table of
+ * BGV parameters (p, N, Q = q_0 ... q_L, L).
  *
  * Conventions shared by every call:
  *  - Return value: 0 on success, a negative BC_ERR_* code otherwise; no call
- *    throws.  bc_last_error() returns a message for the calling thread.
+ *    throws.  bc_last_error() returns a message for the calling thread.  A
+ *    call that fails its argument, level or noise checks launches nothing.
  *  - Ciphertext batches (bc_ctb) live in caller-owned DEVICE memory:
  *    data[count][ncomp][level+1][N] uint64 residues in [0, q_i), limb i
  *    reduced mod q_i, every limb in the NTT (evaluation) domain.  The caller
  *    sizes buffers with bc_ct_words().  Outputs must not alias inputs unless a
- *    call says otherwise.
+ *    call says otherwise; inputs are never modified.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
  *    enqueued asynchronously on it; calls returning host data synchronise it.
- *  - Host pointers are read (or written) before the call returns.
+ *  - Host pointers are read (or written) before the call returns and stay
+ *    owned by the caller.  Contexts, key sets and groups are owned by the
+ *    library (created and destroyed through it).
  *  - A context is immutable after creation; calls on one context may run
  *    concurrently from several threads when they use different streams and
  *    different output buffers.  Workspace comes from a per-context pool.
@@ -36,20 +41,24 @@ extern "C" {
 
 enum {
     BC_OK = 0,
-    BC_ERR_ARG = -1,    /* null or malformed argument, size mismatch        */
-    BC_ERR_PARAM = -2,  /* parameters impossible (no such primes, N, p ...)  */
-    BC_ERR_LEVEL = -3,  /* operation needs a level below 0                   */
-    BC_ERR_OOM = -4,    /* device or host allocation failed                  */
-    BC_ERR_HIP = -5,    /* a HIP runtime call failed                         */
-    BC_ERR_KEY = -6     /* a required switching key was not generated        */
+    BC_ERR_ARG = -1,    /* null or malformed argument, size or shape mismatch              */
+    BC_ERR_PARAM = -2,  /* impossible parameters, or objects of different parameter sets  */
+    BC_ERR_LEVEL = -3,  /* no level left, or the noise estimate would exceed the budget   */
+    BC_ERR_OOM = -4,    /* device or host allocation failed                                */
+    BC_ERR_HIP = -5,    /* a HIP runtime call failed                                       */
+    BC_ERR_KEY = -6     /* a required switching key was not generated                      */
 };
 
-/* BGV parameter set.  Primes: the nQ largest primes below 2^bitsQ that are
+/* BGV parameter set (paper, Background, "Word-wise Universal FHE Scheme":
+ * the plaintext modulus p, the ring degree N and the modulus chain
+ * Q = q_0 ... q_L).  Primes: the nQ largest primes below 2^bitsQ that are
  * 1 mod 2Np, in decreasing order (q_0 > ... > q_{nQ-1}); then the nP largest
  * primes below 2^bitsP with the same congruence, excluding those (special
- * primes p_0 > ... ).  Modulus switching drops the smallest remaining q.  Key
- * switching uses dnum digits of alpha = ceil(nQ/dnum) consecutive primes.
- * Limits: 10 <= logN <= 16, bits <= 61, nQ + nP <= 40, 1 <= dnum <= nQ. */
+ * primes p_0 > ... , whose product P serves key switching).  Modulus
+ * switching drops the smallest remaining q.  Key switching uses dnum digits
+ * of alpha = ceil(nQ/dnum) consecutive primes.  Limits: 10 <= logN <= 16,
+ * p prime below 2^20, 20 <= bits <= 61, nQ + nP <= 40, 1 <= dnum <= nQ,
+ * alpha <= 16, nP <= 16. */
 typedef struct {
     int32_t logN;
     int32_t p;
@@ -61,12 +70,18 @@ typedef struct {
 typedef struct bc_ctx bc_ctx;
 typedef struct bc_keys bc_keys;
 
-/* A batch of `count` ciphertexts at one level; see the layout above. */
+/* A batch of `count` ciphertexts at one level; see the layout above.
+ * noise_bits is the library's estimate of log2 of a bound on the infinity
+ * norm of [c0 + c1 s (+ c2 s^2)]_Q (paper, Background, "Word-wise Universal
+ * FHE Scheme": the noise that limits the number of operations).  Every call
+ * that writes a batch sets it; 0 on input means "unknown" and is taken as a
+ * fresh encryption's. */
 typedef struct {
     uint64_t *data;
     int32_t count;
     int32_t level;
     int32_t ncomp;
+    float noise_bits;
 } bc_ctb;
 
 /* Rotation step meaning the swap of the two slot rows (x -> x^(2N-1)). */
@@ -74,27 +89,43 @@ typedef struct {
 
 /* ---------------------------------------------------------------- context */
 
-/* Builds primes, NTT twiddles and every base-conversion constant on the
- * device (computed once; paper, "GPU-related Optimizations": plan reuse). */
+/* Builds the prime chain, NTT twiddles and every base-conversion constant and
+ * keeps them on the device (computed once; paper, The Design of BoostCom,
+ * "GPU-related Optimizations": plan reuse takes data-independent work off the
+ * critical path).  *out is owned by the caller until bc_ctx_destroy.
+ * BC_ERR_PARAM for an impossible set (checked on the host, before any device
+ * work). */
 int bc_ctx_create(const bc_params *prm, bc_ctx **out);
+/* Waits for the device and frees the context (NULL is a no-op).  Every key
+ * set and group of the context must be destroyed first. */
 int bc_ctx_destroy(bc_ctx *ctx);
-/* moduli[nQ + nP] in the order described at bc_params */
+/* moduli[nQ + nP] in the order described at bc_params (the modulus chain of
+ * "Word-wise Universal FHE Scheme", then the special primes).  BC_ERR_ARG when
+ * cap < nQ + nP. */
 int bc_ctx_moduli(const bc_ctx *ctx, uint64_t *moduli, int32_t cap);
-/* number of slots M */
+/* Number of plaintext slots M (the SIMD slots of "Word-wise Universal FHE
+ * Scheme"), or BC_ERR_ARG for a null context. */
 int bc_ctx_slots(const bc_ctx *ctx);
-/* uint64 words of one ciphertext with ncomp components at `level` */
+/* uint64 words of one ciphertext with ncomp components at `level` (the
+ * (level+1) x N residue matrix of "Efficient Polynomial and NTT", per
+ * component); 0 for invalid arguments. */
 size_t bc_ct_words(const bc_ctx *ctx, int32_t level, int32_t ncomp);
-/* device bytes currently held by the context's workspace pool */
+/* Device bytes currently held by the context's workspace pool. */
 size_t bc_ctx_pool_bytes(const bc_ctx *ctx);
-/* release every cached workspace block (no call may be in flight) */
+/* Releases every cached workspace block (no call may be in flight). */
 int bc_ctx_trim(bc_ctx *ctx);
 
 /* ------------------------------------------------------------------- keys */
 
-/* Sizes of the randomness consumed by bc_keygen for `nrot` rotation keys. */
+/* Sizes of the randomness consumed by bc_keygen for `nrot` rotation keys
+ * (counts of 64-bit words and of 32-bit errors). */
 int bc_keygen_rand_sizes(const bc_ctx *ctx, int32_t nrot, size_t *n_words, size_t *n_errors);
 
-/* Key generation from caller-supplied randomness (host arrays):
+/* Key generation of BGV (paper, Background, "Word-wise Universal FHE
+ * Scheme": RLWE encryption; multiplication and rotation need switching keys,
+ * whose construction the paper leaves to BGV -- hybrid key switching with
+ * the special primes is this library's reading) from caller-supplied
+ * randomness (host arrays):
  *   s[N]        ternary secret in {-1, 0, 1};
  *   a_words     uniform 64-bit words, each reduced mod its limb's prime:
  *               public key [nQ][N], then for the relinearisation key and each
@@ -104,90 +135,143 @@ int bc_keygen_rand_sizes(const bc_ctx *ctx, int32_t nrot, size_t *n_words, size_
  * Produces pk = (-a s + p e, a), and switching keys
  * ksk_j = (-a_j s + p e_j + P g_j s', a_j) over Q_L * P with g_j = 1 mod the
  * primes of digit j and 0 mod all others; s' = s^2 (relinearisation) or
- * s(x^g) with g = 5^r mod 2N for each rotation step r (g = 2N - 1 for
- * BC_ROW_SWAP).  The secret stays inside the key object (decryption needs
- * it).  Synchronous. */
+ * s(x^g) with g = 5^r mod 2N for each rotation step r in [1, M/2)
+ * (g = 2N - 1 for BC_ROW_SWAP; BC_ERR_ARG for other steps).  The secret stays
+ * inside the key object (decryption needs it).  *out is owned by the caller
+ * until bc_keys_destroy.  Synchronous. */
 int bc_keygen(bc_ctx *ctx, const int8_t *s, const uint64_t *a_words, const int32_t *errors,
               const int32_t *rot_steps, int32_t nrot, bc_keys **out);
+/* Waits for the device and frees the key set (NULL is a no-op); comparison
+ * graphs recorded with it are dropped. */
 int bc_keys_destroy(bc_keys *keys);
+/* Checkpoint / resume of a key set: a flat little-endian blob (header with
+ * the parameter set and the rotation steps, the ternary secret, then pk, the
+ * relinearisation key and each rotation key in the COEFFICIENT domain,
+ * limb-major, residues in [0, q_i)).  Export with buf == NULL stores the
+ * size in *size; otherwise cap must be at least that size (BC_ERR_ARG).
+ * Import checks the header (BC_ERR_PARAM for another parameter set,
+ * BC_ERR_ARG for a malformed blob or out-of-range residues) and builds a key
+ * set equal to the exported one.  Both synchronous. */
+int bc_keys_export(bc_ctx *ctx, const bc_keys *keys, void *buf, size_t cap, size_t *size);
+int bc_keys_import(bc_ctx *ctx, const void *buf, size_t size, bc_keys **out);
 
 /* ------------------------------------------------------ client-side calls */
 
-/* Encrypts out->count slot vectors slots[count][M] (values taken mod p) at the
- * top level with public-key randomness u[count][N] (ternary) and
+/* Encryption (paper, Background, "Word-wise Universal FHE Scheme": a
+ * plaintext encoded into a polynomial of the slots, then encrypted).
+ * Encrypts out->count slot vectors slots[count][M] (values taken mod p) at
+ * the top level with public-key randomness u[count][N] (ternary) and
  * errors[count][2][N]: ct = (pk0 u + p e0 + m, pk1 u + p e1), m the slot
- * encoding (coefficient mu_k at x^(k N/M)).  out->level is set to nQ - 1 and
- * out->ncomp to 2; out->data must hold bc_ct_words(nQ-1, 2) * count words. */
+ * encoding (coefficient mu_k at x^(k N/M)).  out->level is set to nQ - 1,
+ * out->ncomp to 2 and out->noise_bits to the fresh estimate; out->data must
+ * hold bc_ct_words(nQ-1, 2) * count words. */
 int bc_encrypt(bc_ctx *ctx, const bc_keys *keys, const uint32_t *slots, const int8_t *u,
                const int32_t *errors, bc_ctb *out, void *stream);
 
-/* Decrypts [c0 + c1 s (+ c2 s^2)]_Q mod p and decodes the slots:
- * slots[count][M].  Synchronises the stream. */
+/* Decryption (same passage): [c0 + c1 s (+ c2 s^2)]_Q centred, mod p,
+ * decoded to slots[count][M].  Synchronises the stream. */
 int bc_decrypt(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t *slots, void *stream);
 /* Same, returning all N plaintext coefficients in [0, p): coeffs[count][N]. */
 int bc_decrypt_poly(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t *coeffs, void *stream);
 
-/* Host <-> device in the COEFFICIENT domain: host[count][ncomp][level+1][N]. */
+/* Host <-> device in the COEFFICIENT domain (the inverse NTT of "Efficient
+ * Polynomial and NTT" applied on export, the forward one on import):
+ * host[count][ncomp][level+1][N].  Import takes out->noise_bits as given
+ * (0: unknown).  Both synchronise the stream. */
 int bc_export(bc_ctx *ctx, const bc_ctb *in, uint64_t *host, void *stream);
 int bc_import(bc_ctx *ctx, const uint64_t *host, bc_ctb *out, void *stream);
 
 /* ------------------------------------------------------ server-side calls */
-/* Binary calls accept b->count == a->count, or b->count dividing a->count
- * (ciphertext i of a pairs with i mod b->count of b).  Operands at different
- * levels are first brought to the lower one by modulus switching. */
+/* Homomorphic operations of "Word-wise Universal FHE Scheme" (addition,
+ * multiplication, rotation, modulus chain), each one batched launch sequence
+ * over the whole residue matrix of the batch (paper, "GPU-related
+ * Optimizations": element-wise work over the (L+1) x N matrix).
+ * Binary calls accept b->count == a->count, or b->count dividing a->count
+ * (ciphertext i of a pairs with i mod b->count of b).  An operand above the
+ * lower operand's level is read at its lowest level+1 limbs: its top primes
+ * are dropped without rescaling, which keeps the plaintext because every
+ * q_i = 1 mod p and the noise stays below the smaller modulus.  The output
+ * descriptor must have the level and component count the call produces
+ * (BC_ERR_ARG otherwise); its noise_bits is set.  BC_ERR_LEVEL, before any
+ * launch, when the output's noise estimate exceeds half its modulus. */
 
-/* Tensor (a0 b0, a0 b1 + a1 b0, a1 b1): out has 3 components. */
+/* Tensor (a0 b0, a0 b1 + a1 b0, a1 b1): out has 3 components at min level. */
 int bc_tensor(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream);
-/* Relinearisation of a 3-component batch with the relinearisation key, same level. */
+/* Relinearisation (key switch of c2 with the s^2 key) of a 3-component batch,
+ * same level. */
 int bc_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, bc_ctb *out, void *stream);
-/* Drops q_level: t = [c_l p^-1]_{q_l} in (-q_l/2, q_l/2], c_i' = (c_i - p t) q_l^-1. */
+/* Modulus switch down the chain (paper: the modulus chain q_0 ... q_L):
+ * drops q_level, t = [c_l p^-1]_{q_l} in (-q_l/2, q_l/2],
+ * c_i' = (c_i - p t) q_l^-1.  BC_ERR_LEVEL at level 0. */
 int bc_mod_switch(bc_ctx *ctx, const bc_ctb *in, bc_ctb *out, void *stream);
-/* Multiplication: align levels, tensor, relinearise, then modulus-switch one
- * prime down unless the level is 0 (paper: the non-scalar multiplication the
- * comparison circuits count). */
+/* The non-scalar multiplication the comparison circuits count (paper,
+ * Introduction; "Word-wise Universal FHE Scheme"): align levels, tensor,
+ * relinearise, then modulus-switch one prime down unless the level is 0. */
 int bc_mul_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *a, const bc_ctb *b, bc_ctb *out,
                  void *stream);
-/* Rotation of each slot row left by `steps` (or BC_ROW_SWAP): automorphism
- * then key switch with the matching rotation key; level unchanged. */
+/* Rotation (paper, "Word-wise Universal FHE Scheme": rotation among the
+ * homomorphic operations; the ciphertext shifting of ShiftMul/ShiftAdd) of
+ * each slot row left by `steps` (or BC_ROW_SWAP): automorphism x -> x^g then
+ * key switch with the matching rotation key; level unchanged.  BC_ERR_KEY
+ * when no rotation key was generated for `steps`. */
 int bc_rotate(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, int32_t steps, bc_ctb *out, void *stream);
+/* Slot-wise addition and subtraction ("Word-wise Universal FHE Scheme";
+ * the additions of the comparison circuits, Introduction). */
 int bc_add(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream);
 int bc_sub(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *stream);
-/* Multiply by c in Z_p (its representative in (-p/2, p/2]). */
+/* Scalar multiplication of the circuits (paper, Introduction): multiply by c
+ * in Z_p (its representative in (-p/2, p/2]). */
 int bc_mul_scalar(bc_ctx *ctx, const bc_ctb *a, int32_t c, bc_ctb *out, void *stream);
-/* Add c in Z_p to every slot (representative in (-p/2, p/2] on x^0 of c0). */
+/* Add the constant c in Z_p to every slot (representative in (-p/2, p/2] on
+ * x^0 of c0), as the circuits' plaintext constants (EQ = 1 - Z^(p-1)). */
 int bc_add_const(bc_ctx *ctx, const bc_ctb *a, int32_t c, bc_ctb *out, void *stream);
 
 /* ---------------------------------------------------------- comparisons */
-/* Digit planes: a_digits[d] (d < ndigits, most significant first) is a batch
- * of `count` ciphertexts, all with the same count, level and ncomp == 2; slot
- * k of plane d holds digit d of integer k.  The univariate circuit
- * LT(x, y) = f(x - y), f the degree p-1 interpolant of [z in [(p+1)/2, p-1]],
- * is exact for digits in [0, (p-1)/2] (base (p+1)/2); it is evaluated with a
- * Paterson-Stockmeyer schedule (p - 1 a power of two: 8 multiplications for
- * p = 17, 30 for p = 257).  EQ = 1 - (x - y)^(p-1).  Digits are combined as
- * LT = LT_0 + EQ_0 (LT_1 + EQ_1 (...)).  Output buffers must be allocated at
- * the level the call reports through bc_compare_levels. */
+/* Word-wise comparison (paper, Background, "Word-wise Universal FHE
+ * Scheme": per-digit LT and EQ over F_p, combined in lexicographic order;
+ * Introduction: the univariate circuit with sqrt(p-3) + O(log p)
+ * non-scalar multiplications).  Digit planes: a_digits[d] (d < ndigits <= 16,
+ * most significant first) is a batch of `count` ciphertexts, all with the
+ * same count, level and ncomp == 2; slot k of plane d holds digit d of
+ * integer k.  The univariate circuit LT(x, y) = f(x - y), f the degree p-1
+ * interpolant of [z in [(p+1)/2, p-1]], is exact for digits in
+ * [0, (p-1)/2] (base (p+1)/2); it is evaluated with a Paterson-Stockmeyer
+ * schedule (p - 1 a power of two: 8 multiplications for p = 17, 30 for
+ * p = 257; BC_ERR_PARAM for other p).  EQ = 1 - (x - y)^(p-1).  Digits are
+ * combined as LT = LT_0 + EQ_0 (LT_1 + EQ_1 (...)).
+ *
+ * bc_compare_levels reports the levels of the outputs for inputs at in_level
+ * (max/min planes one level below LT), and BC_ERR_LEVEL when the LT circuit
+ * does not fit the chain for fresh inputs (host only, no device work). */
 int bc_compare_levels(const bc_ctx *ctx, int32_t in_level, int32_t ndigits, int32_t *lt_level,
                       int32_t *maxmin_level);
-/* out: encryption of [a < b] in every slot. */
+/* out (at the LT level): encryption of [a < b] in every slot. */
 int bc_compare_lt(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits,
                   const bc_ctb *b_digits, bc_ctb *out, void *stream);
-/* max_d = a_d + LT (b_d - a_d) and/or min_d = b_d + LT (a_d - b_d) per plane;
- * lt_out, max_out and min_out may each be NULL (at least one non-NULL). */
+/* The comparison with max/min, the basic tasks of the paper's applications
+ * (Introduction; Methodology, "Applications": min and sorting):
+ * max_d = a_d + LT (b_d - a_d) and/or min_d = b_d + LT (a_d - b_d) per plane
+ * (arrays of ndigits batches at the max/min level); lt_out, max_out and
+ * min_out may each be NULL (at least one non-NULL).  Every step of the
+ * schedule is checked against its noise budget before any launch
+ * (BC_ERR_LEVEL: the circuit is deeper than the chain allows). */
 int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits,
                        const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out,
                        void *stream);
 
-/* Mixed ring sizes.  A group holds several contexts (e.g. N = 2^13, 2^14,
- * 2^15).  bc_group_compare evaluates every member's comparison batch; members
- * run on their own streams, forked from and joined back into `stream`.  The
- * first call for a given set of buffers runs eagerly and records the whole
- * fork/join launch sequence into one hipGraph; later calls replay it with one
- * graph launch, so kernels of different ring sizes overlap on the device.
- * Per member i: keys[i], ndigits[i], planes a_digits[i][0..ndigits[i]) and
- * b_digits[i][..] as for bc_compare_max_min, outputs lt_out[i] (or NULL),
- * max_out[i] / min_out[i] (arrays of ndigits[i] batches, or NULL).  Results
- * are identical to separate bc_compare_max_min calls. */
+/* Mixed ring sizes (paper, The Design of BoostCom, "Multi-Level
+ * Heterogeneous Parallelization": independent comparisons overlapped to fill
+ * the GPU).  A group holds several contexts (e.g. N = 2^13, 2^14, 2^15),
+ * owned by the caller, distinct (BC_ERR_ARG otherwise).  bc_group_compare
+ * evaluates every member's comparison batch; members run on their own
+ * streams, forked from and joined back into `stream`.  The first call for a
+ * given set of buffers runs eagerly and records the whole fork/join launch
+ * sequence into one hipGraph; later calls replay it with one graph launch, so
+ * kernels of different ring sizes overlap on the device.  Per member i:
+ * keys[i], ndigits[i], planes a_digits[i][0..ndigits[i]) and b_digits[i][..]
+ * as for bc_compare_max_min, outputs lt_out[i] (or NULL), max_out[i] /
+ * min_out[i] (arrays of ndigits[i] batches, or NULL).  Results are identical
+ * to separate bc_compare_max_min calls. */
 typedef struct bc_group bc_group;
 int bc_group_create(int32_t n, bc_ctx *const *ctxs, bc_group **out);
 int bc_group_destroy(bc_group *g);
@@ -195,16 +279,19 @@ int bc_group_compare(bc_group *g, const bc_keys *const *keys, const int32_t *ndi
                      const bc_ctb *const *b_digits, bc_ctb *const *lt_out, bc_ctb *const *max_out,
                      bc_ctb *const *min_out, void *stream);
 
-/* Execution mode of the comparison calls: BC_EXEC_BATCHED launches every step
- * of the circuit once for the whole batch; BC_EXEC_GRAPH additionally records
- * the launch sequence of a (shape, buffers) combination into a hipGraph on its
- * first call and replays it afterwards; BC_EXEC_PER_OP runs the same kernels
- * with one ciphertext per launch (the unbatched reference path).  All modes
- * produce identical ciphertexts. */
+/* Execution mode of the comparison calls (paper, "GPU-related
+ * Optimizations": whole-matrix launches instead of one per row):
+ * BC_EXEC_BATCHED launches every step of the circuit once for the whole
+ * batch; BC_EXEC_GRAPH additionally records the launch sequence of a (shape,
+ * buffers, key set) combination into a hipGraph on its first call and
+ * replays it afterwards; BC_EXEC_PER_OP runs the same kernels with one
+ * ciphertext per launch (the unbatched reference path).  All modes produce
+ * identical ciphertexts. */
 enum { BC_EXEC_BATCHED = 0, BC_EXEC_GRAPH = 1, BC_EXEC_PER_OP = 2 };
 int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
 
-/* Tuning knobs (results never change, only speed):
+/* Tuning knobs (results never change, only speed), in the spirit of the
+ * paper's plan reuse ("GPU-related Optimizations"):
  *   BC_TUNE_NTT_CHUNK_BYTES: split every batched transform into launch pairs
  *   over at most this many bytes of limbs (0 = no split), so the first pass's
  *   output is still cached when the second pass reads it.
@@ -241,37 +328,59 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   it (one wait for the device).  Blocks in use are never given back: a
  *   call whose own working set exceeds the bound still runs.  Set it above
  *   the working set of the batches in flight, or calls re-allocate their
- *   workspace. */
+ *   workspace.
+ *   BC_TUNE_TEST_FAIL_ALLOC (test hook, default 0 = off): the n-th next new
+ *   device allocation of the workspace pool fails, so that a caller can force
+ *   BC_ERR_OOM from the host; the hook then switches itself off. */
 enum {
     BC_TUNE_NTT_CHUNK_BYTES = 0,
     BC_TUNE_NTT_SINGLE_PASS = 1,
     BC_TUNE_FP64 = 2,
     BC_TUNE_POOL_LIMIT_BYTES = 3,
     BC_TUNE_NTT_PARTS = 4,
-    BC_TUNE_SPLIT_STREAMS = 5
+    BC_TUNE_SPLIT_STREAMS = 5,
+    BC_TUNE_TEST_FAIL_ALLOC = 6
 };
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);
-/* Times each transform schedule (two-pass, two-pass in cache-sized chunks,
- * single-pass where N allows; each with fp64 and integer arithmetic where the
- * primes allow fp64) on a synthetic batch of this context's shape
- * (about 384 MB of limbs) and keeps the fastest.  Synchronises the stream;
- * takes a few tens of milliseconds. */
+/* Project-written autotuner of the transform schedule (the NTT of
+ * "Efficient Polynomial and NTT"): times each schedule (two-pass, two-pass in
+ * cache-sized chunks, single-pass where N allows; each with fp64 and integer
+ * arithmetic where the primes allow fp64) on a synthetic batch of this
+ * context's shape (about 384 MB of limbs) and keeps the fastest.
+ * Synchronises the stream; takes a few tens of milliseconds. */
 int bc_autotune(bc_ctx *ctx, void *stream);
 
 /* ------------------------------------------------------------ profiling */
-/* When enabled (outside graph mode), every transform launch pair is bracketed
- * with HIP events recorded on the stream it runs on.  bc_profile_read sums,
- * for one kind, the event-measured time (ms), the number of bracketed launch
- * pairs and their algorithmic HBM bytes (every limb read and written once:
- * 16 N bytes per limb).  BC_PROF_NTT_FWD_COMBINE counts the forward
- * transforms that also apply the last step of a multiplication
- * (relinearisation and modulus switch) or of a modulus switch as they store
- * (32 N resp. 24 N bytes per limb: the limb, the operand limbs and the output
- * limb).  BC_PROF_NTT_FWD_PART and BC_PROF_NTT_INV_PART count the part-limb
- * transforms of key switching (BC_TUNE_NTT_PARTS; 16 N bytes per limb: the
- * stages folded into the neighbouring kernels move no extra bytes), and
- * BC_PROF_NTT_FWD / BC_PROF_NTT_INV then the remaining whole-limb ones.
+/* Per-kernel timing of the key-switching path (the paper measures its own
+ * component breakdown, Bottleneck of uFHE Comparison).  When enabled (outside
+ * graph mode), every launch of the kinds below is bracketed with HIP events
+ * recorded on the stream it runs on.  bc_profile_read sums, for one kind, the
+ * event-measured time (ms), the number of bracketed launches and their
+ * algorithmic HBM bytes (each operand word read once, each result word
+ * written once; twiddles and constants excluded):
+ *   BC_PROF_NTT_FWD / _INV: whole-limb transforms, 16 N bytes per limb;
+ *   BC_PROF_NTT_FWD_COMBINE: forward transforms that also apply the last
+ *   step of a multiplication (relinearisation and modulus switch; 32 N bytes
+ *   per limb: the limb, two operand limbs and the output) or of a modulus
+ *   switch (24 N);
+ *   BC_PROF_NTT_FWD_PART / _INV_PART: the part-limb transforms of key
+ *   switching (BC_TUNE_NTT_PARTS; 16 N bytes per limb: the stages folded into
+ *   the neighbouring kernels move no extra bytes);
+ *   BC_PROF_TENSOR: the tensor (with an addend: multiply-accumulate);
+ *   BC_PROF_MODUP: digit decomposition and base extension (each digit's
+ *   source limbs read, its new limbs written);
+ *   BC_PROF_KS_INNER: the key-switch inner product (raised limbs and the key
+ *   read, two accumulators written);
+ *   BC_PROF_RELIN_MS: the fused ModDown + modulus-switch correction
+ *   (special and top limbs read, the correction written);
+ *   BC_PROF_LINCOMB: the Paterson-Stockmeyer block combinations;
+ *   BC_PROF_MUL: whole multiplications (bc_mul_relin and the circuits'
+ *   multiply-accumulates, all their launches), counted at their fused
+ *   minimum (4 (l+1) + 2 beta_l (l+1+k) + 2 l') 8 N bytes per ciphertext at
+ *   level l (two operands read, the key read once per ciphertext, the result
+ *   written; an addend adds 2 (l+1) 8 N), beta_l the active digits, k = nP,
+ *   l' the result's limbs: the comparison circuit's roofline.
  * Reading synchronises on the recorded events; enabling (or disabling) clears
  * earlier records. */
 enum {
@@ -279,11 +388,54 @@ enum {
     BC_PROF_NTT_INV = 1,
     BC_PROF_NTT_FWD_COMBINE = 2,
     BC_PROF_NTT_FWD_PART = 3,
-    BC_PROF_NTT_INV_PART = 4
+    BC_PROF_NTT_INV_PART = 4,
+    BC_PROF_TENSOR = 5,
+    BC_PROF_MODUP = 6,
+    BC_PROF_KS_INNER = 7,
+    BC_PROF_RELIN_MS = 8,
+    BC_PROF_LINCOMB = 9,
+    BC_PROF_MUL = 10
 };
 int bc_profile_enable(bc_ctx *ctx, int32_t on);
 int bc_profile_read(bc_ctx *ctx, int32_t kind, double *ms, int64_t *launches, double *bytes);
 
+/* ---------------------------------------------------------- noise budget */
+/* Host-only noise estimates (paper, Background, "Word-wise Universal FHE
+ * Scheme": noise limits the number of operations; the modulus chain lowers
+ * it), usable without a device: log2 of a bound on the infinity norm of
+ * [c0 + c1 s (+ c2 s^2)]_Q after operation `op` at `level` on inputs with
+ * estimates a_bits (and b_bits; 0 = a fresh encryption's):
+ *   BC_NOISE_FRESH       a fresh encryption (inputs ignored);
+ *   BC_NOISE_BUDGET      log2 (Q_level / 2), the most a ciphertext at
+ *                        `level` may carry and still decrypt;
+ *   BC_NOISE_ADD         a + b;
+ *   BC_NOISE_TENSOR      the tensor of a and b;
+ *   BC_NOISE_MUL         bc_mul_relin at `level` (BC_ERR_LEVEL when the
+ *                        product exceeds the budget);
+ *   BC_NOISE_MOD_SWITCH  dropping q_level (BC_ERR_LEVEL at level 0);
+ *   BC_NOISE_ROTATE      bc_rotate at `level`.
+ * The estimates assume the workloads' randomness (ternary s and u, errors of
+ * deviation 3.2) and are calibrated never to fall below the exact noise of
+ * the same operations.  bc_noise_compare gives the estimates of the LT and
+ * (when maxmin_bits is non-NULL) max/min outputs of the comparison circuit
+ * on inputs at in_level with estimate in_bits, or BC_ERR_LEVEL when a step
+ * would exceed its budget.  BC_ERR_PARAM for an impossible parameter set. */
+enum {
+    BC_NOISE_FRESH = 0,
+    BC_NOISE_BUDGET = 1,
+    BC_NOISE_ADD = 2,
+    BC_NOISE_TENSOR = 3,
+    BC_NOISE_MUL = 4,
+    BC_NOISE_MOD_SWITCH = 5,
+    BC_NOISE_ROTATE = 6
+};
+int bc_noise_estimate(const bc_params *prm, int32_t op, int32_t level, double a_bits, double b_bits,
+                      double *out_bits);
+int bc_noise_compare(const bc_params *prm, int32_t in_level, double in_bits, int32_t ndigits, double *lt_bits,
+                     double *maxmin_bits);
+
+/* Static description of an error code, and the last error message of the
+ * calling thread (valid until its next failing call). */
 const char *bc_strerror(int code);
 const char *bc_last_error(void);
 

@@ -22,8 +22,11 @@ BC_OK, BC_ERR_ARG, BC_ERR_PARAM, BC_ERR_LEVEL, BC_ERR_OOM, BC_ERR_HIP, BC_ERR_KE
 BC_ROW_SWAP = -1
 BC_EXEC_BATCHED, BC_EXEC_GRAPH, BC_EXEC_PER_OP = 0, 1, 2
 BC_PROF_NTT_FWD, BC_PROF_NTT_INV, BC_PROF_NTT_FWD_COMBINE, BC_PROF_NTT_FWD_PART, BC_PROF_NTT_INV_PART = 0, 1, 2, 3, 4
+BC_PROF_TENSOR, BC_PROF_MODUP, BC_PROF_KS_INNER, BC_PROF_RELIN_MS, BC_PROF_LINCOMB, BC_PROF_MUL = 5, 6, 7, 8, 9, 10
 BC_TUNE_NTT_CHUNK_BYTES, BC_TUNE_NTT_SINGLE_PASS, BC_TUNE_FP64, BC_TUNE_POOL_LIMIT_BYTES = 0, 1, 2, 3
 BC_TUNE_NTT_PARTS, BC_TUNE_SPLIT_STREAMS = 4, 5
+BC_TUNE_TEST_FAIL_ALLOC = 6
+BC_NOISE_FRESH, BC_NOISE_BUDGET, BC_NOISE_ADD, BC_NOISE_TENSOR, BC_NOISE_MUL, BC_NOISE_MOD_SWITCH, BC_NOISE_ROTATE = range(7)
 
 
 class BoostcomUnavailable(RuntimeError):
@@ -43,7 +46,7 @@ class bc_params(ctypes.Structure):
 
 class bc_ctb(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("count", ctypes.c_int32), ("level", ctypes.c_int32),
-                ("ncomp", ctypes.c_int32)]
+                ("ncomp", ctypes.c_int32), ("noise_bits", ctypes.c_float)]
 
 
 _lib = None
@@ -61,6 +64,8 @@ _SIGS = {
     "bc_keygen_rand_sizes": (_I, [_V, _I, _P(_S), _P(_S)]),
     "bc_keygen": (_I, [_V, _V, _V, _V, _V, _I, _P(_V)]),
     "bc_keys_destroy": (_I, [_V]),
+    "bc_keys_export": (_I, [_V, _V, _V, _S, _P(_S)]),
+    "bc_keys_import": (_I, [_V, _V, _S, _P(_V)]),
     "bc_encrypt": (_I, [_V, _V, _V, _V, _V, _P(bc_ctb), _V]),
     "bc_decrypt": (_I, [_V, _V, _P(bc_ctb), _V, _V]),
     "bc_decrypt_poly": (_I, [_V, _V, _P(bc_ctb), _V, _V]),
@@ -88,6 +93,8 @@ _SIGS = {
     "bc_get_tuning": (_I, [_V, _I, _P(ctypes.c_int64)]),
     "bc_profile_enable": (_I, [_V, _I]),
     "bc_profile_read": (_I, [_V, _I, _P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_double)]),
+    "bc_noise_estimate": (_I, [_P(bc_params), _I, _I, ctypes.c_double, ctypes.c_double, _P(ctypes.c_double)]),
+    "bc_noise_compare": (_I, [_P(bc_params), _I, ctypes.c_double, _I, _P(ctypes.c_double), _P(ctypes.c_double)]),
     "bc_strerror": (ctypes.c_char_p, [_I]),
     "bc_last_error": (ctypes.c_char_p, []),
 }
@@ -138,14 +145,21 @@ def _np_ptr(a: np.ndarray):
 
 @dataclass
 class Batch:
-    """``count`` ciphertexts [count][ncomp][level+1][N] uint64 in a CUDA tensor."""
+    """``count`` ciphertexts [count][ncomp][level+1][N] uint64 in a CUDA tensor,
+    with the library's noise estimate (log2 bits; 0 = unknown)."""
     tensor: object  # torch.Tensor (int64, cuda)
     count: int
     level: int
     ncomp: int
+    noise: float = 0.0
 
     def ctb(self) -> bc_ctb:
-        return bc_ctb(self.tensor.data_ptr(), self.count, self.level, self.ncomp)
+        return bc_ctb(self.tensor.data_ptr(), self.count, self.level, self.ncomp, self.noise)
+
+    def take(self, c: bc_ctb) -> "Batch":
+        """Adopts the level, components and noise estimate a call wrote to ``c``."""
+        self.level, self.ncomp, self.noise = c.level, c.ncomp, float(c.noise_bits)
+        return self
 
 
 def _ctb_array(batches):
@@ -153,6 +167,11 @@ def _ctb_array(batches):
     for i, b in enumerate(batches):
         arr[i] = b.ctb()
     return arr
+
+
+def _take_array(batches, arr):
+    for i, b in enumerate(batches):
+        b.take(arr[i])
 
 
 class Keys:
@@ -226,6 +245,22 @@ class Context:
                                 ctypes.byref(h)))
         return Keys(self, h, rot_steps)
 
+    def export_keys(self, keys: Keys) -> bytes:
+        """The key set as a coefficient-domain blob (``bc_keys_export``)."""
+        n = ctypes.c_size_t()
+        _check(self.L.bc_keys_export(self.handle, keys.handle, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self.L.bc_keys_export(self.handle, keys.handle, buf, n.value, ctypes.byref(n)))
+        return buf.raw
+
+    def import_keys(self, blob: bytes) -> Keys:
+        """A key set from a blob of ``export_keys`` (``bc_keys_import``)."""
+        h = ctypes.c_void_p()
+        _check(self.L.bc_keys_import(self.handle, blob, len(blob), ctypes.byref(h)))
+        nrot = int(np.frombuffer(blob, dtype=np.int32, count=1, offset=36)[0])
+        steps = np.frombuffer(blob, dtype=np.int32, count=nrot, offset=40).tolist()
+        return Keys(self, h, steps)
+
     # ------------------------------------------------------- client side
     def encrypt(self, keys: Keys, slots, u, errors, out: Batch | None = None) -> Batch:
         slots = np.ascontiguousarray(slots, dtype=np.uint32).reshape(-1, self.M)
@@ -236,8 +271,7 @@ class Context:
         c = out.ctb()
         _check(self.L.bc_encrypt(self.handle, keys.handle, _np_ptr(slots), _np_ptr(u), _np_ptr(e), ctypes.byref(c),
                                  _stream()))
-        out.level, out.ncomp = c.level, c.ncomp
-        return out
+        return out.take(c)
 
     def decrypt(self, keys: Keys, b: Batch) -> np.ndarray:
         out = np.zeros((b.count, self.M), dtype=np.uint32)
@@ -257,9 +291,10 @@ class Context:
         _check(self.L.bc_export(self.handle, ctypes.byref(c), _np_ptr(out), _stream()))
         return out
 
-    def import_(self, host: np.ndarray, level: int, ncomp: int = 2) -> Batch:
+    def import_(self, host: np.ndarray, level: int, ncomp: int = 2, noise: float = 0.0) -> Batch:
         host = np.ascontiguousarray(host, dtype=np.uint64).reshape(-1, ncomp, level + 1, self.N)
         out = self.new_batch(host.shape[0], level, ncomp)
+        out.noise = noise
         c = out.ctb()
         _check(self.L.bc_import(self.handle, _np_ptr(host), ctypes.byref(c), _stream()))
         return out
@@ -269,7 +304,7 @@ class Context:
         out = self.new_batch(a.count, level, ncomp)
         ca, cb, co = a.ctb(), b.ctb(), out.ctb()
         _check(fn(self.handle, *extra, ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(co), _stream()))
-        return out
+        return out.take(co)
 
     def tensor(self, a: Batch, b: Batch) -> Batch:
         return self._binary(self.L.bc_tensor, a, b, min(a.level, b.level), 3)
@@ -286,37 +321,37 @@ class Context:
         ca, cb, co = a.ctb(), b.ctb(), out.ctb()
         _check(self.L.bc_mul_relin(self.handle, keys.handle, ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(co),
                                    _stream()))
-        return out
+        return out.take(co)
 
     def relin(self, keys: Keys, a: Batch) -> Batch:
         out = self.new_batch(a.count, a.level, 2)
         ca, co = a.ctb(), out.ctb()
         _check(self.L.bc_relin(self.handle, keys.handle, ctypes.byref(ca), ctypes.byref(co), _stream()))
-        return out
+        return out.take(co)
 
     def mod_switch(self, a: Batch) -> Batch:
         out = self.new_batch(a.count, a.level - 1, 2)
         ca, co = a.ctb(), out.ctb()
         _check(self.L.bc_mod_switch(self.handle, ctypes.byref(ca), ctypes.byref(co), _stream()))
-        return out
+        return out.take(co)
 
     def rotate(self, keys: Keys, a: Batch, steps: int) -> Batch:
         out = self.new_batch(a.count, a.level, 2)
         ca, co = a.ctb(), out.ctb()
         _check(self.L.bc_rotate(self.handle, keys.handle, ctypes.byref(ca), steps, ctypes.byref(co), _stream()))
-        return out
+        return out.take(co)
 
     def mul_scalar(self, a: Batch, c: int) -> Batch:
         out = self.new_batch(a.count, a.level, a.ncomp)
         ca, co = a.ctb(), out.ctb()
         _check(self.L.bc_mul_scalar(self.handle, ctypes.byref(ca), int(c), ctypes.byref(co), _stream()))
-        return out
+        return out.take(co)
 
     def add_const(self, a: Batch, c: int) -> Batch:
         out = self.new_batch(a.count, a.level, a.ncomp)
         ca, co = a.ctb(), out.ctb()
         _check(self.L.bc_add_const(self.handle, ctypes.byref(ca), int(c), ctypes.byref(co), _stream()))
-        return out
+        return out.take(co)
 
     # ------------------------------------------------------ comparisons
     def compare_levels(self, in_level: int, ndigits: int):
@@ -369,6 +404,12 @@ class Context:
         cmn = _ctb_array(mn) if mn is not None else None
         _check(self.L.bc_compare_max_min(self.handle, keys.handle, nd, A, B,
                                          ctypes.byref(clt) if clt is not None else None, cmx, cmn, _stream()))
+        if lt is not None:
+            lt.take(clt)
+        if mx is not None:
+            _take_array(mx, cmx)
+        if mn is not None:
+            _take_array(mn, cmn)
         return lt, mx, mn
 
     def compare_lt(self, keys: Keys, a_digits, b_digits) -> Batch:
@@ -421,4 +462,11 @@ class Group:
         pmx = (PA * n)(*[ctypes.cast(x, PA) if x is not None else PA() for x in MX]) if want_max else None
         pmn = (PA * n)(*[ctypes.cast(x, PA) if x is not None else PA() for x in MN]) if want_min else None
         _check(self.L.bc_group_compare(self.handle, keys, nd, pa, pb, plt, pmx, pmn, _stream()))
+        for o, lt_c, mx_c, mn_c in zip(outs, LT, MX, MN):
+            if o[0] is not None:
+                o[0].take(lt_c.contents)
+            if o[1] is not None:
+                _take_array(o[1], mx_c)
+            if o[2] is not None:
+                _take_array(o[2], mn_c)
         return outs

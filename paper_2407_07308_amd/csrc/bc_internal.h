@@ -358,6 +358,7 @@ struct Pool {
     size_t cached = 0;               // bytes of free_ blocks
     size_t limit = 0;                // bytes held (live + cached) beyond which cached blocks are evicted (0: none)
     bool recording = false;          // collect every block handed out (graph capture)
+    int64_t fail_after = 0;          // test hook: the n-th next new device allocation fails (0: off)
     std::vector<void *> recorded;
     static size_t size_class(size_t bytes);
     void *alloc(size_t bytes);
@@ -379,7 +380,13 @@ enum ProfKind {
     kProfNttFwdCombine = 2,
     kProfNttFwdPart = 3,
     kProfNttInvPart = 4,
-    kProfKinds = 5
+    kProfTensor = 5,
+    kProfModUp = 6,
+    kProfKsInner = 7,
+    kProfRelinMs = 8,
+    kProfLincomb = 9,
+    kProfMul = 10,
+    kProfKinds = 11
 };
 struct ProfRec {
     int kind;
@@ -412,6 +419,48 @@ struct GraphCache {
     ~GraphCache();
 };
 
+// ------------------------------------------------------------- noise model
+// Host-side estimate of a ciphertext's noise: log2 of a bound on the infinity
+// norm of [c0 + c1 s (+ c2 s^2)]_Q (the plaintext included), which must stay
+// below Q_l / 2 for the ciphertext to decrypt.  Each operation maps the
+// estimates of its inputs to its output's (heuristic: coefficients of the
+// products of independent noise polynomials grow with sqrt(N), maxima over
+// N coefficients with the Gaussian tail factor sqrt(2 ln 2N)); the constants
+// assume the key and encryption randomness the workloads draw (ternary s and
+// u, errors of deviation 3.2).  The oracle's exact noise measurement
+// calibrates it (the estimate must never be below the measured noise).
+struct NoiseModel {
+    int N = 0, nQ = 0, nP = 0, dnum = 0, alpha = 0;
+    double p = 0, z = 0;
+    std::vector<double> lq;   // log2 q_i, i < nQ
+    std::vector<double> lQ;   // log2 (q_0 ... q_l)
+    double lP = 0;            // log2 P
+    NoiseModel() = default;
+    NoiseModel(const bc_params &prm, const std::vector<u64> &mod);
+    double fresh() const;
+    double budget(int level) const { return lQ[level] - 1.0; }  // log2 (Q_l / 2)
+    double add(double a, double b) const;
+    double scalar(double a, double absc) const;
+    double add_const(double a) const;
+    // tensor product (three components)
+    double tensor(double a, double b) const;
+    // key switch (relinearisation or rotation) of a ciphertext with noise t at `level`
+    double key_switch(int level, double t) const;
+    // relinearised product (plus an addend c, or -inf) at `level`, before the
+    // modulus switch
+    double product(int level, double a, double b, double c) const;
+    // the modulus switch that drops q_level
+    double mod_switch(int level, double a) const;
+    // automorphism plus key switch at `level`
+    double rotate(int level, double a) const;
+    // the noise of an input batch (0 = unknown: taken as a fresh encryption's)
+    double input(float bits) const { return bits > 0 ? (double)bits : fresh(); }
+    // BC_ERR_LEVEL unless `bits` fits the budget of `level`
+    void require(int level, double bits, const char *what) const;
+};
+
+std::vector<u64> param_moduli(const bc_params &prm);
+
 }  // namespace bc
 
 struct bc_ctx {
@@ -419,6 +468,7 @@ struct bc_ctx {
     int N, logN, nQ, nP, nmod, dnum, alpha, M;
     bc::u64 p;
     std::vector<bc::u64> mod;  // host copy of the moduli
+    bc::NoiseModel noise;
     // device tables
     bc::u64 *tw = nullptr;            // [nmod][4][N]: W, W', Winv, Winv'
     double *twf = nullptr;            // [nmod][4][N]: W, W/q, Winv, Winv/q (all primes < 2^50)
@@ -466,8 +516,32 @@ inline bool use_fp64(const bc_ctx *c) { return c->fp64 && c->twf != nullptr; }
 inline bool lincomb_small(const bc_ctx *c) { return use_fp64(c) && c->p < ((u64)1 << 20); }
 }  // namespace bc
 
+namespace bc {
+// Brackets one launch (or one operation's launches) with the context's
+// profiler when it is on.
+struct ProfScope {
+    const bc_ctx *c;
+    hipStream_t st;
+    bool on;
+    ProfRec r{};
+    ProfScope(const bc_ctx *ctx, int kind, double bytes, hipStream_t s) : c(ctx), st(s), on(ctx->prof->on) {
+        if (on) c->prof->begin(kind, bytes, st, r);
+    }
+    ~ProfScope() {
+        if (!on) return;
+        try {
+            c->prof->end(r, st);
+        } catch (...) {
+        }
+    }
+};
+}  // namespace bc
+
 struct bc_keys {
     bc_ctx *ctx;
+    // process-wide unique id: recorded graphs are cached under it (a host
+    // address could be reused by a later key set after this one is freed)
+    uint64_t uid = 0;
     int ngal;
     std::vector<int> steps;      // rotation step of each Galois key
     std::vector<bc::u64> gal;    // Galois element

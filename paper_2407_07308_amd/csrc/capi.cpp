@@ -1,7 +1,9 @@
 // capi.cpp -- the extern "C" boundary: argument checks, error codes, the
 // per-thread error message, and hipGraph recording of comparison calls.
 
+#include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <sstream>
 
@@ -118,10 +120,14 @@ void run_compare_split(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, cons
     }
 }
 
+// Token of a key set inside a graph key (keys are identified by their unique
+// id, never by address).
+std::string keys_token(const bc_keys *k) { return "|K" + std::to_string(k->uid) + "|"; }
+
 std::string graph_key(int ndig, const bc_ctb *a, const bc_ctb *b, const bc_ctb *lt, const bc_ctb *mx,
                       const bc_ctb *mn, void *st, const bc_keys *k) {
     std::ostringstream os;
-    os << ndig << '|' << st << '|' << k;
+    os << ndig << '|' << st << keys_token(k);
     auto put = [&](const bc_ctb *x) { os << '|' << (x ? (void *)x->data : nullptr) << ',' << (x ? x->count : 0) << ','
                                         << (x ? x->level : 0); };
     for (int d = 0; d < ndig; d++) {
@@ -134,31 +140,52 @@ std::string graph_key(int ndig, const bc_ctb *a, const bc_ctb *b, const bc_ctb *
     return os.str();
 }
 
-// Checks one comparison request and returns its planes.
-void check_compare(bc_ctx *ctx, const bc_keys *keys, int ndigits, const bc_ctb *a_digits, const bc_ctb *b_digits,
-                   const bc_ctb *lt_out, const bc_ctb *max_out, const bc_ctb *min_out, std::vector<CtB> &A,
-                   std::vector<CtB> &B) {
+// Checks one comparison request and returns its planes and the levels and
+// noise estimates of its outputs (BC_ERR_LEVEL, before anything is launched,
+// when the circuit does not fit the chain).
+CircuitNoise check_compare(bc_ctx *ctx, const bc_keys *keys, int ndigits, const bc_ctb *a_digits,
+                           const bc_ctb *b_digits, const bc_ctb *lt_out, const bc_ctb *max_out,
+                           const bc_ctb *min_out, std::vector<CtB> &A, std::vector<CtB> &B) {
     check_ctx(ctx);
     check_keys(ctx, keys);
     BC_REQUIRE(a_digits && b_digits && ndigits >= 1 && ndigits <= 16, BC_ERR_ARG, "bad digit planes");
     BC_REQUIRE(lt_out || max_out || min_out, BC_ERR_ARG, "no output requested");
     A.clear();
     B.clear();
+    double in_noise = 0;
     for (int d = 0; d < ndigits; d++) {
         A.push_back(from_abi(ctx, &a_digits[d]));
         B.push_back(from_abi(ctx, &b_digits[d]));
+        in_noise = std::max(in_noise, std::max(A.back().noise, B.back().noise));
     }
-    int ltl = 0, mml = 0;
-    compare_levels(ctx, A[0].level, ndigits, &ltl, &mml);
+    for (int d = 0; d < ndigits; d++) {
+        BC_REQUIRE(A[d].count == A[0].count && B[d].count == A[0].count, BC_ERR_ARG,
+                   "every plane needs the same count");
+        BC_REQUIRE(A[d].level == A[0].level && B[d].level == A[0].level, BC_ERR_ARG,
+                   "every plane needs the same level");
+        BC_REQUIRE(A[d].ncomp == 2 && B[d].ncomp == 2, BC_ERR_ARG, "planes must have 2 components");
+    }
+    CircuitNoise cn{};
+    compare_levels(ctx->noise, A[0].level, in_noise, ndigits, max_out || min_out, &cn);
     auto want = [&](const bc_ctb *x, int lv) {
         CtB o = from_abi(ctx, x);
         BC_REQUIRE(o.count == A[0].count && o.level == lv && o.ncomp == 2, BC_ERR_ARG,
                    "output batch: wrong count, level or components");
     };
-    if (lt_out) want(lt_out, ltl);
+    if (lt_out) want(lt_out, cn.lt_level);
     for (int d = 0; d < ndigits; d++) {
-        if (max_out) want(&max_out[d], mml);
-        if (min_out) want(&min_out[d], mml);
+        if (max_out) want(&max_out[d], cn.mm_level);
+        if (min_out) want(&min_out[d], cn.mm_level);
+    }
+    return cn;
+}
+
+// Records the output estimates in the caller's batch descriptors.
+void set_compare_noise(const CircuitNoise &cn, int ndigits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out) {
+    if (lt_out) lt_out->noise_bits = (float)cn.lt_noise;
+    for (int d = 0; d < ndigits; d++) {
+        if (max_out) max_out[d].noise_bits = (float)cn.mm_noise;
+        if (min_out) min_out[d].noise_bits = (float)cn.mm_noise;
     }
 }
 
@@ -217,13 +244,18 @@ int bc_group_compare(bc_group *g, const bc_keys *const *keys, const int32_t *ndi
         BC_REQUIRE(g && keys && ndigits && a_digits && b_digits, BC_ERR_ARG, "null argument");
         const int n = (int)g->ctxs.size();
         std::vector<std::vector<CtB>> A(n), B(n);
+        std::vector<CircuitNoise> cns;
         std::ostringstream key;
         for (int i = 0; i < n; i++) {
             const bc_ctb *lt = lt_out ? lt_out[i] : nullptr, *mx = max_out ? max_out[i] : nullptr,
                          *mn = min_out ? min_out[i] : nullptr;
-            check_compare(g->ctxs[i], keys[i], ndigits[i], a_digits[i], b_digits[i], lt, mx, mn, A[i], B[i]);
+            cns.push_back(check_compare(g->ctxs[i], keys[i], ndigits[i], a_digits[i], b_digits[i], lt, mx, mn, A[i],
+                                        B[i]));
             key << graph_key(ndigits[i], a_digits[i], b_digits[i], lt, mx, mn, stream, keys[i]) << '#';
         }
+        for (int i = 0; i < n; i++)
+            set_compare_noise(cns[i], ndigits[i], lt_out ? lt_out[i] : nullptr, max_out ? max_out[i] : nullptr,
+                              min_out ? min_out[i] : nullptr);
         hipStream_t st = (hipStream_t)stream;
         std::lock_guard<std::mutex> lk(g->mu);
         auto it = g->graphs.entries.find(key.str());
@@ -281,7 +313,7 @@ const char *bc_strerror(int code) {
         case BC_OK: return "ok";
         case BC_ERR_ARG: return "invalid argument";
         case BC_ERR_PARAM: return "invalid or mismatched parameters";
-        case BC_ERR_LEVEL: return "out of levels";
+        case BC_ERR_LEVEL: return "out of levels or noise budget";
         case BC_ERR_OOM: return "out of memory";
         case BC_ERR_HIP: return "HIP runtime error";
         case BC_ERR_KEY: return "missing switching key";
@@ -290,6 +322,49 @@ const char *bc_strerror(int code) {
 }
 
 const char *bc_last_error(void) { return tl_err.c_str(); }
+
+int bc_noise_estimate(const bc_params *prm, int32_t op, int32_t level, double a_bits, double b_bits,
+                      double *out_bits) {
+    return guard([&] {
+        BC_REQUIRE(prm && out_bits, BC_ERR_ARG, "null argument");
+        const NoiseModel m(*prm, param_moduli(*prm));
+        BC_REQUIRE(level >= 0 && level < prm->nQ, BC_ERR_ARG, "level out of range");
+        const double a = m.input((float)a_bits), b = m.input((float)b_bits);
+        double r = 0;
+        switch (op) {
+            case BC_NOISE_FRESH: r = m.fresh(); break;
+            case BC_NOISE_BUDGET: r = m.budget(level); break;
+            case BC_NOISE_ADD: r = m.add(a, b); break;
+            case BC_NOISE_TENSOR: r = m.tensor(a, b); break;
+            case BC_NOISE_MUL:
+                r = m.product(level, a, b, -INFINITY);
+                m.require(level, r, "multiplication");
+                if (level > 0) r = m.mod_switch(level, r);
+                break;
+            case BC_NOISE_MOD_SWITCH:
+                BC_REQUIRE(level >= 1, BC_ERR_LEVEL, "modulus switch: no prime left to drop at level 0");
+                r = m.mod_switch(level, a);
+                break;
+            case BC_NOISE_ROTATE: r = m.rotate(level, a); break;
+            default: throw Error(BC_ERR_ARG, "unknown noise operation");
+        }
+        *out_bits = r;
+    });
+}
+
+int bc_noise_compare(const bc_params *prm, int32_t in_level, double in_bits, int32_t ndigits, double *lt_bits,
+                     double *maxmin_bits) {
+    return guard([&] {
+        BC_REQUIRE(prm, BC_ERR_ARG, "null argument");
+        BC_REQUIRE(in_level >= 0 && in_level < prm->nQ && ndigits >= 1 && ndigits <= 16, BC_ERR_ARG,
+                   "bad level or digit count");
+        const NoiseModel m(*prm, param_moduli(*prm));
+        CircuitNoise cn{};
+        compare_levels(m, in_level, m.input((float)in_bits), ndigits, maxmin_bits != nullptr, &cn);
+        if (lt_bits) *lt_bits = cn.lt_noise;
+        if (maxmin_bits) *maxmin_bits = cn.mm_noise;
+    });
+}
 
 int bc_ctx_create(const bc_params *prm, bc_ctx **out) {
     return guard([&] {
@@ -353,8 +428,47 @@ int bc_keygen(bc_ctx *ctx, const int8_t *s, const uint64_t *a_words, const int32
 
 int bc_keys_destroy(bc_keys *keys) {
     return guard([&] {
-        if (keys) (void)hipDeviceSynchronize();
+        if (!keys) return;
+        (void)hipDeviceSynchronize();
+        // graphs recorded with these keys hold their device pointers: drop
+        // them (group graphs are keyed by the same unique id and never match
+        // a later key set)
+        bc_ctx *c = keys->ctx;
+        const std::string tok = keys_token(keys);
+        {
+            std::lock_guard<std::mutex> g(c->graph_mu);
+            auto &ents = c->graphs->entries;
+            for (auto it = ents.begin(); it != ents.end();) {
+                if (it->first.find(tok) != std::string::npos) {
+                    if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+                    if (it->second.graph) (void)hipGraphDestroy(it->second.graph);
+                    for (void *p : it->second.blocks) (void)hipFree(p);
+                    it = ents.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
         delete keys;
+    });
+}
+
+int bc_keys_export(bc_ctx *ctx, const bc_keys *keys, void *buf, size_t cap, size_t *size) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(size, BC_ERR_ARG, "null size");
+        StreamScope sc(nullptr);
+        *size = keys_export(ctx, keys, buf, cap);
+    });
+}
+
+int bc_keys_import(bc_ctx *ctx, const void *buf, size_t size, bc_keys **out) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(out, BC_ERR_ARG, "null output");
+        StreamScope sc(nullptr);
+        *out = keys_import(ctx, buf, size);
     });
 }
 
@@ -368,6 +482,7 @@ int bc_encrypt(bc_ctx *ctx, const bc_keys *keys, const uint32_t *slots, const in
         out->ncomp = 2;
         StreamScope sc(stream);
         encrypt(ctx, keys, slots, u, errors, from_abi(ctx, out), (hipStream_t)stream);
+        out->noise_bits = (float)ctx->noise.fresh();
     });
 }
 
@@ -414,7 +529,11 @@ int bc_tensor(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *
     return guard([&] {
         check_ctx(ctx);
         StreamScope sc(stream);
-        tensor(ctx, from_abi(ctx, a), from_abi(ctx, b), from_abi(ctx, out), (hipStream_t)stream);
+        const CtB x = from_abi(ctx, a), y = from_abi(ctx, b), o = from_abi(ctx, out);
+        const double nb = ctx->noise.tensor(x.noise, y.noise);
+        ctx->noise.require(o.level, nb, "tensor");
+        tensor(ctx, x, y, o, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
     });
 }
 
@@ -423,7 +542,11 @@ int bc_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, bc_ctb *out, vo
         check_ctx(ctx);
         check_keys(ctx, keys);
         StreamScope sc(stream);
-        relin(ctx, keys, from_abi(ctx, in), from_abi(ctx, out), (hipStream_t)stream);
+        const CtB x = from_abi(ctx, in), o = from_abi(ctx, out);
+        const double nb = ctx->noise.key_switch(x.level, x.noise);
+        ctx->noise.require(x.level, nb, "relinearisation");
+        relin(ctx, keys, x, o, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
     });
 }
 
@@ -431,7 +554,12 @@ int bc_mod_switch(bc_ctx *ctx, const bc_ctb *in, bc_ctb *out, void *stream) {
     return guard([&] {
         check_ctx(ctx);
         StreamScope sc(stream);
-        mod_switch(ctx, from_abi(ctx, in), from_abi(ctx, out), (hipStream_t)stream);
+        const CtB x = from_abi(ctx, in), o = from_abi(ctx, out);
+        BC_REQUIRE(x.level >= 1, BC_ERR_LEVEL, "modulus switch: no prime left to drop at level 0");
+        const double nb = ctx->noise.mod_switch(x.level, x.noise);
+        ctx->noise.require(x.level, x.noise, "modulus switch input");
+        mod_switch(ctx, x, o, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
     });
 }
 
@@ -440,7 +568,13 @@ int bc_mul_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *a, const bc_ctb
         check_ctx(ctx);
         check_keys(ctx, keys);
         StreamScope sc(stream);
-        mul_relin(ctx, keys, from_abi(ctx, a), from_abi(ctx, b), from_abi(ctx, out), (hipStream_t)stream);
+        const CtB x = from_abi(ctx, a), y = from_abi(ctx, b), o = from_abi(ctx, out);
+        const int lv = std::min(x.level, y.level);
+        double nb = ctx->noise.product(lv, x.noise, y.noise, -INFINITY);
+        ctx->noise.require(lv, nb, "multiplication");
+        if (lv > 0) nb = ctx->noise.mod_switch(lv, nb);
+        mul_relin(ctx, keys, x, y, o, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
     });
 }
 
@@ -449,7 +583,11 @@ int bc_rotate(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, int32_t steps,
         check_ctx(ctx);
         check_keys(ctx, keys);
         StreamScope sc(stream);
-        rotate(ctx, keys, from_abi(ctx, in), steps, from_abi(ctx, out), (hipStream_t)stream);
+        const CtB x = from_abi(ctx, in), o = from_abi(ctx, out);
+        const double nb = ctx->noise.rotate(x.level, x.noise);
+        ctx->noise.require(x.level, nb, "rotation");
+        rotate(ctx, keys, x, steps, o, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
     });
 }
 
@@ -457,7 +595,11 @@ int bc_add(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *str
     return guard([&] {
         check_ctx(ctx);
         StreamScope sc(stream);
-        add_sub(ctx, from_abi(ctx, a), from_abi(ctx, b), from_abi(ctx, out), false, (hipStream_t)stream);
+        const CtB x = from_abi(ctx, a), y = from_abi(ctx, b), o = from_abi(ctx, out);
+        const double nb = ctx->noise.add(x.noise, y.noise);
+        ctx->noise.require(o.level, nb, "addition");
+        add_sub(ctx, x, y, o, false, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
     });
 }
 
@@ -465,7 +607,11 @@ int bc_sub(bc_ctx *ctx, const bc_ctb *a, const bc_ctb *b, bc_ctb *out, void *str
     return guard([&] {
         check_ctx(ctx);
         StreamScope sc(stream);
-        add_sub(ctx, from_abi(ctx, a), from_abi(ctx, b), from_abi(ctx, out), true, (hipStream_t)stream);
+        const CtB x = from_abi(ctx, a), y = from_abi(ctx, b), o = from_abi(ctx, out);
+        const double nb = ctx->noise.add(x.noise, y.noise);
+        ctx->noise.require(o.level, nb, "subtraction");
+        add_sub(ctx, x, y, o, true, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
     });
 }
 
@@ -473,7 +619,11 @@ int bc_mul_scalar(bc_ctx *ctx, const bc_ctb *a, int32_t c, bc_ctb *out, void *st
     return guard([&] {
         check_ctx(ctx);
         StreamScope sc(stream);
-        mul_scalar(ctx, from_abi(ctx, a), c, from_abi(ctx, out), (hipStream_t)stream);
+        const CtB x = from_abi(ctx, a), o = from_abi(ctx, out);
+        const double nb = ctx->noise.scalar(x.noise, (double)std::llabs(centred(ctx, c)));
+        ctx->noise.require(o.level, nb, "scalar multiplication");
+        mul_scalar(ctx, x, c, o, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
     });
 }
 
@@ -481,18 +631,23 @@ int bc_add_const(bc_ctx *ctx, const bc_ctb *a, int32_t c, bc_ctb *out, void *str
     return guard([&] {
         check_ctx(ctx);
         StreamScope sc(stream);
-        add_const(ctx, from_abi(ctx, a), c, from_abi(ctx, out), (hipStream_t)stream);
+        const CtB x = from_abi(ctx, a), o = from_abi(ctx, out);
+        const double nb = ctx->noise.add_const(x.noise);
+        ctx->noise.require(o.level, nb, "constant addition");
+        add_const(ctx, x, c, o, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
     });
 }
 
 int bc_compare_levels(const bc_ctx *ctx, int32_t in_level, int32_t ndigits, int32_t *lt_level, int32_t *maxmin_level) {
     return guard([&] {
         check_ctx(ctx);
-        BC_REQUIRE(in_level >= 0 && in_level < ctx->nQ && ndigits >= 1, BC_ERR_ARG, "bad level or digit count");
-        int lt = 0, mm = 0;
-        compare_levels(ctx, in_level, ndigits, &lt, &mm);
-        if (lt_level) *lt_level = lt;
-        if (maxmin_level) *maxmin_level = mm;
+        BC_REQUIRE(in_level >= 0 && in_level < ctx->nQ && ndigits >= 1 && ndigits <= 16, BC_ERR_ARG,
+                   "bad level or digit count");
+        CircuitNoise cn{};
+        compare_levels(ctx->noise, in_level, ctx->noise.fresh(), ndigits, false, &cn);
+        if (lt_level) *lt_level = cn.lt_level;
+        if (maxmin_level) *maxmin_level = cn.mm_level;
     });
 }
 
@@ -509,7 +664,8 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
                        const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out, void *stream) {
     return guard([&] {
         std::vector<CtB> A, B;
-        check_compare(ctx, keys, ndigits, a_digits, b_digits, lt_out, max_out, min_out, A, B);
+        const CircuitNoise cn = check_compare(ctx, keys, ndigits, a_digits, b_digits, lt_out, max_out, min_out, A, B);
+        set_compare_noise(cn, ndigits, lt_out, max_out, min_out);
         hipStream_t st = (hipStream_t)stream;
         StreamScope sc(stream);
         if (ctx->exec_mode != BC_EXEC_GRAPH) {
@@ -572,6 +728,9 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
         else if (key == BC_TUNE_POOL_LIMIT_BYTES) {
             std::lock_guard<std::mutex> g(ctx->pool.mu);
             ctx->pool.limit = (size_t)value;
+        } else if (key == BC_TUNE_TEST_FAIL_ALLOC) {
+            std::lock_guard<std::mutex> g(ctx->pool.mu);
+            ctx->pool.fail_after = value;
         } else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }
@@ -586,6 +745,7 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
         else if (key == BC_TUNE_NTT_PARTS) *value = ntt_parts_log(ctx);
         else if (key == BC_TUNE_SPLIT_STREAMS) *value = ctx->split;
         else if (key == BC_TUNE_POOL_LIMIT_BYTES) *value = (int64_t)ctx->pool.limit;
+        else if (key == BC_TUNE_TEST_FAIL_ALLOC) *value = ctx->pool.fail_after;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }

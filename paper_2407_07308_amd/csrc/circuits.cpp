@@ -20,6 +20,8 @@
 // switched once (x is never below the product's level here).
 
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "ops.h"
@@ -58,18 +60,43 @@ Shape ps_shape(u64 p) {
 
 // ---------------------------------------------------------------- evaluators
 
-struct LevelEval {
-    typedef int V;
+// Levels and noise estimates of the schedule, evaluated on the host before
+// any launch: every step is checked against the budget of its level
+// (BC_ERR_LEVEL when the circuit does not fit the chain).
+struct NoiseEval {
+    struct V {
+        int lv = 0;
+        double nb = 0;
+    };
+    const NoiseModel *m;
     int count = 1;
-    V mul(V a, V b) { return out_level_mul(a, b); }
-    V mul_add(V a, V b, V) { return out_level_mul(a, b); }  // the addend is never below the product
-    V add(V a, V b) { return std::min(a, b); }
-    V sub(V a, V b) { return std::min(a, b); }
-    V mul_scalar(V a, int64_t) { return a; }
-    V add_const(V a, int64_t) { return a; }
-    int level(V a) { return a; }
-    V to_level(V a, int lv) { return std::min(a, lv); }
-    V blocks(const std::vector<V> &, int lv, int, int) { return lv; }
+    V mul(V a, V b) { return mul_add(a, b, V{std::max(a.lv, b.lv), -INFINITY}); }
+    V mul_add(V a, V b, V c) {
+        const int lv = std::min(a.lv, b.lv);  // the addend is never below the product
+        V o{lv > 0 ? lv - 1 : 0, m->product(lv, a.nb, b.nb, c.nb)};
+        m->require(lv, o.nb, "comparison circuit");
+        if (lv > 0) o.nb = m->mod_switch(lv, o.nb);
+        m->require(o.lv, o.nb, "comparison circuit");
+        return o;
+    }
+    V add(V a, V b) {
+        V o{std::min(a.lv, b.lv), m->add(a.nb, b.nb)};
+        m->require(o.lv, o.nb, "comparison circuit");
+        return o;
+    }
+    V sub(V a, V b) { return add(a, b); }
+    V mul_scalar(V a, int64_t c) { return V{a.lv, m->scalar(a.nb, (double)std::llabs(c))}; }
+    V add_const(V a, int64_t) { return V{a.lv, m->add_const(a.nb)}; }
+    int level(V a) { return a.lv; }
+    V to_level(V a, int lv) { return V{std::min(a.lv, lv), a.nb}; }
+    // every block sums b/2 babies with centred coefficients below p/2
+    V blocks(const std::vector<V> &babies, int lv, int b, int) {
+        double nb = -INFINITY;
+        for (const V &x : babies) nb = std::max(nb, x.nb);
+        V o{lv, m->scalar(nb, (double)(b / 2) * (m->p - 1) / 2)};
+        m->require(lv, o.nb, "comparison circuit");
+        return o;
+    }
     V slice(V a, int, int) { return a; }
 };
 
@@ -300,15 +327,25 @@ CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const
     return r;
 }
 
-void compare_levels(const bc_ctx *c, int in_level, int ndig, int *lt_level, int *mm_level) {
-    Shape sh = ps_shape(c->p);
-    LevelEval ev;
-    auto fz = lt_poly(ev, in_level, sh, 1, 0);
-    int lt = lexicographic(ev, fz.first, fz.second, ndig, 1);
-    if (lt_level) *lt_level = lt;
-    if (mm_level) {
-        const int al = ev.to_level(in_level, lt);
-        *mm_level = ev.mul_add(ev.sub(al, al), lt, al);
+void compare_levels(const NoiseModel &m, int in_level, double in_noise, int ndig, bool want_mm, CircuitNoise *out) {
+    Shape sh = ps_shape((u64)m.p);
+    NoiseEval ev{&m};
+    NoiseEval::V in{in_level, in_noise};
+    m.require(in_level, in_noise, "comparison input");
+    auto fz = lt_poly(ev, ev.sub(in, in), sh, 1, (int64_t)(m.p - 1) / 2);
+    NoiseEval::V lt = lexicographic(ev, fz.first, fz.second, ndig, 1);
+    out->lt_level = lt.lv;
+    out->lt_noise = lt.nb;
+    out->mm_level = lt.lv > 0 ? lt.lv - 1 : 0;
+    out->mm_noise = 0;
+    if (want_mm) {
+        const NoiseEval::V al = ev.to_level(in, lt.lv);
+        const NoiseEval::V mm = ev.mul_add(ev.sub(al, al), lt, al);
+        out->mm_level = mm.lv;
+        out->mm_noise = mm.nb;
+    } else {
+        // levels are reported either way
+        out->mm_level = lt.lv > 0 ? lt.lv - 1 : 0;
     }
 }
 

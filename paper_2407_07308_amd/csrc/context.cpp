@@ -242,6 +242,7 @@ void *Pool::alloc(size_t bytes) {
     // to free); the blocks of the shapes in current use were released last
     // and stay.  Never while a graph records: it owns the blocks it was handed.
     if (full) evict_to(limit / 8 * 7 > bytes ? limit / 8 * 7 - bytes : 0);
+    if (fail_after > 0 && --fail_after == 0) throw Error(BC_ERR_OOM, "device workspace allocation failed (test hook)");
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         // give back every cached block and retry once
@@ -368,7 +369,7 @@ Profiler::~Profiler() {
 
 // ----------------------------------------------------------------- context
 
-void build_context(bc_ctx *c, const bc_params &prm) {
+std::vector<u64> param_moduli(const bc_params &prm) {
     BC_REQUIRE(prm.logN >= 10 && prm.logN <= 16, BC_ERR_PARAM, "logN must be in [10, 16]");
     BC_REQUIRE(prm.p >= 3 && prm.p < (1 << 20), BC_ERR_PARAM, "p must be a small odd prime");
     BC_REQUIRE(is_prime64((u64)prm.p), BC_ERR_PARAM, "p must be prime");
@@ -378,6 +379,17 @@ void build_context(bc_ctx *c, const bc_params &prm) {
     BC_REQUIRE(prm.dnum >= 1 && prm.dnum <= prm.nQ, BC_ERR_PARAM, "dnum must be in [1, nQ]");
     BC_REQUIRE((prm.nQ + prm.dnum - 1) / prm.dnum <= kMaxDigit && prm.nP <= kMaxDigit, BC_ERR_PARAM,
                "at most 16 primes per digit and 16 special primes");
+    const u64 pm1 = (u64)prm.p - 1;
+    BC_REQUIRE((1 << (__builtin_ctzll(pm1) - 1)) <= (1 << prm.logN), BC_ERR_PARAM, "more slots than coefficients");
+    const u64 step = 2 * ((u64)1 << prm.logN) * (u64)prm.p;
+    std::vector<u64> mod = prime_chain(step, prm.bitsQ, prm.nQ, {});
+    auto sp = prime_chain(step, prm.bitsP, prm.nP, mod);
+    mod.insert(mod.end(), sp.begin(), sp.end());
+    return mod;
+}
+
+void build_context(bc_ctx *c, const bc_params &prm) {
+    c->mod = param_moduli(prm);
     c->prm = prm;
     c->logN = prm.logN;
     c->N = 1 << prm.logN;
@@ -387,16 +399,10 @@ void build_context(bc_ctx *c, const bc_params &prm) {
     c->dnum = prm.dnum;
     c->alpha = (prm.nQ + prm.dnum - 1) / prm.dnum;
     c->p = (u64)prm.p;
-    u64 pm1 = c->p - 1;
-    int s2 = __builtin_ctzll(pm1);
-    c->M = 1 << (s2 - 1);
-    BC_REQUIRE(c->M <= c->N, BC_ERR_PARAM, "more slots than coefficients");
+    c->M = 1 << (__builtin_ctzll(c->p - 1) - 1);
+    c->noise = NoiseModel(prm, c->mod);
 
-    const int N = c->N, nQ = c->nQ, nP = c->nP, nm = c->nmod;
-    const u64 step = 2 * (u64)N * c->p;
-    c->mod = prime_chain(step, prm.bitsQ, nQ, {});
-    auto sp = prime_chain(step, prm.bitsP, nP, c->mod);
-    c->mod.insert(c->mod.end(), sp.begin(), sp.end());
+    const int N = c->N, nQ = c->nQ, nm = c->nmod;
 
     // twiddles and per-prime constants
     std::vector<u64> tw((size_t)nm * 4 * N);
@@ -503,29 +509,37 @@ void build_context(bc_ctx *c, const bc_params &prm) {
 
 }  // namespace bc
 
+namespace {
+// frees a device table (no runtime call for one never allocated)
+template <class T>
+void dfree(T *p) {
+    if (p) (void)hipFree((void *)p);
+}
+}  // namespace
+
 bc_ctx::~bc_ctx() {
     graphs.reset();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     for (auto s : split_streams) (void)hipStreamDestroy(s);
     for (auto e : split_done) (void)hipEventDestroy(e);
     if (split_fork) (void)hipEventDestroy(split_fork);
-    (void)hipFree(tw);
-    (void)hipFree(twf);
-    (void)hipFree(pinfo);
-    (void)hipFree(modup);
-    (void)hipFree(moddown);
-    (void)hipFree(modsw);
-    (void)hipFree(modup_f);
-    (void)hipFree(moddown_f);
-    (void)hipFree(modsw_f);
-    (void)hipFree(garner);
-    for (auto &kv : ps_coef) (void)hipFree(kv.second);
+    dfree(tw);
+    dfree(twf);
+    dfree(pinfo);
+    dfree(modup);
+    dfree(moddown);
+    dfree(modsw);
+    dfree(modup_f);
+    dfree(moddown_f);
+    dfree(modsw_f);
+    dfree(garner);
+    for (auto &kv : ps_coef) dfree(kv.second);
 }
 
 bc_keys::~bc_keys() {
-    (void)hipFree(s_ntt);
-    (void)hipFree(pk);
-    (void)hipFree(rlk);
-    for (auto p : gk) (void)hipFree(p);
-    for (auto p : perm) (void)hipFree(p);
+    dfree(s_ntt);
+    dfree(pk);
+    dfree(rlk);
+    for (auto p : gk) dfree(p);
+    for (auto p : perm) dfree(p);
 }

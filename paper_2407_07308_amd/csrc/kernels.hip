@@ -746,6 +746,8 @@ inline dim3 grid3(int N, int y, int z) { return dim3((unsigned)(N / kT), (unsign
 
 void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, const u64 *addend, u64 *out, int count, int bcount,
                    int nl, int na, int nb, int nc, hipStream_t st) {
+    ProfScope ps(c, kProfTensor, 8.0 * c->N * nl * (2.0 * count + 2.0 * bcount + (addend ? 2.0 * count : 0) + 3.0 * count),
+                 st);
     if (addend)
         k_tensor<true><<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, addend, out, bcount, nl, na, nb, nc, c->pinfo,
                                                              c->N);
@@ -790,11 +792,19 @@ static void modup_a(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int leve
     else modup_pl<FP, 0, kMaxDigit>(c, xc, mu, count, level, next, st);
 }
 void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, hipStream_t st) {
+    double limbs = 0;  // each digit's source limbs read, its new limbs written
+    for (int j = 0; j < c->dnum; j++) {
+        const ModUpPlan &p = c->h_modup[(size_t)level * c->dnum + j];
+        if (p.nsrc) limbs += p.nsrc + p.ntgt;
+    }
+    ProfScope ps(c, kProfModUp, 8.0 * c->N * limbs * count, st);
     if (use_fp64(c)) modup_a<true>(c, xc, mu, count, level, next, pl, st);
     else modup_a<false>(c, xc, mu, count, level, next, pl, st);
 }
 void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_stride, const u64 *key, u64 *acc,
                      int count, int level, int next, int nact, hipStream_t st) {
+    // raised limbs of every active digit read, two accumulators written, the key read once
+    ProfScope ps(c, kProfKsInner, 8.0 * c->N * next * ((double)count * (nact + 2) + 2.0 * nact), st);
     const dim3 g = grid3(c->N, next, (count + kKsCts - 1) / kKsCts);
     if (use_fp64(c))
         k_ks_inner<true><<<g, kT, 0, st>>>(mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum,
@@ -843,6 +853,8 @@ static void relin_ms_fbc_a(const bc_ctx *c, const u64 *acc, const u64 *d, size_t
 }
 void launch_relin_ms_fbc(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
                          int level, int next, int pl, hipStream_t st) {
+    // per component: the special and top accumulator limbs and d's top limb read, `level` limbs written
+    ProfScope ps(c, kProfRelinMs, 8.0 * c->N * 2.0 * count * (c->nP + 2 + level), st);
     if (use_fp64(c)) relin_ms_fbc_a<true>(c, acc, d, d_ct_stride, E, count, level, next, pl, st);
     else relin_ms_fbc_a<false>(c, acc, d, d_ct_stride, E, count, level, next, pl, st);
 }
@@ -901,6 +913,7 @@ void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *nlb, c
         ba.nlb[k] = nlb[k];
     }
     for (int t = 0; t < nblk; t++) ba.pos[t] = pos[t];
+    ProfScope ps(c, kProfLincomb, 8.0 * c->N * 2.0 * nl * nlaunch * (nbaby + nblk), st);
     if (lincomb_small(c))
         k_lincomb<true><<<grid3(c->N, nl, 2 * nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl,
                                                                     c->pinfo, c->N);

@@ -14,6 +14,7 @@
 #include "ops.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 
 namespace bc {
@@ -38,6 +39,7 @@ CtB from_abi(const bc_ctx *c, const bc_ctb *x) {
     b.count = x->count;
     b.level = x->level;
     b.ncomp = x->ncomp;
+    b.noise = c->noise.input(x->noise_bits);
     return b;
 }
 
@@ -349,11 +351,21 @@ int out_level_mul(int la, int lb) {
     return lv > 0 ? lv - 1 : 0;
 }
 
+// Fused-minimum HBM bytes of a multiplication of `count` ciphertexts at
+// level lv (each operand read once, the key read once per ciphertext, the
+// result written once): (4 (l+1) + 2 beta_l (l+1+k) + 2 l') N 8, l' the
+// output's limbs; an addend adds its 2 (l+1) limbs.
+static double mul_min_bytes(const bc_ctx *c, int count, int lv, bool addend) {
+    const double nl = lv + 1, beta = lv / c->alpha + 1, nout = lv > 0 ? lv : 1;
+    return 8.0 * c->N * count * (4 * nl + 2 * beta * (nl + c->nP) + 2 * nout + (addend ? 2 * nl : 0));
+}
+
 void mul_relin(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const CtB &out, hipStream_t st) {
     check_pair(a, b);
     int lv = std::min(a.level, b.level);
     BC_REQUIRE(out.level == out_level_mul(a.level, b.level) && out.ncomp == 2 && out.count == a.count, BC_ERR_ARG,
                "multiplication: output shape");
+    ProfScope ps(c, kProfMul, mul_min_bytes(c, a.count, lv, false), st);
     CtB t3 = alloc_ct(c, a.count, lv, 3);
     tensor(c, a, b, t3, st);
     if (lv == 0) {
@@ -375,6 +387,7 @@ void mul_relin_add(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, cons
     BC_REQUIRE(out.level == out_level_mul(a.level, b.level) && out.ncomp == 2 && out.count == a.count, BC_ERR_ARG,
                "multiply-accumulate: output shape");
     BC_REQUIRE(a.ncomp == 2 && b.ncomp == 2, BC_ERR_ARG, "tensor takes 2-component ciphertexts");
+    ProfScope ps(c, kProfMul, mul_min_bytes(c, a.count, lv, true), st);
     // operands above lv are read at their lowest lv + 1 limbs (alignment by dropping primes)
     CtB t3 = alloc_ct(c, a.count, lv, 3);
     launch_tensor(c, a.data, b.data, add.data, t3.data, a.count, b.count, lv + 1, a.level + 1, b.level + 1,
@@ -556,8 +569,10 @@ bc_keys *keygen(bc_ctx *c, const int8_t *s, const u64 *words, const int32_t *err
         BC_REQUIRE(steps[r] == BC_ROW_SWAP || (steps[r] >= 1 && steps[r] < c->M / 2), BC_ERR_ARG,
                    "rotation step out of range");
     hipStream_t st = nullptr;
+    static std::atomic<uint64_t> next_uid{1};
     std::unique_ptr<bc_keys> k(new bc_keys());
     k->ctx = c;
+    k->uid = next_uid.fetch_add(1);
     k->ngal = nrot;
     const size_t nwords = (size_t)nQ * N + (size_t)(1 + nrot) * dnum * nm * N;
     const size_t nerr = (size_t)N + (size_t)(1 + nrot) * dnum * N;
@@ -628,6 +643,153 @@ bc_keys *keygen(bc_ctx *c, const int8_t *s, const u64 *words, const int32_t *err
         BC_HIP(hipMalloc(&gk, sizeof(u64) * (size_t)dnum * 2 * nm * N));
         k->gk.push_back(gk);
         make_ksk(s2, gk, (size_t)(1 + r));
+    }
+    BC_HIP(hipStreamSynchronize(st));
+    check_hip();
+    return k.release();
+}
+
+// ------------------------------------------------- key export and import
+// Flat little-endian format, every polynomial in the coefficient domain
+// (limb-major, residues in [0, q_i)):
+//   KeyBlobHeader; int32 steps[nrot]; int8 s[N] (zero-padded to a multiple
+//   of 8 bytes); u64 pk[2][nQ][N]; u64 rlk[dnum][2][nQ+nP][N];
+//   u64 gk[nrot][dnum][2][nQ+nP][N].
+namespace {
+struct KeyBlobHeader {
+    char magic[4];
+    uint32_t version;
+    bc_params prm;
+    int32_t nrot;
+};
+constexpr uint32_t kKeyBlobVersion = 1;
+
+size_t key_blob_size(const bc_ctx *c, int nrot) {
+    const size_t N = c->N, nm = c->nmod;
+    return sizeof(KeyBlobHeader) + sizeof(int32_t) * nrot + (N + 7) / 8 * 8 +
+           sizeof(u64) * (2 * c->nQ * N + (size_t)(1 + nrot) * c->dnum * 2 * nm * N);
+}
+
+// limbs [npoly][nl][N] of primes 0..nl-1 (NTT domain) -> host, coefficient domain
+void download_coeff(bc_ctx *c, const u64 *dev, int npoly, int nl, int nlimb_prime_base, u64 *host, hipStream_t st) {
+    const size_t words = (size_t)npoly * nl * c->N;
+    BufP T = make_buf(c, sizeof(u64) * words);
+    Jobs j;
+    for (int i = 0; i < nl; i++) j.add(i, nlimb_prime_base + i);
+    run_ntt(c, (u64 *)T->p, (size_t)nl * c->N, npoly, j, true, st, dev, (size_t)nl * c->N);
+    BC_HIP(hipMemcpyAsync(host, T->p, sizeof(u64) * words, hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+}
+
+// host coefficient-domain limbs -> device, NTT domain (every residue checked below its prime)
+void upload_ntt(bc_ctx *c, const u64 *host, int npoly, int nl, u64 *dev, hipStream_t st) {
+    const size_t N = c->N;
+    for (int b = 0; b < npoly; b++)
+        for (int i = 0; i < nl; i++) {
+            const u64 q = c->mod[i], *h = host + ((size_t)b * nl + i) * N;
+            for (size_t n = 0; n < N; n++) BC_REQUIRE(h[n] < q, BC_ERR_ARG, "key import: residue out of range");
+        }
+    BC_HIP(hipMemcpyAsync(dev, host, sizeof(u64) * npoly * nl * N, hipMemcpyHostToDevice, st));
+    Jobs j;
+    for (int i = 0; i < nl; i++) j.add(i, i);
+    run_ntt(c, dev, (size_t)nl * N, npoly, j, false, st);
+    BC_HIP(hipStreamSynchronize(st));
+}
+}  // namespace
+
+size_t keys_export(bc_ctx *c, const bc_keys *k, void *buf, size_t cap) {
+    const size_t need = key_blob_size(c, k->ngal);
+    if (!buf) return need;
+    BC_REQUIRE(cap >= need, BC_ERR_ARG, "key export: buffer too small");
+    const int N = c->N, nQ = c->nQ, nm = c->nmod, dnum = c->dnum;
+    hipStream_t st = nullptr;
+    char *o = (char *)buf;
+    KeyBlobHeader h{};
+    std::memcpy(h.magic, "BCK1", 4);
+    h.version = kKeyBlobVersion;
+    h.prm = c->prm;
+    h.nrot = k->ngal;
+    std::memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    std::memcpy(o, k->steps.data(), sizeof(int32_t) * k->ngal);
+    o += sizeof(int32_t) * k->ngal;
+    // the secret's coefficients from its residues mod q_0
+    std::vector<u64> s0((size_t)N);
+    download_coeff(c, k->s_ntt, 1, 1, 0, s0.data(), st);
+    std::memset(o, 0, (N + 7) / 8 * 8);
+    const u64 q0 = c->mod[0];
+    for (int n = 0; n < N; n++) o[n] = (char)(s0[n] == 0 ? 0 : s0[n] == 1 ? 1 : -1);
+    (void)q0;
+    o += (N + 7) / 8 * 8;
+    download_coeff(c, k->pk, 2, nQ, 0, (u64 *)o, st);
+    o += sizeof(u64) * 2 * nQ * N;
+    auto ksk = [&](const u64 *key) {
+        download_coeff(c, key, dnum * 2, nm, 0, (u64 *)o, st);
+        o += sizeof(u64) * (size_t)dnum * 2 * nm * N;
+    };
+    ksk(k->rlk);
+    for (int r = 0; r < k->ngal; r++) ksk(k->gk[r]);
+    return need;
+}
+
+bc_keys *keys_import(bc_ctx *c, const void *buf, size_t size) {
+    BC_REQUIRE(buf && size >= sizeof(KeyBlobHeader), BC_ERR_ARG, "key import: truncated blob");
+    KeyBlobHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    BC_REQUIRE(std::memcmp(h.magic, "BCK1", 4) == 0 && h.version == kKeyBlobVersion, BC_ERR_ARG,
+               "key import: not a key blob of this version");
+    BC_REQUIRE(std::memcmp(&h.prm, &c->prm, sizeof(bc_params)) == 0, BC_ERR_PARAM,
+               "key import: the keys belong to another parameter set");
+    BC_REQUIRE(h.nrot >= 0 && h.nrot <= 64, BC_ERR_ARG, "key import: bad rotation key count");
+    BC_REQUIRE(size == key_blob_size(c, h.nrot), BC_ERR_ARG, "key import: blob size does not match its header");
+    const int N = c->N, nQ = c->nQ, nm = c->nmod, dnum = c->dnum;
+    hipStream_t st = nullptr;
+    const char *in = (const char *)buf + sizeof h;
+    std::vector<int32_t> steps(h.nrot);
+    std::memcpy(steps.data(), in, sizeof(int32_t) * h.nrot);
+    in += sizeof(int32_t) * h.nrot;
+    for (int r = 0; r < h.nrot; r++)
+        BC_REQUIRE(steps[r] == BC_ROW_SWAP || (steps[r] >= 1 && steps[r] < c->M / 2), BC_ERR_ARG,
+                   "key import: rotation step out of range");
+    const int8_t *sh = (const int8_t *)in;
+    for (int n = 0; n < N; n++) BC_REQUIRE(sh[n] >= -1 && sh[n] <= 1, BC_ERR_ARG, "key import: secret not ternary");
+    in += (N + 7) / 8 * 8;
+    static std::atomic<uint64_t> next_uid{1u << 30};
+    std::unique_ptr<bc_keys> k(new bc_keys());
+    k->ctx = c;
+    k->uid = next_uid.fetch_add(1);
+    k->ngal = h.nrot;
+    std::vector<int16_t> primes(nm);
+    for (int i = 0; i < nm; i++) primes[i] = (int16_t)i;
+    BufP dprimes = upload_tmp(c, primes.data(), primes.size(), st);
+    BufP ds = upload_tmp(c, sh, (size_t)N, st);
+    BC_HIP(hipMalloc(&k->s_ntt, sizeof(u64) * nm * N));
+    launch_lift_small(c, nullptr, (const int8_t *)ds->p, N, nullptr, k->s_ntt, (const int16_t *)dprimes->p, 1, nm,
+                      false, st);
+    Jobs jall;
+    for (int i = 0; i < nm; i++) jall.add(i, i);
+    run_ntt(c, k->s_ntt, 0, 1, jall, false, st);
+    BC_HIP(hipMalloc(&k->pk, sizeof(u64) * 2 * nQ * N));
+    upload_ntt(c, (const u64 *)in, 2, nQ, k->pk, st);
+    in += sizeof(u64) * 2 * nQ * N;
+    const size_t kw = (size_t)dnum * 2 * nm * N;
+    BC_HIP(hipMalloc(&k->rlk, sizeof(u64) * kw));
+    upload_ntt(c, (const u64 *)in, dnum * 2, nm, k->rlk, st);
+    in += sizeof(u64) * kw;
+    for (int r = 0; r < h.nrot; r++) {
+        const u64 g = galois_for_step(c, steps[r]);
+        auto perm = galois_perm(c, g);
+        u32 *dperm = nullptr;
+        BC_HIP(hipMalloc(&dperm, sizeof(u32) * N));
+        BC_HIP(hipMemcpy(dperm, perm.data(), sizeof(u32) * N, hipMemcpyHostToDevice));
+        k->perm.push_back(dperm);
+        k->steps.push_back(steps[r]);
+        k->gal.push_back(g);
+        u64 *gk = nullptr;
+        BC_HIP(hipMalloc(&gk, sizeof(u64) * kw));
+        k->gk.push_back(gk);
+        upload_ntt(c, (const u64 *)in, dnum * 2, nm, gk, st);
+        in += sizeof(u64) * kw;
     }
     BC_HIP(hipStreamSynchronize(st));
     check_hip();

@@ -22,6 +22,7 @@ inline BufP make_buf(bc_ctx *c, size_t bytes) { return std::make_shared<Buf>(c, 
 struct CtB {
     u64 *data = nullptr;
     int count = 0, level = 0, ncomp = 2;
+    double noise = 0;  // estimated noise bits (see NoiseModel)
     BufP own;  // null for caller-owned memory
     size_t ct_words(int N) const { return (size_t)ncomp * (level + 1) * N; }
     CtB slice(int first, int n, int N) const {
@@ -56,6 +57,9 @@ int out_level_mul(int la, int lb);
 
 // keys and client side
 bc_keys *keygen(bc_ctx *c, const int8_t *s, const u64 *words, const int32_t *err, const int32_t *steps, int nrot);
+// key sets as a flat coefficient-domain blob (checkpoint / resume, parity)
+size_t keys_export(bc_ctx *c, const bc_keys *k, void *buf, size_t cap);
+bc_keys *keys_import(bc_ctx *c, const void *buf, size_t size);
 void encrypt(bc_ctx *c, const bc_keys *k, const u32 *slots, const int8_t *u, const int32_t *err, const CtB &out,
              hipStream_t st);
 void decrypt_poly(bc_ctx *c, const bc_keys *k, const CtB &in, u32 *coeffs, hipStream_t st);
@@ -69,6 +73,13 @@ struct CompareResult {
     CtB lt, mx, mn;  // mx, mn: plane-major [ndig * count]
 };
 CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, bool want_mm, hipStream_t st);
-void compare_levels(const bc_ctx *c, int in_level, int ndig, int *lt_level, int *mm_level);
+// Levels and noise estimates of the outputs of a comparison of inputs at
+// in_level with noise in_noise; BC_ERR_LEVEL when a step of the circuit would
+// exceed its level's noise budget (the circuit is deeper than the chain).
+struct CircuitNoise {
+    int lt_level, mm_level;
+    double lt_noise, mm_noise;
+};
+void compare_levels(const NoiseModel &m, int in_level, double in_noise, int ndig, bool want_mm, CircuitNoise *out);
 
 }  // namespace bc

@@ -28,5 +28,5 @@ def test_library_exports_every_declared_symbol():
 def test_strerror_is_host_only():
     L = bc.lib()
     assert L.bc_strerror(0) == b"ok"
-    assert L.bc_strerror(bc.BC_ERR_LEVEL) == b"out of levels"
+    assert L.bc_strerror(bc.BC_ERR_LEVEL) == b"out of levels or noise budget"
     assert L.bc_ct_words(None, 0, 2) == 0

@@ -1,16 +1,17 @@
 """Mixed ring sizes in one recorded graph, and the continuous-batching server.
 
 Both are scheduling layers: their results must be byte-identical to the plain
-per-context comparison of the same inputs, which is itself pinned to the
-oracle by the circuit parity tests; decryptions are checked against the
-plaintext semantics.
+per-context comparison of the same inputs, and sampled results are compared
+with the oracle's evaluation of the same request on the same seeded inputs
+(one served request's LT and max planes, one N = 2^13 pair of the mixed
+group); decryptions are checked against the plaintext semantics.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from oracle import Params
+from oracle import CtEvaluator, Oracle, Params
 
 pytestmark = pytest.mark.gpu
 
@@ -105,6 +106,32 @@ def test_server_results_equal_alone_and_in_the_mix():
             assert np.array_equal(val, np.maximum(r.xs, r.ys))
     summ = serving.latency_summary(reqs)
     assert summ["p99_ms"] >= summ["p50_ms"] > 0
+    # oracle parity of one served request (request 1: N = 2^11, 2 groups,
+    # max), group 1 of its batch slice: LT and every max plane
+    r = reqs[1]
+    assert r.kind == "max" and r.N == 1 << 11
+    prm = Params(11, 257, 12, 50, 4, 50, 3)
+    orc = Oracle(prm)
+    orc.keygen(synth.keygen_randomness(4, prm.N, prm.nQ, prm.nP, prm.dnum, 0))
+    gi = 1
+    oa = oracle_planes(orc, r.xs, 300 + 10 * r.rid, gi)
+    ob = oracle_planes(orc, r.ys, 600 + 10 * r.rid, gi)
+    ev = CtEvaluator(orc)
+    o_lt = oracle.compare_lt(ev, oa, ob, prm.p)
+    o_mx, _ = oracle.max_min(ev, oa, ob, o_lt)
+    dev = members[r.N][0]
+    assert np.array_equal(dev.export(r.result[0])[gi], o_lt.data)
+    for d in range(ND):
+        assert np.array_equal(dev.export(r.result[1][d])[gi], o_mx[d].data), f"max plane {d}"
+
+
+def oracle_planes(orc, vals, seed, gi):
+    """The oracle's ciphertexts of group gi of `planes(dev, dk, vals, seed)`."""
+    out = []
+    for d, pl in enumerate(oracle.to_digits(vals, BASE, ND)):
+        r = synth.encrypt_randomness(seed + d, pl.shape[0], orc.N)
+        out.append(orc.encrypt(pl[gi], r["u"][gi], r["e"][gi]))
+    return out
 
 
 def test_server_measures_group_bytes_and_bounds_pools():
@@ -147,6 +174,17 @@ def test_mixed_ring_sizes_at_workload_sizes_concurrently():
         reqs.append((dk, A, B))
         truth.append(((x.astype(np.int64) - y) % 257 >= 129).astype(np.uint32))
     refs = [dev.compare_lt(dk, A, B) for (dev, dk), (_, A, B) in zip(members, reqs)]
+    # oracle parity of pair 5 of the N = 2^13 member
+    prm, pi = chains[13], 5
+    orc = Oracle(prm)
+    orc.keygen(synth.keygen_randomness(50 + 13, prm.N, prm.nQ, prm.nP, prm.dnum, 0))
+    x = synth.slot_values(60 + 13, 24, orc.M, 0, 257)
+    y = synth.slot_values(70 + 13, 24, orc.M, 0, 257)
+    rx, ry = synth.encrypt_randomness(80 + 13, 24, orc.N), synth.encrypt_randomness(90 + 13, 24, orc.N)
+    ox = orc.encrypt(x[pi], rx["u"][pi], rx["e"][pi])
+    oy = orc.encrypt(y[pi], ry["u"][pi], ry["e"][pi])
+    o_lt = oracle.compare_lt(CtEvaluator(orc), [ox], [oy], 257)
+    assert np.array_equal(members[0][0].export(refs[0])[pi], o_lt.data)
     grp = bc.Group([m[0] for m in members])
     outs = grp.compare_max_min(reqs, want_max=False, want_min=False)
     for rep in range(2):

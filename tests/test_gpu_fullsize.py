@@ -88,3 +88,45 @@ def test_uint16_lt_max_min_at_workload_size():
     for d in range(nd):
         same_ct(dev, mx[d], 0, o_mx[d])
         same_ct(dev, mn[d], 0, o_mn[d])
+
+
+@pytest.mark.parametrize("name,seed", [("n14_p257", 104), ("n15_p257", 105)])
+def test_rotation_and_level0_mul_at_workload_size(name, seed):
+    """Rotation at the workload ring sizes takes the key-switching route of
+    those sizes (part-limb raising transforms, then whole-limb ModDown and
+    the key-switch combination): compared with the oracle for a one-slot
+    rotation and the row swap, at the top level and one level down; then one
+    multiplication at level 0 (no modulus switch) at full size."""
+    import paper_2407_07308_amd as bc
+
+    prm = oracle.PARAMS[name]
+    steps = (1, bc.BC_ROW_SWAP)
+    dev = bc.Context.from_params(prm)
+    rnd = synth.keygen_randomness(seed, prm.N, prm.nQ, prm.nP, prm.dnum, len(steps))
+    dk = dev.keygen(rnd["s"], rnd["a"], rnd["e"], steps)
+    dev.autotune()
+    orc = Oracle(prm)
+    orc.keygen(rnd, rot_steps=steps)
+    G = 3
+    vals = synth.slot_values(seed, G, dev.M, 0, prm.p)
+    r = synth.encrypt_randomness(seed + 1, G, dev.N)
+    x = dev.encrypt(dk, vals, r["u"], r["e"])
+    ox = orc.encrypt(vals[0], r["u"][0], r["e"][0])
+    print(f"\n[fullsize] {name}: rotations {steps} of {G} ciphertexts, oracle on ciphertext 0", flush=True)
+    h = dev.M // 2
+    for step in steps:
+        y = dev.rotate(dk, x, step)
+        same_ct(dev, y, 0, orc.rotate(ox, step))
+        want = np.concatenate([vals[:, h:], vals[:, :h]], axis=1) if step == bc.BC_ROW_SWAP else np.concatenate(
+            [np.roll(vals[:, :h], -step, axis=1), np.roll(vals[:, h:], -step, axis=1)], axis=1)
+        assert np.array_equal(dev.decrypt(dk, y), want)
+    x1, ox1 = dev.mod_switch(x), orc.mod_switch(ox)
+    same_ct(dev, dev.rotate(dk, x1, 1), 0, orc.rotate(ox1, 1))
+    # down to level 0, then one multiplication there
+    x0, ox0 = x1, ox1
+    while x0.level > 0:
+        x0, ox0 = dev.mod_switch(x0), orc.mod_switch(ox0)
+    m = dev.mul_relin(dk, x0, x0)
+    assert m.level == 0
+    same_ct(dev, m, 0, orc.mul(ox0, ox0))
+    assert np.array_equal(dev.decrypt(dk, m), vals.astype(np.int64) ** 2 % prm.p)
