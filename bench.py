@@ -40,11 +40,17 @@ def parse():
     ap.add_argument("--groups", type=int, default=64)
     ap.add_argument("--split", type=int, default=2,
                     help="concurrent slices of the batch, each on its own library stream (BC_TUNE_SPLIT_STREAMS)")
+    ap.add_argument("--persistent", type=int, default=0,
+                    help="uint16: 1 runs each step as one persistent launch (the slices as its lanes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-op", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-int", action="store_true", help="skip the integer-arithmetic comparison run")
-    ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate"], default="uint16",
+    ap.add_argument("--no-extra", action="store_true",
+                    help="uint16 only: skip the mixed-N, serving and bivariate keys of the JSON line")
+    ap.add_argument("--extra-window", type=float, default=3.0, help="serving key of the default line: seconds of arrivals")
+    ap.add_argument("--biv-groups", type=int, default=4, help="bivariate: groups of 128 uint16 pairs")
+    ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate", "bivariate"], default="uint16",
                     help="uint16: LT+max+min at N=2^15 (default); mixed: 256 single-digit pairs over "
                          "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream; "
                          "rotate: slot rotations of 192 ciphertexts at N=2^15")
@@ -76,9 +82,11 @@ def main():
     if a.pmc_summary:
         return pmc_summary(*a.pmc_summary)
     if a.workload == "mixed":
-        return mixed(a)
+        return print(json.dumps(mixed(a)))
     if a.workload == "serving":
-        return serve(a)
+        return print(json.dumps(serve(a)))
+    if a.workload == "bivariate":
+        return print(json.dumps(bivariate(a)))
     if a.workload == "rotate":
         return rotate(a)
     import numpy as np
@@ -99,6 +107,8 @@ def main():
     # fastest: 1, 2 and 4 slices gave 165, 159-160 and 164-166 ms a step)
     dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, a.split)
     tuned["split_streams"] = a.split
+    dev.set_tuning(bc.BC_TUNE_PERSISTENT, a.persistent)
+    tuned["persistent"] = a.persistent
     if a.ntt_chunk_mb is not None:
         dev.set_tuning(bc.BC_TUNE_NTT_CHUNK_BYTES, int(a.ntt_chunk_mb * 2**20))
         dev.set_tuning(bc.BC_TUNE_NTT_SINGLE_PASS, 0)
@@ -142,13 +152,15 @@ def main():
         dev.profile_enable(False)
         return e0.elapsed_time(e1) / a.steps, wall, rec
 
-    if a.split > 1:
-        # throughput with the slices concurrent; the per-launch transform
-        # figures then come from a second pass with the slices one after
-        # another, where launches do not overlap (an overlapped launch's
-        # duration includes the other slice's kernels)
+    if a.split > 1 or a.persistent:
+        # throughput with the slices concurrent (or one persistent launch);
+        # the per-launch kernel figures then come from a second pass of
+        # ordinary launches with the slices one after another, where launches
+        # do not overlap (an overlapped launch's duration includes the other
+        # slice's kernels)
         ms_step, wall_step, _ = timed(False)
         dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, 1)
+        dev.set_tuning(bc.BC_TUNE_PERSISTENT, 0)
         dev.compare_max_min(keys, A, B, outs=outs)  # warms the unsplit workspace
         unsplit_ms, _, prof = timed(True)
         dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, a.split)
@@ -284,8 +296,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"uint16 lexicographic LT+max+min, {G} groups x {M} slots x {NDIG} base-129 planes, "
                                f"BGV N=2^{prm['logN']} p={prm['p']} Q={prm['nQ']}x{prm['bitsQ']}b "
-                               f"P={prm['nP']}x{prm['bitsP']}b dnum={prm['dnum']}, batched "
-                               f"({a.split} concurrent slices)",
+                               f"P={prm['nP']}x{prm['bitsP']}b dnum={prm['dnum']}, "
+                               + (f"one persistent launch per step ({a.split} lanes)" if a.persistent else
+                                  f"batched ({a.split} concurrent slices)"),
                    "groups": G, "slots": M, "planes": NDIG, "N": N},
         "slot_comparisons_per_s": value * NDIG,
         "wall_ms_per_step": wall_step,
@@ -294,8 +307,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, copy-calibrated",
                      "kernel": KINDS[rk]["desc"], "kind": rk,
-                     "measured_in": ("the same step with the slices one after another (launches do not overlap)"
-                                     if a.split > 1 else "the timed steps"),
+                     "measured_in": ("the same step as ordinary launches with the slices one after another "
+                                     "(launches do not overlap)" if a.split > 1 or a.persistent else "the timed steps"),
                      "launches": rk_n, "avg_launch_us": 1e3 * rk_ms / max(1, rk_n),
                      "avg_launch_MB": rk_bytes / max(1, rk_n) / 1e6,
                      "ntt_schedule": tuned,
@@ -317,6 +330,31 @@ def main():
         "oracle_parity": oracle_parity,
         "oracle_parity_sample": "group 0 of the timed step: LT, 3 max and 3 min planes, every residue" if cpu else None,
     }
+    if not a.no_extra:
+        # the other workloads, each checked against its plaintext answers:
+        # mixed N (one persistent launch per step), a short serving window,
+        # and uint16 as two base-257 digits with the bivariate circuit
+        import gc
+
+        # the uint16 context, its recorded graph (which holds a whole step's
+        # workspace) and every buffer of this workload go first
+        del outs, A, B, lt, mx, mn, step_bytes
+        po = io = None  # noqa: F841 (the per-op and integer-path outputs, if any)
+        del dev, keys
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        sub = argparse.Namespace(**vars(a))
+        sub.window = a.extra_window
+        for name, fn in (("mixed", mixed), ("serving", serve), ("bivariate", bivariate)):
+            print(f"bench: {name}", file=sys.stderr, flush=True)
+            r = fn(sub)
+            for k in ("n_gpus", "higher_is_better", "scaling", "vs_baseline", "dtype", "data"):
+                r.pop(k, None)
+            out[name] = r
+            gc.collect()
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
     print(json.dumps(out))
 
 
@@ -455,7 +493,9 @@ def rotate(a):
 
 def mixed(a):
     """256 single-digit LT pairs, N i.i.d. uniform on {2^13, 2^14, 2^15}, uniform
-    slot values in [0, 257): one recorded fork/join graph per step."""
+    slot values in [0, 257): the whole group as one persistent launch per step
+    (queue reset + persistent kernel, replayed as a graph), timed beside the
+    fork/join graph of ordinary launches."""
     import numpy as np
     import torch
 
@@ -480,28 +520,98 @@ def mixed(a):
         reqs.append((dk, A, B))
         truth.append(((x.astype(np.int64) - y) % 257 >= 129).astype(np.uint32))
     grp = bc.Group(members)
-    outs = grp.compare_max_min(reqs, want_max=False, want_min=False)
-    for _ in range(max(0, a.warmup - 1)):
-        grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(a.steps):
-        grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / a.steps
-    for dev, (dk, _, _), o, t in zip(members, reqs, outs, truth):
-        if not np.array_equal(dev.decrypt(dk, o[0]), t):
-            print("bench: mixed decryptions are wrong", file=sys.stderr)
-            sys.exit(3)
+    outs = None
+
+    def timed(mode):
+        """ms per step of the group in `mode` (graph replays after warm-up),
+        decryptions checked afterwards; None when the mode is unavailable."""
+        nonlocal outs
+        try:
+            grp.set_mode(mode)
+        except bc.BoostcomError as e:
+            print(f"bench: mixed, mode {mode} unavailable: {e}", file=sys.stderr)
+            return None
+        outs = grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)
+        for _ in range(max(0, a.warmup - 1)):
+            grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            grp.compare_max_min(reqs, outs=outs, want_max=False, want_min=False)
+        e1.record()
+        torch.cuda.synchronize()
+        for dev, (dk, _, _), o, t in zip(members, reqs, outs, truth):
+            if not np.array_equal(dev.decrypt(dk, o[0]), t):
+                print(f"bench: mixed decryptions are wrong (mode {mode})", file=sys.stderr)
+                sys.exit(3)
+        for o in outs:
+            o[0].tensor.zero_()
+        return e0.elapsed_time(e1) / a.steps
+
+    fj = timed(bc.BC_GROUP_FORK_JOIN)
+    ps = timed(bc.BC_GROUP_PERSISTENT)
+    shape = grp.mode()
+    ms = min(x for x in (fj, ps) if x is not None)
     comps = 256 * members[0].M
-    print(json.dumps({"metric": "encrypted LT slot comparisons/s, mixed N in one graph", "value": comps / (ms / 1e3),
+    return ({"metric": "encrypted LT slot comparisons/s, mixed N", "value": comps / (ms / 1e3),
                       "unit": "comparisons/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
                       "data": "synthetic",
                       "config": {"workload": "256 single-digit LT pairs, N uniform on {2^13,2^14,2^15}, p=257",
-                                 "pairs_per_N": {str(1 << L): int((pick == L).sum()) for L in (13, 14, 15)}}}))
+                                 "pairs_per_N": {str(1 << L): int((pick == L).sum()) for L in (13, 14, 15)}},
+                      "mode": "persistent" if ms == ps else "fork/join",
+                      "persistent": None if ps is None else {
+                          "ms_per_step": ps, "stages": shape[1], "tickets": shape[2], "workgroups": shape[3],
+                          "launches_per_step": 2},
+                      "fork_join_ms_per_step": fj})
+
+
+def bivariate(a):
+    """uint16 as two base-257 digits (full-range digits of F_257) compared by
+    the bivariate circuit at N = 2^15: LT + max + min of a.biv_groups groups
+    of 128 pairs, checked against the plaintext answers."""
+    import numpy as np
+    import torch
+
+    import paper_2407_07308_amd as bc
+    import synth
+
+    torch.cuda.set_device(0)
+    prm = dict(logN=15, p=257, nQ=14, bitsQ=50, nP=5, bitsP=50, dnum=3)
+    dev = bc.Context(**prm)
+    rnd = synth.keygen_randomness(SEED + 1, dev.N, prm["nQ"], prm["nP"], prm["dnum"], 0)
+    keys = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
+    dev.autotune()
+    G, nd, base = a.biv_groups, 2, 257
+    xs = synth.integers(SEED + 2, (G, dev.M), 0, 65536)
+    ys = synth.integers(SEED + 2, (G, dev.M), 0, 65536, index=1)
+    A = [dev.encrypt(keys, pl, *synth.encrypt_randomness(SEED + 30 + d, G, dev.N).values())
+         for d, pl in enumerate(digits(xs, base, nd))]
+    B = [dev.encrypt(keys, pl, *synth.encrypt_randomness(SEED + 40 + d, G, dev.N).values())
+         for d, pl in enumerate(digits(ys, base, nd))]
+    outs = dev.compare_max_min(keys, A, B, circuit=bc.BC_CIRCUIT_BIVARIATE)  # warm-up
+    steps = max(1, min(a.steps, 3))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dev.compare_max_min(keys, A, B, outs=outs, circuit=bc.BC_CIRCUIT_BIVARIATE)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    lt, mx, mn = outs
+    val = lambda planes: sum(dev.decrypt(keys, p).astype(np.int64) * base ** (nd - 1 - i) for i, p in enumerate(planes))
+    if not (np.array_equal(dev.decrypt(keys, lt), (xs < ys).astype(np.uint32))
+            and np.array_equal(val(mx), np.maximum(xs, ys)) and np.array_equal(val(mn), np.minimum(xs, ys))):
+        print("bench: bivariate decryptions are wrong", file=sys.stderr)
+        sys.exit(3)
+    return {"metric": "encrypted uint16 comparisons/s, bivariate circuit", "value": G * dev.M / (ms / 1e3),
+            "unit": "comparisons/s", "n_gpus": 1, "steps": steps, "ms_per_step": ms, "higher_is_better": True,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"uint16 as 2 base-257 digits, LT+max+min, bivariate circuit, {G} groups x "
+                                   f"{dev.M} slots, BGV N=2^15 p=257 Q=14x50b P=5x50b dnum=3",
+                       "multiplications_per_group": nd * 518 + nd - 1 + 2 * nd}}
 
 
 def serve(a):
@@ -578,7 +688,7 @@ def serve(a):
     s = serving.latency_summary(reqs)
     groups = sum(r.groups for r in reqs)
     span = max(r.done_at for r in reqs)
-    print(json.dumps({"metric": "serving latency p50/p99 and throughput", "value": s["throughput_req_s"],
+    return ({"metric": "serving latency p50/p99 and throughput", "value": s["throughput_req_s"],
                       "unit": "requests/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u64",
                       "data": "synthetic", "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "mean_ms": s["mean_ms"],
                       "uint16_comparisons_per_s": groups * 128 / span, "batches": srv.stats["batches"],
@@ -589,7 +699,7 @@ def serve(a):
                       "config": {"workload": f"Poisson {a.rate:.0f} req/s for {a.window} s, LT/max/argmax, "
                                              f"n log-uniform 64..4096, N in {{2^14,2^15}}, p=257",
                                  "requests": len(reqs), "groups": groups,
-                                 "distinct_payloads": len(pool)}}))
+                                 "distinct_payloads": len(pool)}})
 
 
 if __name__ == "__main__":

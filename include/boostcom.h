@@ -96,8 +96,10 @@ typedef struct {
  * BC_ERR_PARAM for an impossible set (checked on the host, before any device
  * work). */
 int bc_ctx_create(const bc_params *prm, bc_ctx **out);
-/* Waits for the device and frees the context (NULL is a no-op).  Every key
- * set and group of the context must be destroyed first. */
+/* Releases the caller's handle (NULL is a no-op).  The context is freed,
+ * after a device wait, once its handle, every key set made from it and every
+ * group that lists it are destroyed, in any order; the handle must not be
+ * used after this call. */
 int bc_ctx_destroy(bc_ctx *ctx);
 /* moduli[nQ + nP] in the order described at bc_params (the modulus chain of
  * "Word-wise Universal FHE Scheme", then the special primes).  BC_ERR_ARG when
@@ -259,25 +261,65 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
                        const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out,
                        void *stream);
 
+/* The bivariate circuit (paper, Introduction: the bivariate comparison
+ * circuit, exact on every pair of F_p digits, about 2p multiplications;
+ * Background, "Word-wise Universal FHE Scheme": the bivariate circuit
+ * computes LT and EQ separately).  Digits are full-range, in [0, p-1]
+ * (base p: a uint16 is two base-257 digits).  Per digit, with S = x + y and
+ * Z = x - y: LT(x, y) = (p+1)/2 Z^(p-1) + sum_{k odd} Z^k g_k(S), the unique
+ * interpolant of [x < y] on F_p x F_p of degree < p in S and in Z (its part
+ * even in Z is (p+1)/2 Z^(p-1) because LT(x,y) + LT(y,x) = (x-y)^(p-1));
+ * power ladders of S and Z (every power of S, the odd powers of Z), the g_k
+ * as exact linear combinations of the S powers, one product per odd k:
+ * 2p + 4 multiplications per digit for p = 257, depth log2(p-1) + 1.
+ * EQ = 1 - Z^(p-1); digits are combined as for bc_compare_max_min, and so
+ * are max and min.  Needs p - 1 a power of two, p < 512 and every prime
+ * below 2^50 (BC_ERR_PARAM).  Arguments as for bc_compare_max_min; the
+ * circuit's levels come from bc_compare_levels_circuit. */
+enum { BC_CIRCUIT_UNIVARIATE = 0, BC_CIRCUIT_BIVARIATE = 1 };
+int bc_compare_bivariate(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits,
+                         const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out, void *stream);
+/* bc_compare_levels for either circuit. */
+int bc_compare_levels_circuit(const bc_ctx *ctx, int32_t circuit, int32_t in_level, int32_t ndigits,
+                              int32_t *lt_level, int32_t *maxmin_level);
+
 /* Mixed ring sizes (paper, The Design of BoostCom, "Multi-Level
  * Heterogeneous Parallelization": independent comparisons overlapped to fill
- * the GPU).  A group holds several contexts (e.g. N = 2^13, 2^14, 2^15),
- * owned by the caller, distinct (BC_ERR_ARG otherwise).  bc_group_compare
- * evaluates every member's comparison batch; members run on their own
- * streams, forked from and joined back into `stream`.  The first call for a
- * given set of buffers runs eagerly and records the whole fork/join launch
- * sequence into one hipGraph; later calls replay it with one graph launch, so
- * kernels of different ring sizes overlap on the device.  Per member i:
- * keys[i], ndigits[i], planes a_digits[i][0..ndigits[i]) and b_digits[i][..]
- * as for bc_compare_max_min, outputs lt_out[i] (or NULL), max_out[i] /
- * min_out[i] (arrays of ndigits[i] batches, or NULL).  Results are identical
- * to separate bc_compare_max_min calls. */
+ * the GPU; "GPU-related Optimizations": work batched onto the device at
+ * once).  A group holds several contexts (e.g. N = 2^13, 2^14, 2^15), owned
+ * by the caller, distinct (BC_ERR_ARG otherwise).  bc_group_compare evaluates
+ * every member's comparison batch.  Per member i: keys[i], ndigits[i],
+ * planes a_digits[i][0..ndigits[i]) and b_digits[i][..] as for
+ * bc_compare_max_min, outputs lt_out[i] (or NULL), max_out[i] / min_out[i]
+ * (arrays of ndigits[i] batches, or NULL).  Results are identical to
+ * separate bc_compare_max_min calls in either mode:
+ *   BC_GROUP_PERSISTENT (for members with N = 2^13, 2^14 or 2^15, every
+ *   prime below 2^50 and the default transform schedule): the
+ *   whole group is ONE launch of a persistent kernel that drains a device
+ *   work queue.  Every kernel launch of every member's circuit becomes a
+ *   stage of that queue; members are lanes (each in its own order, lanes
+ *   independent, interleaved stage by stage); every transform is cut into
+ *   2^13-word blocks so that one workgroup shape runs every stage of every
+ *   ring size.  A stalled wait (only a library bug can cause one) ends after
+ *   2 s instead of hanging, and ends every other wait of the launch; the group's next call then returns BC_ERR_HIP.
+ *   BC_GROUP_FORK_JOIN (the default): members run on their own streams,
+ *   forked from and joined back into `stream`, each kernel its own launch.
+ * In both modes the first call for a given set of buffers runs eagerly and
+ * records what it launched (the persistent launch, or the whole fork/join
+ * sequence) into one hipGraph; later calls replay it. */
 typedef struct bc_group bc_group;
 int bc_group_create(int32_t n, bc_ctx *const *ctxs, bc_group **out);
 int bc_group_destroy(bc_group *g);
 int bc_group_compare(bc_group *g, const bc_keys *const *keys, const int32_t *ndigits, const bc_ctb *const *a_digits,
                      const bc_ctb *const *b_digits, bc_ctb *const *lt_out, bc_ctb *const *max_out,
                      bc_ctb *const *min_out, void *stream);
+enum { BC_GROUP_FORK_JOIN = 0, BC_GROUP_PERSISTENT = 1 };
+/* Sets the group's mode (BC_ERR_ARG for a persistent group with a member the
+ * persistent executor cannot run). */
+int bc_group_set_mode(bc_group *g, int32_t mode);
+/* The group's mode, and, for persistent mode, the stages, tickets and
+ * resident workgroups of its last launch (any pointer may be NULL). */
+int bc_group_get_mode(const bc_group *g, int32_t *mode, int32_t *stages, int32_t *tickets, int32_t *workgroups);
 
 /* Execution mode of the comparison calls (paper, "GPU-related
  * Optimizations": whole-matrix launches instead of one per row):
@@ -331,7 +373,12 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   workspace.
  *   BC_TUNE_TEST_FAIL_ALLOC (test hook, default 0 = off): the n-th next new
  *   device allocation of the workspace pool fails, so that a caller can force
- *   BC_ERR_OOM from the host; the hook then switches itself off. */
+ *   BC_ERR_OOM from the host; the hook then switches itself off.
+ *   BC_TUNE_PERSISTENT (default 0): 1 runs bc_compare_lt /
+ *   bc_compare_max_min as ONE launch of the persistent executor (see
+ *   BC_GROUP_PERSISTENT), the BC_TUNE_SPLIT_STREAMS slices of the groups as
+ *   its lanes; graph mode then runs it eagerly (it is a single launch).
+ *   BC_ERR_ARG where the executor cannot run the context (as for groups). */
 enum {
     BC_TUNE_NTT_CHUNK_BYTES = 0,
     BC_TUNE_NTT_SINGLE_PASS = 1,
@@ -339,7 +386,8 @@ enum {
     BC_TUNE_POOL_LIMIT_BYTES = 3,
     BC_TUNE_NTT_PARTS = 4,
     BC_TUNE_SPLIT_STREAMS = 5,
-    BC_TUNE_TEST_FAIL_ALLOC = 6
+    BC_TUNE_TEST_FAIL_ALLOC = 6,
+    BC_TUNE_PERSISTENT = 7
 };
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);
@@ -433,6 +481,12 @@ int bc_noise_estimate(const bc_params *prm, int32_t op, int32_t level, double a_
                       double *out_bits);
 int bc_noise_compare(const bc_params *prm, int32_t in_level, double in_bits, int32_t ndigits, double *lt_bits,
                      double *maxmin_bits);
+/* bc_noise_compare for either circuit (BC_CIRCUIT_UNIVARIATE or
+ * BC_CIRCUIT_BIVARIATE); also reports the output levels (either pointer may
+ * be NULL). */
+int bc_noise_compare_circuit(const bc_params *prm, int32_t circuit, int32_t in_level, double in_bits,
+                             int32_t ndigits, double *lt_bits, double *maxmin_bits, int32_t *lt_level,
+                             int32_t *maxmin_level);
 
 /* Static description of an error code, and the last error message of the
  * calling thread (valid until its next failing call). */

@@ -622,6 +622,124 @@ def max_min(ev, a_digits, b_digits, lt):
     return mx, mn
 
 
+# ---------------------------------------------------------------------------
+# the bivariate circuit (Introduction: the bivariate comparison circuit, exact
+# on every pair of digits of F_p; Background: LT and EQ per digit, combined in
+# lexicographic order)
+# ---------------------------------------------------------------------------
+
+@lru_cache(maxsize=None)
+def _lt_bivariate_table(p: int) -> tuple:
+    """The bivariate interpolant of [x < y] over all (x, y) in [0, p-1]^2, in
+    the variables S = X + Y and Z = X - Y (p odd, so (x, y) -> (s, z) is a
+    bijection of F_p^2): the unique G(S, Z) = sum_{m, k < p} c[m][k] S^m Z^k
+    with G(x + y, x - y) = [x < y].
+
+    Interpolation written out from its definition: the indicator of a point
+    a is 1 - (t - a)^(p-1), and (t - a)^(p-1) = sum_j a^(p-1-j) t^j in F_p
+    (binomial(p-1, j) = (-1)^j mod p), so the coefficient of t^j in the
+    interpolant of h is [j = 0] sum_a h(a) - sum_a h(a) a^(p-1-j) (0^0 = 1);
+    in two variables c = L^T F L with L[a][j] = [j = 0] - a^(p-1-j) and
+    F[s][z] = [x < y] for x = (s + z)/2, y = (s - z)/2."""
+    inv2 = (p + 1) // 2
+    L = np.zeros((p, p), np.int64)
+    for a in range(p):
+        for j in range(p):
+            L[a, j] = ((1 if j == 0 else 0) - pow(a, p - 1 - j, p)) % p
+    F = np.zeros((p, p), np.int64)
+    for sv in range(p):
+        for zv in range(p):
+            x, y = (sv + zv) * inv2 % p, (sv - zv) * inv2 % p
+            F[sv, zv] = 1 if x < y else 0
+    c = (L.T @ F) % p
+    c = (c @ L) % p
+    return tuple(tuple(int(v) for v in row) for row in c)
+
+
+def lt_bivariate_table(p: int) -> np.ndarray:
+    """c[m][k]: coefficient of S^m Z^k (see _lt_bivariate_table)."""
+    return np.array(_lt_bivariate_table(p), dtype=np.int64)
+
+
+def _power_ladder(ev, X, top: int, odd_only: bool):
+    """X^k for k = 1 .. top (top = 2^e), or for the odd k < top and top
+    itself: X^(2^a) by squaring, and X^(2^a + r) = X^(2^a) X^r (r < 2^a; odd r
+    when odd_only) block by block, so every power has depth ceil(log2 k)."""
+    pw = {1: X}
+    a = 1
+    while a < top:
+        pw[2 * a] = ev.mul(pw[a], pw[a])
+        a *= 2
+    a = 2
+    while a < top:
+        for r in range(1, a):
+            if odd_only and r % 2 == 0:
+                continue
+            pw[a + r] = ev.mul(pw[a], pw[r])
+        a *= 2
+    return pw
+
+
+def lt_bivariate(ev, X, Y, p: int):
+    """The bivariate interpolant of [x < y] evaluated on X, Y (exact for every
+    pair of digits in [0, p-1], p - 1 a power of two).
+
+    The interpolant satisfies LT(X, Y) + LT(Y, X) = (X - Y)^(p-1) (the two
+    orders plus equality cover every pair), so in S = X + Y, Z = X - Y its part
+    even in Z is (p+1)/2 Z^(p-1) and the rest is odd in Z:
+    LT = (p+1)/2 Z^(p-1) + sum_{k odd} Z^k g_k(S), g_k(S) = sum_m c[m][k] S^m.
+    Schedule: S^1 .. S^(p-1) (p - 2 products), Z^k for odd k and Z^(p-1)
+    (squarings plus one product per odd k >= 3), g_k(S) as scalar linear
+    combinations of the S powers (all brought to the level of S^(p-1)), one
+    product T_k = Z^k g_k(S) per odd k (Z^k brought to the same level), and
+    LT = (p+1)/2 Z^(p-1) + sum_k T_k (at T's level).  2p + 4 products for
+    p = 257 (518), depth log2(p-1) + 1.
+
+    Returns (LT, Z^(p-1)); Z^(p-1) gives EQ = 1 - Z^(p-1)."""
+    e = (p - 1).bit_length() - 1
+    assert 1 << e == p - 1, "schedule written for p - 1 a power of two"
+    c = lt_bivariate_table(p)
+    Z = ev.sub(X, Y)
+    S = ev.add(X, Y)
+    sp = _power_ladder(ev, S, p - 1, False)
+    zp = _power_ladder(ev, Z, p - 1, True)
+    lv = ev.level(sp[p - 1])
+    sl = {m: ev.to_level(sp[m], lv) for m in range(1, p)}
+    odd = list(range(1, p - 1, 2))
+    terms = []
+    for k in odd:
+        g = None
+        for m in range(1, p):
+            if c[m, k] == 0:
+                continue
+            t = ev.mul_scalar(sl[m], int(c[m, k]))
+            g = t if g is None else ev.add(g, t)
+        if g is None:
+            g = ev.mul_scalar(sl[1], 0)
+        g = ev.add_const(g, int(c[0, k]))
+        terms.append(ev.mul(ev.to_level(zp[k], lv), g))
+    lt_lv = ev.level(terms[0])
+    acc = ev.mul_scalar(ev.to_level(zp[p - 1], lt_lv), (p + 1) // 2)
+    for t in terms:
+        acc = ev.add(acc, t)
+    return acc, zp[p - 1]
+
+
+def compare_lt_bivariate(ev, a_digits, b_digits, p: int):
+    """Lexicographic LT over base-p digit planes (most significant first)
+    with the bivariate circuit per digit:
+    LT = LT_0 + EQ_0 (LT_1 + EQ_1 (... LT_{n-1})), EQ_d = 1 - (a_d - b_d)^(p-1)."""
+    lts, eqs = [], []
+    for a, b in zip(a_digits, b_digits):
+        f, top = lt_bivariate(ev, a, b, p)
+        lts.append(f)
+        eqs.append(eq_from_top(ev, top))
+    acc = lts[-1]
+    for i in range(len(lts) - 2, -1, -1):
+        acc = ev.mul_add(eqs[i], acc, lts[i])
+    return acc
+
+
 def to_digits(values, base: int, ndigits: int):
     """Integer -> digit planes, most significant first."""
     v = np.asarray(values, dtype=np.int64)

@@ -21,11 +21,14 @@ LIB_PATH = os.path.join(_HERE, "libboostcom.so")
 BC_OK, BC_ERR_ARG, BC_ERR_PARAM, BC_ERR_LEVEL, BC_ERR_OOM, BC_ERR_HIP, BC_ERR_KEY = 0, -1, -2, -3, -4, -5, -6
 BC_ROW_SWAP = -1
 BC_EXEC_BATCHED, BC_EXEC_GRAPH, BC_EXEC_PER_OP = 0, 1, 2
+BC_GROUP_FORK_JOIN, BC_GROUP_PERSISTENT = 0, 1
+BC_CIRCUIT_UNIVARIATE, BC_CIRCUIT_BIVARIATE = 0, 1
 BC_PROF_NTT_FWD, BC_PROF_NTT_INV, BC_PROF_NTT_FWD_COMBINE, BC_PROF_NTT_FWD_PART, BC_PROF_NTT_INV_PART = 0, 1, 2, 3, 4
 BC_PROF_TENSOR, BC_PROF_MODUP, BC_PROF_KS_INNER, BC_PROF_RELIN_MS, BC_PROF_LINCOMB, BC_PROF_MUL = 5, 6, 7, 8, 9, 10
 BC_TUNE_NTT_CHUNK_BYTES, BC_TUNE_NTT_SINGLE_PASS, BC_TUNE_FP64, BC_TUNE_POOL_LIMIT_BYTES = 0, 1, 2, 3
 BC_TUNE_NTT_PARTS, BC_TUNE_SPLIT_STREAMS = 4, 5
 BC_TUNE_TEST_FAIL_ALLOC = 6
+BC_TUNE_PERSISTENT = 7
 BC_NOISE_FRESH, BC_NOISE_BUDGET, BC_NOISE_ADD, BC_NOISE_TENSOR, BC_NOISE_MUL, BC_NOISE_MOD_SWITCH, BC_NOISE_ROTATE = range(7)
 
 
@@ -83,11 +86,17 @@ _SIGS = {
     "bc_compare_levels": (_I, [_V, _I, _I, _P(_I), _P(_I)]),
     "bc_compare_lt": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_compare_max_min": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_compare_bivariate": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_compare_levels_circuit": (_I, [_V, _I, _I, _I, _P(_I), _P(_I)]),
+    "bc_noise_compare_circuit": (_I, [_P(bc_params), _I, _I, ctypes.c_double, _I, _P(ctypes.c_double),
+                                      _P(ctypes.c_double), _P(_I), _P(_I)]),
     "bc_set_exec_mode": (_I, [_V, _I]),
     "bc_group_create": (_I, [_I, _P(_V), _P(_V)]),
     "bc_group_destroy": (_I, [_V]),
     "bc_group_compare": (_I, [_V, _P(_V), _P(_I), _P(_P(bc_ctb)), _P(_P(bc_ctb)), _P(_P(bc_ctb)),
                               _P(_P(bc_ctb)), _P(_P(bc_ctb)), _V]),
+    "bc_group_set_mode": (_I, [_V, _I]),
+    "bc_group_get_mode": (_I, [_V, _P(_I), _P(_I), _P(_I), _P(_I)]),
     "bc_set_tuning": (_I, [_V, _I, ctypes.c_int64]),
     "bc_autotune": (_I, [_V, _V]),
     "bc_get_tuning": (_I, [_V, _I, _P(ctypes.c_int64)]),
@@ -354,9 +363,10 @@ class Context:
         return out.take(co)
 
     # ------------------------------------------------------ comparisons
-    def compare_levels(self, in_level: int, ndigits: int):
+    def compare_levels(self, in_level: int, ndigits: int, circuit: int = BC_CIRCUIT_UNIVARIATE):
         lt, mm = ctypes.c_int32(), ctypes.c_int32()
-        _check(self.L.bc_compare_levels(self.handle, in_level, ndigits, ctypes.byref(lt), ctypes.byref(mm)))
+        _check(self.L.bc_compare_levels_circuit(self.handle, circuit, in_level, ndigits, ctypes.byref(lt),
+                                                ctypes.byref(mm)))
         return lt.value, mm.value
 
     def set_exec_mode(self, mode: int):
@@ -387,11 +397,14 @@ class Context:
         _check(self.L.bc_profile_read(self.handle, kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
         return ms.value, n.value, by.value
 
-    def compare_max_min(self, keys: Keys, a_digits, b_digits, want_lt=True, want_max=True, want_min=True, outs=None):
-        """Returns (lt, [max planes], [min planes]); ``outs`` reuses earlier output batches."""
+    def compare_max_min(self, keys: Keys, a_digits, b_digits, want_lt=True, want_max=True, want_min=True, outs=None,
+                        circuit: int = BC_CIRCUIT_UNIVARIATE):
+        """Returns (lt, [max planes], [min planes]); ``outs`` reuses earlier output batches.
+        circuit: BC_CIRCUIT_UNIVARIATE (digits in [0, (p-1)/2]) or
+        BC_CIRCUIT_BIVARIATE (full-range digits, ``bc_compare_bivariate``)."""
         nd = len(a_digits)
         G = a_digits[0].count
-        ltl, mml = self.compare_levels(a_digits[0].level, nd)
+        ltl, mml = self.compare_levels(a_digits[0].level, nd, circuit)
         if outs is None:
             lt = self.new_batch(G, ltl) if want_lt else None
             mx = [self.new_batch(G, mml) for _ in range(nd)] if want_max else None
@@ -402,8 +415,9 @@ class Context:
         clt = lt.ctb() if lt is not None else None
         cmx = _ctb_array(mx) if mx is not None else None
         cmn = _ctb_array(mn) if mn is not None else None
-        _check(self.L.bc_compare_max_min(self.handle, keys.handle, nd, A, B,
-                                         ctypes.byref(clt) if clt is not None else None, cmx, cmn, _stream()))
+        fn = self.L.bc_compare_bivariate if circuit == BC_CIRCUIT_BIVARIATE else self.L.bc_compare_max_min
+        _check(fn(self.handle, keys.handle, nd, A, B, ctypes.byref(clt) if clt is not None else None, cmx, cmn,
+                  _stream()))
         if lt is not None:
             lt.take(clt)
         if mx is not None:
@@ -417,8 +431,10 @@ class Context:
 
 
 class Group:
-    """Several contexts (ring sizes) whose comparison batches run as one
-    recorded fork/join graph (``bc_group_*``)."""
+    """Several contexts (ring sizes) whose comparison batches run together
+    (``bc_group_*``): as a fork/join of ordinary launches (the default) or as
+    one persistent launch draining a device work queue (BC_GROUP_PERSISTENT);
+    either is recorded into a hipGraph."""
 
     def __init__(self, contexts):
         self.contexts = list(contexts)
@@ -433,6 +449,15 @@ class Group:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.bc_group_destroy(self.handle)
             self.handle = None
+
+    def set_mode(self, mode: int):
+        _check(self.L.bc_group_set_mode(self.handle, mode))
+
+    def mode(self):
+        """(mode, stages, tickets, workgroups) of the last persistent launch."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(self.L.bc_group_get_mode(self.handle, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def compare_max_min(self, requests, outs=None, want_lt=True, want_max=True, want_min=True):
         """requests: list over members of (keys, a_digits, b_digits).  Returns

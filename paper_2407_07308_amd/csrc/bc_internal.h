@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -137,6 +138,16 @@ __device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const Barrett &m) {
 
 // ------------------------------------------------------ launch descriptors
 
+// Block coordinates a kernel body works on: the hardware's when the body runs
+// as its own kernel, a virtual block's when the persistent executor runs it.
+struct VBlk {
+    int x, y, z;     // block index
+    int gx, gy, gz;  // grid size
+};
+__device__ __forceinline__ VBlk hw_blk() {
+    return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x, (int)gridDim.y, (int)gridDim.z};
+}
+
 // A list of residue polynomials (limbs) inside a batch: limb k of poly b sits
 // at base + b * poly_stride + off[k] * N and is reduced mod prime[k].
 struct LimbSet {
@@ -151,6 +162,26 @@ struct LimbSet {
     const u64 *ibase;
     u64 ipoly_stride;
     int16_t ioff[kMaxJobs];
+};
+
+// A scalar's residues mod each q_i (Shoup pairs): scalar multiplication and
+// constant addition.
+struct ScalarArg {
+    u64 w[kMaxMod][2];
+};
+
+// Paterson-Stockmeyer blocks: H[pos(t)][ct] = sum_k coef[t][k] * baby_k[ct]
+// (NTT domain, every baby at the same level).  Integer kernel: coef holds
+// Shoup pairs [nblk][nbaby][nl][2] of the centred coefficients mod q_i.
+// fp64 kernel: coef holds the centred coefficients themselves as doubles
+// [nblk][nbaby] (|c| < p/2 < 2^19): each baby word v < 2^50 is split as
+// v = h 2^25 + l, the sums of c h and of c l stay below 16 2^19 2^25 = 2^48
+// (exact in fp64 fused multiply-adds), and the result is
+// (sum c h) (2^25 mod q) + sum c l reduced once.
+struct BabyArg {
+    const u64 *baby[16];
+    int nlb[16];  // limbs per component each baby is stored with (>= nl: its lowest nl are read)
+    int pos[64];  // storage position of block t
 };
 
 // Constants of one prime (device copy).
@@ -338,6 +369,8 @@ struct NttCombine {
     u64 w[kMaxMod][4];
 };
 
+struct PersistRunner;  // persist.h
+
 // ------------------------------------------------------------ workspace pool
 
 // Caching device allocator.  A released block is handed out again only for
@@ -504,6 +537,18 @@ struct bc_ctx {
     std::mutex table_mu;                       // guards lt_c and ps_coef
     std::vector<int64_t> lt_c;                 // LT polynomial coefficients
     std::map<int, bc::u64 *> ps_coef;          // block coefficients: per level (pairs), -1 (small ints)
+    // bivariate circuit: the weights of g_k(S) and of the final sum, as doubles
+    // (one device allocation; built on first use)
+    double *biv_tab = nullptr;
+    int biv_K = 0, biv_M = 0;
+    // owners: the caller's handle, every live key set and every group that
+    // lists the context; the last release deletes it (a key set destroyed
+    // after its context's handle still finds the context)
+    std::atomic<int> refs{1};
+    // comparisons as one persistent launch (BC_TUNE_PERSISTENT), the split
+    // slices as lanes; the runner is created on first use
+    int persistent = 0;
+    std::unique_ptr<bc::PersistRunner> runner;
     ~bc_ctx();
 };
 
@@ -519,12 +564,18 @@ inline bool lincomb_small(const bc_ctx *c) { return use_fp64(c) && c->p < ((u64)
 namespace bc {
 // Brackets one launch (or one operation's launches) with the context's
 // profiler when it is on.
+// Recording of launches for the persistent executor (persist.h): while set,
+// launchers record instead of launching and nothing is profiled.
+struct Recorder;
+extern thread_local Recorder *tl_rec;
+
 struct ProfScope {
     const bc_ctx *c;
     hipStream_t st;
     bool on;
     ProfRec r{};
-    ProfScope(const bc_ctx *ctx, int kind, double bytes, hipStream_t s) : c(ctx), st(s), on(ctx->prof->on) {
+    ProfScope(const bc_ctx *ctx, int kind, double bytes, hipStream_t s)
+        : c(ctx), st(s), on(ctx->prof->on && !tl_rec) {
         if (on) c->prof->begin(kind, bytes, st, r);
     }
     ~ProfScope() {

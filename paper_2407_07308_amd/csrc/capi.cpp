@@ -8,6 +8,7 @@
 #include <sstream>
 
 #include "ops.h"
+#include "persist.h"
 
 namespace bc {
 GraphCache::~GraphCache() {
@@ -49,22 +50,98 @@ int guard(F &&f) {
 }
 
 void check_ctx(const bc_ctx *c) { BC_REQUIRE(c, BC_ERR_ARG, "null context"); }
+
+// Drops one owner of the context; the last one waits for the device and
+// deletes it.
+void ctx_release(bc_ctx *c) {
+    if (!c || c->refs.fetch_sub(1) != 1) return;
+    (void)hipDeviceSynchronize();
+    delete c;
+}
 void check_keys(const bc_ctx *c, const bc_keys *k) {
     BC_REQUIRE(k, BC_ERR_ARG, "null keys");
     BC_REQUIRE(k->ctx == c, BC_ERR_PARAM, "keys belong to another context");
 }
 
+// Every stage kind of the persistent executor exists for this context: fp64
+// arithmetic, single-pass transforms and 2^13-word transform blocks.
+bool persist_supported(const bc_ctx *c) {
+    return use_fp64(c) && c->ntt_single_pass && c->logN - ntt_parts_log(c) == 13 && c->ntt_chunk_bytes == 0;
+}
+
+// Installs a recorder on the calling thread for one scope.
+struct RecordScope {
+    Recorder *prev;
+    explicit RecordScope(Recorder *r) : prev(tl_rec) { tl_rec = r; }
+    ~RecordScope() { tl_rec = prev; }
+};
+
 // Runs the comparison and copies results into the caller's buffers.
 void run_compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, const bc_ctb *lt_out,
-                 const bc_ctb *max_out, const bc_ctb *min_out, hipStream_t st) {
+                 const bc_ctb *max_out, const bc_ctb *min_out, hipStream_t st, int circuit = BC_CIRCUIT_UNIVARIATE) {
     bool mm = max_out || min_out;
-    CompareResult r = compare(c, k, ndig, A, B, mm, st);
+    CompareResult r = compare(c, k, ndig, A, B, mm, st, circuit);
     const int G = A[0].count;
     if (lt_out) copy_ct(c, r.lt, from_abi(c, lt_out), st);
     for (int d = 0; d < ndig; d++) {
         if (max_out) copy_ct(c, r.mx.slice(d * G, G, c->N), from_abi(c, &max_out[d]), st);
         if (min_out) copy_ct(c, r.mn.slice(d * G, G, c->N), from_abi(c, &min_out[d]), st);
     }
+}
+
+// The comparison as one persistent launch on `origin`: the groups split into
+// n slices, each a lane of the executor (workspace blocks tagged with one
+// library stream per slice, which waits for the launch afterwards).
+void run_compare_persistent(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, const bc_ctb *lt_out,
+                            const bc_ctb *max_out, const bc_ctb *min_out, hipStream_t origin, int n) {
+    BC_REQUIRE(persist_supported(c), BC_ERR_ARG, "persistent mode: unsupported context");
+    const int G = A[0].count;
+    std::lock_guard<std::mutex> lk(c->split_mu);
+    while ((int)c->split_streams.size() < n) {
+        hipStream_t s;
+        hipEvent_t e;
+        BC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        c->split_streams.push_back(s);
+        BC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->split_done.push_back(e);
+    }
+    if (!c->split_fork) BC_HIP(hipEventCreateWithFlags(&c->split_fork, hipEventDisableTiming));
+    if (!c->runner) c->runner.reset(new PersistRunner());
+    c->runner->check_stall();
+    for (int i = 0; i < n; i++) {  // earlier work with the slices' blocks comes first
+        BC_HIP(hipEventRecord(c->split_done[i], c->split_streams[i]));
+        BC_HIP(hipStreamWaitEvent(origin, c->split_done[i], 0));
+    }
+    auto cut = [&](const bc_ctb *x, int lo, int cnt) {
+        bc_ctb s = *x;
+        s.data = x->data + (size_t)lo * bc_ct_words(c, x->level, x->ncomp);
+        s.count = cnt;
+        return s;
+    };
+    Recorder rec;
+    {
+        RecordScope rs(&rec);
+        for (int i = 0; i < n; i++) {
+            const int lo = (int)((int64_t)G * i / n), hi = (int)((int64_t)G * (i + 1) / n);
+            std::vector<CtB> a(ndig), b(ndig);
+            std::vector<bc_ctb> mx, mn;
+            for (int d = 0; d < ndig; d++) {
+                a[d] = A[d].slice(lo, hi - lo, c->N);
+                b[d] = B[d].slice(lo, hi - lo, c->N);
+                if (max_out) mx.push_back(cut(&max_out[d], lo, hi - lo));
+                if (min_out) mn.push_back(cut(&min_out[d], lo, hi - lo));
+            }
+            bc_ctb lt;
+            if (lt_out) lt = cut(lt_out, lo, hi - lo);
+            rec.lane = i;
+            StreamScope sc(c->split_streams[i]);
+            run_compare(c, k, ndig, a.data(), b.data(), lt_out ? &lt : nullptr, max_out ? mx.data() : nullptr,
+                        min_out ? mn.data() : nullptr, c->split_streams[i]);
+        }
+    }
+    c->runner->run(c, rec, origin);
+    BC_HIP(hipEventRecord(c->split_fork, origin));
+    for (int i = 0; i < n; i++) BC_HIP(hipStreamWaitEvent(c->split_streams[i], c->split_fork, 0));
 }
 
 // run_compare with the groups split over ctx->split library streams (when
@@ -75,6 +152,10 @@ void run_compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB 
 void run_compare_split(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, const bc_ctb *lt_out,
                        const bc_ctb *max_out, const bc_ctb *min_out, hipStream_t origin) {
     const int G = A[0].count, n = std::min(c->split, G);
+    if (c->persistent && c->exec_mode != BC_EXEC_PER_OP) {
+        run_compare_persistent(c, k, ndig, A, B, lt_out, max_out, min_out, origin, std::max(1, n));
+        return;
+    }
     if (n <= 1) {
         run_compare(c, k, ndig, A, B, lt_out, max_out, min_out, origin);
         return;
@@ -145,7 +226,8 @@ std::string graph_key(int ndig, const bc_ctb *a, const bc_ctb *b, const bc_ctb *
 // when the circuit does not fit the chain).
 CircuitNoise check_compare(bc_ctx *ctx, const bc_keys *keys, int ndigits, const bc_ctb *a_digits,
                            const bc_ctb *b_digits, const bc_ctb *lt_out, const bc_ctb *max_out,
-                           const bc_ctb *min_out, std::vector<CtB> &A, std::vector<CtB> &B) {
+                           const bc_ctb *min_out, std::vector<CtB> &A, std::vector<CtB> &B,
+                           int circuit = BC_CIRCUIT_UNIVARIATE) {
     check_ctx(ctx);
     check_keys(ctx, keys);
     BC_REQUIRE(a_digits && b_digits && ndigits >= 1 && ndigits <= 16, BC_ERR_ARG, "bad digit planes");
@@ -166,7 +248,7 @@ CircuitNoise check_compare(bc_ctx *ctx, const bc_keys *keys, int ndigits, const 
         BC_REQUIRE(A[d].ncomp == 2 && B[d].ncomp == 2, BC_ERR_ARG, "planes must have 2 components");
     }
     CircuitNoise cn{};
-    compare_levels(ctx->noise, A[0].level, in_noise, ndigits, max_out || min_out, &cn);
+    compare_levels(ctx->noise, A[0].level, in_noise, ndigits, max_out || min_out, &cn, circuit);
     auto want = [&](const bc_ctb *x, int lv) {
         CtB o = from_abi(ctx, x);
         BC_REQUIRE(o.count == A[0].count && o.level == lv && o.ncomp == 2, BC_ERR_ARG,
@@ -199,7 +281,11 @@ struct bc_group {
     hipStream_t cap = nullptr;          // recording stream
     bc::GraphCache graphs;
     std::mutex mu;
+    int mode = BC_GROUP_FORK_JOIN;
+    std::unique_ptr<bc::PersistRunner> runner;  // persistent mode's upload and launch state
+    hipEvent_t joined = nullptr;
     ~bc_group() {
+        if (joined) (void)hipEventDestroy(joined);
         for (auto s : streams) (void)hipStreamDestroy(s);
         for (auto e : done) (void)hipEventDestroy(e);
         if (fork) (void)hipEventDestroy(fork);
@@ -226,14 +312,44 @@ int bc_group_create(int32_t n, bc_ctx *const *ctxs, bc_group **out) {
         }
         BC_HIP(hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
         BC_HIP(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+        BC_HIP(hipEventCreateWithFlags(&g->joined, hipEventDisableTiming));
+        g->runner.reset(new PersistRunner());
+        g->mode = BC_GROUP_FORK_JOIN;
+        for (bc_ctx *c : g->ctxs) c->refs.fetch_add(1);  // released by bc_group_destroy
         *out = g.release();
     });
 }
 
 int bc_group_destroy(bc_group *g) {
     return guard([&] {
-        if (g) (void)hipDeviceSynchronize();
+        if (!g) return;
+        (void)hipDeviceSynchronize();
+        const std::vector<bc_ctx *> members = g->ctxs;
         delete g;
+        for (bc_ctx *c : members) ctx_release(c);
+    });
+}
+
+int bc_group_set_mode(bc_group *g, int32_t mode) {
+    return guard([&] {
+        BC_REQUIRE(g, BC_ERR_ARG, "null group");
+        BC_REQUIRE(mode == BC_GROUP_FORK_JOIN || mode == BC_GROUP_PERSISTENT, BC_ERR_ARG, "unknown group mode");
+        if (mode == BC_GROUP_PERSISTENT)
+            for (bc_ctx *c : g->ctxs)
+                BC_REQUIRE(persist_supported(c), BC_ERR_ARG,
+                           "persistent mode needs N = 2^13..2^15, primes below 2^50 and the default transform schedule");
+        std::lock_guard<std::mutex> lk(g->mu);
+        g->mode = mode;
+    });
+}
+
+int bc_group_get_mode(const bc_group *g, int32_t *mode, int32_t *stages, int32_t *tickets, int32_t *workgroups) {
+    return guard([&] {
+        BC_REQUIRE(g, BC_ERR_ARG, "null group");
+        if (mode) *mode = g->mode;
+        if (stages) *stages = g->runner->last.stages;
+        if (tickets) *tickets = g->runner->last.tickets;
+        if (workgroups) *workgroups = g->runner->last.grid;
     });
 }
 
@@ -258,9 +374,79 @@ int bc_group_compare(bc_group *g, const bc_keys *const *keys, const int32_t *ndi
                               min_out ? min_out[i] : nullptr);
         hipStream_t st = (hipStream_t)stream;
         std::lock_guard<std::mutex> lk(g->mu);
+        g->runner->check_stall();
+        const bool persist = g->mode == BC_GROUP_PERSISTENT;
+        if (persist) key << "persistent";
         auto it = g->graphs.entries.find(key.str());
         if (it != g->graphs.entries.end()) {
             BC_HIP(hipGraphLaunch(it->second.exec, st));
+            return;
+        }
+        // persistent mode: every member's launches recorded as one lane each
+        auto record_all = [&](Recorder &rec) {
+            RecordScope rs(&rec);
+            for (int i = 0; i < n; i++) {
+                rec.lane = i;
+                StreamScope sc(g->streams[i]);  // workspace blocks tagged with the member's stream
+                run_compare(g->ctxs[i], keys[i], ndigits[i], A[i].data(), B[i].data(), lt_out ? lt_out[i] : nullptr,
+                            max_out ? max_out[i] : nullptr, min_out ? min_out[i] : nullptr, g->streams[i]);
+            }
+        };
+        if (persist) {
+            // eager: the launch on `st` after the members' earlier work; the
+            // members' streams wait for it (their workspace blocks were used)
+            for (int i = 0; i < n; i++) {
+                BC_HIP(hipEventRecord(g->done[i], g->streams[i]));
+                BC_HIP(hipStreamWaitEvent(st, g->done[i], 0));
+            }
+            Recorder rec;
+            record_all(rec);
+            g->runner->run(g->ctxs[0], rec, st);
+            BC_HIP(hipEventRecord(g->joined, st));
+            for (int i = 0; i < n; i++) BC_HIP(hipStreamWaitEvent(g->streams[i], g->joined, 0));
+            BC_HIP(hipStreamSynchronize(st));
+            // recorded: the blocks the graph keeps, the table uploaded before
+            // capture, the reset and the persistent launch captured
+            for (auto *c : g->ctxs) {
+                std::lock_guard<std::mutex> pg(c->pool.mu);
+                c->pool.recording = true;
+                c->pool.recorded.clear();
+            }
+            GraphEntry e;
+            try {
+                Recorder rec2;
+                record_all(rec2);
+                const PersistPlan plan2 = persist_plan(rec2);
+                void *tab = nullptr;
+                BC_HIP(hipMalloc(&tab, plan2.image.size()));
+                e.blocks.push_back(tab);
+                BC_HIP(hipMemcpy(tab, plan2.image.data(), plan2.image.size(), hipMemcpyHostToDevice));
+                BC_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeRelaxed));
+                try {
+                    persist_run(plan2, tab, g->runner->stall, g->cap);
+                } catch (...) {
+                    hipGraph_t dead = nullptr;
+                    (void)hipStreamEndCapture(g->cap, &dead);
+                    if (dead) (void)hipGraphDestroy(dead);
+                    throw;
+                }
+                BC_HIP(hipStreamEndCapture(g->cap, &e.graph));
+                BC_HIP(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+            } catch (...) {
+                for (auto *c : g->ctxs) {
+                    auto b = c->pool.detach_recorded();
+                    e.blocks.insert(e.blocks.end(), b.begin(), b.end());
+                }
+                for (void *p : e.blocks) (void)hipFree(p);
+                if (e.exec) (void)hipGraphExecDestroy(e.exec);
+                if (e.graph) (void)hipGraphDestroy(e.graph);
+                throw;
+            }
+            for (auto *c : g->ctxs) {
+                auto b = c->pool.detach_recorded();
+                e.blocks.insert(e.blocks.end(), b.begin(), b.end());
+            }
+            g->graphs.entries.emplace(key.str(), std::move(e));
             return;
         }
         // fork/join over the member streams; `origin` is the stream the
@@ -352,18 +538,27 @@ int bc_noise_estimate(const bc_params *prm, int32_t op, int32_t level, double a_
     });
 }
 
-int bc_noise_compare(const bc_params *prm, int32_t in_level, double in_bits, int32_t ndigits, double *lt_bits,
-                     double *maxmin_bits) {
+int bc_noise_compare_circuit(const bc_params *prm, int32_t circuit, int32_t in_level, double in_bits,
+                             int32_t ndigits, double *lt_bits, double *maxmin_bits, int32_t *lt_level,
+                             int32_t *maxmin_level) {
     return guard([&] {
         BC_REQUIRE(prm, BC_ERR_ARG, "null argument");
         BC_REQUIRE(in_level >= 0 && in_level < prm->nQ && ndigits >= 1 && ndigits <= 16, BC_ERR_ARG,
                    "bad level or digit count");
         const NoiseModel m(*prm, param_moduli(*prm));
         CircuitNoise cn{};
-        compare_levels(m, in_level, m.input((float)in_bits), ndigits, maxmin_bits != nullptr, &cn);
+        compare_levels(m, in_level, m.input((float)in_bits), ndigits, maxmin_bits != nullptr, &cn, circuit);
         if (lt_bits) *lt_bits = cn.lt_noise;
         if (maxmin_bits) *maxmin_bits = cn.mm_noise;
+        if (lt_level) *lt_level = cn.lt_level;
+        if (maxmin_level) *maxmin_level = cn.mm_level;
     });
+}
+
+int bc_noise_compare(const bc_params *prm, int32_t in_level, double in_bits, int32_t ndigits, double *lt_bits,
+                     double *maxmin_bits) {
+    return bc_noise_compare_circuit(prm, BC_CIRCUIT_UNIVARIATE, in_level, in_bits, ndigits, lt_bits, maxmin_bits,
+                                    nullptr, nullptr);
 }
 
 int bc_ctx_create(const bc_params *prm, bc_ctx **out) {
@@ -377,10 +572,7 @@ int bc_ctx_create(const bc_params *prm, bc_ctx **out) {
 }
 
 int bc_ctx_destroy(bc_ctx *ctx) {
-    return guard([&] {
-        if (ctx) (void)hipDeviceSynchronize();
-        delete ctx;
-    });
+    return guard([&] { ctx_release(ctx); });
 }
 
 int bc_ctx_moduli(const bc_ctx *ctx, uint64_t *moduli, int32_t cap) {
@@ -423,6 +615,7 @@ int bc_keygen(bc_ctx *ctx, const int8_t *s, const uint64_t *a_words, const int32
         BC_REQUIRE(out, BC_ERR_ARG, "null output");
         StreamScope sc(nullptr);
         *out = keygen(ctx, s, a_words, errors, rot_steps, nrot);
+        ctx->refs.fetch_add(1);
     });
 }
 
@@ -450,6 +643,7 @@ int bc_keys_destroy(bc_keys *keys) {
             }
         }
         delete keys;
+        ctx_release(c);
     });
 }
 
@@ -469,6 +663,7 @@ int bc_keys_import(bc_ctx *ctx, const void *buf, size_t size, bc_keys **out) {
         BC_REQUIRE(out, BC_ERR_ARG, "null output");
         StreamScope sc(nullptr);
         *out = keys_import(ctx, buf, size);
+        ctx->refs.fetch_add(1);
     });
 }
 
@@ -554,8 +749,9 @@ int bc_mod_switch(bc_ctx *ctx, const bc_ctb *in, bc_ctb *out, void *stream) {
     return guard([&] {
         check_ctx(ctx);
         StreamScope sc(stream);
-        const CtB x = from_abi(ctx, in), o = from_abi(ctx, out);
+        const CtB x = from_abi(ctx, in);
         BC_REQUIRE(x.level >= 1, BC_ERR_LEVEL, "modulus switch: no prime left to drop at level 0");
+        const CtB o = from_abi(ctx, out);
         const double nb = ctx->noise.mod_switch(x.level, x.noise);
         ctx->noise.require(x.level, x.noise, "modulus switch input");
         mod_switch(ctx, x, o, (hipStream_t)stream);
@@ -639,15 +835,33 @@ int bc_add_const(bc_ctx *ctx, const bc_ctb *a, int32_t c, bc_ctb *out, void *str
     });
 }
 
-int bc_compare_levels(const bc_ctx *ctx, int32_t in_level, int32_t ndigits, int32_t *lt_level, int32_t *maxmin_level) {
+int bc_compare_levels_circuit(const bc_ctx *ctx, int32_t circuit, int32_t in_level, int32_t ndigits,
+                              int32_t *lt_level, int32_t *maxmin_level) {
     return guard([&] {
         check_ctx(ctx);
         BC_REQUIRE(in_level >= 0 && in_level < ctx->nQ && ndigits >= 1 && ndigits <= 16, BC_ERR_ARG,
                    "bad level or digit count");
         CircuitNoise cn{};
-        compare_levels(ctx->noise, in_level, ctx->noise.fresh(), ndigits, false, &cn);
+        compare_levels(ctx->noise, in_level, ctx->noise.fresh(), ndigits, false, &cn, circuit);
         if (lt_level) *lt_level = cn.lt_level;
         if (maxmin_level) *maxmin_level = cn.mm_level;
+    });
+}
+
+int bc_compare_levels(const bc_ctx *ctx, int32_t in_level, int32_t ndigits, int32_t *lt_level, int32_t *maxmin_level) {
+    return bc_compare_levels_circuit(ctx, BC_CIRCUIT_UNIVARIATE, in_level, ndigits, lt_level, maxmin_level);
+}
+
+int bc_compare_bivariate(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits,
+                         const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out, void *stream) {
+    return guard([&] {
+        std::vector<CtB> A, B;
+        const CircuitNoise cn = check_compare(ctx, keys, ndigits, a_digits, b_digits, lt_out, max_out, min_out, A, B,
+                                              BC_CIRCUIT_BIVARIATE);
+        set_compare_noise(cn, ndigits, lt_out, max_out, min_out);
+        StreamScope sc(stream);
+        run_compare(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, (hipStream_t)stream,
+                    BC_CIRCUIT_BIVARIATE);
     });
 }
 
@@ -668,7 +882,7 @@ int bc_compare_max_min(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const 
         set_compare_noise(cn, ndigits, lt_out, max_out, min_out);
         hipStream_t st = (hipStream_t)stream;
         StreamScope sc(stream);
-        if (ctx->exec_mode != BC_EXEC_GRAPH) {
+        if (ctx->exec_mode != BC_EXEC_GRAPH || ctx->persistent) {  // a persistent call is one launch already
             run_compare_split(ctx, keys, ndigits, A.data(), B.data(), lt_out, max_out, min_out, st);
             return;
         }
@@ -731,6 +945,10 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
         } else if (key == BC_TUNE_TEST_FAIL_ALLOC) {
             std::lock_guard<std::mutex> g(ctx->pool.mu);
             ctx->pool.fail_after = value;
+        } else if (key == BC_TUNE_PERSISTENT) {
+            BC_REQUIRE(value == 0 || persist_supported(ctx), BC_ERR_ARG,
+                       "persistent mode needs N = 2^13..2^15, primes below 2^50 and the default transform schedule");
+            ctx->persistent = value != 0;
         } else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }
@@ -746,6 +964,7 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
         else if (key == BC_TUNE_SPLIT_STREAMS) *value = ctx->split;
         else if (key == BC_TUNE_POOL_LIMIT_BYTES) *value = (int64_t)ctx->pool.limit;
         else if (key == BC_TUNE_TEST_FAIL_ALLOC) *value = ctx->pool.fail_after;
+        else if (key == BC_TUNE_PERSISTENT) *value = ctx->persistent;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }

@@ -98,6 +98,20 @@ struct NoiseEval {
         return o;
     }
     V slice(V a, int, int) { return a; }
+    // the batches pw[idx[j]] brought to level lv, as one batch
+    V gather(const std::vector<V> &pw, const std::vector<int> &idx, int lv) {
+        V o{lv, -INFINITY};
+        for (int j : idx) o.nb = std::max(o.nb, pw[j].nb);
+        return o;
+    }
+    // sums of in's blocks with integer weights (see BivNoise)
+    template <class Tab>
+    V lincomb_wide(const V &in, const Tab &t, bool final) {
+        V o{in.lv, m->scalar(in.nb, final ? t.sum_abs : t.g_abs)};
+        if (!final) o.nb = m->add_const(o.nb);
+        m->require(o.lv, o.nb, "comparison circuit");
+        return o;
+    }
 };
 
 struct DevEval {
@@ -158,6 +172,29 @@ struct DevEval {
     }
     int level(const V &a) { return a.level; }
     V slice(const V &a, int first, int n) { return a.slice(first, n, c->N); }
+    V to_level(const V &a, int lv) {
+        V o = alloc_ct(c, a.count, lv, a.ncomp);
+        bc::to_level_into(c, a, o, st);
+        return o;
+    }
+    V gather(const std::vector<V> &pw, const std::vector<int> &idx, int lv) {
+        const int cnt = pw[idx[0]].count;
+        V o = alloc_ct(c, (int)idx.size() * cnt, lv, 2);
+        for (size_t j = 0; j < idx.size(); j++) bc::to_level_into(c, pw[idx[j]], o.slice((int)j * cnt, cnt, c->N), st);
+        return o;
+    }
+    // the g_k(S) of the bivariate circuit from the gathered S powers, or
+    // (final) LT from the gathered T_k and Z^(p-1) (see BivTable)
+    template <class Tab>
+    V lincomb_wide(const V &in, const Tab &t, bool final) {
+        const int M = final ? t.K + 1 : t.M, K = final ? 1 : t.K;
+        const int cnt = in.count / M;
+        V o = alloc_ct(c, K * cnt, in.level, 2);
+        launch_lincomb_wide(c, in.data, o.data, final ? t.Wsum : t.W, final ? t.c0sum : t.c0, M, K, cnt,
+                            in.level + 1, st);
+        BC_HIP(hipGetLastError());
+        return o;
+    }
     // blocks B_t = sum_{k odd < b} c_{tb+k} Z^k for every t at level lv (each
     // baby's lowest lv + 1 limbs: alignment by dropping primes), stored at
     // bit-reversed t
@@ -282,11 +319,171 @@ typename Ev::V lexicographic(Ev &ev, const typename Ev::V &f, const typename Ev:
     return acc;
 }
 
+// ------------------------------------------------------- bivariate circuit
+// (Introduction: the bivariate circuit, exact for every pair of digits; the
+// paper prints no polynomial or schedule)
+
+// c[m p + k]: coefficient of S^m Z^k in the interpolant G(S, Z) of [x < y]
+// over F_p^2 with S = x + y, Z = x - y (p odd).  Interpolation one axis at a
+// time: the interpolant of h over F_p has a_0 = h(0) and, for j >= 1,
+// a_j = -sum_{t != 0} h(t) t^-j - [j = p - 1] h(0) (from the indicator
+// 1 - (x - t)^(p-1) of each point).
+std::vector<int64_t> bivariate_coefficients(u64 p) {
+    const size_t P = (size_t)p;
+    std::vector<u64> tinv(P * P);  // tinv[t p + j] = t^-j
+    for (u64 t = 1; t < p; t++) {
+        const u64 ti = h_invmod(t, p);
+        u64 v = 1;
+        for (u64 j = 0; j < p; j++) {
+            tinv[t * P + j] = v;
+            v = v * ti % p;
+        }
+    }
+    auto interp = [&](const std::vector<u64> &h, std::vector<u64> &a) {
+        a.assign(P, 0);
+        a[0] = h[0];
+        for (u64 j = 1; j < p; j++) {
+            u64 acc = 0;
+            for (u64 t = 1; t < p; t++) acc = (acc + h[t] * tinv[t * P + j]) % p;
+            if (j == p - 1) acc = (acc + h[0]) % p;
+            a[j] = (p - acc) % p;
+        }
+    };
+    const u64 inv2 = (p + 1) / 2;
+    std::vector<u64> A1(P * P), h(P), a;
+    for (u64 sv = 0; sv < p; sv++) {  // along z for each s
+        for (u64 zv = 0; zv < p; zv++) {
+            const u64 x = (sv + zv) % p * inv2 % p, y = (sv + p - zv) % p * inv2 % p;
+            h[zv] = x < y ? 1 : 0;
+        }
+        interp(h, a);
+        for (u64 k = 0; k < p; k++) A1[sv * P + k] = a[k];
+    }
+    std::vector<int64_t> c(P * P);
+    for (u64 k = 0; k < p; k++) {  // then along s for each power of z
+        for (u64 sv = 0; sv < p; sv++) h[sv] = A1[sv * P + k];
+        interp(h, a);
+        for (u64 m = 0; m < p; m++) c[m * P + k] = (int64_t)a[m];
+    }
+    return c;
+}
+
+// Weights of the bivariate circuit as the wide-combination kernel takes them
+// (centred doubles): rows k' < K = (p-1)/2 of g_{2k'+1}(S) = sum_{m=1}^{p-1}
+// c[m][2k'+1] S^m (+ c[0][2k'+1]), then one row for the final sum
+// LT = sum_k T_k + (p+1)/2 Z^(p-1) (weights 1 ... 1, (p+1)/2; no constant).
+struct BivTable {
+    int K, M;
+    const double *W, *c0, *Wsum, *c0sum;
+};
+// What the noise estimate needs of the same weights: the largest total
+// weight magnitude of one g_k (a bound, (p-1)/2 per weight) and of the sum.
+struct BivNoise {
+    int K, M;
+    double g_abs, sum_abs;
+};
+BivNoise bivariate_noise(u64 p) {
+    const int K = (int)(p - 1) / 2, M = (int)p - 1;
+    return BivNoise{K, M, (double)M * (double)(p - 1) / 2 + 1, (double)K + (double)(p - 1) / 2};
+}
+
+BivTable bivariate_table(bc_ctx *c) {
+    std::lock_guard<std::mutex> g(c->table_mu);
+    const u64 p = c->p;
+    const int K = (int)(p - 1) / 2, M = (int)p - 1;
+    const int KP = (K + lincomb_wide_tile(K) - 1) / lincomb_wide_tile(K) * lincomb_wide_tile(K);
+    const size_t nW = (size_t)KP * M, nS = (size_t)K + 1;
+    if (!c->biv_tab) {
+        BC_REQUIRE(p >= 3 && p < 512 && ((p - 1) & (p - 2)) == 0, BC_ERR_PARAM,
+                   "the bivariate circuit needs p - 1 a power of two and p < 512");
+        const std::vector<int64_t> cf = bivariate_coefficients(p);
+        const size_t P = (size_t)p;
+        // the schedule relies on the part even in Z being (p+1)/2 Z^(p-1)
+        for (size_t k = 0; k < P; k += 2)
+            for (size_t m = 0; m < P; m++)
+                BC_REQUIRE(cf[m * P + k] == ((m == 0 && k == P - 1) ? (int64_t)(p + 1) / 2 : 0), BC_ERR_PARAM,
+                           "bivariate interpolant: unexpected even part");
+        auto cen = [&](int64_t v) { return (double)(v > (int64_t)(p - 1) / 2 ? v - (int64_t)p : v); };
+        std::vector<double> host(nW + KP + nS + 1, 0.0);
+        for (int kk = 0; kk < K; kk++)
+            for (int mm = 0; mm < M; mm++) host[(size_t)kk * M + mm] = cen(cf[(size_t)(mm + 1) * P + 2 * kk + 1]);
+        for (int kk = 0; kk < K; kk++) host[nW + kk] = cen(cf[2 * kk + 1]);
+        for (int kk = 0; kk < K; kk++) host[nW + KP + kk] = 1.0;
+        host[nW + KP + K] = cen((int64_t)(p + 1) / 2);
+        double *d = nullptr;
+        BC_HIP(hipMalloc(&d, sizeof(double) * host.size()));
+        BC_HIP(hipMemcpy(d, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice));
+        c->biv_tab = d;
+        c->biv_K = K;
+        c->biv_M = M;
+    }
+    const double *d = c->biv_tab;
+    return BivTable{K, M, d, d + nW, d + nW + KP, d + nW + KP + nS};
+}
+
+// The bivariate interpolant of [x < y] on Z = X - Y, S = X + Y (batches of
+// `count` ciphertexts), p - 1 = 2^e:
+//   LT = (p+1)/2 Z^(p-1) + sum_{k odd} Z^k g_k(S)
+// (the part even in Z of the interpolant is (p+1)/2 Z^(p-1), since
+// LT(x, y) + LT(y, x) = (x - y)^(p-1)).  Power ladders: X^(2^a) by squaring,
+// X^(2^a + r) = X^(2^a) X^r for r < 2^a (every r for S, odd r for Z), each
+// block of a ladder one batched product against the broadcast X^(2^a); the
+// S powers gathered at the level of S^(p-1) and combined into all g_k by one
+// wide linear combination; the odd Z powers gathered at the same level; one
+// batched product T_k = Z^k g_k; LT by one more wide combination of the T_k
+// and (p+1)/2 Z^(p-1).  Returns (LT, Z^(p-1)).
+template <class Ev, class Tab>
+std::pair<typename Ev::V, typename Ev::V> lt_bivariate(Ev &ev, const typename Ev::V &Z, const typename Ev::V &S,
+                                                       int count, int P1, const Tab &tab) {
+    typedef typename Ev::V V;
+    auto ladder = [&](const V &B, bool odd_only) {
+        std::vector<V> pw(P1 + 1);
+        pw[1] = B;
+        for (int a = 1; a < P1; a *= 2) pw[2 * a] = ev.mul(pw[a], pw[a]);
+        for (int a = 2; a < P1; a *= 2) {
+            std::vector<int> rs;
+            for (int r = 1; r < a; r++)
+                if (!odd_only || (r & 1)) rs.push_back(r);
+            const V prod = ev.mul(ev.gather(pw, rs, ev.level(pw[a])), pw[a]);
+            for (size_t j = 0; j < rs.size(); j++) pw[a + rs[j]] = ev.slice(prod, (int)j * count, count);
+        }
+        return pw;
+    };
+    V G;
+    int lv;
+    {
+        std::vector<V> sp = ladder(S, false);
+        lv = ev.level(sp[P1]);
+        std::vector<int> ms;
+        for (int m = 1; m <= P1; m++) ms.push_back(m);
+        const V SC = ev.gather(sp, ms, lv);
+        sp.clear();  // only the gathered copies are read from here on
+        G = ev.lincomb_wide(SC, tab, false);
+    }
+    std::vector<V> zp = ladder(Z, true);
+    std::vector<int> ks;
+    for (int k = 1; k < P1; k += 2) ks.push_back(k);
+    const V T = ev.mul(ev.gather(zp, ks, lv), G);
+    G = V();
+    const V top = zp[P1];
+    zp.clear();
+    // the T_k and Z^(p-1) as one batch of K + 1 blocks at T's level
+    std::vector<V> parts;
+    for (size_t k = 0; k < ks.size(); k++) parts.push_back(ev.slice(T, (int)k * count, count));
+    parts.push_back(top);
+    std::vector<int> all;
+    for (size_t k = 0; k < parts.size(); k++) all.push_back((int)k);
+    const V LT = ev.lincomb_wide(ev.gather(parts, all, ev.level(T)), tab, true);
+    return {LT, top};
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- entry points
 
-CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, bool want_mm, hipStream_t st) {
+CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, bool want_mm, hipStream_t st,
+                      int circuit) {
+    BC_REQUIRE(circuit == BC_CIRCUIT_UNIVARIATE || circuit == BC_CIRCUIT_BIVARIATE, BC_ERR_ARG, "unknown circuit");
     BC_REQUIRE(ndig >= 1 && ndig <= 16, BC_ERR_ARG, "ndigits must be in [1, 16]");
     const int G = A[0].count, L0 = A[0].level;
     for (int d = 0; d < ndig; d++) {
@@ -294,20 +491,29 @@ CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const
         BC_REQUIRE(A[d].level == L0 && B[d].level == L0, BC_ERR_ARG, "every plane needs the same level");
         BC_REQUIRE(A[d].ncomp == 2 && B[d].ncomp == 2, BC_ERR_ARG, "planes must have 2 components");
     }
-    Shape sh = ps_shape(c->p);
-    if (c->lt_c.empty()) {
-        std::lock_guard<std::mutex> g(c->table_mu);
-        if (c->lt_c.empty()) c->lt_c = lt_coefficients(c->p);
-    }
     DevEval ev{c, k, st, c->exec_mode == BC_EXEC_PER_OP};
     const int N = c->N;
     // the planes of every group as one batch, plane-major, read straight from
-    // the caller's planes: Z = A - B at the input level
+    // the caller's planes: Z = A - B (and S = A + B) at the input level
     CtB Z = alloc_ct(c, ndig * G, L0, 2);
     for (int d = 0; d < ndig; d++)
         ev.each(Z.slice(d * G, G, N), A[d], &B[d],
                 [&](const CtB &oo, const CtB &x, const CtB &y) { bc::add_sub(c, x, y, oo, true, st); });
-    auto fz = lt_poly(ev, Z, sh, ndig * G, c->lt_c[c->p - 1]);
+    std::pair<CtB, CtB> fz;
+    if (circuit == BC_CIRCUIT_BIVARIATE) {
+        const BivTable tab = bivariate_table(c);
+        BC_REQUIRE(use_fp64(c), BC_ERR_PARAM, "the bivariate circuit needs primes below 2^50");
+        CtB S = alloc_ct(c, ndig * G, L0, 2);
+        for (int d = 0; d < ndig; d++) bc::add_sub(c, A[d], B[d], S.slice(d * G, G, N), false, st);
+        fz = lt_bivariate(ev, Z, S, ndig * G, (int)c->p - 1, tab);
+    } else {
+        Shape sh = ps_shape(c->p);
+        if (c->lt_c.empty()) {
+            std::lock_guard<std::mutex> g(c->table_mu);
+            if (c->lt_c.empty()) c->lt_c = lt_coefficients(c->p);
+        }
+        fz = lt_poly(ev, Z, sh, ndig * G, c->lt_c[c->p - 1]);
+    }
     Z = CtB();
     CompareResult r;
     r.lt = lexicographic(ev, fz.first, fz.second, ndig, G);
@@ -327,12 +533,21 @@ CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const
     return r;
 }
 
-void compare_levels(const NoiseModel &m, int in_level, double in_noise, int ndig, bool want_mm, CircuitNoise *out) {
-    Shape sh = ps_shape((u64)m.p);
+void compare_levels(const NoiseModel &m, int in_level, double in_noise, int ndig, bool want_mm, CircuitNoise *out,
+                    int circuit) {
+    BC_REQUIRE(circuit == BC_CIRCUIT_UNIVARIATE || circuit == BC_CIRCUIT_BIVARIATE, BC_ERR_ARG, "unknown circuit");
     NoiseEval ev{&m};
     NoiseEval::V in{in_level, in_noise};
     m.require(in_level, in_noise, "comparison input");
-    auto fz = lt_poly(ev, ev.sub(in, in), sh, 1, (int64_t)(m.p - 1) / 2);
+    std::pair<NoiseEval::V, NoiseEval::V> fz;
+    if (circuit == BC_CIRCUIT_BIVARIATE) {
+        const u64 p = (u64)m.p;
+        BC_REQUIRE(p >= 3 && p < 512 && ((p - 1) & (p - 2)) == 0, BC_ERR_PARAM,
+                   "the bivariate circuit needs p - 1 a power of two and p < 512");
+        fz = lt_bivariate(ev, ev.sub(in, in), ev.add(in, in), 1, (int)p - 1, bivariate_noise(p));
+    } else {
+        fz = lt_poly(ev, ev.sub(in, in), ps_shape((u64)m.p), 1, (int64_t)(m.p - 1) / 2);
+    }
     NoiseEval::V lt = lexicographic(ev, fz.first, fz.second, ndig, 1);
     out->lt_level = lt.lv;
     out->lt_noise = lt.nb;

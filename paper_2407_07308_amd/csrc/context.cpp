@@ -8,6 +8,7 @@
 #include <cstring>
 
 #include "bc_internal.h"
+#include "persist.h"
 
 namespace bc {
 
@@ -518,6 +519,7 @@ void dfree(T *p) {
 }  // namespace
 
 bc_ctx::~bc_ctx() {
+    if (biv_tab) (void)hipFree(biv_tab);
     graphs.reset();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     for (auto s : split_streams) (void)hipStreamDestroy(s);

@@ -23,7 +23,10 @@ void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, i
 void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, hipStream_t st);
 void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_stride, const u64 *key, u64 *acc,
                      int count, int level, int next, int nact, hipStream_t st);
-void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, hipStream_t st);
+// pl > 0: the special limbs come from part-limb inverse transforms (their
+// last pl stages are applied here) and TH goes to part-limb forward ones
+// (their first pl stages are applied here)
+void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, int pl, hipStream_t st);
 void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size_t base_ct_stride, const u64 *acc,
                        const u64 *th, u64 *out, size_t out_ct_stride, int count, int level, int next, hipStream_t st);
 void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, int pl, hipStream_t st);
@@ -44,6 +47,13 @@ void launch_enc_combine(const bc_ctx *c, const u64 *pk, const u64 *U, const u64 
 void launch_dec_inner(const bc_ctx *c, const u64 *ct, const u64 *s, u64 *d, int count, int nl, int ncomp, hipStream_t st);
 void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *nlb, const int *pos, const u64 *coef,
                     u64 *out, int nbaby, int nblk, int count, int ct0, int nlaunch, int nl, hipStream_t st);
+// out[k] = sum_m W[k][m] in[m] (+ c0[k] on component 0), k < K: in is M
+// compact blocks of `count` ciphertexts at nl limbs, out K blocks; W is
+// [KT tile][M] doubles (KT = ceil(K / tile), rows past K zero), |W| <= 2^8,
+// M <= 4096; c0 [KT tile] doubles.  fp64 contexts only.
+int lincomb_wide_tile(int K);
+void launch_lincomb_wide(const bc_ctx *c, const u64 *in, u64 *out, const double *W, const double *c0, int M, int K,
+                         int count, int nl, hipStream_t st);
 void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st);
 
 }  // namespace bc

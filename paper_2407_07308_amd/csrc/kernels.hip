@@ -12,463 +12,78 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "kernels_dev.h"
+#include "persist.h"
 
 namespace bc {
 
 namespace {
 
-constexpr int kT = 256;
-
-__device__ __forceinline__ int ext_prime(int e, int level, int nQ) { return e <= level ? e : nQ + (e - level - 1); }
 
 // ------------------------------------------------------------ ring ops
 
-// (a0 b0, a0 b1 + a1 b0, a1 b1), plus (c0, c1) on the first two components
-// when an addend c is given (a multiply-accumulate's sum before relinearising).
-// The output has nl limbs; each operand is read at its own limb count (na,
-// nb, nc >= nl): an operand above the output's level contributes its lowest
-// nl limbs (level alignment by dropping primes, without a copy).  When b is
-// broadcast (bcount < count, ciphertext ct uses b[ct % bcount]) the grid runs
-// the count / bcount products that share a b ciphertext back to back, so
-// its limbs come from the cache after the first.
 template <bool ADD>
 __global__ void k_tensor(const u64 *__restrict__ a, const u64 *__restrict__ b, const u64 *__restrict__ c,
                          u64 *__restrict__ out, int bcount, int nl, int na, int nb, int nc,
                          const PrimeInfo *__restrict__ pinfo, int N) {
-    const int rep = gridDim.z / bcount;  // products per b ciphertext
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
-    const int ct = (int)(blockIdx.z % rep) * bcount + (int)(blockIdx.z / rep);
-    const size_t L = (size_t)nl * N, La = (size_t)na * N, Lb = (size_t)nb * N;
-    const u64 *A = a + (size_t)ct * 2 * La + (size_t)i * N + n;
-    const u64 *B = b + (size_t)(ct % bcount) * 2 * Lb + (size_t)i * N + n;
-    u64 *O = out + (size_t)ct * 3 * L + (size_t)i * N + n;
-    const Barrett br = pinfo[i].br;
-    u64 a0 = A[0], a1 = A[La], b0 = B[0], b1 = B[Lb];
-    u64 d0 = mul_mod(a0, b0, br), d1 = add_mod(mul_mod(a0, b1, br), mul_mod(a1, b0, br), br.q);
-    if constexpr (ADD) {
-        const size_t Lc = (size_t)nc * N;
-        const u64 *C = c + (size_t)ct * 2 * Lc + (size_t)i * N + n;
-        d0 = add_mod(d0, C[0], br.q);
-        d1 = add_mod(d1, C[Lc], br.q);
-    }
-    O[0] = d0;
-    O[L] = d1;
-    O[2 * L] = mul_mod(a1, b1, br);
+    b_tensor<ADD>(hw_blk(), a, b, c, out, bcount, nl, na, nb, nc, pinfo, N);
 }
 
-// out = a + sgn * b on ncomp components (sgn = +1 / -1); out has nl limbs,
-// a and b are read at their own limb counts (na, nb >= nl)
 __global__ void k_addsub(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 *__restrict__ out, int bcount,
                          int nl, int na, int nb, int ncomp, int sub, const PrimeInfo *__restrict__ pinfo, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    const size_t L = (size_t)nl * N, La = (size_t)na * N, Lb = (size_t)nb * N;
-    const u64 q = pinfo[i].q;
-    for (int c = 0; c < ncomp; c++) {
-        const size_t off = (size_t)i * N + n;
-        u64 x = a[(size_t)ct * ncomp * La + c * La + off], y = b[(size_t)(ct % bcount) * ncomp * Lb + c * Lb + off];
-        out[(size_t)ct * ncomp * L + c * L + off] = sub ? sub_mod(x, y, q) : add_mod(x, y, q);
-    }
+    b_addsub(hw_blk(), a, b, out, bcount, nl, na, nb, ncomp, sub, pinfo, N);
 }
 
-struct ScalarArg {
-    u64 w[kMaxMod][2];
-};
 
 __global__ void k_mul_scalar(const u64 *__restrict__ a, u64 *__restrict__ out, int nl, int ncomp, ScalarArg s,
                              const PrimeInfo *__restrict__ pinfo, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    const size_t L = (size_t)nl * N;
-    const u64 q = pinfo[i].q;
-    for (int c = 0; c < ncomp; c++) {
-        size_t off = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N + n;
-        out[off] = shoup(a[off], s.w[i][0], s.w[i][1], q);
-    }
+    b_mul_scalar(hw_blk(), a, out, nl, ncomp, s, pinfo, N);
 }
 
-// constant polynomial c: every evaluation of component 0 gains c mod q_i
 __global__ void k_add_const(const u64 *__restrict__ a, u64 *__restrict__ out, int nl, int ncomp, ScalarArg s,
                             const PrimeInfo *__restrict__ pinfo, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    const size_t L = (size_t)nl * N;
-    const u64 q = pinfo[i].q;
-    for (int c = 0; c < ncomp; c++) {
-        size_t off = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N + n;
-        u64 x = a[off];
-        out[off] = c == 0 ? add_mod(x, s.w[i][0], q) : x;
-    }
+    b_add_const(hw_blk(), a, out, nl, ncomp, s, pinfo, N);
 }
 
-// out[ct][c][i][r] = in[ct][c][i][perm[r]]
 __global__ void k_permute(const u64 *__restrict__ in, u64 *__restrict__ out, const u32 *__restrict__ perm, int nl,
                           int ncomp, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    const size_t L = (size_t)nl * N;
-    const u32 src = perm[n];
-    for (int c = 0; c < ncomp; c++) {
-        size_t base = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N;
-        out[base + n] = in[base + src];
-    }
+    b_permute(hw_blk(), in, out, perm, nl, ncomp, N);
 }
 
 // ------------------------------------------------------- key switching
 
-// Fast base conversion of digit j (z-grid = ct * dnum + j):
-// y_i = [x_i Qhat_i^-1]_{q_i}, u_t = sum_i y_i Qhat_i mod q_t.
-// With PL > 0 a thread takes the 2^PL words n + v N/2^PL of each limb: it
-// applies the last PL stages of the part-limb inverse transform that made xc
-// to its inputs (unfold_int / unfold_fp) and the first PL forward stages of
-// the new limbs' transforms to its outputs (fold_int / fold_fp).  MD bounds
-// the digit size at compile time.
 template <bool FP, int PL = 0, int MD = kMaxDigit>
 __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const ModUpPlan *__restrict__ plans,
                         const PrimeInfo *__restrict__ pinfo, int nl, int next, int dnum, int N) {
-    constexpr int NV = 1 << PL;
-    const int n = blockIdx.x * kT + threadIdx.x, Q = N >> PL;
-    const int ct = blockIdx.z / dnum, j = blockIdx.z - ct * dnum;
-    const ModUpPlan &pl = plans[j];
-    if (pl.nsrc == 0) return;
-    u64 *out = mu + ((size_t)ct * dnum + j) * next * N + n;
-    const u64 *in = xc + (size_t)ct * nl * N + n;
-    if constexpr (!FP) {
-        // fully unrolled over the compile-time bound so y[] stays in registers
-        u64 y[NV][MD];
-#pragma unroll
-        for (int s = 0; s < MD; s++) {
-            if (s >= pl.nsrc) break;
-            const int i = pl.src_lo + s;
-            u64 x[NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) x[v] = in[(size_t)i * N + v * Q];
-            if constexpr (PL > 0) unfold_int<PL>(x, pinfo[i]);
-#pragma unroll
-            for (int v = 0; v < NV; v++) y[v][s] = shoup(x[v], pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
-        }
-        for (int t = 0; t < pl.ntgt; t++) {
-            const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
-            u64 acc[NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) {
-                acc[v] = 0;
-#pragma unroll
-                for (int s = 0; s < MD; s++) {
-                    if (s >= pl.nsrc) break;
-                    acc[v] = add_mod(acc[v], shoup(y[v][s], pl.qhat[t][s][0], pl.qhat[t][s][1], pt.q), pt.q);
-                }
-            }
-            if constexpr (PL > 0) fold_int<PL>(acc, pt);
-#pragma unroll
-            for (int v = 0; v < NV; v++) out[(size_t)pl.tgt_e[t] * N + v * Q] = acc[v];
-        }
-    } else {
-#pragma clang fp contract(off)
-        // y_s canonical in [0, q_s); each product below 0.75 q_t in magnitude,
-        // so eight of them sum exactly before a reduction
-        double y[NV][MD];
-#pragma unroll
-        for (int s = 0; s < MD; s++) {
-            if (s >= pl.nsrc) break;
-            const PrimeInfo &pi = pinfo[pl.src_lo + s];
-            double x[NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) x[v] = f_load(in[(size_t)(pl.src_lo + s) * N + v * Q]);
-            if constexpr (PL > 0) unfold_fp<PL, false>(x, pi);  // |x| < 1.5 q: fine for the product
-#pragma unroll
-            for (int v = 0; v < NV; v++) y[v][s] = f_canon(f_mulmod(x[v], fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
-        }
-        for (int t = 0; t < pl.ntgt; t++) {
-            const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
-            double acc[NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) {
-                acc[v] = 0.0;
-#pragma unroll
-                for (int s = 0; s < MD; s++) {
-                    if (s >= pl.nsrc) break;
-                    acc[v] += f_mulmod(y[v][s], fpair(pl.qhat[t][s]), pt.qd);
-                    if ((s & 7) == 7) acc[v] = f_reduce(acc[v], pt.qd, pt.qinv);
-                }
-                // the fold takes |x| < 1.6 q and returns canonical words
-                acc[v] = PL > 0 ? f_reduce(acc[v], pt.qd, pt.qinv) : f_canon(acc[v], pt.qd, pt.qinv);
-            }
-            if constexpr (PL > 0) fold_fp<PL>(acc, pt);
-#pragma unroll
-            for (int v = 0; v < NV; v++) out[(size_t)pl.tgt_e[t] * N + v * Q] = f_bits(acc[v]);
-        }
-    }
+    b_modup<FP, PL, MD>(hw_blk(), xc, mu, plans, pinfo, nl, next, dnum, N);
 }
 
-// ACC[ct][c][e] = sum_j MU[ct][j][e] * K_j,c[prime(e)]   (NTT domain), where
-// digit j's own limbs (e in [j alpha, (j+1) alpha)) are X's limbs themselves.
-// A thread takes kKsCts consecutive ciphertexts: each key word is read once
-// for all of them, and every load is issued before the arithmetic.
-constexpr int kKsCts = 8;
-// FP: the products of two variable residues in fp64 (f_mulmod with the
-// quotient factor w/q formed as w * (1/q): two roundings instead of one, so
-// each product lies within 0.875 q of zero for q < 2^50, and eight of them
-// sum exactly before a reduction).  Otherwise Barrett products on u64.
-// Blocks are numbered so that the ciphertext groups vary fastest: the groups
-// that read the same key words run back to back and find them in the cache.
 template <bool FP>
 __global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ x, size_t x_ct_stride,
                            const u64 *__restrict__ key, u64 *__restrict__ acc, int level, int nQ, int nmod, int next,
                            int nact, int dnum, int alpha, int count, const PrimeInfo *__restrict__ pinfo, int N) {
-    const unsigned lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    const unsigned zg = lin % gridDim.z, rest = lin / gridDim.z;
-    const int n = (int)(rest % gridDim.x) * kT + threadIdx.x, e = (int)(rest / gridDim.x), ct0 = (int)zg * kKsCts;
-    const int prime = ext_prime(e, level, nQ);
-    const int own = e <= level ? e / alpha : -1;
-    using S = typename std::conditional<FP, double, u64>::type;
-    S s0[kKsCts], s1[kKsCts];
-#pragma unroll
-    for (int c = 0; c < kKsCts; c++) s0[c] = s1[c] = 0;
-    const Barrett br = pinfo[prime].br;
-    const double q = pinfo[prime].qd, qinv = pinfo[prime].qinv;
-    for (int j = 0; j < nact; j++) {
-        const u64 *K = key + ((size_t)j * 2 * nmod + prime) * N + n;
-        const u64 k0 = K[0], k1 = K[(size_t)nmod * N];
-        u64 u[kKsCts];
-#pragma unroll
-        for (int c = 0; c < kKsCts; c++) {
-            const int ct = min(ct0 + c, count - 1);  // a tail thread repeats the last ciphertext
-            u[c] = j == own ? x[(size_t)ct * x_ct_stride + (size_t)e * N + n]
-                            : mu[(((size_t)ct * dnum + j) * next + e) * N + n];
-        }
-        if constexpr (FP) {
-#pragma clang fp contract(off)
-            const double w0 = f_load(k0), w1 = f_load(k1);
-            const FPair c0{w0, w0 * qinv}, c1{w1, w1 * qinv};
-#pragma unroll
-            for (int c = 0; c < kKsCts; c++) {
-                const double y = f_load(u[c]);
-                s0[c] += f_mulmod(y, c0, q);
-                s1[c] += f_mulmod(y, c1, q);
-                if ((j & 7) == 7) {
-                    s0[c] = f_reduce(s0[c], q, qinv);
-                    s1[c] = f_reduce(s1[c], q, qinv);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < kKsCts; c++) {
-                s0[c] = add_mod(s0[c], mul_mod(u[c], k0, br), br.q);
-                s1[c] = add_mod(s1[c], mul_mod(u[c], k1, br), br.q);
-            }
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < kKsCts; c++) {
-        const int ct = ct0 + c;
-        if (ct < count) {
-            u64 r0, r1;
-            if constexpr (FP) {
-                r0 = f_bits(f_canon(s0[c], q, qinv));
-                r1 = f_bits(f_canon(s1[c], q, qinv));
-            } else {
-                r0 = s0[c];
-                r1 = s1[c];
-            }
-            acc[(((size_t)ct * 2 + 0) * next + e) * N + n] = r0;
-            acc[(((size_t)ct * 2 + 1) * next + e) * N + n] = r1;
-        }
-    }
+    b_ks_inner<FP>(hw_blk(), mu, x, x_ct_stride, key, acc, level, nQ, nmod, next, nact, dnum, alpha, count, pinfo, N);
 }
 
-// Exact division by P, conversion part (z-grid = ct * 2 + c):
-// v_j = [acc_{p_j} p^-1 Phat_j^-1]_{p_j};  TH_i = sum_j v_j Phat_j mod q_i.
+template <bool FP, int PL>
 __global__ void k_moddown(const u64 *__restrict__ acc, u64 *__restrict__ th, const ModDownPlan *__restrict__ pl,
                           const PrimeInfo *__restrict__ pinfo, int level, int nQ, int nP, int next, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z;
-    const int nl = level + 1;
-    u64 v[kMaxDigit];
-#pragma unroll
-    for (int j = 0; j < kMaxDigit; j++) {
-        if (j >= nP) break;
-        u64 x = acc[((size_t)cc * next + nl + j) * N + n];
-        v[j] = shoup(x, pl->vfac[j][0], pl->vfac[j][1], pinfo[nQ + j].q);
-    }
-    for (int i = 0; i < nl; i++) {
-        const u64 q = pinfo[i].q;
-        u64 t = 0;
-#pragma unroll
-        for (int j = 0; j < kMaxDigit; j++) {
-            if (j >= nP) break;
-            t = add_mod(t, shoup(v[j], pl->phat[i][j][0], pl->phat[i][j][1], q), q);
-        }
-        th[((size_t)cc * nl + i) * N + n] = t;
-    }
+    b_moddown<FP, PL>(hw_blk(), acc, th, pl, pinfo, level, nQ, nP, next, N);
 }
 
-// out_c = base_c + ACC_c P^-1 - TH_c (p P^-1)   (NTT domain, limbs i <= level)
 __global__ void k_ks_combine(const u64 *__restrict__ base0, const u64 *__restrict__ base1, size_t base_ct_stride,
                              const u64 *__restrict__ acc, const u64 *__restrict__ th, u64 *__restrict__ out,
                              size_t out_ct_stride, const ModDownPlan *__restrict__ pl,
                              const PrimeInfo *__restrict__ pinfo, int nl, int next, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    const u64 q = pinfo[i].q;
-    for (int c = 0; c < 2; c++) {
-        u64 a = acc[(((size_t)ct * 2 + c) * next + i) * N + n];
-        u64 t = th[(((size_t)ct * 2 + c) * nl + i) * N + n];
-        u64 r = sub_mod(shoup(a, pl->pinv[i][0], pl->pinv[i][1], q), shoup(t, pl->ppinv[i][0], pl->ppinv[i][1], q), q);
-        const u64 *bp = c == 0 ? base0 : base1;
-        if (bp) r = add_mod(r, bp[(size_t)ct * base_ct_stride + (size_t)i * N + n], q);
-        out[(size_t)ct * out_ct_stride + ((size_t)c * nl + i) * N + n] = r;
-    }
+    b_ks_combine(hw_blk(), base0, base1, base_ct_stride, acc, th, out, out_ct_stride, pl, pinfo, nl, next, N);
 }
 
-// ---------------------- relinearisation fused with one modulus switch
-// Coefficient domain, per coefficient and component c (z-grid = ct * 2 + c):
-//   th_i  = sum_j v_j Phat_j mod q_i, v_j = [acc_{p_j} p^-1 Phat_j^-1]_{p_j}
-//   r_l   = d_l + (acc_l - p th_l) P^-1            (relinearised top limb)
-//   t     = [r_l p^-1]_{q_l} in (-q_l/2, q_l/2]
-//   E_i   = (th_i p P^-1 + p t) q_l^-1,  i < l
-// so that, after E is transformed, out_i = (d_i + acc_i P^-1) q_l^-1 - E_i
-// equals the modulus switch of the relinearised ciphertext exactly (every
-// step is linear over Z_{q_i}).  d and acc limbs l are coefficient domain here.
 template <bool FP, int PL = 0, int MD = kMaxDigit>
 __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restrict__ d, size_t d_ct_stride,
                                u64 *__restrict__ E, const ModDownPlan *__restrict__ md,
                                const ModSwitchPlan *__restrict__ ms, const PrimeInfo *__restrict__ pinfo, int level,
                                int nQ, int nP, int next, int N) {
-    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (PL inverse stages unfolded, PL forward folded)
-    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z, Q = N >> PL;
-    const int ct = cc >> 1, c = cc & 1, nl = level + 1;
-    const u64 *A = acc + (size_t)cc * next * N + n;
-    const u64 *D = d + (size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n;
-    u64 *Eo = E + (size_t)cc * level * N + n;
-    if constexpr (!FP) {
-        u64 v[NV][MD], mag[NV];
-        bool neg[NV];
-        const u64 ql = pinfo[level].q;
-        // inputs: the special limbs and the top limb of the accumulator, the
-        // top limb of d (the last PL inverse stages applied here when PL > 0)
-        u64 sp[NV][MD], top[NV], dt[NV];
-#pragma unroll
-        for (int j = 0; j < MD; j++) {
-            if (j >= nP) break;
-            u64 x[NV];
-#pragma unroll
-            for (int w = 0; w < NV; w++) x[w] = A[(size_t)(nl + j) * N + w * Q];
-            if constexpr (PL > 0) unfold_int<PL>(x, pinfo[nQ + j]);
-#pragma unroll
-            for (int w = 0; w < NV; w++) sp[w][j] = x[w];
-        }
-#pragma unroll
-        for (int w = 0; w < NV; w++) {
-            top[w] = A[(size_t)level * N + w * Q];
-            dt[w] = D[w * Q];
-        }
-        if constexpr (PL > 0) {
-            unfold_int<PL>(top, pinfo[level]);
-            unfold_int<PL>(dt, pinfo[level]);
-        }
-#pragma unroll
-        for (int w = 0; w < NV; w++) {
-#pragma unroll
-            for (int j = 0; j < MD; j++) {
-                if (j >= nP) break;
-                v[w][j] = shoup(sp[w][j], md->vfac[j][0], md->vfac[j][1], pinfo[nQ + j].q);
-            }
-            // top limb of the relinearised component
-            u64 th = 0;
-#pragma unroll
-            for (int j = 0; j < MD; j++) {
-                if (j >= nP) break;
-                th = add_mod(th, shoup(v[w][j], md->phat[level][j][0], md->phat[level][j][1], ql), ql);
-            }
-            u64 r = sub_mod(shoup(top[w], md->pinv[level][0], md->pinv[level][1], ql),
-                            shoup(th, md->ppinv[level][0], md->ppinv[level][1], ql), ql);
-            r = add_mod(r, dt[w], ql);
-            const u64 t = shoup(r, ms->pinv_l[0], ms->pinv_l[1], ql);
-            neg[w] = t > (ql - 1) / 2;
-            mag[w] = neg[w] ? ql - t : t;
-        }
-        for (int i = 0; i < level; i++) {
-            const PrimeInfo &pi = pinfo[i];
-            const u64 q = pi.q;
-            u64 e[NV];
-#pragma unroll
-            for (int w = 0; w < NV; w++) {
-                u64 h = 0;
-#pragma unroll
-                for (int j = 0; j < MD; j++) {
-                    if (j >= nP) break;
-                    h = add_mod(h, shoup(v[w][j], md->phat[i][j][0], md->phat[i][j][1], q), q);
-                }
-                u64 pt = shoup(mag[w], pi.p_mod, pi.p_modp, q);
-                pt = (neg[w] && pt) ? q - pt : pt;
-                const u64 x = add_mod(shoup(h, md->ppinv[i][0], md->ppinv[i][1], q), pt, q);
-                e[w] = shoup(x, ms->qlinv[i][0], ms->qlinv[i][1], q);
-            }
-            if constexpr (PL > 0) fold_int<PL>(e, pi);
-#pragma unroll
-            for (int w = 0; w < NV; w++) Eo[(size_t)i * N + w * Q] = e[w];
-        }
-    } else {
-#pragma clang fp contract(off)
-        double v[NV][MD];  // canonical in [0, p_j)
-        double t[NV];
-        const PrimeInfo &pl = pinfo[level];
-        const double ql = pl.qd;
-        // inputs: the special limbs and the top limb of the accumulator, the
-        // top limb of d (the last PL inverse stages applied here when PL > 0)
-        double top[NV], dt[NV];
-#pragma unroll
-        for (int j = 0; j < MD; j++) {
-            if (j >= nP) break;
-            const PrimeInfo &pj = pinfo[nQ + j];
-            double x[NV];
-#pragma unroll
-            for (int w = 0; w < NV; w++) x[w] = f_load(A[(size_t)(nl + j) * N + w * Q]);
-            if constexpr (PL > 0) unfold_fp<PL, false>(x, pj);  // |x| < 1.5 q: fine for the product
-#pragma unroll
-            for (int w = 0; w < NV; w++) v[w][j] = f_canon(f_mulmod(x[w], fpair(md->vfac[j]), pj.qd), pj.qd, pj.qinv);
-        }
-#pragma unroll
-        for (int w = 0; w < NV; w++) {
-            top[w] = f_load(A[(size_t)level * N + w * Q]);
-            dt[w] = f_load(D[w * Q]);
-        }
-        if constexpr (PL > 0) {  // |.| < 1.5 q: they enter r below through a product and a sum
-            unfold_fp<PL, false>(top, pl);
-            unfold_fp<PL, false>(dt, pl);
-        }
-#pragma unroll
-        for (int w = 0; w < NV; w++) {
-            double th = 0.0;
-#pragma unroll
-            for (int j = 0; j < MD; j++) {
-                if (j >= nP) break;
-                th += f_mulmod(v[w][j], fpair(md->phat[level][j]), ql);
-                if ((j & 7) == 7) th = f_reduce(th, ql, pl.qinv);
-            }
-            th = f_reduce(th, ql, pl.qinv);
-            double r = f_mulmod(top[w], fpair(md->pinv[level]), ql) - f_mulmod(th, fpair(md->ppinv[level]), ql) +
-                       dt[w];
-            // the exact centred lift: it enters every other modulus as an integer
-            t[w] = f_centre(f_mulmod(r, fpair(ms->pinv_l), ql), ql, pl.qinv);
-        }
-        // E_i = (sum_j v_j Phat_j p P^-1 + p t) q_l^-1 with the constants folded
-        for (int i = 0; i < level; i++) {
-            const PrimeInfo &pi = pinfo[i];
-            const double q = pi.qd;
-            double e[NV];
-#pragma unroll
-            for (int w = 0; w < NV; w++) {
-                e[w] = f_mulmod(t[w], fpair(ms->rk2[i]), q);
-#pragma unroll
-                for (int j = 0; j < MD; j++) {
-                    if (j >= nP) break;
-                    e[w] += f_mulmod(v[w][j], fpair(ms->rk1[i][j]), q);
-                    if ((j & 7) == 6) e[w] = f_reduce(e[w], q, pi.qinv);
-                }
-                // the fold takes |x| < 1.6 q and returns canonical words
-                e[w] = PL > 0 ? f_reduce(e[w], q, pi.qinv) : f_canon(e[w], q, pi.qinv);
-            }
-            if constexpr (PL > 0) fold_fp<PL>(e, pi);
-#pragma unroll
-            for (int w = 0; w < NV; w++) Eo[(size_t)i * N + w * Q] = f_bits(e[w]);
-        }
-    }
+    b_relin_ms_fbc<FP, PL, MD>(hw_blk(), acc, d, d_ct_stride, E, md, ms, pinfo, level, nQ, nP, next, N);
 }
 
 // out[ct][c][i] = (d_i + acc_i P^-1) q_l^-1 - E_i, i < level (NTT domain)
@@ -491,73 +106,16 @@ __global__ void k_relin_ms_combine(const u64 *__restrict__ d, size_t d_ct_stride
 
 // ----------------------------------------------------- modulus switching
 
-// R[ct][c][i] = p t mod q_i, t = [top p^-1]_{q_l} lifted to (-q_l/2, q_l/2]
 template <bool FP, int PL = 0>
 __global__ void k_ms_fbc(const u64 *__restrict__ top, u64 *__restrict__ R, const ModSwitchPlan *__restrict__ pl,
                          const PrimeInfo *__restrict__ pinfo, int level, int N) {
-    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (PL inverse stages unfolded, PL forward folded)
-    const int n = blockIdx.x * kT + threadIdx.x, cc = blockIdx.z, Q = N >> PL;
-    const u64 *T = top + (size_t)cc * N + n;
-    u64 *Ro = R + (size_t)cc * level * N + n;
-    if constexpr (!FP) {
-        const u64 ql = pl->ql;
-        u64 mag[NV], x[NV];
-        bool neg[NV];
-#pragma unroll
-        for (int w = 0; w < NV; w++) x[w] = T[w * Q];
-        if constexpr (PL > 0) unfold_int<PL>(x, pinfo[level]);
-#pragma unroll
-        for (int w = 0; w < NV; w++) {
-            const u64 t = shoup(x[w], pl->pinv_l[0], pl->pinv_l[1], ql);
-            neg[w] = t > (ql - 1) / 2;
-            mag[w] = neg[w] ? ql - t : t;  // |t| < q_l < q_i
-        }
-        for (int i = 0; i < level; i++) {
-            const PrimeInfo &pi = pinfo[i];
-            u64 r[NV];
-#pragma unroll
-            for (int w = 0; w < NV; w++) {
-                r[w] = shoup(mag[w], pi.p_mod, pi.p_modp, pi.q);
-                r[w] = (neg[w] && r[w]) ? pi.q - r[w] : r[w];
-            }
-            if constexpr (PL > 0) fold_int<PL>(r, pi);
-#pragma unroll
-            for (int w = 0; w < NV; w++) Ro[(size_t)i * N + w * Q] = r[w];
-        }
-    } else {
-        const PrimeInfo &pq = pinfo[level];
-        double t[NV];
-#pragma unroll
-        for (int w = 0; w < NV; w++) t[w] = f_load(T[w * Q]);
-        if constexpr (PL > 0) unfold_fp<PL, false>(t, pq);  // |t| < 1.5 q: fine for the product
-#pragma unroll
-        for (int w = 0; w < NV; w++) t[w] = f_centre(f_mulmod(t[w], fpair(pl->pinv_l), pq.qd), pq.qd, pq.qinv);
-        for (int i = 0; i < level; i++) {
-            const PrimeInfo &pi = pinfo[i];
-            double r[NV];
-#pragma unroll
-            for (int w = 0; w < NV; w++) {
-                r[w] = f_mulmod(t[w], fpair(pi.p_f), pi.qd);  // |r| < 0.65 q
-                if constexpr (PL == 0) r[w] = f_canon(r[w], pi.qd, pi.qinv);
-            }
-            if constexpr (PL > 0) fold_fp<PL>(r, pi);
-#pragma unroll
-            for (int w = 0; w < NV; w++) Ro[(size_t)i * N + w * Q] = f_bits(r[w]);
-        }
-    }
+    b_ms_fbc<FP, PL>(hw_blk(), top, R, pl, pinfo, level, N);
 }
 
-// out[ct][c][i] = (in - R) q_l^-1, i < level
 __global__ void k_ms_combine(const u64 *__restrict__ in, const u64 *__restrict__ R, u64 *__restrict__ out,
                              const ModSwitchPlan *__restrict__ pl, const PrimeInfo *__restrict__ pinfo, int level,
                              int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    const u64 q = pinfo[i].q;
-    for (int c = 0; c < 2; c++) {
-        u64 x = in[(((size_t)ct * 2 + c) * (level + 1) + i) * N + n];
-        u64 r = R[(((size_t)ct * 2 + c) * level + i) * N + n];
-        out[(((size_t)ct * 2 + c) * level + i) * N + n] = shoup(sub_mod(x, r, q), pl->qlinv[i][0], pl->qlinv[i][1], q);
-    }
+    b_ms_combine(hw_blk(), in, R, out, pl, pinfo, level, N);
 }
 
 // -------------------------------------------------------- client side
@@ -666,76 +224,17 @@ __global__ void k_crt_decode(const u64 *__restrict__ d, uint32_t *__restrict__ o
     out[(size_t)ct * N + n] = (uint32_t)r;
 }
 
-// Paterson-Stockmeyer blocks: H[pos(t)][ct] = sum_k coef[t][k] * baby_k[ct]
-// (NTT domain, every baby at the same level).  Integer kernel: coef holds
-// Shoup pairs [nblk][nbaby][nl][2] of the centred coefficients mod q_i.
-// fp64 kernel: coef holds the centred coefficients themselves as doubles
-// [nblk][nbaby] (|c| < p/2 < 2^19): each baby word v < 2^50 is split as
-// v = h 2^25 + l, the sums of c h and of c l stay below 16 2^19 2^25 = 2^48
-// (exact in fp64 fused multiply-adds), and the result is
-// (sum c h) (2^25 mod q) + sum c l reduced once.
-struct BabyArg {
-    const u64 *baby[16];
-    int nlb[16];  // limbs per component each baby is stored with (>= nl: its lowest nl are read)
-    int pos[64];  // storage position of block t
-};
-// Component c of ciphertext ct (blockIdx.z = 2 ct + c): babies are read at
-// ciphertext ct; outputs go to ciphertext ct0 + ct of a batch of `count` per
-// block.
 template <bool FP>
 __global__ void k_lincomb(BabyArg ba, const u64 *__restrict__ coef, u64 *__restrict__ out, int nbaby, int nblk,
                           int count, int ct0, int nl, const PrimeInfo *__restrict__ pinfo, int N) {
-    const int n = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z >> 1;
-    const PrimeInfo &pi = pinfo[i];
-    const u64 q = pi.q;
-    const size_t L = (size_t)nl * N;
-    {
-        const int c = blockIdx.z & 1;
-        if constexpr (!FP) {
-            u64 v[16];
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                if (k >= nbaby) break;
-                const size_t Lk = (size_t)ba.nlb[k] * N;
-                v[k] = ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n];
-            }
-            for (int t = 0; t < nblk; t++) {
-                u64 acc = 0;
-#pragma unroll
-                for (int k = 0; k < 16; k++) {
-                    if (k >= nbaby) break;
-                    const u64 *w = coef + (((size_t)t * nbaby + k) * nl + i) * 2;
-                    acc = add_mod(acc, shoup(v[k], w[0], w[1], q), q);
-                }
-                out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] = acc;
-            }
-        } else {
-#pragma clang fp contract(off)
-            const double *cf = reinterpret_cast<const double *>(coef);
-            double hi[16], lo[16];
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                if (k >= nbaby) break;
-                const size_t Lk = (size_t)ba.nlb[k] * N;
-                const double v = f_load(ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n]);
-                hi[k] = __builtin_floor(v * 0x1p-25);
-                lo[k] = __builtin_fma(-hi[k], 0x1p25, v);
-            }
-            const FPair p25 = fpair(pi.two25_f);
-            for (int t = 0; t < nblk; t++) {
-                double sh = 0.0, sl = 0.0;
-#pragma unroll
-                for (int k = 0; k < 16; k++) {
-                    if (k >= nbaby) break;
-                    const double w = cf[t * nbaby + k];
-                    sh = __builtin_fma(w, hi[k], sh);
-                    sl = __builtin_fma(w, lo[k], sl);
-                }
-                out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] =
-                    f_bits(f_canon(f_mulmod(sh, p25, pi.qd) + sl, pi.qd, pi.qinv));
-            }
-        }
-    }
+    b_lincomb<FP>(hw_blk(), ba, coef, out, nbaby, nblk, count, ct0, nl, pinfo, N);
+}
+
+template <int KB>
+__global__ void k_lincomb_wide(const u64 *__restrict__ in, u64 *__restrict__ out, const double *__restrict__ W,
+                               const double *__restrict__ c0, int M, int K, int KT, int count, int nl,
+                               const PrimeInfo *__restrict__ pinfo, int N) {
+    b_lincomb_wide<KB>(hw_blk(), in, out, W, c0, M, K, KT, count, nl, pinfo, N);
 }
 
 inline dim3 grid3(int N, int y, int z) { return dim3((unsigned)(N / kT), (unsigned)y, (unsigned)z); }
@@ -746,6 +245,11 @@ inline dim3 grid3(int N, int y, int z) { return dim3((unsigned)(N / kT), (unsign
 
 void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, const u64 *addend, u64 *out, int count, int bcount,
                    int nl, int na, int nb, int nc, hipStream_t st) {
+    if (tl_rec) {
+        tl_rec->add(addend ? kPkTensorAdd : kPkTensor, grid3(c->N, nl, count),
+                    PaTensor{a, b, addend, out, bcount, nl, na, nb, addend ? nc : nl, c->pinfo, c->N});
+        return;
+    }
     ProfScope ps(c, kProfTensor, 8.0 * c->N * nl * (2.0 * count + 2.0 * bcount + (addend ? 2.0 * count : 0) + 3.0 * count),
                  st);
     if (addend)
@@ -757,6 +261,11 @@ void launch_tensor(const bc_ctx *c, const u64 *a, const u64 *b, const u64 *adden
 }
 void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int count, int bcount, int nl, int na,
                    int nb, int ncomp, bool sub, hipStream_t st) {
+    if (tl_rec) {
+        tl_rec->add(kPkAddSub, grid3(c->N, nl, count),
+                    PaAddSub{a, b, out, bcount, nl, na, nb, ncomp, sub ? 1 : 0, c->pinfo, c->N});
+        return;
+    }
     k_addsub<<<grid3(c->N, nl, count), kT, 0, st>>>(a, b, out, bcount, nl, na, nb, ncomp, sub ? 1 : 0, c->pinfo,
                                                     c->N);
 }
@@ -771,9 +280,17 @@ static ScalarArg scalar_arg(const bc_ctx *c, int64_t v, int nl) {
     return s;
 }
 void launch_mul_scalar(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st) {
+    if (tl_rec) {
+        tl_rec->add(kPkMulScalar, grid3(c->N, nl, count), PaScalar{a, out, nl, ncomp, scalar_arg(c, v, nl), c->pinfo, c->N});
+        return;
+    }
     k_mul_scalar<<<grid3(c->N, nl, count), kT, 0, st>>>(a, out, nl, ncomp, scalar_arg(c, v, nl), c->pinfo, c->N);
 }
 void launch_add_const(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st) {
+    if (tl_rec) {
+        tl_rec->add(kPkAddConst, grid3(c->N, nl, count), PaScalar{a, out, nl, ncomp, scalar_arg(c, v, nl), c->pinfo, c->N});
+        return;
+    }
     k_add_const<<<grid3(c->N, nl, count), kT, 0, st>>>(a, out, nl, ncomp, scalar_arg(c, v, nl), c->pinfo, c->N);
 }
 void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, int count, int nl, int ncomp,
@@ -782,6 +299,13 @@ void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, i
 }
 template <bool FP, int PL, int MD>
 static void modup_pl(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, hipStream_t st) {
+    if (tl_rec) {
+        static_assert(MD == (PL > 0 ? kFoldDigit : kMaxDigit), "the executor runs the launchers' digit bounds");
+        BC_REQUIRE(FP, BC_ERR_ARG, "the persistent executor needs fp64 arithmetic");
+        tl_rec->add(PL == 2 ? kPkModUp2 : PL == 1 ? kPkModUp1 : kPkModUp0, grid3(c->N >> PL, 1, count * c->dnum),
+                    PaModUp{xc, mu, c->modup_f + (size_t)level * c->dnum, c->pinfo, level + 1, next, c->dnum, c->N});
+        return;
+    }
     k_modup<FP, PL, MD><<<grid3(c->N >> PL, 1, count * c->dnum), kT, 0, st>>>(
         xc, mu, (FP ? c->modup_f : c->modup) + (size_t)level * c->dnum, c->pinfo, level + 1, next, c->dnum, c->N);
 }
@@ -806,6 +330,12 @@ void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_s
     // raised limbs of every active digit read, two accumulators written, the key read once
     ProfScope ps(c, kProfKsInner, 8.0 * c->N * next * ((double)count * (nact + 2) + 2.0 * nact), st);
     const dim3 g = grid3(c->N, next, (count + kKsCts - 1) / kKsCts);
+    if (tl_rec) {
+        BC_REQUIRE(use_fp64(c), BC_ERR_ARG, "the persistent executor needs fp64 arithmetic");
+        tl_rec->add(kPkKsInner, g, PaKsInner{mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum,
+                                             c->alpha, count, c->pinfo, c->N});
+        return;
+    }
     if (use_fp64(c))
         k_ks_inner<true><<<g, kT, 0, st>>>(mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum,
                                            c->alpha, count, c->pinfo, c->N);
@@ -813,11 +343,38 @@ void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_s
         k_ks_inner<false><<<g, kT, 0, st>>>(mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum,
                                             c->alpha, count, c->pinfo, c->N);
 }
-void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, hipStream_t st) {
-    k_moddown<<<grid3(c->N, 1, count * 2), kT, 0, st>>>(acc, th, c->moddown, c->pinfo, level, c->nQ, c->nP, next, c->N);
+template <bool FP, int PL>
+static void moddown_pl(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, hipStream_t st) {
+    const ModDownPlan *md = FP ? c->moddown_f : c->moddown;
+    if (tl_rec) {
+        BC_REQUIRE(FP, BC_ERR_ARG, "the persistent executor needs fp64 arithmetic");
+        tl_rec->add(PL == 2 ? kPkModDown2 : PL == 1 ? kPkModDown1 : kPkModDown0, grid3(c->N >> PL, 1, count * 2),
+                    PaModDown{acc, th, md, c->pinfo, level, c->nQ, c->nP, next, c->N});
+        return;
+    }
+    k_moddown<FP, PL><<<grid3(c->N >> PL, 1, count * 2), kT, 0, st>>>(acc, th, md, c->pinfo, level, c->nQ, c->nP,
+                                                                      next, c->N);
+}
+template <bool FP>
+static void moddown_a(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, int pl,
+                      hipStream_t st) {
+    if (pl == 2) moddown_pl<FP, 2>(c, acc, th, count, level, next, st);
+    else if (pl == 1) moddown_pl<FP, 1>(c, acc, th, count, level, next, st);
+    else moddown_pl<FP, 0>(c, acc, th, count, level, next, st);
+}
+void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, int pl, hipStream_t st) {
+    BC_REQUIRE(pl == 0 || (c->nP <= kFoldDigit), BC_ERR_PARAM, "modulus lowering: too many special primes to fold");
+    if (use_fp64(c)) moddown_a<true>(c, acc, th, count, level, next, pl, st);
+    else moddown_a<false>(c, acc, th, count, level, next, pl, st);
 }
 void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size_t base_ct_stride, const u64 *acc,
                        const u64 *th, u64 *out, size_t out_ct_stride, int count, int level, int next, hipStream_t st) {
+    if (tl_rec) {
+        tl_rec->add(kPkKsCombine, grid3(c->N, level + 1, count),
+                    PaKsCombine{base0, base1, base_ct_stride, acc, th, out, out_ct_stride, c->moddown, c->pinfo,
+                                level + 1, next, c->N});
+        return;
+    }
     k_ks_combine<<<grid3(c->N, level + 1, count), kT, 0, st>>>(base0, base1, base_ct_stride, acc, th, out,
                                                                out_ct_stride, c->moddown, c->pinfo, level + 1, next,
                                                                c->N);
@@ -840,6 +397,14 @@ void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level
 template <bool FP, int PL, int MD>
 static void relin_ms_fbc_pl(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
                             int level, int next, hipStream_t st) {
+    if (tl_rec) {
+        static_assert(MD == (PL > 0 ? kFoldDigit : kMaxDigit), "the executor runs the launchers' digit bounds");
+        BC_REQUIRE(FP, BC_ERR_ARG, "the persistent executor needs fp64 arithmetic");
+        tl_rec->add(PL == 2 ? kPkRelinMs2 : PL == 1 ? kPkRelinMs1 : kPkRelinMs0, grid3(c->N >> PL, 1, count * 2),
+                    PaRelinMs{acc, d, d_ct_stride, E, c->moddown_f, c->modsw_f + level, c->pinfo, level, c->nQ, c->nP,
+                              next, c->N});
+        return;
+    }
     k_relin_ms_fbc<FP, PL, MD><<<grid3(c->N >> PL, 1, count * 2), kT, 0, st>>>(
         acc, d, d_ct_stride, E, FP ? c->moddown_f : c->moddown, (FP ? c->modsw_f : c->modsw) + level, c->pinfo, level,
         c->nQ, c->nP, next, c->N);
@@ -913,6 +478,11 @@ void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *nlb, c
         ba.nlb[k] = nlb[k];
     }
     for (int t = 0; t < nblk; t++) ba.pos[t] = pos[t];
+    if (tl_rec) {
+        tl_rec->add(lincomb_small(c) ? kPkLincombFp : kPkLincombInt, grid3(c->N, nl, 2 * nlaunch),
+                    PaLincomb{ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo, c->N});
+        return;
+    }
     ProfScope ps(c, kProfLincomb, 8.0 * c->N * 2.0 * nl * nlaunch * (nbaby + nblk), st);
     if (lincomb_small(c))
         k_lincomb<true><<<grid3(c->N, nl, 2 * nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl,
@@ -920,6 +490,19 @@ void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *nlb, c
     else
         k_lincomb<false><<<grid3(c->N, nl, 2 * nlaunch), kT, 0, st>>>(ba, coef, out, nbaby, nblk, count, ct0, nl, c->pinfo,
                                                                  c->N);
+}
+int lincomb_wide_tile(int K) { return K >= 16 ? 16 : K >= 8 ? 8 : 1; }
+void launch_lincomb_wide(const bc_ctx *c, const u64 *in, u64 *out, const double *W, const double *c0, int M, int K,
+                         int count, int nl, hipStream_t st) {
+    BC_REQUIRE(use_fp64(c), BC_ERR_PARAM, "wide linear combinations need primes below 2^50");
+    BC_REQUIRE(!tl_rec, BC_ERR_ARG, "the persistent executor does not run wide linear combinations");
+    BC_REQUIRE(M >= 1 && M <= 4096 && K >= 1, BC_ERR_ARG, "wide linear combination: bad shape");
+    const int KB = lincomb_wide_tile(K), KT = (K + KB - 1) / KB;
+    ProfScope ps(c, kProfLincomb, 8.0 * c->N * 2.0 * nl * count * (M + K), st);
+    const dim3 g((unsigned)(KT * (c->N / kT)), (unsigned)nl, (unsigned)(2 * count));
+    if (KB == 16) k_lincomb_wide<16><<<g, kT, 0, st>>>(in, out, W, c0, M, K, KT, count, nl, c->pinfo, c->N);
+    else if (KB == 8) k_lincomb_wide<8><<<g, kT, 0, st>>>(in, out, W, c0, M, K, KT, count, nl, c->pinfo, c->N);
+    else k_lincomb_wide<1><<<g, kT, 0, st>>>(in, out, W, c0, M, K, KT, count, nl, c->pinfo, c->N);
 }
 void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st) {
     k_crt_decode<<<grid3(c->N, 1, count), kT, 0, st>>>(d, out, c->garner, c->pinfo, nl, c->p, c->N);

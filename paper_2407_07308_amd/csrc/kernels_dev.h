@@ -1,0 +1,701 @@
+// kernels_dev.h -- device bodies of the element-wise, base-conversion and
+// key-switching kernels.
+//
+// Each body computes one workgroup's share of its kernel from the block
+// coordinates it is given (VBlk): the hardware's when a kernel of its own
+// runs it, a virtual block's when the persistent executor does.  Every
+// ciphertext limb is a contiguous run of N uint64 residues; a batch is
+// [count][ncomp][nlimb][N]; x covers the N coefficients of a limb (256 per
+// workgroup), y the limb, z the ciphertext of the batch.
+#pragma once
+
+#include <type_traits>
+
+#include "bc_internal.h"
+
+namespace bc {
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ __forceinline__ int ext_prime(int e, int level, int nQ) { return e <= level ? e : nQ + (e - level - 1); }
+
+
+// ACC[ct][c][e] = sum_j MU[ct][j][e] * K_j,c[prime(e)]   (NTT domain), where
+// digit j's own limbs (e in [j alpha, (j+1) alpha)) are X's limbs themselves.
+// A thread takes kKsCts consecutive ciphertexts: each key word is read once
+// for all of them, and every load is issued before the arithmetic.
+constexpr int kKsCts = 8;
+
+
+// (a0 b0, a0 b1 + a1 b0, a1 b1), plus (c0, c1) on the first two components
+// when an addend c is given (a multiply-accumulate's sum before relinearising).
+// The output has nl limbs; each operand is read at its own limb count (na,
+// nb, nc >= nl): an operand above the output's level contributes its lowest
+// nl limbs (level alignment by dropping primes, without a copy).  When b is
+// broadcast (bcount < count, ciphertext ct uses b[ct % bcount]) the grid runs
+// the count / bcount products that share a b ciphertext back to back, so
+// its limbs come from the cache after the first.
+template <bool ADD>
+__device__ __forceinline__ void b_tensor(const VBlk &VB, const u64 *__restrict__ a, const u64 *__restrict__ b, const u64 *__restrict__ c,
+                         u64 *__restrict__ out, int bcount, int nl, int na, int nb, int nc,
+                         const PrimeInfo *__restrict__ pinfo, int N) {
+    const int rep = VB.gz / bcount;  // products per b ciphertext
+    const int n = VB.x * kT + threadIdx.x, i = VB.y;
+    const int ct = (int)(VB.z % rep) * bcount + (int)(VB.z / rep);
+    const size_t L = (size_t)nl * N, La = (size_t)na * N, Lb = (size_t)nb * N;
+    const u64 *A = a + (size_t)ct * 2 * La + (size_t)i * N + n;
+    const u64 *B = b + (size_t)(ct % bcount) * 2 * Lb + (size_t)i * N + n;
+    u64 *O = out + (size_t)ct * 3 * L + (size_t)i * N + n;
+    const Barrett br = pinfo[i].br;
+    u64 a0 = A[0], a1 = A[La], b0 = B[0], b1 = B[Lb];
+    u64 d0 = mul_mod(a0, b0, br), d1 = add_mod(mul_mod(a0, b1, br), mul_mod(a1, b0, br), br.q);
+    if constexpr (ADD) {
+        const size_t Lc = (size_t)nc * N;
+        const u64 *C = c + (size_t)ct * 2 * Lc + (size_t)i * N + n;
+        d0 = add_mod(d0, C[0], br.q);
+        d1 = add_mod(d1, C[Lc], br.q);
+    }
+    O[0] = d0;
+    O[L] = d1;
+    O[2 * L] = mul_mod(a1, b1, br);
+}
+
+// out = a + sgn * b on ncomp components (sgn = +1 / -1); out has nl limbs,
+// a and b are read at their own limb counts (na, nb >= nl)
+__device__ __forceinline__ void b_addsub(const VBlk &VB, const u64 *__restrict__ a, const u64 *__restrict__ b, u64 *__restrict__ out, int bcount,
+                         int nl, int na, int nb, int ncomp, int sub, const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = VB.x * kT + threadIdx.x, i = VB.y, ct = VB.z;
+    const size_t L = (size_t)nl * N, La = (size_t)na * N, Lb = (size_t)nb * N;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < ncomp; c++) {
+        const size_t off = (size_t)i * N + n;
+        u64 x = a[(size_t)ct * ncomp * La + c * La + off], y = b[(size_t)(ct % bcount) * ncomp * Lb + c * Lb + off];
+        out[(size_t)ct * ncomp * L + c * L + off] = sub ? sub_mod(x, y, q) : add_mod(x, y, q);
+    }
+}
+
+__device__ __forceinline__ void b_mul_scalar(const VBlk &VB, const u64 *__restrict__ a, u64 *__restrict__ out, int nl, int ncomp, const ScalarArg &s,
+                             const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = VB.x * kT + threadIdx.x, i = VB.y, ct = VB.z;
+    const size_t L = (size_t)nl * N;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < ncomp; c++) {
+        size_t off = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N + n;
+        out[off] = shoup(a[off], s.w[i][0], s.w[i][1], q);
+    }
+}
+
+// constant polynomial c: every evaluation of component 0 gains c mod q_i
+__device__ __forceinline__ void b_add_const(const VBlk &VB, const u64 *__restrict__ a, u64 *__restrict__ out, int nl, int ncomp, const ScalarArg &s,
+                            const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = VB.x * kT + threadIdx.x, i = VB.y, ct = VB.z;
+    const size_t L = (size_t)nl * N;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < ncomp; c++) {
+        size_t off = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N + n;
+        u64 x = a[off];
+        out[off] = c == 0 ? add_mod(x, s.w[i][0], q) : x;
+    }
+}
+
+// out[ct][c][i][r] = in[ct][c][i][perm[r]]
+__device__ __forceinline__ void b_permute(const VBlk &VB, const u64 *__restrict__ in, u64 *__restrict__ out, const u32 *__restrict__ perm, int nl,
+                          int ncomp, int N) {
+    const int n = VB.x * kT + threadIdx.x, i = VB.y, ct = VB.z;
+    const size_t L = (size_t)nl * N;
+    const u32 src = perm[n];
+    for (int c = 0; c < ncomp; c++) {
+        size_t base = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N;
+        out[base + n] = in[base + src];
+    }
+}
+
+// Fast base conversion of digit j (z-grid = ct * dnum + j):
+// y_i = [x_i Qhat_i^-1]_{q_i}, u_t = sum_i y_i Qhat_i mod q_t.
+// With PL > 0 a thread takes the 2^PL words n + v N/2^PL of each limb: it
+// applies the last PL stages of the part-limb inverse transform that made xc
+// to its inputs (unfold_int / unfold_fp) and the first PL forward stages of
+// the new limbs' transforms to its outputs (fold_int / fold_fp).  MD bounds
+// the digit size at compile time.
+template <bool FP, int PL = 0, int MD = kMaxDigit>
+__device__ __forceinline__ void b_modup(const VBlk &VB, const u64 *__restrict__ xc, u64 *__restrict__ mu, const ModUpPlan *__restrict__ plans,
+                        const PrimeInfo *__restrict__ pinfo, int nl, int next, int dnum, int N) {
+    constexpr int NV = 1 << PL;
+    const int n = VB.x * kT + threadIdx.x, Q = N >> PL;
+    const int ct = VB.z / dnum, j = VB.z - ct * dnum;
+    const ModUpPlan &pl = plans[j];
+    if (pl.nsrc == 0) return;
+    u64 *out = mu + ((size_t)ct * dnum + j) * next * N + n;
+    const u64 *in = xc + (size_t)ct * nl * N + n;
+    if constexpr (!FP) {
+        // fully unrolled over the compile-time bound so y[] stays in registers
+        u64 y[NV][MD];
+#pragma unroll
+        for (int s = 0; s < MD; s++) {
+            if (s >= pl.nsrc) break;
+            const int i = pl.src_lo + s;
+            u64 x[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) x[v] = in[(size_t)i * N + v * Q];
+            if constexpr (PL > 0) unfold_int<PL>(x, pinfo[i]);
+#pragma unroll
+            for (int v = 0; v < NV; v++) y[v][s] = shoup(x[v], pl.qhinv[s][0], pl.qhinv[s][1], pinfo[i].q);
+        }
+        for (int t = 0; t < pl.ntgt; t++) {
+            const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
+            u64 acc[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                acc[v] = 0;
+#pragma unroll
+                for (int s = 0; s < MD; s++) {
+                    if (s >= pl.nsrc) break;
+                    acc[v] = add_mod(acc[v], shoup(y[v][s], pl.qhat[t][s][0], pl.qhat[t][s][1], pt.q), pt.q);
+                }
+            }
+            if constexpr (PL > 0) fold_int<PL>(acc, pt);
+#pragma unroll
+            for (int v = 0; v < NV; v++) out[(size_t)pl.tgt_e[t] * N + v * Q] = acc[v];
+        }
+    } else {
+#pragma clang fp contract(off)
+        // y_s canonical in [0, q_s); each product below 0.75 q_t in magnitude,
+        // so eight of them sum exactly before a reduction
+        double y[NV][MD];
+#pragma unroll
+        for (int s = 0; s < MD; s++) {
+            if (s >= pl.nsrc) break;
+            const PrimeInfo &pi = pinfo[pl.src_lo + s];
+            double x[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) x[v] = f_load(in[(size_t)(pl.src_lo + s) * N + v * Q]);
+            if constexpr (PL > 0) unfold_fp<PL, false>(x, pi);  // |x| < 1.5 q: fine for the product
+#pragma unroll
+            for (int v = 0; v < NV; v++) y[v][s] = f_canon(f_mulmod(x[v], fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
+        }
+        for (int t = 0; t < pl.ntgt; t++) {
+            const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
+            double acc[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                acc[v] = 0.0;
+#pragma unroll
+                for (int s = 0; s < MD; s++) {
+                    if (s >= pl.nsrc) break;
+                    acc[v] += f_mulmod(y[v][s], fpair(pl.qhat[t][s]), pt.qd);
+                    if ((s & 7) == 7) acc[v] = f_reduce(acc[v], pt.qd, pt.qinv);
+                }
+                // the fold takes |x| < 1.6 q and returns canonical words
+                acc[v] = PL > 0 ? f_reduce(acc[v], pt.qd, pt.qinv) : f_canon(acc[v], pt.qd, pt.qinv);
+            }
+            if constexpr (PL > 0) fold_fp<PL>(acc, pt);
+#pragma unroll
+            for (int v = 0; v < NV; v++) out[(size_t)pl.tgt_e[t] * N + v * Q] = f_bits(acc[v]);
+        }
+    }
+}
+
+// FP: the products of two variable residues in fp64 (f_mulmod with the
+// quotient factor w/q formed as w * (1/q): two roundings instead of one, so
+// each product lies within 0.875 q of zero for q < 2^50, and eight of them
+// sum exactly before a reduction).  Otherwise Barrett products on u64.
+// Blocks are numbered so that the ciphertext groups vary fastest: the groups
+// that read the same key words run back to back and find them in the cache.
+template <bool FP>
+__device__ __forceinline__ void b_ks_inner(const VBlk &VB, const u64 *__restrict__ mu, const u64 *__restrict__ x, size_t x_ct_stride,
+                           const u64 *__restrict__ key, u64 *__restrict__ acc, int level, int nQ, int nmod, int next,
+                           int nact, int dnum, int alpha, int count, const PrimeInfo *__restrict__ pinfo, int N) {
+    const unsigned lin = VB.x + VB.gx * (VB.y + VB.gy * VB.z);
+    const unsigned zg = lin % VB.gz, rest = lin / VB.gz;
+    const int n = (int)(rest % VB.gx) * kT + threadIdx.x, e = (int)(rest / VB.gx), ct0 = (int)zg * kKsCts;
+    const int prime = ext_prime(e, level, nQ);
+    const int own = e <= level ? e / alpha : -1;
+    using S = typename std::conditional<FP, double, u64>::type;
+    S s0[kKsCts], s1[kKsCts];
+#pragma unroll
+    for (int c = 0; c < kKsCts; c++) s0[c] = s1[c] = 0;
+    const Barrett br = pinfo[prime].br;
+    const double q = pinfo[prime].qd, qinv = pinfo[prime].qinv;
+    for (int j = 0; j < nact; j++) {
+        const u64 *K = key + ((size_t)j * 2 * nmod + prime) * N + n;
+        const u64 k0 = K[0], k1 = K[(size_t)nmod * N];
+        u64 u[kKsCts];
+#pragma unroll
+        for (int c = 0; c < kKsCts; c++) {
+            const int ct = min(ct0 + c, count - 1);  // a tail thread repeats the last ciphertext
+            u[c] = j == own ? x[(size_t)ct * x_ct_stride + (size_t)e * N + n]
+                            : mu[(((size_t)ct * dnum + j) * next + e) * N + n];
+        }
+        if constexpr (FP) {
+#pragma clang fp contract(off)
+            const double w0 = f_load(k0), w1 = f_load(k1);
+            const FPair c0{w0, w0 * qinv}, c1{w1, w1 * qinv};
+#pragma unroll
+            for (int c = 0; c < kKsCts; c++) {
+                const double y = f_load(u[c]);
+                s0[c] += f_mulmod(y, c0, q);
+                s1[c] += f_mulmod(y, c1, q);
+                if ((j & 7) == 7) {
+                    s0[c] = f_reduce(s0[c], q, qinv);
+                    s1[c] = f_reduce(s1[c], q, qinv);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < kKsCts; c++) {
+                s0[c] = add_mod(s0[c], mul_mod(u[c], k0, br), br.q);
+                s1[c] = add_mod(s1[c], mul_mod(u[c], k1, br), br.q);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kKsCts; c++) {
+        const int ct = ct0 + c;
+        if (ct < count) {
+            u64 r0, r1;
+            if constexpr (FP) {
+                r0 = f_bits(f_canon(s0[c], q, qinv));
+                r1 = f_bits(f_canon(s1[c], q, qinv));
+            } else {
+                r0 = s0[c];
+                r1 = s1[c];
+            }
+            acc[(((size_t)ct * 2 + 0) * next + e) * N + n] = r0;
+            acc[(((size_t)ct * 2 + 1) * next + e) * N + n] = r1;
+        }
+    }
+}
+
+// Exact division by P, conversion part (z-grid = ct * 2 + c):
+// v_j = [acc_{p_j} p^-1 Phat_j^-1]_{p_j};  TH_i = sum_j v_j Phat_j mod q_i.
+// With PL > 0 a thread takes the 2^PL words n + v N/2^PL of each limb: it
+// applies the last PL stages of the part-limb inverse transform of the
+// special limbs to its inputs and the first PL forward stages of TH's
+// transforms to its outputs.  FP: fp64 products with the plan's (w, w/q)
+// pairs; each product lies within 0.75 q_i of zero (v_j < 2^50), so eight sum
+// exactly before a reduction.
+template <bool FP, int PL = 0>
+__device__ __forceinline__ void b_moddown(const VBlk &VB, const u64 *__restrict__ acc, u64 *__restrict__ th,
+                                          const ModDownPlan *__restrict__ pl, const PrimeInfo *__restrict__ pinfo,
+                                          int level, int nQ, int nP, int next, int N) {
+    constexpr int NV = 1 << PL, MD = PL > 0 ? kFoldDigit : kMaxDigit;
+    const int n = VB.x * kT + threadIdx.x, cc = VB.z, Q = N >> PL;
+    const int nl = level + 1;
+    const u64 *A = acc + (size_t)cc * next * N + n;
+    u64 *T = th + (size_t)cc * nl * N + n;
+    if constexpr (!FP) {
+        u64 v[NV][MD];
+#pragma unroll
+        for (int j = 0; j < MD; j++) {
+            if (j >= nP) break;
+            u64 x[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) x[w] = A[(size_t)(nl + j) * N + w * Q];
+            if constexpr (PL > 0) unfold_int<PL>(x, pinfo[nQ + j]);
+#pragma unroll
+            for (int w = 0; w < NV; w++) v[w][j] = shoup(x[w], pl->vfac[j][0], pl->vfac[j][1], pinfo[nQ + j].q);
+        }
+        for (int i = 0; i < nl; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            u64 t[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) {
+                t[w] = 0;
+#pragma unroll
+                for (int j = 0; j < MD; j++) {
+                    if (j >= nP) break;
+                    t[w] = add_mod(t[w], shoup(v[w][j], pl->phat[i][j][0], pl->phat[i][j][1], pi.q), pi.q);
+                }
+            }
+            if constexpr (PL > 0) fold_int<PL>(t, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) T[(size_t)i * N + w * Q] = t[w];
+        }
+    } else {
+#pragma clang fp contract(off)
+        double v[NV][MD];  // canonical in [0, p_j)
+#pragma unroll
+        for (int j = 0; j < MD; j++) {
+            if (j >= nP) break;
+            const PrimeInfo &pj = pinfo[nQ + j];
+            double x[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) x[w] = f_load(A[(size_t)(nl + j) * N + w * Q]);
+            if constexpr (PL > 0) unfold_fp<PL, false>(x, pj);  // |x| < 1.5 q: fine for the product
+#pragma unroll
+            for (int w = 0; w < NV; w++) v[w][j] = f_canon(f_mulmod(x[w], fpair(pl->vfac[j]), pj.qd), pj.qd, pj.qinv);
+        }
+        for (int i = 0; i < nl; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            double t[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) {
+                t[w] = 0.0;
+#pragma unroll
+                for (int j = 0; j < MD; j++) {
+                    if (j >= nP) break;
+                    t[w] += f_mulmod(v[w][j], fpair(pl->phat[i][j]), pi.qd);
+                    if ((j & 7) == 7) t[w] = f_reduce(t[w], pi.qd, pi.qinv);
+                }
+                // the fold takes |x| < 1.6 q and returns canonical words
+                t[w] = PL > 0 ? f_reduce(t[w], pi.qd, pi.qinv) : f_canon(t[w], pi.qd, pi.qinv);
+            }
+            if constexpr (PL > 0) fold_fp<PL>(t, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) T[(size_t)i * N + w * Q] = f_bits(t[w]);
+        }
+    }
+}
+
+// out_c = base_c + ACC_c P^-1 - TH_c (p P^-1)   (NTT domain, limbs i <= level)
+__device__ __forceinline__ void b_ks_combine(const VBlk &VB, const u64 *__restrict__ base0, const u64 *__restrict__ base1, size_t base_ct_stride,
+                             const u64 *__restrict__ acc, const u64 *__restrict__ th, u64 *__restrict__ out,
+                             size_t out_ct_stride, const ModDownPlan *__restrict__ pl,
+                             const PrimeInfo *__restrict__ pinfo, int nl, int next, int N) {
+    const int n = VB.x * kT + threadIdx.x, i = VB.y, ct = VB.z;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < 2; c++) {
+        u64 a = acc[(((size_t)ct * 2 + c) * next + i) * N + n];
+        u64 t = th[(((size_t)ct * 2 + c) * nl + i) * N + n];
+        u64 r = sub_mod(shoup(a, pl->pinv[i][0], pl->pinv[i][1], q), shoup(t, pl->ppinv[i][0], pl->ppinv[i][1], q), q);
+        const u64 *bp = c == 0 ? base0 : base1;
+        if (bp) r = add_mod(r, bp[(size_t)ct * base_ct_stride + (size_t)i * N + n], q);
+        out[(size_t)ct * out_ct_stride + ((size_t)c * nl + i) * N + n] = r;
+    }
+}
+
+// ---------------------- relinearisation fused with one modulus switch
+// Coefficient domain, per coefficient and component c (z-grid = ct * 2 + c):
+//   th_i  = sum_j v_j Phat_j mod q_i, v_j = [acc_{p_j} p^-1 Phat_j^-1]_{p_j}
+//   r_l   = d_l + (acc_l - p th_l) P^-1            (relinearised top limb)
+//   t     = [r_l p^-1]_{q_l} in (-q_l/2, q_l/2]
+//   E_i   = (th_i p P^-1 + p t) q_l^-1,  i < l
+// so that, after E is transformed, out_i = (d_i + acc_i P^-1) q_l^-1 - E_i
+// equals the modulus switch of the relinearised ciphertext exactly (every
+// step is linear over Z_{q_i}).  d and acc limbs l are coefficient domain here.
+template <bool FP, int PL = 0, int MD = kMaxDigit>
+__device__ __forceinline__ void b_relin_ms_fbc(const VBlk &VB, const u64 *__restrict__ acc, const u64 *__restrict__ d, size_t d_ct_stride,
+                               u64 *__restrict__ E, const ModDownPlan *__restrict__ md,
+                               const ModSwitchPlan *__restrict__ ms, const PrimeInfo *__restrict__ pinfo, int level,
+                               int nQ, int nP, int next, int N) {
+    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (PL inverse stages unfolded, PL forward folded)
+    const int n = VB.x * kT + threadIdx.x, cc = VB.z, Q = N >> PL;
+    const int ct = cc >> 1, c = cc & 1, nl = level + 1;
+    const u64 *A = acc + (size_t)cc * next * N + n;
+    const u64 *D = d + (size_t)ct * d_ct_stride + ((size_t)c * nl + level) * N + n;
+    u64 *Eo = E + (size_t)cc * level * N + n;
+    if constexpr (!FP) {
+        u64 v[NV][MD], mag[NV];
+        bool neg[NV];
+        const u64 ql = pinfo[level].q;
+        // inputs: the special limbs and the top limb of the accumulator, the
+        // top limb of d (the last PL inverse stages applied here when PL > 0)
+        u64 sp[NV][MD], top[NV], dt[NV];
+#pragma unroll
+        for (int j = 0; j < MD; j++) {
+            if (j >= nP) break;
+            u64 x[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) x[w] = A[(size_t)(nl + j) * N + w * Q];
+            if constexpr (PL > 0) unfold_int<PL>(x, pinfo[nQ + j]);
+#pragma unroll
+            for (int w = 0; w < NV; w++) sp[w][j] = x[w];
+        }
+#pragma unroll
+        for (int w = 0; w < NV; w++) {
+            top[w] = A[(size_t)level * N + w * Q];
+            dt[w] = D[w * Q];
+        }
+        if constexpr (PL > 0) {
+            unfold_int<PL>(top, pinfo[level]);
+            unfold_int<PL>(dt, pinfo[level]);
+        }
+#pragma unroll
+        for (int w = 0; w < NV; w++) {
+#pragma unroll
+            for (int j = 0; j < MD; j++) {
+                if (j >= nP) break;
+                v[w][j] = shoup(sp[w][j], md->vfac[j][0], md->vfac[j][1], pinfo[nQ + j].q);
+            }
+            // top limb of the relinearised component
+            u64 th = 0;
+#pragma unroll
+            for (int j = 0; j < MD; j++) {
+                if (j >= nP) break;
+                th = add_mod(th, shoup(v[w][j], md->phat[level][j][0], md->phat[level][j][1], ql), ql);
+            }
+            u64 r = sub_mod(shoup(top[w], md->pinv[level][0], md->pinv[level][1], ql),
+                            shoup(th, md->ppinv[level][0], md->ppinv[level][1], ql), ql);
+            r = add_mod(r, dt[w], ql);
+            const u64 t = shoup(r, ms->pinv_l[0], ms->pinv_l[1], ql);
+            neg[w] = t > (ql - 1) / 2;
+            mag[w] = neg[w] ? ql - t : t;
+        }
+        for (int i = 0; i < level; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            const u64 q = pi.q;
+            u64 e[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) {
+                u64 h = 0;
+#pragma unroll
+                for (int j = 0; j < MD; j++) {
+                    if (j >= nP) break;
+                    h = add_mod(h, shoup(v[w][j], md->phat[i][j][0], md->phat[i][j][1], q), q);
+                }
+                u64 pt = shoup(mag[w], pi.p_mod, pi.p_modp, q);
+                pt = (neg[w] && pt) ? q - pt : pt;
+                const u64 x = add_mod(shoup(h, md->ppinv[i][0], md->ppinv[i][1], q), pt, q);
+                e[w] = shoup(x, ms->qlinv[i][0], ms->qlinv[i][1], q);
+            }
+            if constexpr (PL > 0) fold_int<PL>(e, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) Eo[(size_t)i * N + w * Q] = e[w];
+        }
+    } else {
+#pragma clang fp contract(off)
+        double v[NV][MD];  // canonical in [0, p_j)
+        double t[NV];
+        const PrimeInfo &pl = pinfo[level];
+        const double ql = pl.qd;
+        // inputs: the special limbs and the top limb of the accumulator, the
+        // top limb of d (the last PL inverse stages applied here when PL > 0)
+        double top[NV], dt[NV];
+#pragma unroll
+        for (int j = 0; j < MD; j++) {
+            if (j >= nP) break;
+            const PrimeInfo &pj = pinfo[nQ + j];
+            double x[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) x[w] = f_load(A[(size_t)(nl + j) * N + w * Q]);
+            if constexpr (PL > 0) unfold_fp<PL, false>(x, pj);  // |x| < 1.5 q: fine for the product
+#pragma unroll
+            for (int w = 0; w < NV; w++) v[w][j] = f_canon(f_mulmod(x[w], fpair(md->vfac[j]), pj.qd), pj.qd, pj.qinv);
+        }
+#pragma unroll
+        for (int w = 0; w < NV; w++) {
+            top[w] = f_load(A[(size_t)level * N + w * Q]);
+            dt[w] = f_load(D[w * Q]);
+        }
+        if constexpr (PL > 0) {  // |.| < 1.5 q: they enter r below through a product and a sum
+            unfold_fp<PL, false>(top, pl);
+            unfold_fp<PL, false>(dt, pl);
+        }
+#pragma unroll
+        for (int w = 0; w < NV; w++) {
+            double th = 0.0;
+#pragma unroll
+            for (int j = 0; j < MD; j++) {
+                if (j >= nP) break;
+                th += f_mulmod(v[w][j], fpair(md->phat[level][j]), ql);
+                if ((j & 7) == 7) th = f_reduce(th, ql, pl.qinv);
+            }
+            th = f_reduce(th, ql, pl.qinv);
+            double r = f_mulmod(top[w], fpair(md->pinv[level]), ql) - f_mulmod(th, fpair(md->ppinv[level]), ql) +
+                       dt[w];
+            // the exact centred lift: it enters every other modulus as an integer
+            t[w] = f_centre(f_mulmod(r, fpair(ms->pinv_l), ql), ql, pl.qinv);
+        }
+        // E_i = (sum_j v_j Phat_j p P^-1 + p t) q_l^-1 with the constants folded
+        for (int i = 0; i < level; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            const double q = pi.qd;
+            double e[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) {
+                e[w] = f_mulmod(t[w], fpair(ms->rk2[i]), q);
+#pragma unroll
+                for (int j = 0; j < MD; j++) {
+                    if (j >= nP) break;
+                    e[w] += f_mulmod(v[w][j], fpair(ms->rk1[i][j]), q);
+                    if ((j & 7) == 6) e[w] = f_reduce(e[w], q, pi.qinv);
+                }
+                // the fold takes |x| < 1.6 q and returns canonical words
+                e[w] = PL > 0 ? f_reduce(e[w], q, pi.qinv) : f_canon(e[w], q, pi.qinv);
+            }
+            if constexpr (PL > 0) fold_fp<PL>(e, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) Eo[(size_t)i * N + w * Q] = f_bits(e[w]);
+        }
+    }
+}
+
+// R[ct][c][i] = p t mod q_i, t = [top p^-1]_{q_l} lifted to (-q_l/2, q_l/2]
+template <bool FP, int PL = 0>
+__device__ __forceinline__ void b_ms_fbc(const VBlk &VB, const u64 *__restrict__ top, u64 *__restrict__ R, const ModSwitchPlan *__restrict__ pl,
+                         const PrimeInfo *__restrict__ pinfo, int level, int N) {
+    constexpr int NV = 1 << PL;  // words n + v N/2^PL per thread (PL inverse stages unfolded, PL forward folded)
+    const int n = VB.x * kT + threadIdx.x, cc = VB.z, Q = N >> PL;
+    const u64 *T = top + (size_t)cc * N + n;
+    u64 *Ro = R + (size_t)cc * level * N + n;
+    if constexpr (!FP) {
+        const u64 ql = pl->ql;
+        u64 mag[NV], x[NV];
+        bool neg[NV];
+#pragma unroll
+        for (int w = 0; w < NV; w++) x[w] = T[w * Q];
+        if constexpr (PL > 0) unfold_int<PL>(x, pinfo[level]);
+#pragma unroll
+        for (int w = 0; w < NV; w++) {
+            const u64 t = shoup(x[w], pl->pinv_l[0], pl->pinv_l[1], ql);
+            neg[w] = t > (ql - 1) / 2;
+            mag[w] = neg[w] ? ql - t : t;  // |t| < q_l < q_i
+        }
+        for (int i = 0; i < level; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            u64 r[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) {
+                r[w] = shoup(mag[w], pi.p_mod, pi.p_modp, pi.q);
+                r[w] = (neg[w] && r[w]) ? pi.q - r[w] : r[w];
+            }
+            if constexpr (PL > 0) fold_int<PL>(r, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) Ro[(size_t)i * N + w * Q] = r[w];
+        }
+    } else {
+        const PrimeInfo &pq = pinfo[level];
+        double t[NV];
+#pragma unroll
+        for (int w = 0; w < NV; w++) t[w] = f_load(T[w * Q]);
+        if constexpr (PL > 0) unfold_fp<PL, false>(t, pq);  // |t| < 1.5 q: fine for the product
+#pragma unroll
+        for (int w = 0; w < NV; w++) t[w] = f_centre(f_mulmod(t[w], fpair(pl->pinv_l), pq.qd), pq.qd, pq.qinv);
+        for (int i = 0; i < level; i++) {
+            const PrimeInfo &pi = pinfo[i];
+            double r[NV];
+#pragma unroll
+            for (int w = 0; w < NV; w++) {
+                r[w] = f_mulmod(t[w], fpair(pi.p_f), pi.qd);  // |r| < 0.65 q
+                if constexpr (PL == 0) r[w] = f_canon(r[w], pi.qd, pi.qinv);
+            }
+            if constexpr (PL > 0) fold_fp<PL>(r, pi);
+#pragma unroll
+            for (int w = 0; w < NV; w++) Ro[(size_t)i * N + w * Q] = f_bits(r[w]);
+        }
+    }
+}
+
+// out[ct][c][i] = (in - R) q_l^-1, i < level
+__device__ __forceinline__ void b_ms_combine(const VBlk &VB, const u64 *__restrict__ in, const u64 *__restrict__ R, u64 *__restrict__ out,
+                             const ModSwitchPlan *__restrict__ pl, const PrimeInfo *__restrict__ pinfo, int level,
+                             int N) {
+    const int n = VB.x * kT + threadIdx.x, i = VB.y, ct = VB.z;
+    const u64 q = pinfo[i].q;
+    for (int c = 0; c < 2; c++) {
+        u64 x = in[(((size_t)ct * 2 + c) * (level + 1) + i) * N + n];
+        u64 r = R[(((size_t)ct * 2 + c) * level + i) * N + n];
+        out[(((size_t)ct * 2 + c) * level + i) * N + n] = shoup(sub_mod(x, r, q), pl->qlinv[i][0], pl->qlinv[i][1], q);
+    }
+}
+
+// Component c of ciphertext ct (blockIdx.z = 2 ct + c): babies are read at
+// ciphertext ct; outputs go to ciphertext ct0 + ct of a batch of `count` per
+// block.
+template <bool FP>
+__device__ __forceinline__ void b_lincomb(const VBlk &VB, const BabyArg &ba, const u64 *__restrict__ coef, u64 *__restrict__ out, int nbaby, int nblk,
+                          int count, int ct0, int nl, const PrimeInfo *__restrict__ pinfo, int N) {
+    const int n = VB.x * kT + threadIdx.x, i = VB.y, ct = VB.z >> 1;
+    const PrimeInfo &pi = pinfo[i];
+    const u64 q = pi.q;
+    const size_t L = (size_t)nl * N;
+    {
+        const int c = VB.z & 1;
+        if constexpr (!FP) {
+            u64 v[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                if (k >= nbaby) break;
+                const size_t Lk = (size_t)ba.nlb[k] * N;
+                v[k] = ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n];
+            }
+            for (int t = 0; t < nblk; t++) {
+                u64 acc = 0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    if (k >= nbaby) break;
+                    const u64 *w = coef + (((size_t)t * nbaby + k) * nl + i) * 2;
+                    acc = add_mod(acc, shoup(v[k], w[0], w[1], q), q);
+                }
+                out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] = acc;
+            }
+        } else {
+#pragma clang fp contract(off)
+            const double *cf = reinterpret_cast<const double *>(coef);
+            double hi[16], lo[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                if (k >= nbaby) break;
+                const size_t Lk = (size_t)ba.nlb[k] * N;
+                const double v = f_load(ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n]);
+                hi[k] = __builtin_floor(v * 0x1p-25);
+                lo[k] = __builtin_fma(-hi[k], 0x1p25, v);
+            }
+            const FPair p25 = fpair(pi.two25_f);
+            for (int t = 0; t < nblk; t++) {
+                double sh = 0.0, sl = 0.0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    if (k >= nbaby) break;
+                    const double w = cf[t * nbaby + k];
+                    sh = __builtin_fma(w, hi[k], sh);
+                    sl = __builtin_fma(w, lo[k], sl);
+                }
+                out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] =
+                    f_bits(f_canon(f_mulmod(sh, p25, pi.qd) + sl, pi.qd, pi.qinv));
+            }
+        }
+    }
+}
+
+// Wide linear combinations with small integer weights (fp64 arithmetic):
+// out[k] = sum_{m < M} W[k][m] in[m] (+ c0[k] on component 0) for k < K.
+// in holds M blocks of `count` ciphertexts [count][2][nl][N] back to back
+// (block stride count 2 nl N words), out K blocks the same way.  W is
+// [KT KB][M] doubles (rows past K zero), |W| <= 2^8; c0 is [KT KB] doubles.
+// Each input word v < 2^50 is split v = h 2^25 + l; the sums of W h and of
+// W l stay below M 2^8 2^25 <= 2^42 (exact in fp64), and the result is
+// (sum W h)(2^25 mod q) + sum W l (+ c0), reduced once.  Grid: x = KT N/256
+// with the k-tile fastest (the tiles that read the same input words run back
+// to back and find them in the cache), y = limb, z = 2 ct + component.
+template <int KB>
+__device__ __forceinline__ void b_lincomb_wide(const VBlk &VB, const u64 *__restrict__ in, u64 *__restrict__ out,
+                                               const double *__restrict__ W, const double *__restrict__ c0, int M,
+                                               int K, int KT, int count, int nl,
+                                               const PrimeInfo *__restrict__ pinfo, int N) {
+#pragma clang fp contract(off)
+    const int kt = VB.x % KT, n = (VB.x / KT) * kT + threadIdx.x, i = VB.y, cc = VB.z;
+    const size_t blk = (size_t)count * 2 * nl * N;
+    const size_t off = (size_t)cc * nl * N + (size_t)i * N + n;
+    double sh[KB], sl[KB];
+#pragma unroll
+    for (int kk = 0; kk < KB; kk++) sh[kk] = sl[kk] = 0.0;
+    const double *w = W + (size_t)kt * KB * M;
+    for (int m = 0; m < M; m++) {
+        const double v = f_load(in[(size_t)m * blk + off]);
+        const double h = __builtin_floor(v * 0x1p-25), l = __builtin_fma(-h, 0x1p25, v);
+#pragma unroll
+        for (int kk = 0; kk < KB; kk++) {
+            const double wk = w[(size_t)kk * M + m];
+            sh[kk] = __builtin_fma(wk, h, sh[kk]);
+            sl[kk] = __builtin_fma(wk, l, sl[kk]);
+        }
+    }
+    const PrimeInfo &pi = pinfo[i];
+    const FPair p25 = fpair(pi.two25_f);
+    const bool comp0 = (cc & 1) == 0;
+#pragma unroll
+    for (int kk = 0; kk < KB; kk++) {
+        const int k = kt * KB + kk;
+        if (k >= K) break;
+        double r = f_mulmod(sh[kk], p25, pi.qd) + sl[kk];
+        if (comp0) r += c0[k];
+        out[(size_t)k * blk + off] = f_bits(f_canon(r, pi.qd, pi.qinv));
+    }
+}
+
+}  // namespace
+
+}  // namespace bc

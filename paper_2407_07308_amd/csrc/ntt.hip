@@ -19,626 +19,18 @@
 // is a policy: integer (Harvey's lazy butterflies with Shoup products) for
 // any prime, or fp64 for primes below 2^50 (see FpA).
 
-#include <algorithm>
-
-#include "bc_internal.h"
+#include "ntt_dev.h"
+#include "persist.h"
 
 namespace bc {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kLineWords = kThreads * 16;  // words of one workgroup (32 KiB): 16 per thread
-
-// Columns per workgroup of pass A (N2 >= N1 always, so this never exceeds N2).
-constexpr int cols_per_block(int L1) {
-    return (kLineWords >> L1) < (1 << L1) ? (kLineWords >> L1) : (1 << L1);
-}
-
-// ------------------------------------------------------------ arithmetic
-// The transforms are written once over an arithmetic policy A:
-//   A::V                the register type of a word inside a transform
-//   load(u64) / store() canonical word in [0, q) <-> register value
-//   raw(V) / unraw(u64) register value <-> its 64-bit pattern, for LDS and
-//                       for the intermediate between two passes
-//   fw(k) / iw(k)       forward / inverse twiddle of table index k
-//   ct, gs              one butterfly; gs_last folds N^-1 into the final one
-//
-// IntA: Harvey's lazy butterflies on u64 with Shoup products (any q < 2^62):
-// values in [0, 4q) forward, [0, 2q) inverse.
-//
-// FpA (every prime below 2^50): words are integers held in doubles, where
-// the products run at the full fp64 rate (f_mulmod and f_reduce, exact).
-// Values are reduced (prep) at the start of every register chunk (at most
-// five stages) except one loaded from canonical words.  Forward butterflies
-// are lazy, X +- y w mod q: a stage adds at most q (1/2 + B 2^-52) to the bound
-// B, so five stages from B = q stay below 7.2 q.  Inverse butterflies reduce
-// the sum on the chunk's odd stages, keeping values below 4 q and sums and
-// differences below 6 q.  Everything stays below 2^53 (= 8 q for q < 2^50):
-// no step rounds.
-struct IntA {
-    using V = u64;
-    struct T {
-        u64 w, wp;
-    };
-    const u64 *W, *Wp, *Wi, *Wip;
-    u64 q, q2, ninv, ninvp, ninvw1, ninvw1p;
-    __device__ IntA(const void *tw, const PrimeInfo &pi, int prime, int N) {
-        const u64 *b = static_cast<const u64 *>(tw) + (size_t)prime * 4 * N;
-        W = b;
-        Wp = b + N;
-        Wi = b + 2 * N;
-        Wip = b + 3 * N;
-        q = pi.q;
-        q2 = 2 * q;
-        ninv = pi.ninv;
-        ninvp = pi.ninvp;
-        ninvw1 = pi.ninvw1;
-        ninvw1p = pi.ninvw1p;
-    }
-    __device__ T fw(int k) const { return {W[k], Wp[k]}; }
-    __device__ T iw(int k) const { return {Wi[k], Wip[k]}; }
-    __device__ V load(u64 x) const { return x; }
-    __device__ u64 store(V x) const {
-        x = x >= q2 ? x - q2 : x;
-        return x >= q ? x - q : x;
-    }
-    __device__ static u64 raw(V x) { return x; }
-    __device__ static V unraw(u64 x) { return x; }
-    __device__ V prep(V x) const { return x; }
-    __device__ void ct(V &X, V &Y, T t) const {
-        u64 x = X >= q2 ? X - q2 : X;
-        u64 p = shoup_lazy(Y, t.w, t.wp, q);
-        X = x + p;
-        Y = x - p + q2;
-    }
-    __device__ void gs(V &X, V &Y, T t, bool) const {
-        u64 u = X + Y, d = X - Y + q2;
-        X = u >= q2 ? u - q2 : u;
-        Y = shoup_lazy(d, t.w, t.wp, q);
-    }
-    __device__ void gs_last(V &X, V &Y) const {
-        u64 u = X + Y, d = X - Y + q2;
-        X = shoup_lazy(u, ninv, ninvp, q);
-        Y = shoup_lazy(d, ninvw1, ninvw1p, q);
-    }
-    __device__ static T pair(const u64 *p) { return {p[0], p[1]}; }
-    // d w0 + a w1 - e and (d - e) w0, canonical words in and out
-    __device__ u64 combine(u64 d, u64 a, u64 e, T w0, T w1) const {
-        return sub_mod(add_mod(shoup(d, w0.w, w0.wp, q), shoup(a, w1.w, w1.wp, q), q), e, q);
-    }
-    __device__ u64 switch_(u64 d, u64 e, T w0) const { return shoup(sub_mod(d, e, q), w0.w, w0.wp, q); }
-};
-
-struct FpA {
-    using V = double;
-    struct T {
-        double w, wq;
-    };
-    const double *W, *Wq, *Wi, *Wiq;
-    double q, u, ninv, ninvq, ninvw1, ninvw1q;
-    __device__ FpA(const void *tw, const PrimeInfo &pi, int prime, int N) {
-        const double *b = static_cast<const double *>(tw) + (size_t)prime * 4 * N;
-        W = b;
-        Wq = b + N;
-        Wi = b + 2 * N;
-        Wiq = b + 3 * N;
-        q = pi.qd;
-        u = pi.qinv;
-        ninv = pi.ninv_d;
-        ninvq = pi.ninv_q;
-        ninvw1 = pi.ninvw1_d;
-        ninvw1q = pi.ninvw1_q;
-    }
-    __device__ T fw(int k) const { return {W[k], Wq[k]}; }
-    __device__ T iw(int k) const { return {Wi[k], Wiq[k]}; }
-    __device__ double mulmod(double y, double w, double wq) const { return f_mulmod(y, FPair{w, wq}, q); }
-    __device__ double reduce(double x) const { return f_reduce(x, q, u); }
-    __device__ V load(u64 x) const { return f_load(x); }
-    __device__ u64 store(V x) const { return f_bits(f_canon(x, q, u)); }
-    __device__ static u64 raw(V x) { return (u64)__double_as_longlong(x); }
-    __device__ static V unraw(u64 x) { return __longlong_as_double((long long)x); }
-    __device__ V prep(V x) const { return reduce(x); }
-    __device__ void ct(V &X, V &Y, T t) const {
-#pragma clang fp contract(off)
-        double x = X, p = mulmod(Y, t.w, t.wq);
-        X = x + p;
-        Y = x - p;
-    }
-    __device__ void gs(V &X, V &Y, T t, bool red) const {
-#pragma clang fp contract(off)
-        double s = X + Y, d = X - Y;
-        X = red ? reduce(s) : s;
-        Y = mulmod(d, t.w, t.wq);
-    }
-    __device__ void gs_last(V &X, V &Y) const {
-#pragma clang fp contract(off)
-        double s = X + Y, d = X - Y;
-        X = mulmod(s, ninv, ninvq);
-        Y = mulmod(d, ninvw1, ninvw1q);
-    }
-    __device__ static T pair(const u64 *p) {
-        return {__longlong_as_double((long long)p[0]), __longlong_as_double((long long)p[1])};
-    }
-    __device__ u64 combine(u64 d, u64 a, u64 e, T w0, T w1) const {
-#pragma clang fp contract(off)
-        double r = mulmod(f_load(d), w0.w, w0.wq) + mulmod(f_load(a), w1.w, w1.wq) - f_load(e);
-        return store(r);
-    }
-    __device__ u64 switch_(u64 d, u64 e, T w0) const {
-#pragma clang fp contract(off)
-        return store(mulmod(f_load(d) - f_load(e), w0.w, w0.wq));
-    }
-};
-
-// Jobs are ordered limb-major: consecutive workgroups transform the same limb
-// of consecutive ciphertexts, so they share one prime's twiddle table and the
-// set of tables live in each XCD's L2 at any time stays small.
-__device__ __forceinline__ u64 *limb_ptr(const LimbSet &ls, int job, int N, int &prime) {
-    int k = job / ls.npoly, poly = job - k * ls.npoly;
-    prime = ls.prime[k];
-    return ls.base + (size_t)poly * ls.poly_stride + (size_t)ls.off[k] * N;
-}
-// where the job's words are read (its output limb when in place)
-__device__ __forceinline__ const u64 *limb_src(const LimbSet &ls, int job, int N) {
-    int k = job / ls.npoly, poly = job - k * ls.npoly;
-    if (!ls.ibase) return ls.base + (size_t)poly * ls.poly_stride + (size_t)ls.off[k] * N;
-    return ls.ibase + (size_t)poly * ls.ipoly_stride + (size_t)ls.ioff[k] * N;
-}
-
-// Forward chunk: stages on line bits [blo, blo + C) (high to low) of the
-// 2^C words v[k] at line positions X0 + (k << blo); `fresh`: the words are
-// canonical (just loaded), else they are first brought back into range.  For the stage on bit b
-// the twiddle index is tbase(b) + (k >> (C - s)), s = (blo + C - 1) - b, with
-// tbase(b) = mb(b) + G * 2^(L-1-b) + (X0 >> (b + 1)).
-// With NPRE > 0 the twiddles of the first NPRE stages come from pre (stage s,
-// group blk at pre[2^s - 1 + blk]), loaded earlier by fwd_twiddles.
-template <int C, class A, int NPRE = 0>
-__device__ __forceinline__ void fwd_chunk(typename A::V *v, const A &ar, int L, int blo, int X0, int G, int logM,
-                                          bool fresh, const typename A::T *pre = nullptr) {
-    if (!fresh) {
-#pragma unroll
-        for (int k = 0; k < (1 << C); k++) v[k] = ar.prep(v[k]);
-    }
-#pragma unroll
-    for (int s = 0; s < C; s++) {
-        const int b = blo + C - 1 - s;
-        const int half = 1 << (C - 1 - s);
-        const int tb = (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
-#pragma unroll
-        for (int blk = 0; blk < (1 << s); blk++) {
-            const typename A::T w = s < NPRE ? pre[(1 << s) - 1 + blk] : ar.fw(tb + blk);
-#pragma unroll
-            for (int j = 0; j < half; j++) ar.ct(v[blk * 2 * half + j], v[blk * 2 * half + j + half], w);
-        }
-    }
-}
-
-// Loads the twiddles of the first NPRE stages of fwd_chunk<C> (same indices)
-// into pre, so that a caller can issue them before an LDS exchange, whose
-// barriers wait only for LDS traffic, and find them arrived afterwards.
-template <int C, int NPRE, class A>
-__device__ __forceinline__ void fwd_twiddles(typename A::T *pre, const A &ar, int L, int blo, int X0, int G,
-                                             int logM) {
-#pragma unroll
-    for (int s = 0; s < NPRE; s++) {
-        const int b = blo + C - 1 - s;
-        const int tb = (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
-#pragma unroll
-        for (int blk = 0; blk < (1 << s); blk++) pre[(1 << s) - 1 + blk] = ar.fw(tb + blk);
-    }
-}
-
-// Inverse chunk: stages on bits blo .. blo + C - 1 (low to high).  With
-// `scale`, the last stage (the transform's final one, m = 1) folds in N^-1.
-template <int C, class A>
-__device__ __forceinline__ void inv_chunk(typename A::V *v, const A &ar, int L, int blo, int X0, int G, int logM,
-                                          bool scale, bool fresh) {
-    if (!fresh) {
-#pragma unroll
-        for (int k = 0; k < (1 << C); k++) v[k] = ar.prep(v[k]);
-    }
-#pragma unroll
-    for (int s = 0; s < C; s++) {
-        const int b = blo + s;
-        const int half = 1 << s;
-        const int tb = (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
-#pragma unroll
-        for (int blk = 0; blk < (1 << (C - 1 - s)); blk++) {
-            if (scale && s == C - 1) {
-#pragma unroll
-                for (int j = 0; j < half; j++) ar.gs_last(v[blk * 2 * half + j], v[blk * 2 * half + j + half]);
-            } else {
-                const typename A::T w = ar.iw(tb + blk);
-#pragma unroll
-                for (int j = 0; j < half; j++) ar.gs(v[blk * 2 * half + j], v[blk * 2 * half + j + half], w, s & 1);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------- pass A
-// Columns: line = one column of N1 = 2^L1 words (stride N2 in memory), CW
-// columns per workgroup.  Twiddle index of the stage on bit b:
-// m = 2^(L1-1-b), group = row >> (b+1)  (so logM = L1, G = 0).  Forward:
-// canonical words in, raw register values out (read by pass B); inverse: raw
-// in, canonical out.
-template <int L1, bool INV, class A>
-__global__ void __launch_bounds__(kThreads) ntt_cols(LimbSet ls, const void *__restrict__ tw,
-                                                     const PrimeInfo *__restrict__ pinfo, int logN) {
-    using V = typename A::V;
-    constexpr int N1 = 1 << L1;
-    constexpr int CW = cols_per_block(L1);
-    constexpr int CHI = (L1 + 1) / 2, CLO = L1 - CHI;  // chunk on the high / low row bits
-    __shared__ u64 s[N1 * CW];
-    const int N = 1 << logN, N2 = N >> L1;
-    const int colblocks = N2 / CW;
-    const int job = blockIdx.x / colblocks, c0 = (blockIdx.x - job * colblocks) * CW;
-    int prime;
-    u64 *a = limb_ptr(ls, job, N, prime) + c0;
-    const u64 *ain = limb_src(ls, job, N) + c0;  // forward: the transform's input
-    const A ar(tw, pinfo[prime], prime, N);
-    const int tid = threadIdx.x;
-    V v[16];
-
-    // Both chunks touch HBM directly: for a fixed k, consecutive threads take
-    // consecutive columns of one row, so every access is coalesced; LDS only
-    // carries the exchange between the chunks.
-    if (!INV) {
-        // high row bits first: words at rows X0 + (k << CLO)
-        for (int g = tid; g < (1 << CLO) * CW; g += kThreads) {
-            const int col = g % CW, X0 = g / CW;
-#pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) v[k] = ar.load(ain[(size_t)(X0 + (k << CLO)) * N2 + col]);
-            fwd_chunk<CHI>(v, ar, L1, CLO, X0, 0, L1, true);
-#pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) s[(X0 + (k << CLO)) * CW + col] = A::raw(v[k]);
-        }
-        __syncthreads();
-        for (int g = tid; g < (1 << CHI) * CW; g += kThreads) {
-            const int col = g % CW, X0 = (g / CW) << CLO;
-#pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) v[k] = A::unraw(s[(X0 + k) * CW + col]);
-            fwd_chunk<CLO>(v, ar, L1, 0, X0, 0, L1, false);
-#pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) a[(size_t)(X0 + k) * N2 + col] = A::raw(v[k]);
-        }
-    } else {
-        // low row bits first: words at rows X0 + k
-        for (int g = tid; g < (1 << CHI) * CW; g += kThreads) {
-            const int col = g % CW, X0 = (g / CW) << CLO;
-#pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) v[k] = A::unraw(a[(size_t)(X0 + k) * N2 + col]);
-            inv_chunk<CLO>(v, ar, L1, 0, X0, 0, L1, false, false);
-#pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) s[(X0 + k) * CW + col] = A::raw(v[k]);
-        }
-        __syncthreads();
-        for (int g = tid; g < (1 << CLO) * CW; g += kThreads) {
-            const int col = g % CW, X0 = g / CW;
-#pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) v[k] = A::unraw(s[(X0 + (k << CLO)) * CW + col]);
-            inv_chunk<CHI>(v, ar, L1, CLO, X0, 0, L1, true, false);
-#pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) a[(size_t)(X0 + (k << CLO)) * N2 + col] = ar.store(v[k]);
-        }
-    }
-}
-
-// ---------------------------------------------------------------- pass B
-// Rows: line = one row of N2 = 2^L2 contiguous words, R rows per workgroup.
-// Twiddle index of the stage on bit b in row u: m = N / 2^(b+1),
-// group = u * 2^(L2-1-b) + (x >> (b+1))  (logM = logN, G = u).
-// LDS rows are padded by one word per 16 so both chunks' accesses avoid
-// bank conflicts.  Forward: raw in, canonical out; inverse: canonical in, raw
-// out.
-__device__ __forceinline__ int padx(int x) { return x + (x >> 4); }
-
-template <int L2, bool INV, class A>
-__global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const void *__restrict__ tw,
-                                                     const PrimeInfo *__restrict__ pinfo, int logN) {
-    using V = typename A::V;
-    constexpr int N2 = 1 << L2;
-    constexpr int RS = N2 + N2 / 16;  // padded row stride in LDS
-    constexpr int CHI = (L2 + 1) / 2, CLO = L2 - CHI;
-    constexpr int RMAX = kLineWords / N2;
-    __shared__ u64 s[RMAX * RS];
-    const int N = 1 << logN, N1 = N >> L2;
-    const int R = min(RMAX, N1);
-    const int rowblocks = N1 / R;
-    const int job = blockIdx.x / rowblocks, u0 = (blockIdx.x - job * rowblocks) * R;
-    int prime;
-    u64 *a = limb_ptr(ls, job, N, prime) + (size_t)u0 * N2;
-    const u64 *ain = limb_src(ls, job, N) + (size_t)u0 * N2;  // inverse: the transform's input
-    const A ar(tw, pinfo[prime], prime, N);
-    const int tid = threadIdx.x;
-    V v[16];
-
-    if (!INV) {
-        for (int g = tid; g < R << CLO; g += kThreads) {
-            const int rr = g >> CLO, X0 = g & ((1 << CLO) - 1);
-            const u64 *row = a + (size_t)rr * N2;
-#pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) v[k] = A::unraw(row[X0 + (k << CLO)]);
-            fwd_chunk<CHI>(v, ar, L2, CLO, X0, u0 + rr, logN, false);
-#pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) s[rr * RS + padx(X0 + (k << CLO))] = A::raw(v[k]);
-        }
-        __syncthreads();
-        for (int g = tid; g < R << CHI; g += kThreads) {
-            const int rr = g >> CHI, X0 = (g & ((1 << CHI) - 1)) << CLO;
-#pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) v[k] = A::unraw(s[rr * RS + padx(X0 + k)]);
-            fwd_chunk<CLO>(v, ar, L2, 0, X0, u0 + rr, logN, false);
-#pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) s[rr * RS + padx(X0 + k)] = ar.store(v[k]);
-        }
-        __syncthreads();
-        for (int idx = tid; idx < R * N2; idx += kThreads) {
-            int rr = idx >> L2, x = idx & (N2 - 1);
-            a[idx] = s[rr * RS + padx(x)];
-        }
-    } else {
-        for (int idx = tid; idx < R * N2; idx += kThreads) {
-            int rr = idx >> L2, x = idx & (N2 - 1);
-            s[rr * RS + padx(x)] = ain[idx];
-        }
-        __syncthreads();
-        for (int g = tid; g < R << CHI; g += kThreads) {
-            const int rr = g >> CHI, X0 = (g & ((1 << CHI) - 1)) << CLO;
-#pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) v[k] = ar.load(s[rr * RS + padx(X0 + k)]);
-            inv_chunk<CLO>(v, ar, L2, 0, X0, u0 + rr, logN, false, true);
-#pragma unroll
-            for (int k = 0; k < (1 << CLO); k++) s[rr * RS + padx(X0 + k)] = A::raw(v[k]);
-        }
-        __syncthreads();
-        for (int g = tid; g < R << CLO; g += kThreads) {
-            const int rr = g >> CLO, X0 = g & ((1 << CLO) - 1);
-#pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) v[k] = A::unraw(s[rr * RS + padx(X0 + (k << CLO))]);
-            inv_chunk<CHI>(v, ar, L2, CLO, X0, u0 + rr, logN, false, false);
-            u64 *row = a + (size_t)rr * N2;
-#pragma unroll
-            for (int k = 0; k < (1 << CHI); k++) row[X0 + (k << CLO)] = A::raw(v[k]);
-        }
-    }
-}
-
-// ------------------------------------------------------------ single pass
-// One workgroup of N/32 threads transforms a whole limb (N = 2^12 .. 2^15):
-// 32 words per thread in registers, three register chunks on the bit ranges
-// [LOGN-5, LOGN), [C3, C3+5) and [0, C3) (C3 = LOGN - 10), two LDS exchanges
-// between them.  Every word crosses HBM once in and once out.  At N = 2^15
-// the 256 KiB limb does not fit in LDS, so each exchange runs in two rounds
-// split on bit 14 of the word index (128 KiB each).
-struct alignas(16) U64x2 {
-    u64 a, b;
-};
-
-constexpr int kSplitWords = 16384;
-
-// LDS slot of word x.  With SPLIT the exchange runs in two rounds on bit BIT
-// of x (removed from the slot index); BIT is chosen so that in both layouts it
-// is a bit of the thread id, i.e. every thread writes and reads in one round.
-// One pad word per 32 keeps the strided accesses conflict-free.  For every
-// access below, x = base(thread) + (k << S) with the bits of k << S disjoint
-// from the base's and aligned so that lds_pos(base + (k << S)) =
-// lds_pos(base) + lds_pos(k << S): the slot is a per-thread base plus a
-// compile-time offset (an immediate of the LDS instruction).
-template <bool SPLIT, int BIT>
-__host__ __device__ constexpr int lds_pos(int x) {
-    int y = SPLIT ? (((x >> (BIT + 1)) << BIT) | (x & ((1 << BIT) - 1))) : x;
-    return y + (y >> 5);
-}
-template <bool SPLIT, int BIT>
-__host__ __device__ constexpr int lds_round(int x) {
-    return SPLIT ? (x >> BIT) & 1 : 0;
-}
-
-// In the last layout lane l of a wave holds words l*32 .. l*32+31 of the
-// wave's 2048-word block, so direct 16-byte accesses would touch 64 cache
-// lines per instruction.  These move a wave's block between registers and HBM
-// through a wave-private LDS tile (16 x 64 words, rows padded to 65) in two
-// halves of 16 registers, every instruction then covering eight whole
-// 128-byte lines: in half r, instruction j, lane m handles words 2p, 2p+1
-// (p = m % 8) of lane s = 8j + m / 8's sixteen.  Needs 1040 LDS words per
-// wave and no workgroup barrier: only the wave touches its tile.
-constexpr int kTileRow = 65;
-
-// Epilogue of a forward transform of one E limb (NttCombine): the limb's d,
-// acc and out words and its constants.
-template <class A>
-struct McLimb {
-    const u64 *d, *acc;
-    u64 *out;
-    typename A::T w0, w1;
-};
-
-template <class A, int EPI = 0>
-__device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, const A &ar, u64 *tile, int lane,
-                                            const McLimb<A> *mc = nullptr, int boff = 0) {
-#pragma unroll
-    for (int r = 0; r < 2; r++) {
-#pragma unroll
-        for (int i = 0; i < 16; i++) tile[i * kTileRow + lane] = ar.store(v[16 * r + i]);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const int p = lane & 7;
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-            const int sl = 8 * j + (lane >> 3), wi = sl * 32 + 16 * r + 2 * p;
-            U64x2 w{tile[(2 * p) * kTileRow + sl], tile[(2 * p + 1) * kTileRow + sl]};
-            if constexpr (EPI == kNttRelinMs) {
-                const int x = boff + wi;  // word of the limb
-                const U64x2 dv = *reinterpret_cast<const U64x2 *>(mc->d + x);
-                const U64x2 av = *reinterpret_cast<const U64x2 *>(mc->acc + x);
-                *reinterpret_cast<U64x2 *>(mc->out + x) =
-                    U64x2{ar.combine(dv.a, av.a, w.a, mc->w0, mc->w1), ar.combine(dv.b, av.b, w.b, mc->w0, mc->w1)};
-            } else if constexpr (EPI == kNttSwitch) {
-                const int x = boff + wi;
-                const U64x2 dv = *reinterpret_cast<const U64x2 *>(mc->d + x);
-                *reinterpret_cast<U64x2 *>(mc->out + x) = U64x2{ar.switch_(dv.a, w.a, mc->w0), ar.switch_(dv.b, w.b, mc->w0)};
-            } else {
-                *reinterpret_cast<U64x2 *>(blk + wi) = w;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    }
-}
-
-template <class A>
-__device__ __forceinline__ void load_block(const u64 *blk, typename A::V *v, const A &ar, u64 *tile, int lane) {
-#pragma unroll
-    for (int r = 0; r < 2; r++) {
-        const int p = lane & 7;
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-            const int sl = 8 * j + (lane >> 3);
-            U64x2 w = *reinterpret_cast<const U64x2 *>(blk + sl * 32 + 16 * r + 2 * p);
-            tile[(2 * p) * kTileRow + sl] = w.a;
-            tile[(2 * p + 1) * kTileRow + sl] = w.b;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-        for (int i = 0; i < 16; i++) v[16 * r + i] = ar.load(tile[i * kTileRow + lane]);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    }
-}
-
-// PL > 0: the block transforms one of 2^PL parts of a limb of 2^PL N words.
-// Forward: the producer of the words has already applied the first PL
-// stages, and what remains are the stages on bits LOGN-1 .. 0, whose
-// twiddles are those of the full transform's group `hh` (G = hh, logM =
-// LOGN + PL).  Inverse: the stages on bits 0 .. LOGN-1 of the part, without
-// N^-1; the consumer of the words applies the last PL stages.  Parts always
-// exchange in two rounds, so several blocks share a CU.
-template <int LOGN, bool INV, class A, int EPI, int PL = 0>
-__device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__restrict__ tw,
-                                              const PrimeInfo *__restrict__ pinfo, const NttCombine *cb) {
-    using V = typename A::V;
-    constexpr int N = 1 << LOGN, C3 = LOGN - 10;
-    constexpr bool SP = PL > 0 || N > kSplitWords;
-    constexpr int NSPLIT = SP ? 2 : 1;
-    constexpr int NL = N << PL;        // words of the limb
-    constexpr int G3 = 1 << (5 - C3);  // chunk-3 groups per thread
-    constexpr int LW = SP ? N / 2 : N;
-    __shared__ u64 s[LW + LW / 32];
-    const int t = threadIdx.x;
-    const int job = blockIdx.x >> PL, hh = blockIdx.x & ((1 << PL) - 1);
-    constexpr int LOGM = LOGN + PL;
-    int prime;
-    u64 *a = limb_ptr(ls, job, NL, prime) + hh * N;
-    const u64 *ain = limb_src(ls, job, NL) + hh * N;
-    const A ar(tw, pinfo[prime], prime, NL);
-    // word index of register k in each layout
-    const int x1 = t;                                                     // + (k << (LOGN - 5))
-    const int x2 = ((t >> C3) << (C3 + 5)) | (t & ((1 << C3) - 1));       // + (k << C3)
-    const int x3 = t << 5;                                                // + k
-    V v[32];
-
-    // exchange 1-2 splits on bit C3-1 (a bit of t in both layouts), exchange
-    // 2-3 on bit LOGN-1 (t's bit LOGN-6 in both layouts)
-    constexpr int BA = C3 - 1, BB = LOGN - 1;
-    const int ra = lds_round<SP, BA>(x1), rb = lds_round<SP, BB>(x3);
-    const int pa1 = lds_pos<SP, BA>(x1), pa2 = lds_pos<SP, BA>(x2);  // exchange 1-2 bases
-    const int pb2 = lds_pos<SP, BB>(x2), pb3 = lds_pos<SP, BB>(x3);  // exchange 2-3 bases
-    if (!INV) {
-#pragma unroll
-        for (int k = 0; k < 32; k++) v[k] = ar.load(ain[x1 + (k << (LOGN - 5))]);
-        fwd_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, true);
-        // with an epilogue, the next chunk's first two stages' twiddles travel
-        // during the exchange (timed faster there; the plain transform, with
-        // fewer registers to spare, was timed slower with it)
-        constexpr int NPRE = EPI != 0 ? 2 : 0;
-        typename A::T pre[3];
-        if constexpr (NPRE > 0) fwd_twiddles<5, NPRE>(pre, ar, LOGN, C3, x2, hh, LOGM);
-#pragma unroll
-        for (int r = 0; r < NSPLIT; r++) {
-            if (ra == r) {
-#pragma unroll
-                for (int k = 0; k < 32; k++) s[pa1 + lds_pos<SP, BA>(k << (LOGN - 5))] = A::raw(v[k]);
-            }
-            __syncthreads();
-            if (ra == r) {
-#pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa2 + lds_pos<SP, BA>(k << C3)]);
-            }
-            __syncthreads();
-        }
-        fwd_chunk<5, A, NPRE>(v, ar, LOGN, C3, x2, hh, LOGM, false, pre);
-#pragma unroll
-        for (int r = 0; r < NSPLIT; r++) {
-            if (rb == r) {
-#pragma unroll
-                for (int k = 0; k < 32; k++) s[pb2 + lds_pos<SP, BB>(k << C3)] = A::raw(v[k]);
-            }
-            __syncthreads();
-            if (rb == r) {
-#pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb3 + lds_pos<SP, BB>(k)]);
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), hh, LOGM, false);
-        // the exchange above ended with a barrier: LDS is free for the wave tiles
-        const int wave = t >> 6, lane = t & 63;
-        if constexpr (EPI != 0) {
-            const int k = job / ls.npoly, ct = job - k * ls.npoly;
-            const int cc = ls.off[k] / cb->level, i = ls.off[k] - cc * cb->level;
-            McLimb<A> mc;
-            mc.d = cb->d + (size_t)ct * cb->d_ct_stride + ((size_t)cc * (cb->level + 1) + i) * NL + hh * N;
-            mc.acc = EPI == kNttRelinMs ? cb->acc + (((size_t)ct * 2 + cc) * cb->next + i) * NL + hh * N : nullptr;
-            mc.out = cb->out + (((size_t)ct * 2 + cc) * cb->level + i) * NL + hh * N;
-            mc.w0 = A::pair(cb->w[i]);
-            mc.w1 = A::pair(cb->w[i] + 2);
-            store_block<A, EPI>(nullptr, v, ar, s + wave * 16 * kTileRow, lane, &mc, wave << 11);
-        } else {
-            store_block(a + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
-        }
-    } else {
-        const int wave = t >> 6, lane = t & 63;
-        load_block(ain + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
-        __syncthreads();  // every wave is done with its tile before the exchanges reuse LDS
-#pragma unroll
-        for (int j = 0; j < G3; j++) inv_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), hh, LOGM, false, true);
-#pragma unroll
-        for (int r = 0; r < NSPLIT; r++) {
-            if (rb == r) {
-#pragma unroll
-                for (int k = 0; k < 32; k++) s[pb3 + lds_pos<SP, BB>(k)] = A::raw(v[k]);
-            }
-            __syncthreads();
-            if (rb == r) {
-#pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pb2 + lds_pos<SP, BB>(k << C3)]);
-            }
-            __syncthreads();
-        }
-        inv_chunk<5>(v, ar, LOGN, C3, x2, hh, LOGM, false, false);
-#pragma unroll
-        for (int r = 0; r < NSPLIT; r++) {
-            if (ra == r) {
-#pragma unroll
-                for (int k = 0; k < 32; k++) s[pa2 + lds_pos<SP, BA>(k << C3)] = A::raw(v[k]);
-            }
-            __syncthreads();
-            if (ra == r) {
-#pragma unroll
-                for (int k = 0; k < 32; k++) v[k] = A::unraw(s[pa1 + lds_pos<SP, BA>(k << (LOGN - 5))]);
-            }
-            __syncthreads();
-        }
-        inv_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, PL == 0, false);
-#pragma unroll
-        for (int k = 0; k < 32; k++) a[x1 + (k << (LOGN - 5))] = ar.store(v[k]);
-    }
-}
-
 template <int LOGN, bool INV, class A>
 __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const void *__restrict__ tw,
                                                             const PrimeInfo *__restrict__ pinfo) {
-    ntt_full_body<LOGN, INV, A, 0>(ls, tw, pinfo, nullptr);
+    __shared__ u64 s[ntt_lds_words(LOGN, 0)];
+    ntt_full_body<LOGN, INV, A, 0>(ls, tw, pinfo, nullptr, blockIdx.x, s);
 }
 
 // Parts of 2^(LOGN+PL)-word limbs (2^PL blocks per limb, block 2^PL job +
@@ -648,12 +40,14 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const vo
 template <int LOGN, class A, int PL = 1, bool INV = false>
 __global__ void __launch_bounds__(1 << (LOGN - 5), INV ? 3 : 4) ntt_part(LimbSet ls, const void *__restrict__ tw,
                                                                          const PrimeInfo *__restrict__ pinfo) {
-    ntt_full_body<LOGN, INV, A, 0, PL>(ls, tw, pinfo, nullptr);
+    __shared__ u64 s[ntt_lds_words(LOGN, PL)];
+    ntt_full_body<LOGN, INV, A, 0, PL>(ls, tw, pinfo, nullptr, blockIdx.x, s);
 }
 template <int LOGN, class A, int EPI, int PL = 1>
 __global__ void __launch_bounds__(1 << (LOGN - 5), 4)
     ntt_part_combine(LimbSet ls, const void *__restrict__ tw, const PrimeInfo *__restrict__ pinfo, NttCombine cb) {
-    ntt_full_body<LOGN, false, A, EPI, PL>(ls, tw, pinfo, &cb);
+    __shared__ u64 s[ntt_lds_words(LOGN, PL)];
+    ntt_full_body<LOGN, false, A, EPI, PL>(ls, tw, pinfo, &cb, blockIdx.x, s);
 }
 
 // forward transform of E limbs with an NttCombine step as the store (out
@@ -662,13 +56,30 @@ template <int LOGN, class A, int EPI>
 __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full_combine(LimbSet ls, const void *__restrict__ tw,
                                                                     const PrimeInfo *__restrict__ pinfo,
                                                                     NttCombine cb) {
-    ntt_full_body<LOGN, false, A, EPI>(ls, tw, pinfo, &cb);
+    __shared__ u64 s[ntt_lds_words(LOGN, 0)];
+    ntt_full_body<LOGN, false, A, EPI>(ls, tw, pinfo, &cb, blockIdx.x, s);
 }
 
 // Arithmetic of a context's transforms: fp64 when every prime allows it and
 // it is enabled, else the integer butterflies.
 inline bool use_fp(const bc_ctx *c) { return use_fp64(c); }
 inline const void *tw_of(const bc_ctx *c) { return use_fp(c) ? (const void *)c->twf : (const void *)c->tw; }
+
+// Records a transform stage for the persistent executor: 2^13-word blocks
+// (whole limbs at N = 2^13, halves at 2^14, quarters at 2^15), fp64.
+void record_ntt(const bc_ctx *c, const LimbSet &ls, int kind0, int pl, const NttCombine *cb) {
+    BC_REQUIRE(use_fp(c), BC_ERR_ARG, "the persistent executor needs fp64 arithmetic");
+    BC_REQUIRE(c->logN - pl == 13, BC_ERR_ARG,
+               "the persistent executor runs 2^13-word transform blocks (N = 2^13, or part-limb at 2^14 and 2^15)");
+    BC_REQUIRE(!cb || cb->mode == kNttRelinMs, BC_ERR_ARG, "the persistent executor combines relinearisation only");
+    PaNtt a{};
+    a.ls = ls;
+    a.tw = tw_of(c);
+    a.pinfo = c->pinfo;
+    if (cb) a.cb = *cb;
+    // kinds come in (forward, inverse, combine) triples per pl
+    tl_rec->add(kind0 + 3 * pl, dim3((unsigned)(ls.npoly * ls.nlimb) << pl, 1, 1), a, 1);
+}
 
 template <bool INV, class A>
 bool launch_full_a(int logN, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
@@ -759,9 +170,10 @@ static LimbSet chunk_of(const LimbSet &ls, int p0, int step) {
 // N1 = 2^floor(logN/2) rows, N2 = 2^ceil(logN/2) columns.
 void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (ls.npoly == 0 || ls.nlimb == 0) return;
+    if (tl_rec) return record_ntt(c, ls, kPkNttFwd0, 0, nullptr);
     int logN1 = c->logN / 2, logN2 = c->logN - logN1;
     ProfRec r{};
-    const bool prof = c->prof->on;
+    const bool prof = c->prof->on && !tl_rec;
     if (prof) c->prof->begin(kProfNttFwd, ntt_bytes(c, ls), st, r);
     if (c->ntt_single_pass && launch_full<false>(c->logN, ls, c, st)) {
         if (prof) c->prof->end(r, st);
@@ -781,9 +193,10 @@ void ntt_forward(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
 
 void ntt_inverse(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     if (ls.npoly == 0 || ls.nlimb == 0) return;
+    if (tl_rec) return record_ntt(c, ls, kPkNttInv0, 0, nullptr);
     int logN1 = c->logN / 2, logN2 = c->logN - logN1;
     ProfRec r{};
-    const bool prof = c->prof->on;
+    const bool prof = c->prof->on && !tl_rec;
     if (prof) c->prof->begin(kProfNttInv, ntt_bytes(c, ls), st, r);
     if (c->ntt_single_pass && launch_full<true>(c->logN, ls, c, st)) {
         if (prof) c->prof->end(r, st);
@@ -841,8 +254,9 @@ void ntt_forward_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     const int pl = ntt_parts_log(c);
     if (!pl) throw Error(BC_ERR_ARG, "ntt: part-limb transforms are off for this context");
     if (ls.npoly == 0 || ls.nlimb == 0) return;
+    if (tl_rec) return record_ntt(c, ls, kPkNttFwd0, pl, nullptr);
     ProfRec r{};
-    const bool prof = c->prof->on;
+    const bool prof = c->prof->on && !tl_rec;
     if (prof) c->prof->begin(kProfNttFwdPart, ntt_bytes(c, ls), st, r);
     if (use_fp(c)) launch_parts<FpA>(pl, ls, c, st);
     else launch_parts<IntA>(pl, ls, c, st);
@@ -861,8 +275,9 @@ void ntt_inverse_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
     const int pl = ntt_parts_log(c);
     if (!pl) throw Error(BC_ERR_ARG, "ntt: part-limb transforms are off for this context");
     if (ls.npoly == 0 || ls.nlimb == 0) return;
+    if (tl_rec) return record_ntt(c, ls, kPkNttInv0, pl, nullptr);
     ProfRec r{};
-    const bool prof = c->prof->on;
+    const bool prof = c->prof->on && !tl_rec;
     if (prof) c->prof->begin(kProfNttInvPart, ntt_bytes(c, ls), st, r);
     if (use_fp(c)) launch_parts_inv<FpA>(pl, ls, c, st);
     else launch_parts_inv<IntA>(pl, ls, c, st);
@@ -889,8 +304,9 @@ void ntt_forward_parts_combine(const bc_ctx *c, const LimbSet &ls, const NttComb
     if (!pl) throw Error(BC_ERR_ARG, "ntt: part-limb transforms are off for this context");
     if (cb.mode != kNttRelinMs && cb.mode != kNttSwitch) throw Error(BC_ERR_ARG, "ntt: unknown combine step");
     if (ls.npoly == 0 || ls.nlimb == 0) return;
+    if (tl_rec) return record_ntt(c, ls, kPkNttComb0, pl, &cb);
     ProfRec r{};
-    const bool prof = c->prof->on;
+    const bool prof = c->prof->on && !tl_rec;
     const double per_limb = (cb.mode == kNttRelinMs ? 32.0 : 24.0) * c->N;
     if (prof) c->prof->begin(kProfNttFwdCombine, per_limb * ls.npoly * ls.nlimb, st, r);
     if (use_fp(c)) launch_parts_combine_a<FpA>(pl, ls, cb, c, st);
@@ -903,8 +319,12 @@ bool ntt_forward_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &c
     if (!c->ntt_single_pass || c->logN < 12 || c->logN > 15) return false;
     if (cb.mode != kNttRelinMs && cb.mode != kNttSwitch) throw Error(BC_ERR_ARG, "ntt: unknown combine step");
     if (ls.npoly == 0 || ls.nlimb == 0) return true;
+    if (tl_rec) {
+        record_ntt(c, ls, kPkNttComb0, 0, &cb);
+        return true;
+    }
     ProfRec r{};
-    const bool prof = c->prof->on;
+    const bool prof = c->prof->on && !tl_rec;
     // E read and out written, d (and acc) read
     const double per_limb = (cb.mode == kNttRelinMs ? 32.0 : 24.0) * c->N;
     if (prof) c->prof->begin(kProfNttFwdCombine, per_limb * ls.npoly * ls.nlimb, st, r);

@@ -12,6 +12,7 @@
 // Universal FHE Scheme").
 
 #include "ops.h"
+#include "persist.h"
 
 #include <algorithm>
 #include <atomic>
@@ -230,20 +231,45 @@ void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int co
     Jobs js;
     for (int k = 0; k < 2; k++)
         for (int t = 0; t < c->nP; t++) js.add(k * next + nl + t, c->nQ + t);
-    run_ntt(c, acc, (size_t)2 * next * N, count, js, true, st);
+    // with part-limb transforms the modulus lowering applies the last stages
+    // of the special limbs' inverse transforms and the first stages of TH's
+    // forward ones
+    const int parts = ntt_parts_log(c);
+    if (parts) run_ntt_parts(c, acc, (size_t)2 * next * N, count, js, true, st);
+    else run_ntt(c, acc, (size_t)2 * next * N, count, js, true, st);
     BufP TH = make_buf(c, sizeof(u64) * (size_t)count * 2 * nl * N);
     u64 *th = (u64 *)TH->p;
-    launch_moddown(c, acc, th, count, level, next, st);
-    run_ntt(c, th, (size_t)2 * nl * N, count, all_limbs(2, nl), false, st);
+    launch_moddown(c, acc, th, count, level, next, parts, st);
+    if (parts) run_ntt_parts(c, th, (size_t)2 * nl * N, count, all_limbs(2, nl), false, st);
+    else run_ntt(c, th, (size_t)2 * nl * N, count, all_limbs(2, nl), false, st);
     launch_ks_combine(c, base0, base1, base_stride, acc, th, out, out_stride, count, level, next, st);
     check_hip();
 }
 
 }  // namespace
 
+// Device-to-device copy of `rows` rows of `width` words (row pitches in
+// words): a recorded copy stage under the persistent executor, else a HIP copy.
+static void copy_rows(const u64 *src, u64 *dst, size_t spitch, size_t dpitch, size_t width, size_t rows,
+                      hipStream_t st) {
+    if (tl_rec) {
+        if (rows == 1) spitch = dpitch = width;
+        const size_t nb = (width + kCopyBlockWords - 1) / kCopyBlockWords;
+        BC_REQUIRE(nb < (1u << 30) && rows < (1u << 30), BC_ERR_ARG, "copy too large to record");
+        tl_rec->add(kPkCopy, dim3((unsigned)nb, (unsigned)rows, 1), PaCopy{src, dst, spitch, dpitch, width});
+        return;
+    }
+    if (rows == 1)
+        BC_HIP(hipMemcpyAsync(dst, src, sizeof(u64) * width, hipMemcpyDeviceToDevice, st));
+    else
+        BC_HIP(hipMemcpy2DAsync(dst, sizeof(u64) * dpitch, src, sizeof(u64) * spitch, sizeof(u64) * width, rows,
+                                hipMemcpyDeviceToDevice, st));
+}
+
 void copy_ct(const bc_ctx *c, const CtB &src, const CtB &dst, hipStream_t st) {
     BC_REQUIRE(src.count == dst.count && src.level == dst.level && src.ncomp == dst.ncomp, BC_ERR_ARG,
                "copy: shape mismatch");
+    if (tl_rec) return copy_rows(src.data, dst.data, 0, 0, (size_t)src.count * src.ct_words(c->N), 1, st);
     BC_HIP(hipMemcpyAsync(dst.data, src.data, sizeof(u64) * (size_t)src.count * src.ct_words(c->N),
                           hipMemcpyDeviceToDevice, st));
 }
@@ -318,9 +344,9 @@ void to_level_into(bc_ctx *c, const CtB &x, const CtB &out, hipStream_t st) {
         copy_ct(c, x, out, st);
         return;
     }
-    const size_t limb = sizeof(u64) * c->N;
-    BC_HIP(hipMemcpy2DAsync(out.data, (level + 1) * limb, x.data, (x.level + 1) * limb, (level + 1) * limb,
-                            (size_t)x.count * x.ncomp, hipMemcpyDeviceToDevice, st));
+    const size_t limb = c->N;
+    copy_rows(x.data, out.data, (x.level + 1) * limb, (level + 1) * limb, (level + 1) * limb, (size_t)x.count * x.ncomp,
+              st);
 }
 
 
@@ -351,13 +377,14 @@ int out_level_mul(int la, int lb) {
     return lv > 0 ? lv - 1 : 0;
 }
 
-// Fused-minimum HBM bytes of a multiplication of `count` ciphertexts at
-// level lv (each operand read once, the key read once per ciphertext, the
-// result written once): (4 (l+1) + 2 beta_l (l+1+k) + 2 l') N 8, l' the
-// output's limbs; an addend adds its 2 (l+1) limbs.
+// Fused-minimum HBM bytes of a batched multiplication of `count` ciphertexts
+// at level lv: each operand read once, the result written once (count
+// (4 (l+1) + 2 l') N 8, l' the output's limbs; an addend adds its 2 (l+1)
+// limbs), and the switching key read once for the whole batch
+// (2 beta_l (l+1+k) N 8).
 static double mul_min_bytes(const bc_ctx *c, int count, int lv, bool addend) {
     const double nl = lv + 1, beta = lv / c->alpha + 1, nout = lv > 0 ? lv : 1;
-    return 8.0 * c->N * count * (4 * nl + 2 * beta * (nl + c->nP) + 2 * nout + (addend ? 2 * nl : 0));
+    return 8.0 * c->N * (count * (4 * nl + 2 * nout + (addend ? 2 * nl : 0)) + 2 * beta * (nl + c->nP));
 }
 
 void mul_relin(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const CtB &out, hipStream_t st) {

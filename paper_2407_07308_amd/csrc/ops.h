@@ -72,7 +72,10 @@ u64 galois_for_step(const bc_ctx *c, int step);
 struct CompareResult {
     CtB lt, mx, mn;  // mx, mn: plane-major [ndig * count]
 };
-CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, bool want_mm, hipStream_t st);
+// circuit: BC_CIRCUIT_UNIVARIATE (digits in [0, (p-1)/2], the
+// Paterson-Stockmeyer schedule) or BC_CIRCUIT_BIVARIATE (digits in [0, p-1])
+CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, bool want_mm, hipStream_t st,
+                      int circuit = BC_CIRCUIT_UNIVARIATE);
 // Levels and noise estimates of the outputs of a comparison of inputs at
 // in_level with noise in_noise; BC_ERR_LEVEL when a step of the circuit would
 // exceed its level's noise budget (the circuit is deeper than the chain).
@@ -80,6 +83,7 @@ struct CircuitNoise {
     int lt_level, mm_level;
     double lt_noise, mm_noise;
 };
-void compare_levels(const NoiseModel &m, int in_level, double in_noise, int ndig, bool want_mm, CircuitNoise *out);
+void compare_levels(const NoiseModel &m, int in_level, double in_noise, int ndig, bool want_mm, CircuitNoise *out,
+                    int circuit = BC_CIRCUIT_UNIVARIATE);
 
 }  // namespace bc

@@ -95,6 +95,7 @@ def test_key_shape_context_and_null_errors():
     dev, dk = make(PRM, rot=(1,))
     other, ok = make(PRM, seed=4)
     _, x = enc(dev, dk, 2, 30)
+    L = dev.L
     # no rotation key for step 2
     expect(bc.BC_ERR_KEY, dev.rotate, dk, x, 2)
     # keys of another context
@@ -103,14 +104,17 @@ def test_key_shape_context_and_null_errors():
     # mismatched shapes: count not dividing, output of the wrong level
     _, y3 = enc(dev, dk, 3, 32)
     expect(bc.BC_ERR_ARG, dev.add, x, y3)
-    L = dev.L
     wrong = dev.new_batch(2, x.level, 2)  # a product lands one level lower
     ca, cw = x.ctb(), wrong.ctb()
     rc = L.bc_mul_relin(dev.handle, dk.handle, ctypes.byref(ca), ctypes.byref(ca), ctypes.byref(cw), None)
     assert rc == bc.BC_ERR_ARG and L.bc_last_error()
-    # planes of different levels in one comparison
+    # planes of different levels in one comparison (the C call itself: the
+    # binding would size the output from the first plane's level)
     x1 = dev.mod_switch(x)
-    expect(bc.BC_ERR_ARG, dev.compare_lt, dk, [x, x1], [x, x])
+    lt = dev.new_batch(2, 0, 2)
+    pa, pb, co = bc._ctb_array([x, x1]), bc._ctb_array([x, x]), lt.ctb()
+    assert L.bc_compare_lt(dev.handle, dk.handle, 2, pa, pb, ctypes.byref(co), None) == bc.BC_ERR_ARG
+    assert b"level" in L.bc_last_error()
     # null pointers
     assert L.bc_mul_relin(dev.handle, dk.handle, None, ctypes.byref(ca), ctypes.byref(cw), None) == bc.BC_ERR_ARG
     assert L.bc_mul_relin(None, dk.handle, ctypes.byref(ca), ctypes.byref(ca), ctypes.byref(cw), None) == bc.BC_ERR_ARG

@@ -106,3 +106,34 @@ def test_graph_cache_never_replays_with_freed_keys():
         torch.cuda.synchronize()
         del dk
         gc.collect()
+
+
+def test_handles_can_be_released_in_any_order():
+    """A key set or group released after its context's handle still finds the
+    context (the context lives until its last owner goes), so garbage
+    collection may finalise the Python objects in any order."""
+    import paper_2407_07308_amd as bc
+
+    prm = Params(10, 257, 8, 50, 4, 50, 2)
+    for order in (("ctx", "group", "keys"), ("ctx", "keys", "group"), ("keys", "ctx", "group")):
+        dev = bc.Context.from_params(prm)
+        rnd = synth.keygen_randomness(23, prm.N, prm.nQ, prm.nP, prm.dnum, 0)
+        dk = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
+        vals = synth.slot_values(24, 1, dev.M, 0, prm.p)
+        r = synth.encrypt_randomness(25, 1, prm.N)
+        x = dev.encrypt(dk, vals, r["u"], r["e"])
+        assert np.array_equal(dev.decrypt(dk, dev.mul_relin(dk, x, x)), vals.astype(np.int64) ** 2 % prm.p)
+        grp = bc.Group([dev])
+        L = dev.L
+        objs = {"ctx": (dev, L.bc_ctx_destroy), "group": (grp, L.bc_group_destroy), "keys": (dk, L.bc_keys_destroy)}
+        for name in order:
+            obj, destroy = objs[name]
+            assert destroy(obj.handle) == 0, name
+            obj.handle = None
+    # the library is still usable afterwards
+    dev = bc.Context.from_params(prm)
+    rnd = synth.keygen_randomness(26, prm.N, prm.nQ, prm.nP, prm.dnum, 0)
+    dk = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
+    vals = synth.slot_values(27, 2, dev.M, 0, prm.p)
+    r = synth.encrypt_randomness(28, 2, prm.N)
+    assert np.array_equal(dev.decrypt(dk, dev.encrypt(dk, vals, r["u"], r["e"])), vals)

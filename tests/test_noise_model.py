@@ -135,3 +135,37 @@ def test_workload_chains_fit_and_shallower_ones_are_refused():
         assert isinstance(r, tuple), (name, r)
         assert r[0] <= est(prm, BUDGET, 0)
         assert est_compare(prm, 1, f, nd, mm) == -3, name
+
+
+def test_bivariate_circuit_estimate_against_the_oracle():
+    """The bivariate circuit's estimate (every S power and odd Z power, the
+    wide combinations of g_k and of the final sum) stays above the noise the
+    oracle measures on the same schedule, within a loose slack (its weight
+    bound counts every coefficient as (p-1)/2), and reports the levels the
+    oracle's outputs sit at; on the uint16 chain two base-257 digits fit."""
+    L, bc = lib()
+    prm = Params(10, 257, 11, 50, 4, 50, 4)
+    orc = Oracle(prm)
+    orc.keygen(synth.keygen_randomness(91, prm.N, prm.nQ, prm.nP, prm.dnum, 0))
+    x = synth.slot_values(92, 1, orc.M, 0, 257)[0]
+    y = synth.slot_values(92, 1, orc.M, 0, 257, 1)[0]
+    r = synth.encrypt_randomness(93, 2, prm.N)
+    cx, cy = orc.encrypt(x, r["u"][0], r["e"][0]), orc.encrypt(y, r["u"][1], r["e"][1])
+    lt, _ = oracle.lt_bivariate(CtEvaluator(orc), cx, cy, 257)
+    p = bc.bc_params(prm.logN, prm.p, prm.nQ, prm.bitsQ, prm.nP, prm.bitsP, prm.dnum)
+    f = est(prm, FRESH, prm.nQ - 1)
+    e, lv = ctypes.c_double(), ctypes.c_int32()
+    assert L.bc_noise_compare_circuit(ctypes.byref(p), bc.BC_CIRCUIT_BIVARIATE, prm.nQ - 1, f, 1, ctypes.byref(e),
+                                      None, ctypes.byref(lv), None) == 0
+    assert lv.value == lt.level
+    meas = orc.noise_bits(lt)
+    assert meas <= e.value <= meas + 20.0, (meas, e.value)
+    # two base-257 digits with max/min on the N = 2^15 chain: LT at level 3
+    prm15 = oracle.PARAMS["n15_p257"]
+    p15 = bc.bc_params(prm15.logN, prm15.p, prm15.nQ, prm15.bitsQ, prm15.nP, prm15.bitsP, prm15.dnum)
+    mm, lv2 = ctypes.c_double(), ctypes.c_int32()
+    assert L.bc_noise_compare_circuit(ctypes.byref(p15), bc.BC_CIRCUIT_BIVARIATE, prm15.nQ - 1,
+                                      est(prm15, FRESH, prm15.nQ - 1), 2, ctypes.byref(e), ctypes.byref(mm),
+                                      ctypes.byref(lv), ctypes.byref(lv2)) == 0
+    assert (lv.value, lv2.value) == (3, 2)
+    assert L.bc_noise_compare_circuit(ctypes.byref(p15), 7, 13, 0.0, 1, None, None, None, None) == bc.BC_ERR_ARG
