@@ -378,7 +378,11 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   bc_compare_max_min as ONE launch of the persistent executor (see
  *   BC_GROUP_PERSISTENT), the BC_TUNE_SPLIT_STREAMS slices of the groups as
  *   its lanes; graph mode then runs it eagerly (it is a single launch).
- *   BC_ERR_ARG where the executor cannot run the context (as for groups). */
+ *   BC_ERR_ARG where the executor cannot run the context (as for groups).
+ *   BC_TUNE_MFMA (default 1): the bivariate circuit's linear combinations of
+ *   the S powers (a dense 128 x 256 contraction for p = 257) run on the
+ *   matrix cores as exact split-int8 products; 0 runs them in fp64 on the
+ *   vector units.  Both give the same bytes. */
 enum {
     BC_TUNE_NTT_CHUNK_BYTES = 0,
     BC_TUNE_NTT_SINGLE_PASS = 1,
@@ -387,7 +391,8 @@ enum {
     BC_TUNE_NTT_PARTS = 4,
     BC_TUNE_SPLIT_STREAMS = 5,
     BC_TUNE_TEST_FAIL_ALLOC = 6,
-    BC_TUNE_PERSISTENT = 7
+    BC_TUNE_PERSISTENT = 7,
+    BC_TUNE_MFMA = 8
 };
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);

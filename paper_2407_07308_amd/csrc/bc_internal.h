@@ -27,6 +27,7 @@ constexpr int kMaxMod = 40;    // nQ + nP
 constexpr int kMaxJobs = 160;  // limbs listed in one transform launch
 constexpr int kMaxDigit = 16;  // primes per key-switching digit, and special primes
 constexpr int kFoldDigit = 8;  // the same bound for the kernels that fold transform stages
+constexpr int kWideMfmaK = 128, kWideMfmaM = 256;  // largest outputs / inputs of the matrix-core combination
 
 // ------------------------------------------------------------------ errors
 
@@ -541,6 +542,8 @@ struct bc_ctx {
     // (one device allocation; built on first use)
     double *biv_tab = nullptr;
     int biv_K = 0, biv_M = 0;
+    bool biv_mfma = false;  // the table has the matrix-core copy
+    int mfma = 1;           // BC_TUNE_MFMA: use the matrix-core kernels where they apply
     // owners: the caller's handle, every live key set and every group that
     // lists the context; the last release deletes it (a key set destroyed
     // after its context's handle still finds the context)

@@ -945,6 +945,8 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
         } else if (key == BC_TUNE_TEST_FAIL_ALLOC) {
             std::lock_guard<std::mutex> g(ctx->pool.mu);
             ctx->pool.fail_after = value;
+        } else if (key == BC_TUNE_MFMA) {
+            ctx->mfma = value != 0;
         } else if (key == BC_TUNE_PERSISTENT) {
             BC_REQUIRE(value == 0 || persist_supported(ctx), BC_ERR_ARG,
                        "persistent mode needs N = 2^13..2^15, primes below 2^50 and the default transform schedule");
@@ -965,6 +967,7 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
         else if (key == BC_TUNE_POOL_LIMIT_BYTES) *value = (int64_t)ctx->pool.limit;
         else if (key == BC_TUNE_TEST_FAIL_ALLOC) *value = ctx->pool.fail_after;
         else if (key == BC_TUNE_PERSISTENT) *value = ctx->persistent;
+        else if (key == BC_TUNE_MFMA) *value = ctx->mfma;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }

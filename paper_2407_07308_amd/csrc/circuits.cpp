@@ -190,8 +190,11 @@ struct DevEval {
         const int M = final ? t.K + 1 : t.M, K = final ? 1 : t.K;
         const int cnt = in.count / M;
         V o = alloc_ct(c, K * cnt, in.level, 2);
-        launch_lincomb_wide(c, in.data, o.data, final ? t.Wsum : t.W, final ? t.c0sum : t.c0, M, K, cnt,
-                            in.level + 1, st);
+        if (!final && t.W8)
+            launch_lincomb_wide_mfma(c, in.data, o.data, t.W8, t.c0, t.corr, M, K, cnt, in.level + 1, st);
+        else
+            launch_lincomb_wide(c, in.data, o.data, final ? t.Wsum : t.W, final ? t.c0sum : t.c0, M, K, cnt,
+                                in.level + 1, st);
         BC_HIP(hipGetLastError());
         return o;
     }
@@ -375,6 +378,8 @@ std::vector<int64_t> bivariate_coefficients(u64 p) {
 struct BivTable {
     int K, M;
     const double *W, *c0, *Wsum, *c0sum;
+    const int8_t *W8;  // the g_k weights as int8 [128][256] for the matrix cores (null: p too large)
+    const int *corr;   // their weights equal to 128, listed per row
 };
 // What the noise estimate needs of the same weights: the largest total
 // weight magnitude of one g_k (a bound, (p-1)/2 per weight) and of the sum.
@@ -410,15 +415,38 @@ BivTable bivariate_table(bc_ctx *c) {
         for (int kk = 0; kk < K; kk++) host[nW + kk] = cen(cf[2 * kk + 1]);
         for (int kk = 0; kk < K; kk++) host[nW + KP + kk] = 1.0;
         host[nW + KP + K] = cen((int64_t)(p + 1) / 2);
-        double *d = nullptr;
-        BC_HIP(hipMalloc(&d, sizeof(double) * host.size()));
+        // the matrix-core copy: int8 weights (128 is not one: listed apart)
+        std::vector<int8_t> w8((size_t)kWideMfmaK * kWideMfmaM, 0);
+        std::vector<int> corr(K + 1, 0), cm;
+        if (K <= kWideMfmaK && M <= kWideMfmaM) {
+            for (int kk = 0; kk < K; kk++) {
+                for (int mm = 0; mm < M; mm++) {
+                    const double v = host[(size_t)kk * M + mm];
+                    if (v == 128.0) cm.push_back(mm);
+                    else w8[(size_t)kk * kWideMfmaM + mm] = (int8_t)v;
+                }
+                corr[kk + 1] = (int)cm.size();
+            }
+        }
+        corr.insert(corr.end(), cm.begin(), cm.end());
+        // the int8 rows start on a 256-byte boundary (16-byte operand loads)
+        const size_t bytes_d = (sizeof(double) * host.size() + 255) / 256 * 256;
+        const size_t bytes = bytes_d + w8.size() + sizeof(int) * corr.size();
+        char *d = nullptr;
+        BC_HIP(hipMalloc(&d, bytes));
         BC_HIP(hipMemcpy(d, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice));
-        c->biv_tab = d;
+        BC_HIP(hipMemcpy(d + bytes_d, w8.data(), w8.size(), hipMemcpyHostToDevice));
+        BC_HIP(hipMemcpy(d + bytes_d + w8.size(), corr.data(), sizeof(int) * corr.size(), hipMemcpyHostToDevice));
+        c->biv_tab = (double *)d;
+        c->biv_mfma = K <= kWideMfmaK && M <= kWideMfmaM;
         c->biv_K = K;
         c->biv_M = M;
     }
     const double *d = c->biv_tab;
-    return BivTable{K, M, d, d + nW, d + nW + KP, d + nW + KP + nS};
+    const char *b = (const char *)d + (sizeof(double) * (nW + KP + nS + 1) + 255) / 256 * 256;
+    return BivTable{K, M, d, d + nW, d + nW + KP, d + nW + KP + nS,
+                    c->biv_mfma && c->mfma ? (const int8_t *)b : nullptr,
+                    (const int *)(b + (size_t)kWideMfmaK * kWideMfmaM)};
 }
 
 // The bivariate interpolant of [x < y] on Z = X - Y, S = X + Y (batches of

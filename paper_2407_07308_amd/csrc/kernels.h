@@ -54,6 +54,11 @@ void launch_lincomb(const bc_ctx *c, const u64 *const *babies, const int *nlb, c
 int lincomb_wide_tile(int K);
 void launch_lincomb_wide(const bc_ctx *c, const u64 *in, u64 *out, const double *W, const double *c0, int M, int K,
                          int count, int nl, hipStream_t st);
+// The same on the matrix cores (exact split-int8 products): W8 int8 [128][256]
+// with the weights equal to 128 zeroed and listed in corr (offsets [K + 1],
+// then input indices); M <= 256, K <= 128.
+void launch_lincomb_wide_mfma(const bc_ctx *c, const u64 *in, u64 *out, const int8_t *W8, const double *c0,
+                              const int *corr, int M, int K, int count, int nl, hipStream_t st);
 void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st);
 
 }  // namespace bc

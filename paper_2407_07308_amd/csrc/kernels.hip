@@ -237,6 +237,15 @@ __global__ void k_lincomb_wide(const u64 *__restrict__ in, u64 *__restrict__ out
     b_lincomb_wide<KB>(hw_blk(), in, out, W, c0, M, K, KT, count, nl, pinfo, N);
 }
 
+__global__ void __launch_bounds__(256) k_lincomb_wide_mfma(const u64 *__restrict__ in, u64 *__restrict__ out,
+                                                           const int8_t *__restrict__ W8,
+                                                           const double *__restrict__ c0,
+                                                           const int *__restrict__ corr, int M, int K, int count,
+                                                           int nl, const PrimeInfo *__restrict__ pinfo, int N) {
+    __shared__ __align__(16) unsigned char lds[8 * 32 * kWideRow];
+    b_lincomb_wide_mfma(hw_blk(), in, out, W8, c0, corr, M, K, count, nl, pinfo, N, lds);
+}
+
 inline dim3 grid3(int N, int y, int z) { return dim3((unsigned)(N / kT), (unsigned)y, (unsigned)z); }
 
 }  // namespace
@@ -503,6 +512,16 @@ void launch_lincomb_wide(const bc_ctx *c, const u64 *in, u64 *out, const double 
     if (KB == 16) k_lincomb_wide<16><<<g, kT, 0, st>>>(in, out, W, c0, M, K, KT, count, nl, c->pinfo, c->N);
     else if (KB == 8) k_lincomb_wide<8><<<g, kT, 0, st>>>(in, out, W, c0, M, K, KT, count, nl, c->pinfo, c->N);
     else k_lincomb_wide<1><<<g, kT, 0, st>>>(in, out, W, c0, M, K, KT, count, nl, c->pinfo, c->N);
+}
+void launch_lincomb_wide_mfma(const bc_ctx *c, const u64 *in, u64 *out, const int8_t *W8, const double *c0,
+                              const int *corr, int M, int K, int count, int nl, hipStream_t st) {
+    BC_REQUIRE(use_fp64(c), BC_ERR_PARAM, "wide linear combinations need primes below 2^50");
+    BC_REQUIRE(!tl_rec, BC_ERR_ARG, "the persistent executor does not run wide linear combinations");
+    BC_REQUIRE(M >= 1 && M <= kWideMfmaM && K >= 1 && K <= kWideMfmaK && c->N % 32 == 0, BC_ERR_ARG,
+               "wide linear combination on the matrix cores: bad shape");
+    ProfScope ps(c, kProfLincomb, 8.0 * c->N * 2.0 * nl * count * (M + K), st);
+    const dim3 g((unsigned)(c->N / 32), (unsigned)nl, (unsigned)(2 * count));
+    k_lincomb_wide_mfma<<<g, 256, 0, st>>>(in, out, W8, c0, corr, M, K, count, nl, c->pinfo, c->N);
 }
 void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, int nl, hipStream_t st) {
     k_crt_decode<<<grid3(c->N, 1, count), kT, 0, st>>>(d, out, c->garner, c->pinfo, nl, c->p, c->N);

@@ -696,6 +696,118 @@ __device__ __forceinline__ void b_lincomb_wide(const VBlk &VB, const u64 *__rest
     }
 }
 
+// The same wide combination on the matrix cores, exactly: every input word
+// v < 2^56 is split into eight 7-bit digits x_a (v = sum_a x_a 2^(7a)), and
+// for each digit one int8 x int8 -> int32 matrix product
+// S_a[k][pos] = sum_m W8[k][m] x_a[m][pos] runs on v_mfma_i32_32x32x32_i8
+// (32 outputs x 32 positions, 32 inputs a step): |S_a| <= M 128 127 < 2^23
+// for M <= 256.  The weights are W8 = W except where W = 128 (not an int8):
+// there W8 = 0 and the input enters through a correction list (`corr`:
+// offsets [K + 1], then input indices), added as 128 x mod q.  Recombination
+// in fp64: R_lo = sum_{a<4} S_a 2^(7a), R_hi = sum_{a>=4} S_a 2^(7(a-4)), both
+// below 2^45 (exact), out = R_hi (2^28 mod q) + R_lo (+ c0) reduced once.
+// Block: 256 threads, a tile of 32 positions (one limb of one ciphertext
+// component) and all K outputs, wave w taking outputs 32 w .. 32 w + 31.  The
+// tile's digits sit in LDS as bytes [8][32][M + 16] (one 16-byte read per
+// lane and step).  The weights come as int8 [KP][M] (KP = 128, rows past K
+// zero); the A and B operands of a lane cover the same 16 inputs of a step in
+// the same byte order, so the products do not depend on how the hardware
+// orders them; which output row each accumulator register holds is read once
+// from a product whose rows carry their own index.
+constexpr int kWideRow = kWideMfmaM + 16;
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
+__device__ __forceinline__ void b_lincomb_wide_mfma(const VBlk &VB, const u64 *__restrict__ in,
+                                                    u64 *__restrict__ out, const int8_t *__restrict__ W8,
+                                                    const double *__restrict__ c0, const int *__restrict__ corr,
+                                                    int M, int K, int count, int nl,
+                                                    const PrimeInfo *__restrict__ pinfo, int N,
+                                                    unsigned char *__restrict__ lds) {
+#pragma clang fp contract(off)
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int i = VB.y, cc = VB.z;
+    const int pos0 = VB.x * 32;  // first position of the tile inside the limb
+    const size_t blk = (size_t)count * 2 * nl * N;
+    const size_t off0 = (size_t)cc * nl * N + (size_t)i * N + pos0;
+    const int steps = (M + 31) / 32;
+    // the tile's digits into LDS: thread t takes position t % 32 and input
+    // quads q = t / 32, t / 32 + 8, ... (four inputs packed per dword)
+    {
+        const int pp = t & 31;
+        for (int q = t >> 5; q < steps * 8; q += 8) {
+            u64 w[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int m = 4 * q + j;
+                w[j] = m < M ? in[(size_t)m * blk + off0 + pp] : 0;
+            }
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                u32 d = 0;
+#pragma unroll
+                for (int j = 0; j < 4; j++) d |= (u32)((w[j] >> (7 * a)) & 127) << (8 * j);
+                *reinterpret_cast<u32 *>(lds + ((size_t)a * 32 + pp) * kWideRow + 4 * q) = d;
+            }
+        }
+    }
+    __syncthreads();
+    const int row_l = lane & 31, half = lane >> 5;  // A row / B column of this lane, its half of a step
+    // which output row (inside the wave's 32) each accumulator register holds
+    int rowof[16];
+    {
+        v4i_t a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+        if (half == 0) {
+            a[0] = row_l;  // byte 0: this row's index
+            b[0] = 1;
+        }
+        v16i_t z = {0};
+        z = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, z, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 16; r++) rowof[r] = z[r];
+    }
+    const int k0 = wave * 32;
+    double rlo[16], rhi[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) rlo[r] = rhi[r] = 0.0;
+    if (k0 < K) {
+        for (int a = 0; a < 8; a++) {
+            v16i_t acc = {0};
+            for (int st = 0; st < steps; st++) {
+                const v4i_t av = *reinterpret_cast<const v4i_t *>(W8 + (size_t)(k0 + row_l) * kWideMfmaM + st * 32 +
+                                                                  half * 16);
+                const v4i_t bv = *reinterpret_cast<const v4i_t *>(lds + ((size_t)a * 32 + row_l) * kWideRow +
+                                                                  st * 32 + half * 16);
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc, 0, 0, 0);
+            }
+            const double sc = (double)(1 << (7 * (a & 3)));
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                if (a < 4) rlo[r] = __builtin_fma((double)acc[r], sc, rlo[r]);
+                else rhi[r] = __builtin_fma((double)acc[r], sc, rhi[r]);
+            }
+        }
+        const PrimeInfo &pi = pinfo[i];
+        // 2^28 and 128 (both below q) as (w, w/q) pairs
+        const double q = pi.qd, u = pi.qinv;
+        const double w28 = f_canon(0x1p28, q, u), w128 = 128.0;
+        const FPair f28{w28, w28 * u}, f128{w128, w128 * u};
+        const bool comp0 = (cc & 1) == 0;
+        const int pos = pos0 + row_l;  // this lane's column
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int k = k0 + rowof[r];
+            if (k >= K) continue;
+            double v = f_mulmod(rhi[r], f28, q) + rlo[r];
+            for (int e = corr[k]; e < corr[k + 1]; e++) {
+                const int m = corr[K + 1 + e];
+                v += f_mulmod(f_load(in[(size_t)m * blk + (size_t)cc * nl * N + (size_t)i * N + pos]), f128, q);
+            }
+            if (comp0) v += c0[k];
+            out[(size_t)k * blk + (size_t)cc * nl * N + (size_t)i * N + pos] = f_bits(f_canon(v, q, u));
+        }
+    }
+}
+
 }  // namespace
 
 }  // namespace bc

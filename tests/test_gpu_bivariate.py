@@ -96,3 +96,25 @@ def test_bivariate_uint16_two_digits_full_size():
     # the same call again gives the same bytes (the workspace pool reuses blocks)
     lt2 = dev.compare_max_min(dk, A, B, True, False, False, circuit=bc.BC_CIRCUIT_BIVARIATE)[0]
     assert np.array_equal(dev.export(lt2), dev.export(lt))
+
+
+@pytest.mark.parametrize("p,prm", [(257, Params(12, 257, 13, 50, 4, 50, 4)), (17, Params(12, 17, 9, 36, 2, 36, 3))])
+def test_matrix_core_combination_equals_vector_units(p, prm):
+    """The g_k(S) combinations on the matrix cores (split-int8 products) and
+    in fp64 on the vector units give the same ciphertext bytes."""
+    import paper_2407_07308_amd as bc
+
+    print(f"bivariate: matrix cores vs vector units, p={p}", flush=True)
+    dev, dk, _ = setup(prm, 75)
+    G = 3
+    x = synth.slot_values(76, G, dev.M, 0, p)
+    y = synth.slot_values(77, G, dev.M, 0, p)
+    x[0, :4], y[0, :4] = [0, p - 1, 5, p - 1], [p - 1, 0, 5, p - 1]
+    rx, ry = synth.encrypt_randomness(78, G, dev.N), synth.encrypt_randomness(79, G, dev.N)
+    A, B = [dev.encrypt(dk, x, rx["u"], rx["e"])], [dev.encrypt(dk, y, ry["u"], ry["e"])]
+    out = {}
+    for mfma in (1, 0):
+        dev.set_tuning(bc.BC_TUNE_MFMA, mfma)
+        out[mfma] = dev.compare_max_min(dk, A, B, True, False, False, circuit=bc.BC_CIRCUIT_BIVARIATE)[0]
+    assert np.array_equal(dev.export(out[1]), dev.export(out[0]))
+    assert np.array_equal(dev.decrypt(dk, out[1]), (x < y).astype(np.uint32))
