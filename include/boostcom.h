@@ -211,6 +211,25 @@ int bc_mod_switch(bc_ctx *ctx, const bc_ctb *in, bc_ctb *out, void *stream);
  * relinearise, then modulus-switch one prime down unless the level is 0. */
 int bc_mul_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *a, const bc_ctb *b, bc_ctb *out,
                  void *stream);
+/* bc_mul_relin for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, same kernels, same output bytes, but no allocation of any
+ * kind.  The workspace is a fixed 64 MiB device array per GPU (one copy on
+ * each GPU the library runs on, held until the process ends), whose device
+ * address bc_ctx_create looks up once per device.  The caller passes inputs
+ * and the output as for bc_mul_relin.  Limit: (3 (l+1) + dnum (l+1+nP)
+ * + (l+1) + 2 (l+1+nP) + 2 max(l,1)) N 8 count bytes, each of the five
+ * buffers rounded up to 256 bytes, must fit in 64 MiB (l = the lower operand
+ * level); for example one ciphertext at the top of the N = 2^15 chain
+ * (14 x 50-bit + 5 x 50-bit primes, dnum 3) needs 44.25 MiB.  Larger calls
+ * return BC_ERR_ARG before any launch.  Every call on one GPU uses the same
+ * array and leaves its contents behind: calls on one stream are ordered, but
+ * calls that overlap on one GPU (other streams, other threads, other
+ * contexts) race and corrupt each other's results.  BC_ERR_HIP when the
+ * array's address could not be looked up; BC_ERR_ARG when the current device
+ * is not the context's. */
+int bc_mul_relin_noalloc(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *a, const bc_ctb *b, bc_ctb *out,
+                         void *stream);
 /* Rotation (paper, "Word-wise Universal FHE Scheme": rotation among the
  * homomorphic operations; the ciphertext shifting of ShiftMul/ShiftAdd) of
  * each slot row left by `steps` (or BC_ROW_SWAP): automorphism x -> x^g then

@@ -79,6 +79,7 @@ _SIGS = {
     "bc_relin": (_I, [_V, _V, _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_mod_switch": (_I, [_V, _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_mul_relin": (_I, [_V, _V, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_mul_relin_noalloc": (_I, [_V, _V, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_rotate": (_I, [_V, _V, _P(bc_ctb), _I, _P(bc_ctb), _V]),
     "bc_add": (_I, [_V, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_sub": (_I, [_V, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
@@ -331,6 +332,17 @@ class Context:
         ca, cb, co = a.ctb(), b.ctb(), out.ctb()
         _check(self.L.bc_mul_relin(self.handle, keys.handle, ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(co),
                                    _stream()))
+        return out.take(co)
+
+    def mul_relin_noalloc(self, keys: Keys, a: Batch, b: Batch, out: Batch = None) -> Batch:
+        """bc_mul_relin_noalloc: the library allocates nothing (its workspace
+        is the fixed per-GPU scratch array); ``out`` may be passed in."""
+        lv = min(a.level, b.level)
+        if out is None:
+            out = self.new_batch(a.count, lv - 1 if lv > 0 else 0, 2)
+        ca, cb, co = a.ctb(), b.ctb(), out.ctb()
+        _check(self.L.bc_mul_relin_noalloc(self.handle, keys.handle, ctypes.byref(ca), ctypes.byref(cb),
+                                           ctypes.byref(co), _stream()))
         return out.take(co)
 
     def relin(self, keys: Keys, a: Batch) -> Batch:

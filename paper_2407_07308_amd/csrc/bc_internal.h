@@ -552,6 +552,9 @@ struct bc_ctx {
     // slices as lanes; the runner is created on first use
     int persistent = 0;
     std::unique_ptr<bc::PersistRunner> runner;
+    int device = 0;                 // current device at creation (every call runs there)
+    void *scratch = nullptr;        // that device's allocation-free workspace (device address)
+    std::string scratch_err;        // why the lookup failed, if it did
     ~bc_ctx();
 };
 

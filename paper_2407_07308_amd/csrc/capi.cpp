@@ -567,6 +567,14 @@ int bc_ctx_create(const bc_params *prm, bc_ctx **out) {
         std::unique_ptr<bc_ctx> c(new bc_ctx());
         build_context(c.get(), *prm);
         c->graphs.reset(new GraphCache());
+        // set-up of the allocation-free entry point on this device (a failed
+        // lookup only disables that entry point)
+        BC_HIP(hipGetDevice(&c->device));
+        try {
+            c->scratch = scratch_lookup(c->device);
+        } catch (const Error &e) {
+            c->scratch_err = e.what();
+        }
         *out = c.release();
     });
 }
@@ -769,6 +777,31 @@ int bc_mul_relin(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *a, const bc_ctb
         double nb = ctx->noise.product(lv, x.noise, y.noise, -INFINITY);
         ctx->noise.require(lv, nb, "multiplication");
         if (lv > 0) nb = ctx->noise.mod_switch(lv, nb);
+        mul_relin(ctx, keys, x, y, o, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
+    });
+}
+
+int bc_mul_relin_noalloc(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *a, const bc_ctb *b, bc_ctb *out,
+                         void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(ctx->scratch, BC_ERR_HIP, "allocation-free workspace unavailable: " + ctx->scratch_err);
+        int dev = -1;
+        BC_HIP(hipGetDevice(&dev));
+        BC_REQUIRE(dev == ctx->device, BC_ERR_ARG, "allocation-free call on another device than the context's");
+        StreamScope sc(stream);
+        const CtB x = from_abi(ctx, a), y = from_abi(ctx, b), o = from_abi(ctx, out);
+        const int lv = std::min(x.level, y.level);
+        const size_t need = mul_relin_workspace(ctx, x.count, lv);
+        BC_REQUIRE(need <= kScratchBytes, BC_ERR_ARG,
+                   "allocation-free multiplication needs " + std::to_string(need) + " bytes of workspace; the fixed " +
+                       "scratch holds " + std::to_string(kScratchBytes) + " (use fewer ciphertexts per call)");
+        double nb = ctx->noise.product(lv, x.noise, y.noise, -INFINITY);
+        ctx->noise.require(lv, nb, "multiplication");
+        if (lv > 0) nb = ctx->noise.mod_switch(lv, nb);
+        ArenaScope ws(ctx->scratch, kScratchBytes);
         mul_relin(ctx, keys, x, y, o, (hipStream_t)stream);
         out->noise_bits = (float)nb;
     });

@@ -7,7 +7,7 @@
 #include <algorithm>
 #include <cstring>
 
-#include "bc_internal.h"
+#include "ops.h"
 #include "persist.h"
 
 namespace bc {
@@ -206,6 +206,7 @@ void build_plans(const bc_ctx *c, PairSet setp, std::vector<ModUpPlan> &mu, ModD
 // ------------------------------------------------------------------ pool
 
 thread_local hipStream_t tl_stream = nullptr;
+thread_local Arena *tl_arena = nullptr;
 
 // Block sizes are rounded up to a size class (four per power of two, at
 // least 256 bytes), and a request takes any cached block of its stream up to

@@ -7,6 +7,13 @@ namespace bc {
 
 void build_context(bc_ctx *c, const bc_params &prm);
 
+// Size of the fixed device workspace of the allocation-free multiplication
+// (one array per GPU, kept until the process ends).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+// Device address of that workspace on `device`, which must be the current
+// device; looked up on the first call per device, then cached.
+void *scratch_lookup(int device);
+
 // The output has nl limbs per component; na, nb, nc (>= nl) are the limbs
 // per component the operands are stored with (their lowest nl are read).
 // addend: null, or [count][2][nc][N] added to the first two components.

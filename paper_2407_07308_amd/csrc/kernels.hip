@@ -527,4 +527,30 @@ void launch_crt_decode(const bc_ctx *c, const u64 *d, uint32_t *out, int count, 
     k_crt_decode<<<grid3(c->N, 1, count), kT, 0, st>>>(d, out, c->garner, c->pinfo, nl, c->p, c->N);
 }
 
+// ------------------------------------------------- allocation-free workspace
+// Workspace of the allocation-free multiplication: a fixed device array of
+// kScratchBytes (every GPU the library runs on holds its own copy until the
+// process ends).  In host code the array's name only stands for the symbol:
+// its device address is looked up once per device, with that device current,
+// and only that address is ever handed to kernels or copies.
+static __device__ __align__(256) u64 scratch[kScratchBytes / sizeof(u64)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_addr[kMaxDevices];
+}  // namespace
+
+void *scratch_lookup(int device) {
+    BC_REQUIRE(device >= 0 && device < kMaxDevices, BC_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_addr[device]) {
+        void *ptr = nullptr;
+        BC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        BC_REQUIRE(ptr, BC_ERR_HIP, "no device address for the allocation-free workspace");
+        scratch_addr[device] = ptr;
+    }
+    return scratch_addr[device];
+}
+
 }  // namespace bc

@@ -427,6 +427,18 @@ void mul_relin_add(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, cons
     relin_mod_switch(c, k, t3, out, st);
 }
 
+// Mirrors the buffers mul_relin takes: the tensor T3, then (ks_accumulate)
+// the raised digits MU, the coefficient-domain copy XC and the accumulators
+// ACC, then E (relinearise + switch) or, at level 0, TH (key switch).
+size_t mul_relin_workspace(const bc_ctx *c, int count, int lv) {
+    auto rnd = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t limb = sizeof(u64) * (size_t)c->N * count;
+    const size_t nl = lv + 1, next = nl + c->nP;
+    size_t t = rnd(3 * nl * limb) + rnd(c->dnum * next * limb) + rnd(nl * limb) + rnd(2 * next * limb);
+    t += lv > 0 ? rnd(2 * (size_t)lv * limb) : rnd(2 * nl * limb);
+    return t;
+}
+
 CtB mul(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, hipStream_t st) {
     CtB out = alloc_ct(c, a.count, out_level_mul(a.level, b.level), 2);
     mul_relin(c, k, a, b, out, st);

@@ -5,12 +5,40 @@
 
 namespace bc {
 
-// Pooled device buffer, returned to the context pool when the last owner drops it.
+// Caller-provided workspace carved front to back (allocation-free calls):
+// while a thread has one installed, every workspace buffer of its operations
+// comes from it instead of the pool, and nothing is returned until the call
+// ends.
+struct Arena {
+    char *base;
+    size_t cap, used = 0;
+    void *take(size_t bytes) {
+        bytes = (bytes + 255) / 256 * 256;
+        BC_REQUIRE(used + bytes <= cap, BC_ERR_ARG, "operation needs more workspace than the fixed scratch holds");
+        void *p = base + used;
+        used += bytes;
+        return p;
+    }
+};
+extern thread_local Arena *tl_arena;
+struct ArenaScope {
+    Arena a;
+    Arena *prev;
+    ArenaScope(void *base, size_t cap) : a{(char *)base, cap}, prev(tl_arena) { tl_arena = &a; }
+    ~ArenaScope() { tl_arena = prev; }
+};
+
+// Device workspace buffer: from the context pool (returned when the last owner
+// drops it), or from the thread's arena when one is installed.
 struct Buf {
     bc_ctx *c;
     void *p;
-    Buf(bc_ctx *ctx, size_t bytes) : c(ctx), p(ctx->pool.alloc(bytes)) {}
-    ~Buf() { c->pool.release(p); }
+    bool pooled;
+    Buf(bc_ctx *ctx, size_t bytes)
+        : c(ctx), p(tl_arena ? tl_arena->take(bytes) : ctx->pool.alloc(bytes)), pooled(!tl_arena) {}
+    ~Buf() {
+        if (pooled) c->pool.release(p);
+    }
     Buf(const Buf &) = delete;
     Buf &operator=(const Buf &) = delete;
 };
@@ -45,6 +73,9 @@ void mul_relin(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const Ct
 void mul_relin_add(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, const CtB &add, const CtB &out,
                    hipStream_t st);
 CtB mul(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, hipStream_t st);
+// Workspace bytes mul_relin takes for `count` products at level lv (each
+// buffer rounded up to 256 bytes, none reused within the call).
+size_t mul_relin_workspace(const bc_ctx *c, int count, int lv);
 void rotate(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB &out, hipStream_t st);
 void add_sub(bc_ctx *c, const CtB &a, const CtB &b, const CtB &out, bool sub, hipStream_t st);
 CtB add(bc_ctx *c, const CtB &a, const CtB &b, hipStream_t st);
