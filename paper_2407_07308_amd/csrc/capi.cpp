@@ -89,14 +89,9 @@ void run_compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB 
     }
 }
 
-// The comparison as one persistent launch on `origin`: the groups split into
-// n slices, each a lane of the executor (workspace blocks tagged with one
-// library stream per slice, which waits for the launch afterwards).
-void run_compare_persistent(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, const bc_ctb *lt_out,
-                            const bc_ctb *max_out, const bc_ctb *min_out, hipStream_t origin, int n) {
-    BC_REQUIRE(persist_supported(c), BC_ERR_ARG, "persistent mode: unsupported context");
-    const int G = A[0].count;
-    std::lock_guard<std::mutex> lk(c->split_mu);
+// At least n library streams on context c (workspace tags of its slices),
+// and their events; the caller holds c->split_mu.
+void ensure_split_streams(bc_ctx *c, int n) {
     while ((int)c->split_streams.size() < n) {
         hipStream_t s;
         hipEvent_t e;
@@ -106,42 +101,71 @@ void run_compare_persistent(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A,
         c->split_done.push_back(e);
     }
     if (!c->split_fork) BC_HIP(hipEventCreateWithFlags(&c->split_fork, hipEventDisableTiming));
-    if (!c->runner) c->runner.reset(new PersistRunner());
-    c->runner->check_stall();
-    for (int i = 0; i < n; i++) {  // earlier work with the slices' blocks comes first
+}
+
+// Slices of one comparison for the persistent executor: the groups split
+// into S slices (S = the device's XCDs, at most the group count); slice s
+// is lane lane0 + s of `rec`, pinned to XCD s, its workspace tagged with c's
+// library stream s.  Before the launch `origin` must wait for those streams'
+// earlier work (join_before), after it they wait for the launch
+// (join_after).  The caller holds c->split_mu and has run ensure_split_streams.
+int record_slices(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, const bc_ctb *lt_out,
+                  const bc_ctb *max_out, const bc_ctb *min_out, Recorder &rec, int lane0) {
+    const int G = A[0].count, S = std::min(rec.nq, G);
+    auto cut = [&](const bc_ctb *x, int lo, int cnt) {
+        bc_ctb sl = *x;
+        sl.data = x->data + (size_t)lo * bc_ct_words(c, x->level, x->ncomp);
+        sl.count = cnt;
+        return sl;
+    };
+    RecordScope rs(&rec);
+    for (int i = 0; i < S; i++) {
+        const int lo = (int)((int64_t)G * i / S), hi = (int)((int64_t)G * (i + 1) / S);
+        std::vector<CtB> a(ndig), b(ndig);
+        std::vector<bc_ctb> mx, mn;
+        for (int d = 0; d < ndig; d++) {
+            a[d] = A[d].slice(lo, hi - lo, c->N);
+            b[d] = B[d].slice(lo, hi - lo, c->N);
+            if (max_out) mx.push_back(cut(&max_out[d], lo, hi - lo));
+            if (min_out) mn.push_back(cut(&min_out[d], lo, hi - lo));
+        }
+        bc_ctb lt;
+        if (lt_out) lt = cut(lt_out, lo, hi - lo);
+        rec.lane = lane0 + i;
+        if ((int)rec.lane_xcd.size() <= rec.lane) rec.lane_xcd.resize(rec.lane + 1, 0);
+        rec.lane_xcd[rec.lane] = i;
+        StreamScope sc(c->split_streams[i]);
+        run_compare(c, k, ndig, a.data(), b.data(), lt_out ? &lt : nullptr, max_out ? mx.data() : nullptr,
+                    min_out ? mn.data() : nullptr, c->split_streams[i]);
+    }
+    return S;
+}
+void join_before(bc_ctx *c, int S, hipStream_t origin) {
+    for (int i = 0; i < S; i++) {
         BC_HIP(hipEventRecord(c->split_done[i], c->split_streams[i]));
         BC_HIP(hipStreamWaitEvent(origin, c->split_done[i], 0));
     }
-    auto cut = [&](const bc_ctb *x, int lo, int cnt) {
-        bc_ctb s = *x;
-        s.data = x->data + (size_t)lo * bc_ct_words(c, x->level, x->ncomp);
-        s.count = cnt;
-        return s;
-    };
-    Recorder rec;
-    {
-        RecordScope rs(&rec);
-        for (int i = 0; i < n; i++) {
-            const int lo = (int)((int64_t)G * i / n), hi = (int)((int64_t)G * (i + 1) / n);
-            std::vector<CtB> a(ndig), b(ndig);
-            std::vector<bc_ctb> mx, mn;
-            for (int d = 0; d < ndig; d++) {
-                a[d] = A[d].slice(lo, hi - lo, c->N);
-                b[d] = B[d].slice(lo, hi - lo, c->N);
-                if (max_out) mx.push_back(cut(&max_out[d], lo, hi - lo));
-                if (min_out) mn.push_back(cut(&min_out[d], lo, hi - lo));
-            }
-            bc_ctb lt;
-            if (lt_out) lt = cut(lt_out, lo, hi - lo);
-            rec.lane = i;
-            StreamScope sc(c->split_streams[i]);
-            run_compare(c, k, ndig, a.data(), b.data(), lt_out ? &lt : nullptr, max_out ? mx.data() : nullptr,
-                        min_out ? mn.data() : nullptr, c->split_streams[i]);
-        }
-    }
-    c->runner->run(c, rec, origin);
+}
+void join_after(bc_ctx *c, int S, hipStream_t origin) {
     BC_HIP(hipEventRecord(c->split_fork, origin));
-    for (int i = 0; i < n; i++) BC_HIP(hipStreamWaitEvent(c->split_streams[i], c->split_fork, 0));
+    for (int i = 0; i < S; i++) BC_HIP(hipStreamWaitEvent(c->split_streams[i], c->split_fork, 0));
+}
+
+// The comparison as one persistent launch on `origin`, one lane per XCD.
+void run_compare_persistent(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, const bc_ctb *lt_out,
+                            const bc_ctb *max_out, const bc_ctb *min_out, hipStream_t origin) {
+    BC_REQUIRE(persist_supported(c), BC_ERR_ARG, "persistent mode: unsupported context");
+    std::lock_guard<std::mutex> lk(c->split_mu);
+    if (!c->runner) c->runner.reset(new PersistRunner());
+    c->runner->check_stall();
+    Recorder rec;
+    rec.nq = persist_xcds();
+    ensure_split_streams(c, rec.nq);
+    const int S = std::min(rec.nq, A[0].count);
+    join_before(c, S, origin);
+    record_slices(c, k, ndig, A, B, lt_out, max_out, min_out, rec, 0);
+    c->runner->run(c, rec, origin);
+    join_after(c, S, origin);
 }
 
 // run_compare with the groups split over ctx->split library streams (when
@@ -153,7 +177,7 @@ void run_compare_split(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, cons
                        const bc_ctb *max_out, const bc_ctb *min_out, hipStream_t origin) {
     const int G = A[0].count, n = std::min(c->split, G);
     if (c->persistent && c->exec_mode != BC_EXEC_PER_OP) {
-        run_compare_persistent(c, k, ndig, A, B, lt_out, max_out, min_out, origin, std::max(1, n));
+        run_compare_persistent(c, k, ndig, A, B, lt_out, max_out, min_out, origin);
         return;
     }
     if (n <= 1) {
@@ -383,27 +407,29 @@ int bc_group_compare(bc_group *g, const bc_keys *const *keys, const int32_t *ndi
             return;
         }
         // persistent mode: every member's launches recorded as one lane each
-        auto record_all = [&](Recorder &rec) {
-            RecordScope rs(&rec);
-            for (int i = 0; i < n; i++) {
-                rec.lane = i;
-                StreamScope sc(g->streams[i]);  // workspace blocks tagged with the member's stream
-                run_compare(g->ctxs[i], keys[i], ndigits[i], A[i].data(), B[i].data(), lt_out ? lt_out[i] : nullptr,
-                            max_out ? max_out[i] : nullptr, min_out ? min_out[i] : nullptr, g->streams[i]);
+        // persistent mode: every member's groups split into one slice per
+        // XCD, each slice a lane pinned to its XCD (lane i * kMaxXcd + s)
+        const int nq = persist ? persist_xcds() : 1;
+        std::vector<std::unique_lock<std::mutex>> member_locks;
+        if (persist)
+            for (bc_ctx *c : g->ctxs) {
+                member_locks.emplace_back(c->split_mu);
+                ensure_split_streams(c, nq);
             }
+        auto record_all = [&](Recorder &rec) {
+            rec.nq = nq;
+            for (int i = 0; i < n; i++)
+                record_slices(g->ctxs[i], keys[i], ndigits[i], A[i].data(), B[i].data(), lt_out ? lt_out[i] : nullptr,
+                              max_out ? max_out[i] : nullptr, min_out ? min_out[i] : nullptr, rec, i * kMaxXcd);
         };
         if (persist) {
-            // eager: the launch on `st` after the members' earlier work; the
-            // members' streams wait for it (their workspace blocks were used)
-            for (int i = 0; i < n; i++) {
-                BC_HIP(hipEventRecord(g->done[i], g->streams[i]));
-                BC_HIP(hipStreamWaitEvent(st, g->done[i], 0));
-            }
+            // eager: the launch on `st` after the slices' earlier work; their
+            // streams wait for it (their workspace blocks were used)
+            for (int i = 0; i < n; i++) join_before(g->ctxs[i], std::min(nq, A[i][0].count), st);
             Recorder rec;
             record_all(rec);
             g->runner->run(g->ctxs[0], rec, st);
-            BC_HIP(hipEventRecord(g->joined, st));
-            for (int i = 0; i < n; i++) BC_HIP(hipStreamWaitEvent(g->streams[i], g->joined, 0));
+            for (int i = 0; i < n; i++) join_after(g->ctxs[i], std::min(nq, A[i][0].count), st);
             BC_HIP(hipStreamSynchronize(st));
             // recorded: the blocks the graph keeps, the table uploaded before
             // capture, the reset and the persistent launch captured

@@ -155,12 +155,25 @@ struct PStage {
     int pad[3];
 };
 
+// Queues: one per XCD when the lanes are pinned to XCDs (each XCD's
+// workgroups take only its tickets, and a hand-off stays inside one L2), else
+// one for the device.
+constexpr int kMaxXcd = 16;
+
 // Queue state in device memory: zeroed before every launch.
 struct PQueue {
-    int next;       // next ticket
-    int stalled;    // a bounded wait expired
+    int next[kMaxXcd];  // next ticket of each queue
+    int stalled;        // a bounded wait expired, or a queue was left undrained
+    int exited;         // workgroups that have left
     int pad[2];
-    int done[1];    // tickets done per stage (nstage entries)
+    int done[1];        // tickets done per stage (nstage entries)
+};
+
+// The queues' shape (uploaded with the plan, after the queue state).
+struct PHeader {
+    int nq;                // queues (1: device-wide, else one per XCD)
+    int ntick[kMaxXcd];    // tickets of each queue
+    int map_off[kMaxXcd];  // where each queue's ticket -> stage map starts
 };
 
 struct Recorder {
@@ -171,6 +184,10 @@ struct Recorder {
     };
     int lane = 0;
     std::vector<S> stages;
+    // queues of the layout: 1 (device-wide), or the number of XCDs, lane l
+    // then running on XCD lane_xcd[l]
+    int nq = 1;
+    std::vector<int> lane_xcd;
     // grid of virtual blocks; `per` = 0 picks the blocks per ticket from the
     // stage's size
     template <class T>
@@ -189,11 +206,11 @@ struct Recorder {
 extern thread_local Recorder *tl_rec;
 
 // A recording laid out for the executor: one host image of the device table
-// [queue state | stages | ticket -> stage map | arguments].
+// [queue state | queue shape | stages | ticket -> stage maps | arguments].
 struct PersistPlan {
     std::vector<char> image;
-    size_t off_stage = 0, off_map = 0, off_args = 0;
-    int nstage = 0, ntick = 0;
+    size_t off_head = 0, off_stage = 0, off_map = 0, off_args = 0;
+    int nstage = 0, ntick = 0, nq = 1;
 };
 PersistPlan persist_plan(const Recorder &rec);
 // Runs an uploaded plan on `st`: the queue state is zeroed by a small kernel,
@@ -203,6 +220,8 @@ PersistPlan persist_plan(const Recorder &rec);
 void persist_run(const PersistPlan &plan, void *table, int *stall_flag, hipStream_t st);
 // Workgroups of the persistent launch (resident capacity of the device).
 int persist_grid();
+// XCDs of the current device (1 when the runtime does not say).
+int persist_xcds();
 struct PersistShape {
     int stages, tickets, grid;
 };

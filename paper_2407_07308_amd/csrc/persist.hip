@@ -157,24 +157,36 @@ __device__ __forceinline__ void run_block(int kind, const char *__restrict__ A, 
 
 __device__ __forceinline__ bool uses_lds(int kind) { return kind >= kPkNttFwd0 && kind <= kPkNttComb2; }
 
-// Every workgroup: take a ticket, wait for its lane's previous stage, run its
-// virtual blocks, count it done; until the tickets run out.  The next ticket
-// is taken while the current one runs (the queue still drains: the lowest
-// unfinished ticket is always the one its holder runs next).
+// Every workgroup: take a ticket of its queue, wait for its lane's previous
+// stage, run its virtual blocks, count it done; until the tickets run out.
+// The next ticket is taken while the current one runs (the queue still
+// drains: the lowest unfinished ticket is always the one its holder runs
+// next).  With one queue per XCD a workgroup serves its own XCD's queue,
+// whose lanes never depend on another XCD: a hand-off then needs the
+// producer's stores in the shared L2 (each wave waits for its stores) and the
+// consumer's L1 invalidated, and no L2 is written back or invalidated.  With
+// one device-wide queue the hand-off releases and acquires at agent scope.
 __global__ void __launch_bounds__(kPT, 3) k_persist(const PStage *__restrict__ stages, const int *__restrict__ tmap,
-                                                 const char *__restrict__ args, PQueue *q, int ntick,
-                                                 int *stall_flag) {
+                                                    const char *__restrict__ args, PQueue *q,
+                                                    const PHeader *__restrict__ hd, int *stall_flag) {
     __shared__ u64 lds[kPLds];
     __shared__ int sh_next;
-    if (threadIdx.x == 0) sh_next = __hip_atomic_fetch_add(&q->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int nq = __builtin_amdgcn_readfirstlane(hd->nq);
+    const bool local = nq > 1;
+    // this workgroup's XCD (hardware register XCC_ID, 4 bits)
+    const int x = local ? (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) % (unsigned)nq) : 0;
+    const int ntick = __builtin_amdgcn_readfirstlane(hd->ntick[x]);
+    const int *map = tmap + __builtin_amdgcn_readfirstlane(hd->map_off[x]);
+    if (threadIdx.x == 0) sh_next = __hip_atomic_fetch_add(&q->next[x], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     int acquired = -1;  // the dependency this workgroup has acquired last
     for (;;) {
         const int t = __builtin_amdgcn_readfirstlane(sh_next);
         __syncthreads();  // every wave has read sh_next
         if (t >= ntick) break;
-        if (threadIdx.x == 0) sh_next = __hip_atomic_fetch_add(&q->next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int si = __builtin_amdgcn_readfirstlane(tmap[t]);
+        if (threadIdx.x == 0)
+            sh_next = __hip_atomic_fetch_add(&q->next[x], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int si = __builtin_amdgcn_readfirstlane(map[t]);
         const PStage &S = stages[si];
         const int dep = __builtin_amdgcn_readfirstlane(S.dep);
         if (dep >= 0 && dep != acquired) {
@@ -191,10 +203,12 @@ __global__ void __launch_bounds__(kPT, 3) k_persist(const PStage *__restrict__ s
                         break;
                     }
                 }
+                // one acquire per workgroup (the waves share the CU's L1, and
+                // none has loaded yet): the L1 alone when the producer shares
+                // this XCD's L2, else the agent-scope acquire
+                if (local) asm volatile("buffer_inv sc0" ::: "memory");
+                else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
-            // one acquire per workgroup: the waves share the CU's L1 and the
-            // XCD's L2, which it invalidates, and none has loaded yet
-            if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __syncthreads();
             acquired = dep;
         }
@@ -209,21 +223,32 @@ __global__ void __launch_bounds__(kPT, 3) k_persist(const PStage *__restrict__ s
             run_block(kind, A, vblk_of(gx, gy, gz, v), v, lds);
             if (uses_lds(kind)) __syncthreads();  // the next block reuses the exchange buffer
         }
-        // every wave's stores have reached the XCD's L2; then one write-back
-        // of that L2 (the agent-scope release) before the ticket counts
+        // every wave's stores have reached the XCD's L2; then (device-wide
+        // queue) one write-back of that L2 before the ticket counts
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_fetch_add(&q->done[si], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+    }
+    // the last workgroup out checks that every queue was drained (a queue of
+    // an XCD that received no workgroup would not be: reported as a stall)
+    if (threadIdx.x == 0 &&
+        __hip_atomic_fetch_add(&q->exited, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (int)gridDim.x - 1) {
+        for (int y = 0; y < nq; y++)
+            if (__hip_atomic_load(&q->next[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hd->ntick[y]) {
+                __hip_atomic_store(&q->stalled, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(stall_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
     }
 }
 
 __global__ void k_persist_reset(PQueue *q, int nstage) {
+    if (threadIdx.x < kMaxXcd) q->next[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
-        q->next = 0;
         q->stalled = 0;
+        q->exited = 0;
     }
     for (int i = threadIdx.x; i < nstage; i += blockDim.x) q->done[i] = 0;
 }
@@ -247,8 +272,28 @@ int persist_grid() {
     return cached[dev];
 }
 
+int persist_xcds() {
+    static std::mutex mu;
+    static int cached[64] = {0};
+    int dev = 0;
+    BC_HIP(hipGetDevice(&dev));
+    BC_REQUIRE(dev >= 0 && dev < 64, BC_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> g(mu);
+    if (!cached[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            n = 1;
+        }
+        cached[dev] = std::max(1, std::min(n, kMaxXcd));
+    }
+    return cached[dev];
+}
+
 PersistPlan persist_plan(const Recorder &rec) {
     PersistPlan p;
+    const int nq = std::max(1, std::min(rec.nq, kMaxXcd));
+    p.nq = nq;
     // lanes in order of first appearance; stages of a lane in recording order
     std::vector<int> lane_ids;
     std::vector<std::vector<int>> lanes;
@@ -262,35 +307,48 @@ PersistPlan persist_plan(const Recorder &rec) {
         }
         lanes[it - lane_ids.begin()].push_back(i);
     }
-    // interleave the lanes stage by stage
-    std::vector<int> order, dep;
+    auto queue_of = [&](int lane) {
+        if (nq == 1) return 0;
+        BC_REQUIRE(lane >= 0 && lane < (int)rec.lane_xcd.size(), BC_ERR_ARG, "persistent executor: lane without XCD");
+        return rec.lane_xcd[lane] % nq;
+    };
+    // per queue: its lanes interleaved stage by stage, each lane in order
+    std::vector<int> order, dep, qof;
     std::vector<int> last(lanes.size(), -1);
     size_t depth = 0;
     for (auto &l : lanes) depth = std::max(depth, l.size());
-    for (size_t r = 0; r < depth; r++)
-        for (size_t l = 0; l < lanes.size(); l++)
-            if (r < lanes[l].size()) {
-                dep.push_back(last[l]);
-                last[l] = (int)order.size();
-                order.push_back(lanes[l][r]);
-            }
-    const int grid = persist_grid();
+    for (int x = 0; x < nq; x++)
+        for (size_t r = 0; r < depth; r++)
+            for (size_t l = 0; l < lanes.size(); l++)
+                if (r < lanes[l].size() && queue_of(lane_ids[l]) == x) {
+                    dep.push_back(last[l]);
+                    last[l] = (int)order.size();
+                    order.push_back(lanes[l][r]);
+                    qof.push_back(x);
+                }
+    // resident workgroups serving one queue
+    const int grid = std::max(1, persist_grid() / nq);
     std::vector<PStage> st(order.size());
     std::vector<char> args;
+    PHeader hd{};
+    hd.nq = nq;
     int ntick = 0;
     for (size_t k = 0; k < order.size(); k++) {
         const Recorder::S &s = rec.stages[order[k]];
+        const int x = qof[k];
         PStage &d = st[k];
         d = s.st;
         const long long nvb = (long long)d.gx * d.gy * d.gz;
         BC_REQUIRE(nvb > 0 && nvb < (1ll << 30), BC_ERR_ARG, "persistent executor: stage grid out of range");
-        // a stage's tickets: at most one per resident workgroup (every ticket
-        // ends with a write-back of its XCD's L2, so few and large ones)
+        // a stage's tickets: at most one per workgroup of its queue (few and
+        // large: every ticket ends with a hand-off)
         if (d.per <= 0) d.per = (int)std::max<long long>(1, (nvb + grid - 1) / grid);
         d.ntick = (int)((nvb + d.per - 1) / d.per);
-        d.start = ntick;
+        d.start = hd.ntick[x];  // tickets are numbered inside the queue
         d.dep = dep[k];
-        BC_REQUIRE(d.dep < (int)k, BC_ERR_ARG, "persistent executor: dependency order");
+        BC_REQUIRE(d.dep < (int)k && (d.dep < 0 || qof[d.dep] == x), BC_ERR_ARG,
+                   "persistent executor: dependency order");
+        hd.ntick[x] += d.ntick;
         ntick += d.ntick;
         BC_REQUIRE(ntick < (1 << 30), BC_ERR_ARG, "persistent executor: too many tickets");
         args.resize((args.size() + 15) / 16 * 16);
@@ -298,18 +356,20 @@ PersistPlan persist_plan(const Recorder &rec) {
         args.insert(args.end(), s.args.begin(), s.args.end());
         BC_REQUIRE(args.size() < (1u << 31), BC_ERR_ARG, "persistent executor: arguments too large");
     }
+    for (int x = 1; x < nq; x++) hd.map_off[x] = hd.map_off[x - 1] + hd.ntick[x - 1];
     p.nstage = (int)st.size();
     p.ntick = ntick;
-    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t qbytes = up(offsetof(PQueue, done) + sizeof(int) * std::max(1, p.nstage));
-    p.off_stage = qbytes;
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    p.off_head = up(offsetof(PQueue, done) + sizeof(int) * std::max(1, p.nstage));
+    p.off_stage = up(p.off_head + sizeof(PHeader));
     p.off_map = up(p.off_stage + sizeof(PStage) * st.size());
     p.off_args = up(p.off_map + sizeof(int) * (size_t)ntick);
     p.image.assign(up(p.off_args + args.size()), 0);
+    std::memcpy(p.image.data() + p.off_head, &hd, sizeof hd);
     if (!st.empty()) std::memcpy(p.image.data() + p.off_stage, st.data(), sizeof(PStage) * st.size());
     int *map = reinterpret_cast<int *>(p.image.data() + p.off_map);
     for (size_t k = 0; k < st.size(); k++)
-        for (int t = 0; t < st[k].ntick; t++) map[st[k].start + t] = (int)k;
+        for (int t = 0; t < st[k].ntick; t++) map[hd.map_off[qof[k]] + st[k].start + t] = (int)k;
     if (!args.empty()) std::memcpy(p.image.data() + p.off_args, args.data(), args.size());
     return p;
 }
@@ -375,7 +435,7 @@ void persist_run(const PersistPlan &plan, void *table, int *stall_flag, hipStrea
     k_persist_reset<<<1, kPT, 0, st>>>(q, plan.nstage);
     k_persist<<<persist_grid(), kPT, 0, st>>>(reinterpret_cast<const PStage *>(base + plan.off_stage),
                                              reinterpret_cast<const int *>(base + plan.off_map), base + plan.off_args,
-                                             q, plan.ntick, stall_flag);
+                                             q, reinterpret_cast<const PHeader *>(base + plan.off_head), stall_flag);
     BC_HIP(hipGetLastError());
 }
 
