@@ -52,6 +52,9 @@ struct IntA {
     struct T {
         u64 w, wp;
     };
+    // twiddles come from the table (a Shoup companion would need a division)
+    static constexpr bool kDerive = false;
+    __device__ T derive(T a, T) const { return a; }
     const u64 *W, *Wp, *Wi, *Wip;
     u64 q, q2, ninv, ninvp, ninvw1, ninvw1p;
     __device__ IntA(const void *tw, const PrimeInfo &pi, int prime, int N) {
@@ -106,6 +109,7 @@ struct FpA {
     struct T {
         double w, wq;
     };
+    static constexpr bool kDerive = true;
     const double *W, *Wq, *Wi, *Wiq;
     double q, u, ninv, ninvq, ninvw1, ninvw1q;
     __device__ FpA(const void *tw, const PrimeInfo &pi, int prime, int N) {
@@ -123,6 +127,18 @@ struct FpA {
     }
     __device__ T fw(int k) const { return {W[k], Wq[k]}; }
     __device__ T iw(int k) const { return {Wi[k], Wiq[k]}; }
+    // The twiddle a.w c.w (a product of two table entries, or of derived
+    // ones).  With |a.w| < 3q/4 the product lies below q (1/2 + 3/16) < 3q/4
+    // (f_mulmod's bound, q < 2^50): the bound holds along any chain.  Its
+    // quotient factor w/q is w * (1/q) corrected by one Newton step, within
+    // 2^-53 (1 + 2^-50) of w/q, so a butterfly's quotient estimate y (w/q)
+    // errs by at most 1/2 + |y| (3/4) 2^-52 (1 + 2^-50): inside the bound that
+    // the table's twiddles (canonical, w/q correctly rounded) give.
+    __device__ T derive(T a, T c) const {
+#pragma clang fp contract(off)
+        const double w = mulmod(a.w, c.w, c.wq), k = w * u;
+        return {w, __builtin_fma(__builtin_fma(-k, q, w), u, k)};
+    }
     __device__ double mulmod(double y, double w, double wq) const { return f_mulmod(y, FPair{w, wq}, q); }
     __device__ double reduce(double x) const { return f_reduce(x, q, u); }
     __device__ V load(u64 x) const { return f_load(x); }
@@ -396,6 +412,103 @@ __global__ void __launch_bounds__(kThreads) ntt_rows(LimbSet ls, const void *__r
     }
 }
 
+// ------------------------------------------------ derived twiddles
+// Bit reversal is additive over disjoint bits, so W[z + c] = W[z] W[c]
+// whenever c < 2^k and the low k bits of z are zero; and W[y] = W[2y]^2 for
+// y < N/2 (brv(2y) = brv(y) / 2, brv(y) even).  The same holds for the
+// inverse table.  In the second and third register chunks of the single-pass
+// layouts a thread's twiddles of one stage are W[tb + c], c = 0 .. 2^(4-r)-1
+// (r the stage's register bit), with the low 4 - r bits of tb zero, and
+// consecutive stages' bases satisfy tb(b) = 2 tb(b + 1).  So one table word
+// per stage (forward) or per chunk (inverse) suffices: the rest are products
+// with W[2^k]^(+-1), visiting c in Gray-code order so that each twiddle is
+// one product away from the one before.  This replaces the chunks' dependent
+// table loads with arithmetic.
+template <class A>
+struct GrayC {
+    typename A::T up[4], dn[4];  // multiplier when bit k of c turns on / off
+};
+__device__ __forceinline__ double uniform_f64(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <class A>
+__device__ __forceinline__ GrayC<A> gray_constants(const A &ar, bool inv) {
+    GrayC<A> g;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const typename A::T f = ar.fw(1 << k), i = ar.iw(1 << k);
+        const typename A::T u = inv ? i : f, d = inv ? f : i;
+        g.up[k] = {uniform_f64(u.w), uniform_f64(u.wq)};
+        g.dn[k] = {uniform_f64(d.w), uniform_f64(d.wq)};
+    }
+    return g;
+}
+// first twiddle of the stage on line bit b (its index has the low bits that
+// number the thread's groups zero)
+__device__ __forceinline__ int stage_base(int L, int b, int X0, int G, int logM) {
+    return (1 << (logM - 1 - b)) + (G << (L - 1 - b)) + (X0 >> (b + 1));
+}
+// Forward stages on register bits NS-1 .. 0 of the 32 words v[k] at line
+// positions X0 + (k << blo); base[r] = W[stage_base(blo + r)].
+template <int NS, class A>
+__device__ __forceinline__ void fwd_chunk_d(typename A::V *v, const A &ar, const typename A::T *base,
+                                            const GrayC<A> &gc, bool fresh) {
+    static_assert(NS >= 1 && NS <= 5, "a chunk covers at most the 32 registers");
+    if (!fresh) {
+#pragma unroll
+        for (int k = 0; k < 32; k++) v[k] = ar.prep(v[k]);
+    }
+#pragma unroll
+    for (int r = NS - 1; r >= 0; r--) {
+        const int half = 1 << r;
+        typename A::T w = base[r];
+#pragma unroll
+        for (int i = 0; i < (32 >> (r + 1)); i++) {
+            const int g = i ^ (i >> 1);
+            if (i > 0) {
+                const int k = __builtin_ctz(i);
+                w = ar.derive(w, (g >> k) & 1 ? gc.up[k] : gc.dn[k]);
+            }
+#pragma unroll
+            for (int j = 0; j < half; j++) ar.ct(v[(g << (r + 1)) + j], v[(g << (r + 1)) + j + half], w);
+        }
+    }
+}
+template <int NS, class A>
+__device__ __forceinline__ void fwd_bases(typename A::T *base, const A &ar, int L, int blo, int X0, int G, int logM) {
+#pragma unroll
+    for (int r = 0; r < NS; r++) base[r] = ar.fw(stage_base(L, blo + r, X0, G, logM));
+}
+// Inverse stages on register bits 0 .. NS-1; base = Winv[stage_base(blo)]
+// (each later stage's base is the square of the one before).
+template <int NS, class A>
+__device__ __forceinline__ void inv_chunk_d(typename A::V *v, const A &ar, typename A::T base, const GrayC<A> &gc,
+                                            bool fresh) {
+    static_assert(NS >= 1 && NS <= 5, "a chunk covers at most the 32 registers");
+    if (!fresh) {
+#pragma unroll
+        for (int k = 0; k < 32; k++) v[k] = ar.prep(v[k]);
+    }
+#pragma unroll
+    for (int r = 0; r < NS; r++) {
+        if (r > 0) base = ar.derive(base, base);
+        const int half = 1 << r;
+        typename A::T w = base;
+#pragma unroll
+        for (int i = 0; i < (32 >> (r + 1)); i++) {
+            const int g = i ^ (i >> 1);
+            if (i > 0) {
+                const int k = __builtin_ctz(i);
+                w = ar.derive(w, (g >> k) & 1 ? gc.up[k] : gc.dn[k]);
+            }
+#pragma unroll
+            for (int j = 0; j < half; j++) ar.gs(v[(g << (r + 1)) + j], v[(g << (r + 1)) + j + half], w, r & 1);
+        }
+    }
+}
+
 // ------------------------------------------------------------ single pass
 // One workgroup of N/32 threads transforms a whole limb (N = 2^12 .. 2^15):
 // 32 words per thread in registers, three register chunks on the bit ranges
@@ -542,6 +655,11 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
     const int ra = lds_round<SP, BA>(x1), rb = lds_round<SP, BB>(x3);
     const int pa1 = lds_pos<SP, BA>(x1), pa2 = lds_pos<SP, BA>(x2);  // exchange 1-2 bases
     const int pb2 = lds_pos<SP, BB>(x2), pb3 = lds_pos<SP, BB>(x3);  // exchange 2-3 bases
+    // chunks 2 and 3 derive their twiddles (fp64 arithmetic); their table
+    // words are loaded before the exchange in front of them
+    constexpr bool DER = A::kDerive;
+    GrayC<A> gc;
+    if constexpr (DER) gc = gray_constants(ar, INV);
     if (!INV) {
 #pragma unroll
         for (int k = 0; k < 32; k++) v[k] = ar.load(ain[x1 + (k << (LOGN - 5))]);
@@ -549,9 +667,10 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
         // with an epilogue, the next chunk's first two stages' twiddles travel
         // during the exchange (timed faster there; the plain transform, with
         // fewer registers to spare, was timed slower with it)
-        constexpr int NPRE = EPI != 0 ? 2 : 0;
-        typename A::T pre[3];
+        constexpr int NPRE = DER ? 0 : EPI != 0 ? 2 : 0;
+        typename A::T pre[3], b2[5];
         if constexpr (NPRE > 0) fwd_twiddles<5, NPRE>(pre, ar, LOGN, C3, x2, hh, LOGM);
+        if constexpr (DER) fwd_bases<5>(b2, ar, LOGN, C3, x2, hh, LOGM);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (ra == r) {
@@ -565,7 +684,10 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             }
             __syncthreads();
         }
-        fwd_chunk<5, A, NPRE>(v, ar, LOGN, C3, x2, hh, LOGM, false, pre);
+        if constexpr (DER) fwd_chunk_d<5>(v, ar, b2, gc, false);
+        else fwd_chunk<5, A, NPRE>(v, ar, LOGN, C3, x2, hh, LOGM, false, pre);
+        typename A::T b3[C3];
+        if constexpr (DER) fwd_bases<C3>(b3, ar, LOGN, 0, x3, hh, LOGM);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (rb == r) {
@@ -579,8 +701,12 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             }
             __syncthreads();
         }
+        if constexpr (DER) {
+            fwd_chunk_d<C3>(v, ar, b3, gc, false);
+        } else {
 #pragma unroll
-        for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), hh, LOGM, false);
+            for (int j = 0; j < G3; j++) fwd_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), hh, LOGM, false);
+        }
         // the exchange above ended with a barrier: LDS is free for the wave tiles
         const int wave = t >> 6, lane = t & 63;
         if constexpr (EPI != 0) {
@@ -600,8 +726,15 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
         const int wave = t >> 6, lane = t & 63;
         load_block(ain + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
         __syncthreads();  // every wave is done with its tile before the exchanges reuse LDS
+        if constexpr (DER) {
+            inv_chunk_d<C3>(v, ar, ar.iw(stage_base(LOGN, 0, x3, hh, LOGM)), gc, true);
+        } else {
 #pragma unroll
-        for (int j = 0; j < G3; j++) inv_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), hh, LOGM, false, true);
+            for (int j = 0; j < G3; j++)
+                inv_chunk<C3>(v + (j << C3), ar, LOGN, 0, x3 + (j << C3), hh, LOGM, false, true);
+        }
+        typename A::T b2{};
+        if constexpr (DER) b2 = ar.iw(stage_base(LOGN, C3, x2, hh, LOGM));
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (rb == r) {
@@ -615,7 +748,8 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             }
             __syncthreads();
         }
-        inv_chunk<5>(v, ar, LOGN, C3, x2, hh, LOGM, false, false);
+        if constexpr (DER) inv_chunk_d<5>(v, ar, b2, gc, false);
+        else inv_chunk<5>(v, ar, LOGN, C3, x2, hh, LOGM, false, false);
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (ra == r) {
