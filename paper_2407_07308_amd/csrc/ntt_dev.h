@@ -483,7 +483,8 @@ __device__ __forceinline__ void fwd_bases(typename A::T *base, const A &ar, int 
 }
 // Inverse stages on register bits 0 .. NS-1; base = Winv[stage_base(blo)]
 // (each later stage's base is the square of the one before).
-template <int NS, class A>
+// SCALE: the last stage is the transform's final one (m = 1), N^-1 folded in.
+template <int NS, class A, bool SCALE = false>
 __device__ __forceinline__ void inv_chunk_d(typename A::V *v, const A &ar, typename A::T base, const GrayC<A> &gc,
                                             bool fresh) {
     static_assert(NS >= 1 && NS <= 5, "a chunk covers at most the 32 registers");
@@ -493,8 +494,13 @@ __device__ __forceinline__ void inv_chunk_d(typename A::V *v, const A &ar, typen
     }
 #pragma unroll
     for (int r = 0; r < NS; r++) {
-        if (r > 0) base = ar.derive(base, base);
         const int half = 1 << r;
+        if (SCALE && r == NS - 1) {
+#pragma unroll
+            for (int j = 0; j < half; j++) ar.gs_last(v[j], v[j + half]);
+            break;
+        }
+        if (r > 0) base = ar.derive(base, base);
         typename A::T w = base;
 #pragma unroll
         for (int i = 0; i < (32 >> (r + 1)); i++) {
@@ -663,6 +669,8 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
     if (!INV) {
 #pragma unroll
         for (int k = 0; k < 32; k++) v[k] = ar.load(ain[x1 + (k << (LOGN - 5))]);
+        // the first chunk's twiddles are the same for every thread: from the
+        // table (deriving them was timed slower here, faster in the inverse)
         fwd_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, true);
         // with an epilogue, the next chunk's first two stages' twiddles travel
         // during the exchange (timed faster there; the plain transform, with
@@ -750,6 +758,8 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
         }
         if constexpr (DER) inv_chunk_d<5>(v, ar, b2, gc, false);
         else inv_chunk<5>(v, ar, LOGN, C3, x2, hh, LOGM, false, false);
+        typename A::T b1{};
+        if constexpr (DER) b1 = ar.iw(stage_base(LOGN, LOGN - 5, x1, hh, LOGM));
 #pragma unroll
         for (int r = 0; r < NSPLIT; r++) {
             if (ra == r) {
@@ -763,7 +773,8 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             }
             __syncthreads();
         }
-        inv_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, PL == 0, false);
+        if constexpr (DER) inv_chunk_d<5, A, PL == 0>(v, ar, b1, gc, false);
+        else inv_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, PL == 0, false);
 #pragma unroll
         for (int k = 0; k < 32; k++) a[x1 + (k << (LOGN - 5))] = ar.store(v[k]);
     }
