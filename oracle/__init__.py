@@ -540,6 +540,57 @@ class CtEvaluator:
     def to_level(self, a, lv):
         return self.o.to_level(a, lv)
 
+    def rotate(self, a, step):
+        return self.o.rotate(a, step)
+
+
+class SlotEvaluator:
+    """Plain slot vectors over F_p with the evaluator interface: M values,
+    two rows of M/2 slots, rotate(x, s)[j] = x[j + s] within the row (what the
+    automorphism x -> x^(5^s) does to the slots, see ``slot_roots``).  For
+    checking the slot-packed schedules without encryption."""
+
+    def __init__(self, p, M):
+        self.p, self.M = p, M
+        self.mults = 0
+        self.rotations = 0
+        self.depth_of = {}
+
+    def _arr(self, a):
+        return np.asarray(a, dtype=np.int64) % self.p
+
+    def mul(self, a, b):
+        self.mults += 1
+        return self._arr(a) * self._arr(b) % self.p
+
+    def mul_add(self, a, b, c):
+        self.mults += 1
+        return (self._arr(a) * self._arr(b) + self._arr(c)) % self.p
+
+    def add(self, a, b):
+        return (self._arr(a) + self._arr(b)) % self.p
+
+    def sub(self, a, b):
+        return (self._arr(a) - self._arr(b)) % self.p
+
+    def mul_scalar(self, a, c):
+        return self._arr(a) * c % self.p
+
+    def add_const(self, a, c):
+        return (self._arr(a) + c) % self.p
+
+    def level(self, a):
+        return 0
+
+    def to_level(self, a, lv):
+        return a
+
+    def rotate(self, a, step):
+        self.rotations += 1
+        h = self.M // 2
+        x = self._arr(a).reshape(2, h)
+        return np.roll(x, -step, axis=1).reshape(-1)
+
 
 def lt_univariate(ev, Z, p: int):
     """Paterson-Stockmeyer evaluation of f(Z) for p - 1 = 2^e (p = 17, 257).
@@ -738,6 +789,74 @@ def compare_lt_bivariate(ev, a_digits, b_digits, p: int):
     for i in range(len(lts) - 2, -1, -1):
         acc = ev.mul_add(eqs[i], acc, lts[i])
     return acc
+
+
+# ---------------------------------------------------------------------------
+# slot-packed digits (Background, "Word-wise Universal FHE Scheme": the
+# lexicographic combination by ShiftMul -- shift the ciphertext and multiply
+# by the equality result -- and ShiftAdd -- a summation done by shifting)
+# ---------------------------------------------------------------------------
+
+def digit_lt_eq(ev, a, b, p: int, circuit: str = "univariate"):
+    """Per-slot (LT, EQ) of two ciphertexts of digits: the univariate f(a - b)
+    (digits in [0, (p-1)/2]) or the bivariate interpolant (any digits), with
+    EQ = 1 - (a - b)^(p-1) from the same schedule."""
+    if circuit == "bivariate":
+        f, top = lt_bivariate(ev, a, b, p)
+    else:
+        f, top = lt_univariate(ev, ev.sub(a, b), p)
+    return f, eq_from_top(ev, top)
+
+
+def compare_lt_packed(ev, a, b, p: int, l: int, circuit: str = "univariate"):
+    """LT of integers packed l digits each into consecutive slots of one
+    ciphertext: integer k of a slot row at positions k l .. k l + l - 1, most
+    significant digit first, l a power of two dividing the row length.
+
+    Per-slot (L, E) = (LT, EQ) of the digits, then one round per shift
+    s = 1, 2, ..., l/2 (rot(X, s) holds at slot j the value of slot j + s of
+    its row):
+        L <- L + E rot(L, s)     (ShiftMul: shift, multiply by EQ; ShiftAdd)
+        E <- E rot(E, s)         (skipped in the last round)
+    After the round with shift s, slot k l + i (i a multiple of 2s) holds the
+    lexicographic (LT, EQ) of digits i .. i + 2s - 1 of integer k, so slot k l
+    ends with the integer's LT (the other slots hold values of no meaning).
+    Each L update is one multiply-accumulate."""
+    assert l >= 1 and l & (l - 1) == 0, "l must be a power of two"
+    L, E = digit_lt_eq(ev, a, b, p, circuit)
+    s = 1
+    while s < l:
+        Lr = ev.rotate(L, s)
+        last = 2 * s >= l
+        Er = None if last else ev.rotate(E, s)
+        L = ev.mul_add(E, Lr, L)
+        if not last:
+            E = ev.mul(E, Er)
+        s *= 2
+    return L
+
+
+def tournament(ev, x, p: int, k: int, want_max: bool = False, circuit: str = "univariate"):
+    """Minimum (maximum) over windows of k = 2^r consecutive slots of a row,
+    by r rounds of comparisons between the ciphertext and its own shifts:
+    round t, s = 2^t:
+        Y = rot(X, s);  L = LT(X, Y) per slot;
+        X <- Y + L (X - Y)   (min)   or   X <- X + L (Y - X)   (max)
+    with X and Y first brought to L's level.  After the rounds slot j holds
+    the min (max) of slots j .. j + k - 1 of its row (cyclically): the
+    windows starting at multiples of k are tournaments over disjoint arrays
+    of k values, the winner landing in the array's first slot."""
+    assert k >= 1 and k & (k - 1) == 0, "k must be a power of two"
+    X = x
+    s = 1
+    while s < k:
+        Y = ev.rotate(X, s)
+        L, _ = digit_lt_eq(ev, X, Y, p, circuit)
+        lv = ev.level(L)
+        Xl, Yl = ev.to_level(X, lv), ev.to_level(Y, lv)
+        X = ev.mul_add(L, ev.sub(Yl, Xl), Xl) if want_max else ev.mul_add(L, ev.sub(Xl, Yl), Yl)
+        s *= 2
+    return X
 
 
 def to_digits(values, base: int, ndigits: int):
