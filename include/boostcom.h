@@ -302,6 +302,45 @@ int bc_compare_bivariate(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, cons
 int bc_compare_levels_circuit(const bc_ctx *ctx, int32_t circuit, int32_t in_level, int32_t ndigits,
                               int32_t *lt_level, int32_t *maxmin_level);
 
+/* Slot-packed comparison (paper, Background, "Word-wise Universal FHE
+ * Scheme": the digits of one integer sit in slots of one ciphertext, and their
+ * LT and EQ are combined in lexicographic order by ShiftMul -- shift the
+ * ciphertext, multiply by the equality result -- and ShiftAdd -- a summation
+ * done by shifting).  a, b: batches of the same count and level whose slots
+ * hold base-p digits: in each slot row (M/2 slots, see bc_rotate) integer k
+ * occupies slots k*l .. k*l + l - 1, most significant digit first;
+ * l = digits_per_int, a power of two up to M/2 (BC_ERR_ARG).  Per-slot LT
+ * and EQ by `circuit` (BC_CIRCUIT_UNIVARIATE: digits in [0, (p-1)/2];
+ * BC_CIRCUIT_BIVARIATE: any digit), then log2(l) rounds with shifts
+ * s = 1, 2, ..., l/2:  L <- L + E * rot(L, s),  E <- E * rot(E, s).
+ * lt_out (caller-allocated, same count, level from bc_packed_levels): slot
+ * k*l of every row decrypts to [a_k < b_k]; the other slots hold values of
+ * no meaning.  keys must hold rotation keys for steps 1, 2, ..., l/2
+ * (BC_ERR_KEY).  Depth: the digit circuit's plus log2(l) (BC_ERR_LEVEL when
+ * the estimated noise would exceed a level's budget).  Runs on `stream` with
+ * workspace from the context's pool; never captured into a graph. */
+int bc_compare_packed(bc_ctx *ctx, const bc_keys *keys, int32_t circuit, int32_t digits_per_int, const bc_ctb *a,
+                      const bc_ctb *b, bc_ctb *lt_out, void *stream);
+/* Level of bc_compare_packed's output for inputs at in_level (fresh noise). */
+int bc_packed_levels(const bc_ctx *ctx, int32_t circuit, int32_t in_level, int32_t digits_per_int,
+                     int32_t *lt_level);
+
+/* Tournament over small arrays of slots (same passage: comparisons between a
+ * ciphertext and its own shifts).  in: a batch whose slots hold digits (one
+ * digit per value, ranges as for bc_compare_packed's circuits).  For
+ * window = 2^r (a power of two up to M/2, BC_ERR_ARG), r rounds with
+ * s = 1, 2, ..., window/2: Y = rot(X, s), L = LT(X, Y) per slot, then
+ * X <- Y + L (X - Y) (minimum) or, with want_max != 0, X <- X + L (Y - X).
+ * out (same count, level from bc_tournament_levels): slot j decrypts to the
+ * minimum (maximum) of slots j .. j + window - 1 of its row, cyclically; the
+ * slots at multiples of `window` hold the winners of disjoint arrays of
+ * `window` values.  Rotation keys for 1, 2, ..., window/2 (BC_ERR_KEY);
+ * BC_ERR_LEVEL as above.  Runs on `stream`, never captured. */
+int bc_tournament(bc_ctx *ctx, const bc_keys *keys, int32_t circuit, int32_t window, int32_t want_max,
+                  const bc_ctb *in, bc_ctb *out, void *stream);
+/* Level of bc_tournament's output for an input at in_level (fresh noise). */
+int bc_tournament_levels(const bc_ctx *ctx, int32_t circuit, int32_t in_level, int32_t window, int32_t *out_level);
+
 /* Mixed ring sizes (paper, The Design of BoostCom, "Multi-Level
  * Heterogeneous Parallelization": independent comparisons overlapped to fill
  * the GPU; "GPU-related Optimizations": work batched onto the device at

@@ -90,6 +90,10 @@ _SIGS = {
     "bc_compare_max_min": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_compare_bivariate": (_I, [_V, _V, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
     "bc_compare_levels_circuit": (_I, [_V, _I, _I, _I, _P(_I), _P(_I)]),
+    "bc_compare_packed": (_I, [_V, _V, _I, _I, _P(bc_ctb), _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_packed_levels": (_I, [_V, _I, _I, _I, _P(_I)]),
+    "bc_tournament": (_I, [_V, _V, _I, _I, _I, _P(bc_ctb), _P(bc_ctb), _V]),
+    "bc_tournament_levels": (_I, [_V, _I, _I, _I, _P(_I)]),
     "bc_noise_compare_circuit": (_I, [_P(bc_params), _I, _I, ctypes.c_double, _I, _P(ctypes.c_double),
                                       _P(ctypes.c_double), _P(_I), _P(_I)]),
     "bc_set_exec_mode": (_I, [_V, _I]),
@@ -381,6 +385,38 @@ class Context:
         _check(self.L.bc_compare_levels_circuit(self.handle, circuit, in_level, ndigits, ctypes.byref(lt),
                                                 ctypes.byref(mm)))
         return lt.value, mm.value
+
+    def packed_levels(self, in_level: int, digits_per_int: int, circuit: int = BC_CIRCUIT_UNIVARIATE) -> int:
+        lv = ctypes.c_int32()
+        _check(self.L.bc_packed_levels(self.handle, circuit, in_level, digits_per_int, ctypes.byref(lv)))
+        return lv.value
+
+    def compare_packed(self, keys: Keys, a: Batch, b: Batch, digits_per_int: int,
+                       circuit: int = BC_CIRCUIT_UNIVARIATE, out: Batch = None) -> Batch:
+        """LT of slot-packed integers (``bc_compare_packed``): valid at the first
+        slot of every block of ``digits_per_int`` slots."""
+        if out is None:
+            out = self.new_batch(a.count, self.packed_levels(a.level, digits_per_int, circuit), 2)
+        ca, cb, co = a.ctb(), b.ctb(), out.ctb()
+        _check(self.L.bc_compare_packed(self.handle, keys.handle, circuit, digits_per_int, ctypes.byref(ca),
+                                        ctypes.byref(cb), ctypes.byref(co), _stream()))
+        return out.take(co)
+
+    def tournament_levels(self, in_level: int, window: int, circuit: int = BC_CIRCUIT_UNIVARIATE) -> int:
+        lv = ctypes.c_int32()
+        _check(self.L.bc_tournament_levels(self.handle, circuit, in_level, window, ctypes.byref(lv)))
+        return lv.value
+
+    def tournament(self, keys: Keys, x: Batch, window: int, want_max: bool = False,
+                   circuit: int = BC_CIRCUIT_UNIVARIATE, out: Batch = None) -> Batch:
+        """Minimum (maximum) over every window of ``window`` slots of a row
+        (``bc_tournament``)."""
+        if out is None:
+            out = self.new_batch(x.count, self.tournament_levels(x.level, window, circuit), 2)
+        cx, co = x.ctb(), out.ctb()
+        _check(self.L.bc_tournament(self.handle, keys.handle, circuit, window, 1 if want_max else 0,
+                                    ctypes.byref(cx), ctypes.byref(co), _stream()))
+        return out.take(co)
 
     def set_exec_mode(self, mode: int):
         _check(self.L.bc_set_exec_mode(self.handle, mode))

@@ -911,6 +911,96 @@ int bc_compare_levels(const bc_ctx *ctx, int32_t in_level, int32_t ndigits, int3
     return bc_compare_levels_circuit(ctx, BC_CIRCUIT_UNIVARIATE, in_level, ndigits, lt_level, maxmin_level);
 }
 
+int bc_packed_levels(const bc_ctx *ctx, int32_t circuit, int32_t in_level, int32_t digits_per_int, int32_t *lt_level) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(circuit == BC_CIRCUIT_UNIVARIATE || circuit == BC_CIRCUIT_BIVARIATE, BC_ERR_ARG, "unknown circuit");
+        BC_REQUIRE(in_level >= 0 && in_level < ctx->nQ, BC_ERR_ARG, "bad level");
+        BC_REQUIRE(digits_per_int >= 1 && (digits_per_int & (digits_per_int - 1)) == 0 &&
+                       digits_per_int <= ctx->M / 2,
+                   BC_ERR_ARG, "digits per integer must be a power of two up to half the slots");
+        int lv = 0;
+        double nb = 0;
+        packed_levels(ctx->noise, in_level, ctx->noise.fresh(), digits_per_int, circuit, &lv, &nb);
+        if (lt_level) *lt_level = lv;
+    });
+}
+
+int bc_tournament_levels(const bc_ctx *ctx, int32_t circuit, int32_t in_level, int32_t window, int32_t *out_level) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(circuit == BC_CIRCUIT_UNIVARIATE || circuit == BC_CIRCUIT_BIVARIATE, BC_ERR_ARG, "unknown circuit");
+        BC_REQUIRE(in_level >= 0 && in_level < ctx->nQ, BC_ERR_ARG, "bad level");
+        BC_REQUIRE(window >= 1 && (window & (window - 1)) == 0 && window <= ctx->M / 2, BC_ERR_ARG,
+                   "the window must be a power of two up to half the slots");
+        int lv = 0;
+        double nb = 0;
+        tournament_levels(ctx->noise, in_level, ctx->noise.fresh(), window, circuit, &lv, &nb);
+        if (out_level) *out_level = lv;
+    });
+}
+
+namespace {
+// BC_ERR_KEY unless `keys` hold rotation keys for steps 1, 2, 4, ... < len.
+void require_shift_keys(const bc_keys *k, int len) {
+    for (int s = 1; s < len; s *= 2) {
+        bool have = false;
+        for (int i = 0; i < k->ngal; i++) have = have || k->steps[i] == s;
+        BC_REQUIRE(have, BC_ERR_KEY, "missing a rotation key for a shift of the packed schedule");
+    }
+}
+}  // namespace
+
+int bc_compare_packed(bc_ctx *ctx, const bc_keys *keys, int32_t circuit, int32_t digits_per_int, const bc_ctb *a,
+                      const bc_ctb *b, bc_ctb *lt_out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(a && b && lt_out, BC_ERR_ARG, "null batch");
+        const CtB x = from_abi(ctx, a), y = from_abi(ctx, b), o = from_abi(ctx, lt_out);
+        BC_REQUIRE(x.count == y.count && x.level == y.level && x.ncomp == 2 && y.ncomp == 2, BC_ERR_ARG,
+                   "packed operands: same count and level, 2 components");
+        BC_REQUIRE(digits_per_int >= 1 && (digits_per_int & (digits_per_int - 1)) == 0 &&
+                       digits_per_int <= ctx->M / 2,
+                   BC_ERR_ARG, "digits per integer must be a power of two up to half the slots");
+        int lv = 0;
+        double nb = 0;
+        packed_levels(ctx->noise, x.level, std::max(x.noise, y.noise), digits_per_int, circuit, &lv, &nb);
+        BC_REQUIRE(o.count == x.count && o.level == lv && o.ncomp == 2, BC_ERR_ARG,
+                   "output batch: wrong count, level or components");
+        require_shift_keys(keys, digits_per_int);
+        StreamScope sc(stream);
+        const hipStream_t st = (hipStream_t)stream;
+        const CtB r = compare_packed(ctx, keys, x, y, digits_per_int, circuit, st);
+        copy_ct(ctx, r, o, st);
+        lt_out->noise_bits = (float)nb;
+    });
+}
+
+int bc_tournament(bc_ctx *ctx, const bc_keys *keys, int32_t circuit, int32_t window, int32_t want_max,
+                  const bc_ctb *in, bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(in && out, BC_ERR_ARG, "null batch");
+        const CtB x = from_abi(ctx, in), o = from_abi(ctx, out);
+        BC_REQUIRE(x.ncomp == 2, BC_ERR_ARG, "tournament input: 2 components");
+        BC_REQUIRE(window >= 1 && (window & (window - 1)) == 0 && window <= ctx->M / 2, BC_ERR_ARG,
+                   "the window must be a power of two up to half the slots");
+        int lv = 0;
+        double nb = 0;
+        tournament_levels(ctx->noise, x.level, x.noise, window, circuit, &lv, &nb);
+        BC_REQUIRE(o.count == x.count && o.level == lv && o.ncomp == 2, BC_ERR_ARG,
+                   "output batch: wrong count, level or components");
+        require_shift_keys(keys, window);
+        StreamScope sc(stream);
+        const hipStream_t st = (hipStream_t)stream;
+        const CtB r = tournament(ctx, keys, x, window, want_max != 0, circuit, st);
+        copy_ct(ctx, r, o, st);
+        out->noise_bits = (float)nb;
+    });
+}
+
 int bc_compare_bivariate(bc_ctx *ctx, const bc_keys *keys, int32_t ndigits, const bc_ctb *a_digits,
                          const bc_ctb *b_digits, bc_ctb *lt_out, bc_ctb *max_out, bc_ctb *min_out, void *stream) {
     return guard([&] {

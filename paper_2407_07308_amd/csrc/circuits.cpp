@@ -85,6 +85,11 @@ struct NoiseEval {
         return o;
     }
     V sub(V a, V b) { return add(a, b); }
+    V rotate(V a, int) {
+        V o{a.lv, m->rotate(a.lv, a.nb)};
+        m->require(o.lv, o.nb, "comparison circuit");
+        return o;
+    }
     V mul_scalar(V a, int64_t c) { return V{a.lv, m->scalar(a.nb, (double)std::llabs(c))}; }
     V add_const(V a, int64_t) { return V{a.lv, m->add_const(a.nb)}; }
     int level(V a) { return a.lv; }
@@ -163,6 +168,11 @@ struct DevEval {
     V mul_scalar(const V &a, int64_t v) {
         V o = alloc_ct(c, a.count, a.level, a.ncomp);
         each(o, a, nullptr, [&](const V &oo, const V &x, const V &) { bc::mul_scalar(c, x, v, oo, st); });
+        return o;
+    }
+    V rotate(const V &a, int steps) {
+        V o = alloc_ct(c, a.count, a.level, 2);
+        each(o, a, nullptr, [&](const V &oo, const V &x, const V &) { bc::rotate(c, k, x, steps, oo, st); });
         return o;
     }
     V add_const(const V &a, int64_t v) {
@@ -505,9 +515,137 @@ std::pair<typename Ev::V, typename Ev::V> lt_bivariate(Ev &ev, const typename Ev
     return {LT, top};
 }
 
+// ------------------------------------------------------- slot-packed digits
+// (Background, "Word-wise Universal FHE Scheme": the digits' LT and EQ
+// combined by ShiftMul -- shift the ciphertext, multiply by the equality
+// result -- and ShiftAdd -- a summation done by shifting)
+
+// Per-slot (LT, Z^(p-1)) of the digit batches X, Y (`count` ciphertexts
+// each) by the chosen digit circuit.
+template <class Ev, class BT>
+std::pair<typename Ev::V, typename Ev::V> digit_circuit(Ev &ev, const typename Ev::V &X, const typename Ev::V &Y,
+                                                        int count, int circuit, u64 p, const BT &biv, int64_t ctop) {
+    const typename Ev::V Z = ev.sub(X, Y);
+    if (circuit == BC_CIRCUIT_BIVARIATE) return lt_bivariate(ev, Z, ev.add(X, Y), count, (int)p - 1, biv);
+    return lt_poly(ev, Z, ps_shape(p), count, ctop);
+}
+
+// Integers packed l digits each into consecutive slots of a row (most
+// significant first): from the per-slot L = LT and E = 1 - Z^(p-1), one round
+// per shift s = 1, 2, ..., l/2 (rotation by s brings slot j + s of the row to
+// slot j):
+//   L <- L + E rot(L, s)   (one multiply-accumulate),   E <- E rot(E, s)
+// (E not in the last round).  After the round with shift s, slot k l + i
+// (i a multiple of 2s) holds the lexicographic (LT, EQ) of digits i .. i+2s-1
+// of integer k: slot k l ends with integer k's LT.
+template <class Ev>
+typename Ev::V packed_tree(Ev &ev, typename Ev::V L, const typename Ev::V &top, int l) {
+    typedef typename Ev::V V;
+    V E = ev.add_const(ev.mul_scalar(top, -1), 1);
+    for (int s = 1; s < l; s *= 2) {
+        const bool last = 2 * s >= l;
+        const V Lr = ev.rotate(L, s);
+        V Er;
+        if (!last) Er = ev.rotate(E, s);
+        L = ev.mul_add(E, Lr, L);
+        if (!last) E = ev.mul(E, Er);
+    }
+    return L;
+}
+
+// Minimum (maximum) over windows of `window` = 2^r slots of a row: round t
+// (s = 2^t) compares X with Y = rot(X, s) slot by slot and keeps
+// Y + L (X - Y) (min) or X + L (Y - X) (max), X and Y brought to L's level.
+// Slot j ends with the min (max) of slots j .. j + window - 1 of its row
+// (cyclically); windows at multiples of `window` are disjoint tournaments.
+template <class Ev, class BT>
+typename Ev::V tournament_rounds(Ev &ev, typename Ev::V X, int count, int window, bool want_max, int circuit, u64 p,
+                                 const BT &biv, int64_t ctop) {
+    typedef typename Ev::V V;
+    for (int s = 1; s < window; s *= 2) {
+        const V Y = ev.rotate(X, s);
+        const V L = digit_circuit(ev, X, Y, count, circuit, p, biv, ctop).first;
+        const int lv = ev.level(L);
+        const V Xl = ev.to_level(X, lv), Yl = ev.to_level(Y, lv);
+        X = want_max ? ev.mul_add(L, ev.sub(Yl, Xl), Xl) : ev.mul_add(L, ev.sub(Xl, Yl), Yl);
+    }
+    return X;
+}
+
+void check_packed_args(const bc_ctx *c, int circuit, int len, const char *what) {
+    BC_REQUIRE(circuit == BC_CIRCUIT_UNIVARIATE || circuit == BC_CIRCUIT_BIVARIATE, BC_ERR_ARG, "unknown circuit");
+    BC_REQUIRE(len >= 1 && (len & (len - 1)) == 0 && len <= c->M / 2, BC_ERR_ARG, what);
+}
+
+// The digit circuit's tables on the device side.
+struct DevDigit {
+    BivTable biv{};
+    int64_t ctop = 0;
+};
+DevDigit dev_digit(bc_ctx *c, int circuit) {
+    DevDigit d;
+    if (circuit == BC_CIRCUIT_BIVARIATE) {
+        d.biv = bivariate_table(c);
+        BC_REQUIRE(use_fp64(c), BC_ERR_PARAM, "the bivariate circuit needs primes below 2^50");
+    } else {
+        (void)ps_shape(c->p);
+        if (c->lt_c.empty()) {
+            std::lock_guard<std::mutex> g(c->table_mu);
+            if (c->lt_c.empty()) c->lt_c = lt_coefficients(c->p);
+        }
+        d.ctop = c->lt_c[c->p - 1];
+    }
+    return d;
+}
+BivNoise noise_biv(const NoiseModel &m, int circuit) {
+    const u64 p = (u64)m.p;
+    if (circuit == BC_CIRCUIT_BIVARIATE)
+        BC_REQUIRE(p >= 3 && p < 512 && ((p - 1) & (p - 2)) == 0, BC_ERR_PARAM,
+                   "the bivariate circuit needs p - 1 a power of two and p < 512");
+    return bivariate_noise(p);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- entry points
+
+CtB compare_packed(bc_ctx *c, const bc_keys *k, const CtB &A, const CtB &B, int l, int circuit, hipStream_t st) {
+    check_packed_args(c, circuit, l, "digits per integer must be a power of two up to half the slots");
+    BC_REQUIRE(A.count == B.count && A.level == B.level && A.ncomp == 2 && B.ncomp == 2, BC_ERR_ARG,
+               "packed operands: same count and level, 2 components");
+    DevEval ev{c, k, st, c->exec_mode == BC_EXEC_PER_OP};
+    const DevDigit d = dev_digit(c, circuit);
+    const auto fz = digit_circuit(ev, A, B, A.count, circuit, c->p, d.biv, d.ctop);
+    return packed_tree(ev, fz.first, fz.second, l);
+}
+
+CtB tournament(bc_ctx *c, const bc_keys *k, const CtB &X, int window, bool want_max, int circuit, hipStream_t st) {
+    check_packed_args(c, circuit, window, "the window must be a power of two up to half the slots");
+    BC_REQUIRE(X.ncomp == 2, BC_ERR_ARG, "tournament input: 2 components");
+    DevEval ev{c, k, st, c->exec_mode == BC_EXEC_PER_OP};
+    const DevDigit d = dev_digit(c, circuit);
+    return tournament_rounds(ev, X, X.count, window, want_max, circuit, c->p, d.biv, d.ctop);
+}
+
+void packed_levels(const NoiseModel &m, int in_level, double in_noise, int l, int circuit, int *lv, double *nb) {
+    NoiseEval ev{&m};
+    const NoiseEval::V in{in_level, in_noise};
+    m.require(in_level, in_noise, "comparison input");
+    const auto fz = digit_circuit(ev, in, in, 1, circuit, (u64)m.p, noise_biv(m, circuit), (int64_t)(m.p - 1) / 2);
+    const NoiseEval::V L = packed_tree(ev, fz.first, fz.second, l);
+    *lv = L.lv;
+    *nb = L.nb;
+}
+
+void tournament_levels(const NoiseModel &m, int in_level, double in_noise, int window, int circuit, int *lv,
+                       double *nb) {
+    NoiseEval ev{&m};
+    m.require(in_level, in_noise, "tournament input");
+    const NoiseEval::V X = tournament_rounds(ev, NoiseEval::V{in_level, in_noise}, 1, window, false, circuit,
+                                             (u64)m.p, noise_biv(m, circuit), (int64_t)(m.p - 1) / 2);
+    *lv = X.lv;
+    *nb = X.nb;
+}
 
 CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, bool want_mm, hipStream_t st,
                       int circuit) {

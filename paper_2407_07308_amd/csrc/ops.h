@@ -107,6 +107,17 @@ struct CompareResult {
 // Paterson-Stockmeyer schedule) or BC_CIRCUIT_BIVARIATE (digits in [0, p-1])
 CompareResult compare(bc_ctx *c, const bc_keys *k, int ndig, const CtB *A, const CtB *B, bool want_mm, hipStream_t st,
                       int circuit = BC_CIRCUIT_UNIVARIATE);
+// Slot-packed integers (l digits each in consecutive slots of a row, most
+// significant first): LT valid at each integer's first slot.  Needs rotation
+// keys for steps 1, 2, ..., l/2.
+CtB compare_packed(bc_ctx *c, const bc_keys *k, const CtB &A, const CtB &B, int l, int circuit, hipStream_t st);
+// Minimum (want_max: maximum) over every window of `window` consecutive
+// slots of a row, at the window's first slot.  Rotation keys 1, 2, ..., window/2.
+CtB tournament(bc_ctx *c, const bc_keys *k, const CtB &X, int window, bool want_max, int circuit, hipStream_t st);
+// Output level and noise estimate of those two (BC_ERR_LEVEL when too deep).
+void packed_levels(const NoiseModel &m, int in_level, double in_noise, int l, int circuit, int *lv, double *nb);
+void tournament_levels(const NoiseModel &m, int in_level, double in_noise, int window, int circuit, int *lv,
+                       double *nb);
 // Levels and noise estimates of the outputs of a comparison of inputs at
 // in_level with noise in_noise; BC_ERR_LEVEL when a step of the circuit would
 // exceed its level's noise budget (the circuit is deeper than the chain).
