@@ -50,7 +50,10 @@ def parse():
                     help="uint16 only: skip the mixed-N, serving and bivariate keys of the JSON line")
     ap.add_argument("--extra-window", type=float, default=3.0, help="serving key of the default line: seconds of arrivals")
     ap.add_argument("--biv-groups", type=int, default=4, help="bivariate: groups of 128 uint16 pairs")
-    ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate", "bivariate"], default="uint16",
+    ap.add_argument("--packed-cts", type=int, default=64,
+                    help="packed: ciphertexts per batch (32 uint16 integers each)")
+    ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate", "bivariate", "packed"],
+                    default="uint16",
                     help="uint16: LT+max+min at N=2^15 (default); mixed: 256 single-digit pairs over "
                          "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream; "
                          "rotate: slot rotations of 192 ciphertexts at N=2^15")
@@ -87,6 +90,8 @@ def main():
         return print(json.dumps(serve(a)))
     if a.workload == "bivariate":
         return print(json.dumps(bivariate(a)))
+    if a.workload == "packed":
+        return print(json.dumps(packed(a)))
     if a.workload == "rotate":
         return rotate(a)
     import numpy as np
@@ -333,7 +338,8 @@ def main():
     if not a.no_extra:
         # the other workloads, each checked against its plaintext answers:
         # mixed N (one persistent launch per step), a short serving window,
-        # and uint16 as two base-257 digits with the bivariate circuit
+        # uint16 as two base-257 digits with the bivariate circuit, and uint16
+        # packed four slots per integer (rotations inside the circuit)
         import gc
 
         # the uint16 context, its recorded graph (which holds a whole step's
@@ -346,7 +352,7 @@ def main():
         torch.cuda.empty_cache()
         sub = argparse.Namespace(**vars(a))
         sub.window = a.extra_window
-        for name, fn in (("mixed", mixed), ("serving", serve), ("bivariate", bivariate)):
+        for name, fn in (("mixed", mixed), ("serving", serve), ("bivariate", bivariate), ("packed", packed)):
             print(f"bench: {name}", file=sys.stderr, flush=True)
             r = fn(sub)
             for k in ("n_gpus", "higher_is_better", "scaling", "vs_baseline", "dtype", "data"):
@@ -612,6 +618,82 @@ def bivariate(a):
             "config": {"workload": f"uint16 as 2 base-257 digits, LT+max+min, bivariate circuit, {G} groups x "
                                    f"{dev.M} slots, BGV N=2^15 p=257 Q=14x50b P=5x50b dnum=3",
                        "multiplications_per_group": nd * 518 + nd - 1 + 2 * nd}}
+
+
+def packed(a):
+    """uint16 packed into slots (three base-129 digits under a zero digit, four
+    consecutive slots per integer, 32 integers per ciphertext) at N = 2^15:
+    per-slot LT and EQ by the univariate circuit, then two rounds of rotation
+    and multiply-accumulate; plus the tournament minimum over pairs of slots
+    of the same batch.  Checked against the plaintext answers."""
+    import numpy as np
+    import torch
+
+    import paper_2407_07308_amd as bc
+    import synth
+
+    torch.cuda.set_device(0)
+    prm = dict(logN=15, p=257, nQ=14, bitsQ=50, nP=5, bitsP=50, dnum=3)
+    dev = bc.Context(**prm)
+    steps_rot = (1, 2)
+    rnd = synth.keygen_randomness(SEED + 3, dev.N, prm["nQ"], prm["nP"], prm["dnum"], len(steps_rot))
+    keys = dev.keygen(rnd["s"], rnd["a"], rnd["e"], steps_rot)
+    dev.autotune()
+    G, l, nd, base, M = a.packed_cts, 4, 3, 129, dev.M
+    per = M // l
+    xs = synth.integers(SEED + 4, (G, per), 0, 65536)
+    ys = synth.integers(SEED + 4, (G, per), 0, 65536, index=1)
+
+    def pack(vals):
+        out = np.zeros((G, M), dtype=np.uint32)
+        h = M // 2
+        for i, pl in enumerate(digits(vals, base, l)):  # digit i of every integer
+            for k in range(per):
+                r, j = divmod(k, h // l)
+                out[:, r * h + j * l + i] = pl[:, k]
+        return out
+    A = dev.encrypt(keys, pack(xs), *synth.encrypt_randomness(SEED + 50, G, dev.N).values())
+    B = dev.encrypt(keys, pack(ys), *synth.encrypt_randomness(SEED + 51, G, dev.N).values())
+    lt = dev.compare_packed(keys, A, B, l)  # warm-up
+    steps = max(1, min(a.steps, 3))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dev.compare_packed(keys, A, B, l, out=lt)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    h = M // 2
+    first = [r * h + j * l for r in range(2) for j in range(h // l)]
+    if not np.array_equal(dev.decrypt(keys, lt)[:, first], (xs < ys).astype(np.uint32)):
+        print("bench: packed decryptions are wrong", file=sys.stderr)
+        sys.exit(3)
+    # the tournament over pairs of slots (single base-129 digits per slot)
+    x1 = synth.slot_values(SEED + 52, G, M, 0, 129)
+    X = dev.encrypt(keys, x1, *synth.encrypt_randomness(SEED + 53, G, dev.N).values())
+    mn = dev.tournament(keys, X, 2)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        dev.tournament(keys, X, 2, out=mn)
+    e1.record()
+    torch.cuda.synchronize()
+    t_ms = e0.elapsed_time(e1) / steps
+    rows = x1.reshape(G, 2, h).astype(np.int64)
+    want = np.minimum(rows, np.roll(rows, -1, axis=2)).reshape(G, M)
+    if not np.array_equal(dev.decrypt(keys, mn).astype(np.int64), want):
+        print("bench: tournament decryptions are wrong", file=sys.stderr)
+        sys.exit(3)
+    return {"metric": "encrypted uint16 comparisons/s, slot-packed digits", "value": G * per / (ms / 1e3),
+            "unit": "comparisons/s", "n_gpus": 1, "steps": steps, "ms_per_step": ms, "higher_is_better": True,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"uint16 as 3 base-129 digits in 4 consecutive slots, LT by the univariate "
+                                   f"circuit + 2 rounds of rotation and multiply-accumulate, {G} ciphertexts x "
+                                   f"{per} integers, BGV N=2^15 p=257 Q=14x50b P=5x50b dnum=3",
+                       "multiplications_per_ciphertext": 30 + 3, "rotations_per_ciphertext": 3},
+            "tournament": {"ms_per_call": t_ms, "window": 2, "ciphertexts": G,
+                           "min_pairs_per_s": G * M / (t_ms / 1e3)}}
 
 
 def serve(a):
