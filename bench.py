@@ -50,6 +50,8 @@ def parse():
                     help="uint16 only: skip the mixed-N, serving and bivariate keys of the JSON line")
     ap.add_argument("--extra-window", type=float, default=3.0, help="serving key of the default line: seconds of arrivals")
     ap.add_argument("--biv-groups", type=int, default=4, help="bivariate: groups of 128 uint16 pairs")
+    ap.add_argument("--no-mfma", action="store_true",
+                    help="bivariate: the scalar combinations on the fp64 vector units instead of the matrix cores")
     ap.add_argument("--packed-cts", type=int, default=64,
                     help="packed: ciphertexts per batch (32 uint16 integers each)")
     ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate", "bivariate", "packed"],
@@ -589,6 +591,8 @@ def bivariate(a):
     rnd = synth.keygen_randomness(SEED + 1, dev.N, prm["nQ"], prm["nP"], prm["dnum"], 0)
     keys = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
     dev.autotune()
+    if getattr(a, "no_mfma", False):
+        dev.set_tuning(bc.BC_TUNE_MFMA, 0)
     G, nd, base = a.biv_groups, 2, 257
     xs = synth.integers(SEED + 2, (G, dev.M), 0, 65536)
     ys = synth.integers(SEED + 2, (G, dev.M), 0, 65536, index=1)
@@ -617,7 +621,9 @@ def bivariate(a):
             "dtype": "u64", "data": "synthetic",
             "config": {"workload": f"uint16 as 2 base-257 digits, LT+max+min, bivariate circuit, {G} groups x "
                                    f"{dev.M} slots, BGV N=2^15 p=257 Q=14x50b P=5x50b dnum=3",
-                       "multiplications_per_group": nd * 518 + nd - 1 + 2 * nd}}
+                       "multiplications_per_group": nd * 518 + nd - 1 + 2 * nd,
+                       "scalar_combinations": "fp64 vector units" if getattr(a, "no_mfma", False)
+                       else "int8 matrix cores"}}
 
 
 def packed(a):
