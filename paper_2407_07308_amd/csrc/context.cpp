@@ -467,8 +467,15 @@ void build_context(bc_ctx *c, const bc_params &prm) {
             double *F = &twf[(size_t)m * 4 * N], qd = (double)c->mod[m];
             for (int k = 0; k < N; k++) {
                 F[k] = (double)W[k];
-                F[N + k] = F[k] / qd;
                 F[2 * N + k] = (double)Wi[k];
+                // W[2^k] and Winv[2^k], k < 4, are the transforms' multipliers
+                // for derived twiddles: held centred (|w| <= q/2), which keeps
+                // the derived twiddles below 5q/8 (any butterfly takes either form)
+                if (k == 1 || k == 2 || k == 4 || k == 8) {
+                    if (F[k] > 0.5 * qd) F[k] -= qd;
+                    if (F[2 * N + k] > 0.5 * qd) F[2 * N + k] -= qd;
+                }
+                F[N + k] = F[k] / qd;
                 F[3 * N + k] = F[2 * N + k] / qd;
             }
         }

@@ -55,6 +55,7 @@ struct IntA {
     // twiddles come from the table (a Shoup companion would need a division)
     static constexpr bool kDerive = false;
     __device__ T derive(T a, T) const { return a; }
+    __device__ T square(T a) const { return a; }
     const u64 *W, *Wp, *Wi, *Wip;
     u64 q, q2, ninv, ninvp, ninvw1, ninvw1p;
     __device__ IntA(const void *tw, const PrimeInfo &pi, int prime, int N) {
@@ -127,16 +128,26 @@ struct FpA {
     }
     __device__ T fw(int k) const { return {W[k], Wq[k]}; }
     __device__ T iw(int k) const { return {Wi[k], Wiq[k]}; }
-    // The twiddle a.w c.w (a product of two table entries, or of derived
-    // ones).  With |a.w| < 3q/4 the product lies below q (1/2 + 3/16) < 3q/4
-    // (f_mulmod's bound, q < 2^50): the bound holds along any chain.  Its
-    // quotient factor w/q is w * (1/q) corrected by one Newton step, within
-    // 2^-53 (1 + 2^-50) of w/q, so a butterfly's quotient estimate y (w/q)
-    // errs by at most 1/2 + |y| (3/4) 2^-52 (1 + 2^-50): inside the bound that
-    // the table's twiddles (canonical, w/q correctly rounded) give.
+    // Derived twiddles.  derive(a, c) = a.w c.w for a multiplier c held
+    // centred in the table (|c.w| <= q/2, c.wq = c.w/q correctly rounded): the
+    // quotient estimate errs by at most 1/2 + |a.w| 2^-53, so the product lies
+    // below q (1/2 + |a.w| 2^-53) <= q (1/2 + 1/8 |a.w|/q) (q < 2^50), and
+    // along any chain from a table word (< q) below 5q/8.  Its quotient factor
+    // is w * (1/q) (two roundings): a butterfly's estimate y (w/q) then errs
+    // by at most 1/2 + |y| (5/8)(3/2) 2^-52 < 1/2 + |y| 2^-52, inside the
+    // bound the table's twiddles (canonical, w/q correctly rounded) give.
     __device__ T derive(T a, T c) const {
 #pragma clang fp contract(off)
-        const double w = mulmod(a.w, c.w, c.wq), k = w * u;
+        const double w = mulmod(a.w, c.w, c.wq);
+        return {w, w * u};
+    }
+    // square(a) = a.w^2 for a derived or table a (|a.w| < q): below
+    // q (1/2 + 5/32 + 1/16) < 3q/4; its quotient factor corrected by one
+    // Newton step (within 2^-53 (1 + 2^-50) of w/q), so the butterfly bound
+    // holds (|y| (3/4) 2^-52) and a chain continued from it stays below 5q/8.
+    __device__ T square(T a) const {
+#pragma clang fp contract(off)
+        const double w = mulmod(a.w, a.w, a.wq), k = w * u;
         return {w, __builtin_fma(__builtin_fma(-k, q, w), u, k)};
     }
     __device__ double mulmod(double y, double w, double wq) const { return f_mulmod(y, FPair{w, wq}, q); }
@@ -500,7 +511,7 @@ __device__ __forceinline__ void inv_chunk_d(typename A::V *v, const A &ar, typen
             for (int j = 0; j < half; j++) ar.gs_last(v[j], v[j + half]);
             break;
         }
-        if (r > 0) base = ar.derive(base, base);
+        if (r > 0) base = ar.square(base);
         typename A::T w = base;
 #pragma unroll
         for (int i = 0; i < (32 >> (r + 1)); i++) {
