@@ -370,29 +370,29 @@ def main():
 # rocprofv3 trace, the sources their code comes from, and what a launch moves.
 KINDS = {
     "forward_combine": {"prof": "BC_PROF_NTT_FWD_COMBINE", "re": r"ntt_(part|full)_combine<",
-                        "src": ["ntt.hip", "bc_internal.h"],
+                        "src": ["ntt.hip", "ntt_dev.h", "context.cpp", "bc_internal.h"],
                         "desc": "forward NTT of the relinearise+switch correction with the multiplication's last step "
                                 "as its store (32 N bytes per limb: the limb, d and the accumulator read, the result "
                                 "written)"},
     "forward_part": {"prof": "BC_PROF_NTT_FWD_PART", "re": r"ntt_part<\d+, [^,]+, \d+(, false)?>",
-                     "src": ["ntt.hip", "bc_internal.h"],
+                     "src": ["ntt.hip", "ntt_dev.h", "context.cpp", "bc_internal.h"],
                      "desc": "forward NTT of the raised limbs, 2^13-word part-limb blocks (16 N bytes per limb)"},
     "inverse_part": {"prof": "BC_PROF_NTT_INV_PART", "re": r"ntt_part<\d+, [^,]+, \d+, true>",
-                     "src": ["ntt.hip", "bc_internal.h"],
+                     "src": ["ntt.hip", "ntt_dev.h", "context.cpp", "bc_internal.h"],
                      "desc": "inverse NTT of the key-switched limbs, 2^13-word part-limb blocks (16 N bytes per limb)"},
     "forward": {"prof": "BC_PROF_NTT_FWD", "re": r"ntt_(full|cols|rows)<\d+, false",
-                "src": ["ntt.hip", "bc_internal.h"], "desc": "whole-limb forward NTT (16 N bytes per limb)"},
+                "src": ["ntt.hip", "ntt_dev.h", "context.cpp", "bc_internal.h"], "desc": "whole-limb forward NTT (16 N bytes per limb)"},
     "inverse": {"prof": "BC_PROF_NTT_INV", "re": r"ntt_(full|cols|rows)<\d+, true",
-                "src": ["ntt.hip", "bc_internal.h"], "desc": "whole-limb inverse NTT (16 N bytes per limb)"},
-    "tensor": {"prof": "BC_PROF_TENSOR", "re": r"k_tensor<", "src": ["kernels.hip", "bc_internal.h"],
+                "src": ["ntt.hip", "ntt_dev.h", "context.cpp", "bc_internal.h"], "desc": "whole-limb inverse NTT (16 N bytes per limb)"},
+    "tensor": {"prof": "BC_PROF_TENSOR", "re": r"k_tensor<", "src": ["kernels.hip", "kernels_dev.h", "bc_internal.h"],
                "desc": "tensor product / multiply-accumulate (operands read once, 3 components written)"},
-    "modup": {"prof": "BC_PROF_MODUP", "re": r"k_modup<", "src": ["kernels.hip", "bc_internal.h"],
+    "modup": {"prof": "BC_PROF_MODUP", "re": r"k_modup<", "src": ["kernels.hip", "kernels_dev.h", "bc_internal.h"],
               "desc": "digit decomposition + basis extension (each digit's limbs read, new limbs written)"},
-    "ks_inner": {"prof": "BC_PROF_KS_INNER", "re": r"k_ks_inner<", "src": ["kernels.hip", "bc_internal.h"],
+    "ks_inner": {"prof": "BC_PROF_KS_INNER", "re": r"k_ks_inner<", "src": ["kernels.hip", "kernels_dev.h", "bc_internal.h"],
                  "desc": "key-switch inner product (raised limbs and key read, two accumulators written)"},
-    "relin_ms": {"prof": "BC_PROF_RELIN_MS", "re": r"k_relin_ms_fbc<", "src": ["kernels.hip", "bc_internal.h"],
+    "relin_ms": {"prof": "BC_PROF_RELIN_MS", "re": r"k_relin_ms_fbc<", "src": ["kernels.hip", "kernels_dev.h", "bc_internal.h"],
                  "desc": "ModDown + modulus-switch correction (special and top limbs read, correction written)"},
-    "lincomb": {"prof": "BC_PROF_LINCOMB", "re": r"k_lincomb<", "src": ["kernels.hip", "bc_internal.h"],
+    "lincomb": {"prof": "BC_PROF_LINCOMB", "re": r"k_lincomb<", "src": ["kernels.hip", "kernels_dev.h", "bc_internal.h"],
                 "desc": "Paterson-Stockmeyer block combinations (babies read, blocks written)"},
     "mul": {"prof": "BC_PROF_MUL", "re": None, "src": [], "desc": "whole multiplications"},
 }
