@@ -440,7 +440,15 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   BC_TUNE_MFMA (default 1): the bivariate circuit's linear combinations of
  *   the S powers (a dense 128 x 256 contraction for p = 257) run on the
  *   matrix cores as exact split-int8 products; 0 runs them in fp64 on the
- *   vector units.  Both give the same bytes. */
+ *   vector units.  Both give the same bytes.
+ *   BC_TUNE_RAW_HANDOFF (default 1): with part-limb transforms and fp64
+ *   arithmetic, the key-switching kernels hand their intermediate limbs to
+ *   each other (raised limbs, coefficient-domain copies, the switch
+ *   correction) as the bit patterns of integer-valued doubles reduced to
+ *   |x| <= q/2, instead of canonical words in [0, q): one reduction instead
+ *   of the canonical form and its integer conversion at every hand-off.
+ *   0 keeps canonical words everywhere.  Both give the same bytes; the
+ *   caller's batches always hold canonical words. */
 enum {
     BC_TUNE_NTT_CHUNK_BYTES = 0,
     BC_TUNE_NTT_SINGLE_PASS = 1,
@@ -450,7 +458,8 @@ enum {
     BC_TUNE_SPLIT_STREAMS = 5,
     BC_TUNE_TEST_FAIL_ALLOC = 6,
     BC_TUNE_PERSISTENT = 7,
-    BC_TUNE_MFMA = 8
+    BC_TUNE_MFMA = 8,
+    BC_TUNE_RAW_HANDOFF = 9
 };
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);

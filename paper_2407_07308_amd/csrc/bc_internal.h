@@ -108,6 +108,9 @@ __device__ __forceinline__ double f_centre(double x, double q, double qinv) {
     r = r > h ? r - q : r;
     return r < -h ? r + q : r;
 }
+// an integer-valued double passed between kernels as its bit pattern
+__device__ __forceinline__ double f_raw_load(u64 x) { return __longlong_as_double((long long)x); }
+__device__ __forceinline__ u64 f_raw_bits(double x) { return (u64)__double_as_longlong(x); }
 // 0 <= x < 2^52 as a double: OR-ing 2^52's exponent into the pattern gives 2^52 + x
 __device__ __forceinline__ double f_load(u64 x) {
 #pragma clang fp contract(off)
@@ -163,6 +166,10 @@ struct LimbSet {
     const u64 *ibase;
     u64 ipoly_stride;
     int16_t ioff[kMaxJobs];
+    // part-limb transforms with fp64 arithmetic: the limbs are read / written
+    // as the bit patterns of reduced integer-valued doubles (|x| <= q/2)
+    // instead of canonical words (between key-switching kernels only)
+    int8_t raw_in = 0, raw_out = 0;
 };
 
 // A scalar's residues mod each q_i (Shoup pairs): scalar multiplication and
@@ -239,7 +246,9 @@ __device__ __forceinline__ void bfly_fp(double &x, double &y, const u64 *w, doub
     y = x - p;
     x = x + p;
 }
-template <int PL>
+// CANON: canonical results, else reduced ones (|x| <= q/2, for consumers
+// that take the fp64 pattern of the words)
+template <int PL, bool CANON = true>
 __device__ __forceinline__ void fold_fp(double *v, const PrimeInfo &pi) {
     static_assert(PL == 1 || PL == 2, "one or two stages");
     if constexpr (PL == 1) {
@@ -251,7 +260,7 @@ __device__ __forceinline__ void fold_fp(double *v, const PrimeInfo &pi) {
         bfly_fp(v[2], v[3], pi.w123_f[2], pi.qd);
     }
 #pragma unroll
-    for (int j = 0; j < (1 << PL); j++) v[j] = f_canon(v[j], pi.qd, pi.qinv);
+    for (int j = 0; j < (1 << PL); j++) v[j] = CANON ? f_canon(v[j], pi.qd, pi.qinv) : f_reduce(v[j], pi.qd, pi.qinv);
 }
 
 // The last PL inverse stages (PL = 1, 2), N^-1 included, on the 2^PL words
@@ -544,6 +553,7 @@ struct bc_ctx {
     int biv_K = 0, biv_M = 0;
     bool biv_mfma = false;  // the table has the matrix-core copy
     int mfma = 1;           // BC_TUNE_MFMA: use the matrix-core kernels where they apply
+    int raw_handoff = 1;    // BC_TUNE_RAW_HANDOFF: key-switching intermediates as reduced fp64 patterns
     // owners: the caller's handle, every live key set and every group that
     // lists the context; the last release deletes it (a key set destroyed
     // after its context's handle still finds the context)

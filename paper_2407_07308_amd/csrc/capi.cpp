@@ -1096,6 +1096,8 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
             ctx->pool.fail_after = value;
         } else if (key == BC_TUNE_MFMA) {
             ctx->mfma = value != 0;
+        } else if (key == BC_TUNE_RAW_HANDOFF) {
+            ctx->raw_handoff = value != 0;
         } else if (key == BC_TUNE_PERSISTENT) {
             BC_REQUIRE(value == 0 || persist_supported(ctx), BC_ERR_ARG,
                        "persistent mode needs N = 2^13..2^15, primes below 2^50 and the default transform schedule");
@@ -1117,6 +1119,7 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
         else if (key == BC_TUNE_TEST_FAIL_ALLOC) *value = ctx->pool.fail_after;
         else if (key == BC_TUNE_PERSISTENT) *value = ctx->persistent;
         else if (key == BC_TUNE_MFMA) *value = ctx->mfma;
+        else if (key == BC_TUNE_RAW_HANDOFF) *value = ctx->raw_handoff;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }

@@ -27,9 +27,13 @@ void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, i
                     hipStream_t st);
 // `pl`: the first pl forward stages of the transforms that follow are applied
 // to the outputs (ntt_parts_log(c), or 0)
-void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, hipStream_t st);
+// raw: the input and the new limbs as reduced fp64 patterns (fp64 arithmetic,
+// ordinary launches; see LimbSet::raw_in)
+void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, hipStream_t st,
+                  bool raw = false);
+// raw: mu's raised limbs as reduced fp64 patterns
 void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_stride, const u64 *key, u64 *acc,
-                     int count, int level, int next, int nact, hipStream_t st);
+                     int count, int level, int next, int nact, hipStream_t st, bool raw = false);
 // pl > 0: the special limbs come from part-limb inverse transforms (their
 // last pl stages are applied here) and TH goes to part-limb forward ones
 // (their first pl stages are applied here)
@@ -37,8 +41,9 @@ void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int lev
 void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size_t base_ct_stride, const u64 *acc,
                        const u64 *th, u64 *out, size_t out_ct_stride, int count, int level, int next, hipStream_t st);
 void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, int pl, hipStream_t st);
+// raw: the coefficient-domain inputs and E as reduced fp64 patterns
 void launch_relin_ms_fbc(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
-                         int level, int next, int pl, hipStream_t st);
+                         int level, int next, int pl, hipStream_t st, bool raw = false);
 void launch_relin_ms_combine(const bc_ctx *c, const u64 *d, size_t d_ct_stride, const u64 *acc, const u64 *E, u64 *out,
                              int count, int level, int next, hipStream_t st);
 void launch_ms_combine(const bc_ctx *c, const u64 *in, const u64 *R, u64 *out, int count, int level, hipStream_t st);

@@ -52,17 +52,18 @@ __global__ void k_permute(const u64 *__restrict__ in, u64 *__restrict__ out, con
 
 // ------------------------------------------------------- key switching
 
-template <bool FP, int PL = 0, int MD = kMaxDigit>
+template <bool FP, int PL = 0, int MD = kMaxDigit, bool RAW = false>
 __global__ void k_modup(const u64 *__restrict__ xc, u64 *__restrict__ mu, const ModUpPlan *__restrict__ plans,
                         const PrimeInfo *__restrict__ pinfo, int nl, int next, int dnum, int N) {
-    b_modup<FP, PL, MD>(hw_blk(), xc, mu, plans, pinfo, nl, next, dnum, N);
+    b_modup<FP, PL, MD, RAW>(hw_blk(), xc, mu, plans, pinfo, nl, next, dnum, N);
 }
 
-template <bool FP>
+template <bool FP, bool RAW = false>
 __global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ x, size_t x_ct_stride,
                            const u64 *__restrict__ key, u64 *__restrict__ acc, int level, int nQ, int nmod, int next,
                            int nact, int dnum, int alpha, int count, const PrimeInfo *__restrict__ pinfo, int N) {
-    b_ks_inner<FP>(hw_blk(), mu, x, x_ct_stride, key, acc, level, nQ, nmod, next, nact, dnum, alpha, count, pinfo, N);
+    b_ks_inner<FP, RAW>(hw_blk(), mu, x, x_ct_stride, key, acc, level, nQ, nmod, next, nact, dnum, alpha, count, pinfo,
+                        N);
 }
 
 template <bool FP, int PL>
@@ -78,12 +79,12 @@ __global__ void k_ks_combine(const u64 *__restrict__ base0, const u64 *__restric
     b_ks_combine(hw_blk(), base0, base1, base_ct_stride, acc, th, out, out_ct_stride, pl, pinfo, nl, next, N);
 }
 
-template <bool FP, int PL = 0, int MD = kMaxDigit>
+template <bool FP, int PL = 0, int MD = kMaxDigit, bool RAW = false>
 __global__ void k_relin_ms_fbc(const u64 *__restrict__ acc, const u64 *__restrict__ d, size_t d_ct_stride,
                                u64 *__restrict__ E, const ModDownPlan *__restrict__ md,
                                const ModSwitchPlan *__restrict__ ms, const PrimeInfo *__restrict__ pinfo, int level,
                                int nQ, int nP, int next, int N) {
-    b_relin_ms_fbc<FP, PL, MD>(hw_blk(), acc, d, d_ct_stride, E, md, ms, pinfo, level, nQ, nP, next, N);
+    b_relin_ms_fbc<FP, PL, MD, RAW>(hw_blk(), acc, d, d_ct_stride, E, md, ms, pinfo, level, nQ, nP, next, N);
 }
 
 // out[ct][c][i] = (d_i + acc_i P^-1) q_l^-1 - E_i, i < level (NTT domain)
@@ -307,7 +308,9 @@ void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, i
     k_permute<<<grid3(c->N, nl, count), kT, 0, st>>>(in, out, perm, nl, ncomp, c->N);
 }
 template <bool FP, int PL, int MD>
-static void modup_pl(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, hipStream_t st) {
+static void modup_pl(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, bool raw,
+                     hipStream_t st) {
+    BC_REQUIRE(!raw || (FP && !tl_rec), BC_ERR_ARG, "reduced fp64 words: ordinary fp64 launches only");
     if (tl_rec) {
         static_assert(MD == (PL > 0 ? kFoldDigit : kMaxDigit), "the executor runs the launchers' digit bounds");
         BC_REQUIRE(FP, BC_ERR_ARG, "the persistent executor needs fp64 arithmetic");
@@ -315,27 +318,32 @@ static void modup_pl(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int lev
                     PaModUp{xc, mu, c->modup_f + (size_t)level * c->dnum, c->pinfo, level + 1, next, c->dnum, c->N});
         return;
     }
-    k_modup<FP, PL, MD><<<grid3(c->N >> PL, 1, count * c->dnum), kT, 0, st>>>(
-        xc, mu, (FP ? c->modup_f : c->modup) + (size_t)level * c->dnum, c->pinfo, level + 1, next, c->dnum, c->N);
+    const ModUpPlan *plans = (FP ? c->modup_f : c->modup) + (size_t)level * c->dnum;
+    const dim3 g = grid3(c->N >> PL, 1, count * c->dnum);
+    if (FP && raw) k_modup<FP, PL, MD, FP><<<g, kT, 0, st>>>(xc, mu, plans, c->pinfo, level + 1, next, c->dnum, c->N);
+    else k_modup<FP, PL, MD><<<g, kT, 0, st>>>(xc, mu, plans, c->pinfo, level + 1, next, c->dnum, c->N);
 }
 template <bool FP>
-static void modup_a(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, hipStream_t st) {
-    if (pl == 2) modup_pl<FP, 2, kFoldDigit>(c, xc, mu, count, level, next, st);
-    else if (pl == 1) modup_pl<FP, 1, kFoldDigit>(c, xc, mu, count, level, next, st);
-    else modup_pl<FP, 0, kMaxDigit>(c, xc, mu, count, level, next, st);
+static void modup_a(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, bool raw,
+                    hipStream_t st) {
+    if (pl == 2) modup_pl<FP, 2, kFoldDigit>(c, xc, mu, count, level, next, raw, st);
+    else if (pl == 1) modup_pl<FP, 1, kFoldDigit>(c, xc, mu, count, level, next, raw, st);
+    else modup_pl<FP, 0, kMaxDigit>(c, xc, mu, count, level, next, raw, st);
 }
-void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, hipStream_t st) {
+void launch_modup(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, int pl, hipStream_t st,
+                  bool raw) {
     double limbs = 0;  // each digit's source limbs read, its new limbs written
     for (int j = 0; j < c->dnum; j++) {
         const ModUpPlan &p = c->h_modup[(size_t)level * c->dnum + j];
         if (p.nsrc) limbs += p.nsrc + p.ntgt;
     }
     ProfScope ps(c, kProfModUp, 8.0 * c->N * limbs * count, st);
-    if (use_fp64(c)) modup_a<true>(c, xc, mu, count, level, next, pl, st);
-    else modup_a<false>(c, xc, mu, count, level, next, pl, st);
+    if (use_fp64(c)) modup_a<true>(c, xc, mu, count, level, next, pl, raw, st);
+    else modup_a<false>(c, xc, mu, count, level, next, pl, raw, st);
 }
 void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_stride, const u64 *key, u64 *acc,
-                     int count, int level, int next, int nact, hipStream_t st) {
+                     int count, int level, int next, int nact, hipStream_t st, bool raw) {
+    BC_REQUIRE(!raw || (use_fp64(c) && !tl_rec), BC_ERR_ARG, "reduced fp64 words: ordinary fp64 launches only");
     // raised limbs of every active digit read, two accumulators written, the key read once
     ProfScope ps(c, kProfKsInner, 8.0 * c->N * next * ((double)count * (nact + 2) + 2.0 * nact), st);
     const dim3 g = grid3(c->N, next, (count + kKsCts - 1) / kKsCts);
@@ -345,7 +353,10 @@ void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_s
                                              c->alpha, count, c->pinfo, c->N});
         return;
     }
-    if (use_fp64(c))
+    if (use_fp64(c) && raw)
+        k_ks_inner<true, true><<<g, kT, 0, st>>>(mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact,
+                                                 c->dnum, c->alpha, count, c->pinfo, c->N);
+    else if (use_fp64(c))
         k_ks_inner<true><<<g, kT, 0, st>>>(mu, x, x_ct_stride, key, acc, level, c->nQ, c->nmod, next, nact, c->dnum,
                                            c->alpha, count, c->pinfo, c->N);
     else
@@ -405,7 +416,8 @@ void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level
 }
 template <bool FP, int PL, int MD>
 static void relin_ms_fbc_pl(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
-                            int level, int next, hipStream_t st) {
+                            int level, int next, bool raw, hipStream_t st) {
+    BC_REQUIRE(!raw || (FP && !tl_rec), BC_ERR_ARG, "reduced fp64 words: ordinary fp64 launches only");
     if (tl_rec) {
         static_assert(MD == (PL > 0 ? kFoldDigit : kMaxDigit), "the executor runs the launchers' digit bounds");
         BC_REQUIRE(FP, BC_ERR_ARG, "the persistent executor needs fp64 arithmetic");
@@ -414,23 +426,29 @@ static void relin_ms_fbc_pl(const bc_ctx *c, const u64 *acc, const u64 *d, size_
                               next, c->N});
         return;
     }
-    k_relin_ms_fbc<FP, PL, MD><<<grid3(c->N >> PL, 1, count * 2), kT, 0, st>>>(
-        acc, d, d_ct_stride, E, FP ? c->moddown_f : c->moddown, (FP ? c->modsw_f : c->modsw) + level, c->pinfo, level,
-        c->nQ, c->nP, next, c->N);
+    const dim3 g = grid3(c->N >> PL, 1, count * 2);
+    const ModDownPlan *md = FP ? c->moddown_f : c->moddown;
+    const ModSwitchPlan *ms = (FP ? c->modsw_f : c->modsw) + level;
+    if (FP && raw)
+        k_relin_ms_fbc<FP, PL, MD, FP><<<g, kT, 0, st>>>(acc, d, d_ct_stride, E, md, ms, c->pinfo, level, c->nQ, c->nP,
+                                                        next, c->N);
+    else
+        k_relin_ms_fbc<FP, PL, MD><<<g, kT, 0, st>>>(acc, d, d_ct_stride, E, md, ms, c->pinfo, level, c->nQ, c->nP,
+                                                    next, c->N);
 }
 template <bool FP>
 static void relin_ms_fbc_a(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
-                           int level, int next, int pl, hipStream_t st) {
-    if (pl == 2) relin_ms_fbc_pl<FP, 2, kFoldDigit>(c, acc, d, d_ct_stride, E, count, level, next, st);
-    else if (pl == 1) relin_ms_fbc_pl<FP, 1, kFoldDigit>(c, acc, d, d_ct_stride, E, count, level, next, st);
-    else relin_ms_fbc_pl<FP, 0, kMaxDigit>(c, acc, d, d_ct_stride, E, count, level, next, st);
+                           int level, int next, int pl, bool raw, hipStream_t st) {
+    if (pl == 2) relin_ms_fbc_pl<FP, 2, kFoldDigit>(c, acc, d, d_ct_stride, E, count, level, next, raw, st);
+    else if (pl == 1) relin_ms_fbc_pl<FP, 1, kFoldDigit>(c, acc, d, d_ct_stride, E, count, level, next, raw, st);
+    else relin_ms_fbc_pl<FP, 0, kMaxDigit>(c, acc, d, d_ct_stride, E, count, level, next, raw, st);
 }
 void launch_relin_ms_fbc(const bc_ctx *c, const u64 *acc, const u64 *d, size_t d_ct_stride, u64 *E, int count,
-                         int level, int next, int pl, hipStream_t st) {
+                         int level, int next, int pl, hipStream_t st, bool raw) {
     // per component: the special and top accumulator limbs and d's top limb read, `level` limbs written
     ProfScope ps(c, kProfRelinMs, 8.0 * c->N * 2.0 * count * (c->nP + 2 + level), st);
-    if (use_fp64(c)) relin_ms_fbc_a<true>(c, acc, d, d_ct_stride, E, count, level, next, pl, st);
-    else relin_ms_fbc_a<false>(c, acc, d, d_ct_stride, E, count, level, next, pl, st);
+    if (use_fp64(c)) relin_ms_fbc_a<true>(c, acc, d, d_ct_stride, E, count, level, next, pl, raw, st);
+    else relin_ms_fbc_a<false>(c, acc, d, d_ct_stride, E, count, level, next, pl, raw, st);
 }
 void launch_relin_ms_combine(const bc_ctx *c, const u64 *d, size_t d_ct_stride, const u64 *acc, const u64 *E, u64 *out,
                              int count, int level, int next, hipStream_t st) {

@@ -119,7 +119,9 @@ __device__ __forceinline__ void b_permute(const VBlk &VB, const u64 *__restrict_
 // to its inputs (unfold_int / unfold_fp) and the first PL forward stages of
 // the new limbs' transforms to its outputs (fold_int / fold_fp).  MD bounds
 // the digit size at compile time.
-template <bool FP, int PL = 0, int MD = kMaxDigit>
+// RAW (fp64 only): the input and the new limbs are reduced fp64 patterns
+// (|x| <= q/2) instead of canonical words.
+template <bool FP, int PL = 0, int MD = kMaxDigit, bool RAW = false>
 __device__ __forceinline__ void b_modup(const VBlk &VB, const u64 *__restrict__ xc, u64 *__restrict__ mu, const ModUpPlan *__restrict__ plans,
                         const PrimeInfo *__restrict__ pinfo, int nl, int next, int dnum, int N) {
     constexpr int NV = 1 << PL;
@@ -170,7 +172,8 @@ __device__ __forceinline__ void b_modup(const VBlk &VB, const u64 *__restrict__ 
             const PrimeInfo &pi = pinfo[pl.src_lo + s];
             double x[NV];
 #pragma unroll
-            for (int v = 0; v < NV; v++) x[v] = f_load(in[(size_t)(pl.src_lo + s) * N + v * Q]);
+            for (int v = 0; v < NV; v++)
+                x[v] = RAW ? f_raw_load(in[(size_t)(pl.src_lo + s) * N + v * Q]) : f_load(in[(size_t)(pl.src_lo + s) * N + v * Q]);
             if constexpr (PL > 0) unfold_fp<PL, false>(x, pi);  // |x| < 1.5 q: fine for the product
 #pragma unroll
             for (int v = 0; v < NV; v++) y[v][s] = f_canon(f_mulmod(x[v], fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
@@ -187,12 +190,12 @@ __device__ __forceinline__ void b_modup(const VBlk &VB, const u64 *__restrict__ 
                     acc[v] += f_mulmod(y[v][s], fpair(pl.qhat[t][s]), pt.qd);
                     if ((s & 7) == 7) acc[v] = f_reduce(acc[v], pt.qd, pt.qinv);
                 }
-                // the fold takes |x| < 1.6 q and returns canonical words
-                acc[v] = PL > 0 ? f_reduce(acc[v], pt.qd, pt.qinv) : f_canon(acc[v], pt.qd, pt.qinv);
+                // the fold takes |x| < 1.6 q and returns canonical (reduced) words
+                acc[v] = PL > 0 || RAW ? f_reduce(acc[v], pt.qd, pt.qinv) : f_canon(acc[v], pt.qd, pt.qinv);
             }
-            if constexpr (PL > 0) fold_fp<PL>(acc, pt);
+            if constexpr (PL > 0) fold_fp<PL, !RAW>(acc, pt);
 #pragma unroll
-            for (int v = 0; v < NV; v++) out[(size_t)pl.tgt_e[t] * N + v * Q] = f_bits(acc[v]);
+            for (int v = 0; v < NV; v++) out[(size_t)pl.tgt_e[t] * N + v * Q] = RAW ? f_raw_bits(acc[v]) : f_bits(acc[v]);
         }
     }
 }
@@ -203,7 +206,9 @@ __device__ __forceinline__ void b_modup(const VBlk &VB, const u64 *__restrict__ 
 // sum exactly before a reduction).  Otherwise Barrett products on u64.
 // Blocks are numbered so that the ciphertext groups vary fastest: the groups
 // that read the same key words run back to back and find them in the cache.
-template <bool FP>
+// RAW (fp64 only): the raised limbs in mu are reduced fp64 patterns; the
+// digits' own limbs read from x are canonical words either way.
+template <bool FP, bool RAW = false>
 __device__ __forceinline__ void b_ks_inner(const VBlk &VB, const u64 *__restrict__ mu, const u64 *__restrict__ x, size_t x_ct_stride,
                            const u64 *__restrict__ key, u64 *__restrict__ acc, int level, int nQ, int nmod, int next,
                            int nact, int dnum, int alpha, int count, const PrimeInfo *__restrict__ pinfo, int N) {
@@ -234,7 +239,7 @@ __device__ __forceinline__ void b_ks_inner(const VBlk &VB, const u64 *__restrict
             const FPair c0{w0, w0 * qinv}, c1{w1, w1 * qinv};
 #pragma unroll
             for (int c = 0; c < kKsCts; c++) {
-                const double y = f_load(u[c]);
+                const double y = RAW && j != own ? f_raw_load(u[c]) : f_load(u[c]);
                 s0[c] += f_mulmod(y, c0, q);
                 s1[c] += f_mulmod(y, c1, q);
                 if ((j & 7) == 7) {
@@ -375,7 +380,9 @@ __device__ __forceinline__ void b_ks_combine(const VBlk &VB, const u64 *__restri
 // so that, after E is transformed, out_i = (d_i + acc_i P^-1) q_l^-1 - E_i
 // equals the modulus switch of the relinearised ciphertext exactly (every
 // step is linear over Z_{q_i}).  d and acc limbs l are coefficient domain here.
-template <bool FP, int PL = 0, int MD = kMaxDigit>
+// RAW (fp64 only): the accumulator's special and top limbs and d's top limb
+// are read, and E is written, as reduced fp64 patterns.
+template <bool FP, int PL = 0, int MD = kMaxDigit, bool RAW = false>
 __device__ __forceinline__ void b_relin_ms_fbc(const VBlk &VB, const u64 *__restrict__ acc, const u64 *__restrict__ d, size_t d_ct_stride,
                                u64 *__restrict__ E, const ModDownPlan *__restrict__ md,
                                const ModSwitchPlan *__restrict__ ms, const PrimeInfo *__restrict__ pinfo, int level,
@@ -469,15 +476,16 @@ __device__ __forceinline__ void b_relin_ms_fbc(const VBlk &VB, const u64 *__rest
             const PrimeInfo &pj = pinfo[nQ + j];
             double x[NV];
 #pragma unroll
-            for (int w = 0; w < NV; w++) x[w] = f_load(A[(size_t)(nl + j) * N + w * Q]);
+            for (int w = 0; w < NV; w++)
+                x[w] = RAW ? f_raw_load(A[(size_t)(nl + j) * N + w * Q]) : f_load(A[(size_t)(nl + j) * N + w * Q]);
             if constexpr (PL > 0) unfold_fp<PL, false>(x, pj);  // |x| < 1.5 q: fine for the product
 #pragma unroll
             for (int w = 0; w < NV; w++) v[w][j] = f_canon(f_mulmod(x[w], fpair(md->vfac[j]), pj.qd), pj.qd, pj.qinv);
         }
 #pragma unroll
         for (int w = 0; w < NV; w++) {
-            top[w] = f_load(A[(size_t)level * N + w * Q]);
-            dt[w] = f_load(D[w * Q]);
+            top[w] = RAW ? f_raw_load(A[(size_t)level * N + w * Q]) : f_load(A[(size_t)level * N + w * Q]);
+            dt[w] = RAW ? f_raw_load(D[w * Q]) : f_load(D[w * Q]);
         }
         if constexpr (PL > 0) {  // |.| < 1.5 q: they enter r below through a product and a sum
             unfold_fp<PL, false>(top, pl);
@@ -512,12 +520,12 @@ __device__ __forceinline__ void b_relin_ms_fbc(const VBlk &VB, const u64 *__rest
                     e[w] += f_mulmod(v[w][j], fpair(ms->rk1[i][j]), q);
                     if ((j & 7) == 6) e[w] = f_reduce(e[w], q, pi.qinv);
                 }
-                // the fold takes |x| < 1.6 q and returns canonical words
-                e[w] = PL > 0 ? f_reduce(e[w], q, pi.qinv) : f_canon(e[w], q, pi.qinv);
+                // the fold takes |x| < 1.6 q and returns canonical (reduced) words
+                e[w] = PL > 0 || RAW ? f_reduce(e[w], q, pi.qinv) : f_canon(e[w], q, pi.qinv);
             }
-            if constexpr (PL > 0) fold_fp<PL>(e, pi);
+            if constexpr (PL > 0) fold_fp<PL, !RAW>(e, pi);
 #pragma unroll
-            for (int w = 0; w < NV; w++) Eo[(size_t)i * N + w * Q] = f_bits(e[w]);
+            for (int w = 0; w < NV; w++) Eo[(size_t)i * N + w * Q] = RAW ? f_raw_bits(e[w]) : f_bits(e[w]);
         }
     }
 }

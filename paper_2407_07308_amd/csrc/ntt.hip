@@ -19,6 +19,8 @@
 // is a policy: integer (Harvey's lazy butterflies with Shoup products) for
 // any prime, or fp64 for primes below 2^50 (see FpA).
 
+#include <type_traits>
+
 #include "ntt_dev.h"
 #include "persist.h"
 
@@ -37,17 +39,17 @@ __global__ void __launch_bounds__(1 << (LOGN - 5)) ntt_full(LimbSet ls, const vo
 // part), several blocks per CU: four waves per SIMD (128 registers a lane)
 // forward; three inverse, whose chunks need more registers (timed faster
 // than four with spills).
-template <int LOGN, class A, int PL = 1, bool INV = false>
+template <int LOGN, class A, int PL = 1, bool INV = false, bool RIN = false, bool ROUT = false>
 __global__ void __launch_bounds__(1 << (LOGN - 5), INV ? 3 : 4) ntt_part(LimbSet ls, const void *__restrict__ tw,
                                                                          const PrimeInfo *__restrict__ pinfo) {
     __shared__ u64 s[ntt_lds_words(LOGN, PL)];
-    ntt_full_body<LOGN, INV, A, 0, PL>(ls, tw, pinfo, nullptr, blockIdx.x, s);
+    ntt_full_body<LOGN, INV, A, 0, PL, false, RIN, ROUT>(ls, tw, pinfo, nullptr, blockIdx.x, s);
 }
-template <int LOGN, class A, int EPI, int PL = 1>
+template <int LOGN, class A, int EPI, int PL = 1, bool RIN = false>
 __global__ void __launch_bounds__(1 << (LOGN - 5), 4)
     ntt_part_combine(LimbSet ls, const void *__restrict__ tw, const PrimeInfo *__restrict__ pinfo, NttCombine cb) {
     __shared__ u64 s[ntt_lds_words(LOGN, PL)];
-    ntt_full_body<LOGN, false, A, EPI, PL>(ls, tw, pinfo, &cb, blockIdx.x, s);
+    ntt_full_body<LOGN, false, A, EPI, PL, false, RIN>(ls, tw, pinfo, &cb, blockIdx.x, s);
 }
 
 // forward transform of E limbs with an NttCombine step as the store (out
@@ -68,6 +70,7 @@ inline const void *tw_of(const bc_ctx *c) { return use_fp(c) ? (const void *)c->
 // Records a transform stage for the persistent executor: 2^13-word blocks
 // (whole limbs at N = 2^13, halves at 2^14, quarters at 2^15), fp64.
 void record_ntt(const bc_ctx *c, const LimbSet &ls, int kind0, int pl, const NttCombine *cb) {
+    BC_REQUIRE(!ls.raw_in && !ls.raw_out, BC_ERR_ARG, "the persistent executor passes canonical words");
     BC_REQUIRE(use_fp(c), BC_ERR_ARG, "the persistent executor needs fp64 arithmetic");
     BC_REQUIRE(c->logN - pl == 13, BC_ERR_ARG,
                "the persistent executor runs 2^13-word transform blocks (N = 2^13, or part-limb at 2^14 and 2^15)");
@@ -243,11 +246,29 @@ int ntt_parts_log(const bc_ctx *c) {
     return c->logN == 15 ? 2 : c->logN == 14 ? 1 : 0;
 }
 
+// the part-limb kernel for the limb set's word forms (reduced fp64 patterns
+// only with fp64 arithmetic)
+template <class A, bool INV>
+static void launch_parts_k(int pl, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
+    const unsigned nblk = (unsigned)(ls.npoly * ls.nlimb) << pl;
+    auto go = [&](auto rin, auto rout) {
+        constexpr bool RI = decltype(rin)::value, RO = decltype(rout)::value;
+        if (pl == 2) ntt_part<13, A, 2, INV, RI, RO><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
+        else ntt_part<13, A, 1, INV, RI, RO><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
+    };
+    if constexpr (A::kDerive) {
+        if (ls.raw_in && ls.raw_out) go(std::true_type{}, std::true_type{});
+        else if (ls.raw_in) go(std::true_type{}, std::false_type{});
+        else if (ls.raw_out) go(std::false_type{}, std::true_type{});
+        else go(std::false_type{}, std::false_type{});
+    } else {
+        BC_REQUIRE(!ls.raw_in && !ls.raw_out, BC_ERR_ARG, "reduced fp64 words need the fp64 arithmetic");
+        go(std::false_type{}, std::false_type{});
+    }
+}
 template <class A>
 static void launch_parts(int pl, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
-    const unsigned nblk = (unsigned)(ls.npoly * ls.nlimb) << pl;
-    if (pl == 2) ntt_part<13, A, 2><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
-    else ntt_part<13, A, 1><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
+    launch_parts_k<A, false>(pl, ls, c, st);
 }
 
 void ntt_forward_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
@@ -266,9 +287,7 @@ void ntt_forward_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
 
 template <class A>
 static void launch_parts_inv(int pl, const LimbSet &ls, const bc_ctx *c, hipStream_t st) {
-    const unsigned nblk = (unsigned)(ls.npoly * ls.nlimb) << pl;
-    if (pl == 2) ntt_part<13, A, 2, true><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
-    else ntt_part<13, A, 1, true><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo);
+    launch_parts_k<A, true>(pl, ls, c, st);
 }
 
 void ntt_inverse_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
@@ -288,8 +307,19 @@ void ntt_inverse_parts(const bc_ctx *c, const LimbSet &ls, hipStream_t st) {
 template <class A, int EPI>
 static void launch_parts_combine(int pl, const LimbSet &ls, const NttCombine &cb, const bc_ctx *c, hipStream_t st) {
     const unsigned nblk = (unsigned)(ls.npoly * ls.nlimb) << pl;
-    if (pl == 2) ntt_part_combine<13, A, EPI, 2><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo, cb);
-    else ntt_part_combine<13, A, EPI, 1><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo, cb);
+    BC_REQUIRE(!ls.raw_out, BC_ERR_ARG, "a combined transform stores canonical words");
+    auto go = [&](auto rin) {
+        constexpr bool RI = decltype(rin)::value;
+        if (pl == 2) ntt_part_combine<13, A, EPI, 2, RI><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo, cb);
+        else ntt_part_combine<13, A, EPI, 1, RI><<<nblk, 256, 0, st>>>(ls, tw_of(c), c->pinfo, cb);
+    };
+    if constexpr (A::kDerive) {
+        if (ls.raw_in) go(std::true_type{});
+        else go(std::false_type{});
+    } else {
+        BC_REQUIRE(!ls.raw_in, BC_ERR_ARG, "reduced fp64 words need the fp64 arithmetic");
+        go(std::false_type{});
+    }
 }
 
 template <class A>

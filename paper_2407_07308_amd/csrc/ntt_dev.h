@@ -80,6 +80,7 @@ struct IntA {
     }
     __device__ static u64 raw(V x) { return x; }
     __device__ static V unraw(u64 x) { return x; }
+    __device__ V reduce(V x) const { return x; }  // (no reduced fp64 words on this path)
     __device__ V prep(V x) const { return x; }
     __device__ void ct(V &X, V &Y, T t) const {
         u64 x = X >= q2 ? X - q2 : X;
@@ -576,13 +577,14 @@ struct McLimb {
     typename A::T w0, w1;
 };
 
-template <class A, int EPI = 0>
+// ROUT: words stored as their reduced fp64 pattern (|x| <= q/2, see ntt_full_body)
+template <class A, int EPI = 0, bool ROUT = false>
 __device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, const A &ar, u64 *tile, int lane,
                                             const McLimb<A> *mc = nullptr, int boff = 0) {
 #pragma unroll
     for (int r = 0; r < 2; r++) {
 #pragma unroll
-        for (int i = 0; i < 16; i++) tile[i * kTileRow + lane] = ar.store(v[16 * r + i]);
+        for (int i = 0; i < 16; i++) tile[i * kTileRow + lane] = ROUT ? A::raw(ar.reduce(v[16 * r + i])) : ar.store(v[16 * r + i]);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const int p = lane & 7;
 #pragma unroll
@@ -607,7 +609,7 @@ __device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, co
     }
 }
 
-template <class A>
+template <class A, bool RIN = false>
 __device__ __forceinline__ void load_block(const u64 *blk, typename A::V *v, const A &ar, u64 *tile, int lane) {
 #pragma unroll
     for (int r = 0; r < 2; r++) {
@@ -621,7 +623,7 @@ __device__ __forceinline__ void load_block(const u64 *blk, typename A::V *v, con
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-        for (int i = 0; i < 16; i++) v[16 * r + i] = ar.load(tile[i * kTileRow + lane]);
+        for (int i = 0; i < 16; i++) v[16 * r + i] = RIN ? A::unraw(tile[i * kTileRow + lane]) : ar.load(tile[i * kTileRow + lane]);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 }
@@ -641,11 +643,18 @@ __host__ __device__ constexpr int ntt_lds_words(int logn, int pl, bool split = f
 // exchange in two rounds, so several blocks share a CU.
 // SPL: exchange in two rounds even where the whole buffer would fit (half the
 // LDS, for callers that share it with other bodies).
-template <int LOGN, bool INV, class A, int EPI, int PL = 0, bool SPL = false>
+// RIN / ROUT (fp64 arithmetic only): the limbs are read / written as the bit
+// patterns of integer-valued doubles instead of canonical words; written ones
+// are reduced to |x| <= q/2 (one f_reduce instead of the canonical form and
+// its integer conversion).  Such words pass between the key-switching
+// kernels only; every consumer takes |x| <= q/2 where it takes [0, q).
+template <int LOGN, bool INV, class A, int EPI, int PL = 0, bool SPL = false, bool RIN = false, bool ROUT = false>
 __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__restrict__ tw,
                                               const PrimeInfo *__restrict__ pinfo, const NttCombine *cb, int bid,
                                               u64 *__restrict__ s) {
     using V = typename A::V;
+    static_assert(!(RIN || ROUT) || A::kDerive, "reduced fp64 words need the fp64 arithmetic");
+    static_assert(!(ROUT && EPI != 0), "an epilogue stores canonical words");
     constexpr int N = 1 << LOGN, C3 = LOGN - 10;
     constexpr bool SP = SPL || PL > 0 || N > kSplitWords;
     constexpr int NSPLIT = SP ? 2 : 1;
@@ -679,7 +688,7 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
     if constexpr (DER) gc = gray_constants(ar, INV);
     if (!INV) {
 #pragma unroll
-        for (int k = 0; k < 32; k++) v[k] = ar.load(ain[x1 + (k << (LOGN - 5))]);
+        for (int k = 0; k < 32; k++) v[k] = RIN ? A::unraw(ain[x1 + (k << (LOGN - 5))]) : ar.load(ain[x1 + (k << (LOGN - 5))]);
         // the first chunk's twiddles are the same for every thread: from the
         // table (deriving them was timed slower here, faster in the inverse)
         fwd_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, true);
@@ -739,11 +748,11 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             mc.w1 = A::pair(cb->w[i] + 2);
             store_block<A, EPI>(nullptr, v, ar, s + wave * 16 * kTileRow, lane, &mc, wave << 11);
         } else {
-            store_block(a + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
+            store_block<A, 0, ROUT>(a + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
         }
     } else {
         const int wave = t >> 6, lane = t & 63;
-        load_block(ain + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
+        load_block<A, RIN>(ain + (wave << 11), v, ar, s + wave * 16 * kTileRow, lane);
         __syncthreads();  // every wave is done with its tile before the exchanges reuse LDS
         if constexpr (DER) {
             inv_chunk_d<C3>(v, ar, ar.iw(stage_base(LOGN, 0, x3, hh, LOGM)), gc, true);
@@ -787,7 +796,7 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
         if constexpr (DER) inv_chunk_d<5, A, PL == 0>(v, ar, b1, gc, false);
         else inv_chunk<5>(v, ar, LOGN, LOGN - 5, x1, hh, LOGM, PL == 0, false);
 #pragma unroll
-        for (int k = 0; k < 32; k++) a[x1 + (k << (LOGN - 5))] = ar.store(v[k]);
+        for (int k = 0; k < 32; k++) a[x1 + (k << (LOGN - 5))] = ROUT ? A::raw(ar.reduce(v[k])) : ar.store(v[k]);
     }
 }
 

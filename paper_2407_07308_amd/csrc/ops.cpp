@@ -88,10 +88,13 @@ void run_ntt(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j
 // Part-limb transforms (ntt_parts_log(c) > 0), as run_ntt: forward, of limbs
 // whose first stages their producer applied; inverse, leaving the last
 // stages to the kernel that consumes the limbs.
+// raw_in / raw_out: the limbs are read / written as reduced fp64 patterns
 void run_ntt_parts(const bc_ctx *c, u64 *base, size_t stride, int npoly, const Jobs &j, bool inverse, hipStream_t st,
-                   const u64 *in = nullptr, size_t in_stride = 0) {
+                   const u64 *in = nullptr, size_t in_stride = 0, bool raw_in = false, bool raw_out = false) {
     for (size_t s = 0; s < j.l.size(); s += kMaxJobs) {
         LimbSet ls{};
+        ls.raw_in = raw_in;
+        ls.raw_out = raw_out;
         ls.base = base;
         ls.poly_stride = stride;
         ls.npoly = npoly;
@@ -107,6 +110,11 @@ void run_ntt_parts(const bc_ctx *c, u64 *base, size_t stride, int npoly, const J
         else ntt_forward_parts(c, ls, st);
     }
 }
+
+// Whether the key-switching kernels pass their intermediate limbs as reduced
+// fp64 patterns: part-limb transforms with fp64 arithmetic, ordinary launches
+// (the persistent executor's stages pass canonical words).
+bool raw_handoff(const bc_ctx *c) { return c->raw_handoff && ntt_parts_log(c) > 0 && use_fp64(c) && !tl_rec; }
 
 // all limbs of a [count][ncomp][nl][N] batch
 Jobs all_limbs(int ncomp, int nl) {
@@ -135,19 +143,23 @@ BufP ks_accumulate(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int
     // with part-limb transforms, modup applies the last stages of X's inverse
     // transform and the first stages of the new limbs' forward transforms
     const int parts = ntt_parts_log(c);
-    if (parts) run_ntt_parts(c, xc, (size_t)nl * N, count, jx, true, st, X, x_stride);
+    // XC and MU hold reduced fp64 patterns between these kernels (fp64
+    // arithmetic, ordinary launches): no canonical form and integer
+    // conversion at each hand-off
+    const bool raw = raw_handoff(c);
+    if (parts) run_ntt_parts(c, xc, (size_t)nl * N, count, jx, true, st, X, x_stride, false, raw);
     else run_ntt(c, xc, (size_t)nl * N, count, jx, true, st, X, x_stride);
-    launch_modup(c, xc, mu, count, level, next, parts, st);
+    launch_modup(c, xc, mu, count, level, next, parts, st, raw);
     Jobs jm;
     for (int j = 0; j < nact; j++) {
         const ModUpPlan &pl = c->h_modup[(size_t)level * dnum + j];
         for (int t = 0; t < pl.ntgt; t++) jm.add(j * next + pl.tgt_e[t], pl.tgt_prime[t]);
     }
-    if (parts) run_ntt_parts(c, mu, (size_t)dnum * next * N, count, jm, false, st);
+    if (parts) run_ntt_parts(c, mu, (size_t)dnum * next * N, count, jm, false, st, nullptr, 0, raw, raw);
     else run_ntt(c, mu, (size_t)dnum * next * N, count, jm, false, st);
     XC.reset();
     BufP ACC = make_buf(c, sizeof(u64) * (size_t)count * 2 * next * N);
-    launch_ks_inner(c, mu, X, x_stride, key, (u64 *)ACC->p, count, level, next, nact, st);
+    launch_ks_inner(c, mu, X, x_stride, key, (u64 *)ACC->p, count, level, next, nact, st, raw);
     return ACC;
 }
 
@@ -170,15 +182,18 @@ void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out
     // with part-limb transforms the fbc kernel applies the last stages of
     // these inverse transforms and the first stages of E's forward transform
     const int parts = ntt_parts_log(c);
+    // the transformed special and top limbs, d's top limbs and E pass as
+    // reduced fp64 patterns (as in ks_accumulate)
+    const bool raw = raw_handoff(c);
     if (parts) {
-        run_ntt_parts(c, acc, (size_t)2 * next * N, count, ja, true, st);
-        run_ntt_parts(c, t3.data, 3 * L, count, jd, true, st);
+        run_ntt_parts(c, acc, (size_t)2 * next * N, count, ja, true, st, nullptr, 0, false, raw);
+        run_ntt_parts(c, t3.data, 3 * L, count, jd, true, st, nullptr, 0, false, raw);
     } else {
         run_ntt(c, acc, (size_t)2 * next * N, count, ja, true, st);
         run_ntt(c, t3.data, 3 * L, count, jd, true, st);
     }
     BufP E = make_buf(c, sizeof(u64) * (size_t)count * 2 * lv * N);
-    launch_relin_ms_fbc(c, acc, t3.data, 3 * L, (u64 *)E->p, count, lv, next, parts, st);
+    launch_relin_ms_fbc(c, acc, t3.data, 3 * L, (u64 *)E->p, count, lv, next, parts, st, raw);
     // out = (d + acc P^-1) q_l^-1 - NTT(E): fused into E's transform where the
     // schedule has such a kernel, else transform and combine separately
     NttCombine cb{};
@@ -206,6 +221,7 @@ void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out
         }
     }
     LimbSet ls{};
+    ls.raw_in = raw;
     ls.base = (u64 *)E->p;
     ls.poly_stride = (u64)2 * lv * N;
     ls.npoly = count;

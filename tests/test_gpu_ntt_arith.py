@@ -3,7 +3,9 @@
 With every prime below 2^50 the transforms run in fp64 arithmetic; the
 integer butterflies remain selectable.  Both must give the same bytes under
 every schedule (single-pass with or without part-limb transforms, two-pass
-whole or chunked), and the ciphertexts must equal the oracle's.  With the single-pass schedule the last
+whole or chunked; with the key-switching kernels handing their intermediate
+limbs over as reduced fp64 patterns or as canonical words), and the
+ciphertexts must equal the oracle's.  With the single-pass schedule the last
 steps of a multiplication and of a modulus switch run inside the forward
 transform's store; the other schedules run them as separate kernels, so the
 comparison covers both.  Sizes: N = 2^12 .. 2^15, the range of the
@@ -18,16 +20,17 @@ from oracle import Oracle, Params
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [  # (fp64, single pass, chunk bytes, part-limb transforms)
-    (1, 1, 0, 1), (1, 1, 0, 0), (1, 0, 0, 1), (1, 0, 1 << 20, 1),
-    (0, 1, 0, 1), (0, 1, 0, 0), (0, 0, 0, 1), (0, 0, 1 << 20, 1)]
+SCHEDULES = [  # (fp64, single pass, chunk bytes, part-limb transforms, fp64 hand-off)
+    (1, 1, 0, 1, 1), (1, 1, 0, 1, 0), (1, 1, 0, 0, 1), (1, 0, 0, 1, 1), (1, 0, 1 << 20, 1, 1),
+    (0, 1, 0, 1, 1), (0, 1, 0, 0, 1), (0, 0, 0, 1, 1), (0, 0, 1 << 20, 1, 1)]
 
 
 def run_all(dev, dk, slots, r):
     import paper_2407_07308_amd as bc
 
     outs = []
-    for fp, single, chunk, parts in SCHEDULES:
+    for fp, single, chunk, parts, raw in SCHEDULES:
+        dev.set_tuning(bc.BC_TUNE_RAW_HANDOFF, raw)
         dev.set_tuning(bc.BC_TUNE_FP64, fp)
         dev.set_tuning(bc.BC_TUNE_NTT_SINGLE_PASS, single)
         dev.set_tuning(bc.BC_TUNE_NTT_CHUNK_BYTES, chunk)
@@ -57,6 +60,7 @@ def test_fp64_and_integer_transforms_agree(logN):
     slots = synth.slot_values(32, count, dev.M, 0, prm.p)
     r = synth.encrypt_randomness(33, count, prm.N)
     outs = run_all(dev, dk, slots, r)
+    dev.set_tuning(bc.BC_TUNE_RAW_HANDOFF, 1)
     want = (slots.astype(np.int64) ** 2 % prm.p).astype(np.uint32)
     for i, (ct, prod, dec, ms) in enumerate(outs):
         assert np.array_equal(ct, outs[0][0]), SCHEDULES[i]
