@@ -85,6 +85,10 @@ def _load():
             "or_relin": (None, [V, P, P, I, P]),
             "or_automorphism": (None, [V, P, I, I, L, P]),
             "or_rotate": (None, [V, P, P, I, L, P]),
+            "or_find_root_m": (U, [U, U]),
+            "or_poly_eval": (None, [P, I, P, I, U, P]),
+            "or_poly_mod_monic": (None, [P, I, i64p, I, U, P]),
+            "or_cyclo_mul": (None, [P, P, I, i64p, U, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -863,3 +867,124 @@ def to_digits(values, base: int, ndigits: int):
     """Integer -> digit planes, most significant first."""
     v = np.asarray(values, dtype=np.int64)
     return [((v // base ** (ndigits - 1 - i)) % base).astype(np.uint32) for i in range(ndigits)]
+
+
+# ---------------------------------------------------------------------------
+# non-power-of-two cyclotomic rings Z_q[X]/(Phi_m(X)), m odd (Background,
+# "Efficient Polynomial and NTT": polynomials in the integer DFT
+# representation, a (L+1) x phi(m) matrix; the BluesteinNTT converts between
+# coefficients and that representation when the degree phi(m) is not a power
+# of two).  The representation is the values at the primitive m-th roots of
+# unity omega^k, k in Z_m^* ascending; here it is computed by its
+# definition (polynomial evaluation), independently of any fast transform.
+# ---------------------------------------------------------------------------
+
+def _mobius(n: int) -> int:
+    r, k, f = 1, n, 2
+    while f * f <= k:
+        if k % f == 0:
+            k //= f
+            if k % f == 0:
+                return 0
+            r = -r
+        f += 1
+    return -r if k > 1 else r
+
+
+def cyclotomic(m: int) -> list:
+    """Coefficients of Phi_m, lowest first: the product over d | m of
+    (X^d - 1)^mu(m/d) (multiplications first, then the exact divisions)."""
+    divs = [d for d in range(1, m + 1) if m % d == 0]
+    poly = [1]
+    for d in divs:  # multiply by (X^d - 1)
+        if _mobius(m // d) == 1:
+            out = [0] * (len(poly) + d)
+            for i, c in enumerate(poly):
+                out[i + d] += c
+                out[i] -= c
+            poly = out
+    for d in divs:  # divide by (X^d - 1): q_i = q_(i-d) - p_i, from the bottom
+        if _mobius(m // d) == -1:
+            n = len(poly) - d
+            q = [0] * n
+            for i in range(n):
+                q[i] = -poly[i] + (q[i - d] if i >= d else 0)
+            assert all(poly[n + i] == q[n + i - d] for i in range(d)), "inexact division"
+            poly = q
+    while len(poly) > 1 and poly[-1] == 0:
+        poly.pop()
+    return poly
+
+
+def zm_star(m: int) -> list:
+    """The k in [0, m) prime to m, ascending: the positions the DFT
+    representation keeps."""
+    return [k for k in range(m) if math.gcd(k, m) == 1]
+
+
+def bluestein_length(m: int) -> int:
+    """The power-of-two length of Bluestein's convolution: at least 2m - 1."""
+    L = 1
+    while L < 2 * m - 1:
+        L *= 2
+    return L
+
+
+class CycloRing:
+    """Z_q[X]/(Phi_m) for `nprimes` primes: the largest below 2^bits that are
+    1 mod 2 L m (an m-th root of unity, and a power-of-two transform of
+    length L), omega_i the smallest x^((q_i - 1)/m) of order exactly m."""
+
+    def __init__(self, m: int, nprimes: int, bits: int):
+        assert m % 2 == 1 and m >= 3
+        self.m = m
+        self.L = bluestein_length(m)
+        self.phi = cyclotomic(m)
+        self.N = len(self.phi) - 1
+        self.zm = zm_star(m)
+        assert len(self.zm) == self.N
+        L = lib()
+        out = np.zeros(nprimes, dtype=np.uint64)
+        n = L.or_gen_primes(2 * self.L * m, bits, nprimes, _p(np.zeros(1, np.uint64)), 0, _p(out))
+        assert n == nprimes, "not enough primes"
+        self.moduli = [int(q) for q in out]
+        self.omega = [int(L.or_find_root_m(q, m)) for q in self.moduli]
+        self._phi = np.array(self.phi, dtype=np.int64)
+
+    def forward(self, a: np.ndarray) -> np.ndarray:
+        """a[nprimes][N] coefficients -> values a(omega^k), k in Z_m^* ascending."""
+        out = np.zeros_like(a, dtype=np.uint64)
+        for i, (q, w) in enumerate(zip(self.moduli, self.omega)):
+            pts = np.array([pow(w, k, q) for k in self.zm], dtype=np.uint64)
+            self_a = np.ascontiguousarray(a[i], dtype=np.uint64)
+            lib().or_poly_eval(_p(self_a), self.N, _p(pts), self.N, q, _p(out[i]))
+        return out
+
+    def inverse(self, A: np.ndarray) -> np.ndarray:
+        """Values at the primitive roots -> the coefficients of the unique
+        polynomial of degree < N taking them: the inverse length-m DFT of the
+        values placed at k in Z_m^* (zero elsewhere), b_j = m^-1 sum_k A_k
+        omega^(-jk), is a polynomial of degree < m with those values at the
+        primitive roots; its remainder modulo Phi_m is the answer."""
+        out = np.zeros_like(A, dtype=np.uint64)
+        m = self.m
+        for i, (q, w) in enumerate(zip(self.moduli, self.omega)):
+            c = np.zeros(m, dtype=np.uint64)
+            c[self.zm] = A[i]
+            wi = pow(w, q - 2, q)
+            pts = np.array([pow(wi, j, q) for j in range(m)], dtype=np.uint64)
+            b = np.zeros(m, dtype=np.uint64)
+            lib().or_poly_eval(_p(c), m, _p(pts), m, q, _p(b))
+            minv = pow(m, q - 2, q)
+            b = np.array([int(x) * minv % q for x in b], dtype=np.uint64)
+            lib().or_poly_mod_monic(_p(b), m, self._phi.ctypes.data_as(i64p), self.N, q, _p(out[i]))
+        return out
+
+    def mul(self, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+        """a b mod (Phi_m, q_i): schoolbook product and long division."""
+        out = np.zeros_like(a, dtype=np.uint64)
+        for i, q in enumerate(self.moduli):
+            x = np.ascontiguousarray(a[i], dtype=np.uint64)
+            y = np.ascontiguousarray(b[i], dtype=np.uint64)
+            lib().or_cyclo_mul(_p(x), _p(y), self.N, self._phi.ctypes.data_as(i64p), q, _p(out[i]))
+        return out

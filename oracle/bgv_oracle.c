@@ -646,3 +646,75 @@ void or_rotate(const or_ctx *c, const u64 *gk, const u64 *ct, int level, i64 g, 
     free(sg);
     free(ks);
 }
+
+/* ------------------------------------------------------------------ */
+/* cyclotomic rings of odd order m (the non-power-of-two rings)        */
+/* ------------------------------------------------------------------ */
+
+/* Smallest x >= 2 whose power x^((q-1)/m) has order exactly m (m | q - 1):
+ * w^(m/r) != 1 for every prime r dividing m. */
+u64 or_find_root_m(u64 q, u64 m) {
+    u64 fac[32];
+    int nf = 0;
+    u64 t = m;
+    for (u64 r = 2; r * r <= t; r++)
+        if (t % r == 0) {
+            fac[nf++] = r;
+            while (t % r == 0) t /= r;
+        }
+    if (t > 1) fac[nf++] = t;
+    for (u64 x = 2; x < q; x++) {
+        u64 w = or_powmod(x, (q - 1) / m, q);
+        int ok = w != 1 || m == 1;
+        for (int i = 0; i < nf && ok; i++)
+            if (or_powmod(w, m / fac[i], q) == 1) ok = 0;
+        if (ok) return w;
+    }
+    return 0;
+}
+
+/* Horner evaluation: out[k] = sum_{i<n} a[i] x[k]^i mod q. */
+void or_poly_eval(const u64 *a, int n, const u64 *x, int npts, u64 q, u64 *out) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < npts; k++) {
+        u64 acc = 0;
+        for (int i = n - 1; i >= 0; i--) acc = addmod(or_mulmod(acc, x[k], q), a[i], q);
+        out[k] = acc;
+    }
+}
+
+/* Remainder of b (length nb) modulo the monic phi of degree n (phi[0..n],
+ * signed coefficients) over Z_q, by long division; out has n words. */
+void or_poly_mod_monic(const u64 *b, int nb, const i64 *phi, int n, u64 q, u64 *out) {
+    u64 *r = (u64 *)malloc(sizeof(u64) * (size_t)(nb > n ? nb : n));
+    for (int i = 0; i < nb; i++) r[i] = b[i] % q;
+    for (int i = nb; i < n; i++) r[i] = 0;
+    for (int top = nb - 1; top >= n; top--) {
+        const u64 c = r[top];
+        if (!c) continue;
+        /* r -= c X^(top-n) phi */
+        for (int j = 0; j <= n; j++) {
+            if (!phi[j]) continue;
+            const u64 t = or_mulmod(c, smod(phi[j], q), q);
+            r[top - n + j] = submod(r[top - n + j], t, q);
+        }
+    }
+    memcpy(out, r, sizeof(u64) * n);
+    free(r);
+}
+
+/* Schoolbook product of a and b (n coefficients each) modulo phi (monic,
+ * degree n) over Z_q. */
+void or_cyclo_mul(const u64 *a, const u64 *b, int n, const i64 *phi, u64 q, u64 *out) {
+    const int np = 2 * n - 1;
+    u64 *p = (u64 *)malloc(sizeof(u64) * (size_t)np);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < np; k++) {
+        u64 acc = 0;
+        const int lo = k - (n - 1) > 0 ? k - (n - 1) : 0, hi = k < n - 1 ? k : n - 1;
+        for (int i = lo; i <= hi; i++) acc = addmod(acc, or_mulmod(a[i], b[k - i], q), q);
+        p[k] = acc;
+    }
+    or_poly_mod_monic(p, np, phi, n, q, out);
+    free(p);
+}
