@@ -341,6 +341,43 @@ int bc_tournament(bc_ctx *ctx, const bc_keys *keys, int32_t circuit, int32_t win
 /* Level of bc_tournament's output for an input at in_level (fresh noise). */
 int bc_tournament_levels(const bc_ctx *ctx, int32_t circuit, int32_t in_level, int32_t window, int32_t *out_level);
 
+/* ------------------------------------------- non-power-of-two rings */
+
+/* Transforms of the cyclotomic rings Z_q[X]/(Phi_m(X)), m odd (paper,
+ * Background, "Efficient Polynomial and NTT": when the ring degree
+ * n = phi(m) is not a power of two, BluesteinNTT converts polynomials between
+ * coefficients and the integer DFT representation, a (L+1) x phi(m) matrix).
+ * The representation of a polynomial a (degree < n) modulo prime q_i is the
+ * vector of a(omega_i^k) for the k in [0, m) prime to m, ascending; omega_i is
+ * the smallest x^((q_i - 1)/m), x >= 2, of order exactly m.  A plan fixes m
+ * (odd, 3 <= m <= 32767 with a convolution length L -- the smallest power of
+ * two >= max(2m - 1, 1024) -- of at most 2^16), `nprimes` primes (the largest
+ * below 2^bits, 30 <= bits <= 61, that are 1 mod 2 L m) and everything the
+ * transforms reuse: roots, the chirps TF1 = psi^(j^2) (psi = omega^((m+1)/2)),
+ * the NTT of the padded chirp polynomial, the mask of the kept positions and
+ * its prefix sum (the paper's branch removal: the filter is one independent
+ * selective copy per position, "GPU-related Optimizations"), Phi_m and the
+ * series inverse its remainder step uses.  BC_ERR_PARAM for m, nprimes or
+ * bits out of range.  *out is owned by the caller until bc_bluestein_destroy. */
+typedef struct bc_bluestein bc_bluestein;
+int bc_bluestein_create(int32_t m, int32_t nprimes, int32_t bits, bc_bluestein **out);
+/* Waits for the device and frees the plan (NULL is a no-op). */
+int bc_bluestein_destroy(bc_bluestein *plan);
+/* n = phi(m), the convolution length L, and the primes (nprimes words, or
+ * NULL). */
+int bc_bluestein_info(const bc_bluestein *plan, int32_t *n, int32_t *conv_len, uint64_t *moduli);
+/* Forward (coefficients -> representation) and inverse transforms of `count`
+ * polynomials: in and out are device arrays [count][nprimes][n] of canonical
+ * words (residue i reduced mod prime i), distinct (BC_ERR_ARG in place).
+ * Forward: the input times TF1, zero-padded to L, convolved with the chirp
+ * polynomial through length-L negacyclic NTTs, folded to m words
+ * (c_k = lin_k + lin_(k+m)), times TF1, filtered to the n kept positions.
+ * Inverse: the values placed at their positions, the same convolution with
+ * psi^-1 and m^-1, then the remainder modulo Phi_m.  Enqueued on `stream`;
+ * workspace from the plan's pool.  1 <= count <= 65535. */
+int bc_bluestein_forward(bc_bluestein *plan, const uint64_t *in, uint64_t *out, int32_t count, void *stream);
+int bc_bluestein_inverse(bc_bluestein *plan, const uint64_t *in, uint64_t *out, int32_t count, void *stream);
+
 /* Mixed ring sizes (paper, The Design of BoostCom, "Multi-Level
  * Heterogeneous Parallelization": independent comparisons overlapped to fill
  * the GPU; "GPU-related Optimizations": work batched onto the device at

@@ -923,8 +923,10 @@ def zm_star(m: int) -> list:
 
 
 def bluestein_length(m: int) -> int:
-    """The power-of-two length of Bluestein's convolution: at least 2m - 1."""
-    L = 1
+    """The power-of-two length of Bluestein's convolution: at least 2m - 1,
+    and at least 2^10 (the reading: the smallest transform length the device
+    library runs; the primes, 1 mod 2 L m, follow from it)."""
+    L = 1024
     while L < 2 * m - 1:
         L *= 2
     return L

@@ -111,6 +111,11 @@ _SIGS = {
     "bc_profile_read": (_I, [_V, _I, _P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_double)]),
     "bc_noise_estimate": (_I, [_P(bc_params), _I, _I, ctypes.c_double, ctypes.c_double, _P(ctypes.c_double)]),
     "bc_noise_compare": (_I, [_P(bc_params), _I, ctypes.c_double, _I, _P(ctypes.c_double), _P(ctypes.c_double)]),
+    "bc_bluestein_create": (_I, [_I, _I, _I, _P(_V)]),
+    "bc_bluestein_destroy": (_I, [_V]),
+    "bc_bluestein_info": (_I, [_V, _P(_I), _P(_I), _P(ctypes.c_uint64)]),
+    "bc_bluestein_forward": (_I, [_V, _V, _V, _I, _V]),
+    "bc_bluestein_inverse": (_I, [_V, _V, _V, _I, _V]),
     "bc_strerror": (ctypes.c_char_p, [_I]),
     "bc_last_error": (ctypes.c_char_p, []),
 }
@@ -545,3 +550,44 @@ class Group:
             if o[2] is not None:
                 _take_array(o[2], mn_c)
         return outs
+
+
+class Bluestein:
+    """Transforms of Z_q[X]/(Phi_m(X)), m odd (``bc_bluestein_*``): polynomials
+    as torch uint64 tensors [count][nprimes][n] on the device."""
+
+    def __init__(self, m: int, nprimes: int, bits: int = 50):
+        self.L = lib()
+        h = ctypes.c_void_p()
+        _check(self.L.bc_bluestein_create(m, nprimes, bits, ctypes.byref(h)))
+        self.handle = h
+        n, conv = ctypes.c_int32(), ctypes.c_int32()
+        mods = (ctypes.c_uint64 * nprimes)()
+        _check(self.L.bc_bluestein_info(h, ctypes.byref(n), ctypes.byref(conv), mods))
+        self.m, self.n, self.conv_len, self.nprimes = m, n.value, conv.value, nprimes
+        self.moduli = [int(x) for x in mods]
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self.L.bc_bluestein_destroy(self.handle)
+            self.handle = None
+
+    def new(self, count: int):
+        import torch
+
+        return torch.zeros((count, self.nprimes, self.n), dtype=torch.uint64, device="cuda")
+
+    def _run(self, fn, x, out):
+        import torch
+
+        assert x.dtype == torch.uint64 and x.is_cuda and x.is_contiguous() and tuple(x.shape[1:]) == (self.nprimes, self.n)
+        if out is None:
+            out = self.new(x.shape[0])
+        _check(fn(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), x.shape[0], _stream()))
+        return out
+
+    def forward(self, x, out=None):
+        return self._run(self.L.bc_bluestein_forward, x, out)
+
+    def inverse(self, x, out=None):
+        return self._run(self.L.bc_bluestein_inverse, x, out)

@@ -19,7 +19,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["persist.hip", "ntt.hip", "kernels.hip", "context.cpp", "noise.cpp", "ops.cpp", "circuits.cpp", "capi.cpp"]
+SOURCES = ["persist.hip", "ntt.hip", "kernels.hip", "bluestein.hip", "context.cpp", "noise.cpp", "ops.cpp", "circuits.cpp", "capi.cpp"]
 
 # Packed FP32 instructions are disabled for all device code (the only floating
 # point is the fp64 transform arithmetic; the flag keeps the compiler from

@@ -8,6 +8,7 @@
 #include <sstream>
 
 #include "ops.h"
+#include "bluestein.h"
 #include "persist.h"
 
 namespace bc {
@@ -998,6 +999,45 @@ int bc_tournament(bc_ctx *ctx, const bc_keys *keys, int32_t circuit, int32_t win
         const CtB r = tournament(ctx, keys, x, window, want_max != 0, circuit, st);
         copy_ct(ctx, r, o, st);
         out->noise_bits = (float)nb;
+    });
+}
+
+int bc_bluestein_create(int32_t m, int32_t nprimes, int32_t bits, bc_bluestein **out) {
+    return guard([&] {
+        BC_REQUIRE(out, BC_ERR_ARG, "null output");
+        *out = bluestein_create(m, nprimes, bits);
+    });
+}
+
+int bc_bluestein_destroy(bc_bluestein *plan) {
+    return guard([&] {
+        if (plan) bluestein_destroy(plan);
+    });
+}
+
+int bc_bluestein_info(const bc_bluestein *plan, int32_t *n, int32_t *conv_len, uint64_t *moduli) {
+    return guard([&] {
+        BC_REQUIRE(plan, BC_ERR_ARG, "null plan");
+        int nn = 0, L = 0;
+        bluestein_info(plan, &nn, &L, moduli);
+        if (n) *n = nn;
+        if (conv_len) *conv_len = L;
+    });
+}
+
+int bc_bluestein_forward(bc_bluestein *plan, const uint64_t *in, uint64_t *out, int32_t count, void *stream) {
+    return guard([&] {
+        BC_REQUIRE(plan, BC_ERR_ARG, "null plan");
+        BC_REQUIRE(in != out, BC_ERR_ARG, "the transform does not run in place");
+        bluestein_forward(plan, in, out, count, (hipStream_t)stream);
+    });
+}
+
+int bc_bluestein_inverse(bc_bluestein *plan, const uint64_t *in, uint64_t *out, int32_t count, void *stream) {
+    return guard([&] {
+        BC_REQUIRE(plan, BC_ERR_ARG, "null plan");
+        BC_REQUIRE(in != out, BC_ERR_ARG, "the transform does not run in place");
+        bluestein_inverse(plan, in, out, count, (hipStream_t)stream);
     });
 }
 

@@ -390,8 +390,19 @@ std::vector<u64> param_moduli(const bc_params &prm) {
     return mod;
 }
 
-void build_context(bc_ctx *c, const bc_params &prm) {
-    c->mod = param_moduli(prm);
+void build_context(bc_ctx *c, const bc_params &prm) { build_context_moduli(c, prm, param_moduli(prm)); }
+
+std::vector<u64> primes_one_mod(u64 step, int bits, int count) { return prime_chain(step, bits, count, {}); }
+
+// A context over explicitly chosen primes (each 1 mod 2N); prm supplies the
+// ring degree, the plaintext modulus and the split into nQ + nP primes.
+void build_context_moduli(bc_ctx *c, const bc_params &prm, std::vector<u64> mod) {
+    BC_REQUIRE((int)mod.size() == prm.nQ + prm.nP && prm.nQ >= 1 && prm.nP >= 1 && (int)mod.size() <= kMaxMod,
+               BC_ERR_PARAM, "bad prime counts");
+    for (u64 q : mod)
+        BC_REQUIRE(q % (2 * ((u64)1 << prm.logN)) == 1 && is_prime64(q), BC_ERR_PARAM,
+                   "every prime must be 1 mod 2N");
+    c->mod = std::move(mod);
     c->prm = prm;
     c->logN = prm.logN;
     c->N = 1 << prm.logN;

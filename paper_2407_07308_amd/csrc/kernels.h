@@ -6,6 +6,9 @@
 namespace bc {
 
 void build_context(bc_ctx *c, const bc_params &prm);
+void build_context_moduli(bc_ctx *c, const bc_params &prm, std::vector<u64> mod);
+// the `count` largest primes below 2^bits that are 1 mod step, decreasing
+std::vector<u64> primes_one_mod(u64 step, int bits, int count);
 
 // Size of the fixed device workspace of the allocation-free multiplication
 // (one array per GPU, kept until the process ends).
