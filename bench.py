@@ -54,7 +54,7 @@ def parse():
                     help="bivariate: the scalar combinations on the fp64 vector units instead of the matrix cores")
     ap.add_argument("--packed-cts", type=int, default=64,
                     help="packed: ciphertexts per batch (32 uint16 integers each)")
-    ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate", "bivariate", "packed"],
+    ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate", "bivariate", "packed", "bluestein"],
                     default="uint16",
                     help="uint16: LT+max+min at N=2^15 (default); mixed: 256 single-digit pairs over "
                          "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream; "
@@ -94,6 +94,8 @@ def main():
         return print(json.dumps(bivariate(a)))
     if a.workload == "packed":
         return print(json.dumps(packed(a)))
+    if a.workload == "bluestein":
+        return print(json.dumps(bluestein_bench(a)))
     if a.workload == "rotate":
         return rotate(a)
     import numpy as np
@@ -354,7 +356,8 @@ def main():
         torch.cuda.empty_cache()
         sub = argparse.Namespace(**vars(a))
         sub.window = a.extra_window
-        for name, fn in (("mixed", mixed), ("serving", serve), ("bivariate", bivariate), ("packed", packed)):
+        for name, fn in (("mixed", mixed), ("serving", serve), ("bivariate", bivariate), ("packed", packed),
+                         ("bluestein", bluestein_bench)):
             print(f"bench: {name}", file=sys.stderr, flush=True)
             r = fn(sub)
             for k in ("n_gpus", "higher_is_better", "scaling", "vs_baseline", "dtype", "data"):
@@ -700,6 +703,51 @@ def packed(a):
                        "multiplications_per_ciphertext": 30 + 3, "rotations_per_ciphertext": 3},
             "tournament": {"ms_per_call": t_ms, "window": 2, "ciphertexts": G,
                            "min_pairs_per_s": G * M / (t_ms / 1e3)}}
+
+
+def bluestein_bench(a):
+    """Transforms of the non-power-of-two ring Z_q[X]/(Phi_m), m = 18157
+    (n = phi(m) = 17820, convolution length 2^16), on 16 polynomials of 14
+    primes each (a ciphertext's worth of limbs): forward and inverse timed
+    separately, checked by the round trip."""
+    import numpy as np
+    import torch
+
+    import paper_2407_07308_amd as bc
+    import synth
+
+    torch.cuda.set_device(0)
+    m, nprimes, count = 18157, 14, 16
+    plan = bc.Bluestein(m, nprimes, 50)
+    g = synth.generator(SEED + 7, "poly")
+    x = np.stack([np.stack([g.integers(0, q, plan.n, dtype=np.uint64) for q in plan.moduli]) for _ in range(count)])
+    xd = torch.from_numpy(x).cuda()
+    fx = plan.forward(xd)
+    back = plan.inverse(fx)
+    torch.cuda.synchronize()
+    if not torch.equal(back, xd):
+        print("bench: Bluestein round trip failed", file=sys.stderr)
+        sys.exit(3)
+    steps = max(3, min(a.steps, 10))
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(steps):
+        plan.forward(xd, out=fx)
+    e1.record()
+    for _ in range(steps):
+        plan.inverse(fx, out=back)
+    e2.record()
+    torch.cuda.synchronize()
+    fwd, inv = e0.elapsed_time(e1) / steps, e1.elapsed_time(e2) / steps
+    limbs = count * nprimes
+    return {"metric": "non-power-of-two ring transforms (forward + inverse), limbs/s", "value": limbs / ((fwd + inv) / 1e3),
+            "unit": "limbs/s", "n_gpus": 1, "steps": steps, "higher_is_better": True, "dtype": "u64",
+            "data": "synthetic",
+            "config": {"workload": f"Z_q[X]/(Phi_m), m={m} (n={plan.n}), convolution length {plan.conv_len}, "
+                                   f"{count} polynomials x {nprimes} primes of 50 bits, Bluestein forward and inverse"},
+            "forward_ms": fwd, "inverse_ms": inv,
+            "forward_us_per_limb": 1e3 * fwd / limbs, "inverse_us_per_limb": 1e3 * inv / limbs,
+            "forward_algorithmic_GBs": 16.0 * plan.n * limbs / (fwd / 1e3) / 1e9}
 
 
 def serve(a):

@@ -26,7 +26,9 @@
 // degree n = phi(m): with D = m - n, the quotient h of b by Phi_m satisfies
 // rev(h) = rev(b) rev(Phi_m)^-1 mod X^D (reversals at degrees D-1, m-1, n),
 // a short product with a series inverse computed once per prime, and the
-// remainder is b - h Phi_m on the low n coefficients.
+// remainder is b - h Phi_m on the low n coefficients, h Phi_m (degree m - 1 <
+// L) formed on the same length-L transforms with Phi_m's transform computed
+// once per prime.
 //
 // Plan reuse (same section: plan reuse for BluesteinFFT): primes, roots,
 // chirps, the transformed chirp polynomials, the mask and its prefix sum, the
@@ -48,9 +50,9 @@ struct bc_bluestein {
     bc_ctx *nt = nullptr;  // power-of-two transform context of length L over the plan's primes
     // device tables, [np][len][2] pairs (value, Shoup companion)
     bc::u64 *tf = nullptr, *tfi = nullptr, *tfis = nullptr, *dh = nullptr, *dih = nullptr, *rinv = nullptr;
+    bc::u64 *phih = nullptr;  // transform of Phi_m zero-padded to L
     uint8_t *inz = nullptr;
     int *sumz = nullptr;
-    int64_t *phi = nullptr;  // Phi_m's coefficients (n + 1), the same for every prime
     ~bc_bluestein();
 };
 
@@ -121,38 +123,33 @@ __global__ void k_bs_fold_chirp(u64 *__restrict__ W, const u64 *__restrict__ tfi
     w[j] = shoup(add_mod(w[j], w[j + m], q), t[0], t[1], q);
 }
 
-// quotient of b (W[.][.][0..m)) by Phi_m: rev(h)_s = sum_(u <= s) b_(m-1-u) rinv_(s-u),
-// h_(D-1-s) = rev(h)_s, s < D
+// quotient of b (W[.][.][0..m)) by Phi_m, zero-padded to L: for s < D,
+// rev(h)_s = sum_(u <= s) b_(m-1-u) rinv_(s-u) goes to position D-1-s;
+// positions D .. L-1 are zero
 __global__ void k_bs_quotient(const u64 *__restrict__ W, u64 *__restrict__ H, const u64 *__restrict__ rinv,
                               const PrimeInfo *__restrict__ pinfo, int m, int D, int L, int np) {
     const int s = blockIdx.x * kBT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
-    if (s >= D) return;
+    if (s >= L) return;
+    u64 *hrow = H + ((size_t)ct * np + i) * L;
+    if (s >= D) {
+        hrow[s] = 0;
+        return;
+    }
     const u64 q = pinfo[i].q;
     const u64 *b = W + ((size_t)ct * np + i) * L;
     const u64 *r = rinv + (size_t)i * D * 2;
     u64 acc = 0;
     for (int u = 0; u <= s; u++) acc = add_mod(acc, shoup(b[m - 1 - u], r[2 * (s - u)], r[2 * (s - u) + 1], q), q);
-    H[((size_t)ct * np + i) * D + (D - 1 - s)] = acc;
+    hrow[D - 1 - s] = acc;
 }
 
-// a_j = b_j - sum_(k <= min(D-1, j)) h_k Phi_(j-k), j < n.  Phi_m's
-// coefficients are small integers: the positive and negative parts are summed
-// as integers (bounded at plan creation below 2^63) and reduced once.
-__global__ void k_bs_reduce(const u64 *__restrict__ W, const u64 *__restrict__ H, const int64_t *__restrict__ phi,
-                            u64 *__restrict__ out, const PrimeInfo *__restrict__ pinfo, int n, int D, int L, int np) {
+// a_j = b_j - (h Phi_m)_j, j < n
+__global__ void k_bs_remainder(const u64 *__restrict__ W, const u64 *__restrict__ HP, u64 *__restrict__ out,
+                               const PrimeInfo *__restrict__ pinfo, int n, int L, int np) {
     const int j = blockIdx.x * kBT + threadIdx.x, i = blockIdx.y, ct = blockIdx.z;
     if (j >= n) return;
-    const u64 q = pinfo[i].q;
-    const u64 *h = H + ((size_t)ct * np + i) * D;
-    u64 pos = 0, neg = 0;
-    const int kmax = j < D - 1 ? j : D - 1;
-    for (int k = 0; k <= kmax; k++) {
-        const int64_t c = phi[j - k];
-        if (c > 0) pos += h[k] * (u64)c;
-        else if (c < 0) neg += h[k] * (u64)(-c);
-    }
-    const u64 t = sub_mod(pos % q, neg % q, q);
-    out[((size_t)ct * np + i) * n + j] = sub_mod(W[((size_t)ct * np + i) * L + j], t, q);
+    const size_t row = ((size_t)ct * np + i) * L;
+    out[((size_t)ct * np + i) * n + j] = sub_mod(W[row + j], HP[row + j], pinfo[i].q);
 }
 
 dim3 grid_of(int len, int np, int count) { return dim3((unsigned)((len + kBT - 1) / kBT), (unsigned)np, (unsigned)count); }
@@ -269,15 +266,11 @@ bc_bluestein *bluestein_create(int m, int np, int bits) {
     const std::vector<int64_t> phi = cyclotomic_poly(m);
     b->n = (int)phi.size() - 1;
     b->D = m - b->n;
-    int64_t amax = 0;
-    for (int64_t c : phi) amax = std::max<int64_t>(amax, c < 0 ? -c : c);
     // primes 1 mod 2 L m (m-th roots, negacyclic transforms of length L); one
     // more serves as the transform context's unused special prime
     const u64 step = 2 * (u64)b->L * (u64)m;
     std::vector<u64> pr = primes_one_mod(step, bits, np + 1);
     b->mod.assign(pr.begin(), pr.begin() + np);
-    BC_REQUIRE((double)amax * b->D * std::ldexp(1.0, bits) < std::ldexp(1.0, 63), BC_ERR_PARAM,
-               "Phi_m's coefficients too large for the remainder kernel");
     bc_params prm{logL, 3, np, bits, 1, bits, np};
     b->nt = new bc_ctx();
     build_context_moduli(b->nt, prm, pr);
@@ -293,7 +286,7 @@ bc_bluestein *bluestein_create(int m, int np, int bits) {
         run += inz[k];
     }
     BC_REQUIRE(run == n, BC_ERR_PARAM, "phi(m) and the cyclotomic degree disagree");
-    std::vector<u64> tf, tfi, tfis, dpad((size_t)np * L, 0), dipad((size_t)np * L, 0), rinv;
+    std::vector<u64> tf, tfi, tfis, dpad((size_t)np * L, 0), dipad((size_t)np * L, 0), phpad((size_t)np * L, 0), rinv;
     for (int i = 0; i < np; i++) {
         const u64 q = b->mod[i];
         const u64 w = order_m_root(q, (u64)m), psi = h_powmod(w, (u64)(m + 1) / 2, q);
@@ -324,6 +317,7 @@ bc_bluestein *bluestein_create(int m, int np, int bits) {
             rv[s] = acc;
         }
         for (int s = 0; s < D; s++) push_pair(rinv, rv[s], q);
+        for (int j = 0; j <= n; j++) phpad[(size_t)i * L + j] = rp[n - j];
     }
     b->tf = upload_vec(tf);
     b->tfi = upload_vec(tfi);
@@ -331,10 +325,10 @@ bc_bluestein *bluestein_create(int m, int np, int bits) {
     b->rinv = upload_vec(rinv);
     b->inz = upload_vec(inz);
     b->sumz = upload_vec(sumz);
-    b->phi = upload_vec(phi);
-    // the transformed chirp polynomials (once per plan), with Shoup companions
-    for (int pass = 0; pass < 2; pass++) {
-        std::vector<u64> &h = pass ? dipad : dpad;
+    // the transformed chirp polynomials and Phi_m (once per plan), with Shoup
+    // companions
+    for (int pass = 0; pass < 3; pass++) {
+        std::vector<u64> &h = pass == 2 ? phpad : pass ? dipad : dpad;
         u64 *d = upload_vec(h);
         ntt_forward(b->nt, plan_limbs(b.get(), d, 1), nullptr);
         BC_HIP(hipMemcpy(h.data(), d, sizeof(u64) * h.size(), hipMemcpyDeviceToHost));
@@ -343,7 +337,7 @@ bc_bluestein *bluestein_create(int m, int np, int bits) {
         pairs.reserve(2 * h.size());
         for (int i = 0; i < np; i++)
             for (int j = 0; j < L; j++) push_pair(pairs, h[(size_t)i * L + j], b->mod[i]);
-        (pass ? b->dih : b->dh) = upload_vec(pairs);
+        (pass == 2 ? b->phih : pass ? b->dih : b->dh) = upload_vec(pairs);
     }
     return b.release();
 }
@@ -374,7 +368,7 @@ void bluestein_inverse(bc_bluestein *b, const u64 *in, u64 *out, int count, hipS
     BC_REQUIRE(count >= 1 && count <= 65535 && in && out, BC_ERR_ARG, "bad batch");
     StreamTag tag(st);
     BufP W = make_buf(b->nt, sizeof(u64) * (size_t)count * b->np * b->L);
-    BufP H = make_buf(b->nt, sizeof(u64) * (size_t)count * b->np * std::max(1, b->D));
+    BufP H = make_buf(b->nt, sizeof(u64) * (size_t)count * b->np * b->L);
     u64 *w = (u64 *)W->p, *h = (u64 *)H->p;
     const PrimeInfo *pi = b->nt->pinfo;
     k_bs_unfilter_chirp<<<grid_of(b->L, b->np, count), kBT, 0, st>>>(in, w, b->tfi, b->inz, b->sumz, pi, b->n, b->m,
@@ -382,8 +376,10 @@ void bluestein_inverse(bc_bluestein *b, const u64 *in, u64 *out, int count, hipS
     BC_HIP(hipGetLastError());
     convolve(b, w, b->dih, count, st);
     k_bs_fold_chirp<<<grid_of(b->m, b->np, count), kBT, 0, st>>>(w, b->tfis, pi, b->m, b->L, b->np);
-    k_bs_quotient<<<grid_of(b->D, b->np, count), kBT, 0, st>>>(w, h, b->rinv, pi, b->m, b->D, b->L, b->np);
-    k_bs_reduce<<<grid_of(b->n, b->np, count), kBT, 0, st>>>(w, h, b->phi, out, pi, b->n, b->D, b->L, b->np);
+    k_bs_quotient<<<grid_of(b->L, b->np, count), kBT, 0, st>>>(w, h, b->rinv, pi, b->m, b->D, b->L, b->np);
+    BC_HIP(hipGetLastError());
+    convolve(b, h, b->phih, count, st);  // h Phi_m
+    k_bs_remainder<<<grid_of(b->n, b->np, count), kBT, 0, st>>>(w, h, out, pi, b->n, b->L, b->np);
     BC_HIP(hipGetLastError());
 }
 
@@ -391,8 +387,8 @@ void bluestein_inverse(bc_bluestein *b, const u64 *in, u64 *out, int count, hipS
 
 bc_bluestein::~bc_bluestein() {
     (void)hipDeviceSynchronize();
-    for (void *p : {(void *)tf, (void *)tfi, (void *)tfis, (void *)dh, (void *)dih, (void *)rinv, (void *)inz,
-                    (void *)sumz, (void *)phi})
+    for (void *p : {(void *)tf, (void *)tfi, (void *)tfis, (void *)dh, (void *)dih, (void *)rinv, (void *)phih,
+                    (void *)inz, (void *)sumz})
         if (p) (void)hipFree(p);
     delete nt;
 }
