@@ -59,6 +59,8 @@ def parse():
                     help="uint16: LT+max+min at N=2^15 (default); mixed: 256 single-digit pairs over "
                          "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream; "
                          "rotate: slot rotations of 192 ciphertexts at N=2^15")
+    ap.add_argument("--serve-streams", type=int, default=2, help="serving: batches in flight (streams)")
+    ap.add_argument("--serve-max-groups", type=int, default=32, help="serving: groups per batch at most")
     ap.add_argument("--window", type=float, default=10.0, help="serving: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: mean requests per second")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -804,7 +806,7 @@ def serve(a):
         r.xs, r.ys = xs, ys
         reqs.append(r)
     torch.cuda.synchronize()
-    srv = serving.Server(members, max_batch_groups=32, streams=2)
+    srv = serving.Server(members, max_batch_groups=a.serve_max_groups, streams=a.serve_streams)
     step = max(1, len(reqs) // 20)
     checked = reqs[:: max(1, len(reqs) // 8)]
     keep = {id(r) for r in checked}

@@ -6,15 +6,21 @@ for LT, MAX or ARGMAX (the LT bit: 1 where the second operand is larger).  The
 server keeps keys resident per ring size, admits arrived requests while the
 device-memory estimate of the work in flight stays under a budget, coalesces
 admitted requests of one ring size into a single batch (their planes are
-concatenated on the device), launches the batched comparison on one of
-several streams so consecutive batches overlap on the GPU, and completes
-requests by polling the batch's event.  Latency = completion time - arrival
-time.  Everything the batch computes runs in the library's kernels; this loop
-only schedules.
+concatenated on the device), and launches batched comparisons on every free
+stream -- batches of different ring sizes side by side, the oldest waiting
+ring size first -- so they overlap on the GPU.  Each batch in flight has a
+waiter thread blocked on its completion event (the HIP event wait releases
+the interpreter lock), which hands the finished batch to the loop through a
+queue; the loop sleeps on that queue until a batch finishes or the next
+request arrives, and never polls.  Latency = completion time - arrival time.
+Everything the batch computes runs in the library's kernels; this loop only
+schedules.
 """
 from __future__ import annotations
 
 import collections
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -149,6 +155,33 @@ class Server:
         # keep the concatenated inputs alive until the batch completes
         return _InFlight(reqs, ev, (outs, A, B), offsets, sum(self._group_bytes(N, len(r.a)) * r.groups for r in reqs))
 
+    def _next_batch(self, ready, used: int, any_inflight: bool):
+        """The next admissible batch: requests of one ring size, taken in
+        arrival order, ring sizes tried in the order of their oldest waiting
+        request; at most max_batch_groups groups and within the memory budget
+        (a single request is admitted over budget only when nothing is in
+        flight).  Returns (requests, bytes) or None."""
+        sizes = []
+        for r in ready:
+            if r.N not in sizes:
+                sizes.append(r.N)
+        for N in sizes:
+            batch, nbytes, g = [], 0, 0
+            for r in ready:
+                if r.N != N:
+                    continue
+                need = self._group_bytes(N, len(r.a)) * r.groups
+                if batch and (g + r.groups > self.max_batch_groups or used + nbytes + need > self.budget):
+                    break
+                if not batch and used + need > self.budget and (any_inflight or nbytes):
+                    break  # wait for memory to free up
+                batch.append(r)
+                nbytes += need
+                g += r.groups
+            if batch:
+                return batch, nbytes
+        return None
+
     def run(self, requests: list, clock=time.perf_counter, progress=None, on_complete=None):
         """Serves `requests` (sorted by arrival) against their arrival times;
         returns them completed, with latencies filled in.  `progress(done,
@@ -158,61 +191,74 @@ class Server:
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         ready = collections.deque()
         inflight: list[_InFlight] = []
-        busy = [False] * len(self.streams)
+        free = list(range(len(self.streams)))
+        finished: queue.Queue = queue.Queue()
         t0 = clock()
         used = 0
         done = 0
+
+        def wait_for(f):
+            f.event.synchronize()
+            finished.put(f)
+
+        def complete(f):
+            nonlocal used, done
+            t = clock() - t0
+            f.waiter.join()
+            (lt, mx, _), _, _ = f.outs
+            for r, off in zip(f.reqs, f.offsets):
+                ctx = self.members[r.N][0]
+                r.result = (_slice(lt, ctx, off, r.groups),
+                            [_slice(m, ctx, off, r.groups) for m in mx] if (mx and r.kind == "max") else None)
+                r.done_at = t
+                if on_complete:
+                    on_complete(r)
+            used -= f.bytes
+            free.append(f.stream)
+            inflight.remove(f)
+            done += len(f.reqs)
+            held = sum(c.pool_bytes() for c, _ in self.members.values())
+            self.stats["max_pool_bytes"] = max(self.stats.get("max_pool_bytes", 0), held)
+            if progress:
+                progress(done, len(requests))
+
         while pending or ready or inflight:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 ready.append(pending.popleft())
-            for f in list(inflight):
-                if f.event.query():
-                    t = clock() - t0
-                    (lt, mx, _), _, _ = f.outs
-                    for r, off in zip(f.reqs, f.offsets):
-                        ctx = self.members[r.N][0]
-                        r.result = (_slice(lt, ctx, off, r.groups),
-                                    [_slice(m, ctx, off, r.groups) for m in mx] if (mx and r.kind == "max") else None)
-                        r.done_at = t
-                        if on_complete:
-                            on_complete(r)
-                    used -= f.bytes
-                    busy[f.stream] = False
-                    inflight.remove(f)
-                    done += len(f.reqs)
-                    held = sum(c.pool_bytes() for c, _ in self.members.values())
-                    self.stats["max_pool_bytes"] = max(self.stats.get("max_pool_bytes", 0), held)
-                    if progress:
-                        progress(done, len(requests))
-            launched = False
-            if ready and not all(busy):
-                N = ready[0].N  # ring size of the oldest waiting request
-                batch, nbytes, g = [], 0, 0
-                for r in list(ready):
-                    if r.N != N:
-                        continue
-                    need = self._group_bytes(N, len(r.a)) * r.groups
-                    if batch and (g + r.groups > self.max_batch_groups or used + nbytes + need > self.budget):
-                        break
-                    if not batch and used + need > self.budget and inflight:
-                        break  # wait for memory to free up
-                    batch.append(r)
-                    nbytes += need
-                    g += r.groups
-                if batch:
-                    for r in batch:
-                        ready.remove(r)
-                    si = busy.index(False)
-                    f = self._launch(batch, si)
-                    f.stream = si
-                    busy[si] = True
-                    used += nbytes
-                    self.stats["max_inflight_bytes"] = max(self.stats["max_inflight_bytes"], used)
-                    inflight.append(f)
-                    launched = True
-            if not launched:
-                time.sleep(0.0002)
+            while True:  # batches that finished meanwhile
+                try:
+                    complete(finished.get_nowait())
+                except queue.Empty:
+                    break
+            # fill every free stream with an admissible batch
+            while ready and free:
+                nb = self._next_batch(ready, used, bool(inflight))
+                if nb is None:
+                    break
+                batch, nbytes = nb
+                for r in batch:
+                    ready.remove(r)
+                si = free.pop(0)
+                f = self._launch(batch, si)
+                f.stream = si
+                used += nbytes
+                self.stats["max_inflight_bytes"] = max(self.stats["max_inflight_bytes"], used)
+                self.stats["max_concurrent_batches"] = max(self.stats.get("max_concurrent_batches", 0),
+                                                           len(inflight) + 1)
+                f.waiter = threading.Thread(target=wait_for, args=(f,), daemon=True)
+                inflight.append(f)
+                f.waiter.start()
+            # sleep until a batch finishes or the next request arrives
+            if pending or inflight:
+                timeout = max(0.0, pending[0].arrival - (clock() - t0)) if pending else None
+                if inflight:
+                    try:
+                        complete(finished.get(timeout=timeout))
+                    except queue.Empty:
+                        pass
+                elif timeout:
+                    time.sleep(timeout)
         return requests
 
 
