@@ -379,10 +379,10 @@ KINDS = {
                         "desc": "forward NTT of the relinearise+switch correction with the multiplication's last step "
                                 "as its store (32 N bytes per limb: the limb, d and the accumulator read, the result "
                                 "written)"},
-    "forward_part": {"prof": "BC_PROF_NTT_FWD_PART", "re": r"ntt_part<\d+, [^,]+, \d+(, false)?>",
+    "forward_part": {"prof": "BC_PROF_NTT_FWD_PART", "re": r"ntt_part<\d+, [^,]+, \d+(, false(, (true|false)){0,2})?>",
                      "src": ["ntt.hip", "ntt_dev.h", "context.cpp", "bc_internal.h"],
                      "desc": "forward NTT of the raised limbs, 2^13-word part-limb blocks (16 N bytes per limb)"},
-    "inverse_part": {"prof": "BC_PROF_NTT_INV_PART", "re": r"ntt_part<\d+, [^,]+, \d+, true>",
+    "inverse_part": {"prof": "BC_PROF_NTT_INV_PART", "re": r"ntt_part<\d+, [^,]+, \d+, true(, (true|false)){0,2}>",
                      "src": ["ntt.hip", "ntt_dev.h", "context.cpp", "bc_internal.h"],
                      "desc": "inverse NTT of the key-switched limbs, 2^13-word part-limb blocks (16 N bytes per limb)"},
     "forward": {"prof": "BC_PROF_NTT_FWD", "re": r"ntt_(full|cols|rows)<\d+, false",
