@@ -446,6 +446,20 @@ class Oracle:
         self.lib.or_rotate(self.ctx, _p(self.keys["gk"][step]), _p(ct.data), ct.level, g, _p(out))
         return Ct(out, ct.level)
 
+    def mul_monomial(self, ct: Ct, e: int) -> Ct:
+        """ct times the monomial x^e (any integer e; x^N = -1): every
+        coefficient a_i of every component and limb moves to x^(i+e), negated
+        when i + e wraps past N an odd number of times.  No noise growth."""
+        N = self.N
+        idx = (np.arange(N, dtype=np.int64) + e) % (2 * N)
+        pos, neg = idx % N, idx >= N
+        out = np.zeros_like(ct.data)
+        for i in range(ct.level + 1):
+            q = np.uint64(self.q[i])
+            a = ct.data[:, i, :]
+            out[:, i, pos] = np.where(neg, (q - a) % q, a)
+        return Ct(out, ct.level)
+
     def negacyclic_mul(self, prime: int, a: np.ndarray, b: np.ndarray) -> np.ndarray:
         out = np.zeros(self.N, np.uint64)
         self.lib.or_negacyclic_mul(self.ctx, prime, _p(np.ascontiguousarray(a, np.uint64)),
@@ -861,6 +875,99 @@ def tournament(ev, x, p: int, k: int, want_max: bool = False, circuit: str = "un
         X = ev.mul_add(L, ev.sub(Yl, Xl), Xl) if want_max else ev.mul_add(L, ev.sub(Xl, Yl), Yl)
         s *= 2
     return X
+
+
+# ---------------------------------------------------------------------------
+# F_{p^d} slots and the "mod extract" of their F_p digits (Background,
+# "Word-wise Universal FHE Scheme": an integer is an element of F_{p^d}^l,
+# each F_{p^d} component split into F_p digits before the per-digit LT/EQ)
+# ---------------------------------------------------------------------------
+
+def fpd_degree(p: int, N: int) -> int:
+    """d = N / M.  Over F_p, x^N + 1 = prod_j (x^d - zeta_j) with the slot
+    roots zeta_j of ``slot_roots``; d is the order of p modulo 2N, so each
+    factor is irreducible and slot j holds an element of
+    F_p[x]/(x^d - zeta_j), a field of p^d elements."""
+    return N // slot_count(p)
+
+
+def encode_fpd(E, p: int, N: int) -> np.ndarray:
+    """Plaintext whose slot j holds sum_k E[j][k] x^k in F_p[x]/(x^d - zeta_j)
+    (the power basis 1, x, ..., x^(d-1)): m = sum_k x^k mu_k(x^d), mu_k the
+    slot encoding of column k (``encode_poly``), so coefficient d i + k of m
+    is coefficient d i of column k's encoding."""
+    M = slot_count(p)
+    d = N // M
+    E = np.asarray(E, dtype=np.int64).reshape(M, d) % p
+    out = np.zeros(N, dtype=np.uint32)
+    for k in range(d):
+        if E[:, k].any():
+            out[k::d] = encode_poly(E[:, k], p, N)[0::d]
+    return out
+
+
+def decode_fpd(m, p: int, N: int) -> np.ndarray:
+    """The slots of m as F_{p^d} elements, by definition: m mod (x^d - zeta_j),
+    with x^(d i + k) = zeta_j^i x^k; row j holds its power-basis coordinates."""
+    M = slot_count(p)
+    d = N // M
+    rows = np.asarray(m, dtype=np.int64).reshape(M, d) % p  # row i: coefficients d i .. d i + d - 1
+    out = np.zeros((M, d), dtype=np.int64)
+    for j, z in enumerate(slot_roots(p, M)):
+        zi = np.array([pow(z, i, p) for i in range(M)], dtype=np.int64)
+        out[j] = (zi[:, None] * rows).sum(axis=0) % p
+    return out
+
+
+def fpd_slot_mul(a, b, z: int, p: int) -> np.ndarray:
+    """Product in F_p[x]/(x^d - z): the full product, then x^(d + k) = z x^k."""
+    a, b = np.asarray(a, dtype=np.int64), np.asarray(b, dtype=np.int64)
+    d = len(a)
+    c = np.convolve(a, b) % p
+    out = c[:d].copy()
+    out[: d - 1] = (out[: d - 1] + z * c[d:]) % p
+    return out
+
+
+def plain_automorphism(m, g: int, N: int, p: int) -> np.ndarray:
+    """m(x^g) mod (x^N + 1, p), g odd: coefficient i moves to x^(i g)."""
+    out = np.zeros(N, dtype=np.int64)
+    for i, c in enumerate(np.asarray(m, dtype=np.int64)):
+        j = i * g % (2 * N)
+        if j < N:
+            out[j] = (out[j] + c) % p
+        else:
+            out[j - N] = (out[j - N] - c) % p
+    return out
+
+
+def frobenius_steps(p: int, N: int) -> list[int]:
+    """Rotation steps r_b with 5^(r_b) = p^(2^b) mod 2N, b < log2(d): the
+    automorphisms x -> x^(p^(2^b)) are Frobenius powers on every F_{p^d} slot
+    (p = 1 mod 4, so p lies in the cyclic group <5> of order N/2 mod 2N and
+    the rotation keys serve them).  Found by walking the powers of 5."""
+    twoN = 2 * N
+    log5, x = {}, 1
+    for r in range(N // 2):
+        log5[x] = r
+        x = x * 5 % twoN
+    t = fpd_degree(p, N).bit_length() - 1
+    return [log5[pow(p, 1 << b, twoN)] for b in range(t)]
+
+
+def extract_digit(ev, orc: "Oracle", ct: Ct, k: int, p: int) -> Ct:
+    """Coordinate k of every slot's F_{p^d} element, as the F_p slot values of
+    a new ciphertext: d^-1 Tr(x^-k m).  The trace Tr = sum over the Frobenius
+    group <p> (order d) of x -> x^g fixes mu(x^d) and takes x^j, 0 < |j| < d,
+    to zero (x^j is a root of unity of order above 2M in each slot, whose
+    minimal polynomial over F_p is a binomial of degree > 1, so its conjugates
+    sum to zero); so Tr(x^-k m) = d mu_k(x^d).  The sum over the group is taken
+    as log2(d) doublings z <- z + sigma_{p^(2^b)}(z), each a rotation."""
+    N = orc.N
+    z = orc.mul_monomial(ct, 2 * N - k)  # x^-k = -x^(N-k)
+    for r in frobenius_steps(p, N):
+        z = ev.add(z, ev.rotate(z, r))
+    return ev.mul_scalar(z, pow(fpd_degree(p, N), -1, p))
 
 
 def to_digits(values, base: int, ndigits: int):
