@@ -54,7 +54,9 @@ def parse():
                     help="bivariate: the scalar combinations on the fp64 vector units instead of the matrix cores")
     ap.add_argument("--packed-cts", type=int, default=64,
                     help="packed: ciphertexts per batch (32 uint16 integers each)")
-    ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate", "bivariate", "packed", "bluestein"],
+    ap.add_argument("--fpd-cts", type=int, default=32,
+                    help="fpd: ciphertexts per batch (128 uint16 values each, two F_p digits per F_257^256 slot)")
+    ap.add_argument("--workload", choices=["uint16", "mixed", "serving", "rotate", "bivariate", "packed", "bluestein", "fpd"],
                     default="uint16",
                     help="uint16: LT+max+min at N=2^15 (default); mixed: 256 single-digit pairs over "
                          "N in {2^13,2^14,2^15} in one graph; serving: Poisson request stream; "
@@ -98,6 +100,8 @@ def main():
         return print(json.dumps(packed(a)))
     if a.workload == "bluestein":
         return print(json.dumps(bluestein_bench(a)))
+    if a.workload == "fpd":
+        return print(json.dumps(fpd_bench(a)))
     if a.workload == "rotate":
         return rotate(a)
     import numpy as np
@@ -359,7 +363,7 @@ def main():
         sub = argparse.Namespace(**vars(a))
         sub.window = a.extra_window
         for name, fn in (("mixed", mixed), ("serving", serve), ("bivariate", bivariate), ("packed", packed),
-                         ("bluestein", bluestein_bench)):
+                         ("bluestein", bluestein_bench), ("fpd", fpd_bench)):
             print(f"bench: {name}", file=sys.stderr, flush=True)
             r = fn(sub)
             for k in ("n_gpus", "higher_is_better", "scaling", "vs_baseline", "dtype", "data"):
@@ -705,6 +709,54 @@ def packed(a):
                        "multiplications_per_ciphertext": 30 + 3, "rotations_per_ciphertext": 3},
             "tournament": {"ms_per_call": t_ms, "window": 2, "ciphertexts": G,
                            "min_pairs_per_s": G * M / (t_ms / 1e3)}}
+
+
+def fpd_bench(a):
+    """uint16 values as two coordinates of the F_{257^256} slots of a
+    ciphertext at N = 2^15 (128 values per ciphertext): both F_p digits
+    extracted by the mod-extract step (monomial product, eight Frobenius
+    doublings, the scalar 1/d) for a batch of ciphertexts, checked against the
+    plaintext coordinates."""
+    import numpy as np
+    import torch
+
+    import paper_2407_07308_amd as bc
+    import synth
+
+    torch.cuda.set_device(0)
+    prm = dict(logN=15, p=257, nQ=14, bitsQ=50, nP=5, bitsP=50, dnum=3)
+    dev = bc.Context(**prm)
+    d, steps_f = dev.fpd_info()
+    rnd = synth.keygen_randomness(SEED + 7, dev.N, prm["nQ"], prm["nP"], prm["dnum"], len(steps_f))
+    keys = dev.keygen(rnd["s"], rnd["a"], rnd["e"], steps_f)
+    dev.autotune()
+    G, M, p = a.fpd_cts, dev.M, prm["p"]
+    xs = synth.integers(SEED + 8, (G, M), 0, 65536)
+    E = np.zeros((G, M, d), dtype=np.uint32)
+    E[:, :, 1], E[:, :, 0] = xs // p, xs % p
+    X = dev.encrypt_poly(keys, dev.encode_fpd(E), *synth.encrypt_randomness(SEED + 9, G, dev.N).values())
+    out = dev.extract_digits(keys, X, [1, 0])  # warm-up
+    steps = max(1, min(a.steps, 3))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dev.extract_digits(keys, X, [1, 0], out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    planes = out.split(2)
+    if not (np.array_equal(dev.decrypt(keys, planes[0]), E[:, :, 1]) and
+            np.array_equal(dev.decrypt(keys, planes[1]), E[:, :, 0])):
+        print("bench: extracted digits are wrong", file=sys.stderr)
+        sys.exit(3)
+    return {"metric": "F_{p^d} digit extractions/s", "value": 2 * G / (ms / 1e3), "unit": "digit planes/s",
+            "n_gpus": 1, "steps": steps, "ms_per_step": ms, "higher_is_better": True, "dtype": "u64",
+            "data": "synthetic", "values_per_s": G * M / (ms / 1e3),
+            "config": {"workload": f"uint16 as coordinates 1 and 0 of the F_257^{d} slots, {G} ciphertexts x {M} "
+                                   f"values, both digits extracted (x^-k product, {len(steps_f)} Frobenius "
+                                   f"doublings, scalar 1/d), BGV N=2^15 p=257 Q=14x50b P=5x50b dnum=3",
+                       "rotations_per_call": 2 * G * len(steps_f)}}
 
 
 def bluestein_bench(a):

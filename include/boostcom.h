@@ -137,8 +137,9 @@ int bc_keygen_rand_sizes(const bc_ctx *ctx, int32_t nrot, size_t *n_words, size_
  * Produces pk = (-a s + p e, a), and switching keys
  * ksk_j = (-a_j s + p e_j + P g_j s', a_j) over Q_L * P with g_j = 1 mod the
  * primes of digit j and 0 mod all others; s' = s^2 (relinearisation) or
- * s(x^g) with g = 5^r mod 2N for each rotation step r in [1, M/2)
- * (g = 2N - 1 for BC_ROW_SWAP; BC_ERR_ARG for other steps).  The secret stays
+ * s(x^g) with g = 5^r mod 2N for each rotation step r in [1, N/2) (steps
+ * from M/2 on leave the slot rows in place and act inside the F_{p^d} slots,
+ * see bc_fpd_info; g = 2N - 1 for BC_ROW_SWAP; BC_ERR_ARG for other steps).  The secret stays
  * inside the key object (decryption needs it).  *out is owned by the caller
  * until bc_keys_destroy.  Synchronous. */
 int bc_keygen(bc_ctx *ctx, const int8_t *s, const uint64_t *a_words, const int32_t *errors,
@@ -232,8 +233,9 @@ int bc_mul_relin_noalloc(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *a, cons
                          void *stream);
 /* Rotation (paper, "Word-wise Universal FHE Scheme": rotation among the
  * homomorphic operations; the ciphertext shifting of ShiftMul/ShiftAdd) of
- * each slot row left by `steps` (or BC_ROW_SWAP): automorphism x -> x^g then
- * key switch with the matching rotation key; level unchanged.  BC_ERR_KEY
+ * each slot row left by `steps` mod M/2 (or BC_ROW_SWAP): automorphism
+ * x -> x^g, g = 5^steps mod 2N, then key switch with the matching rotation
+ * key; level unchanged.  BC_ERR_KEY
  * when no rotation key was generated for `steps`. */
 int bc_rotate(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, int32_t steps, bc_ctb *out, void *stream);
 /* Slot-wise addition and subtraction ("Word-wise Universal FHE Scheme";
@@ -340,6 +342,48 @@ int bc_tournament(bc_ctx *ctx, const bc_keys *keys, int32_t circuit, int32_t win
                   const bc_ctb *in, bc_ctb *out, void *stream);
 /* Level of bc_tournament's output for an input at in_level (fresh noise). */
 int bc_tournament_levels(const bc_ctx *ctx, int32_t circuit, int32_t in_level, int32_t window, int32_t *out_level);
+
+/* ------------------------------------------------ F_{p^d} slots */
+
+/* Integers as elements of F_{p^d} (paper, Background, "Word-wise Universal
+ * FHE Scheme": an integer is decomposed into l slots of F_{p^d}, and each
+ * slot's element split into F_p digits by the mod-extract step before the
+ * per-digit LT/EQ).  Over F_p, x^N + 1 is the product of the M factors
+ * x^d - zeta_j (d = N/M, zeta_j the slot roots of bc_decrypt's encoding), each
+ * irreducible because d is the order of p modulo 2N: slot j holds an element
+ * of F_p[x]/(x^d - zeta_j), a field of p^d elements, written here in the power
+ * basis 1, x, ..., x^(d-1).  The slot values of bc_encrypt are the constants.
+ * The Frobenius powers x -> x^(p^(2^b)), b < log2(d), are automorphisms
+ * x -> x^(5^r) with steps r in [M/2, N/2) (p = 1 mod 4 lies in <5>): their
+ * rotation keys serve the extraction.
+ * bc_fpd_info: *degree = d, *nsteps = log2(d), steps[0 .. log2 d) the
+ * rotation steps r_b with 5^(r_b) = p^(2^b) mod 2N (cap: the array's length;
+ * BC_ERR_ARG when it is too small; any pointer may be NULL).  BC_ERR_PARAM
+ * when p is not a power of 5 modulo 2N. */
+int bc_fpd_info(const bc_ctx *ctx, int32_t *degree, int32_t *nsteps, int32_t *steps, int32_t cap);
+/* Host-side encoding: elems[count][M][d] (coordinates mod p) -> plaintext
+ * coefficients coeffs[count][N] = sum_k x^k mu_k(x^d), mu_k the slot encoding
+ * of coordinate k; bc_decode_fpd is its inverse (each slot's element is the
+ * plaintext reduced modulo x^d - zeta_j).  Synchronous, no device work. */
+int bc_encode_fpd(const bc_ctx *ctx, const uint32_t *elems, int32_t count, uint32_t *coeffs);
+int bc_decode_fpd(const bc_ctx *ctx, const uint32_t *coeffs, int32_t count, uint32_t *elems);
+/* Encryption of plaintext polynomials coeffs[count][N] (values taken mod p)
+ * with the randomness of bc_encrypt; otherwise as bc_encrypt. */
+int bc_encrypt_poly(bc_ctx *ctx, const bc_keys *keys, const uint32_t *coeffs, const int8_t *u,
+                    const int32_t *errors, bc_ctb *out, void *stream);
+/* The mod-extract step: for each of the ndigits coordinates k = digits[i]
+ * (0 <= k < d), out holds, as ciphertexts i * in->count .. (i + 1) *
+ * in->count - 1 (digit-major, at in->level, 2 components), encryptions whose
+ * slot j decrypts to coordinate k of slot j's element of the input.  Computed
+ * as d^-1 Tr(x^-k c): the monomial product (no noise growth), then log2(d)
+ * doublings z <- z + rot(z, r_b) over the Frobenius steps (the trace over
+ * the Frobenius group, which keeps the constants and removes every other
+ * power of x below d), then the scalar d^-1 mod p.  out must not overlap in;
+ * rotation keys for every step of bc_fpd_info (BC_ERR_KEY); BC_ERR_ARG for a
+ * digit out of range or a wrong output shape; BC_ERR_LEVEL when the estimated
+ * noise exceeds the input level's budget.  Runs on `stream`. */
+int bc_extract_digits(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, const int32_t *digits, int32_t ndigits,
+                      bc_ctb *out, void *stream);
 
 /* ------------------------------------------- non-power-of-two rings */
 

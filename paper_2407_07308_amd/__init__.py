@@ -111,6 +111,11 @@ _SIGS = {
     "bc_profile_read": (_I, [_V, _I, _P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_double)]),
     "bc_noise_estimate": (_I, [_P(bc_params), _I, _I, ctypes.c_double, ctypes.c_double, _P(ctypes.c_double)]),
     "bc_noise_compare": (_I, [_P(bc_params), _I, ctypes.c_double, _I, _P(ctypes.c_double), _P(ctypes.c_double)]),
+    "bc_fpd_info": (_I, [_V, _P(_I), _P(_I), _P(_I), _I]),
+    "bc_encode_fpd": (_I, [_V, _V, _I, _V]),
+    "bc_decode_fpd": (_I, [_V, _V, _I, _V]),
+    "bc_encrypt_poly": (_I, [_V, _V, _V, _V, _V, _P(bc_ctb), _V]),
+    "bc_extract_digits": (_I, [_V, _V, _P(bc_ctb), _V, _I, _P(bc_ctb), _V]),
     "bc_bluestein_create": (_I, [_I, _I, _I, _P(_V)]),
     "bc_bluestein_destroy": (_I, [_V]),
     "bc_bluestein_info": (_I, [_V, _P(_I), _P(_I), _P(ctypes.c_uint64)]),
@@ -181,6 +186,14 @@ class Batch:
         """Adopts the level, components and noise estimate a call wrote to ``c``."""
         self.level, self.ncomp, self.noise = c.level, c.ncomp, float(c.noise_bits)
         return self
+
+    def split(self, parts: int) -> list["Batch"]:
+        """``parts`` batches of count / parts ciphertexts each, viewing
+        consecutive ranges of this one (no copy)."""
+        assert self.count % parts == 0
+        n = self.count // parts
+        w = self.tensor.numel() // parts
+        return [Batch(self.tensor[i * w:(i + 1) * w], n, self.level, self.ncomp, self.noise) for i in range(parts)]
 
 
 def _ctb_array(batches):
@@ -422,6 +435,50 @@ class Context:
         cx, co = x.ctb(), out.ctb()
         _check(self.L.bc_tournament(self.handle, keys.handle, circuit, window, 1 if want_max else 0,
                                     ctypes.byref(cx), ctypes.byref(co), _stream()))
+        return out.take(co)
+
+    # ------------------------------------------------ F_{p^d} slots
+    def fpd_info(self):
+        """(d, Frobenius rotation steps) of ``bc_fpd_info``."""
+        d, n = ctypes.c_int32(), ctypes.c_int32()
+        steps = (ctypes.c_int32 * 32)()
+        _check(self.L.bc_fpd_info(self.handle, ctypes.byref(d), ctypes.byref(n), steps, 32))
+        return d.value, list(steps[: n.value])
+
+    def encode_fpd(self, elems) -> np.ndarray:
+        """elems[count][M][d] -> plaintext coefficients [count][N] (``bc_encode_fpd``)."""
+        d = self.N // self.M
+        elems = np.ascontiguousarray(elems, dtype=np.uint32).reshape(-1, self.M, d)
+        out = np.zeros((elems.shape[0], self.N), dtype=np.uint32)
+        _check(self.L.bc_encode_fpd(self.handle, _np_ptr(elems), elems.shape[0], _np_ptr(out)))
+        return out
+
+    def decode_fpd(self, coeffs) -> np.ndarray:
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint32).reshape(-1, self.N)
+        out = np.zeros((coeffs.shape[0], self.M, self.N // self.M), dtype=np.uint32)
+        _check(self.L.bc_decode_fpd(self.handle, _np_ptr(coeffs), coeffs.shape[0], _np_ptr(out)))
+        return out
+
+    def encrypt_poly(self, keys: Keys, coeffs, u, errors, out: Batch | None = None) -> Batch:
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint32).reshape(-1, self.N)
+        count = coeffs.shape[0]
+        u = np.ascontiguousarray(u, dtype=np.int8).reshape(count, self.N)
+        e = np.ascontiguousarray(errors, dtype=np.int32).reshape(count, 2, self.N)
+        out = out or self.new_batch(count, self.nQ - 1, 2)
+        c = out.ctb()
+        _check(self.L.bc_encrypt_poly(self.handle, keys.handle, _np_ptr(coeffs), _np_ptr(u), _np_ptr(e),
+                                      ctypes.byref(c), _stream()))
+        return out.take(c)
+
+    def extract_digits(self, keys: Keys, x: Batch, digits, out: Batch = None) -> Batch:
+        """Coordinates ``digits`` of every F_{p^d} slot as F_p slot values
+        (``bc_extract_digits``): digit-major, len(digits) * x.count ciphertexts."""
+        dg = np.ascontiguousarray(digits, dtype=np.int32).reshape(-1)
+        if out is None:
+            out = self.new_batch(x.count * len(dg), x.level, 2)
+        cx, co = x.ctb(), out.ctb()
+        _check(self.L.bc_extract_digits(self.handle, keys.handle, ctypes.byref(cx), _np_ptr(dg), len(dg),
+                                        ctypes.byref(co), _stream()))
         return out.take(co)
 
     def set_exec_mode(self, mode: int):

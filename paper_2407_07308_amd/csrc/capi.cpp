@@ -1002,6 +1002,69 @@ int bc_tournament(bc_ctx *ctx, const bc_keys *keys, int32_t circuit, int32_t win
     });
 }
 
+int bc_fpd_info(const bc_ctx *ctx, int32_t *degree, int32_t *nsteps, int32_t *steps, int32_t cap) {
+    return guard([&] {
+        check_ctx(ctx);
+        const std::vector<int> st = frobenius_steps(ctx);
+        if (degree) *degree = ctx->N / ctx->M;
+        if (nsteps) *nsteps = (int32_t)st.size();
+        if (steps) {
+            BC_REQUIRE(cap >= (int32_t)st.size(), BC_ERR_ARG, "steps array too small");
+            for (size_t i = 0; i < st.size(); i++) steps[i] = st[i];
+        }
+    });
+}
+
+int bc_encode_fpd(const bc_ctx *ctx, const uint32_t *elems, int32_t count, uint32_t *coeffs) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(elems && coeffs && count >= 1, BC_ERR_ARG, "encode: null buffer or empty batch");
+        encode_fpd(ctx, elems, count, coeffs);
+    });
+}
+
+int bc_decode_fpd(const bc_ctx *ctx, const uint32_t *coeffs, int32_t count, uint32_t *elems) {
+    return guard([&] {
+        check_ctx(ctx);
+        BC_REQUIRE(elems && coeffs && count >= 1, BC_ERR_ARG, "decode: null buffer or empty batch");
+        decode_fpd(ctx, coeffs, count, elems);
+    });
+}
+
+int bc_encrypt_poly(bc_ctx *ctx, const bc_keys *keys, const uint32_t *coeffs, const int8_t *u, const int32_t *errors,
+                    bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(out && out->data && out->count >= 1, BC_ERR_ARG, "bad output batch");
+        out->level = ctx->nQ - 1;
+        out->ncomp = 2;
+        StreamScope sc(stream);
+        encrypt_poly(ctx, keys, coeffs, u, errors, from_abi(ctx, out), (hipStream_t)stream);
+        out->noise_bits = (float)ctx->noise.fresh();
+    });
+}
+
+int bc_extract_digits(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, const int32_t *digits, int32_t ndigits,
+                      bc_ctb *out, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        BC_REQUIRE(in && out, BC_ERR_ARG, "null batch");
+        const CtB x = from_abi(ctx, in), o = from_abi(ctx, out);
+        // each doubling adds a rotated copy: the noise doubles and gains the key switch
+        double nb = x.noise;
+        for (size_t i = 0; i < frobenius_steps(ctx).size(); i++) nb = ctx->noise.add(nb, ctx->noise.rotate(x.level, nb));
+        const int64_t dinv = centred(ctx, (int64_t)h_invmod((u64)((ctx->N / ctx->M) % ctx->p), (u64)ctx->p));
+        nb = ctx->noise.scalar(nb, (double)std::llabs(dinv));
+        ctx->noise.require(x.level, nb, "digit extraction");
+        StreamScope sc(stream);
+        std::vector<int> dg(digits ? digits : nullptr, digits ? digits + std::max(ndigits, 0) : nullptr);
+        extract_digits(ctx, keys, x, dg.data(), (int)dg.size(), o, (hipStream_t)stream);
+        out->noise_bits = (float)nb;
+    });
+}
+
 int bc_bluestein_create(int32_t m, int32_t nprimes, int32_t bits, bc_bluestein **out) {
     return guard([&] {
         BC_REQUIRE(out, BC_ERR_ARG, "null output");

@@ -627,6 +627,38 @@ CtB tournament(bc_ctx *c, const bc_keys *k, const CtB &X, int window, bool want_
     return tournament_rounds(ev, X, X.count, window, want_max, circuit, c->p, d.biv, d.ctop);
 }
 
+// The mod-extract step (Background, "Word-wise Universal FHE Scheme"): digit
+// k of a slot's F_{p^d} element is d^-1 Tr(x^-k m), the trace summing the d
+// Frobenius images; it runs as log2(d) doublings z <- z + sigma(z), every
+// digit and ciphertext of the batch in each launch.
+void extract_digits(bc_ctx *c, const bc_keys *k, const CtB &in, const int *digits, int ndig, const CtB &out,
+                    hipStream_t st) {
+    const int N = c->N, d = N / c->M, nl = in.level + 1;
+    BC_REQUIRE(in.ncomp == 2 && in.count >= 1, BC_ERR_ARG, "extraction input: 2 components");
+    BC_REQUIRE(digits && ndig >= 1, BC_ERR_ARG, "no digits to extract");
+    BC_REQUIRE(out.ncomp == 2 && out.level == in.level && out.count == in.count * ndig, BC_ERR_ARG,
+               "extraction output: ndigits x count ciphertexts at the input's level");
+    BC_REQUIRE(out.data != in.data, BC_ERR_ARG, "extraction cannot run in place");
+    for (int j = 0; j < ndig; j++)
+        BC_REQUIRE(digits[j] >= 0 && digits[j] < d, BC_ERR_ARG, "digit index beyond the slot degree N/M");
+    const std::vector<int> steps = frobenius_steps(c);
+    for (int r : steps) {
+        bool have = false;
+        for (int i = 0; i < k->ngal; i++) have = have || k->steps[i] == r;
+        BC_REQUIRE(have, BC_ERR_KEY, "no rotation key for a Frobenius step");
+    }
+    const size_t W = in.ct_words(N);
+    for (int j = 0; j < ndig; j++)  // x^-k = x^(2N - k)
+        launch_mul_monomial(c, in.data, out.data + (size_t)j * in.count * W, in.count, nl, 2,
+                            (2 * N - digits[j]) % (2 * N), st);
+    CtB tmp = alloc_ct(c, out.count, out.level, 2);
+    for (int r : steps) {
+        rotate(c, k, out, r, tmp, st);
+        add_sub(c, out, tmp, out, false, st);
+    }
+    mul_scalar(c, out, (int64_t)h_invmod((u64)(d % c->p), (u64)c->p), out, st);
+}
+
 void packed_levels(const NoiseModel &m, int in_level, double in_noise, int l, int circuit, int *lv, double *nb) {
     NoiseEval ev{&m};
     const NoiseEval::V in{in_level, in_noise};

@@ -26,6 +26,8 @@ void launch_addsub(const bc_ctx *c, const u64 *a, const u64 *b, u64 *out, int co
                    int nb, int ncomp, bool sub, hipStream_t st);
 void launch_mul_scalar(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st);
 void launch_add_const(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st);
+// out = a x^e (0 <= e < 2N) on count batches of nl limbs x ncomp components (NTT domain; in place allowed)
+void launch_mul_monomial(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int e, hipStream_t st);
 void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, int count, int nl, int ncomp,
                     hipStream_t st);
 // `pl`: the first pl forward stages of the transforms that follow are applied

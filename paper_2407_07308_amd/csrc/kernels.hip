@@ -45,6 +45,11 @@ __global__ void k_add_const(const u64 *__restrict__ a, u64 *__restrict__ out, in
     b_add_const(hw_blk(), a, out, nl, ncomp, s, pinfo, N);
 }
 
+__global__ void k_mul_monomial(const u64 *__restrict__ a, u64 *__restrict__ out, int nl, int ncomp, int e,
+                               const u64 *__restrict__ tw, const PrimeInfo *__restrict__ pinfo, int N, int logN) {
+    b_mul_monomial(hw_blk(), a, out, nl, ncomp, e, tw, pinfo, N, logN);
+}
+
 __global__ void k_permute(const u64 *__restrict__ in, u64 *__restrict__ out, const u32 *__restrict__ perm, int nl,
                           int ncomp, int N) {
     b_permute(hw_blk(), in, out, perm, nl, ncomp, N);
@@ -302,6 +307,11 @@ void launch_add_const(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl
         return;
     }
     k_add_const<<<grid3(c->N, nl, count), kT, 0, st>>>(a, out, nl, ncomp, scalar_arg(c, v, nl), c->pinfo, c->N);
+}
+void launch_mul_monomial(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int e, hipStream_t st) {
+    BC_REQUIRE(e >= 0 && e < 2 * c->N, BC_ERR_ARG, "monomial exponent out of range");
+    BC_REQUIRE(!tl_rec, BC_ERR_ARG, "the persistent executor does not run monomial products");
+    k_mul_monomial<<<grid3(c->N, nl, count), kT, 0, st>>>(a, out, nl, ncomp, e, c->tw, c->pinfo, c->N, c->logN);
 }
 void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, int count, int nl, int ncomp,
                     hipStream_t st) {

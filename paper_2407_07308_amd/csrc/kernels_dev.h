@@ -87,6 +87,27 @@ __device__ __forceinline__ void b_mul_scalar(const VBlk &VB, const u64 *__restri
     }
 }
 
+// multiplication by the monomial x^e, 0 <= e < 2N: position r of a limb holds
+// the evaluation at psi^(2 brv(r) + 1), where x^e is psi^(e (2 brv(r) + 1));
+// psi^x for x < N is the table word W[brv(x)], and psi^(x + N) = -psi^x
+__device__ __forceinline__ void b_mul_monomial(const VBlk &VB, const u64 *__restrict__ a, u64 *__restrict__ out, int nl,
+                                               int ncomp, int e, const u64 *__restrict__ tw,
+                                               const PrimeInfo *__restrict__ pinfo, int N, int logN) {
+    const int n = VB.x * kT + threadIdx.x, i = VB.y, ct = VB.z;
+    const size_t L = (size_t)nl * N;
+    const u32 ev = 2u * (__brev((u32)n) >> (32 - logN)) + 1u;
+    const u32 x = (u32)(((u64)e * ev) & (2u * (u64)N - 1));
+    const bool neg = x >= (u32)N;
+    const u32 r = __brev(neg ? x - (u32)N : x) >> (32 - logN);
+    const u64 *W = tw + (size_t)i * 4 * N;
+    const u64 w = W[r], wp = W[N + r], q = pinfo[i].q;
+    for (int c = 0; c < ncomp; c++) {
+        const size_t off = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N + n;
+        const u64 v = shoup(a[off], w, wp, q);
+        out[off] = neg && v ? q - v : v;
+    }
+}
+
 // constant polynomial c: every evaluation of component 0 gains c mod q_i
 __device__ __forceinline__ void b_add_const(const VBlk &VB, const u64 *__restrict__ a, u64 *__restrict__ out, int nl, int ncomp, const ScalarArg &s,
                             const PrimeInfo *__restrict__ pinfo, int N) {

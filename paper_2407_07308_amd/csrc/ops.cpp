@@ -591,6 +591,75 @@ void decode_slots(const bc_ctx *c, const u32 *coeffs, u32 *slots, int count) {
         }
 }
 
+// F_{p^d} slots: slot j holds sum_k E[j][k] x^k in F_p[x]/(x^d - zeta_j), d = N/M;
+// the plaintext is sum_k x^k mu_k(x^d), mu_k the slot encoding of column k
+void encode_fpd(const bc_ctx *c, const u32 *elems, int count, u32 *m) {
+    const u64 p = c->p;
+    const int M = c->M, N = c->N, d = N / M;
+    auto pts = slot_points(c);
+    std::vector<u64> inv_pts(M);
+    for (int j = 0; j < M; j++) inv_pts[j] = h_invmod(pts[j], p);
+    const u64 minv = h_invmod((u64)M, p);
+    std::memset(m, 0, sizeof(u32) * (size_t)count * N);
+    std::vector<u64> col(M), pw(M);
+    for (int ct = 0; ct < count; ct++)
+        for (int k = 0; k < d; k++) {
+            bool any = false;
+            for (int j = 0; j < M; j++) {
+                col[j] = elems[((size_t)ct * M + j) * d + k] % p;
+                any = any || col[j];
+            }
+            if (!any) continue;
+            for (int j = 0; j < M; j++) pw[j] = 1;
+            for (int i = 0; i < M; i++) {
+                u64 acc = 0;
+                for (int j = 0; j < M; j++) {
+                    acc = (acc + col[j] * pw[j]) % p;
+                    pw[j] = pw[j] * inv_pts[j] % p;
+                }
+                m[(size_t)ct * N + (size_t)i * d + k] = (u32)(acc * minv % p);
+            }
+        }
+}
+
+// slot j's element: m mod (x^d - zeta_j), with x^(d i + k) = zeta_j^i x^k
+void decode_fpd(const bc_ctx *c, const u32 *m, int count, u32 *elems) {
+    const u64 p = c->p;
+    const int M = c->M, N = c->N, d = N / M;
+    auto pts = slot_points(c);
+    std::vector<u64> acc(d);
+    for (int ct = 0; ct < count; ct++)
+        for (int j = 0; j < M; j++) {
+            std::fill(acc.begin(), acc.end(), 0);
+            u64 zi = 1;
+            for (int i = 0; i < M; i++) {
+                const u32 *row = m + (size_t)ct * N + (size_t)i * d;
+                for (int k = 0; k < d; k++) acc[k] = (acc[k] + (row[k] % p) * zi) % p;
+                zi = zi * pts[j] % p;
+            }
+            for (int k = 0; k < d; k++) elems[((size_t)ct * M + j) * d + k] = (u32)acc[k];
+        }
+}
+
+// rotation steps r_b with 5^(r_b) = p^(2^b) mod 2N, b < log2(d): the Frobenius
+// powers x -> x^(p^(2^b)) of the F_{p^d} slots (p = 1 mod 4 lies in <5>)
+std::vector<int> frobenius_steps(const bc_ctx *c) {
+    const u64 twoN = 2 * (u64)c->N;
+    std::vector<int> log5(twoN, -1);
+    u64 x = 1;
+    for (int r = 0; r < c->N / 2; r++) {
+        log5[x] = r;
+        x = x * 5 % twoN;
+    }
+    std::vector<int> steps;
+    for (int b = 0; (1 << b) < c->N / c->M; b++) {
+        const int r = log5[h_powmod((u64)c->p % twoN, (u64)1 << b, twoN)];
+        BC_REQUIRE(r >= 1, BC_ERR_PARAM, "p is not a power of 5 modulo 2N");
+        steps.push_back(r);
+    }
+    return steps;
+}
+
 // ---------------------------------------------------------- client side
 
 namespace {
@@ -621,7 +690,7 @@ bc_keys *keygen(bc_ctx *c, const int8_t *s, const u64 *words, const int32_t *err
     BC_REQUIRE(nrot >= 0 && (nrot == 0 || steps), BC_ERR_ARG, "keygen: rotation steps");
     const int N = c->N, nQ = c->nQ, nm = c->nmod, dnum = c->dnum;
     for (int r = 0; r < nrot; r++)
-        BC_REQUIRE(steps[r] == BC_ROW_SWAP || (steps[r] >= 1 && steps[r] < c->M / 2), BC_ERR_ARG,
+        BC_REQUIRE(steps[r] == BC_ROW_SWAP || (steps[r] >= 1 && steps[r] < c->N / 2), BC_ERR_ARG,
                    "rotation step out of range");
     hipStream_t st = nullptr;
     static std::atomic<uint64_t> next_uid{1};
@@ -804,7 +873,7 @@ bc_keys *keys_import(bc_ctx *c, const void *buf, size_t size) {
     std::memcpy(steps.data(), in, sizeof(int32_t) * h.nrot);
     in += sizeof(int32_t) * h.nrot;
     for (int r = 0; r < h.nrot; r++)
-        BC_REQUIRE(steps[r] == BC_ROW_SWAP || (steps[r] >= 1 && steps[r] < c->M / 2), BC_ERR_ARG,
+        BC_REQUIRE(steps[r] == BC_ROW_SWAP || (steps[r] >= 1 && steps[r] < c->N / 2), BC_ERR_ARG,
                    "key import: rotation step out of range");
     const int8_t *sh = (const int8_t *)in;
     for (int n = 0; n < N; n++) BC_REQUIRE(sh[n] >= -1 && sh[n] <= 1, BC_ERR_ARG, "key import: secret not ternary");
@@ -854,10 +923,18 @@ bc_keys *keys_import(bc_ctx *c, const void *buf, size_t size) {
 void encrypt(bc_ctx *c, const bc_keys *k, const u32 *slots, const int8_t *u, const int32_t *err, const CtB &out,
              hipStream_t st) {
     BC_REQUIRE(slots && u && err, BC_ERR_ARG, "encrypt: null input");
+    std::vector<u32> m((size_t)out.count * c->N);
+    encode(c, slots, out.count, m.data());
+    encrypt_poly(c, k, m.data(), u, err, out, st);
+}
+
+void encrypt_poly(bc_ctx *c, const bc_keys *k, const u32 *coeffs, const int8_t *u, const int32_t *err, const CtB &out,
+                  hipStream_t st) {
+    BC_REQUIRE(coeffs && u && err, BC_ERR_ARG, "encrypt: null input");
     const int N = c->N, nQ = c->nQ, count = out.count;
     BC_REQUIRE(out.level == nQ - 1 && out.ncomp == 2, BC_ERR_ARG, "encrypt: output must be at the top level");
     std::vector<u32> m((size_t)count * N);
-    encode(c, slots, count, m.data());
+    for (size_t i = 0; i < m.size(); i++) m[i] = (u32)(coeffs[i] % (u64)c->p);
     BufP dm = upload_tmp(c, m.data(), m.size(), st);
     BufP du = upload_tmp(c, u, (size_t)count * N, st);
     BufP de = upload_tmp(c, err, (size_t)count * 2 * N, st);

@@ -95,6 +95,19 @@ void encrypt(bc_ctx *c, const bc_keys *k, const u32 *slots, const int8_t *u, con
              hipStream_t st);
 void decrypt_poly(bc_ctx *c, const bc_keys *k, const CtB &in, u32 *coeffs, hipStream_t st);
 void decode_slots(const bc_ctx *c, const u32 *coeffs, u32 *slots, int count);
+// the plaintext polynomial itself (coefficients taken mod p)
+void encrypt_poly(bc_ctx *c, const bc_keys *k, const u32 *coeffs, const int8_t *u, const int32_t *err, const CtB &out,
+                  hipStream_t st);
+// F_{p^d} slots in the power basis: elems[count][M][d] <-> coeffs[count][N]
+void encode_fpd(const bc_ctx *c, const u32 *elems, int count, u32 *m);
+void decode_fpd(const bc_ctx *c, const u32 *m, int count, u32 *elems);
+// rotation steps of the Frobenius powers p^(2^b), b < log2(N/M)
+std::vector<int> frobenius_steps(const bc_ctx *c);
+// digit k of every slot's F_{p^d} element as F_p slot values: out holds
+// ndig * in.count ciphertexts, digit-major, at in.level; rotation keys for
+// every Frobenius step
+void extract_digits(bc_ctx *c, const bc_keys *k, const CtB &in, const int *digits, int ndig, const CtB &out,
+                    hipStream_t st);
 void import_ct(bc_ctx *c, const u64 *host, const CtB &out, hipStream_t st);
 void export_ct(bc_ctx *c, const CtB &in, u64 *host, hipStream_t st);
 u64 galois_for_step(const bc_ctx *c, int step);

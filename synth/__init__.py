@@ -37,6 +37,7 @@ _PURPOSES = {
     "ints": 9,
     "schedule": 10,
     "poly": 11,
+    "fpd": 12,
 }
 
 
