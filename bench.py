@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--biv-groups", type=int, default=4, help="bivariate: groups of 128 uint16 pairs")
     ap.add_argument("--no-mfma", action="store_true",
                     help="bivariate: the scalar combinations on the fp64 vector units instead of the matrix cores")
+    ap.add_argument("--mfma-modup", type=int, default=None, choices=[0, 1],
+                    help="uint16: modulus raising on the matrix cores (1) or the fp64 vector units (0); "
+                         "default: the library's")
     ap.add_argument("--packed-cts", type=int, default=64,
                     help="packed: ciphertexts per batch (32 uint16 integers each)")
     ap.add_argument("--fpd-cts", type=int, default=32,
@@ -124,6 +127,9 @@ def main():
     tuned["split_streams"] = a.split
     dev.set_tuning(bc.BC_TUNE_PERSISTENT, a.persistent)
     tuned["persistent"] = a.persistent
+    if a.mfma_modup is not None:
+        dev.set_tuning(bc.BC_TUNE_MFMA_MODUP, a.mfma_modup)
+    tuned["mfma_modup"] = dev.get_tuning(bc.BC_TUNE_MFMA_MODUP)
     if a.ntt_chunk_mb is not None:
         dev.set_tuning(bc.BC_TUNE_NTT_CHUNK_BYTES, int(a.ntt_chunk_mb * 2**20))
         dev.set_tuning(bc.BC_TUNE_NTT_SINGLE_PASS, 0)

@@ -529,7 +529,16 @@ int bc_set_exec_mode(bc_ctx *ctx, int32_t mode);
  *   |x| <= q/2, instead of canonical words in [0, q): one reduction instead
  *   of the canonical form and its integer conversion at every hand-off.
  *   0 keeps canonical words everywhere.  Both give the same bytes; the
- *   caller's batches always hold canonical words. */
+ *   caller's batches always hold canonical words.
+ *   BC_TUNE_MFMA_MODUP (default 0): modulus raising (the fast base
+ *   conversion of each digit, with the forward transform's first stages the
+ *   part-limb schedule folds into it) as an exact split-int8 contraction on
+ *   the matrix cores: input residues as bytes, the constants times the fold
+ *   matrix as signed base-256 digits, int32 sums recombined in fp64.  Same
+ *   bytes as the fp64 kernel.  BC_ERR_ARG unless the context has fp64
+ *   arithmetic, every prime above 2^33 and alpha 2^parts <= 32 (a context
+ *   whose transform schedule changes afterwards runs the fp64 kernel where
+ *   no table fits). */
 enum {
     BC_TUNE_NTT_CHUNK_BYTES = 0,
     BC_TUNE_NTT_SINGLE_PASS = 1,
@@ -540,7 +549,8 @@ enum {
     BC_TUNE_TEST_FAIL_ALLOC = 6,
     BC_TUNE_PERSISTENT = 7,
     BC_TUNE_MFMA = 8,
-    BC_TUNE_RAW_HANDOFF = 9
+    BC_TUNE_RAW_HANDOFF = 9,
+    BC_TUNE_MFMA_MODUP = 10
 };
 int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value);
 int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);

@@ -31,6 +31,7 @@ BC_TUNE_TEST_FAIL_ALLOC = 6
 BC_TUNE_PERSISTENT = 7
 BC_TUNE_MFMA = 8
 BC_TUNE_RAW_HANDOFF = 9
+BC_TUNE_MFMA_MODUP = 10
 BC_NOISE_FRESH, BC_NOISE_BUDGET, BC_NOISE_ADD, BC_NOISE_TENSOR, BC_NOISE_MUL, BC_NOISE_MOD_SWITCH, BC_NOISE_ROTATE = range(7)
 
 

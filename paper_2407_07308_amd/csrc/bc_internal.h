@@ -332,6 +332,16 @@ struct ModUpPlan {
     u64 qhat[kMaxMod][kMaxMod][2];  // [t][i]: Qhat_i mod q_t, Shoup
 };
 
+// Split-int8 matrix-core form of modulus raising with PL folded forward
+// stages: per plan (level x digit) a block of plan_stride bytes of tiles of
+// 32 rows x kpad signed digits, and per (plan, target, output word) the fp64
+// correction of the byte shift (see b_modup_mfma).
+struct ModUpMfma {
+    int8_t *w8 = nullptr;
+    double *corr = nullptr;
+    int kpad = 0, plan_stride = 0;
+};
+
 // Exact division by P (modulus lowering); independent of the level.
 struct ModDownPlan {
     u64 vfac[kMaxMod][2];           // [p^-1 Phat_j^-1]_{p_j}
@@ -553,6 +563,8 @@ struct bc_ctx {
     int biv_K = 0, biv_M = 0;
     bool biv_mfma = false;  // the table has the matrix-core copy
     int mfma = 1;           // BC_TUNE_MFMA: use the matrix-core kernels where they apply
+    int mfma_modup = 0;     // BC_TUNE_MFMA_MODUP: modulus raising on the matrix cores
+    bc::ModUpMfma modup_mfma[3];  // its weight tables, per number of folded stages
     int raw_handoff = 1;    // BC_TUNE_RAW_HANDOFF: key-switching intermediates as reduced fp64 patterns
     // owners: the caller's handle, every live key set and every group that
     // lists the context; the last release deletes it (a key set destroyed

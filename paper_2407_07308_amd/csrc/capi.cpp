@@ -1201,6 +1201,10 @@ int bc_set_tuning(bc_ctx *ctx, int32_t key, int64_t value) {
             ctx->mfma = value != 0;
         } else if (key == BC_TUNE_RAW_HANDOFF) {
             ctx->raw_handoff = value != 0;
+        } else if (key == BC_TUNE_MFMA_MODUP) {
+            BC_REQUIRE(value == 0 || ctx->modup_mfma[ntt_parts_log(ctx)].w8, BC_ERR_ARG,
+                       "modulus raising on the matrix cores needs fp64 primes above 2^33 and alpha 2^parts <= 32");
+            ctx->mfma_modup = value != 0;
         } else if (key == BC_TUNE_PERSISTENT) {
             BC_REQUIRE(value == 0 || persist_supported(ctx), BC_ERR_ARG,
                        "persistent mode needs N = 2^13..2^15, primes below 2^50 and the default transform schedule");
@@ -1223,6 +1227,7 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value) {
         else if (key == BC_TUNE_PERSISTENT) *value = ctx->persistent;
         else if (key == BC_TUNE_MFMA) *value = ctx->mfma;
         else if (key == BC_TUNE_RAW_HANDOFF) *value = ctx->raw_handoff;
+        else if (key == BC_TUNE_MFMA_MODUP) *value = ctx->mfma_modup;
         else throw Error(BC_ERR_ARG, "unknown tuning key");
     });
 }

@@ -117,6 +117,75 @@ void set_shoup(u64 dst[2], u64 w, u64 q) {
 
 void set_fpair(u64 dst[2], u64 w, u64 q) { h_fpair(dst, w, q); }
 
+// Tables of the matrix-core modulus raising (b_modup_mfma): for PL folded
+// forward stages (NV = 2^PL words per base position), plan (level, digit),
+// target t and output word v, the row block of M[t][v][s][v'] 2^(8a) mod p_t
+// as seven signed base-256 digits, K = (s NV + v') 8 + a, and the correction
+// 128 sum_K W mod p_t.  Built when every digit fits the kernel (alpha NV <= 32)
+// and every prime exceeds 2^33 (2^32 is its own residue in the recombination).
+void build_modup_mfma(bc_ctx *c) {
+    const int nm = c->nmod, nplans = (int)c->h_modup.size();
+    for (int m = 0; m < nm; m++)
+        if (c->mod[m] <= ((u64)1 << 33)) return;
+    for (int PL = 0; PL <= 2; PL++) {
+        const int NV = 1 << PL, TPT = 4 / NV;
+        if (c->alpha * NV > 32 || (c->N >> PL) % 128) continue;
+        const int kpad = 32 * ((c->alpha * NV * 8 + 31) / 32);
+        const int tiles = (nm + TPT - 1) / TPT, stride = tiles * 32 * kpad;
+        std::vector<int8_t> w((size_t)nplans * stride, 0);
+        std::vector<double> corr((size_t)nplans * nm * 4, 0.0);
+        for (int pi = 0; pi < nplans; pi++) {
+            const ModUpPlan &pl = c->h_modup[pi];
+            for (int t = 0; t < pl.ntgt; t++) {
+                const int pm = pl.tgt_prime[t];
+                const u64 q = c->mod[pm];
+                const u64 w1 = c->h_pinfo[pm].w123[0][0], w2 = c->h_pinfo[pm].w123[1][0],
+                          w3 = c->h_pinfo[pm].w123[2][0];
+                // the fold's matrix: out[v] = sum_v' F[v][v'] in[v'] (the forward stages of fold_fp)
+                u64 F[4][4] = {{1}};
+                if (PL == 1) {
+                    F[0][0] = 1, F[0][1] = w1, F[1][0] = 1, F[1][1] = q - w1;
+                } else if (PL == 2) {
+                    const u64 w21 = h_mulmod(w2, w1, q), w31 = h_mulmod(w3, w1, q);
+                    const u64 rows[4][4] = {{1, w2, w1, w21},
+                                            {1, q - w2, w1, (q - w21) % q},
+                                            {1, w3, q - w1, (q - w31) % q},
+                                            {1, q - w3, q - w1, w31}};
+                    std::memcpy(F, rows, sizeof(F));
+                }
+                for (int v = 0; v < NV; v++) {
+                    const int unit = (t % TPT) * NV + v, h = unit / 2;
+                    int8_t *blk = &w[(size_t)pi * stride + (size_t)(t / TPT) * 32 * kpad];
+                    u64 csum = 0;
+                    for (int sidx = 0; sidx < pl.nsrc; sidx++)
+                        for (int v2 = 0; v2 < NV; v2++) {
+                            u64 W = h_mulmod(F[v][v2], pl.qhat[t][sidx][0], q);
+                            for (int a = 0; a < 7; a++, W = h_mulmod(W, 256, q)) {
+                                csum = (csum + W) % q;
+                                int64_t x = (int64_t)W;
+                                const int K = (sidx * NV + v2) * 8 + a;
+                                for (int b = 0; b < 7; b++) {
+                                    int64_t d = x & 255;
+                                    if (d >= 128) d -= 256;
+                                    x = (x - d) / 256;
+                                    const int r = 8 * (unit % 2) + b, row = 8 * (r / 4) + 4 * h + r % 4;
+                                    blk[(size_t)row * kpad + K] = (int8_t)d;
+                                }
+                                BC_REQUIRE(x == 0, BC_ERR_PARAM, "modulus raising weight beyond seven digits");
+                            }
+                        }
+                    corr[((size_t)pi * nm + t) * 4 + v] = (double)h_mulmod(csum, 128, q);
+                }
+            }
+        }
+        ModUpMfma &T = c->modup_mfma[PL];
+        T.w8 = upload(w.data(), w.size());
+        T.corr = upload(corr.data(), corr.size());
+        T.kpad = kpad;
+        T.plan_stride = stride;
+    }
+}
+
 typedef void (*PairSet)(u64 dst[2], u64 w, u64 q);
 
 // Base-conversion and modulus-switching constants, each stored as a pair by
@@ -509,6 +578,7 @@ void build_context_moduli(bc_ctx *c, const bc_params &prm, std::vector<u64> mod)
             c->modup_f = upload(mu.data(), mu.size());
             c->moddown_f = upload(md.get(), 1);
             c->modsw_f = upload(ms.data(), nQ);
+            build_modup_mfma(c);
         }
     }
 
@@ -553,6 +623,10 @@ bc_ctx::~bc_ctx() {
     dfree(modup_f);
     dfree(moddown_f);
     dfree(modsw_f);
+    for (auto &T : modup_mfma) {
+        dfree(T.w8);
+        dfree(T.corr);
+    }
     dfree(garner);
     for (auto &kv : ps_coef) dfree(kv.second);
 }

@@ -252,6 +252,18 @@ __global__ void __launch_bounds__(256) k_lincomb_wide_mfma(const u64 *__restrict
     b_lincomb_wide_mfma(hw_blk(), in, out, W8, c0, corr, M, K, count, nl, pinfo, N, lds);
 }
 
+template <int PL, bool RAW, int STEPS>
+__global__ void __launch_bounds__(kMfmaThreads) k_modup_mfma(const u64 *__restrict__ xc, u64 *__restrict__ mu,
+                                                             const ModUpPlan *__restrict__ plans,
+                                                             const int8_t *__restrict__ w8,
+                                                             const double *__restrict__ corr, int plan_stride,
+                                                             int plan0, const PrimeInfo *__restrict__ pinfo, int nl,
+                                                             int next, int dnum, int nmod, int N) {
+    __shared__ __align__(16) unsigned char lds[kMfmaPos * (32 * STEPS + 16)];
+    b_modup_mfma<PL, RAW, STEPS>(hw_blk(), xc, mu, plans, w8, corr, plan_stride, plan0, pinfo, nl, next, dnum, nmod, N,
+                                 lds);
+}
+
 inline dim3 grid3(int N, int y, int z) { return dim3((unsigned)(N / kT), (unsigned)y, (unsigned)z); }
 
 }  // namespace
@@ -317,6 +329,35 @@ void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, i
                     hipStream_t st) {
     k_permute<<<grid3(c->N, nl, count), kT, 0, st>>>(in, out, perm, nl, ncomp, c->N);
 }
+template <int PL, bool RAW, int STEPS>
+static void modup_mfma_k(const bc_ctx *c, const ModUpMfma &T, const u64 *xc, u64 *mu, const ModUpPlan *plans, int count,
+                         int level, int next, hipStream_t st) {
+    const dim3 g((unsigned)((c->N >> PL) / kMfmaPos), 1, (unsigned)(count * c->dnum));
+    k_modup_mfma<PL, RAW, STEPS><<<g, kMfmaThreads, 0, st>>>(xc, mu, plans, T.w8, T.corr, T.plan_stride,
+                                                              level * c->dnum, c->pinfo, level + 1, next, c->dnum,
+                                                              c->nmod, c->N);
+}
+template <int PL, bool RAW>
+static void modup_mfma_r(const bc_ctx *c, const ModUpMfma &T, const u64 *xc, u64 *mu, const ModUpPlan *plans,
+                         int count, int level, int next, hipStream_t st) {
+    switch (T.kpad / 32) {
+        case 1: return modup_mfma_k<PL, RAW, 1>(c, T, xc, mu, plans, count, level, next, st);
+        case 2: return modup_mfma_k<PL, RAW, 2>(c, T, xc, mu, plans, count, level, next, st);
+        case 3: return modup_mfma_k<PL, RAW, 3>(c, T, xc, mu, plans, count, level, next, st);
+        case 4: return modup_mfma_k<PL, RAW, 4>(c, T, xc, mu, plans, count, level, next, st);
+        case 5: return modup_mfma_k<PL, RAW, 5>(c, T, xc, mu, plans, count, level, next, st);
+        case 6: return modup_mfma_k<PL, RAW, 6>(c, T, xc, mu, plans, count, level, next, st);
+        case 7: return modup_mfma_k<PL, RAW, 7>(c, T, xc, mu, plans, count, level, next, st);
+        case 8: return modup_mfma_k<PL, RAW, 8>(c, T, xc, mu, plans, count, level, next, st);
+        default: throw Error(BC_ERR_ARG, "modulus raising on the matrix cores: digit too wide");
+    }
+}
+template <int PL>
+static void launch_modup_mfma(const bc_ctx *c, const ModUpMfma &T, const u64 *xc, u64 *mu, const ModUpPlan *plans,
+                              int count, int level, int next, bool raw, hipStream_t st) {
+    if (raw) modup_mfma_r<PL, true>(c, T, xc, mu, plans, count, level, next, st);
+    else modup_mfma_r<PL, false>(c, T, xc, mu, plans, count, level, next, st);
+}
 template <bool FP, int PL, int MD>
 static void modup_pl(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int level, int next, bool raw,
                      hipStream_t st) {
@@ -329,6 +370,13 @@ static void modup_pl(const bc_ctx *c, const u64 *xc, u64 *mu, int count, int lev
         return;
     }
     const ModUpPlan *plans = (FP ? c->modup_f : c->modup) + (size_t)level * c->dnum;
+    if constexpr (FP) {
+        const ModUpMfma &T = c->modup_mfma[PL];
+        if (c->mfma_modup && T.w8) {
+            launch_modup_mfma<PL>(c, T, xc, mu, plans, count, level, next, raw, st);
+            return;
+        }
+    }
     const dim3 g = grid3(c->N >> PL, 1, count * c->dnum);
     if (FP && raw) k_modup<FP, PL, MD, FP><<<g, kT, 0, st>>>(xc, mu, plans, c->pinfo, level + 1, next, c->dnum, c->N);
     else k_modup<FP, PL, MD><<<g, kT, 0, st>>>(xc, mu, plans, c->pinfo, level + 1, next, c->dnum, c->N);

@@ -837,6 +837,116 @@ __device__ __forceinline__ void b_lincomb_wide_mfma(const VBlk &VB, const u64 *_
     }
 }
 
+// Modulus raising on the matrix cores (fp64 contexts).  For one digit, the
+// output word v of target t at base position n (a word of the first PL
+// forward stages, like b_modup's fold) is sum over sources s and input words
+// v' of y[s][v'](n) * M[t][v][s][v'] mod p_t, M the base-conversion constant
+// Qhat_s mod p_t times the fold matrix of the PL stages.  Exact split-int8
+// form: y < 2^50 is taken as its bytes y_a (a < 7) shifted to signed
+// y_a - 128; the host folds 2^(8a) into the constant and writes each product
+// W = M 2^(8a) mod p_t as seven signed base-256 digits w_b (rows (t, v, b),
+// columns K = (s, v', a)); v_mfma_i32_32x32x32_i8 sums the byte products
+// exactly in int32 (|sum| < 140 * 2^14), and the lane holding the eight rows b
+// of a word recombines them in fp64: lo = sum_{b<4} acc_b 2^(8b) (< 2^47),
+// hi = sum_{b>=4} acc_b 2^(8(b-4)) (< 2^39), result lo + hi (2^32 mod p_t) +
+// C[t][v], C = 128 sum_K W restoring the byte shift.  A block takes 128 base
+// positions: phase one writes their input bytes to LDS (row = position, K
+// contiguous, STEPS x 32 bytes), phase two gives each of its two waves 64
+// positions (two B operands, two independent product chains) and runs every
+// target tile of the digit, the next tile's weights loading under the
+// current tile's products; the 32 rows of a tile are four words (t, v) x
+// eight b, placed so that a lane's sixteen accumulators hold two whole words
+// (the 32x32 output layout: register r of lane half h is row
+// 8 (r/4) + 4 h + r%4).
+constexpr int kMfmaPos = 128;
+constexpr int kMfmaThreads = 128;  // two waves, 64 positions (two column tiles) each
+template <int PL, bool RAW, int STEPS>
+__device__ __forceinline__ void b_modup_mfma(const VBlk &VB, const u64 *__restrict__ xc, u64 *__restrict__ mu,
+                                             const ModUpPlan *__restrict__ plans, const int8_t *__restrict__ w8,
+                                             const double *__restrict__ corr, int plan_stride, int plan0,
+                                             const PrimeInfo *__restrict__ pinfo, int nl, int next, int dnum,
+                                             int nmod, int N, unsigned char *__restrict__ lds) {
+#pragma clang fp contract(off)
+    constexpr int NV = 1 << PL, TPT = 4 / NV, KPAD = 32 * STEPS, KSTRIDE = KPAD + 16;
+    const int Q = N >> PL;
+    const int ct = VB.z / dnum, j = VB.z - ct * dnum;
+    const ModUpPlan &pl = plans[j];
+    if (pl.nsrc == 0) return;
+    const int n0 = VB.x * kMfmaPos, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const u64 *in = xc + (size_t)ct * nl * N + n0;
+#pragma unroll 1
+    for (int u = tid; u < kMfmaPos * pl.nsrc; u += kMfmaThreads) {
+        const int nn = u & (kMfmaPos - 1), s = u / kMfmaPos;
+        const PrimeInfo &pi = pinfo[pl.src_lo + s];
+        double x[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const u64 w = in[(size_t)(pl.src_lo + s) * N + v * Q + nn];
+            x[v] = RAW ? f_raw_load(w) : f_load(w);
+        }
+        if constexpr (PL > 0) unfold_fp<PL, false>(x, pi);
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const double y = f_canon(f_mulmod(x[v], fpair(pl.qhinv[s]), pi.qd), pi.qd, pi.qinv);
+            // y + 2^52 carries y in its mantissa; the mask drops the exponent
+            // and flips the top bit of every byte (b -> b - 128 as int8)
+            const u64 bytes = (u64)__double_as_longlong(y + 0x1p52) ^ 0xC3B0808080808080ull;
+            *reinterpret_cast<u64 *>(lds + (size_t)nn * KSTRIDE + (s * NV + v) * 8) = bytes;
+        }
+    }
+    __syncthreads();
+    const int row_l = lane & 31, half = lane >> 5;
+    v4i_t b0[STEPS], b1[STEPS];
+#pragma unroll
+    for (int st = 0; st < STEPS; st++) {
+        b0[st] = *reinterpret_cast<const v4i_t *>(lds + (size_t)(wave * 64 + row_l) * KSTRIDE + st * 32 + half * 16);
+        b1[st] = *reinterpret_cast<const v4i_t *>(lds + (size_t)(wave * 64 + 32 + row_l) * KSTRIDE + st * 32 + half * 16);
+    }
+    const int8_t *wp = w8 + (size_t)(plan0 + j) * plan_stride + (size_t)row_l * KPAD + half * 16;
+    u64 *out = mu + ((size_t)ct * dnum + j) * next * N + n0 + wave * 64 + row_l;
+    const int ntiles = (pl.ntgt + TPT - 1) / TPT;
+    v4i_t a_cur[STEPS], a_nxt[STEPS];
+#pragma unroll
+    for (int st = 0; st < STEPS; st++) a_cur[st] = *reinterpret_cast<const v4i_t *>(wp + st * 32);
+#pragma unroll 1
+    for (int tile = 0; tile < ntiles; tile++) {
+        if (tile + 1 < ntiles) {  // the next tile's weights load under this tile's products
+#pragma unroll
+            for (int st = 0; st < STEPS; st++)
+                a_nxt[st] = *reinterpret_cast<const v4i_t *>(wp + (size_t)(tile + 1) * 32 * KPAD + st * 32);
+        }
+        v16i_t acc[2] = {{0}, {0}};
+#pragma unroll
+        for (int st = 0; st < STEPS; st++) {
+            acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_cur[st], b0[st], acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_cur[st], b1[st], acc[1], 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int unit = 2 * half + k, t = tile * TPT + unit / NV, v = unit % NV;
+            if (t >= pl.ntgt) continue;
+            const PrimeInfo &pt = pinfo[pl.tgt_prime[t]];
+            const double q = pt.qd, u = pt.qinv, c = corr[((size_t)(plan0 + j) * nmod + t) * 4 + v];
+            const FPair c32{0x1p32, 0x1p32 * u};
+            u64 *o = out + (size_t)pl.tgt_e[t] * N + v * Q;
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const v16i_t &A = acc[h];
+                const double lo = __builtin_fma(
+                    (double)A[8 * k + 3], 0x1p24,
+                    __builtin_fma((double)A[8 * k + 2], 0x1p16, __builtin_fma((double)A[8 * k + 1], 0x1p8, (double)A[8 * k])));
+                const double hi = __builtin_fma((double)A[8 * k + 6], 0x1p16,
+                                                __builtin_fma((double)A[8 * k + 5], 0x1p8, (double)A[8 * k + 4]));
+                double r = (lo + c) + f_mulmod(hi, c32, q);
+                r = RAW ? f_reduce(r, q, u) : f_canon(r, q, u);
+                o[32 * h] = RAW ? f_raw_bits(r) : f_bits(r);
+            }
+        }
+#pragma unroll
+        for (int st = 0; st < STEPS; st++) a_cur[st] = a_nxt[st];
+    }
+}
+
 }  // namespace
 
 }  // namespace bc

@@ -20,16 +20,18 @@ from oracle import Oracle, Params
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [  # (fp64, single pass, chunk bytes, part-limb transforms, fp64 hand-off)
-    (1, 1, 0, 1, 1), (1, 1, 0, 1, 0), (1, 1, 0, 0, 1), (1, 0, 0, 1, 1), (1, 0, 1 << 20, 1, 1),
-    (0, 1, 0, 1, 1), (0, 1, 0, 0, 1), (0, 0, 0, 1, 1), (0, 0, 1 << 20, 1, 1)]
+SCHEDULES = [  # (fp64, single pass, chunk bytes, part-limb transforms, fp64 hand-off, modulus raising on MFMA)
+    (1, 1, 0, 1, 1, 0), (1, 1, 0, 1, 0, 0), (1, 1, 0, 0, 1, 0), (1, 0, 0, 1, 1, 0), (1, 0, 1 << 20, 1, 1, 0),
+    (1, 1, 0, 1, 1, 1), (1, 1, 0, 1, 0, 1), (1, 1, 0, 0, 1, 1), (1, 0, 0, 1, 1, 1),
+    (0, 1, 0, 1, 1, 0), (0, 1, 0, 0, 1, 0), (0, 0, 0, 1, 1, 0), (0, 0, 1 << 20, 1, 1, 0)]
 
 
 def run_all(dev, dk, slots, r):
     import paper_2407_07308_amd as bc
 
     outs = []
-    for fp, single, chunk, parts, raw in SCHEDULES:
+    for fp, single, chunk, parts, raw, mfma in SCHEDULES:
+        dev.set_tuning(bc.BC_TUNE_MFMA_MODUP, 0)
         dev.set_tuning(bc.BC_TUNE_RAW_HANDOFF, raw)
         dev.set_tuning(bc.BC_TUNE_FP64, fp)
         dev.set_tuning(bc.BC_TUNE_NTT_SINGLE_PASS, single)
@@ -39,6 +41,7 @@ def run_all(dev, dk, slots, r):
         logN = dev.N.bit_length() - 1
         folded = logN - 13 if (single and parts and logN >= 14) else 0
         assert dev.get_tuning(bc.BC_TUNE_NTT_PARTS) == folded
+        dev.set_tuning(bc.BC_TUNE_MFMA_MODUP, mfma)
         ct = dev.encrypt(dk, slots, r["u"], r["e"])
         prod = dev.mul_relin(dk, ct, ct)
         ms = dev.mod_switch(ct)
@@ -60,6 +63,7 @@ def test_fp64_and_integer_transforms_agree(logN):
     slots = synth.slot_values(32, count, dev.M, 0, prm.p)
     r = synth.encrypt_randomness(33, count, prm.N)
     outs = run_all(dev, dk, slots, r)
+    dev.set_tuning(bc.BC_TUNE_MFMA_MODUP, 0)
     dev.set_tuning(bc.BC_TUNE_RAW_HANDOFF, 1)
     want = (slots.astype(np.int64) ** 2 % prm.p).astype(np.uint32)
     for i, (ct, prod, dec, ms) in enumerate(outs):
