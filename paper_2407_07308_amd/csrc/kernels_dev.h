@@ -636,41 +636,48 @@ __device__ __forceinline__ void b_lincomb(const VBlk &VB, const BabyArg &ba, con
             u64 v[16];
 #pragma unroll
             for (int k = 0; k < 16; k++) {
-                if (k >= nbaby) break;
-                const size_t Lk = (size_t)ba.nlb[k] * N;
-                v[k] = ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n];
+                if (k < nbaby) {
+                    const size_t Lk = (size_t)ba.nlb[k] * N;
+                    v[k] = ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n];
+                }
             }
             for (int t = 0; t < nblk; t++) {
                 u64 acc = 0;
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
-                    if (k >= nbaby) break;
-                    const u64 *w = coef + (((size_t)t * nbaby + k) * nl + i) * 2;
-                    acc = add_mod(acc, shoup(v[k], w[0], w[1], q), q);
+                    if (k < nbaby) {
+                        const u64 *w = coef + (((size_t)t * nbaby + k) * nl + i) * 2;
+                        acc = add_mod(acc, shoup(v[k], w[0], w[1], q), q);
+                    }
                 }
                 out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] = acc;
             }
         } else {
 #pragma clang fp contract(off)
             const double *cf = reinterpret_cast<const double *>(coef);
+            // fully unrolled with uniform guards (a break on the runtime count
+            // would leave the loops rolled and index the register arrays
+            // through the index mode)
             double hi[16], lo[16];
 #pragma unroll
             for (int k = 0; k < 16; k++) {
-                if (k >= nbaby) break;
-                const size_t Lk = (size_t)ba.nlb[k] * N;
-                const double v = f_load(ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n]);
-                hi[k] = __builtin_floor(v * 0x1p-25);
-                lo[k] = __builtin_fma(-hi[k], 0x1p25, v);
+                if (k < nbaby) {
+                    const size_t Lk = (size_t)ba.nlb[k] * N;
+                    const double v = f_load(ba.baby[k][(size_t)ct * 2 * Lk + (size_t)c * Lk + (size_t)i * N + n]);
+                    hi[k] = __builtin_floor(v * 0x1p-25);
+                    lo[k] = __builtin_fma(-hi[k], 0x1p25, v);
+                }
             }
             const FPair p25 = fpair(pi.two25_f);
             for (int t = 0; t < nblk; t++) {
                 double sh = 0.0, sl = 0.0;
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
-                    if (k >= nbaby) break;
-                    const double w = cf[t * nbaby + k];
-                    sh = __builtin_fma(w, hi[k], sh);
-                    sl = __builtin_fma(w, lo[k], sl);
+                    if (k < nbaby) {
+                        const double w = cf[t * nbaby + k];
+                        sh = __builtin_fma(w, hi[k], sh);
+                        sl = __builtin_fma(w, lo[k], sl);
+                    }
                 }
                 out[((size_t)ba.pos[t] * count + ct0 + ct) * 2 * L + (size_t)c * L + (size_t)i * N + n] =
                     f_bits(f_canon(f_mulmod(sh, p25, pi.qd) + sl, pi.qd, pi.qinv));
