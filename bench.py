@@ -120,7 +120,8 @@ def main():
     N, M = dev.N, dev.M
     rnd = synth.keygen_randomness(SEED, N, prm["nQ"], prm["nP"], prm["dnum"], 0)
     keys = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
-    tuned = dev.autotune()
+    dev.autotune()
+    tuned = dev.autotune_mul(keys)
     # the groups run as SPLIT concurrent slices on library streams (two timed
     # fastest: 1, 2 and 4 slices gave 165, 159-160 and 164-166 ms a step)
     dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, a.split)

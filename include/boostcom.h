@@ -561,6 +561,19 @@ int bc_get_tuning(const bc_ctx *ctx, int32_t key, int64_t *value);
  * context's shape (about 384 MB of limbs) and keeps the fastest.
  * Synchronises the stream; takes a few tens of milliseconds. */
 int bc_autotune(bc_ctx *ctx, void *stream);
+/* Autotuner of the whole multiplication (tensor, relinearisation and
+ * modulus switch, the operation every step of the circuits repeats): times
+ * bc_mul_relin at the top level on a synthetic batch of this context's shape
+ * (about 512 MB of ciphertexts, at most 64) under each combination of fp64 or
+ * integer arithmetic, transform schedule (single-pass, two-pass, two-pass in
+ * 128 MB chunks), part-limb key-switching transforms, the reduced fp64
+ * hand-off and modulus raising on the matrix cores (BC_TUNE_FP64,
+ * BC_TUNE_NTT_SINGLE_PASS, BC_TUNE_NTT_CHUNK_BYTES, BC_TUNE_NTT_PARTS,
+ * BC_TUNE_RAW_HANDOFF, BC_TUNE_MFMA_MODUP, where the context allows each) and
+ * keeps the fastest; every combination gives the same bytes.  Needs the
+ * relinearisation key of `keys`.  Synchronises the stream; takes about a
+ * second at N = 2^15. */
+int bc_autotune_mul(bc_ctx *ctx, const bc_keys *keys, void *stream);
 
 /* ------------------------------------------------------------ profiling */
 /* Per-kernel timing of the key-switching path (the paper measures its own

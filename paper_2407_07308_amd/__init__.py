@@ -107,6 +107,7 @@ _SIGS = {
     "bc_group_get_mode": (_I, [_V, _P(_I), _P(_I), _P(_I), _P(_I)]),
     "bc_set_tuning": (_I, [_V, _I, ctypes.c_int64]),
     "bc_autotune": (_I, [_V, _V]),
+    "bc_autotune_mul": (_I, [_V, _V, _V]),
     "bc_get_tuning": (_I, [_V, _I, _P(ctypes.c_int64)]),
     "bc_profile_enable": (_I, [_V, _I]),
     "bc_profile_read": (_I, [_V, _I, _P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_double)]),
@@ -495,6 +496,17 @@ class Context:
                 "chunk_bytes": self.get_tuning(BC_TUNE_NTT_CHUNK_BYTES),
                 "fp64": self.get_tuning(BC_TUNE_FP64),
                 "parts_log": self.get_tuning(BC_TUNE_NTT_PARTS)}
+
+    def autotune_mul(self, keys: Keys) -> dict:
+        """Picks the fastest arithmetic, transform schedule and key-switching
+        forms for a whole multiplication (``bc_autotune_mul``); returns them."""
+        _check(self.L.bc_autotune_mul(self.handle, keys.handle, _stream()))
+        return {"single_pass": self.get_tuning(BC_TUNE_NTT_SINGLE_PASS),
+                "chunk_bytes": self.get_tuning(BC_TUNE_NTT_CHUNK_BYTES),
+                "fp64": self.get_tuning(BC_TUNE_FP64),
+                "parts_log": self.get_tuning(BC_TUNE_NTT_PARTS),
+                "raw_handoff": self.get_tuning(BC_TUNE_RAW_HANDOFF),
+                "mfma_modup": self.get_tuning(BC_TUNE_MFMA_MODUP)}
 
     def get_tuning(self, key: int) -> int:
         v = ctypes.c_int64()

@@ -1299,6 +1299,83 @@ int bc_autotune(bc_ctx *ctx, void *stream) {
     });
 }
 
+int bc_autotune_mul(bc_ctx *ctx, const bc_keys *keys, void *stream) {
+    return guard([&] {
+        check_ctx(ctx);
+        check_keys(ctx, keys);
+        StreamScope sc(stream);
+        hipStream_t st = (hipStream_t)stream;
+        const int lv = ctx->nQ - 1;
+        const size_t ctb = (size_t)2 * (lv + 1) * ctx->N * sizeof(u64);
+        const int count = (int)std::min<size_t>(64, std::max<size_t>(2, ((size_t)512 << 20) / ctb));
+        CtB a = alloc_ct(ctx, count, lv, 2);
+        BC_HIP(hipMemsetAsync(a.data, 0, ctb * count, st));  // the kernels' time does not depend on the values
+        CtB out = alloc_ct(ctx, count, out_level_mul(lv, lv), 2);
+        struct Cand {
+            int fp, single;
+            size_t chunk;
+            int parts, raw, mfma;
+        };
+        const bool pass1 = ctx->logN >= 12 && ctx->logN <= 15;
+        std::vector<Cand> cands;
+        for (int fp : {1, 0}) {
+            if (fp && !ctx->twf) continue;
+            for (int single : {1, 0})
+                for (size_t chunk : {(size_t)0, (size_t)128 << 20}) {
+                    if (single && (!pass1 || chunk)) continue;  // chunking applies to the two-pass schedule
+                    for (int parts : {1, 0}) {
+                        if (parts && !single) continue;
+                        for (int raw : {1, 0}) {
+                            if (raw && !(fp && parts)) continue;
+                            for (int mfma : {0, 1}) {
+                                if (mfma && !fp) continue;
+                                cands.push_back({fp, single, chunk, parts, raw, mfma});
+                            }
+                        }
+                    }
+                }
+        }
+        const bool prof = ctx->prof->on;
+        ctx->prof->on = false;
+        const Cand keep{ctx->fp64, ctx->ntt_single_pass, ctx->ntt_chunk_bytes, ctx->ntt_parts, ctx->raw_handoff,
+                        ctx->mfma_modup};
+        hipEvent_t e0, e1;
+        BC_HIP(hipEventCreate(&e0));
+        BC_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        Cand pick = keep;
+        for (const Cand &cd : cands) {
+            ctx->fp64 = cd.fp;
+            ctx->ntt_single_pass = cd.single;
+            ctx->ntt_chunk_bytes = cd.chunk;
+            ctx->ntt_parts = cd.parts;
+            ctx->raw_handoff = cd.raw;
+            if (cd.mfma && !ctx->modup_mfma[ntt_parts_log(ctx)].w8) continue;
+            ctx->mfma_modup = cd.mfma;
+            mul_relin(ctx, keys, a, a, out, st);
+            BC_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 3; r++) mul_relin(ctx, keys, a, a, out, st);
+            BC_HIP(hipEventRecord(e1, st));
+            BC_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            BC_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                pick = cd;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->fp64 = pick.fp;
+        ctx->ntt_single_pass = pick.single;
+        ctx->ntt_chunk_bytes = pick.chunk;
+        ctx->ntt_parts = pick.parts;
+        ctx->raw_handoff = pick.raw;
+        ctx->mfma_modup = pick.mfma;
+        ctx->prof->on = prof;
+    });
+}
+
 int bc_profile_enable(bc_ctx *ctx, int32_t on) {
     return guard([&] {
         check_ctx(ctx);

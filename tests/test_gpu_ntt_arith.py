@@ -87,3 +87,25 @@ def test_integer_only_context_reports_no_fp64():
 
     dev = bc.Context.from_params(Params(12, 257, 4, 50, 1, 60, 4))
     assert dev.get_tuning(bc.BC_TUNE_FP64) == 0
+
+
+def test_autotune_mul_keeps_the_bytes():
+    """The multiplication autotuner times every schedule and form the context
+    allows and keeps one; the products are the same bytes before and after."""
+    import paper_2407_07308_amd as bc
+
+    prm = Params(14, 257, 4, 50, 2, 50, 2)
+    print("\n[ntt arith] autotune_mul at N=2^14", flush=True)
+    dev = bc.Context.from_params(prm)
+    rnd = synth.keygen_randomness(34, prm.N, prm.nQ, prm.nP, prm.dnum, 0)
+    dk = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
+    slots = synth.slot_values(35, 2, dev.M, 0, prm.p)
+    r = synth.encrypt_randomness(36, 2, prm.N)
+    ct = dev.encrypt(dk, slots, r["u"], r["e"])
+    before = dev.export(dev.mul_relin(dk, ct, ct))
+    tuned = dev.autotune_mul(dk)
+    assert set(tuned) == {"single_pass", "chunk_bytes", "fp64", "parts_log", "raw_handoff", "mfma_modup"}
+    assert tuned["fp64"] in (0, 1) and tuned["parts_log"] in (0, 1)
+    assert not tuned["raw_handoff"] or (tuned["fp64"] and tuned["parts_log"])
+    assert np.array_equal(dev.export(dev.mul_relin(dk, ct, ct)), before)
+    print("[ntt arith] tuned", tuned, flush=True)
