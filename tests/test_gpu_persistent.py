@@ -190,6 +190,15 @@ def test_context_comparison_as_one_persistent_launch():
                     x.tensor.zero_()
                 torch.cuda.synchronize()
                 dev.compare_max_min(dk, A, B, outs=got)
+            # the last call's outputs, then one more call, whose set-up reports
+            # whether the last launch stalled; its own outputs checked after it
+            torch.cuda.synchronize()
+            last_ok = [same(dev, x, y) for x, y in zip([got[0]] + got[1] + got[2], [ref[0]] + ref[1] + ref[2])]
+            dev.compare_max_min(dk, A, B, outs=got)
+            assert all(last_ok), (split, mode, "last", last_ok)
             dev.set_tuning(bc.BC_TUNE_PERSISTENT, 0)
             dev.set_exec_mode(bc.BC_EXEC_BATCHED)
+            torch.cuda.synchronize()
+            for x, y in zip([got[0]] + got[1] + got[2], [ref[0]] + ref[1] + ref[2]):
+                assert same(dev, x, y), (split, mode, "extra")
     assert np.array_equal(dev.decrypt(dk, got[0]), (xs < ys).astype(np.uint32))
