@@ -440,7 +440,9 @@ int bc_bluestein_inverse(bc_bluestein *plan, const uint64_t *in, uint64_t *out, 
  *   independent, interleaved stage by stage); every transform is cut into
  *   2^13-word blocks so that one workgroup shape runs every stage of every
  *   ring size.  A stalled wait (only a library bug can cause one) ends after
- *   2 s instead of hanging, and ends every other wait of the launch; the group's next call then returns BC_ERR_HIP.
+ *   2 s instead of hanging, and ends every other wait of the launch; the group's next call then returns BC_ERR_HIP
+ *   (for a context's own persistent comparison, BC_TUNE_PERSISTENT, so do its
+ *   next persistent call and its next bc_export, bc_decrypt or bc_decrypt_poly).
  *   BC_GROUP_FORK_JOIN (the default): members run on their own streams,
  *   forked from and joined back into `stream`, each kernel its own launch.
  * In both modes the first call for a given set of buffers runs eagerly and

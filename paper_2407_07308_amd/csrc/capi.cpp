@@ -723,6 +723,7 @@ int bc_decrypt_poly(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t
         BC_REQUIRE(coeffs, BC_ERR_ARG, "null output");
         StreamScope sc(stream);
         decrypt_poly(ctx, keys, from_abi(ctx, in), coeffs, (hipStream_t)stream);
+        report_stall(ctx);
     });
 }
 
@@ -735,15 +736,26 @@ int bc_decrypt(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t *slo
         CtB x = from_abi(ctx, in);
         std::vector<uint32_t> coeffs((size_t)x.count * ctx->N);
         decrypt_poly(ctx, keys, x, coeffs.data(), (hipStream_t)stream);
+        report_stall(ctx);
         decode_slots(ctx, coeffs.data(), slots, x.count);
     });
 }
+
+namespace {
+// After a synchronising read-back: a persistent launch of this context that
+// stalled (its results invalid) is reported here as well as by the next launch.
+void report_stall(bc_ctx *c) {
+    std::lock_guard<std::mutex> lk(c->split_mu);
+    if (c->runner) c->runner->check_stall();
+}
+}  // namespace
 
 int bc_export(bc_ctx *ctx, const bc_ctb *in, uint64_t *host, void *stream) {
     return guard([&] {
         check_ctx(ctx);
         StreamScope sc(stream);
         export_ct(ctx, from_abi(ctx, in), host, (hipStream_t)stream);
+        report_stall(ctx);
     });
 }
 
