@@ -716,6 +716,15 @@ int bc_encrypt(bc_ctx *ctx, const bc_keys *keys, const uint32_t *slots, const in
     });
 }
 
+namespace {
+// After a synchronising read-back: a persistent launch of this context that
+// stalled (its results invalid) is reported here as well as by the next launch.
+void report_stall(bc_ctx *c) {
+    std::lock_guard<std::mutex> lk(c->split_mu);
+    if (c->runner) c->runner->check_stall();
+}
+}  // namespace
+
 int bc_decrypt_poly(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t *coeffs, void *stream) {
     return guard([&] {
         check_ctx(ctx);
@@ -740,15 +749,6 @@ int bc_decrypt(bc_ctx *ctx, const bc_keys *keys, const bc_ctb *in, uint32_t *slo
         decode_slots(ctx, coeffs.data(), slots, x.count);
     });
 }
-
-namespace {
-// After a synchronising read-back: a persistent launch of this context that
-// stalled (its results invalid) is reported here as well as by the next launch.
-void report_stall(bc_ctx *c) {
-    std::lock_guard<std::mutex> lk(c->split_mu);
-    if (c->runner) c->runner->check_stall();
-}
-}  // namespace
 
 int bc_export(bc_ctx *ctx, const bc_ctb *in, uint64_t *host, void *stream) {
     return guard([&] {
