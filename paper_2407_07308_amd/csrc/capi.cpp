@@ -1351,39 +1351,45 @@ int bc_autotune_mul(bc_ctx *ctx, const bc_keys *keys, void *stream) {
         ctx->prof->on = false;
         const Cand keep{ctx->fp64, ctx->ntt_single_pass, ctx->ntt_chunk_bytes, ctx->ntt_parts, ctx->raw_handoff,
                         ctx->mfma_modup};
-        hipEvent_t e0, e1;
-        BC_HIP(hipEventCreate(&e0));
-        BC_HIP(hipEventCreate(&e1));
-        float best = 1e30f;
-        Cand pick = keep;
-        for (const Cand &cd : cands) {
+        auto apply = [&](const Cand &cd) {
             ctx->fp64 = cd.fp;
             ctx->ntt_single_pass = cd.single;
             ctx->ntt_chunk_bytes = cd.chunk;
             ctx->ntt_parts = cd.parts;
             ctx->raw_handoff = cd.raw;
-            if (cd.mfma && !ctx->modup_mfma[ntt_parts_log(ctx)].w8) continue;
             ctx->mfma_modup = cd.mfma;
-            mul_relin(ctx, keys, a, a, out, st);
-            BC_HIP(hipEventRecord(e0, st));
-            for (int r = 0; r < 3; r++) mul_relin(ctx, keys, a, a, out, st);
-            BC_HIP(hipEventRecord(e1, st));
-            BC_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            BC_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                pick = cd;
+        };
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        float best = 1e30f;
+        Cand pick = keep;
+        try {
+            BC_HIP(hipEventCreate(&e0));
+            BC_HIP(hipEventCreate(&e1));
+            for (const Cand &cd : cands) {
+                apply(cd);
+                if (cd.mfma && !ctx->modup_mfma[ntt_parts_log(ctx)].w8) continue;
+                mul_relin(ctx, keys, a, a, out, st);
+                BC_HIP(hipEventRecord(e0, st));
+                for (int r = 0; r < 3; r++) mul_relin(ctx, keys, a, a, out, st);
+                BC_HIP(hipEventRecord(e1, st));
+                BC_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                BC_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    pick = cd;
+                }
             }
+        } catch (...) {  // the context keeps the settings it came with
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            apply(keep);
+            ctx->prof->on = prof;
+            throw;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        ctx->fp64 = pick.fp;
-        ctx->ntt_single_pass = pick.single;
-        ctx->ntt_chunk_bytes = pick.chunk;
-        ctx->ntt_parts = pick.parts;
-        ctx->raw_handoff = pick.raw;
-        ctx->mfma_modup = pick.mfma;
+        apply(pick);
         ctx->prof->on = prof;
     });
 }

@@ -638,7 +638,11 @@ void extract_digits(bc_ctx *c, const bc_keys *k, const CtB &in, const int *digit
     BC_REQUIRE(digits && ndig >= 1, BC_ERR_ARG, "no digits to extract");
     BC_REQUIRE(out.ncomp == 2 && out.level == in.level && out.count == in.count * ndig, BC_ERR_ARG,
                "extraction output: ndigits x count ciphertexts at the input's level");
-    BC_REQUIRE(out.data != in.data, BC_ERR_ARG, "extraction cannot run in place");
+    {
+        const u64 *ib = in.data, *ie = ib + (size_t)in.count * in.ct_words(N);
+        const u64 *ob = out.data, *oe = ob + (size_t)out.count * out.ct_words(N);
+        BC_REQUIRE(oe <= ib || ie <= ob, BC_ERR_ARG, "extraction output overlaps its input");
+    }
     for (int j = 0; j < ndig; j++)
         BC_REQUIRE(digits[j] >= 0 && digits[j] < d, BC_ERR_ARG, "digit index beyond the slot degree N/M");
     const std::vector<int> steps = frobenius_steps(c);

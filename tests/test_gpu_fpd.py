@@ -129,6 +129,13 @@ def test_extract_errors():
     assert code(lambda: dev.extract_digits(dk, ct, [])) == bc.BC_ERR_ARG
     assert code(lambda: dev.extract_digits(dk, ct, [0], out=ct)) == bc.BC_ERR_ARG  # in place
     assert code(lambda: dev.extract_digits(dk, ct, [0, 1], out=dev.new_batch(1, ct.level, 2))) == bc.BC_ERR_ARG
+    # an output that overlaps the input in part
+    big = dev.new_batch(3, ct.level, 2)
+    big.split(3)[1].tensor.copy_(ct.tensor)
+    w = big.tensor.numel() // 3
+    src = bc.Batch(big.tensor[w:2 * w], 1, ct.level, 2, ct.noise)
+    dst = bc.Batch(big.tensor[:2 * w], 2, ct.level, 2)
+    assert code(lambda: dev.extract_digits(dk, src, [0, 1], out=dst)) == bc.BC_ERR_ARG
     # keys without the last Frobenius step
     rnd = synth.keygen_randomness(60, prm.N, prm.nQ, prm.nP, prm.dnum, len(steps) - 1)
     k2 = dev.keygen(rnd["s"], rnd["a"], rnd["e"], steps[:-1])
