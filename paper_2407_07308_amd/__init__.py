@@ -483,6 +483,18 @@ class Context:
                                         ctypes.byref(co), _stream()))
         return out.take(co)
 
+    def compare_fpd(self, keys: Keys, a: Batch, b: Batch, ndigits: int, circuit: int = BC_CIRCUIT_BIVARIATE,
+                    want_max: bool = False, want_min: bool = False):
+        """Integers packed as F_{p^d} slot elements (coordinate ndigits - 1 the
+        most significant base-p digit): both operands' digits extracted
+        (``bc_extract_digits``), then the lexicographic comparison of the
+        digit planes (``bc_compare_max_min``).  Returns (lt, [max planes],
+        [min planes]) as ``compare_max_min`` does."""
+        order = list(range(ndigits - 1, -1, -1))
+        A = self.extract_digits(keys, a, order).split(ndigits)
+        B = self.extract_digits(keys, b, order).split(ndigits)
+        return self.compare_max_min(keys, A, B, True, want_max, want_min, circuit=circuit)
+
     def set_exec_mode(self, mode: int):
         _check(self.L.bc_set_exec_mode(self.handle, mode))
 

@@ -102,6 +102,10 @@ def test_extract_full_size_and_compare():
         assert np.array_equal(dev.decrypt(dk, Y[i]), EY[:, :, k]), k
     lt = dev.compare_max_min(dk, X, Y, True, False, False, circuit=bc.BC_CIRCUIT_BIVARIATE)[0]
     assert np.array_equal(dev.decrypt(dk, lt), (xs < ys).astype(np.uint32))
+    # the same through the packed comparison helper, with the maximum
+    lt2, mx, _ = dev.compare_fpd(dk, cx, cy, 2, want_max=True)
+    assert np.array_equal(dev.export(lt2), dev.export(lt))
+    assert np.array_equal(dev.decrypt(dk, mx[0]).astype(np.int64) * p + dev.decrypt(dk, mx[1]), np.maximum(xs, ys))
     print("fpd: N=2^15 oracle sample", flush=True)
     o = Oracle(prm)
     o.keygen(rnd, rot_steps=steps)
