@@ -348,6 +348,7 @@ struct ModDownPlan {
     u64 phat[kMaxMod][kMaxMod][2];  // [i][j]: Phat_j mod q_i
     u64 pinv[kMaxMod][2];           // P^-1 mod q_i
     u64 ppinv[kMaxMod][2];          // p P^-1 mod q_i
+    u64 phatpp[kMaxMod][kMaxMod][2];  // [i][j]: Phat_j p P^-1 mod q_i (the scaled correction)
 };
 
 // Dropping q_l (modulus switching at level l).
@@ -378,7 +379,13 @@ struct GarnerTable {
 // d has level + 1 limbs per component (stride d_ct_stride per ciphertext);
 // acc is [count][2][next][N].  w[i] holds the constants mod q_i as pairs of
 // the transform's arithmetic (Shoup pairs, or (w, w/q) doubles).
-enum { kNttRelinMs = 1, kNttSwitch = 2 };
+//   kNttKsCombine: out_i = d_i w0_i + acc_i w1_i - E_i (the key switch of a
+//                 rotation: d the automorphism's component 0 and, for
+//                 component 1, `zeros`; w0 = 1, w1 = P^-1, E the
+//                 modulus-lowering correction already scaled by p P^-1);
+//                 here `level` counts the limbs of a component of E, d and
+//                 out alike.
+enum { kNttRelinMs = 1, kNttSwitch = 2, kNttKsCombine = 3 };
 struct NttCombine {
     int mode;
     const u64 *d;
@@ -387,6 +394,9 @@ struct NttCombine {
     u64 *out;
     int level, next;
     u64 w[kMaxMod][4];
+    // kNttKsCombine: N zero words, component 1's base (one load path for
+    // both components, no branch on the base in the store loop)
+    const u64 *zeros;
 };
 
 struct PersistRunner;  // persist.h
@@ -534,6 +544,7 @@ struct bc_ctx {
     bc::ModDownPlan *moddown_f = nullptr;
     bc::ModSwitchPlan *modsw_f = nullptr;
     bc::GarnerTable *garner = nullptr;
+    bc::u64 *zeros = nullptr;  // [N] zero words (the key switch's missing base)
     std::vector<bc::PrimeInfo> h_pinfo;
     std::vector<bc::ModUpPlan> h_modup;  // host copies (launch sizing)
     bc::Pool pool;

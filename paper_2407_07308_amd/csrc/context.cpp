@@ -244,7 +244,14 @@ void build_plans(const bc_ctx *c, PairSet setp, std::vector<ModUpPlan> &mu, ModD
         }
         u64 Pinv = h_invmod(P, q);
         setp(md.pinv[i], Pinv, q);
-        setp(md.ppinv[i], h_mulmod(Pinv, c->p % q, q), q);
+        const u64 ppi = h_mulmod(Pinv, c->p % q, q);
+        setp(md.ppinv[i], ppi, q);
+        for (int j = 0; j < nP; j++) {
+            u64 prod = 1;
+            for (int t = 0; t < nP; t++)
+                if (t != j) prod = h_mulmod(prod, c->mod[nQ + t] % q, q);
+            setp(md.phatpp[i][j], h_mulmod(prod, ppi, q), q);
+        }
     }
     // modulus switching, one plan per level
     ms.assign(nQ, ModSwitchPlan{});
@@ -595,6 +602,8 @@ void build_context_moduli(bc_ctx *c, const bc_params &prm, std::vector<u64> mod)
         g->qprod_p[i] = run;
     }
     c->garner = upload(g.get(), 1);
+    const std::vector<u64> zeros((size_t)c->N, 0);
+    c->zeros = upload(zeros.data(), zeros.size());
 }
 
 }  // namespace bc
@@ -628,6 +637,7 @@ bc_ctx::~bc_ctx() {
         dfree(T.corr);
     }
     dfree(garner);
+    dfree(zeros);
     for (auto &kv : ps_coef) dfree(kv.second);
 }
 

@@ -42,7 +42,9 @@ void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_s
 // pl > 0: the special limbs come from part-limb inverse transforms (their
 // last pl stages are applied here) and TH goes to part-limb forward ones
 // (their first pl stages are applied here)
-void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, int pl, hipStream_t st);
+// scaled: TH p P^-1 instead of TH (for the rotation's fused key-switch combine)
+void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, int pl, hipStream_t st,
+                    bool scaled = false);
 void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size_t base_ct_stride, const u64 *acc,
                        const u64 *th, u64 *out, size_t out_ct_stride, int count, int level, int next, hipStream_t st);
 void launch_ms_fbc(const bc_ctx *c, const u64 *top, u64 *R, int count, int level, int pl, hipStream_t st);

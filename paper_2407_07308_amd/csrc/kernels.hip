@@ -71,10 +71,10 @@ __global__ void k_ks_inner(const u64 *__restrict__ mu, const u64 *__restrict__ x
                         N);
 }
 
-template <bool FP, int PL>
+template <bool FP, int PL, bool SC = false>
 __global__ void k_moddown(const u64 *__restrict__ acc, u64 *__restrict__ th, const ModDownPlan *__restrict__ pl,
                           const PrimeInfo *__restrict__ pinfo, int level, int nQ, int nP, int next, int N) {
-    b_moddown<FP, PL>(hw_blk(), acc, th, pl, pinfo, level, nQ, nP, next, N);
+    b_moddown<FP, PL, SC>(hw_blk(), acc, th, pl, pinfo, level, nQ, nP, next, N);
 }
 
 __global__ void k_ks_combine(const u64 *__restrict__ base0, const u64 *__restrict__ base1, size_t base_ct_stride,
@@ -422,28 +422,31 @@ void launch_ks_inner(const bc_ctx *c, const u64 *mu, const u64 *x, size_t x_ct_s
                                             c->alpha, count, c->pinfo, c->N);
 }
 template <bool FP, int PL>
-static void moddown_pl(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, hipStream_t st) {
+static void moddown_pl(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, bool scaled,
+                       hipStream_t st) {
     const ModDownPlan *md = FP ? c->moddown_f : c->moddown;
     if (tl_rec) {
-        BC_REQUIRE(FP, BC_ERR_ARG, "the persistent executor needs fp64 arithmetic");
+        BC_REQUIRE(FP && !scaled, BC_ERR_ARG, "the persistent executor needs fp64 arithmetic, unscaled lowering");
         tl_rec->add(PL == 2 ? kPkModDown2 : PL == 1 ? kPkModDown1 : kPkModDown0, grid3(c->N >> PL, 1, count * 2),
                     PaModDown{acc, th, md, c->pinfo, level, c->nQ, c->nP, next, c->N});
         return;
     }
-    k_moddown<FP, PL><<<grid3(c->N >> PL, 1, count * 2), kT, 0, st>>>(acc, th, md, c->pinfo, level, c->nQ, c->nP,
-                                                                      next, c->N);
+    const dim3 g = grid3(c->N >> PL, 1, count * 2);
+    if (scaled) k_moddown<FP, PL, true><<<g, kT, 0, st>>>(acc, th, md, c->pinfo, level, c->nQ, c->nP, next, c->N);
+    else k_moddown<FP, PL><<<g, kT, 0, st>>>(acc, th, md, c->pinfo, level, c->nQ, c->nP, next, c->N);
 }
 template <bool FP>
 static void moddown_a(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, int pl,
-                      hipStream_t st) {
-    if (pl == 2) moddown_pl<FP, 2>(c, acc, th, count, level, next, st);
-    else if (pl == 1) moddown_pl<FP, 1>(c, acc, th, count, level, next, st);
-    else moddown_pl<FP, 0>(c, acc, th, count, level, next, st);
+                      bool scaled, hipStream_t st) {
+    if (pl == 2) moddown_pl<FP, 2>(c, acc, th, count, level, next, scaled, st);
+    else if (pl == 1) moddown_pl<FP, 1>(c, acc, th, count, level, next, scaled, st);
+    else moddown_pl<FP, 0>(c, acc, th, count, level, next, scaled, st);
 }
-void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, int pl, hipStream_t st) {
+void launch_moddown(const bc_ctx *c, const u64 *acc, u64 *th, int count, int level, int next, int pl, hipStream_t st,
+                    bool scaled) {
     BC_REQUIRE(pl == 0 || (c->nP <= kFoldDigit), BC_ERR_PARAM, "modulus lowering: too many special primes to fold");
-    if (use_fp64(c)) moddown_a<true>(c, acc, th, count, level, next, pl, st);
-    else moddown_a<false>(c, acc, th, count, level, next, pl, st);
+    if (use_fp64(c)) moddown_a<true>(c, acc, th, count, level, next, pl, scaled, st);
+    else moddown_a<false>(c, acc, th, count, level, next, pl, scaled, st);
 }
 void launch_ks_combine(const bc_ctx *c, const u64 *base0, const u64 *base1, size_t base_ct_stride, const u64 *acc,
                        const u64 *th, u64 *out, size_t out_ct_stride, int count, int level, int next, hipStream_t st) {

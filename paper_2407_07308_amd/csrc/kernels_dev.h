@@ -295,14 +295,16 @@ __device__ __forceinline__ void b_ks_inner(const VBlk &VB, const u64 *__restrict
 }
 
 // Exact division by P, conversion part (z-grid = ct * 2 + c):
-// v_j = [acc_{p_j} p^-1 Phat_j^-1]_{p_j};  TH_i = sum_j v_j Phat_j mod q_i.
+// v_j = [acc_{p_j} p^-1 Phat_j^-1]_{p_j};  TH_i = sum_j v_j Phat_j mod q_i
+// (SC: TH_i p P^-1, the constants Phat_j p P^-1 folded, for a consumer that
+// subtracts it unscaled).
 // With PL > 0 a thread takes the 2^PL words n + v N/2^PL of each limb: it
 // applies the last PL stages of the part-limb inverse transform of the
 // special limbs to its inputs and the first PL forward stages of TH's
 // transforms to its outputs.  FP: fp64 products with the plan's (w, w/q)
 // pairs; each product lies within 0.75 q_i of zero (v_j < 2^50), so eight sum
 // exactly before a reduction.
-template <bool FP, int PL = 0>
+template <bool FP, int PL = 0, bool SC = false>
 __device__ __forceinline__ void b_moddown(const VBlk &VB, const u64 *__restrict__ acc, u64 *__restrict__ th,
                                           const ModDownPlan *__restrict__ pl, const PrimeInfo *__restrict__ pinfo,
                                           int level, int nQ, int nP, int next, int N) {
@@ -332,7 +334,8 @@ __device__ __forceinline__ void b_moddown(const VBlk &VB, const u64 *__restrict_
 #pragma unroll
                 for (int j = 0; j < MD; j++) {
                     if (j >= nP) break;
-                    t[w] = add_mod(t[w], shoup(v[w][j], pl->phat[i][j][0], pl->phat[i][j][1], pi.q), pi.q);
+                    const u64 *w2 = SC ? pl->phatpp[i][j] : pl->phat[i][j];
+                    t[w] = add_mod(t[w], shoup(v[w][j], w2[0], w2[1], pi.q), pi.q);
                 }
             }
             if constexpr (PL > 0) fold_int<PL>(t, pi);
@@ -362,7 +365,7 @@ __device__ __forceinline__ void b_moddown(const VBlk &VB, const u64 *__restrict_
 #pragma unroll
                 for (int j = 0; j < MD; j++) {
                     if (j >= nP) break;
-                    t[w] += f_mulmod(v[w][j], fpair(pl->phat[i][j]), pi.qd);
+                    t[w] += f_mulmod(v[w][j], fpair(SC ? pl->phatpp[i][j] : pl->phat[i][j]), pi.qd);
                     if ((j & 7) == 7) t[w] = f_reduce(t[w], pi.qd, pi.qinv);
                 }
                 // the fold takes |x| < 1.6 q and returns canonical words

@@ -234,8 +234,9 @@ static bool launch_full_combine(int logN, const LimbSet &ls, const NttCombine &c
 template <class A>
 static bool launch_full_combine_a(int logN, const LimbSet &ls, const NttCombine &cb, const bc_ctx *c,
                                   hipStream_t st) {
-    return cb.mode == kNttRelinMs ? launch_full_combine<A, kNttRelinMs>(logN, ls, cb, c, st)
-                                  : launch_full_combine<A, kNttSwitch>(logN, ls, cb, c, st);
+    return cb.mode == kNttRelinMs    ? launch_full_combine<A, kNttRelinMs>(logN, ls, cb, c, st)
+           : cb.mode == kNttKsCombine ? launch_full_combine<A, kNttKsCombine>(logN, ls, cb, c, st)
+                                      : launch_full_combine<A, kNttSwitch>(logN, ls, cb, c, st);
 }
 
 // ----------------------------------------------------------- part limbs
@@ -326,18 +327,20 @@ template <class A>
 static void launch_parts_combine_a(int pl, const LimbSet &ls, const NttCombine &cb, const bc_ctx *c,
                                    hipStream_t st) {
     if (cb.mode == kNttRelinMs) launch_parts_combine<A, kNttRelinMs>(pl, ls, cb, c, st);
+    else if (cb.mode == kNttKsCombine) launch_parts_combine<A, kNttKsCombine>(pl, ls, cb, c, st);
     else launch_parts_combine<A, kNttSwitch>(pl, ls, cb, c, st);
 }
 
 void ntt_forward_parts_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &cb, hipStream_t st) {
     const int pl = ntt_parts_log(c);
     if (!pl) throw Error(BC_ERR_ARG, "ntt: part-limb transforms are off for this context");
-    if (cb.mode != kNttRelinMs && cb.mode != kNttSwitch) throw Error(BC_ERR_ARG, "ntt: unknown combine step");
+    if (cb.mode != kNttRelinMs && cb.mode != kNttSwitch && cb.mode != kNttKsCombine)
+        throw Error(BC_ERR_ARG, "ntt: unknown combine step");
     if (ls.npoly == 0 || ls.nlimb == 0) return;
     if (tl_rec) return record_ntt(c, ls, kPkNttComb0, pl, &cb);
     ProfRec r{};
     const bool prof = c->prof->on && !tl_rec;
-    const double per_limb = (cb.mode == kNttRelinMs ? 32.0 : 24.0) * c->N;
+    const double per_limb = (cb.mode == kNttRelinMs ? 32.0 : cb.mode == kNttKsCombine ? 28.0 : 24.0) * c->N;
     if (prof) c->prof->begin(kProfNttFwdCombine, per_limb * ls.npoly * ls.nlimb, st, r);
     if (use_fp(c)) launch_parts_combine_a<FpA>(pl, ls, cb, c, st);
     else launch_parts_combine_a<IntA>(pl, ls, cb, c, st);
@@ -347,7 +350,8 @@ void ntt_forward_parts_combine(const bc_ctx *c, const LimbSet &ls, const NttComb
 
 bool ntt_forward_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &cb, hipStream_t st) {
     if (!c->ntt_single_pass || c->logN < 12 || c->logN > 15) return false;
-    if (cb.mode != kNttRelinMs && cb.mode != kNttSwitch) throw Error(BC_ERR_ARG, "ntt: unknown combine step");
+    if (cb.mode != kNttRelinMs && cb.mode != kNttSwitch && cb.mode != kNttKsCombine)
+        throw Error(BC_ERR_ARG, "ntt: unknown combine step");
     if (ls.npoly == 0 || ls.nlimb == 0) return true;
     if (tl_rec) {
         record_ntt(c, ls, kPkNttComb0, 0, &cb);
@@ -356,7 +360,7 @@ bool ntt_forward_combine(const bc_ctx *c, const LimbSet &ls, const NttCombine &c
     ProfRec r{};
     const bool prof = c->prof->on && !tl_rec;
     // E read and out written, d (and acc) read
-    const double per_limb = (cb.mode == kNttRelinMs ? 32.0 : 24.0) * c->N;
+    const double per_limb = (cb.mode == kNttRelinMs ? 32.0 : cb.mode == kNttKsCombine ? 28.0 : 24.0) * c->N;
     if (prof) c->prof->begin(kProfNttFwdCombine, per_limb * ls.npoly * ls.nlimb, st, r);
     const bool ok = use_fp(c) ? launch_full_combine_a<FpA>(c->logN, ls, cb, c, st)
                               : launch_full_combine_a<IntA>(c->logN, ls, cb, c, st);

@@ -591,7 +591,7 @@ __device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, co
         for (int j = 0; j < 8; j++) {
             const int sl = 8 * j + (lane >> 3), wi = sl * 32 + 16 * r + 2 * p;
             U64x2 w{tile[(2 * p) * kTileRow + sl], tile[(2 * p + 1) * kTileRow + sl]};
-            if constexpr (EPI == kNttRelinMs) {
+            if constexpr (EPI == kNttRelinMs || EPI == kNttKsCombine) {
                 const int x = boff + wi;  // word of the limb
                 const U64x2 dv = *reinterpret_cast<const U64x2 *>(mc->d + x);
                 const U64x2 av = *reinterpret_cast<const U64x2 *>(mc->acc + x);
@@ -741,8 +741,11 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             const int k = job / ls.npoly, ct = job - k * ls.npoly;
             const int cc = ls.off[k] / cb->level, i = ls.off[k] - cc * cb->level;
             McLimb<A> mc;
-            mc.d = cb->d + (size_t)ct * cb->d_ct_stride + ((size_t)cc * (cb->level + 1) + i) * NL + hh * N;
-            mc.acc = EPI == kNttRelinMs ? cb->acc + (((size_t)ct * 2 + cc) * cb->next + i) * NL + hh * N : nullptr;
+            if constexpr (EPI == kNttKsCombine)  // the base: component 0 only, level limbs per component
+                mc.d = cc == 0 ? cb->d + (size_t)ct * cb->d_ct_stride + (size_t)i * NL + hh * N : cb->zeros;
+            else
+                mc.d = cb->d + (size_t)ct * cb->d_ct_stride + ((size_t)cc * (cb->level + 1) + i) * NL + hh * N;
+            mc.acc = EPI != kNttSwitch ? cb->acc + (((size_t)ct * 2 + cc) * cb->next + i) * NL + hh * N : nullptr;
             mc.out = cb->out + (((size_t)ct * 2 + cc) * cb->level + i) * NL + hh * N;
             mc.w0 = A::pair(cb->w[i]);
             mc.w1 = A::pair(cb->w[i] + 2);

@@ -255,10 +255,53 @@ void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int co
     else run_ntt(c, acc, (size_t)2 * next * N, count, js, true, st);
     BufP TH = make_buf(c, sizeof(u64) * (size_t)count * 2 * nl * N);
     u64 *th = (u64 *)TH->p;
-    launch_moddown(c, acc, th, count, level, next, parts, st);
-    if (parts) run_ntt_parts(c, th, (size_t)2 * nl * N, count, all_limbs(2, nl), false, st);
-    else run_ntt(c, th, (size_t)2 * nl * N, count, all_limbs(2, nl), false, st);
-    launch_ks_combine(c, base0, base1, base_stride, acc, th, out, out_stride, count, level, next, st);
+    // with one base (a rotation's automorphism component 0) the last step runs
+    // in TH's forward transform as it stores: TH comes out of the lowering
+    // already scaled by p P^-1 and out = base + acc P^-1 - NTT(TH)
+    const bool fused = !tl_rec && !base1 && out_stride == (size_t)2 * nl * N &&
+                       (parts || (c->ntt_single_pass && c->logN >= 12 && c->logN <= 15));
+    launch_moddown(c, acc, th, count, level, next, parts, st, fused);
+    if (fused) {
+        NttCombine cb{};
+        cb.mode = kNttKsCombine;
+        cb.d = base0;
+        cb.d_ct_stride = base_stride;
+        cb.zeros = c->zeros;
+        cb.acc = acc;
+        cb.out = out;
+        cb.level = nl;
+        cb.next = next;
+        for (int i = 0; i < nl; i++) {
+            const u64 q = c->mod[i];
+            u64 P = 1;
+            for (int t = 0; t < c->nP; t++) P = h_mulmod(P, c->mod[c->nQ + t] % q, q);
+            const u64 pinv = h_invmod(P, q);
+            if (use_fp64(c)) {
+                h_fpair(cb.w[i], 1, q);
+                h_fpair(cb.w[i] + 2, pinv, q);
+            } else {
+                cb.w[i][0] = 1;
+                cb.w[i][1] = h_shoup(1, q);
+                cb.w[i][2] = pinv;
+                cb.w[i][3] = h_shoup(pinv, q);
+            }
+        }
+        LimbSet ls{};
+        ls.base = th;
+        ls.poly_stride = (u64)2 * nl * N;
+        ls.npoly = count;
+        ls.nlimb = 2 * nl;
+        for (int k = 0; k < 2 * nl; k++) {
+            ls.off[k] = (int16_t)k;
+            ls.prime[k] = (int16_t)(k % nl);
+        }
+        if (parts) ntt_forward_parts_combine(c, ls, cb, st);
+        else BC_REQUIRE(ntt_forward_combine(c, ls, cb, st), BC_ERR_ARG, "key switch: no fused transform");
+    } else {
+        if (parts) run_ntt_parts(c, th, (size_t)2 * nl * N, count, all_limbs(2, nl), false, st);
+        else run_ntt(c, th, (size_t)2 * nl * N, count, all_limbs(2, nl), false, st);
+        launch_ks_combine(c, base0, base1, base_stride, acc, th, out, out_stride, count, level, next, st);
+    }
     check_hip();
 }
 
