@@ -578,6 +578,13 @@ struct McLimb {
 };
 
 // ROUT: words stored as their reduced fp64 pattern (|x| <= q/2, see ntt_full_body)
+// With an epilogue the loads of d and acc for kStoreGroup<EPI> tile rows are
+// issued together before their combinations are stored (each word is read and
+// then written by the same lane, so an output that is its own d stays
+// correct).  The part-limb kernels of the rotation's key switch (a base
+// pointer that depends on the component) spilled with groups of four.
+template <int EPI>
+constexpr int kStoreGroup = EPI == kNttKsCombine ? 2 : 4;
 template <class A, int EPI = 0, bool ROUT = false>
 __device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, const A &ar, u64 *tile, int lane,
                                             const McLimb<A> *mc = nullptr, int boff = 0) {
@@ -587,22 +594,36 @@ __device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, co
         for (int i = 0; i < 16; i++) tile[i * kTileRow + lane] = ROUT ? A::raw(ar.reduce(v[16 * r + i])) : ar.store(v[16 * r + i]);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const int p = lane & 7;
+        if constexpr (EPI == 0) {
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
-            const int sl = 8 * j + (lane >> 3), wi = sl * 32 + 16 * r + 2 * p;
-            U64x2 w{tile[(2 * p) * kTileRow + sl], tile[(2 * p + 1) * kTileRow + sl]};
-            if constexpr (EPI == kNttRelinMs || EPI == kNttKsCombine) {
-                const int x = boff + wi;  // word of the limb
-                const U64x2 dv = *reinterpret_cast<const U64x2 *>(mc->d + x);
-                const U64x2 av = *reinterpret_cast<const U64x2 *>(mc->acc + x);
-                *reinterpret_cast<U64x2 *>(mc->out + x) =
-                    U64x2{ar.combine(dv.a, av.a, w.a, mc->w0, mc->w1), ar.combine(dv.b, av.b, w.b, mc->w0, mc->w1)};
-            } else if constexpr (EPI == kNttSwitch) {
-                const int x = boff + wi;
-                const U64x2 dv = *reinterpret_cast<const U64x2 *>(mc->d + x);
-                *reinterpret_cast<U64x2 *>(mc->out + x) = U64x2{ar.switch_(dv.a, w.a, mc->w0), ar.switch_(dv.b, w.b, mc->w0)};
-            } else {
-                *reinterpret_cast<U64x2 *>(blk + wi) = w;
+            for (int j = 0; j < 8; j++) {
+                const int sl = 8 * j + (lane >> 3), wi = sl * 32 + 16 * r + 2 * p;
+                *reinterpret_cast<U64x2 *>(blk + wi) = U64x2{tile[(2 * p) * kTileRow + sl], tile[(2 * p + 1) * kTileRow + sl]};
+            }
+        } else {
+            constexpr int G = kStoreGroup<EPI>;
+#pragma unroll
+            for (int j0 = 0; j0 < 8; j0 += G) {
+                U64x2 dv[G], av[G];
+#pragma unroll
+                for (int g = 0; g < G; g++) {
+                    const int x = boff + (8 * (j0 + g) + (lane >> 3)) * 32 + 16 * r + 2 * p;  // word of the limb
+                    dv[g] = *reinterpret_cast<const U64x2 *>(mc->d + x);
+                    if constexpr (EPI != kNttSwitch) av[g] = *reinterpret_cast<const U64x2 *>(mc->acc + x);
+                }
+#pragma unroll
+                for (int g = 0; g < G; g++) {
+                    const int sl = 8 * (j0 + g) + (lane >> 3), x = boff + sl * 32 + 16 * r + 2 * p;
+                    const U64x2 w{tile[(2 * p) * kTileRow + sl], tile[(2 * p + 1) * kTileRow + sl]};
+                    U64x2 o;
+                    if constexpr (EPI == kNttSwitch) {
+                        o = U64x2{ar.switch_(dv[g].a, w.a, mc->w0), ar.switch_(dv[g].b, w.b, mc->w0)};
+                    } else {
+                        o = U64x2{ar.combine(dv[g].a, av[g].a, w.a, mc->w0, mc->w1),
+                                  ar.combine(dv[g].b, av[g].b, w.b, mc->w0, mc->w1)};
+                    }
+                    *reinterpret_cast<U64x2 *>(mc->out + x) = o;
+                }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
