@@ -630,17 +630,24 @@ __device__ __forceinline__ void store_block(u64 *blk, const typename A::V *v, co
     }
 }
 
+// Every global load of the block is issued before the first tile pass (the
+// second half's loads would otherwise wait behind the first half's LDS work).
 template <class A, bool RIN = false>
 __device__ __forceinline__ void load_block(const u64 *blk, typename A::V *v, const A &ar, u64 *tile, int lane) {
+    const int p = lane & 7;
+    U64x2 w[2][8];
 #pragma unroll
     for (int r = 0; r < 2; r++) {
-        const int p = lane & 7;
+#pragma unroll
+        for (int j = 0; j < 8; j++) w[r][j] = *reinterpret_cast<const U64x2 *>(blk + (8 * j + (lane >> 3)) * 32 + 16 * r + 2 * p);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const int sl = 8 * j + (lane >> 3);
-            U64x2 w = *reinterpret_cast<const U64x2 *>(blk + sl * 32 + 16 * r + 2 * p);
-            tile[(2 * p) * kTileRow + sl] = w.a;
-            tile[(2 * p + 1) * kTileRow + sl] = w.b;
+            tile[(2 * p) * kTileRow + sl] = w[r][j].a;
+            tile[(2 * p + 1) * kTileRow + sl] = w[r][j].b;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
