@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--mfma-modup", type=int, default=None, choices=[0, 1],
                     help="uint16: modulus raising on the matrix cores (1) or the fp64 vector units (0); "
                          "default: the library's")
+    ap.add_argument("--raw-handoff", type=int, default=None, choices=[0, 1],
+                    help="uint16: limbs between key-switching kernels as reduced fp64 patterns (1) or canonical "
+                         "words (0); default: what the multiplication autotuner picks (profiles pin it)")
     ap.add_argument("--packed-cts", type=int, default=64,
                     help="packed: ciphertexts per batch (32 uint16 integers each)")
     ap.add_argument("--fpd-cts", type=int, default=32,
@@ -131,6 +134,9 @@ def main():
     if a.mfma_modup is not None:
         dev.set_tuning(bc.BC_TUNE_MFMA_MODUP, a.mfma_modup)
     tuned["mfma_modup"] = dev.get_tuning(bc.BC_TUNE_MFMA_MODUP)
+    if a.raw_handoff is not None:
+        dev.set_tuning(bc.BC_TUNE_RAW_HANDOFF, a.raw_handoff)
+        tuned["raw_handoff"] = a.raw_handoff
     if a.ntt_chunk_mb is not None:
         dev.set_tuning(bc.BC_TUNE_NTT_CHUNK_BYTES, int(a.ntt_chunk_mb * 2**20))
         dev.set_tuning(bc.BC_TUNE_NTT_SINGLE_PASS, 0)
