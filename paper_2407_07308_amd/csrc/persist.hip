@@ -16,7 +16,7 @@
 // (every wave waits for its stores, then one release and one counter
 // increment per ticket);
 // consumers wait on the counter (one lane of one wave, bounded by a wall
-// clock) and then acquire (one cache invalidation per workgroup).  A
+// clock) and then acquire (each wave invalidates the L1 after the barrier).  A
 // workgroup that runs several tickets after the same dependency acquires it
 // once.
 
@@ -203,13 +203,14 @@ __global__ void __launch_bounds__(kPT, 3) k_persist(const PStage *__restrict__ s
                         break;
                     }
                 }
-                // one acquire per workgroup (the waves share the CU's L1, and
-                // none has loaded yet): the L1 alone when the producer shares
-                // this XCD's L2, else the agent-scope acquire
-                if (local) asm volatile("buffer_inv sc0" ::: "memory");
-                else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
+            // every wave acquires for itself after the barrier (the barrier
+            // does not order one wave's cache invalidation before another
+            // wave's loads): the L1 alone when the producer shares this XCD's
+            // L2, else the agent-scope acquire
+            if (local) asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+            else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             acquired = dep;
         }
         const int kind = __builtin_amdgcn_readfirstlane(S.kind);
