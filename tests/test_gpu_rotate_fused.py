@@ -51,8 +51,6 @@ def rotations(prm, tune, levels=3, seed=71):
 def test_fused_matches_separate_combine(prm, parts, fp64):
     import paper_2407_07308_amd as bc
 
-    if prm.logN == 15 and not fp64:
-        pytest.skip("the integer arithmetic at 2^15 is covered by the fp64 chain's bytes at 2^14")
     print(f"rotate fused: N=2^{prm.logN} parts {parts} fp64 {fp64}", flush=True)
     base = [(bc.BC_TUNE_FP64, fp64)]
     _, _, _, _, got = rotations(prm, base + [(bc.BC_TUNE_NTT_PARTS, parts)])
