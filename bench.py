@@ -125,8 +125,9 @@ def main():
     keys = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
     dev.autotune()
     tuned = dev.autotune_mul(keys)
-    # the groups run as SPLIT concurrent slices on library streams (two timed
-    # fastest: 1, 2 and 4 slices gave 165, 159-160 and 164-166 ms a step)
+    # the groups run as SPLIT concurrent slices on library streams (two kept:
+    # re-timed with the current kernels, 1, 2, 3 and 4 slices gave 128.0,
+    # 123.0-125.7, 122.3-126.7 and 126.5-127.2 ms a step)
     dev.set_tuning(bc.BC_TUNE_SPLIT_STREAMS, a.split)
     tuned["split_streams"] = a.split
     dev.set_tuning(bc.BC_TUNE_PERSISTENT, a.persistent)
