@@ -379,12 +379,12 @@ struct GarnerTable {
 // d has level + 1 limbs per component (stride d_ct_stride per ciphertext);
 // acc is [count][2][next][N].  w[i] holds the constants mod q_i as pairs of
 // the transform's arithmetic (Shoup pairs, or (w, w/q) doubles).
-//   kNttKsCombine: out_i = d_i w0_i + acc_i w1_i - E_i (the key switch of a
-//                 rotation: d the automorphism's component 0 and, for
-//                 component 1, `zeros`; w0 = 1, w1 = P^-1, E the
-//                 modulus-lowering correction already scaled by p P^-1);
-//                 here `level` counts the limbs of a component of E, d and
-//                 out alike.
+//   kNttKsCombine: out_i = d_i w0_i + acc_i w1_i - E_i (a key switch: d the
+//                 base of component 0, d1 that of component 1 (a table of N
+//                 zero words, d1_limb = d1_ct_stride = 0, when it has none);
+//                 w0 = 1, w1 = P^-1, E the modulus-lowering correction
+//                 already scaled by p P^-1); here `level` counts the limbs of
+//                 a component of E, d and out alike.
 enum { kNttRelinMs = 1, kNttSwitch = 2, kNttKsCombine = 3 };
 struct NttCombine {
     int mode;
@@ -394,9 +394,11 @@ struct NttCombine {
     u64 *out;
     int level, next;
     u64 w[kMaxMod][4];
-    // kNttKsCombine: N zero words, component 1's base (one load path for
-    // both components, no branch on the base in the store loop)
-    const u64 *zeros;
+    // kNttKsCombine: component 1's base, limb l of ciphertext ct at
+    // d1 + ct d1_ct_stride + l d1_limb (one load path for both components,
+    // no branch on the base in the store loop)
+    const u64 *d1;
+    u64 d1_ct_stride, d1_limb;
 };
 
 struct PersistRunner;  // persist.h

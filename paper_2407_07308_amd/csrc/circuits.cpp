@@ -655,12 +655,14 @@ void extract_digits(bc_ctx *c, const bc_keys *k, const CtB &in, const int *digit
     for (int j = 0; j < ndig; j++)  // x^-k = x^(2N - k)
         launch_mul_monomial(c, in.data, out.data + (size_t)j * in.count * W, in.count, nl, 2,
                             (2 * N - digits[j]) % (2 * N), st);
+    // z <- z + sigma(z) between out and tmp; the scalar d^-1 writes out
     CtB tmp = alloc_ct(c, out.count, out.level, 2);
+    const CtB *z = &out, *zn = &tmp;
     for (int r : steps) {
-        rotate(c, k, out, r, tmp, st);
-        add_sub(c, out, tmp, out, false, st);
+        rotate_add(c, k, *z, r, *zn, st);
+        std::swap(z, zn);
     }
-    mul_scalar(c, out, (int64_t)h_invmod((u64)(d % c->p), (u64)c->p), out, st);
+    mul_scalar(c, *z, (int64_t)h_invmod((u64)(d % c->p), (u64)c->p), out, st);
 }
 
 void packed_levels(const NoiseModel &m, int in_level, double in_noise, int l, int circuit, int *lv, double *nb) {

@@ -28,8 +28,9 @@ void launch_mul_scalar(const bc_ctx *c, const u64 *a, u64 *out, int count, int n
 void launch_add_const(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int64_t v, hipStream_t st);
 // out = a x^e (0 <= e < 2N) on count batches of nl limbs x ncomp components (NTT domain; in place allowed)
 void launch_mul_monomial(const bc_ctx *c, const u64 *a, u64 *out, int count, int nl, int ncomp, int e, hipStream_t st);
+// add0: component 0 gets the input's own component 0 added (in != out)
 void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, int count, int nl, int ncomp,
-                    hipStream_t st);
+                    hipStream_t st, bool add0 = false);
 // `pl`: the first pl forward stages of the transforms that follow are applied
 // to the outputs (ntt_parts_log(c), or 0)
 // raw: the input and the new limbs as reduced fp64 patterns (fp64 arithmetic,

@@ -51,8 +51,8 @@ __global__ void k_mul_monomial(const u64 *__restrict__ a, u64 *__restrict__ out,
 }
 
 __global__ void k_permute(const u64 *__restrict__ in, u64 *__restrict__ out, const u32 *__restrict__ perm, int nl,
-                          int ncomp, int N) {
-    b_permute(hw_blk(), in, out, perm, nl, ncomp, N);
+                          int ncomp, int N, const PrimeInfo *__restrict__ pinfo, bool add0) {
+    b_permute(hw_blk(), in, out, perm, nl, ncomp, N, pinfo, add0);
 }
 
 // ------------------------------------------------------- key switching
@@ -326,8 +326,9 @@ void launch_mul_monomial(const bc_ctx *c, const u64 *a, u64 *out, int count, int
     k_mul_monomial<<<grid3(c->N, nl, count), kT, 0, st>>>(a, out, nl, ncomp, e, c->tw, c->pinfo, c->N, c->logN);
 }
 void launch_permute(const bc_ctx *c, const u64 *in, u64 *out, const u32 *perm, int count, int nl, int ncomp,
-                    hipStream_t st) {
-    k_permute<<<grid3(c->N, nl, count), kT, 0, st>>>(in, out, perm, nl, ncomp, c->N);
+                    hipStream_t st, bool add0) {
+    BC_REQUIRE(!add0 || in != out, BC_ERR_ARG, "permute-and-add runs out of place");
+    k_permute<<<grid3(c->N, nl, count), kT, 0, st>>>(in, out, perm, nl, ncomp, c->N, c->pinfo, add0);
 }
 template <int PL, bool RAW, int STEPS>
 static void modup_mfma_k(const bc_ctx *c, const ModUpMfma &T, const u64 *xc, u64 *mu, const ModUpPlan *plans, int count,

@@ -121,15 +121,18 @@ __device__ __forceinline__ void b_add_const(const VBlk &VB, const u64 *__restric
     }
 }
 
-// out[ct][c][i][r] = in[ct][c][i][perm[r]]
+// out[ct][c][i][r] = in[ct][c][i][perm[r]]  (+ in[ct][0][i][r] on component 0
+// when add0: the automorphism's component 0 with the input's own added, the
+// base of a rotate-and-add's key switch)
 __device__ __forceinline__ void b_permute(const VBlk &VB, const u64 *__restrict__ in, u64 *__restrict__ out, const u32 *__restrict__ perm, int nl,
-                          int ncomp, int N) {
+                          int ncomp, int N, const PrimeInfo *__restrict__ pinfo = nullptr, bool add0 = false) {
     const int n = VB.x * kT + threadIdx.x, i = VB.y, ct = VB.z;
     const size_t L = (size_t)nl * N;
     const u32 src = perm[n];
     for (int c = 0; c < ncomp; c++) {
         size_t base = (size_t)ct * ncomp * L + (size_t)c * L + (size_t)i * N;
-        out[base + n] = in[base + src];
+        const u64 x = in[base + src];
+        out[base + n] = c == 0 && add0 ? add_mod(x, in[base + n], pinfo[i].q) : x;
     }
 }
 

@@ -769,8 +769,9 @@ __device__ __forceinline__ void ntt_full_body(const LimbSet &ls, const void *__r
             const int k = job / ls.npoly, ct = job - k * ls.npoly;
             const int cc = ls.off[k] / cb->level, i = ls.off[k] - cc * cb->level;
             McLimb<A> mc;
-            if constexpr (EPI == kNttKsCombine)  // the base: component 0 only, level limbs per component
-                mc.d = cc == 0 ? cb->d + (size_t)ct * cb->d_ct_stride + (size_t)i * NL + hh * N : cb->zeros;
+            if constexpr (EPI == kNttKsCombine)  // the bases: level limbs per component
+                mc.d = cc == 0 ? cb->d + (size_t)ct * cb->d_ct_stride + (size_t)i * NL + hh * N
+                               : cb->d1 + (size_t)ct * cb->d1_ct_stride + (size_t)i * cb->d1_limb + hh * N;
             else
                 mc.d = cb->d + (size_t)ct * cb->d_ct_stride + ((size_t)cc * (cb->level + 1) + i) * NL + hh * N;
             mc.acc = EPI != kNttSwitch ? cb->acc + (((size_t)ct * 2 + cc) * cb->next + i) * NL + hh * N : nullptr;

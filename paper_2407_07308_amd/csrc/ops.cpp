@@ -255,10 +255,10 @@ void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int co
     else run_ntt(c, acc, (size_t)2 * next * N, count, js, true, st);
     BufP TH = make_buf(c, sizeof(u64) * (size_t)count * 2 * nl * N);
     u64 *th = (u64 *)TH->p;
-    // with one base (a rotation's automorphism component 0) the last step runs
-    // in TH's forward transform as it stores: TH comes out of the lowering
-    // already scaled by p P^-1 and out = base + acc P^-1 - NTT(TH)
-    const bool fused = !tl_rec && !base1 && out_stride == (size_t)2 * nl * N &&
+    // the last step runs in TH's forward transform as it stores: TH comes out
+    // of the lowering already scaled by p P^-1 and out = base + acc P^-1 -
+    // NTT(TH), component 1's base the zero table when there is none
+    const bool fused = !tl_rec && out_stride == (size_t)2 * nl * N &&
                        (parts || (c->ntt_single_pass && c->logN >= 12 && c->logN <= 15));
     launch_moddown(c, acc, th, count, level, next, parts, st, fused);
     if (fused) {
@@ -266,7 +266,9 @@ void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int co
         cb.mode = kNttKsCombine;
         cb.d = base0;
         cb.d_ct_stride = base_stride;
-        cb.zeros = c->zeros;
+        cb.d1 = base1 ? base1 : c->zeros;
+        cb.d1_ct_stride = base1 ? base_stride : 0;
+        cb.d1_limb = base1 ? (u64)N : 0;
         cb.acc = acc;
         cb.out = out;
         cb.level = nl;
@@ -521,6 +523,24 @@ void rotate(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB &ou
     CtB sig = alloc_ct(c, in.count, in.level, 2);
     launch_permute(c, in.data, sig.data, k->perm[idx], in.count, in.level + 1, 2, st);
     key_switch(c, k->gk[idx], sig.data + L, 2 * L, in.count, in.level, sig.data, nullptr, 2 * L, out.data, 2 * L, st);
+}
+
+// out = in + rotation of in: the automorphism's component 0 with in's own
+// added is component 0's base of the key switch, in's component 1 that of
+// component 1, so the sum costs no pass of its own (out != in)
+void rotate_add(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB &out, hipStream_t st) {
+    BC_REQUIRE(in.ncomp == 2, BC_ERR_ARG, "rotation takes 2-component ciphertexts");
+    BC_REQUIRE(out.ncomp == 2 && out.level == in.level && out.count == in.count, BC_ERR_ARG, "rotation: output shape");
+    BC_REQUIRE(out.data != in.data, BC_ERR_ARG, "rotate-and-add runs out of place");
+    int idx = -1;
+    for (int i = 0; i < k->ngal; i++)
+        if (k->steps[i] == steps) idx = i;
+    BC_REQUIRE(idx >= 0, BC_ERR_KEY, "no rotation key for this step");
+    const size_t L = (size_t)(in.level + 1) * c->N;
+    CtB sig = alloc_ct(c, in.count, in.level, 2);
+    launch_permute(c, in.data, sig.data, k->perm[idx], in.count, in.level + 1, 2, st, true);
+    key_switch(c, k->gk[idx], sig.data + L, 2 * L, in.count, in.level, sig.data, in.data + L, 2 * L, out.data, 2 * L,
+               st);
 }
 
 void add_sub(bc_ctx *c, const CtB &a0, const CtB &b0, const CtB &out, bool sub, hipStream_t st) {

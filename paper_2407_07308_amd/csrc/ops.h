@@ -77,6 +77,8 @@ CtB mul(bc_ctx *c, const bc_keys *k, const CtB &a, const CtB &b, hipStream_t st)
 // buffer rounded up to 256 bytes, none reused within the call).
 size_t mul_relin_workspace(const bc_ctx *c, int count, int lv);
 void rotate(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB &out, hipStream_t st);
+// out = in + rotate(in) (out != in)
+void rotate_add(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB &out, hipStream_t st);
 void add_sub(bc_ctx *c, const CtB &a, const CtB &b, const CtB &out, bool sub, hipStream_t st);
 CtB add(bc_ctx *c, const CtB &a, const CtB &b, hipStream_t st);
 CtB sub(bc_ctx *c, const CtB &a, const CtB &b, hipStream_t st);

@@ -5,7 +5,8 @@ part-limb kernels (2^14, 2^15), fp64 and integer arithmetic.  Each gives the
 bytes of the separate transform + combine path (the context with the
 single-pass transforms off) at the top level and after modulus switches;
 decryptions are the rotated slots; at N = 2^12 one level down and at 2^15
-the top level against the oracle."""
+the top level against the oracle.  A level-0 product, whose key switch has a
+base in both components, against the separate path."""
 import numpy as np
 import pytest
 
@@ -71,3 +72,33 @@ def test_fused_matches_oracle():
             oc = o.mod_switch(oc)
         for s in STEPS:
             assert np.array_equal(got[(oc.level, s)][1], o.rotate(oc, s).data), (prm.logN, s)
+
+
+@pytest.mark.parametrize("prm,parts", [(P12, 1), (P14, 1), (P14, 0)])
+def test_level0_relinearisation_with_two_bases(prm, parts):
+    """A product at level 0 relinearises without a modulus switch: the key
+    switch's combine has a base in both components (d0, d1), stored by TH's
+    transform like a rotation's; same bytes as the separate path."""
+    import paper_2407_07308_amd as bc
+
+    print(f"relinearise at level 0: N=2^{prm.logN} parts {parts}", flush=True)
+
+    def run(tune):
+        dev = bc.Context.from_params(prm)
+        for k, v in tune:
+            dev.set_tuning(k, v)
+        rnd = synth.keygen_randomness(81, prm.N, prm.nQ, prm.nP, prm.dnum, 0)
+        dk = dev.keygen(rnd["s"], rnd["a"], rnd["e"], ())
+        vals = synth.slot_values(82, 3, dev.M, 0, prm.p)
+        r = synth.encrypt_randomness(83, 3, prm.N)
+        x = dev.encrypt(dk, vals, r["u"], r["e"])
+        while x.level > 0:
+            x = dev.mod_switch(x)
+        y = dev.mul_relin(dk, x, x)
+        assert y.level == 0
+        assert np.array_equal(dev.decrypt(dk, y), (vals.astype(np.int64) ** 2) % prm.p)
+        return dev.export(y)
+
+    got = run([(bc.BC_TUNE_NTT_PARTS, parts)])
+    ref = run([(bc.BC_TUNE_NTT_SINGLE_PASS, 0)])
+    assert np.array_equal(got, ref)
