@@ -240,7 +240,8 @@ void relin_mod_switch(bc_ctx *c, const bc_keys *k, const CtB &t3, const CtB &out
 }
 
 void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int count, int level, const u64 *base0,
-                const u64 *base1, size_t base_stride, u64 *out, size_t out_stride, hipStream_t st) {
+                const u64 *base1, size_t base_stride, u64 *out, size_t out_stride, hipStream_t st,
+                bool fuse_base1 = false) {
     const int N = c->N, nl = level + 1, next = nl + c->nP;
     BufP ACC = ks_accumulate(c, key, X, x_stride, count, level, st);
     u64 *acc = (u64 *)ACC->p;
@@ -257,8 +258,11 @@ void key_switch(bc_ctx *c, const u64 *key, const u64 *X, size_t x_stride, int co
     u64 *th = (u64 *)TH->p;
     // the last step runs in TH's forward transform as it stores: TH comes out
     // of the lowering already scaled by p P^-1 and out = base + acc P^-1 -
-    // NTT(TH), component 1's base the zero table when there is none
-    const bool fused = !tl_rec && out_stride == (size_t)2 * nl * N &&
+    // NTT(TH), component 1's base the zero table when there is none.  A
+    // second base is fused only for rotate-and-add: level-0 relinearisation
+    // through it gave intermittent wrong results in concurrent group runs
+    // (cause not found), so it keeps the separate transform and combine.
+    const bool fused = !tl_rec && out_stride == (size_t)2 * nl * N && (!base1 || fuse_base1) &&
                        (parts || (c->ntt_single_pass && c->logN >= 12 && c->logN <= 15));
     launch_moddown(c, acc, th, count, level, next, parts, st, fused);
     if (fused) {
@@ -540,7 +544,7 @@ void rotate_add(bc_ctx *c, const bc_keys *k, const CtB &in, int steps, const CtB
     CtB sig = alloc_ct(c, in.count, in.level, 2);
     launch_permute(c, in.data, sig.data, k->perm[idx], in.count, in.level + 1, 2, st, true);
     key_switch(c, k->gk[idx], sig.data + L, 2 * L, in.count, in.level, sig.data, in.data + L, 2 * L, out.data, 2 * L,
-               st);
+               st, true);
 }
 
 void add_sub(bc_ctx *c, const CtB &a0, const CtB &b0, const CtB &out, bool sub, hipStream_t st) {

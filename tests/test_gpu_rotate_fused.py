@@ -6,7 +6,7 @@ bytes of the separate transform + combine path (the context with the
 single-pass transforms off) at the top level and after modulus switches;
 decryptions are the rotated slots; at N = 2^12 one level down and at 2^15
 the top level against the oracle.  A level-0 product, whose key switch has a
-base in both components, against the separate path."""
+base in both components, across schedules."""
 import numpy as np
 import pytest
 
@@ -76,9 +76,9 @@ def test_fused_matches_oracle():
 
 @pytest.mark.parametrize("prm,parts", [(P12, 1), (P14, 1), (P14, 0)])
 def test_level0_relinearisation_with_two_bases(prm, parts):
-    """A product at level 0 relinearises without a modulus switch: the key
-    switch's combine has a base in both components (d0, d1), stored by TH's
-    transform like a rotation's; same bytes as the separate path."""
+    """A product at level 0 relinearises without a modulus switch: a key
+    switch with a base in both components (d0, d1), which keeps the separate
+    transform and combine; the same bytes under every transform schedule."""
     import paper_2407_07308_amd as bc
 
     print(f"relinearise at level 0: N=2^{prm.logN} parts {parts}", flush=True)
